@@ -1,0 +1,346 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: a
+hand-derived closed form, an explicit kernel matrix, float64 autograd of the
+Hamiltonian, a library ODE solver, conservation laws of Hamilton's equations,
+equivariances, brute-force octree node sets, and limits in which the
+Barnes-Hut rule must reduce to the exact sum.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from helpers import (canonical_octree, euler_objective_torch, kernel_matrix,
+                     morton_interleave, rel_l2, rhs_autograd, rhs_numpy)
+from paper_1907_04834_amd import workloads as W
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rand(n, seed, scale=0.3, pscale=0.1):
+    rng = np.random.default_rng(seed)
+    return scale * rng.standard_normal((n, 3)), pscale * rng.standard_normal((n, 3))
+
+
+# ---------------------------------------------------------------- exact RHS
+def test_two_point_closed_form(oracle):
+    rows = {}
+    for line in open(os.path.join(GOLD, "two_point_rhs.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        k, *vals = line.split()
+        rows.setdefault(k, []).append([float(x) for x in vals])
+    sigma = rows["sigma"][0][0]
+    q, p = np.array(rows["q"]), np.array(rows["p"])
+    v, a = oracle.rhs_exact(q, p, sigma)
+    np.testing.assert_allclose(v, np.array(rows["v"]), rtol=0, atol=1e-15)
+    np.testing.assert_allclose(a, np.array(rows["a"]), rtol=0, atol=1e-15)
+    assert abs(oracle.energy(p, v) - rows["H"][0][0]) < 1e-14
+
+
+@pytest.mark.parametrize("n,seed", [(1, 0), (2, 1), (7, 2), (64, 3)])
+def test_rhs_is_hamiltonian_vector_field(oracle, n, seed):
+    """P1: v = K(q) p with the explicit 3N x 3N matrix, and (v, a) equal
+    (dH/dp, -dH/dq) of H = 1/2 <p, K p> by float64 autograd."""
+    q, p = _rand(n, seed)
+    sigma = 0.25
+    v, a = oracle.rhs_exact(q, p, sigma)
+    K = kernel_matrix(q, sigma)
+    np.testing.assert_allclose(v.ravel(), K @ p.ravel(), rtol=0, atol=1e-13)
+    va, aa = rhs_autograd(q, p, sigma)
+    np.testing.assert_allclose(v, va, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(a, aa, rtol=0, atol=1e-13)
+
+
+def test_kernel_spd_and_symmetric(oracle):
+    """P2: K(q) is symmetric positive semi-definite; <u, K w> = <w, K u>
+    through the oracle's velocity routine at a size with no explicit K."""
+    q, p = _rand(40, 4)
+    K = kernel_matrix(q, 0.3)
+    assert np.linalg.eigvalsh(K).min() > -1e-12
+    q, u = _rand(700, 5)
+    _, w = _rand(700, 6)
+    ku = oracle.field_exact(q, q, u, 0.2)
+    kw = oracle.field_exact(q, q, w, 0.2)
+    lhs, rhs = float((w * ku).sum()), float((u * kw).sum())
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+def test_linear_momentum_conserved(oracle):
+    """P3: sum_i a_i = 0 (pair terms cancel), so Euler keeps sum_i p_i."""
+    w = W.sphere_1024(n=300)
+    v, a = oracle.rhs_exact(w.q0, w.p0, w.sigma)
+    assert np.abs(a.sum(0)).max() <= 1e-12 * np.abs(a).sum()
+    q1, p1, _ = oracle.shoot(w.q0, w.p0, w.sigma, 10)
+    np.testing.assert_allclose(p1.sum(0), w.p0.sum(0), rtol=1e-12, atol=1e-14)
+
+
+def test_angular_momentum_rate_zero(oracle):
+    """P4: H is rotation invariant, so d/dt sum q x p = sum (v x p + q x a) = 0."""
+    q, p = _rand(200, 7, scale=0.5)
+    v, a = oracle.rhs_exact(q, p, 0.2)
+    rate = np.cross(v, p).sum(0) + np.cross(q, a).sum(0)
+    scale = np.abs(np.cross(v, p)).sum() + np.abs(np.cross(q, a)).sum()
+    assert np.abs(rate).max() <= 1e-13 * scale
+
+
+def test_energy_drift_first_order(oracle):
+    """P5: with the 1/2 pairing the flow conserves H; forward Euler drifts by
+    O(dt), so the drift halves when nt doubles."""
+    w = W.sphere_1024(n=256)
+    drift = []
+    for nt in (20, 40, 80, 160):
+        _, _, H = oracle.shoot(w.q0, w.p0, w.sigma, nt)
+        drift.append(abs(H[-1] - H[0]))
+    ratios = [drift[i] / drift[i + 1] for i in range(3)]
+    for r in ratios:
+        assert 1.8 < r < 2.2, ratios
+
+
+def test_euler_converges_to_ode_solution(oracle):
+    """P6: q(1) from nt Euler steps approaches a DOP853 solution (scipy,
+    rtol 1e-12, RHS from the explicit-matrix formulation) at rate 1/nt."""
+    from scipy.integrate import solve_ivp
+    q0, p0 = _rand(24, 8, scale=0.3, pscale=0.2)
+    sigma = 0.3
+
+    def f(_t, y):
+        q, p = y[:72].reshape(24, 3), y[72:].reshape(24, 3)
+        v, a = rhs_numpy(q, p, sigma)
+        return np.concatenate([v.ravel(), a.ravel()])
+
+    sol = solve_ivp(f, (0, 1), np.concatenate([q0.ravel(), p0.ravel()]),
+                    method="DOP853", rtol=1e-12, atol=1e-14)
+    qref = sol.y[:72, -1].reshape(24, 3)
+    errs = []
+    for nt in (32, 64, 128):
+        q1, _, _ = oracle.shoot(q0, p0, sigma, nt)
+        errs.append(np.abs(q1 - qref).max())
+    assert 1.8 < errs[0] / errs[1] < 2.2 and 1.8 < errs[1] / errs[2] < 2.2, errs
+
+
+def test_closed_forms(oracle):
+    """P7: one point moves in a straight line (q1 = q0 + p0, p constant);
+    widely separated points do the same; with sigma -> inf every point
+    translates by sum_j p_j."""
+    q0 = np.array([[0.1, -0.2, 0.3]])
+    p0 = np.array([[0.5, 0.25, -1.0]])
+    q1, p1, H = oracle.shoot(q0, p0, 0.1, 7)
+    np.testing.assert_allclose(q1, q0 + p0, atol=1e-15)
+    np.testing.assert_allclose(p1, p0, atol=0)
+    np.testing.assert_allclose(H, np.full(8, (p0 ** 2).sum()), rtol=1e-15)
+    qs = np.array([[0, 0, 0], [10, 0, 0], [0, 10, 0], [0, 0, 10.0]])
+    ps = 0.1 * np.eye(4, 3)
+    q1, p1, _ = oracle.shoot(qs, ps, 0.05, 5)
+    np.testing.assert_allclose(q1, qs + ps, atol=1e-15)
+    q, p = _rand(30, 9, scale=0.1)
+    q1, p1, _ = oracle.shoot(q, p, 1e6, 4)
+    np.testing.assert_allclose(q1, q + p.sum(0), atol=1e-9)
+
+
+def test_exact_equivariance(oracle):
+    """P8: translation, rotation, permutation and joint scaling of
+    (q, p, sigma) act on the shot state in the obvious way."""
+    q, p = _rand(150, 10, scale=0.4, pscale=0.05)
+    sigma, nt = 0.2, 6
+    q1, p1, H = oracle.shoot(q, p, sigma, nt)
+    R = W.random_rotation(np.random.default_rng(11))
+    t = np.array([0.3, -1.0, 2.0])
+    qr, pr, Hr = oracle.shoot(q @ R.T + t, p @ R.T, sigma, nt)
+    np.testing.assert_allclose(qr, q1 @ R.T + t, atol=1e-12)
+    np.testing.assert_allclose(pr, p1 @ R.T, atol=1e-12)
+    np.testing.assert_allclose(Hr, H, rtol=1e-12)
+    perm = np.random.default_rng(12).permutation(150)
+    qp_, pp_, _ = oracle.shoot(q[perm], p[perm], sigma, nt)
+    np.testing.assert_allclose(qp_, q1[perm], atol=1e-13)
+    s = 2.0
+    qs, ps, _ = oracle.shoot(s * q, s * p, s * sigma, nt)
+    np.testing.assert_allclose(qs, s * q1, atol=1e-12)
+    np.testing.assert_allclose(ps, s * p1, atol=1e-12)
+
+
+# ---------------------------------------------------------------- octree
+def _dyadic_points(n, seed, bits=12):
+    rng = np.random.default_rng(seed)
+    return rng.integers(0, 2 ** bits, size=(n, 3)) / float(2 ** bits)
+
+
+def test_integer_coordinates(oracle):
+    """The octant coordinates: 21 bits, zero at the per-axis minimum, the
+    top value at the maximum of the longest axis, monotone in q, and exact
+    for dyadic points (q - lo = k / 2^m with extent 1 -> c = k 2^(21-m))."""
+    q = _dyadic_points(500, 13, bits=10)
+    q[0] = 0.0
+    q[1, 0] = 1.0  # x extent exactly 1 = the longest axis
+    ic = oracle.int_coords(q).astype(np.int64)
+    assert ic.min() == 0 and ic.max() == 2 ** 21 - 1
+    lo = q.min(0)
+    expect = np.round((q - lo) * 2 ** 21).astype(np.int64)
+    expect = np.minimum(expect, 2 ** 21 - 1)
+    np.testing.assert_array_equal(ic, expect)
+    rng = np.random.default_rng(14)
+    x = rng.random((2000, 3))
+    c = oracle.int_coords(x).astype(np.int64)
+    for ax in range(3):
+        o = np.argsort(x[:, ax], kind="stable")
+        assert (np.diff(c[o, ax]) >= 0).all()
+
+
+@pytest.mark.parametrize("leaf_cap", [1, 3, 8])
+def test_tree_matches_brute_force_cells(oracle, leaf_cap):
+    """P12: the recursive-insertion tree has exactly the node set of the
+    canonical octree (non-empty cells whose parent holds more than leaf_cap
+    points), with correct counts and statistics, for any insertion order."""
+    rng = np.random.default_rng(15 + leaf_cap)
+    q = W.ellipsoid_surface(rng, 600, (1.0, 0.6, 0.4), 0.01)
+    q[:5] = q[5]  # a cluster of coincident points
+    p = 0.02 * rng.standard_normal((600, 3))
+    ic = oracle.int_coords(q)
+    brute = canonical_octree(ic, leaf_cap)
+    for order in (None, rng.permutation(600)):
+        d = oracle.tree_dump(q, p, leaf_cap=leaf_cap, order=order)
+        got = {(int(l), int(pf)): int(c) for l, pf, c in
+               zip(d["level"], d["prefix"], d["count"])}
+        assert set(got) == set(brute)
+        idx = {key: i for i, key in enumerate(zip(d["level"].tolist(),
+                                                  d["prefix"].tolist()))}
+        for key, mem in brute.items():
+            i = idx[key]
+            mem = list(mem)
+            assert got[key] == len(mem)
+            np.testing.assert_allclose(d["P"][i], p[mem].sum(0), atol=1e-15)
+            np.testing.assert_allclose(d["C"][i], q[mem].mean(0), atol=1e-14)
+            np.testing.assert_array_equal(d["lo"][i], q[mem].min(0))
+            np.testing.assert_array_equal(d["hi"][i], q[mem].max(0))
+            assert bool(d["leaf"][i]) == (len(mem) <= leaf_cap or key[0] == 21)
+
+
+# ---------------------------------------------------------------- Barnes-Hut
+def test_bh_reduces_to_exact(oracle):
+    """P9: theta = 0, an infinite cutoff, or leaf_cap >= N give the exact sum."""
+    w = W.ellipsoid_20k(n=3000)
+    q, p = w.q0.astype(np.float64), w.p0.astype(np.float64)
+    v, a = oracle.rhs_exact(q, p, w.sigma)
+    for kw in ({"theta": 0.0}, {"theta": 0.5, "kappa": np.inf},
+               {"theta": np.inf, "leaf_cap": 3000}):
+        vb, ab, c = oracle.rhs_bh(q, p, w.sigma, **kw)
+        assert c["monopoles"] == 0 and c["pairs"] == 3000 * 3000
+        assert rel_l2(vb, v) < 1e-13 and rel_l2(ab, a) < 1e-13
+
+
+@pytest.mark.parametrize("theta", [0.3, 0.5, 0.8, np.inf])
+def test_bh_a_priori_bound(oracle, theta):
+    """P10: each target's BH error is within the bound obtained from the
+    mean-value theorem on the approximated nodes' boxes."""
+    w = W.ellipsoid_20k(n=4000)
+    q, p = w.q0.astype(np.float64), w.p0.astype(np.float64)
+    v, a = oracle.rhs_exact(q, p, w.sigma)
+    vb, ab, c, bv, ba = oracle.rhs_bh(q, p, w.sigma, theta, bounds=True)
+    assert c["monopoles"] > 0
+    ev = np.linalg.norm(vb - v, axis=1)
+    ea = np.linalg.norm(ab - a, axis=1)
+    assert (ev <= bv + 1e-15).all() and (ea <= ba + 1e-14).all()
+
+
+def test_bh_exact_on_coincident_far_clusters(oracle):
+    """P11: when every far node is a cluster of coincident points, the
+    n_k virtual points at C_k with P_k / n_k reproduce the exact sums for
+    any theta (this fails for a literal single /n_k momentum reading)."""
+    rng = np.random.default_rng(16)
+    centres = rng.random((12, 3)) * 4.0
+    q = np.repeat(centres, 9, axis=0)
+    p = 0.1 * rng.standard_normal(q.shape)
+    sigma = 0.1
+    v, a = oracle.rhs_exact(q, p, sigma)
+    for theta in (0.3, np.inf):
+        vb, ab, c = oracle.rhs_bh(q, p, sigma, theta)
+        assert c["monopoles"] > 0
+        np.testing.assert_allclose(vb, v, atol=1e-15)
+        np.testing.assert_allclose(ab, a, atol=1e-13)
+
+
+def test_bh_equivariance(oracle):
+    """P8 for Barnes-Hut: axis permutation, dyadic translation, scaling by 2
+    and point permutation leave the node sets unchanged, so the result
+    transforms exactly like the exact one (dyadic inputs keep it exact)."""
+    q = _dyadic_points(800, 17, bits=9)
+    p = np.random.default_rng(18).integers(-64, 64, size=(800, 3)) / 1024.0
+    sigma, th = 0.05, 0.5
+    v, a, c = oracle.rhs_bh(q, p, sigma, th)
+    ax = [1, 2, 0]
+    v2, a2, c2 = oracle.rhs_bh(q[:, ax], p[:, ax], sigma, th)
+    assert c2 == c
+    np.testing.assert_allclose(v2, v[:, ax], atol=1e-14)
+    np.testing.assert_allclose(a2, a[:, ax], atol=1e-12)
+    v3, a3, c3 = oracle.rhs_bh(q + 0.5, p, sigma, th)
+    assert c3 == c
+    np.testing.assert_allclose(v3, v, atol=1e-14)
+    v4, a4, c4 = oracle.rhs_bh(2 * q, 2 * p, 2 * sigma, th)
+    assert c4 == c
+    np.testing.assert_allclose(v4, 2 * v, atol=1e-14)
+    np.testing.assert_allclose(a4, 2 * a, atol=1e-12)
+    perm = np.random.default_rng(19).permutation(800)
+    v5, a5, c5 = oracle.rhs_bh(q[perm], p[perm], sigma, th)
+    assert c5 == c
+    np.testing.assert_allclose(v5, v[perm], atol=1e-14)
+
+
+def test_bh_error_shrinks_with_theta(oracle):
+    """The BH error is monotone in the opening angle on a surface workload."""
+    w = W.ellipsoid_20k(n=5000)
+    q, p = w.q0.astype(np.float64), w.p0.astype(np.float64)
+    v, a = oracle.rhs_exact(q, p, w.sigma)
+    errs = []
+    for th in (0.3, 0.5, 0.8, np.inf):
+        vb, ab, _ = oracle.rhs_bh(q, p, w.sigma, th)
+        errs.append(rel_l2(vb, v))
+    assert errs == sorted(errs) and errs[0] < 1e-2, errs
+
+
+# ---------------------------------------------------------------- adjoint
+def test_adjoint_matches_autograd(oracle):
+    """P13: the discrete adjoint equals float64 autograd through the Euler
+    loop (objective |q(1) - y|^2 / n + lam <p0, K p0>)."""
+    q0, p0 = _rand(40, 20, scale=0.3, pscale=0.1)
+    y = q0 + 0.05 * np.random.default_rng(21).standard_normal(q0.shape)
+    sigma, nt, lam = 0.25, 6, 0.01
+    e, g = oracle.objective_grad(q0, p0, y, sigma, nt, lam)
+    et, gt = euler_objective_torch(q0, p0, y, sigma, nt, lam)
+    assert abs(e - et) <= 1e-13 * abs(et)
+    np.testing.assert_allclose(g, gt, rtol=0, atol=1e-12 * np.abs(gt).max())
+
+
+def test_adjoint_finite_differences(oracle):
+    """Central differences (h = 1e-4) of the oracle objective agree with the
+    adjoint gradient along random directions."""
+    w = W.adjoint_50k(n=400)
+    q0, p0, y = (x.astype(np.float64) for x in (w.q0, w.p0, w.extra["target"]))
+    e, g = oracle.objective_grad(q0, p0, y, w.sigma, 8, 0.01)
+    for u in W.directions(42, 400, 4):
+        fd = (oracle.objective_grad(q0, p0 + 1e-4 * u, y, w.sigma, 8, 0.01, grad=False)
+              - oracle.objective_grad(q0, p0 - 1e-4 * u, y, w.sigma, 8, 0.01, grad=False)) / 2e-4
+        assert abs(fd - (g * u).sum()) <= 1e-7 * abs(fd)
+
+
+def test_bh_adjoint_limits(oracle):
+    """The tree backward stage equals the exact adjoint when theta = 0, and
+    stays close to it at theta = 0.5."""
+    w = W.ellipsoid_20k(n=1500)
+    q, p = w.q0.astype(np.float64), w.p0.astype(np.float64)
+    rng = np.random.default_rng(22)
+    al, be = 0.01 * rng.standard_normal(q.shape), 0.01 * rng.standard_normal(q.shape)
+    gq, gp = oracle.adjoint_rhs(q, p, al, be, w.sigma)
+    gq0, gp0 = oracle.adjoint_rhs(q, p, al, be, w.sigma, method="bh", theta=0.0)
+    assert rel_l2(gq0, gq) < 1e-13 and rel_l2(gp0, gp) < 1e-13
+    gq5, gp5 = oracle.adjoint_rhs(q, p, al, be, w.sigma, method="bh", theta=0.5)
+    assert rel_l2(gq5, gq) < 5e-2 and rel_l2(gp5, gp) < 5e-2
+
+
+def test_bh_shooting_theta0_is_exact(oracle):
+    w = W.ellipsoid_20k(n=1200)
+    q, p = w.q0.astype(np.float64), w.p0.astype(np.float64)
+    q1, p1, H = oracle.shoot(q, p, w.sigma, 5)
+    qb, pb, Hb = oracle.shoot(q, p, w.sigma, 5, method="bh", theta=0.0)
+    assert rel_l2(qb, q1) < 1e-14 and rel_l2(pb, p1) < 1e-13
+    np.testing.assert_allclose(Hb, H, rtol=1e-13)
