@@ -1,0 +1,182 @@
+/*
+ * gs.h -- C ABI of the MI355X (gfx950) point-set geodesic shooting library.
+ *
+ * The library evaluates the right-hand side of the Gaussian-kernel Hamiltonian
+ * flow of point-set geodesic shooting and integrates it, exactly (all pairs)
+ * or with a Barnes-Hut octree approximation, following Wang, Xie, Yushkevich,
+ * Gee, "Barnes-Hut Approximation for Point Set Geodesic Shooting"
+ * (arXiv:1907.04834).
+ *
+ * Mathematical definitions (Sec. 2.1, eq. 1 and eq. 3):
+ *   G(r)  = exp(-r^2 / (2 sigma^2))                      (unnormalised, G(0)=1)
+ *   v_i   = sum_j G(|q_i - q_j|) p_j                    (self term included)
+ *   a_i   = sigma^-2 sum_j G(|q_i - q_j|) (p_i . p_j) (q_i - q_j)
+ *   dq/dt = v,  dp/dt = a   (Hamilton's equations for 1/2 <p, K(q) p>)
+ *   H     = <p, K(q) p> = sum_i p_i . v_i
+ *
+ * Common conventions for every entry point
+ *   - Point arrays (q, p, dq, dp, q0, p0, q1, p1, target, grad) are DEVICE
+ *     pointers to row-major [n][3] arrays (x, y, z of point 0, then point 1,
+ *     ...), float32 unless the name ends in _f64.  The caller owns them.
+ *   - `ws` is a caller-owned DEVICE workspace of at least gs_workspace_bytes()
+ *     bytes (256-byte aligned).  The library allocates no device memory and
+ *     keeps no pointer after a call returns.
+ *   - `stream` is the HIP stream every kernel is enqueued on.  Calls only
+ *     enqueue work and return; results are valid once the stream reaches the
+ *     point after the call.  The library never synchronises the stream
+ *     except in gs_get_status / gs_bh_counters / gs_kernel_timing_read.
+ *   - Argument errors are reported before any device work is enqueued:
+ *     n < 0, non-finite or non-positive sigma, nt < 1, theta < 0 or NaN,
+ *     cutoff_sigmas <= 0 or NaN, leaf_cap outside [1, 64], a NULL array when
+ *     n > 0, or a workspace that is too small.  n == 0 is a no-op (GS_OK).
+ *   - Outputs must not alias inputs, except q1/p1 which may equal q0/p0.
+ *   - gs_last_error() returns a thread-local message for the last failure.
+ *   - Calls are reentrant when they use distinct workspaces.
+ */
+#ifndef GS_H
+#define GS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GS_OK = 0,
+    GS_ERR_INVALID = -1,     /* bad argument (see conventions above)        */
+    GS_ERR_WORKSPACE = -2,   /* workspace pointer NULL or too small         */
+    GS_ERR_HIP = -3,         /* a HIP call or kernel launch failed          */
+    GS_ERR_NONFINITE = -4,   /* non-finite coordinates met on the tree path */
+    GS_ERR_UNSUPPORTED = -5  /* combination of options not implemented      */
+} gs_status;
+
+typedef enum {
+    GS_EXACT = 0,  /* all N^2 pairs (Sec. 2.1)                              */
+    GS_BH = 1      /* Barnes-Hut octree approximation (Sec. 2.2)             */
+} gs_method;
+
+/* Operation codes for gs_workspace_bytes. */
+typedef enum {
+    GS_OP_RHS = 0,      /* gs_rhs_exact / gs_rhs_bh / gs_rhs_exact_f64        */
+    GS_OP_SHOOT = 1,    /* gs_shoot / gs_shoot_f64                            */
+    GS_OP_ADJOINT = 2,  /* gs_shoot_adjoint                                   */
+    GS_OP_FIELD = 3     /* gs_field                                           */
+} gs_op;
+
+/* flags */
+#define GS_FLAG_F64 1u /* size the workspace for the _f64 entry points        */
+
+typedef struct {
+    double sigma;          /* kernel width, > 0                                */
+    double cutoff_sigmas;  /* kappa: a node is far when the distance from the
+                              target to its tight box is >= kappa * sigma
+                              (the paper's 3 sigma rule, Sec. 2.2)           */
+    double theta;          /* opening angle >= 0: an approximated node must
+                              also satisfy s_k < theta |x - C_k| (s_k: largest
+                              side of its tight box).  INFINITY = the paper's
+                              rule alone; 0 = exact.                         */
+    int32_t leaf_cap;      /* octree leaves hold <= leaf_cap points (1..64);
+                              1 = the paper's single-point leaves            */
+    int32_t nt;            /* forward-Euler steps over t in [0, 1], >= 1     */
+    uint32_t flags;        /* GS_FLAG_*                                       */
+    int32_t reserved;      /* must be 0                                       */
+} gs_params;
+
+/* Library version string (static storage). */
+const char *gs_version(void);
+
+/* Message of the last failed call on this thread (static per thread). */
+const char *gs_last_error(void);
+
+/* Fills *p with the defaults: sigma 1, cutoff 3, theta 0.5, leaf_cap 1,
+ * nt 40, flags 0. */
+void gs_params_default(gs_params *p);
+
+/* Workspace bytes needed by `op` for n points with these parameters and
+ * method.  Host-only; no device work.  Returns 0 for invalid arguments. */
+size_t gs_workspace_bytes(int64_t n, const gs_params *prm, int32_t method, int32_t op);
+
+/* Exact right-hand side (Sec. 2.1, eq. 1 and the pairwise velocity of eq. 3):
+ * (dq, dp) = (v, a) as defined above, all N^2 pairs, FP32 pair arithmetic
+ * with per-target compensated accumulation.  Uses prm->sigma only. */
+gs_status gs_rhs_exact(const float *q, const float *p, int64_t n, const gs_params *prm,
+                       float *dq, float *dp, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* The same in FP64 (q, p, dq, dp are double[n][3]). */
+gs_status gs_rhs_exact_f64(const double *q, const double *p, int64_t n,
+                           const gs_params *prm, double *dq, double *dp, void *ws,
+                           size_t ws_bytes, hipStream_t stream);
+
+/* Barnes-Hut right-hand side (Sec. 2.2, eq. 4 and the momentum-dot
+ * replacement): rebuilds the octree of q (root cube anchored at the per-axis
+ * minimum with side equal to the largest extent; octants from 21-bit integer
+ * coordinates; a node with more than leaf_cap points below level 21 is split),
+ * then for every target x walks it from the root: a node with >= 2 points
+ * that is far (kappa sigma) and passes the opening angle contributes as n_k
+ * virtual points at its centre C_k with momentum P_k / n_k each; a leaf that
+ * is not approximated contributes its exact pairs; other nodes are opened.
+ * Non-finite coordinates make gs_get_status report GS_ERR_NONFINITE. */
+gs_status gs_rhs_bh(const float *q, const float *p, int64_t n, const gs_params *prm,
+                    float *dq, float *dp, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Geodesic shooting (Sec. 2.1: the flow of eq. 1 discretised in time):
+ * prm->nt forward-Euler steps of size 1/nt from (q0, p0), each step using the
+ * right-hand side of `method` evaluated at the state at the start of the
+ * step.  Writes q1 = q(1), p1 = p(1).  H (nullable, DEVICE double[nt + 1])
+ * receives <p_t, v_t> for t = 0..nt (FP64 reduction; v from `method`). */
+gs_status gs_shoot(const float *q0, const float *p0, int64_t n, const gs_params *prm,
+                   int32_t method, float *q1, float *p1, double *H, void *ws,
+                   size_t ws_bytes, hipStream_t stream);
+
+/* Exact shooting in FP64 (arrays are double[n][3]). */
+gs_status gs_shoot_f64(const double *q0, const double *p0, int64_t n,
+                       const gs_params *prm, double *q1, double *p1, double *H,
+                       void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Objective and gradient (Sec. 2.1 eq. 2; backward stage of Sec. 2.2):
+ *   E(p0) = (1/n) sum_i |q_i(1) - target_i|^2 + lambda <p0, K(q0) p0>
+ * and grad = dE/dp0 by the discrete adjoint of the Euler scheme.  The forward
+ * states are kept every `ckpt_every` steps and the steps in between are
+ * recomputed during the backward sweep.  On the Barnes-Hut path the backward
+ * stage also uses node sums of the adjoint variables.  objective is a DEVICE
+ * double[1]; grad_p0 a DEVICE float[n][3]. */
+gs_status gs_shoot_adjoint(const float *q0, const float *p0, const float *target,
+                           int64_t n, const gs_params *prm, int32_t method,
+                           double lambda, int32_t ckpt_every, double *objective,
+                           float *grad_p0, void *ws, size_t ws_bytes,
+                           hipStream_t stream);
+
+/* Velocity field of eq. (3) at m arbitrary points x (DEVICE float[m][3]):
+ * v(x) = sum_j G(|x - q_j|) p_j over the n sources (q, p).  Exact sum. */
+gs_status gs_field(const float *x, int64_t m, const float *q, const float *p, int64_t n,
+                   const gs_params *prm, float *v, void *ws, size_t ws_bytes,
+                   hipStream_t stream);
+
+/* Waits for `stream` and returns the device-side status word of the last
+ * Barnes-Hut call that used this workspace (GS_OK or GS_ERR_NONFINITE). */
+gs_status gs_get_status(const void *ws, hipStream_t stream);
+
+/* Waits for `stream` and copies the counters of the last Barnes-Hut RHS that
+ * used this workspace: out[0] exact pairs, out[1] monopoles (approximated
+ * nodes), out[2] node visits, out[3] octree nodes.  Counts are summed over
+ * all targets of the last evaluated RHS. */
+gs_status gs_bh_counters(const void *ws, hipStream_t stream, int64_t out[4]);
+
+/* Per-launch timing of the dominant pair kernels.  While enabled, every
+ * launch of a pair kernel (exact all-pairs, Barnes-Hut traversal, adjoint
+ * pairs) is bracketed by HIP events on its stream.  gs_kernel_timing_read
+ * waits for the recorded events and returns, per kernel kind k (0 exact,
+ * 1 traversal, 2 adjoint, 3 tree build), the number of launches counts[k]
+ * and their summed duration ms[k]; reading resets the accumulators. */
+gs_status gs_kernel_timing(int32_t enable);
+gs_status gs_kernel_timing_read(int64_t counts[4], double ms[4]);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GS_H */

@@ -1,0 +1,442 @@
+// capi.cpp -- the extern "C" entry points of gs.h: argument validation,
+// workspace planning and the launch sequences of each operation.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "internal.h"
+#include "tree.h"
+
+namespace gs {
+
+// ---------------------------------------------------------------- errors
+static thread_local char g_err[512] = "";
+
+void set_error(const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+gs_status hip_fail(hipError_t e, const char *what) {
+    set_error("%s: %s", what, hipGetErrorString(e));
+    return GS_ERR_HIP;
+}
+
+// ---------------------------------------------------------------- timing
+namespace {
+struct TimingState {
+    std::mutex mu;
+    bool on = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[4];
+    hipEvent_t open[4] = {nullptr, nullptr, nullptr, nullptr};
+};
+TimingState &timing() {
+    static TimingState t;
+    return t;
+}
+}  // namespace
+
+void timing_begin(int kind, hipStream_t s) {
+    TimingState &t = timing();
+    std::lock_guard<std::mutex> g(t.mu);
+    if (!t.on) return;
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return;
+    (void)hipEventRecord(e, s);
+    t.open[kind] = e;
+}
+
+void timing_end(int kind, hipStream_t s) {
+    TimingState &t = timing();
+    std::lock_guard<std::mutex> g(t.mu);
+    if (!t.on || !t.open[kind]) return;
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return;
+    (void)hipEventRecord(e, s);
+    t.ev[kind].push_back({t.open[kind], e});
+    t.open[kind] = nullptr;
+}
+
+}  // namespace gs
+
+using namespace gs;
+
+namespace {
+
+// Workspace header: status word and Barnes-Hut counters live in the first
+// 256 bytes of every workspace.
+struct WsHeader {
+    int32_t status;
+    int32_t pad;
+    unsigned long long counters[4];
+};
+constexpr size_t kHeader = 256;
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+gs_status check_params(const gs_params *prm, bool need_nt, bool need_tree) {
+    if (!prm) {
+        set_error("params is NULL");
+        return GS_ERR_INVALID;
+    }
+    if (!finite_pos(prm->sigma)) {
+        set_error("sigma must be finite and > 0 (got %g)", prm->sigma);
+        return GS_ERR_INVALID;
+    }
+    if (need_nt && prm->nt < 1) {
+        set_error("nt must be >= 1 (got %d)", prm->nt);
+        return GS_ERR_INVALID;
+    }
+    if (need_tree) {
+        if (std::isnan(prm->theta) || prm->theta < 0.0) {
+            set_error("theta must be >= 0 (got %g)", prm->theta);
+            return GS_ERR_INVALID;
+        }
+        if (std::isnan(prm->cutoff_sigmas) || prm->cutoff_sigmas <= 0.0) {
+            set_error("cutoff_sigmas must be > 0 (got %g)", prm->cutoff_sigmas);
+            return GS_ERR_INVALID;
+        }
+        if (prm->leaf_cap < 1 || prm->leaf_cap > 64) {
+            set_error("leaf_cap must be in [1, 64] (got %d)", prm->leaf_cap);
+            return GS_ERR_INVALID;
+        }
+    }
+    if (prm->reserved != 0) {
+        set_error("params.reserved must be 0");
+        return GS_ERR_INVALID;
+    }
+    return GS_OK;
+}
+
+gs_status check_n(int64_t n) {
+    if (n < 0) {
+        set_error("n must be >= 0 (got %lld)", (long long)n);
+        return GS_ERR_INVALID;
+    }
+    if (n > (int64_t(1) << 31) - 4096) {
+        set_error("n too large (%lld)", (long long)n);
+        return GS_ERR_INVALID;
+    }
+    return GS_OK;
+}
+
+gs_status check_ptrs(std::initializer_list<const void *> ptrs) {
+    for (const void *p : ptrs)
+        if (!p) {
+            set_error("NULL array argument");
+            return GS_ERR_INVALID;
+        }
+    return GS_OK;
+}
+
+gs_status check_ws(void *ws, size_t have, size_t need) {
+    if (!ws || have < need) {
+        set_error("workspace too small: need %zu bytes, got %zu", need, have);
+        return GS_ERR_WORKSPACE;
+    }
+    if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) {
+        set_error("workspace must be 256-byte aligned");
+        return GS_ERR_WORKSPACE;
+    }
+    return GS_OK;
+}
+
+#define GS_TRY(x)                     \
+    do {                              \
+        gs_status st_ = (x);          \
+        if (st_ != GS_OK) return st_; \
+    } while (0)
+
+// ---------------------------------------------------------------- layouts
+// Every operation lays out its buffers with the same code whether it is
+// measuring (base == nullptr) or carving the caller's workspace.
+struct ShootExactBufs {
+    ExactBufs ex;
+    double *Sq, *Sp;  // FP64 state [n][3]
+    double *Hpart;
+};
+
+ShootExactBufs layout_shoot_exact(Arena &a, int64_t n, int nt) {
+    ShootExactBufs b{};
+    ExactPlan pl = plan_exact(n, n);
+    carve_exact(a, pl, b.ex);
+    b.Sq = a.take<double>(3 * n);
+    b.Sp = a.take<double>(3 * n);
+    b.Hpart = a.take<double>((size_t)(nt + 1) * combine_blocks(n));
+    return b;
+}
+
+struct ShootF64Bufs {
+    double *q, *p, *v, *a, *Hpart;
+};
+
+ShootF64Bufs layout_shoot_f64(Arena &a, int64_t n, int nt) {
+    ShootF64Bufs b{};
+    b.q = a.take<double>(3 * n);
+    b.p = a.take<double>(3 * n);
+    b.v = a.take<double>(3 * n);
+    b.a = a.take<double>(3 * n);
+    b.Hpart = a.take<double>((size_t)(nt + 1) * combine_blocks(n));
+    return b;
+}
+
+size_t measure_bytes(int64_t n, const gs_params *prm, int32_t method, int32_t op) {
+    Arena a{nullptr, kHeader, 0};
+    const bool f64 = (prm->flags & GS_FLAG_F64) != 0;
+    switch (op) {
+        case GS_OP_RHS:
+            if (f64) break;
+            if (method == GS_EXACT) {
+                ExactBufs b;
+                carve_exact(a, plan_exact(n, n), b);
+            } else {
+                TreeBufs t;
+                carve_tree(a, n, t);
+            }
+            break;
+        case GS_OP_SHOOT:
+            if (f64) {
+                layout_shoot_f64(a, n, prm->nt);
+            } else if (method == GS_EXACT) {
+                layout_shoot_exact(a, n, prm->nt);
+            } else {
+                layout_shoot_bh(a, n, prm->nt);
+            }
+            break;
+        case GS_OP_FIELD: {
+            ExactBufs b;
+            carve_exact(a, plan_exact(n, n), b);
+            break;
+        }
+        default:
+            return 0;
+    }
+    return a.off + 256;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *gs_version(void) { return "gsbh 0.1 (gfx950, HIP)"; }
+
+const char *gs_last_error(void) { return g_err; }
+
+void gs_params_default(gs_params *p) {
+    if (!p) return;
+    p->sigma = 1.0;
+    p->cutoff_sigmas = 3.0;
+    p->theta = 0.5;
+    p->leaf_cap = 1;
+    p->nt = 40;
+    p->flags = 0;
+    p->reserved = 0;
+}
+
+size_t gs_workspace_bytes(int64_t n, const gs_params *prm, int32_t method, int32_t op) {
+    if (check_n(n) != GS_OK || !prm) return 0;
+    if (method != GS_EXACT && method != GS_BH) return 0;
+    if (op == GS_OP_SHOOT && prm->nt < 1) return 0;
+    return measure_bytes(n, prm, method, op);
+}
+
+gs_status gs_rhs_exact(const float *q, const float *p, int64_t n, const gs_params *prm,
+                       float *dq, float *dp, void *ws, size_t ws_bytes, hipStream_t stream) {
+    GS_TRY(check_n(n));
+    GS_TRY(check_params(prm, false, false));
+    if (n == 0) return GS_OK;
+    GS_TRY(check_ptrs({q, p, dq, dp}));
+    gs_params pr = *prm;
+    pr.flags &= ~GS_FLAG_F64;
+    GS_TRY(check_ws(ws, ws_bytes, measure_bytes(n, &pr, GS_EXACT, GS_OP_RHS)));
+    Arena a{static_cast<char *>(ws), kHeader, ws_bytes};
+    ExactPlan pl = plan_exact(n, n);
+    ExactBufs b;
+    carve_exact(a, pl, b);
+    const int64_t npad = pl.nsrc > pl.ntgt ? pl.nsrc : pl.ntgt;
+    GS_TRY(launch_pack(q, p, n, npad, b.Q, b.P, stream));
+    GS_TRY(launch_exact_pairs(pl, b.Q, b.P, b.Q, b.P, prm->sigma, true, b.part, stream));
+    return launch_combine_rhs(pl, b.part, prm->sigma, dq, dp, stream);
+}
+
+gs_status gs_rhs_exact_f64(const double *q, const double *p, int64_t n, const gs_params *prm,
+                           double *dq, double *dp, void *ws, size_t ws_bytes,
+                           hipStream_t stream) {
+    (void)ws;
+    (void)ws_bytes;
+    GS_TRY(check_n(n));
+    GS_TRY(check_params(prm, false, false));
+    if (n == 0) return GS_OK;
+    GS_TRY(check_ptrs({q, p, dq, dp}));
+    return launch_exact_f64(q, p, n, prm->sigma, true, dq, dp, stream);
+}
+
+gs_status gs_shoot(const float *q0, const float *p0, int64_t n, const gs_params *prm,
+                   int32_t method, float *q1, float *p1, double *H, void *ws, size_t ws_bytes,
+                   hipStream_t stream) {
+    GS_TRY(check_n(n));
+    if (method != GS_EXACT && method != GS_BH) {
+        set_error("unknown method %d", method);
+        return GS_ERR_INVALID;
+    }
+    GS_TRY(check_params(prm, true, method == GS_BH));
+    if (n == 0) return GS_OK;
+    GS_TRY(check_ptrs({q0, p0, q1, p1}));
+    gs_params pr = *prm;
+    pr.flags &= ~GS_FLAG_F64;
+    GS_TRY(check_ws(ws, ws_bytes, measure_bytes(n, &pr, method, GS_OP_SHOOT)));
+    Arena a{static_cast<char *>(ws), kHeader, ws_bytes};
+    const double dt = 1.0 / prm->nt;
+    if (method == GS_BH) {
+        ShootBhBufs b = layout_shoot_bh(a, n, prm->nt);
+        return shoot_bh(q0, p0, n, *prm, q1, p1, H, b, static_cast<char *>(ws), stream);
+    }
+    ShootExactBufs b = layout_shoot_exact(a, n, prm->nt);
+    ExactPlan pl = plan_exact(n, n);
+    const int nblk = combine_blocks(n);
+    const int64_t npad = pl.nsrc > pl.ntgt ? pl.nsrc : pl.ntgt;
+    GS_TRY(launch_pack_state(q0, p0, n, npad, b.Sq, b.Sp, b.ex.Q, b.ex.P, stream));
+    for (int t = 0; t < prm->nt; ++t) {
+        GS_TRY(launch_exact_pairs(pl, b.ex.Q, b.ex.P, b.ex.Q, b.ex.P, prm->sigma, true,
+                                  b.ex.part, stream));
+        GS_TRY(launch_combine_euler(pl, b.ex.part, prm->sigma, dt, b.Sq, b.Sp, b.ex.Q, b.ex.P,
+                                    H ? b.Hpart + (size_t)t * nblk : nullptr, stream));
+    }
+    if (H) {
+        // energy of the final state: one velocity-only pass
+        GS_TRY(launch_exact_pairs(pl, b.ex.Q, b.ex.P, b.ex.Q, b.ex.P, prm->sigma, false,
+                                  b.ex.part, stream));
+        GS_TRY(launch_combine_euler(pl, b.ex.part, prm->sigma, 0.0, b.Sq, b.Sp, b.ex.Q, b.ex.P,
+                                    b.Hpart + (size_t)prm->nt * nblk, stream));
+        GS_TRY(launch_reduce_h(b.Hpart, nblk, prm->nt + 1, H, stream));
+    }
+    return launch_unpack_state(b.Sq, b.Sp, n, q1, p1, stream);
+}
+
+gs_status gs_shoot_f64(const double *q0, const double *p0, int64_t n, const gs_params *prm,
+                       double *q1, double *p1, double *H, void *ws, size_t ws_bytes,
+                       hipStream_t stream) {
+    GS_TRY(check_n(n));
+    GS_TRY(check_params(prm, true, false));
+    if (n == 0) return GS_OK;
+    GS_TRY(check_ptrs({q0, p0, q1, p1}));
+    gs_params pr = *prm;
+    pr.flags |= GS_FLAG_F64;
+    GS_TRY(check_ws(ws, ws_bytes, measure_bytes(n, &pr, GS_EXACT, GS_OP_SHOOT)));
+    Arena a{static_cast<char *>(ws), kHeader, ws_bytes};
+    ShootF64Bufs b = layout_shoot_f64(a, n, prm->nt);
+    const int nblk = combine_blocks(n);
+    const double dt = 1.0 / prm->nt;
+    GS_TRY(launch_copy_f64(q0, b.q, 3 * n, stream));
+    GS_TRY(launch_copy_f64(p0, b.p, 3 * n, stream));
+    for (int t = 0; t < prm->nt; ++t) {
+        GS_TRY(launch_exact_f64(b.q, b.p, n, prm->sigma, true, b.v, b.a, stream));
+        GS_TRY(launch_euler_f64(b.q, b.p, b.v, b.a, n, dt,
+                                H ? b.Hpart + (size_t)t * nblk : nullptr, stream));
+    }
+    if (H) {
+        GS_TRY(launch_exact_f64(b.q, b.p, n, prm->sigma, false, b.v, b.a, stream));
+        GS_TRY(launch_euler_f64(b.q, b.p, b.v, b.a, n, 0.0, b.Hpart + (size_t)prm->nt * nblk,
+                                stream));
+        GS_TRY(launch_reduce_h(b.Hpart, nblk, prm->nt + 1, H, stream));
+    }
+    GS_TRY(launch_copy_f64(b.q, q1, 3 * n, stream));
+    return launch_copy_f64(b.p, p1, 3 * n, stream);
+}
+
+gs_status gs_rhs_bh(const float *q, const float *p, int64_t n, const gs_params *prm, float *dq,
+                    float *dp, void *ws, size_t ws_bytes, hipStream_t stream) {
+    GS_TRY(check_n(n));
+    GS_TRY(check_params(prm, false, true));
+    if (n == 0) return GS_OK;
+    GS_TRY(check_ptrs({q, p, dq, dp}));
+    gs_params pr = *prm;
+    pr.flags &= ~GS_FLAG_F64;
+    GS_TRY(check_ws(ws, ws_bytes, measure_bytes(n, &pr, GS_BH, GS_OP_RHS)));
+    Arena a{static_cast<char *>(ws), kHeader, ws_bytes};
+    TreeBufs t;
+    carve_tree(a, n, t);
+    return rhs_bh(q, p, n, *prm, dq, dp, t, static_cast<char *>(ws), stream);
+}
+
+gs_status gs_shoot_adjoint(const float *q0, const float *p0, const float *target, int64_t n,
+                           const gs_params *prm, int32_t method, double lambda,
+                           int32_t ckpt_every, double *objective, float *grad_p0, void *ws,
+                           size_t ws_bytes, hipStream_t stream) {
+    (void)q0, (void)p0, (void)target, (void)n, (void)prm, (void)method, (void)lambda;
+    (void)ckpt_every, (void)objective, (void)grad_p0, (void)ws, (void)ws_bytes, (void)stream;
+    set_error("gs_shoot_adjoint: not built yet");
+    return GS_ERR_UNSUPPORTED;
+}
+
+gs_status gs_field(const float *x, int64_t m, const float *q, const float *p, int64_t n,
+                   const gs_params *prm, float *v, void *ws, size_t ws_bytes,
+                   hipStream_t stream) {
+    (void)x, (void)m, (void)q, (void)p, (void)n, (void)prm, (void)v, (void)ws, (void)ws_bytes;
+    (void)stream;
+    set_error("gs_field: not built yet");
+    return GS_ERR_UNSUPPORTED;
+}
+
+gs_status gs_get_status(const void *ws, hipStream_t stream) {
+    if (!ws) {
+        set_error("workspace is NULL");
+        return GS_ERR_INVALID;
+    }
+    GS_HIP(hipStreamSynchronize(stream));
+    WsHeader h;
+    GS_HIP(hipMemcpy(&h, ws, sizeof(h), hipMemcpyDeviceToHost));
+    if (h.status != 0) {
+        set_error("non-finite coordinates met while building the octree");
+        return GS_ERR_NONFINITE;
+    }
+    return GS_OK;
+}
+
+gs_status gs_bh_counters(const void *ws, hipStream_t stream, int64_t out[4]) {
+    if (!ws || !out) {
+        set_error("NULL argument");
+        return GS_ERR_INVALID;
+    }
+    GS_HIP(hipStreamSynchronize(stream));
+    WsHeader h;
+    GS_HIP(hipMemcpy(&h, ws, sizeof(h), hipMemcpyDeviceToHost));
+    for (int k = 0; k < 4; ++k) out[k] = (int64_t)h.counters[k];
+    return GS_OK;
+}
+
+gs_status gs_kernel_timing(int32_t enable) {
+    TimingState &t = timing();
+    std::lock_guard<std::mutex> g(t.mu);
+    t.on = enable != 0;
+    return GS_OK;
+}
+
+gs_status gs_kernel_timing_read(int64_t counts[4], double ms[4]) {
+    TimingState &t = timing();
+    std::lock_guard<std::mutex> g(t.mu);
+    for (int k = 0; k < 4; ++k) {
+        double sum = 0.0;
+        for (auto &pr : t.ev[k]) {
+            GS_HIP(hipEventSynchronize(pr.second));
+            float e = 0.f;
+            GS_HIP(hipEventElapsedTime(&e, pr.first, pr.second));
+            sum += e;
+            (void)hipEventDestroy(pr.first);
+            (void)hipEventDestroy(pr.second);
+        }
+        if (counts) counts[k] = (int64_t)t.ev[k].size();
+        if (ms) ms[k] = sum;
+        t.ev[k].clear();
+    }
+    return GS_OK;
+}
+
+}  // extern "C"

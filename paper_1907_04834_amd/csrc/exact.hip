@@ -1,0 +1,445 @@
+// exact.hip -- exact all-pairs right-hand side (Sec. 2.1, eq. 1 and eq. 3),
+// the Euler step with the FP64 energy reduction, and the FP64 variants.
+//
+// FP32 all-pairs kernel (k_exact_pairs):
+//   * one lane owns T targets (held in registers); a wave owns 64*T
+//     consecutive targets; the source range [0, N) is split into S chunks
+//     (grid.y) so that a launch has tens of waves per SIMD;
+//   * sources are read with wave-uniform addresses, so they arrive through
+//     the scalar data cache straight into SGPRs and every pair is pure VALU
+//     work with no LDS or VGPR staging of source data;
+//   * per pair: d = q_i - q_j (exact for near pairs), r2, G = exp2(-c r2)
+//     with c = log2(e) / (2 sigma^2) on the hardware v_exp_f32, v += G p_j,
+//     w = G (p_i . p_j), a += w d;
+//   * compensation: each tile of kTile sources is summed in FP32 and the
+//     tile sums are added into FP64 accumulators, so the rounding error of a
+//     target's sum grows with the tile length, not with N;
+//   * each (split, target) writes its six FP64 partial sums; a second kernel
+//     adds the S partials in a fixed order (bitwise deterministic).
+#include "internal.h"
+
+namespace gs {
+
+namespace {
+
+constexpr double kLog2e = 1.4426950408889634074;
+
+__global__ void k_pack(const float *__restrict__ q, const float *__restrict__ p, int64_t n,
+                       int64_t npad, float4 *__restrict__ Q, float4 *__restrict__ P) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npad) return;
+    if (i < n) {
+        Q[i] = make_float4(q[3 * i], q[3 * i + 1], q[3 * i + 2], 0.f);
+        P[i] = make_float4(p[3 * i], p[3 * i + 1], p[3 * i + 2], 0.f);
+    } else {
+        // padding: zero momentum, so a padded source adds exactly zero
+        Q[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+        P[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+}
+
+// Shooting state: positions and momenta are carried in FP64 between Euler
+// steps (rounding the state to FP32 every step would perturb near-pair
+// distances by ~1e-7 / sigma per step and the flow amplifies that drift);
+// each step hands FP32 copies to the pair kernel.
+__global__ void k_pack_state(const float *__restrict__ q, const float *__restrict__ p, int64_t n,
+                             int64_t npad, double *__restrict__ Sq, double *__restrict__ Sp,
+                             float4 *__restrict__ Q, float4 *__restrict__ P) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npad) return;
+    if (i < n) {
+        const float x = q[3 * i], y = q[3 * i + 1], z = q[3 * i + 2];
+        const float u = p[3 * i], v = p[3 * i + 1], w = p[3 * i + 2];
+        Sq[3 * i] = x;
+        Sq[3 * i + 1] = y;
+        Sq[3 * i + 2] = z;
+        Sp[3 * i] = u;
+        Sp[3 * i + 1] = v;
+        Sp[3 * i + 2] = w;
+        Q[i] = make_float4(x, y, z, 0.f);
+        P[i] = make_float4(u, v, w, 0.f);
+    } else {
+        Q[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+        P[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+}
+
+__global__ void k_unpack_state(const double *__restrict__ Sq, const double *__restrict__ Sp,
+                               int64_t n, float *__restrict__ q, float *__restrict__ p) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 3 * n) return;
+    q[i] = (float)Sq[i];
+    p[i] = (float)Sp[i];
+}
+
+__global__ void k_unpack(const float4 *__restrict__ Q, const float4 *__restrict__ P, int64_t n,
+                         float *__restrict__ q, float *__restrict__ p) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float4 a = Q[i], b = P[i];
+    q[3 * i] = a.x;
+    q[3 * i + 1] = a.y;
+    q[3 * i + 2] = a.z;
+    p[3 * i] = b.x;
+    p[3 * i + 1] = b.y;
+    p[3 * i + 2] = b.z;
+}
+
+template <int T, bool WITH_A>
+__global__ __launch_bounds__(256) void k_exact_pairs(
+    const float4 *__restrict__ Qt, const float4 *__restrict__ Pt, int64_t ntgt,
+    const float4 *__restrict__ Qs, const float4 *__restrict__ Ps, int64_t chunk, int64_t nsrc,
+    float negc, double *__restrict__ part) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int64_t t0 = wave * (64 * T) + lane;
+
+    float x[T], y[T], z[T], px[T], py[T], pz[T];
+#pragma unroll
+    for (int k = 0; k < T; ++k) {
+        const float4 a = Qt[t0 + 64 * k];
+        x[k] = a.x;
+        y[k] = a.y;
+        z[k] = a.z;
+        if (WITH_A) {
+            const float4 b = Pt[t0 + 64 * k];
+            px[k] = b.x;
+            py[k] = b.y;
+            pz[k] = b.z;
+        }
+    }
+    double sv[T][3], sa[T][3];
+#pragma unroll
+    for (int k = 0; k < T; ++k)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) sv[k][c] = sa[k][c] = 0.0;
+
+    const int64_t j0 = (int64_t)blockIdx.y * chunk;
+    const int64_t j1 = j0 + chunk < nsrc ? j0 + chunk : nsrc;
+    for (int64_t jt = j0; jt < j1; jt += kTile) {
+        float tv[T][3], ta[T][3];
+#pragma unroll
+        for (int k = 0; k < T; ++k)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) tv[k][c] = ta[k][c] = 0.f;
+#pragma unroll 8
+        for (int u = 0; u < kTile; ++u) {
+            const float4 qj = Qs[jt + u];
+            const float4 pj = Ps[jt + u];
+#pragma unroll
+            for (int k = 0; k < T; ++k) {
+                const float dx = x[k] - qj.x, dy = y[k] - qj.y, dz = z[k] - qj.z;
+                const float r2 = dx * dx + dy * dy + dz * dz;
+                const float g = __builtin_amdgcn_exp2f(r2 * negc);
+                tv[k][0] += g * pj.x;
+                tv[k][1] += g * pj.y;
+                tv[k][2] += g * pj.z;
+                if (WITH_A) {
+                    const float w = g * (px[k] * pj.x + py[k] * pj.y + pz[k] * pj.z);
+                    ta[k][0] += w * dx;
+                    ta[k][1] += w * dy;
+                    ta[k][2] += w * dz;
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < T; ++k)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                sv[k][c] += (double)tv[k][c];
+                if (WITH_A) sa[k][c] += (double)ta[k][c];
+            }
+    }
+    double *dst = part + (int64_t)blockIdx.y * 6 * ntgt;
+#pragma unroll
+    for (int k = 0; k < T; ++k) {
+        const int64_t i = t0 + 64 * k;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            dst[c * ntgt + i] = sv[k][c];
+            if (WITH_A) dst[(3 + c) * ntgt + i] = sa[k][c];
+        }
+    }
+}
+
+__device__ inline double block_sum_f64(double v, double *lds) {
+    // Fixed reduction tree: wave shuffle, then the per-wave sums in order.
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if ((threadIdx.x & 63) == 0) lds[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < nw; ++k) s += lds[k];
+    return s;
+}
+
+__global__ __launch_bounds__(256) void k_combine_rhs(const double *__restrict__ part, int splits,
+                                                     int64_t ntgt, int64_t n, double inv_s2,
+                                                     float *__restrict__ dq,
+                                                     float *__restrict__ dp) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int s = 0; s < splits; ++s)
+#pragma unroll
+        for (int c = 0; c < 6; ++c) acc[c] += part[((int64_t)s * 6 + c) * ntgt + i];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        dq[3 * i + c] = (float)acc[c];
+        if (dp) dp[3 * i + c] = (float)(acc[3 + c] * inv_s2);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_combine_euler(const double *__restrict__ part,
+                                                       int splits, int64_t ntgt, int64_t n,
+                                                       double inv_s2, double dt,
+                                                       double *__restrict__ Sq,
+                                                       double *__restrict__ Sp,
+                                                       float4 *__restrict__ Q,
+                                                       float4 *__restrict__ P,
+                                                       double *__restrict__ Hpart) {
+    __shared__ double lds[8];
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double e = 0.0;
+    if (i < n) {
+        double acc[6] = {0, 0, 0, 0, 0, 0};
+        for (int s = 0; s < splits; ++s)
+#pragma unroll
+            for (int c = 0; c < 6; ++c) acc[c] += part[((int64_t)s * 6 + c) * ntgt + i];
+        double q[3], p[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            q[c] = Sq[3 * i + c];
+            p[c] = Sp[3 * i + c];
+        }
+        e = p[0] * acc[0] + p[1] * acc[1] + p[2] * acc[2];
+        if (dt > 0.0) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                q[c] += dt * acc[c];
+                p[c] += dt * (acc[3 + c] * inv_s2);
+                Sq[3 * i + c] = q[c];
+                Sp[3 * i + c] = p[c];
+            }
+            Q[i] = make_float4((float)q[0], (float)q[1], (float)q[2], 0.f);
+            P[i] = make_float4((float)p[0], (float)p[1], (float)p[2], 0.f);
+        }
+    }
+    if (Hpart) {
+        double s = block_sum_f64(e, lds);
+        if (threadIdx.x == 0) Hpart[blockIdx.x] = s;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_reduce_h(const double *__restrict__ Hpart, int nblk,
+                                                  double *__restrict__ H) {
+    __shared__ double lds[8];
+    const int t = blockIdx.x;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x) s += Hpart[(int64_t)t * nblk + b];
+    s = block_sum_f64(s, lds);
+    if (threadIdx.x == 0) H[t] = s;
+}
+
+// ---------------------------------------------------------------- FP64 path
+template <bool WITH_A>
+__global__ __launch_bounds__(256) void k_exact_f64(const double *__restrict__ q,
+                                                   const double *__restrict__ p, int64_t n,
+                                                   double sigma, double *__restrict__ v,
+                                                   double *__restrict__ a) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = i < n;
+    const int64_t ii = live ? i : 0;
+    const double xi = q[3 * ii], yi = q[3 * ii + 1], zi = q[3 * ii + 2];
+    const double pxi = p[3 * ii], pyi = p[3 * ii + 1], pzi = p[3 * ii + 2];
+    const double m = -1.0 / (2.0 * sigma * sigma);
+    double vx = 0, vy = 0, vz = 0, ax = 0, ay = 0, az = 0;
+    for (int64_t j = 0; j < n; ++j) {
+        const double dx = xi - q[3 * j], dy = yi - q[3 * j + 1], dz = zi - q[3 * j + 2];
+        const double g = exp((dx * dx + dy * dy + dz * dz) * m);
+        const double pjx = p[3 * j], pjy = p[3 * j + 1], pjz = p[3 * j + 2];
+        vx += g * pjx;
+        vy += g * pjy;
+        vz += g * pjz;
+        if (WITH_A) {
+            const double w = g * (pxi * pjx + pyi * pjy + pzi * pjz);
+            ax += w * dx;
+            ay += w * dy;
+            az += w * dz;
+        }
+    }
+    if (!live) return;
+    v[3 * i] = vx;
+    v[3 * i + 1] = vy;
+    v[3 * i + 2] = vz;
+    if (WITH_A) {
+        const double inv = 1.0 / (sigma * sigma);
+        a[3 * i] = ax * inv;
+        a[3 * i + 1] = ay * inv;
+        a[3 * i + 2] = az * inv;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_euler_f64(double *__restrict__ q, double *__restrict__ p,
+                                                   const double *__restrict__ v,
+                                                   const double *__restrict__ a, int64_t n,
+                                                   double dt, double *__restrict__ Hpart) {
+    __shared__ double lds[8];
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double e = 0.0;
+    if (i < n) {
+        e = p[3 * i] * v[3 * i] + p[3 * i + 1] * v[3 * i + 1] + p[3 * i + 2] * v[3 * i + 2];
+        if (dt > 0.0)
+            for (int c = 0; c < 3; ++c) {
+                q[3 * i + c] += dt * v[3 * i + c];
+                p[3 * i + c] += dt * a[3 * i + c];
+            }
+    }
+    if (Hpart) {
+        double s = block_sum_f64(e, lds);
+        if (threadIdx.x == 0) Hpart[blockIdx.x] = s;
+    }
+}
+
+__global__ void k_copy_f64(const double *__restrict__ s, double *__restrict__ d, int64_t count) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) d[i] = s[i];
+}
+
+inline unsigned nblocks(int64_t n, int b = kBlock) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+// ---------------------------------------------------------------- planning
+ExactPlan plan_exact(int64_t n_targets, int64_t n_sources) {
+    ExactPlan pl{};
+    pl.n = n_targets;
+    pl.tpl = 2;
+    const int64_t tgt_per_block = 64 * pl.tpl * 4;
+    pl.ntgt = round_up(n_targets > 0 ? n_targets : 1, tgt_per_block);
+    pl.nsrc = round_up(n_sources > 0 ? n_sources : 1, kTile);
+    // Aim at ~24 waves per SIMD (1024 SIMDs) so that the per-SIMD work is
+    // balanced to a few percent; never split below one tile per split.
+    const int64_t waves_t = pl.ntgt / (64 * pl.tpl);
+    int64_t s = (24 * 1024 + waves_t - 1) / waves_t;
+    const int64_t max_s = pl.nsrc / kTile;
+    if (s > max_s) s = max_s;
+    if (s > 64) s = 64;
+    if (s < 1) s = 1;
+    pl.chunk = round_up((pl.nsrc + s - 1) / s, kTile);
+    pl.splits = (int)((pl.nsrc + pl.chunk - 1) / pl.chunk);
+    return pl;
+}
+
+void carve_exact(Arena &a, const ExactPlan &pl, ExactBufs &b) {
+    const int64_t m = pl.nsrc > pl.ntgt ? pl.nsrc : pl.ntgt;
+    b.Q = a.take<float4>(m);
+    b.P = a.take<float4>(m);
+    b.part = a.take<double>((size_t)pl.splits * 6 * pl.ntgt);
+}
+
+int combine_blocks(int64_t n) { return (int)nblocks(n > 0 ? n : 1); }
+
+// ---------------------------------------------------------------- launchers
+gs_status launch_pack(const float *q, const float *p, int64_t n, int64_t npad, float4 *Q,
+                      float4 *P, hipStream_t s) {
+    hipLaunchKernelGGL(k_pack, dim3(nblocks(npad)), dim3(kBlock), 0, s, q, p, n, npad, Q, P);
+    GS_LAUNCH_CHECK("pack");
+    return GS_OK;
+}
+
+gs_status launch_unpack(const float4 *Q, const float4 *P, int64_t n, float *q, float *p,
+                        hipStream_t s) {
+    hipLaunchKernelGGL(k_unpack, dim3(nblocks(n)), dim3(kBlock), 0, s, Q, P, n, q, p);
+    GS_LAUNCH_CHECK("unpack");
+    return GS_OK;
+}
+
+gs_status launch_exact_pairs(const ExactPlan &pl, const float4 *Qt, const float4 *Pt,
+                             const float4 *Qs, const float4 *Ps, double sigma, bool with_a,
+                             double *part, hipStream_t s) {
+    const float negc = (float)(-kLog2e / (2.0 * sigma * sigma));
+    dim3 grid((unsigned)(pl.ntgt / (64 * pl.tpl * 4)), (unsigned)pl.splits);
+    timing_begin(KIND_EXACT, s);
+    if (with_a)
+        hipLaunchKernelGGL((k_exact_pairs<2, true>), grid, dim3(256), 0, s, Qt, Pt, pl.ntgt, Qs,
+                           Ps, pl.chunk, pl.nsrc, negc, part);
+    else
+        hipLaunchKernelGGL((k_exact_pairs<2, false>), grid, dim3(256), 0, s, Qt, Pt, pl.ntgt,
+                           Qs, Ps, pl.chunk, pl.nsrc, negc, part);
+    timing_end(KIND_EXACT, s);
+    GS_LAUNCH_CHECK("exact_pairs");
+    return GS_OK;
+}
+
+gs_status launch_combine_rhs(const ExactPlan &pl, const double *part, double sigma, float *dq,
+                             float *dp, hipStream_t s) {
+    hipLaunchKernelGGL(k_combine_rhs, dim3(nblocks(pl.n)), dim3(kBlock), 0, s, part, pl.splits,
+                       pl.ntgt, pl.n, 1.0 / (sigma * sigma), dq, dp);
+    GS_LAUNCH_CHECK("combine_rhs");
+    return GS_OK;
+}
+
+gs_status launch_combine_euler(const ExactPlan &pl, const double *part, double sigma, double dt,
+                               double *Sq, double *Sp, float4 *Q, float4 *P, double *Hpart,
+                               hipStream_t s) {
+    hipLaunchKernelGGL(k_combine_euler, dim3(nblocks(pl.n)), dim3(kBlock), 0, s, part,
+                       pl.splits, pl.ntgt, pl.n, 1.0 / (sigma * sigma), dt, Sq, Sp, Q, P,
+                       Hpart);
+    GS_LAUNCH_CHECK("combine_euler");
+    return GS_OK;
+}
+
+gs_status launch_pack_state(const float *q, const float *p, int64_t n, int64_t npad, double *Sq,
+                            double *Sp, float4 *Q, float4 *P, hipStream_t s) {
+    hipLaunchKernelGGL(k_pack_state, dim3(nblocks(npad)), dim3(kBlock), 0, s, q, p, n, npad, Sq,
+                       Sp, Q, P);
+    GS_LAUNCH_CHECK("pack_state");
+    return GS_OK;
+}
+
+gs_status launch_unpack_state(const double *Sq, const double *Sp, int64_t n, float *q, float *p,
+                              hipStream_t s) {
+    hipLaunchKernelGGL(k_unpack_state, dim3(nblocks(3 * n)), dim3(kBlock), 0, s, Sq, Sp, n, q,
+                       p);
+    GS_LAUNCH_CHECK("unpack_state");
+    return GS_OK;
+}
+
+gs_status launch_reduce_h(const double *Hpart, int nblk, int count, double *H, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_h, dim3((unsigned)count), dim3(kBlock), 0, s, Hpart, nblk, H);
+    GS_LAUNCH_CHECK("reduce_h");
+    return GS_OK;
+}
+
+gs_status launch_exact_f64(const double *q, const double *p, int64_t n, double sigma,
+                           bool with_a, double *v, double *a, hipStream_t s) {
+    timing_begin(KIND_EXACT, s);
+    if (with_a)
+        hipLaunchKernelGGL(k_exact_f64<true>, dim3(nblocks(n)), dim3(kBlock), 0, s, q, p, n,
+                           sigma, v, a);
+    else
+        hipLaunchKernelGGL(k_exact_f64<false>, dim3(nblocks(n)), dim3(kBlock), 0, s, q, p, n,
+                           sigma, v, a);
+    timing_end(KIND_EXACT, s);
+    GS_LAUNCH_CHECK("exact_f64");
+    return GS_OK;
+}
+
+gs_status launch_euler_f64(double *q, double *p, const double *v, const double *a, int64_t n,
+                           double dt, double *Hpart, hipStream_t s) {
+    hipLaunchKernelGGL(k_euler_f64, dim3(nblocks(n)), dim3(kBlock), 0, s, q, p, v, a, n, dt,
+                       Hpart);
+    GS_LAUNCH_CHECK("euler_f64");
+    return GS_OK;
+}
+
+gs_status launch_copy_f64(const double *src, double *dst, int64_t count, hipStream_t s) {
+    hipLaunchKernelGGL(k_copy_f64, dim3(nblocks(count)), dim3(kBlock), 0, s, src, dst, count);
+    GS_LAUNCH_CHECK("copy_f64");
+    return GS_OK;
+}
+
+}  // namespace gs

@@ -1,0 +1,110 @@
+// internal.h -- declarations shared by the HIP translation units of the
+// geodesic-shooting library (kernel launchers, workspace layout, errors).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "gs.h"
+
+namespace gs {
+
+// ---------------------------------------------------------------- errors
+void set_error(const char *fmt, ...);
+gs_status hip_fail(hipError_t e, const char *what);
+
+#define GS_HIP(call)                                       \
+    do {                                                   \
+        hipError_t e_ = (call);                            \
+        if (e_ != hipSuccess) return hip_fail(e_, #call);  \
+    } while (0)
+#define GS_LAUNCH_CHECK(what)                              \
+    do {                                                   \
+        hipError_t e_ = hipGetLastError();                 \
+        if (e_ != hipSuccess) return hip_fail(e_, what);   \
+    } while (0)
+
+// ---------------------------------------------------------------- timing
+enum TimedKind { KIND_EXACT = 0, KIND_TRAVERSE = 1, KIND_ADJOINT = 2, KIND_TREE = 3 };
+// Bracket a launch of a timed kernel (no-ops unless timing is enabled).
+void timing_begin(int kind, hipStream_t s);
+void timing_end(int kind, hipStream_t s);
+
+// ---------------------------------------------------------------- workspace
+// A bump allocator over the caller's workspace; with base == nullptr it only
+// measures.
+struct Arena {
+    char *base;
+    size_t off;
+    size_t cap;
+    template <class T>
+    T *take(size_t count) {
+        off = (off + 255) & ~size_t(255);
+        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+constexpr int kTile = 64;       // sources per compensated tile (exact FP32 kernel)
+constexpr int kBlock = 256;     // threads per block for O(N) kernels
+
+inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+// Source split of the exact all-pairs kernel: number of source ranges that
+// the targets' sums are split over so that a launch has enough waves.
+struct ExactPlan {
+    int64_t n;        // real points
+    int64_t nsrc;     // padded source count (multiple of kTile)
+    int64_t ntgt;     // padded target count
+    int splits;       // S
+    int64_t chunk;    // sources per split (multiple of kTile)
+    int tpl;          // targets per lane
+};
+ExactPlan plan_exact(int64_t n_targets, int64_t n_sources);
+
+// Buffers of one exact FP32 RHS evaluation.
+struct ExactBufs {
+    float4 *Q;        // [nsrc] x, y, z, 0
+    float4 *P;        // [nsrc] px, py, pz, 0
+    double *part;     // [S][6][ntgt]
+};
+void carve_exact(Arena &a, const ExactPlan &pl, ExactBufs &b);
+
+// ---------------------------------------------------------------- launchers
+// exact.hip
+gs_status launch_pack(const float *q, const float *p, int64_t n, int64_t npad, float4 *Q,
+                      float4 *P, hipStream_t s);
+gs_status launch_unpack(const float4 *Q, const float4 *P, int64_t n, float *q, float *p,
+                        hipStream_t s);
+gs_status launch_exact_pairs(const ExactPlan &pl, const float4 *Qt, const float4 *Pt,
+                             const float4 *Qs, const float4 *Ps, double sigma, bool with_a,
+                             double *part, hipStream_t s);
+// Sums the split partials of target i and writes (v, a) as float [n][3].
+gs_status launch_combine_rhs(const ExactPlan &pl, const double *part, double sigma,
+                             float *dq, float *dp, hipStream_t s);
+// Sums the partials, adds p_i . v_i of each block into Hpart (nullable), and,
+// if dt > 0, advances the FP64 state (Sq += dt v, Sp += dt a) and refreshes
+// its FP32 copies Q, P.
+gs_status launch_combine_euler(const ExactPlan &pl, const double *part, double sigma,
+                               double dt, double *Sq, double *Sp, float4 *Q, float4 *P,
+                               double *Hpart, hipStream_t s);
+// FP64 state from float [n][3] inputs, plus its FP32 packed copies.
+gs_status launch_pack_state(const float *q, const float *p, int64_t n, int64_t npad, double *Sq,
+                            double *Sp, float4 *Q, float4 *P, hipStream_t s);
+gs_status launch_unpack_state(const double *Sq, const double *Sp, int64_t n, float *q, float *p,
+                              hipStream_t s);
+int combine_blocks(int64_t n);
+// H[t] = sum_b Hpart[t * nblk + b] for t in [0, count).
+gs_status launch_reduce_h(const double *Hpart, int nblk, int count, double *H, hipStream_t s);
+
+// FP64 exact path.
+gs_status launch_exact_f64(const double *q, const double *p, int64_t n, double sigma,
+                           bool with_a, double *v, double *a, hipStream_t s);
+gs_status launch_euler_f64(double *q, double *p, const double *v, const double *a,
+                           int64_t n, double dt, double *Hpart, hipStream_t s);
+gs_status launch_copy_f64(const double *src, double *dst, int64_t count, hipStream_t s);
+
+}  // namespace gs

@@ -1,0 +1,266 @@
+"""Python binding of the C ABI in include/gs.h (argument marshalling only).
+
+Every function here takes torch tensors that live on a ROCm device, allocates
+the outputs and the workspace with torch, and calls the entry point of the
+same name in libgsbh.so on torch's current stream.  All arithmetic runs in the
+library's HIP kernels; if the library is missing this module raises instead
+of computing anything itself.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libgsbh.so")
+
+GS_EXACT, GS_BH = 0, 1
+GS_OP_RHS, GS_OP_SHOOT, GS_OP_ADJOINT, GS_OP_FIELD = 0, 1, 2, 3
+GS_FLAG_F64 = 1
+STATUS = {0: "GS_OK", -1: "GS_ERR_INVALID", -2: "GS_ERR_WORKSPACE", -3: "GS_ERR_HIP",
+          -4: "GS_ERR_NONFINITE", -5: "GS_ERR_UNSUPPORTED"}
+
+
+class GsError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("sigma", ctypes.c_double), ("cutoff_sigmas", ctypes.c_double),
+                ("theta", ctypes.c_double), ("leaf_cap", ctypes.c_int32),
+                ("nt", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("reserved", ctypes.c_int32)]
+
+
+def params(sigma, nt=40, theta=0.5, cutoff_sigmas=3.0, leaf_cap=1, flags=0) -> Params:
+    return Params(float(sigma), float(cutoff_sigmas), float(theta), int(leaf_cap),
+                  int(nt), int(flags), 0)
+
+
+_lib = None
+_vp, _i64, _i32, _sz, _dbl = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                              ctypes.c_size_t, ctypes.c_double)
+_PP = ctypes.POINTER(Params)
+
+# name -> (restype, argtypes); the order follows include/gs.h
+_SIGS = {
+    "gs_version": (ctypes.c_char_p, []),
+    "gs_last_error": (ctypes.c_char_p, []),
+    "gs_params_default": (None, [_PP]),
+    "gs_workspace_bytes": (_sz, [_i64, _PP, _i32, _i32]),
+    "gs_rhs_exact": (ctypes.c_int, [_vp, _vp, _i64, _PP, _vp, _vp, _vp, _sz, _vp]),
+    "gs_rhs_exact_f64": (ctypes.c_int, [_vp, _vp, _i64, _PP, _vp, _vp, _vp, _sz, _vp]),
+    "gs_rhs_bh": (ctypes.c_int, [_vp, _vp, _i64, _PP, _vp, _vp, _vp, _sz, _vp]),
+    "gs_shoot": (ctypes.c_int, [_vp, _vp, _i64, _PP, _i32, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "gs_shoot_f64": (ctypes.c_int, [_vp, _vp, _i64, _PP, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "gs_shoot_adjoint": (ctypes.c_int, [_vp, _vp, _vp, _i64, _PP, _i32, _dbl, _i32, _vp,
+                                        _vp, _vp, _sz, _vp]),
+    "gs_field": (ctypes.c_int, [_vp, _i64, _vp, _vp, _i64, _PP, _vp, _vp, _sz, _vp]),
+    "gs_get_status": (ctypes.c_int, [_vp, _vp]),
+    "gs_bh_counters": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(ctypes.c_int64)]),
+    "gs_kernel_timing": (ctypes.c_int, [_i32]),
+    "gs_kernel_timing_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int64),
+                                             ctypes.POINTER(ctypes.c_double)]),
+}
+EXPORTS = tuple(_SIGS)
+
+
+def lib():
+    """Load libgsbh.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(
+                f"{LIB_PATH} is missing: build it with `python -m paper_1907_04834_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != 0:
+        raise GsError(status, lib().gs_last_error().decode())
+
+
+def _stream(dev):
+    return ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else None
+
+
+def _pts(x, dtype, name):
+    if not isinstance(x, torch.Tensor) or not x.is_cuda:
+        raise TypeError(f"{name} must be a ROCm device tensor")
+    if x.dtype != dtype or x.dim() != 2 or x.shape[1] != 3 or not x.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous ({dtype}) tensor of shape (n, 3)")
+    return x
+
+
+def _workspace(n, prm, method, op, dev):
+    nbytes = lib().gs_workspace_bytes(n, ctypes.byref(prm), method, op)
+    if nbytes == 0:
+        raise GsError(-1, "invalid arguments for gs_workspace_bytes")
+    # torch's caching allocator returns 512-byte aligned blocks
+    return torch.empty(nbytes, dtype=torch.uint8, device=dev)
+
+
+def gs_version() -> str:
+    return lib().gs_version().decode()
+
+
+def gs_workspace_bytes(n, prm: Params, method=GS_EXACT, op=GS_OP_RHS) -> int:
+    return int(lib().gs_workspace_bytes(n, ctypes.byref(prm), method, op))
+
+
+def gs_rhs_exact(q, p, prm: Params, ws=None):
+    """(dq, dp) = (v, a) of the exact right-hand side; float32 (n, 3)."""
+    _pts(q, torch.float32, "q")
+    _pts(p, torch.float32, "p")
+    n = q.shape[0]
+    dq, dp = torch.empty_like(q), torch.empty_like(q)
+    if ws is None:
+        ws = _workspace(n, prm, GS_EXACT, GS_OP_RHS, q.device)
+    _check(lib().gs_rhs_exact(_ptr(q), _ptr(p), n, ctypes.byref(prm), _ptr(dq), _ptr(dp),
+                              _ptr(ws), ws.numel(), _stream(q.device)))
+    return dq, dp
+
+
+def gs_rhs_exact_f64(q, p, prm: Params):
+    _pts(q, torch.float64, "q")
+    _pts(p, torch.float64, "p")
+    n = q.shape[0]
+    dq, dp = torch.empty_like(q), torch.empty_like(q)
+    _check(lib().gs_rhs_exact_f64(_ptr(q), _ptr(p), n, ctypes.byref(prm), _ptr(dq),
+                                  _ptr(dp), None, 0, _stream(q.device)))
+    return dq, dp
+
+
+def gs_rhs_bh(q, p, prm: Params, ws=None, return_ws=False):
+    """(dq, dp) of the Barnes-Hut right-hand side; float32 (n, 3)."""
+    _pts(q, torch.float32, "q")
+    _pts(p, torch.float32, "p")
+    n = q.shape[0]
+    dq, dp = torch.empty_like(q), torch.empty_like(q)
+    if ws is None:
+        ws = _workspace(n, prm, GS_BH, GS_OP_RHS, q.device)
+    _check(lib().gs_rhs_bh(_ptr(q), _ptr(p), n, ctypes.byref(prm), _ptr(dq), _ptr(dp),
+                           _ptr(ws), ws.numel(), _stream(q.device)))
+    return (dq, dp, ws) if return_ws else (dq, dp)
+
+
+def gs_shoot(q0, p0, prm: Params, method=GS_EXACT, with_energy=True, ws=None):
+    """Forward-Euler shooting; returns (q1, p1, H) with H float64 (nt+1,) or None."""
+    _pts(q0, torch.float32, "q0")
+    _pts(p0, torch.float32, "p0")
+    n = q0.shape[0]
+    q1, p1 = torch.empty_like(q0), torch.empty_like(p0)
+    H = torch.zeros(prm.nt + 1, dtype=torch.float64, device=q0.device) if with_energy else None
+    if ws is None:
+        ws = _workspace(n, prm, method, GS_OP_SHOOT, q0.device)
+    _check(lib().gs_shoot(_ptr(q0), _ptr(p0), n, ctypes.byref(prm), method, _ptr(q1),
+                          _ptr(p1), _ptr(H), _ptr(ws), ws.numel(), _stream(q0.device)))
+    return q1, p1, H
+
+
+def gs_shoot_f64(q0, p0, prm: Params, with_energy=True):
+    _pts(q0, torch.float64, "q0")
+    _pts(p0, torch.float64, "p0")
+    n = q0.shape[0]
+    q1, p1 = torch.empty_like(q0), torch.empty_like(p0)
+    H = torch.zeros(prm.nt + 1, dtype=torch.float64, device=q0.device) if with_energy else None
+    pr = Params.from_buffer_copy(prm)
+    pr.flags |= GS_FLAG_F64
+    ws = _workspace(n, pr, GS_EXACT, GS_OP_SHOOT, q0.device)
+    _check(lib().gs_shoot_f64(_ptr(q0), _ptr(p0), n, ctypes.byref(prm), _ptr(q1), _ptr(p1),
+                              _ptr(H), _ptr(ws), ws.numel(), _stream(q0.device)))
+    return q1, p1, H
+
+
+def gs_shoot_adjoint(q0, p0, target, prm: Params, method=GS_EXACT, lam=0.01, ckpt_every=8,
+                     ws=None):
+    """Objective E(p0) (float64 scalar tensor) and dE/dp0 (float32 (n, 3))."""
+    _pts(q0, torch.float32, "q0")
+    _pts(p0, torch.float32, "p0")
+    _pts(target, torch.float32, "target")
+    n = q0.shape[0]
+    obj = torch.zeros(1, dtype=torch.float64, device=q0.device)
+    grad = torch.empty_like(p0)
+    if ws is None:
+        pr = Params.from_buffer_copy(prm)
+        nbytes = lib().gs_workspace_bytes(n, ctypes.byref(pr), method, GS_OP_ADJOINT)
+        if nbytes == 0:
+            raise GsError(-1, "invalid arguments for gs_workspace_bytes")
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=q0.device)
+    _check(lib().gs_shoot_adjoint(_ptr(q0), _ptr(p0), _ptr(target), n, ctypes.byref(prm),
+                                  method, float(lam), int(ckpt_every), _ptr(obj), _ptr(grad),
+                                  _ptr(ws), ws.numel(), _stream(q0.device)))
+    return obj[0], grad
+
+
+def gs_field(x, q, p, prm: Params):
+    """Velocity field of eq. (3) at points x; float32 (m, 3)."""
+    _pts(x, torch.float32, "x")
+    _pts(q, torch.float32, "q")
+    _pts(p, torch.float32, "p")
+    v = torch.empty_like(x)
+    nmax = max(x.shape[0], q.shape[0])
+    ws = _workspace(nmax, prm, GS_EXACT, GS_OP_FIELD, x.device)
+    _check(lib().gs_field(_ptr(x), x.shape[0], _ptr(q), _ptr(p), q.shape[0], ctypes.byref(prm),
+                          _ptr(v), _ptr(ws), ws.numel(), _stream(x.device)))
+    return v
+
+
+def gs_get_status(ws) -> int:
+    return int(lib().gs_get_status(_ptr(ws), _stream(ws.device)))
+
+
+def gs_bh_counters(ws) -> dict:
+    out = (ctypes.c_int64 * 4)()
+    _check(lib().gs_bh_counters(_ptr(ws), _stream(ws.device), out))
+    return {"pairs": out[0], "monopoles": out[1], "visits": out[2], "nodes": out[3]}
+
+
+def gs_kernel_timing(enable: bool):
+    _check(lib().gs_kernel_timing(1 if enable else 0))
+
+
+KINDS = ("exact", "traverse", "adjoint", "tree")
+
+
+def gs_kernel_timing_read() -> dict:
+    c = (ctypes.c_int64 * 4)()
+    ms = (ctypes.c_double * 4)()
+    _check(lib().gs_kernel_timing_read(c, ms))
+    return {k: {"launches": int(c[i]), "ms": float(ms[i])} for i, k in enumerate(KINDS)}
+
+
+@dataclass
+class Shot:
+    q1: torch.Tensor
+    p1: torch.Tensor
+    H: torch.Tensor | None
+
+
+def shoot(q0, p0, sigma, nt=40, method="exact", theta=0.5, leaf_cap=1, cutoff_sigmas=3.0):
+    """Convenience wrapper: shoot FP32 (or FP64 exact) point sets."""
+    prm = params(sigma, nt=nt, theta=theta, leaf_cap=leaf_cap, cutoff_sigmas=cutoff_sigmas)
+    if q0.dtype == torch.float64:
+        if method != "exact":
+            raise GsError(-5, "FP64 shooting is exact only")
+        return Shot(*gs_shoot_f64(q0, p0, prm))
+    return Shot(*gs_shoot(q0, p0, prm, GS_EXACT if method == "exact" else GS_BH))
+
+
+INF = math.inf

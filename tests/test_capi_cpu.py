@@ -1,0 +1,97 @@
+"""C-ABI contract checks that need no GPU: the library loads, exports every
+entry point that include/gs.h declares, sizes workspaces, and rejects bad
+arguments before any device work is enqueued."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+from paper_1907_04834_amd import gs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "gs.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gs_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = gs.lib()
+    names = declared_symbols()
+    assert len(names) >= 14
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) == set(gs.EXPORTS)
+
+
+def test_version_and_defaults():
+    assert "gfx950" in gs.gs_version()
+    p = gs.Params()
+    gs.lib().gs_params_default(ctypes.byref(p))
+    assert (p.sigma, p.cutoff_sigmas, p.theta, p.leaf_cap, p.nt) == (1.0, 3.0, 0.5, 1, 40)
+
+
+def test_workspace_sizes():
+    prm = gs.params(0.05, nt=40)
+    small = gs.gs_workspace_bytes(1000, prm, gs.GS_EXACT, gs.GS_OP_RHS)
+    big = gs.gs_workspace_bytes(200000, prm, gs.GS_EXACT, gs.GS_OP_RHS)
+    assert 0 < small < big
+    assert gs.gs_workspace_bytes(200000, prm, gs.GS_BH, gs.GS_OP_RHS) > 0
+    assert gs.gs_workspace_bytes(200000, prm, gs.GS_EXACT, gs.GS_OP_SHOOT) >= big
+    assert gs.gs_workspace_bytes(-1, prm, gs.GS_EXACT, gs.GS_OP_RHS) == 0
+    assert gs.gs_workspace_bytes(10, prm, 7, gs.GS_OP_RHS) == 0
+
+
+def _call(name, *args):
+    return getattr(gs.lib(), name)(*args)
+
+
+FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+
+
+@pytest.mark.parametrize("field,value", [("sigma", 0.0), ("sigma", -1.0),
+                                         ("sigma", math.nan), ("sigma", math.inf)])
+def test_rejects_bad_sigma(field, value):
+    prm = gs.params(0.1)
+    setattr(prm, field, value)
+    st = _call("gs_rhs_exact", FAKE, FAKE, 10, ctypes.byref(prm), FAKE, FAKE, FAKE, 1 << 30,
+               None)
+    assert st == -1
+    assert "sigma" in gs.lib().gs_last_error().decode()
+
+
+@pytest.mark.parametrize("field,value", [("theta", -0.1), ("theta", math.nan),
+                                         ("cutoff_sigmas", 0.0), ("leaf_cap", 0),
+                                         ("leaf_cap", 65), ("nt", 0)])
+def test_rejects_bad_tree_params(field, value):
+    prm = gs.params(0.1)
+    setattr(prm, field, value)
+    st = _call("gs_shoot", FAKE, FAKE, 10, ctypes.byref(prm), gs.GS_BH, FAKE, FAKE, None,
+               FAKE, 1 << 30, None)
+    assert st == -1
+
+
+def test_rejects_negative_n_null_and_small_workspace():
+    prm = gs.params(0.1)
+    assert _call("gs_rhs_exact", FAKE, FAKE, -5, ctypes.byref(prm), FAKE, FAKE, FAKE, 1 << 30,
+                 None) == -1
+    assert _call("gs_rhs_exact", None, FAKE, 10, ctypes.byref(prm), FAKE, FAKE, FAKE, 1 << 30,
+                 None) == -1
+    st = _call("gs_rhs_exact", FAKE, FAKE, 10, ctypes.byref(prm), FAKE, FAKE, FAKE, 16, None)
+    assert st == -2
+    assert "workspace" in gs.lib().gs_last_error().decode()
+    st = _call("gs_shoot", FAKE, FAKE, 10, ctypes.byref(prm), 3, FAKE, FAKE, None, FAKE,
+               1 << 30, None)
+    assert st == -1
+
+
+def test_zero_points_is_a_noop():
+    prm = gs.params(0.1)
+    assert _call("gs_rhs_exact", None, None, 0, ctypes.byref(prm), None, None, None, 0,
+                 None) == 0
+    assert _call("gs_shoot", None, None, 0, ctypes.byref(prm), gs.GS_BH, None, None, None,
+                 None, 0, None) == 0
