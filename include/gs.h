@@ -160,20 +160,24 @@ gs_status gs_field(const float *x, int64_t m, const float *q, const float *p, in
  * Barnes-Hut call that used this workspace (GS_OK or GS_ERR_NONFINITE). */
 gs_status gs_get_status(const void *ws, hipStream_t stream);
 
-/* Waits for `stream` and copies the counters of the last Barnes-Hut RHS that
- * used this workspace: out[0] exact pairs, out[1] monopoles (approximated
- * nodes), out[2] node visits, out[3] octree nodes.  Counts are summed over
- * all targets of the last evaluated RHS. */
+/* Waits for `stream` and copies the counters of the last Barnes-Hut call
+ * (gs_rhs_bh or gs_shoot with GS_BH) that used this workspace, summed over
+ * all targets and all right-hand sides that call evaluated (nt + 1 for a
+ * shooting that returns H, nt otherwise): out[0] exact pairs, out[1]
+ * monopoles (approximated nodes), out[2] node visits, out[3] octree nodes. */
 gs_status gs_bh_counters(const void *ws, hipStream_t stream, int64_t out[4]);
 
-/* Per-launch timing of the dominant pair kernels.  While enabled, every
- * launch of a pair kernel (exact all-pairs, Barnes-Hut traversal, adjoint
- * pairs) is bracketed by HIP events on its stream.  gs_kernel_timing_read
- * waits for the recorded events and returns, per kernel kind k (0 exact,
- * 1 traversal, 2 adjoint, 3 tree build), the number of launches counts[k]
- * and their summed duration ms[k]; reading resets the accumulators. */
+/* Per-launch timing of the dominant kernels.  While enabled, every launch of
+ * a timed kernel kind is bracketed by HIP events on its stream.
+ * gs_kernel_timing_read waits for the recorded events and returns, per kind
+ * k, the number of launches counts[k] and their summed duration ms[k]
+ * (milliseconds); reading resets the accumulators.  Kinds: 0 exact
+ * all-pairs (v and a), 1 Barnes-Hut traversal (v and a), 2 adjoint pair
+ * kernels, 3 octree build (its whole launch sequence), 4 exact all-pairs
+ * velocity only, 5 Barnes-Hut traversal velocity only. */
+#define GS_TIMING_KINDS 6
 gs_status gs_kernel_timing(int32_t enable);
-gs_status gs_kernel_timing_read(int64_t counts[4], double ms[4]);
+gs_status gs_kernel_timing_read(int64_t counts[GS_TIMING_KINDS], double ms[GS_TIMING_KINDS]);
 
 #ifdef __cplusplus
 }

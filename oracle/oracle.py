@@ -68,6 +68,7 @@ def lib():
                                         _dbl, _dbl, _i32, _D]
         L.or_objective_grad.restype = _dbl
         L.or_version.restype = ctypes.c_char_p
+        L.or_threads.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -221,6 +222,11 @@ def int_coords(q):
     ic = np.zeros((q.shape[0], 3), dtype=np.uint32)
     lib().or_int_coords(q.shape[0], qp, ic.ctypes.data_as(_U32))
     return ic
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's parallel loops use."""
+    return int(lib().or_threads())
 
 
 def version() -> str:

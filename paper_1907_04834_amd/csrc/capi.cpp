@@ -34,8 +34,8 @@ namespace {
 struct TimingState {
     std::mutex mu;
     bool on = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[4];
-    hipEvent_t open[4] = {nullptr, nullptr, nullptr, nullptr};
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[KIND_COUNT];
+    hipEvent_t open[KIND_COUNT] = {};
 };
 TimingState &timing() {
     static TimingState t;
@@ -147,12 +147,6 @@ gs_status check_ws(void *ws, size_t have, size_t need) {
     }
     return GS_OK;
 }
-
-#define GS_TRY(x)                     \
-    do {                              \
-        gs_status st_ = (x);          \
-        if (st_ != GS_OK) return st_; \
-    } while (0)
 
 // ---------------------------------------------------------------- layouts
 // Every operation lays out its buffers with the same code whether it is
@@ -419,10 +413,11 @@ gs_status gs_kernel_timing(int32_t enable) {
     return GS_OK;
 }
 
-gs_status gs_kernel_timing_read(int64_t counts[4], double ms[4]) {
+gs_status gs_kernel_timing_read(int64_t counts[GS_TIMING_KINDS], double ms[GS_TIMING_KINDS]) {
+    static_assert(GS_TIMING_KINDS == KIND_COUNT, "timing kinds");
     TimingState &t = timing();
     std::lock_guard<std::mutex> g(t.mu);
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < KIND_COUNT; ++k) {
         double sum = 0.0;
         for (auto &pr : t.ev[k]) {
             GS_HIP(hipEventSynchronize(pr.second));

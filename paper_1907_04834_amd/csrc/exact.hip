@@ -362,14 +362,15 @@ gs_status launch_exact_pairs(const ExactPlan &pl, const float4 *Qt, const float4
                              double *part, hipStream_t s) {
     const float negc = (float)(-kLog2e / (2.0 * sigma * sigma));
     dim3 grid((unsigned)(pl.ntgt / (64 * pl.tpl * 4)), (unsigned)pl.splits);
-    timing_begin(KIND_EXACT, s);
+    const int kind = with_a ? KIND_EXACT : KIND_EXACT_V;
+    timing_begin(kind, s);
     if (with_a)
         hipLaunchKernelGGL((k_exact_pairs<2, true>), grid, dim3(256), 0, s, Qt, Pt, pl.ntgt, Qs,
                            Ps, pl.chunk, pl.nsrc, negc, part);
     else
         hipLaunchKernelGGL((k_exact_pairs<2, false>), grid, dim3(256), 0, s, Qt, Pt, pl.ntgt,
                            Qs, Ps, pl.chunk, pl.nsrc, negc, part);
-    timing_end(KIND_EXACT, s);
+    timing_end(kind, s);
     GS_LAUNCH_CHECK("exact_pairs");
     return GS_OK;
 }

@@ -20,6 +20,11 @@ gs_status hip_fail(hipError_t e, const char *what);
         hipError_t e_ = (call);                            \
         if (e_ != hipSuccess) return hip_fail(e_, #call);  \
     } while (0)
+#define GS_TRY(x)                     \
+    do {                              \
+        gs_status st_ = (x);          \
+        if (st_ != GS_OK) return st_; \
+    } while (0)
 #define GS_LAUNCH_CHECK(what)                              \
     do {                                                   \
         hipError_t e_ = hipGetLastError();                 \
@@ -27,7 +32,15 @@ gs_status hip_fail(hipError_t e, const char *what);
     } while (0)
 
 // ---------------------------------------------------------------- timing
-enum TimedKind { KIND_EXACT = 0, KIND_TRAVERSE = 1, KIND_ADJOINT = 2, KIND_TREE = 3 };
+enum TimedKind {
+    KIND_EXACT = 0,       // exact all-pairs kernel, (v, a)
+    KIND_TRAVERSE = 1,    // Barnes-Hut traversal, (v, a)
+    KIND_ADJOINT = 2,     // adjoint pair kernels
+    KIND_TREE = 3,        // whole octree build (all its launches)
+    KIND_EXACT_V = 4,     // exact all-pairs kernel, velocity only
+    KIND_TRAVERSE_V = 5,  // Barnes-Hut traversal, velocity only
+    KIND_COUNT = 6
+};
 // Bracket a launch of a timed kernel (no-ops unless timing is enabled).
 void timing_begin(int kind, hipStream_t s);
 void timing_end(int kind, hipStream_t s);

@@ -1,27 +1,741 @@
-// tree.hip -- Barnes-Hut octree (placeholder until the tree path lands).
+// tree.hip -- GPU build of the Barnes-Hut octree (Sec. 2.2, "Oct-tree
+// Representation of Space") and its node statistics.
+//
+// Launch sequence of one build (no host synchronisation, so it can be
+// captured in a graph):
+//   bbox_partial -> bbox_final     tight box of all points, E, 2^21/E
+//   morton                         63-bit keys: 21 bits per axis, x highest
+//   8 x (hist, scan, scatter)      stable LSD radix sort of (key, index)
+//   gather                         sorted FP32 copies of q, p
+//   boundaries                     split level of every pair of neighbours and
+//                                  the internal-node flag of its cell
+//   scan(flag)                     internal-node ranks
+//   children                       child count of every internal node
+//   scan(nchild)                   contiguous child blocks
+//   root, nodes                    node records (ranges, child links)
+//   stats                          bottom-up FP64 sums, tight boxes, centres
+//
+// Tree semantics.  For sorted keys K, the boundary between points i and i+1
+// has split level L = floor(lcp(K_i, K_i+1) / 3) (21 when the keys are equal).
+// The level-L cell containing both points is split there; the first such
+// boundary in a cell represents the cell.  A represented cell with more than
+// leaf_cap points is an internal node of the compressed octree (all its
+// ancestors hold even more points, so they are split too); its children are
+// the non-empty level-(L+1) sub-cells: a child with <= leaf_cap points, or
+// whose points share one key, is a leaf; otherwise it is the internal node
+// represented by its own first split.
+#include <hip/hip_runtime.h>
+
 #include "tree.h"
 
 namespace gs {
 
-void carve_tree(Arena &a, int64_t n, TreeBufs &t) { t.unused = a.take<char>(n); }
+namespace {
 
-ShootBhBufs layout_shoot_bh(Arena &a, int64_t n, int nt) {
-    (void)nt;
-    ShootBhBufs b{};
-    carve_tree(a, n, b.tree);
-    return b;
+typedef unsigned long long u64;
+
+constexpr int kSortThreads = 256;
+constexpr int kSortPerThread = 8;
+constexpr int kSortTile = kSortThreads * kSortPerThread;  // 2048 keys per block
+constexpr int kScanTile = 2048;                            // items per scan block
+
+inline unsigned nblk(int64_t n, int b = kBlock) { return (unsigned)((n + b - 1) / b); }
+
+// ---------------------------------------------------------------- bbox
+__global__ __launch_bounds__(256) void k_bbox_partial(const float *__restrict__ q, int64_t n,
+                                                      float *__restrict__ part) {
+    __shared__ float red[6][256];
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    float bad = 0.f;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const float x = q[3 * i + c];
+            if (!isfinite(x)) bad = 1.f;
+            lo[c] = fminf(lo[c], x);
+            hi[c] = fmaxf(hi[c], x);
+        }
+    }
+    // a non-finite coordinate is recorded in slot 0 as NaN
+    if (bad != 0.f) lo[0] = NAN;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        red[c][threadIdx.x] = lo[c];
+        red[3 + c][threadIdx.x] = hi[c];
+    }
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const float a = red[c][threadIdx.x], b = red[c][threadIdx.x + s];
+                // keep a NaN flag in slot 0 sticky
+                red[c][threadIdx.x] = (c == 0 && (isnan(a) || isnan(b))) ? NAN : fminf(a, b);
+                red[3 + c][threadIdx.x] = fmaxf(red[3 + c][threadIdx.x], red[3 + c][threadIdx.x + s]);
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) part[blockIdx.x * 6 + threadIdx.x] = red[threadIdx.x][0];
 }
 
-gs_status rhs_bh(const float *, const float *, int64_t, const gs_params &, float *, float *,
-                 TreeBufs &, char *, hipStream_t) {
-    set_error("Barnes-Hut path not built yet");
-    return GS_ERR_UNSUPPORTED;
+__global__ void k_bbox_final(const float *__restrict__ part, int nb, TreeMeta *__restrict__ meta,
+                             int *__restrict__ status) {
+    if (threadIdx.x != 0) return;
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    int bad = 0;
+    for (int b = 0; b < nb; ++b) {
+        if (isnan(part[6 * b])) bad = 1;
+        for (int c = 0; c < 3; ++c) {
+            lo[c] = fminf(lo[c], part[6 * b + c]);
+            hi[c] = fmaxf(hi[c], part[6 * b + 3 + c]);
+        }
+    }
+    double e = 0.0;
+    for (int c = 0; c < 3; ++c) {
+        meta->lo[c] = lo[c];
+        meta->hi[c] = hi[c];
+        const double ext = (double)hi[c] - (double)lo[c];
+        if (ext > e) e = ext;
+    }
+    if (bad || !isfinite(e)) {
+        bad = 1;
+        e = 0.0;  // degenerate tree: one leaf (results are not meaningful)
+    }
+    meta->extent = e;
+    meta->scale = e > 0.0 ? 2097152.0 / e : 0.0;
+    meta->nonfinite = bad;
+    if (bad && status) *status = 1;
 }
 
-gs_status shoot_bh(const float *, const float *, int64_t, const gs_params &, float *, float *,
-                   double *, ShootBhBufs &, char *, hipStream_t) {
-    set_error("Barnes-Hut path not built yet");
-    return GS_ERR_UNSUPPORTED;
+// ---------------------------------------------------------------- Morton keys
+__device__ inline u64 spread3(unsigned v) {
+    // bits b of v -> bit 3b of the result (v < 2^21)
+    u64 x = v & 0x1fffffull;
+    x = (x | (x << 32)) & 0x1f00000000ffffull;
+    x = (x | (x << 16)) & 0x1f0000ff0000ffull;
+    x = (x | (x << 8)) & 0x100f00f00f00f00full;
+    x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
+    x = (x | (x << 2)) & 0x1249249249249249ull;
+    return x;
+}
+
+__device__ inline unsigned quantize(float x, float lo, double scale) {
+    // c = min(2^21 - 1, floor((x - lo) * 2^21 / E)), evaluated in FP64
+    const double f = floor(((double)x - (double)lo) * scale);
+    if (!(f >= 0.0)) return 0u;  // also NaN
+    if (f >= 2097151.0) return 2097151u;
+    return (unsigned)f;
+}
+
+__global__ __launch_bounds__(256) void k_morton(const float *__restrict__ q, int64_t n,
+                                                const TreeMeta *__restrict__ meta,
+                                                u64 *__restrict__ keys,
+                                                unsigned *__restrict__ vals) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double sc = meta->scale;
+    const unsigned cx = quantize(q[3 * i], meta->lo[0], sc);
+    const unsigned cy = quantize(q[3 * i + 1], meta->lo[1], sc);
+    const unsigned cz = quantize(q[3 * i + 2], meta->lo[2], sc);
+    keys[i] = (spread3(cx) << 2) | (spread3(cy) << 1) | spread3(cz);
+    vals[i] = (unsigned)i;
+}
+
+// ---------------------------------------------------------------- radix sort
+__global__ __launch_bounds__(kSortThreads) void k_rs_hist(const u64 *__restrict__ keys, int64_t n,
+                                                          int shift, int nb,
+                                                          unsigned *__restrict__ hist) {
+    __shared__ unsigned h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    for (int r = 0; r < kSortPerThread; ++r) {
+        const int64_t i = base + r * kSortThreads + threadIdx.x;
+        if (i < n) atomicAdd(&h[(unsigned)(keys[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+}
+
+// Exclusive scan of `count` u32 values in place, by one block of 1024 threads
+// (each thread scans a contiguous run, then the run totals are scanned).
+__global__ __launch_bounds__(1024) void k_scan_small(unsigned *__restrict__ x, int64_t count) {
+    __shared__ unsigned tot[1024];
+    const int t = threadIdx.x;
+    const int64_t per = (count + 1023) / 1024;
+    const int64_t b = t * per, e = b + per < count ? b + per : count;
+    unsigned s = 0;
+    for (int64_t i = b; i < e; ++i) s += x[i];
+    tot[t] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        unsigned v = t >= off ? tot[t - off] : 0u;
+        __syncthreads();
+        tot[t] += v;
+        __syncthreads();
+    }
+    unsigned run = t > 0 ? tot[t - 1] : 0u;
+    for (int64_t i = b; i < e; ++i) {
+        const unsigned v = x[i];
+        x[i] = run;
+        run += v;
+    }
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_rs_scatter(
+    const u64 *__restrict__ kin, const unsigned *__restrict__ vin, u64 *__restrict__ kout,
+    unsigned *__restrict__ vout, int64_t n, int shift, int nb, const unsigned *__restrict__ hist) {
+    __shared__ unsigned base[256];
+    __shared__ unsigned run[256];
+    __shared__ unsigned wcnt[kSortThreads / 64][256];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    base[t] = hist[(int64_t)t * nb + blockIdx.x];
+    run[t] = 0;
+    for (int w = 0; w < kSortThreads / 64; ++w) wcnt[w][t] = 0;
+    __syncthreads();
+    const u64 lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int64_t tile = (int64_t)blockIdx.x * kSortTile;
+    for (int r = 0; r < kSortPerThread; ++r) {
+        const int64_t i = tile + r * kSortThreads + t;
+        const bool valid = i < n;
+        u64 key = valid ? kin[i] : 0ull;
+        const unsigned val = valid ? vin[i] : 0u;
+        const unsigned d = (unsigned)(key >> shift) & 255u;
+        // lanes of this wave holding the same digit (stable by lane order)
+        u64 peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const u64 m = __ballot((d >> b) & 1u);
+            peers &= ((d >> b) & 1u) ? m : ~m;
+        }
+        const unsigned lr = __popcll(peers & lt);
+        if (valid && lr == 0) wcnt[wv][d] = __popcll(peers);
+        __syncthreads();
+        unsigned rank = 0;
+        if (valid) {
+            rank = run[d] + lr;
+            for (int w = 0; w < wv; ++w) rank += wcnt[w][d];
+        }
+        __syncthreads();
+        unsigned add = 0;
+        for (int w = 0; w < kSortThreads / 64; ++w) {
+            add += wcnt[w][t];
+            wcnt[w][t] = 0;
+        }
+        run[t] += add;
+        if (valid) {
+            const unsigned pos = base[d] + rank;
+            kout[pos] = key;
+            vout[pos] = val;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void k_gather(const float *__restrict__ q,
+                                                const float *__restrict__ p,
+                                                const unsigned *__restrict__ perm, int64_t n,
+                                                float4 *__restrict__ Qs, float4 *__restrict__ Ps) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int64_t i = perm[t];
+    Qs[t] = make_float4(q[3 * i], q[3 * i + 1], q[3 * i + 2], 0.f);
+    Ps[t] = make_float4(p[3 * i], p[3 * i + 1], p[3 * i + 2], 0.f);
+}
+
+// ---------------------------------------------------------------- generic scan
+// Exclusive scan of n u32 values: per-block totals, then each block adds the
+// totals of the blocks before it.  out may equal in.  *total (nullable)
+// receives the sum.
+__global__ __launch_bounds__(256) void k_scan_blocksum(const unsigned *__restrict__ in,
+                                                       int64_t n, unsigned *__restrict__ part) {
+    __shared__ unsigned red[256];
+    const int64_t b = (int64_t)blockIdx.x * kScanTile;
+    unsigned s = 0;
+    for (int k = 0; k < kScanTile / 256; ++k) {
+        const int64_t i = b + k * 256 + threadIdx.x;
+        if (i < n) s += in[i];
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_scan_apply(const unsigned *__restrict__ in,
+                                                    unsigned *__restrict__ out, int64_t n,
+                                                    const unsigned *__restrict__ part,
+                                                    unsigned *__restrict__ total) {
+    __shared__ unsigned sc[256];
+    __shared__ unsigned carry;
+    const int t = threadIdx.x;
+    // offset of this block: sum of the previous block totals
+    unsigned off = 0;
+    for (int b = t; b < (int)blockIdx.x; b += 256) off += part[b];
+    sc[t] = off;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (t < s) sc[t] += sc[t + s];
+        __syncthreads();
+    }
+    if (t == 0) carry = sc[0];
+    __syncthreads();
+    const int64_t b = (int64_t)blockIdx.x * kScanTile;
+    for (int k = 0; k < kScanTile / 256; ++k) {
+        const int64_t i = b + k * 256 + t;
+        const unsigned v = i < n ? in[i] : 0u;
+        sc[t] = v;
+        __syncthreads();
+        for (int o = 1; o < 256; o <<= 1) {
+            const unsigned u = t >= o ? sc[t - o] : 0u;
+            __syncthreads();
+            sc[t] += u;
+            __syncthreads();
+        }
+        const unsigned incl = sc[t];
+        const unsigned c = carry;
+        if (i < n) out[i] = c + incl - v;
+        __syncthreads();
+        if (t == 255) carry = c + incl;
+        __syncthreads();
+    }
+    if (total && blockIdx.x == gridDim.x - 1 && t == 0) *total = carry;
+}
+
+// ---------------------------------------------------------------- tree
+__device__ inline int split_level(u64 a, u64 b) {
+    const u64 x = a ^ b;
+    if (x == 0ull) return kLevels;
+    return (__clzll((long long)x) - 1) / 3;
+}
+
+__device__ inline int level_shift(int L) { return 63 - 3 * L; }
+
+// first index in [lo, hi) with K[i] >= key
+__device__ inline int64_t lower_bound(const u64 *__restrict__ K, int64_t lo, int64_t hi, u64 key) {
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (K[mid] < key)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void k_boundaries(const u64 *__restrict__ K, int64_t n,
+                                                    int leaf_cap, unsigned char *__restrict__ lvl,
+                                                    unsigned *__restrict__ flag,
+                                                    unsigned *__restrict__ bs,
+                                                    unsigned *__restrict__ be) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (i == n - 1) {  // no boundary after the last point
+        flag[i] = 0;
+        return;
+    }
+    const u64 a = K[i];
+    const int L = split_level(a, K[i + 1]);
+    lvl[i] = (unsigned char)L;
+    unsigned f = 0;
+    if (L < kLevels) {
+        const int sh = level_shift(L);
+        const u64 pre = L == 0 ? 0ull : (a >> sh);
+        const u64 cell_lo = L == 0 ? 0ull : (pre << sh);
+        const u64 cell_hi = L == 0 ? ~0ull : (((pre + 1) << sh) - 1);
+        const int64_t s = lower_bound(K, 0, i, cell_lo);
+        // end: first index after i + 1 with a key above the cell
+        int64_t lo = i + 1, hi = n;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (K[mid] <= cell_hi)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        const int64_t e = lo;
+        // representative: the first split of the cell, i.e. K[s] and K[i]
+        // share the level-(L+1) prefix
+        const bool rep = ((K[s] ^ a) >> level_shift(L + 1)) == 0ull;
+        if (rep && e - s > leaf_cap) {
+            f = 1;
+            bs[i] = (unsigned)s;
+            be[i] = (unsigned)e;
+        }
+    }
+    flag[i] = f;
+}
+
+// Child runs of the internal cell [s, e) split at level L: up to 8 non-empty
+// level-(L+1) sub-cells in octant order.  Returns their count; c[k], c[k+1]
+// bound child k.
+__device__ inline int child_runs(const u64 *__restrict__ K, int64_t s, int64_t e, int L,
+                                 unsigned *c) {
+    const u64 pre = L == 0 ? 0ull : (K[s] >> level_shift(L));
+    const int sh = level_shift(L + 1);
+    int cnt = 0;
+    int64_t prev = s;
+    for (int d = 1; d < 8; ++d) {
+        const int64_t pos = lower_bound(K, prev, e, ((pre << 3) | (u64)d) << sh);
+        if (pos > prev) {
+            c[cnt++] = (unsigned)prev;
+            prev = pos;
+        }
+    }
+    if (prev < e) c[cnt++] = (unsigned)prev;
+    c[cnt] = (unsigned)e;
+    return cnt;
+}
+
+// Representative boundary of the compressed internal node covering [a, b)
+// (b - a > leaf_cap, keys not all equal).
+__device__ inline int64_t child_rep(const u64 *__restrict__ K, int64_t a, int64_t b) {
+    const int L = split_level(K[a], K[b - 1]);
+    const int sh = level_shift(L + 1);
+    const u64 pre = K[a] >> sh;
+    return lower_bound(K, a, b, (pre + 1) << sh) - 1;
+}
+
+__global__ __launch_bounds__(256) void k_children(const u64 *__restrict__ K, int64_t n,
+                                                  const unsigned char *__restrict__ lvl,
+                                                  const unsigned *__restrict__ flag,
+                                                  const unsigned *__restrict__ rank,
+                                                  const unsigned *__restrict__ bs,
+                                                  const unsigned *__restrict__ be,
+                                                  unsigned *__restrict__ rank_bnd,
+                                                  unsigned *__restrict__ nchild) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n - 1 || !flag[i]) return;
+    unsigned c[9];
+    const int cnt = child_runs(K, bs[i], be[i], lvl[i], c);
+    const unsigned r = rank[i];
+    rank_bnd[r] = (unsigned)i;
+    nchild[r] = (unsigned)cnt;
+}
+
+__device__ inline void zero_stats(BhNode &nd) {
+    nd.cx = nd.cy = nd.cz = nd.s2 = 0.0;
+    nd.lox = nd.loy = nd.loz = nd.hix = nd.hiy = nd.hiz = 0.f;
+    nd.px = nd.py = nd.pz = 0.f;
+}
+
+// Root record.  Runs as one thread after the scans.
+__global__ void k_root(const u64 *__restrict__ K, int64_t n, int leaf_cap,
+                       const unsigned *__restrict__ rank, const unsigned *__restrict__ nchild,
+                       const unsigned *__restrict__ cstart, TreeMeta *__restrict__ meta,
+                       BhNode *__restrict__ nodes, int *__restrict__ node_of,
+                       int *__restrict__ parent_rank, unsigned *__restrict__ counter) {
+    if (threadIdx.x != 0) return;
+    BhNode nd;
+    zero_stats(nd);
+    nd.n = (int)n;
+    const unsigned m = meta->n_internal;
+    if (n <= leaf_cap || K[0] == K[n - 1] || m == 0) {
+        nd.first = 0;
+        nd.nchild = 0;
+        meta->root_leaf = 1;
+        meta->root_rank = -1;
+        meta->n_nodes = 1;
+    } else {
+        const int64_t rb = child_rep(K, 0, n);
+        const unsigned r = rank[rb];
+        nd.first = 1 + (int)cstart[r];
+        nd.nchild = (int)nchild[r];
+        node_of[r] = 0;
+        meta->root_leaf = 0;
+        meta->root_rank = (int)r;
+        meta->n_nodes = 1 + (int)(cstart[m - 1] + nchild[m - 1]);
+    }
+    nodes[0] = nd;
+    parent_rank[0] = -1;
+    counter[0] = 0;
+}
+
+__global__ __launch_bounds__(256) void k_nodes(const u64 *__restrict__ K, int leaf_cap,
+                                               const TreeMeta *__restrict__ meta,
+                                               const unsigned char *__restrict__ lvl,
+                                               const unsigned *__restrict__ rank,
+                                               const unsigned *__restrict__ bs,
+                                               const unsigned *__restrict__ be,
+                                               const unsigned *__restrict__ rank_bnd,
+                                               const unsigned *__restrict__ nchild,
+                                               const unsigned *__restrict__ cstart,
+                                               BhNode *__restrict__ nodes, int *__restrict__ node_of,
+                                               int *__restrict__ parent_rank,
+                                               unsigned *__restrict__ counter) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= meta->n_internal || meta->root_leaf) return;
+    const unsigned i = rank_bnd[r];
+    unsigned c[9];
+    const int cnt = child_runs(K, bs[i], be[i], lvl[i], c);
+    const int base = 1 + (int)cstart[r];
+    for (int k = 0; k < cnt; ++k) {
+        const int id = base + k;
+        const int64_t a = c[k], b = c[k + 1];
+        BhNode nd;
+        zero_stats(nd);
+        nd.n = (int)(b - a);
+        if (b - a <= leaf_cap || K[a] == K[b - 1]) {
+            nd.first = (int)a;
+            nd.nchild = 0;
+        } else {
+            const unsigned rc = rank[child_rep(K, a, b)];
+            nd.first = 1 + (int)cstart[rc];
+            nd.nchild = (int)nchild[rc];
+            node_of[rc] = id;
+        }
+        nodes[id] = nd;
+        parent_rank[id] = (int)r;
+        counter[id] = 0;
+    }
+}
+
+// Statistics of a node from FP64 sums, box and count.
+__device__ inline void finish_node(BhNode &nd, const double *sum, const float *lo,
+                                   const float *hi) {
+    const double inv = 1.0 / (double)nd.n;
+    nd.cx = sum[0] * inv;
+    nd.cy = sum[1] * inv;
+    nd.cz = sum[2] * inv;
+    nd.px = (float)sum[3];
+    nd.py = (float)sum[4];
+    nd.pz = (float)sum[5];
+    nd.lox = lo[0];
+    nd.loy = lo[1];
+    nd.loz = lo[2];
+    nd.hix = hi[0];
+    nd.hiy = hi[1];
+    nd.hiz = hi[2];
+    double s = 0.0;
+    for (int c = 0; c < 3; ++c) {
+        const double side = (double)hi[c] - (double)lo[c];
+        if (side > s) s = side;
+    }
+    nd.s2 = s * s;
+}
+
+// Bottom-up statistics.  One thread per leaf computes the leaf from its
+// points, then climbs: the last child to arrive at a parent (atomic counter)
+// computes the parent from all its children in child order, so the result
+// does not depend on arrival order.
+__global__ __launch_bounds__(256) void k_stats(const float4 *__restrict__ Qs,
+                                               const float4 *__restrict__ Ps,
+                                               const TreeMeta *__restrict__ meta,
+                                               BhNode *__restrict__ nodes, double *__restrict__ nsum,
+                                               const int *__restrict__ node_of,
+                                               const int *__restrict__ parent_rank,
+                                               unsigned *__restrict__ counter) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= meta->n_nodes) return;
+    BhNode nd = nodes[id];
+    if (nd.nchild != 0) return;
+    double sum[6] = {0, 0, 0, 0, 0, 0};
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int j = nd.first; j < nd.first + nd.n; ++j) {
+        const float4 a = Qs[j], b = Ps[j];
+        sum[0] += a.x;
+        sum[1] += a.y;
+        sum[2] += a.z;
+        sum[3] += b.x;
+        sum[4] += b.y;
+        sum[5] += b.z;
+        lo[0] = fminf(lo[0], a.x);
+        lo[1] = fminf(lo[1], a.y);
+        lo[2] = fminf(lo[2], a.z);
+        hi[0] = fmaxf(hi[0], a.x);
+        hi[1] = fmaxf(hi[1], a.y);
+        hi[2] = fmaxf(hi[2], a.z);
+    }
+    finish_node(nd, sum, lo, hi);
+    nodes[id] = nd;
+    for (int c = 0; c < 6; ++c) nsum[6 * id + c] = sum[c];
+    int cur = (int)id;
+    while (true) {
+        const int pr = parent_rank[cur];
+        if (pr < 0) break;
+        const int par = node_of[pr];
+        __threadfence();
+        const unsigned old = __hip_atomic_fetch_add(&counter[par], 1u, __ATOMIC_ACQ_REL,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+        BhNode pn = nodes[par];
+        if (old + 1 != (unsigned)pn.nchild) break;
+        __threadfence();
+        double ps[6] = {0, 0, 0, 0, 0, 0};
+        float plo[3] = {INFINITY, INFINITY, INFINITY}, phi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        for (int k = 0; k < pn.nchild; ++k) {
+            const int ch = pn.first + k;
+            const BhNode cn = nodes[ch];
+            for (int c = 0; c < 6; ++c) ps[c] += nsum[6 * ch + c];
+            plo[0] = fminf(plo[0], cn.lox);
+            plo[1] = fminf(plo[1], cn.loy);
+            plo[2] = fminf(plo[2], cn.loz);
+            phi[0] = fmaxf(phi[0], cn.hix);
+            phi[1] = fmaxf(phi[1], cn.hiy);
+            phi[2] = fmaxf(phi[2], cn.hiz);
+        }
+        finish_node(pn, ps, plo, phi);
+        nodes[par] = pn;
+        for (int c = 0; c < 6; ++c) nsum[6 * par + c] = ps[c];
+        cur = par;
+    }
+}
+
+// Node sums of per-point adjoint vectors (original order, [n][3] FP64).
+__global__ __launch_bounds__(256) void k_adj_sums(const double *__restrict__ al,
+                                                  const double *__restrict__ be,
+                                                  const unsigned *__restrict__ perm,
+                                                  const TreeMeta *__restrict__ meta,
+                                                  const BhNode *__restrict__ nodes,
+                                                  double *__restrict__ adj,
+                                                  const int *__restrict__ node_of,
+                                                  const int *__restrict__ parent_rank,
+                                                  unsigned *__restrict__ counter) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= meta->n_nodes) return;
+    const BhNode nd = nodes[id];
+    if (nd.nchild != 0) return;
+    double sum[6] = {0, 0, 0, 0, 0, 0};
+    for (int j = nd.first; j < nd.first + nd.n; ++j) {
+        const int64_t i = perm[j];
+        for (int c = 0; c < 3; ++c) {
+            sum[c] += al[3 * i + c];
+            sum[3 + c] += be[3 * i + c];
+        }
+    }
+    for (int c = 0; c < 6; ++c) adj[6 * id + c] = sum[c];
+    int cur = (int)id;
+    while (true) {
+        const int pr = parent_rank[cur];
+        if (pr < 0) break;
+        const int par = node_of[pr];
+        __threadfence();
+        const unsigned old = __hip_atomic_fetch_add(&counter[par], 1u, __ATOMIC_ACQ_REL,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+        const BhNode pn = nodes[par];
+        if (old + 1 != (unsigned)pn.nchild) break;
+        __threadfence();
+        double ps[6] = {0, 0, 0, 0, 0, 0};
+        for (int k = 0; k < pn.nchild; ++k)
+            for (int c = 0; c < 6; ++c) ps[c] += adj[6 * (pn.first + k) + c];
+        for (int c = 0; c < 6; ++c) adj[6 * par + c] = ps[c];
+        cur = par;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_zero_u32(unsigned *__restrict__ x, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = 0u;
+}
+
+gs_status scan_u32(const unsigned *in, unsigned *out, int64_t n, unsigned *part, unsigned *total,
+                   hipStream_t s) {
+    const unsigned nb = (unsigned)((n + kScanTile - 1) / kScanTile);
+    hipLaunchKernelGGL(k_scan_blocksum, dim3(nb), dim3(256), 0, s, in, n, part);
+    hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(256), 0, s, in, out, n, part, total);
+    GS_LAUNCH_CHECK("scan");
+    return GS_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- host side
+void carve_tree(Arena &a, int64_t n, TreeBufs &t) {
+    const int64_t m = n > 1 ? n : 1;
+    t.n = n;
+    t.bbox_blocks = (int)((m + 2047) / 2048 < 1024 ? (m + 2047) / 2048 : 1024);
+    t.sort_blocks = (int)((m + kSortTile - 1) / kSortTile);
+    t.meta = a.take<TreeMeta>(1);
+    t.bbox_part = a.take<float>(6 * (size_t)t.bbox_blocks);
+    t.keyA = a.take<u64>(m);
+    t.keyB = a.take<u64>(m);
+    t.valA = a.take<unsigned>(m);
+    t.valB = a.take<unsigned>(m);
+    t.hist = a.take<unsigned>(256 * (size_t)t.sort_blocks);
+    t.scan_part = a.take<unsigned>((m + kScanTile - 1) / kScanTile + 1);
+    t.Qs = a.take<float4>(m);
+    t.Ps = a.take<float4>(m);
+    t.lvl = a.take<unsigned char>(m);
+    t.flag = a.take<unsigned>(m);
+    t.rank = a.take<unsigned>(m);
+    t.bnd_s = a.take<unsigned>(m);
+    t.bnd_e = a.take<unsigned>(m);
+    t.rank_bnd = a.take<unsigned>(m);
+    t.nchild = a.take<unsigned>(m);
+    t.cstart = a.take<unsigned>(m);
+    t.node_of = a.take<int>(m);
+    t.parent_rank = a.take<int>(2 * m);
+    t.counter = a.take<unsigned>(2 * m);
+    t.nsum = a.take<double>(12 * m);
+    t.nodes = a.take<BhNode>(2 * m);
+    t.adj = a.take<double>(12 * m);
+}
+
+gs_status build_tree(const float *q, const float *p, int64_t n, int leaf_cap, TreeBufs &t,
+                     int *status, hipStream_t s) {
+    timing_begin(KIND_TREE, s);
+    hipLaunchKernelGGL(k_bbox_partial, dim3(t.bbox_blocks), dim3(256), 0, s, q, n, t.bbox_part);
+    hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(64), 0, s, t.bbox_part, t.bbox_blocks, t.meta,
+                       status);
+    hipLaunchKernelGGL(k_morton, dim3(nblk(n)), dim3(256), 0, s, q, n, t.meta, t.keyA, t.valA);
+    GS_LAUNCH_CHECK("bbox/morton");
+    u64 *ki = t.keyA, *ko = t.keyB;
+    unsigned *vi = t.valA, *vo = t.valB;
+    const int nb = t.sort_blocks;
+    for (int pass = 0; pass < 8; ++pass) {
+        const int shift = 8 * pass;
+        hipLaunchKernelGGL(k_rs_hist, dim3(nb), dim3(kSortThreads), 0, s, ki, n, shift, nb, t.hist);
+        hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, s, t.hist, (int64_t)256 * nb);
+        hipLaunchKernelGGL(k_rs_scatter, dim3(nb), dim3(kSortThreads), 0, s, ki, vi, ko, vo, n,
+                           shift, nb, t.hist);
+        u64 *tk = ki;
+        ki = ko;
+        ko = tk;
+        unsigned *tv = vi;
+        vi = vo;
+        vo = tv;
+    }
+    GS_LAUNCH_CHECK("radix sort");
+    // after an even number of passes the sorted data is back in keyA/valA
+    const u64 *K = t.keyA;
+    const unsigned *perm = t.valA;
+    hipLaunchKernelGGL(k_gather, dim3(nblk(n)), dim3(256), 0, s, q, p, perm, n, t.Qs, t.Ps);
+    hipLaunchKernelGGL(k_boundaries, dim3(nblk(n)), dim3(256), 0, s, K, n, leaf_cap, t.lvl,
+                       t.flag, t.bnd_s, t.bnd_e);
+    GS_LAUNCH_CHECK("boundaries");
+    unsigned *n_internal = reinterpret_cast<unsigned *>(&t.meta->n_internal);
+    GS_TRY(scan_u32(t.flag, t.rank, n, t.scan_part, n_internal, s));
+    hipLaunchKernelGGL(k_children, dim3(nblk(n)), dim3(256), 0, s, K, n, t.lvl, t.flag, t.rank,
+                       t.bnd_s, t.bnd_e, t.rank_bnd, t.nchild);
+    GS_LAUNCH_CHECK("children");
+    // nchild of ranks >= n_internal is never read; the scan covers n - 1
+    // entries whose tail beyond n_internal may hold stale values, which only
+    // affects cstart of ranks that do not exist.
+    GS_TRY(scan_u32(t.nchild, t.cstart, n > 1 ? n - 1 : 1, t.scan_part, nullptr, s));
+    hipLaunchKernelGGL(k_root, dim3(1), dim3(64), 0, s, K, n, leaf_cap, t.rank, t.nchild,
+                       t.cstart, t.meta, t.nodes, t.node_of, t.parent_rank, t.counter);
+    hipLaunchKernelGGL(k_nodes, dim3(nblk(n)), dim3(256), 0, s, K, leaf_cap, t.meta, t.lvl,
+                       t.rank, t.bnd_s, t.bnd_e, t.rank_bnd, t.nchild, t.cstart, t.nodes,
+                       t.node_of, t.parent_rank, t.counter);
+    hipLaunchKernelGGL(k_stats, dim3(nblk(2 * n)), dim3(256), 0, s, t.Qs, t.Ps, t.meta, t.nodes,
+                       t.nsum, t.node_of, t.parent_rank, t.counter);
+    timing_end(KIND_TREE, s);
+    GS_LAUNCH_CHECK("nodes/stats");
+    return GS_OK;
+}
+
+gs_status tree_adjoint_sums(const double *alpha, const double *beta, TreeBufs &t,
+                            hipStream_t s) {
+    const int64_t n = t.n;
+    hipLaunchKernelGGL(k_zero_u32, dim3(nblk(2 * n)), dim3(256), 0, s, t.counter, 2 * n);
+    hipLaunchKernelGGL(k_adj_sums, dim3(nblk(2 * n)), dim3(256), 0, s, alpha, beta, t.valA,
+                       t.meta, t.nodes, t.adj, t.node_of, t.parent_rank, t.counter);
+    GS_LAUNCH_CHECK("adjoint sums");
+    return GS_OK;
 }
 
 }  // namespace gs

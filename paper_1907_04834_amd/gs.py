@@ -236,12 +236,12 @@ def gs_kernel_timing(enable: bool):
     _check(lib().gs_kernel_timing(1 if enable else 0))
 
 
-KINDS = ("exact", "traverse", "adjoint", "tree")
+KINDS = ("exact", "traverse", "adjoint", "tree", "exact_v", "traverse_v")
 
 
 def gs_kernel_timing_read() -> dict:
-    c = (ctypes.c_int64 * 4)()
-    ms = (ctypes.c_double * 4)()
+    c = (ctypes.c_int64 * len(KINDS))()
+    ms = (ctypes.c_double * len(KINDS))()
     _check(lib().gs_kernel_timing_read(c, ms))
     return {k: {"launches": int(c[i]), "ms": float(ms[i])} for i, k in enumerate(KINDS)}
 
