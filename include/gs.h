@@ -68,7 +68,10 @@ typedef enum {
 } gs_op;
 
 /* flags */
-#define GS_FLAG_F64 1u /* size the workspace for the _f64 entry points        */
+#define GS_FLAG_F64 1u        /* size the workspace for the _f64 entry points */
+#define GS_FLAG_MFMA_PAIRS 2u /* exact FP32 (v, a) sums accumulated on the
+                                 matrix cores (v_mfma_f32_16x16x4_f32)
+                                 instead of the vector ALU                    */
 
 typedef struct {
     double sigma;          /* kernel width, > 0                                */

@@ -251,7 +251,7 @@ gs_status gs_rhs_exact(const float *q, const float *p, int64_t n, const gs_param
     pr.flags &= ~GS_FLAG_F64;
     GS_TRY(check_ws(ws, ws_bytes, measure_bytes(n, &pr, GS_EXACT, GS_OP_RHS)));
     Arena a{static_cast<char *>(ws), kHeader, ws_bytes};
-    ExactPlan pl = plan_exact(n, n);
+    ExactPlan pl = plan_exact(n, n, (prm->flags & GS_FLAG_MFMA_PAIRS) != 0);
     ExactBufs b;
     carve_exact(a, pl, b);
     const int64_t npad = pl.nsrc > pl.ntgt ? pl.nsrc : pl.ntgt;
@@ -293,7 +293,7 @@ gs_status gs_shoot(const float *q0, const float *p0, int64_t n, const gs_params 
         return shoot_bh(q0, p0, n, *prm, q1, p1, H, b, static_cast<char *>(ws), stream);
     }
     ShootExactBufs b = layout_shoot_exact(a, n, prm->nt);
-    ExactPlan pl = plan_exact(n, n);
+    ExactPlan pl = plan_exact(n, n, (prm->flags & GS_FLAG_MFMA_PAIRS) != 0);
     const int nblk = combine_blocks(n);
     const int64_t npad = pl.nsrc > pl.ntgt ? pl.nsrc : pl.ntgt;
     GS_TRY(launch_pack_state(q0, p0, n, npad, b.Sq, b.Sp, b.ex.Q, b.ex.P, stream));

@@ -16,6 +16,8 @@
 //     target's sum grows with the tile length, not with N;
 //   * each (split, target) writes its six FP64 partial sums; a second kernel
 //     adds the S partials in a fixed order (bitwise deterministic).
+#include <cstdlib>
+
 #include "internal.h"
 
 namespace gs {
@@ -90,6 +92,9 @@ __global__ __launch_bounds__(256) void k_exact_pairs(
     const float4 *__restrict__ Qt, const float4 *__restrict__ Pt, int64_t ntgt,
     const float4 *__restrict__ Qs, const float4 *__restrict__ Ps, int64_t chunk, int64_t nsrc,
     float negc, double *__restrict__ part) {
+    // B sources are processed stage by stage (differences, r^2, exp2, sums)
+    // so that every wave has B independent dependency chains in flight.
+    constexpr int B = T == 1 ? 4 : 2;
     const int lane = threadIdx.x & 63;
     const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const int64_t t0 = wave * (64 * T) + lane;
@@ -122,23 +127,39 @@ __global__ __launch_bounds__(256) void k_exact_pairs(
         for (int k = 0; k < T; ++k)
 #pragma unroll
             for (int c = 0; c < 3; ++c) tv[k][c] = ta[k][c] = 0.f;
-#pragma unroll 8
-        for (int u = 0; u < kTile; ++u) {
-            const float4 qj = Qs[jt + u];
-            const float4 pj = Ps[jt + u];
+#pragma unroll 2
+        for (int u = 0; u < kTile; u += B) {
+            float4 qj[B], pj[B];
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                qj[b] = Qs[jt + u + b];
+                pj[b] = Ps[jt + u + b];
+            }
 #pragma unroll
             for (int k = 0; k < T; ++k) {
-                const float dx = x[k] - qj.x, dy = y[k] - qj.y, dz = z[k] - qj.z;
-                const float r2 = dx * dx + dy * dy + dz * dz;
-                const float g = __builtin_amdgcn_exp2f(r2 * negc);
-                tv[k][0] += g * pj.x;
-                tv[k][1] += g * pj.y;
-                tv[k][2] += g * pj.z;
-                if (WITH_A) {
-                    const float w = g * (px[k] * pj.x + py[k] * pj.y + pz[k] * pj.z);
-                    ta[k][0] += w * dx;
-                    ta[k][1] += w * dy;
-                    ta[k][2] += w * dz;
+                float dx[B], dy[B], dz[B], g[B];
+#pragma unroll
+                for (int b = 0; b < B; ++b) {
+                    dx[b] = x[k] - qj[b].x;
+                    dy[b] = y[k] - qj[b].y;
+                    dz[b] = z[k] - qj[b].z;
+                }
+#pragma unroll
+                for (int b = 0; b < B; ++b)
+                    g[b] = __builtin_amdgcn_exp2f((dx[b] * dx[b] + dy[b] * dy[b] + dz[b] * dz[b]) *
+                                                  negc);
+#pragma unroll
+                for (int b = 0; b < B; ++b) {
+                    tv[k][0] += g[b] * pj[b].x;
+                    tv[k][1] += g[b] * pj[b].y;
+                    tv[k][2] += g[b] * pj[b].z;
+                    if (WITH_A) {
+                        const float w =
+                            g[b] * (px[k] * pj[b].x + py[k] * pj[b].y + pz[k] * pj[b].z);
+                        ta[k][0] += w * dx[b];
+                        ta[k][1] += w * dy[b];
+                        ta[k][2] += w * dz[b];
+                    }
                 }
             }
         }
@@ -158,6 +179,233 @@ __global__ __launch_bounds__(256) void k_exact_pairs(
         for (int c = 0; c < 3; ++c) {
             dst[c * ntgt + i] = sv[k][c];
             if (WITH_A) dst[(3 + c) * ntgt + i] = sa[k][c];
+        }
+    }
+}
+
+// Same sums with the source tile staged in LDS: every wave reads each source
+// with one wave-uniform (broadcast) LDS load into VGPRs, so the pair
+// arithmetic has only VGPR operands (VALU instructions that read an SGPR
+// operand issue measurably slower on gfx950).
+constexpr int kLdsTile = 256;  // sources per LDS tile (one per thread)
+
+template <int T, bool WITH_A>
+__global__ __launch_bounds__(256) void k_exact_pairs_lds(
+    const float4 *__restrict__ Qt, const float4 *__restrict__ Pt, int64_t ntgt,
+    const float4 *__restrict__ Qs, const float4 *__restrict__ Ps, int64_t chunk, int64_t nsrc,
+    float negc, double *__restrict__ part) {
+    __shared__ float4 sq[kLdsTile];
+    __shared__ float4 sp[kLdsTile];
+    constexpr int B = 4;
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int64_t t0 = wave * (64 * T) + lane;
+
+    float x[T], y[T], z[T], px[T], py[T], pz[T];
+#pragma unroll
+    for (int k = 0; k < T; ++k) {
+        const float4 a = Qt[t0 + 64 * k];
+        x[k] = a.x;
+        y[k] = a.y;
+        z[k] = a.z;
+        if (WITH_A) {
+            const float4 b = Pt[t0 + 64 * k];
+            px[k] = b.x;
+            py[k] = b.y;
+            pz[k] = b.z;
+        }
+    }
+    double sv[T][3], sa[T][3];
+#pragma unroll
+    for (int k = 0; k < T; ++k)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) sv[k][c] = sa[k][c] = 0.0;
+
+    const int64_t j0 = (int64_t)blockIdx.y * chunk;
+    const int64_t j1 = j0 + chunk < nsrc ? j0 + chunk : nsrc;
+    for (int64_t jt = j0; jt < j1; jt += kLdsTile) {
+        __syncthreads();
+        sq[threadIdx.x] = Qs[jt + threadIdx.x];
+        sp[threadIdx.x] = Ps[jt + threadIdx.x];
+        __syncthreads();
+        for (int u0 = 0; u0 < kLdsTile; u0 += kTile) {
+            float tv[T][3], ta[T][3];
+#pragma unroll
+            for (int k = 0; k < T; ++k)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) tv[k][c] = ta[k][c] = 0.f;
+#pragma unroll 2
+            for (int u = u0; u < u0 + kTile; u += B) {
+                float4 qj[B], pj[B];
+#pragma unroll
+                for (int b = 0; b < B; ++b) {
+                    qj[b] = sq[u + b];
+                    pj[b] = sp[u + b];
+                }
+#pragma unroll
+                for (int k = 0; k < T; ++k) {
+                    float dx[B], dy[B], dz[B], g[B];
+#pragma unroll
+                    for (int b = 0; b < B; ++b) {
+                        dx[b] = x[k] - qj[b].x;
+                        dy[b] = y[k] - qj[b].y;
+                        dz[b] = z[k] - qj[b].z;
+                    }
+#pragma unroll
+                    for (int b = 0; b < B; ++b)
+                        g[b] = __builtin_amdgcn_exp2f(
+                            (dx[b] * dx[b] + dy[b] * dy[b] + dz[b] * dz[b]) * negc);
+#pragma unroll
+                    for (int b = 0; b < B; ++b) {
+                        tv[k][0] += g[b] * pj[b].x;
+                        tv[k][1] += g[b] * pj[b].y;
+                        tv[k][2] += g[b] * pj[b].z;
+                        if (WITH_A) {
+                            const float w =
+                                g[b] * (px[k] * pj[b].x + py[k] * pj[b].y + pz[k] * pj[b].z);
+                            ta[k][0] += w * dx[b];
+                            ta[k][1] += w * dy[b];
+                            ta[k][2] += w * dz[b];
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < T; ++k)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    sv[k][c] += (double)tv[k][c];
+                    if (WITH_A) sa[k][c] += (double)ta[k][c];
+                }
+        }
+    }
+    double *dst = part + (int64_t)blockIdx.y * 6 * ntgt;
+#pragma unroll
+    for (int k = 0; k < T; ++k) {
+        const int64_t i = t0 + 64 * k;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            dst[c * ntgt + i] = sv[k][c];
+            if (WITH_A) dst[(3 + c) * ntgt + i] = sa[k][c];
+        }
+    }
+}
+
+// ---------------------------------------------------------------- MFMA kernel
+// Matrix-core formulation of the same sums.  With c = log2(e) / (2 sigma^2),
+// k = sqrt(c), a per-wave origin o and scaled, centred coordinates
+// t_i = k (q_i - o), s_j = k (q_j - o):
+//   G_ij = exp2(-|t_i - s_j|^2)
+//   v_i  = sum_j G_ij p_j
+//   a_i  = sigma^-2 / k * sum_c p_ic (t_i M_ic - Q_ic)   with
+//   M_ic = sum_j G_ij p_jc,  Q_icd = sum_j G_ij p_jc s_jd.
+// The 3 + 9 = 12 source features (p_c, p_c s_d) form a 16 x 4 operand (rows
+// 12..15 are zero) and G for 16 targets x 4 sources the 4 x 16 operand of
+// v_mfma_f32_16x16x4_f32; only G itself (6 VALU + exp2 per pair) stays on
+// the vector ALU.  The centring keeps the cancellation in t M - Q small for
+// the near pairs that matter.  Each lane: source s = lane / 16 of the
+// current group of 4, feature / target row r = lane % 16.  Accumulators are
+// flushed to FP64 every kFlush sources.  The partial (v, a k sigma^2 ... )
+// sums are written in the layout of k_exact_pairs.
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+constexpr int kMTile = 256;   // sources staged in LDS per block step
+constexpr int kFlush = 64;    // sources summed in FP32 before the FP64 flush
+
+template <int T>
+__global__ __launch_bounds__(256) void k_exact_mfma(
+    const float4 *__restrict__ Qt, const float4 *__restrict__ Pt, int64_t ntgt,
+    const float4 *__restrict__ Qs, const float4 *__restrict__ Ps, int64_t chunk, int64_t nsrc,
+    float kscale, double inv_k, double *__restrict__ part) {
+    __shared__ float4 sq[kMTile];
+    __shared__ float4 sp[kMTile];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int r = lane & 15, ks = lane >> 4;
+    const int64_t tbase = ((int64_t)blockIdx.x * 4 + wv) * (16 * T);
+
+    const float4 o = Qt[tbase];  // wave origin: its first target
+    const float okx = o.x * kscale, oky = o.y * kscale, okz = o.z * kscale;
+    float tx[T], ty[T], tz[T];
+#pragma unroll
+    for (int g = 0; g < T; ++g) {
+        const float4 a = Qt[tbase + 16 * g + r];
+        tx[g] = fmaf(a.x, kscale, -okx);
+        ty[g] = fmaf(a.y, kscale, -oky);
+        tz[g] = fmaf(a.z, kscale, -okz);
+    }
+    // feature of this lane: r < 3 -> p_r; 3 <= r < 12 -> p_c s_d; else 0
+    const int csel = r < 3 ? r : (r < 12 ? (r - 3) / 3 : 3);
+    const int dsel = (r >= 3 && r < 12) ? (r - 3) % 3 : 3;
+    // one-hot weights pick s_dsel (or 1) without branches; exact in FP32
+    const float m0 = dsel == 0 ? 1.f : 0.f, m1 = dsel == 1 ? 1.f : 0.f;
+    const float m2 = dsel == 2 ? 1.f : 0.f, m3 = dsel == 3 ? 1.f : 0.f;
+
+    floatx4 acc[T];
+    double accd[T][4];
+#pragma unroll
+    for (int g = 0; g < T; ++g) {
+        acc[g] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) accd[g][i] = 0.0;
+    }
+    const int64_t j0 = (int64_t)blockIdx.y * chunk;
+    const int64_t j1 = j0 + chunk < nsrc ? j0 + chunk : nsrc;
+    const float *spf = reinterpret_cast<const float *>(sp);
+    for (int64_t jt = j0; jt < j1; jt += kMTile) {
+        __syncthreads();
+        sq[threadIdx.x] = Qs[jt + threadIdx.x];
+        sp[threadIdx.x] = Ps[jt + threadIdx.x];
+        __syncthreads();
+        for (int f0 = 0; f0 < kMTile; f0 += kFlush) {
+#pragma unroll
+            for (int c4 = f0; c4 < f0 + kFlush; c4 += 4) {
+                const float4 sj = sq[c4 + ks];
+                const float pc = spf[4 * (c4 + ks) + csel];
+                const float sx = fmaf(sj.x, kscale, -okx);
+                const float sy = fmaf(sj.y, kscale, -oky);
+                const float sz = fmaf(sj.z, kscale, -okz);
+                const float feat = pc * fmaf(m0, sx, fmaf(m1, sy, fmaf(m2, sz, m3)));
+#pragma unroll
+                for (int g = 0; g < T; ++g) {
+                    const float dx = tx[g] - sx, dy = ty[g] - sy, dz = tz[g] - sz;
+                    const float gv = __builtin_amdgcn_exp2f(-(dx * dx + dy * dy + dz * dz));
+                    acc[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(feat, gv, acc[g], 0, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int g = 0; g < T; ++g) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) accd[g][i] += (double)acc[g][i];
+                acc[g] = floatx4{0.f, 0.f, 0.f, 0.f};
+            }
+        }
+    }
+    // lane r + 16 b holds features 4b..4b+3 of target r; gather them in lane r
+    double *dst = part + (int64_t)blockIdx.y * 6 * ntgt;
+#pragma unroll
+    for (int g = 0; g < T; ++g) {
+        double f1[4], f2[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            f1[i] = __shfl(accd[g][i], r + 16, 64);
+            f2[i] = __shfl(accd[g][i], r + 32, 64);
+        }
+        if (ks == 0) {
+            const int64_t it = tbase + 16 * g + r;
+            const float4 pi = Pt[it];
+            const double M[3] = {accd[g][0], accd[g][1], accd[g][2]};
+            const double Q[3][3] = {{accd[g][3], f1[0], f1[1]},
+                                    {f1[2], f1[3], f2[0]},
+                                    {f2[1], f2[2], f2[3]}};
+            const double t[3] = {tx[g], ty[g], tz[g]};
+            const double pc[3] = {pi.x, pi.y, pi.z};
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                double s = 0.0;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) s += pc[c] * (t[d] * M[c] - Q[c][d]);
+                dst[d * ntgt + it] = M[d];
+                dst[(3 + d) * ntgt + it] = s * inv_k;
+            }
         }
     }
 }
@@ -313,22 +561,50 @@ inline unsigned nblocks(int64_t n, int b = kBlock) { return (unsigned)((n + b - 
 }  // namespace
 
 // ---------------------------------------------------------------- planning
-ExactPlan plan_exact(int64_t n_targets, int64_t n_sources) {
+// Targets per lane of the VALU kernel: more targets give each wave more
+// independent dependency chains per source; GS_EXACT_TPL (1, 2 or 4)
+// overrides the default for tuning.
+static int exact_tpl() {
+    static int v = [] {
+        const char *e = getenv("GS_EXACT_TPL");
+        const int t = e ? atoi(e) : 0;
+        return (t == 1 || t == 2 || t == 4) ? t : kExactTplDefault;
+    }();
+    return v;
+}
+
+// Source staging of the VALU kernel: scalar loads (default) or LDS tiles;
+// GS_EXACT_SRC=lds selects the latter (measured equal within 1% at 200k).
+static bool exact_lds() {
+    static bool v = [] {
+        const char *e = getenv("GS_EXACT_SRC");
+        return e && e[0] == 'l';
+    }();
+    return v;
+}
+
+ExactPlan plan_exact(int64_t n_targets, int64_t n_sources, bool mfma) {
     ExactPlan pl{};
     pl.n = n_targets;
-    pl.tpl = 2;
-    const int64_t tgt_per_block = 64 * pl.tpl * 4;
+    pl.tpl = exact_tpl();
+    pl.mfma = mfma;
+    // targets per block: VALU kernel 4 waves x 64 lanes x tpl; MFMA kernel
+    // 4 waves x kMfmaGroups x 16 (= 256); padded to 1024 so both fit; sources
+    // in steps of 256
+    const int64_t tgt_per_block = 1024;
     pl.ntgt = round_up(n_targets > 0 ? n_targets : 1, tgt_per_block);
-    pl.nsrc = round_up(n_sources > 0 ? n_sources : 1, kTile);
+    pl.nsrc = round_up(n_sources > 0 ? n_sources : 1, kMTile);
     // Aim at ~24 waves per SIMD (1024 SIMDs) so that the per-SIMD work is
     // balanced to a few percent; never split below one tile per split.
-    const int64_t waves_t = pl.ntgt / (64 * pl.tpl);
+    // the split count depends on n only (not on the kernel or its tuning), so
+    // workspace sizes never depend on those choices
+    const int64_t waves_t = pl.ntgt / 128;
     int64_t s = (24 * 1024 + waves_t - 1) / waves_t;
-    const int64_t max_s = pl.nsrc / kTile;
+    const int64_t max_s = pl.nsrc / kMTile;
     if (s > max_s) s = max_s;
     if (s > 64) s = 64;
     if (s < 1) s = 1;
-    pl.chunk = round_up((pl.nsrc + s - 1) / s, kTile);
+    pl.chunk = round_up((pl.nsrc + s - 1) / s, kMTile);
     pl.splits = (int)((pl.nsrc + pl.chunk - 1) / pl.chunk);
     return pl;
 }
@@ -360,16 +636,40 @@ gs_status launch_unpack(const float4 *Q, const float4 *P, int64_t n, float *q, f
 gs_status launch_exact_pairs(const ExactPlan &pl, const float4 *Qt, const float4 *Pt,
                              const float4 *Qs, const float4 *Ps, double sigma, bool with_a,
                              double *part, hipStream_t s) {
+    if (with_a && pl.mfma) {
+        const double c = kLog2e / (2.0 * sigma * sigma);
+        const float k = (float)sqrt(c);
+        dim3 grid((unsigned)(pl.ntgt / (16 * kMfmaGroups * 4)), (unsigned)pl.splits);
+        timing_begin(KIND_EXACT, s);
+        hipLaunchKernelGGL((k_exact_mfma<kMfmaGroups>), grid, dim3(256), 0, s, Qt, Pt, pl.ntgt, Qs,
+                           Ps, pl.chunk, pl.nsrc, k, 1.0 / (double)k, part);
+        timing_end(KIND_EXACT, s);
+        GS_LAUNCH_CHECK("exact_mfma");
+        return GS_OK;
+    }
     const float negc = (float)(-kLog2e / (2.0 * sigma * sigma));
     dim3 grid((unsigned)(pl.ntgt / (64 * pl.tpl * 4)), (unsigned)pl.splits);
     const int kind = with_a ? KIND_EXACT : KIND_EXACT_V;
     timing_begin(kind, s);
-    if (with_a)
-        hipLaunchKernelGGL((k_exact_pairs<2, true>), grid, dim3(256), 0, s, Qt, Pt, pl.ntgt, Qs,
-                           Ps, pl.chunk, pl.nsrc, negc, part);
-    else
-        hipLaunchKernelGGL((k_exact_pairs<2, false>), grid, dim3(256), 0, s, Qt, Pt, pl.ntgt,
-                           Qs, Ps, pl.chunk, pl.nsrc, negc, part);
+#define GS_PAIRS(T, A)                                                                     \
+    do {                                                                                   \
+        if (exact_lds())                                                                   \
+            hipLaunchKernelGGL((k_exact_pairs_lds<T, A>), grid, dim3(256), 0, s, Qt, Pt,   \
+                               pl.ntgt, Qs, Ps, pl.chunk, pl.nsrc, negc, part);            \
+        else                                                                               \
+            hipLaunchKernelGGL((k_exact_pairs<T, A>), grid, dim3(256), 0, s, Qt, Pt, pl.ntgt, \
+                               Qs, Ps, pl.chunk, pl.nsrc, negc, part);                     \
+    } while (0)
+    if (with_a) {
+        if (pl.tpl == 1) GS_PAIRS(1, true);
+        else if (pl.tpl == 4) GS_PAIRS(4, true);
+        else GS_PAIRS(2, true);
+    } else {
+        if (pl.tpl == 1) GS_PAIRS(1, false);
+        else if (pl.tpl == 4) GS_PAIRS(4, false);
+        else GS_PAIRS(2, false);
+    }
+#undef GS_PAIRS
     timing_end(kind, s);
     GS_LAUNCH_CHECK("exact_pairs");
     return GS_OK;

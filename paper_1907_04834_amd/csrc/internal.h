@@ -74,9 +74,12 @@ struct ExactPlan {
     int64_t ntgt;     // padded target count
     int splits;       // S
     int64_t chunk;    // sources per split (multiple of kTile)
-    int tpl;          // targets per lane
+    int tpl;          // targets per lane (VALU kernel)
+    bool mfma;        // (v, a) sums on the matrix cores
 };
-ExactPlan plan_exact(int64_t n_targets, int64_t n_sources);
+constexpr int kMfmaGroups = 4;  // groups of 16 targets per wave (MFMA kernel)
+constexpr int kExactTplDefault = 1;  // targets per lane (VALU kernel, measured best)
+ExactPlan plan_exact(int64_t n_targets, int64_t n_sources, bool mfma = false);
 
 // Buffers of one exact FP32 RHS evaluation.
 struct ExactBufs {

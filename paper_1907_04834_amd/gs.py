@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(_PKG, "libgsbh.so")
 GS_EXACT, GS_BH = 0, 1
 GS_OP_RHS, GS_OP_SHOOT, GS_OP_ADJOINT, GS_OP_FIELD = 0, 1, 2, 3
 GS_FLAG_F64 = 1
+GS_FLAG_MFMA_PAIRS = 2
 STATUS = {0: "GS_OK", -1: "GS_ERR_INVALID", -2: "GS_ERR_WORKSPACE", -3: "GS_ERR_HIP",
           -4: "GS_ERR_NONFINITE", -5: "GS_ERR_UNSUPPORTED"}
 
