@@ -167,8 +167,13 @@ gs_status gs_get_status(const void *ws, hipStream_t stream);
  * (gs_rhs_bh or gs_shoot with GS_BH) that used this workspace, summed over
  * all targets and all right-hand sides that call evaluated (nt + 1 for a
  * shooting that returns H, nt otherwise): out[0] exact pairs, out[1]
- * monopoles (approximated nodes), out[2] node visits, out[3] octree nodes. */
-gs_status gs_bh_counters(const void *ws, hipStream_t stream, int64_t out[4]);
+ * monopoles (approximated nodes), out[2] node visits, out[3] octree nodes.
+ * Wave-level diagnostics of the GPU traversal: out[4] leaf-point steps
+ * executed by waves (each serves up to 64 targets), out[5] node records
+ * decided by waves, out[6] the largest out[4] + out[5] of a single wave,
+ * out[7] reserved (0). */
+#define GS_BH_COUNTERS 8
+gs_status gs_bh_counters(const void *ws, hipStream_t stream, int64_t out[GS_BH_COUNTERS]);
 
 /* Per-launch timing of the dominant kernels.  While enabled, every launch of
  * a timed kernel kind is bracketed by HIP events on its stream.

@@ -75,8 +75,9 @@ namespace {
 struct WsHeader {
     int32_t status;
     int32_t pad;
-    unsigned long long counters[4];
+    unsigned long long counters[GS_BH_COUNTERS];
 };
+static_assert(sizeof(WsHeader) <= 256, "workspace header");
 constexpr size_t kHeader = 256;
 
 bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
@@ -394,7 +395,7 @@ gs_status gs_get_status(const void *ws, hipStream_t stream) {
     return GS_OK;
 }
 
-gs_status gs_bh_counters(const void *ws, hipStream_t stream, int64_t out[4]) {
+gs_status gs_bh_counters(const void *ws, hipStream_t stream, int64_t out[GS_BH_COUNTERS]) {
     if (!ws || !out) {
         set_error("NULL argument");
         return GS_ERR_INVALID;
@@ -402,7 +403,7 @@ gs_status gs_bh_counters(const void *ws, hipStream_t stream, int64_t out[4]) {
     GS_HIP(hipStreamSynchronize(stream));
     WsHeader h;
     GS_HIP(hipMemcpy(&h, ws, sizeof(h), hipMemcpyDeviceToHost));
-    for (int k = 0; k < 4; ++k) out[k] = (int64_t)h.counters[k];
+    for (int k = 0; k < GS_BH_COUNTERS; ++k) out[k] = (int64_t)h.counters[k];
     return GS_OK;
 }
 

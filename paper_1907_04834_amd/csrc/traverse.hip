@@ -26,7 +26,6 @@ namespace gs {
 namespace {
 
 typedef unsigned long long u64;
-constexpr int kStack = 192;  // > 7 siblings x 22 levels + 8
 
 __device__ inline bool decide(const BhNode &nd, double x, double y, double z,
                               const BhParams &bp) {
@@ -58,6 +57,37 @@ __device__ inline bool decide(const BhNode &nd, double x, double y, double z,
 
 enum Mode { MODE_RHS = 0, MODE_SHOOT = 1, MODE_ENERGY = 2 };
 
+// Per-wave LDS used by the traversal.
+constexpr int kBlockStack = 192;  // entries of (first child, count, lane mask)
+constexpr int kStage = 128;       // leaf points staged per round
+struct WaveLds {
+    u64 mask[kBlockStack];
+    int first[kBlockStack];
+    int count[kBlockStack];
+    BhNode node[8];      // the sibling block being decided
+    u64 lmask[8];        // leaf children of the block that need exact pairs
+    int lfirst[8], lcount[8], loff[8];
+    float4 lq[kStage + 4];  // staged leaf points (+4 readable pad entries)
+    float4 lp[kStage + 4];  // staged leaf momenta
+};
+
+// Orders the LDS writes of this wave before its following LDS reads (all
+// lanes of a wave run in lock step; this only stops compiler reordering).
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Traversal loop per sibling block:
+//   1. decide every node of the block (monopoles inline), record the leaf
+//      children that some lane opens, push the opened internal children;
+//   2. start loading the node records of the next block (top of stack);
+//   3. load the recorded leaves' points in rounds of kStage (one batch of
+//      loads per round) and add their exact pairs;
+//   4. store the prefetched records for the next iteration.
+// So each block costs about one memory round trip instead of one per node
+// and one per leaf.
 template <bool WITH_A>
 __global__ __launch_bounds__(256) void k_bh_traverse(
     const BhNode *__restrict__ nodes, const float4 *__restrict__ Qs, const float4 *__restrict__ Ps,
@@ -66,10 +96,10 @@ __global__ __launch_bounds__(256) void k_bh_traverse(
     double *__restrict__ Sp, float *__restrict__ q32, float *__restrict__ p32, double dt,
     double *__restrict__ Hpart, u64 *__restrict__ counters, const TreeMeta *__restrict__ meta,
     int *__restrict__ status) {
-    __shared__ int s_node[4][kStack];
-    __shared__ u64 s_mask[4][kStack];
+    __shared__ WaveLds lds_all[4];
     __shared__ double s_red[4];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    WaveLds &L = lds_all[wv];
     const int64_t t = ((int64_t)blockIdx.x * 4 + wv) * 64 + lane;
     const bool active = t < n;
     const float4 xq = active ? Qs[t] : make_float4(0.f, 0.f, 0.f, 0.f);
@@ -79,86 +109,147 @@ __global__ __launch_bounds__(256) void k_bh_traverse(
     double V[3] = {0, 0, 0}, A[3] = {0, 0, 0};
     float mv[3] = {0.f, 0.f, 0.f}, ma[3] = {0.f, 0.f, 0.f};
     unsigned c_pairs = 0, c_mono = 0, c_visit = 0;
+    unsigned w_steps = 0, w_nodes = 0;  // wave-level leaf-loop steps and node decisions
 
     int sp = 0;
     const u64 live = __ballot(active);
-    if (live != 0ull) {
-        s_node[wv][0] = 0;
-        s_mask[wv][0] = live;
+    if (live != 0ull) {  // the root as a block of one
+        L.first[0] = 0;
+        L.count[0] = 1;
+        L.mask[0] = live;
         sp = 1;
+        float4 *dstn = reinterpret_cast<float4 *>(L.node);
+        if (lane < 5) dstn[lane] = reinterpret_cast<const float4 *>(nodes)[lane];
     }
+    wave_sync();
     while (sp > 0) {
         --sp;
-        const int k = __builtin_amdgcn_readfirstlane(s_node[wv][sp]);
-        const u64 m = s_mask[wv][sp];
-        const BhNode nd = nodes[k];
+        const int bc = __builtin_amdgcn_readfirstlane(L.count[sp]);
+        const u64 m = L.mask[sp];
         const bool mine = (m >> lane) & 1ull;
-        bool need = false;
-        if (mine) {
-            ++c_visit;
-            if (decide(nd, xd, yd, zd, bp)) {
-                // n_k virtual points at C_k, momentum P_k / n_k each
-                const float dx = xq.x - (float)nd.cx, dy = xq.y - (float)nd.cy,
-                            dz = xq.z - (float)nd.cz;
-                const float g = __builtin_amdgcn_exp2f((dx * dx + dy * dy + dz * dz) * bp.negc);
-                mv[0] += g * nd.px;
-                mv[1] += g * nd.py;
-                mv[2] += g * nd.pz;
-                if (WITH_A) {
-                    const float w = g * (xp.x * nd.px + xp.y * nd.py + xp.z * nd.pz);
-                    ma[0] += w * dx;
-                    ma[1] += w * dy;
-                    ma[2] += w * dz;
-                }
-                ++c_mono;
-            } else {
-                need = true;
-            }
-        }
-        const u64 open = __ballot(need);
-        if (open == 0ull) continue;
-        if (nd.nchild == 0) {
-            // exact pairs with the leaf's members
-            float tv[3] = {0.f, 0.f, 0.f}, ta[3] = {0.f, 0.f, 0.f};
-            const int j1 = nd.first + nd.n;
-            for (int j = nd.first; j < j1; ++j) {
-                const float4 qj = Qs[j];
-                const float4 pj = Ps[j];
-                if (need) {
-                    const float dx = xq.x - qj.x, dy = xq.y - qj.y, dz = xq.z - qj.z;
+        // 1. decisions
+        int nleaf = 0, total = 0;
+        w_nodes += (unsigned)bc;
+        for (int k = 0; k < bc; ++k) {
+            const BhNode nd = L.node[k];
+            bool need = false;
+            if (mine) {
+                ++c_visit;
+                if (decide(nd, xd, yd, zd, bp)) {
+                    // n_k virtual points at C_k, momentum P_k / n_k each
+                    const float dx = xq.x - (float)nd.cx, dy = xq.y - (float)nd.cy,
+                                dz = xq.z - (float)nd.cz;
                     const float g =
                         __builtin_amdgcn_exp2f((dx * dx + dy * dy + dz * dz) * bp.negc);
-                    tv[0] += g * pj.x;
-                    tv[1] += g * pj.y;
-                    tv[2] += g * pj.z;
+                    mv[0] += g * nd.px;
+                    mv[1] += g * nd.py;
+                    mv[2] += g * nd.pz;
                     if (WITH_A) {
-                        const float w = g * (xp.x * pj.x + xp.y * pj.y + xp.z * pj.z);
-                        ta[0] += w * dx;
-                        ta[1] += w * dy;
-                        ta[2] += w * dz;
+                        const float w = g * (xp.x * nd.px + xp.y * nd.py + xp.z * nd.pz);
+                        ma[0] += w * dx;
+                        ma[1] += w * dy;
+                        ma[2] += w * dz;
                     }
+                    ++c_mono;
+                } else {
+                    need = true;
                 }
             }
-            if (need) {
-                c_pairs += (unsigned)nd.n;
+            const u64 open = __ballot(need);
+            if (open == 0ull) continue;
+            const int nfirst = __builtin_amdgcn_readfirstlane(nd.first);
+            const int ncount = __builtin_amdgcn_readfirstlane(nd.n);
+            const int nchild = __builtin_amdgcn_readfirstlane(nd.nchild);
+            if (need) c_pairs += nchild == 0 ? (unsigned)ncount : 0u;
+            if (nchild == 0) {
+                L.lmask[nleaf] = open;
+                L.lfirst[nleaf] = nfirst;
+                L.lcount[nleaf] = ncount;
+                L.loff[nleaf] = total;
+                total += ncount;
+                ++nleaf;
+            } else {
+                if (sp >= kBlockStack) {
+                    // cannot happen for trees of at most 22 levels; stop safely
+                    if (lane == 0 && status) *status = 2;
+                    sp = -1;
+                    break;
+                }
+                L.first[sp] = nfirst;
+                L.count[sp] = nchild;
+                L.mask[sp] = open;
+                ++sp;
+            }
+        }
+        if (sp < 0) break;
+        wave_sync();
+        // 2. prefetch the next block's node records (5 x 16 B per node)
+        float4 pre = make_float4(0.f, 0.f, 0.f, 0.f);
+        int pre_n = 0;
+        if (sp > 0) {
+            const int nf = __builtin_amdgcn_readfirstlane(L.first[sp - 1]);
+            pre_n = 5 * __builtin_amdgcn_readfirstlane(L.count[sp - 1]);
+            if (lane < pre_n) pre = reinterpret_cast<const float4 *>(nodes + nf)[lane];
+        }
+        // 3. exact pairs of the recorded leaves, kStage points per round
+        for (int r0 = 0; r0 < total; r0 += kStage) {
+            const int rcnt = total - r0 < kStage ? total - r0 : kStage;
+            for (int e = lane; e < rcnt; e += 64) {
+                const int g = r0 + e;  // position in the concatenated leaves
+                int r = 0;
+                for (int k = 1; k < nleaf; ++k)
+                    if (L.loff[k] <= g) r = k;
+                const int j = L.lfirst[r] + (g - L.loff[r]);
+                L.lq[e] = Qs[j];
+                L.lp[e] = Ps[j];
+            }
+            wave_sync();
+            for (int r = 0; r < nleaf; ++r) {
+                const int lo = L.loff[r], hi = lo + L.lcount[r];
+                const int a = lo > r0 ? lo : r0, b = hi < r0 + rcnt ? hi : r0 + rcnt;
+                if (a >= b) continue;
+                w_steps += (unsigned)(b - a);
+                const bool use = (L.lmask[r] >> lane) & 1ull;
+                if (!use) continue;
+                float tv[3] = {0.f, 0.f, 0.f}, ta[3] = {0.f, 0.f, 0.f};
+                // groups of 4 staged points: all LDS reads of a group are
+                // issued before its arithmetic (points past the leaf are
+                // masked by a zero weight)
+                for (int j = a - r0; j < b - r0; j += 4) {
+                    float4 qj[4], pj[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        qj[u] = L.lq[j + u];
+                        pj[u] = L.lp[j + u];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const float dx = xq.x - qj[u].x, dy = xq.y - qj[u].y, dz = xq.z - qj[u].z;
+                        float g = __builtin_amdgcn_exp2f((dx * dx + dy * dy + dz * dz) * bp.negc);
+                        g = (j + u < b - r0) ? g : 0.f;
+                        tv[0] += g * pj[u].x;
+                        tv[1] += g * pj[u].y;
+                        tv[2] += g * pj[u].z;
+                        if (WITH_A) {
+                            const float w =
+                                g * (xp.x * pj[u].x + xp.y * pj[u].y + xp.z * pj[u].z);
+                            ta[0] += w * dx;
+                            ta[1] += w * dy;
+                            ta[2] += w * dz;
+                        }
+                    }
+                }
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     V[c] += (double)tv[c];
                     if (WITH_A) A[c] += (double)ta[c];
                 }
             }
-        } else {
-            if (sp + nd.nchild > kStack) {
-                // cannot happen for trees of at most 22 levels; stop safely
-                if (lane == 0 && status) *status = 2;
-                break;
-            }
-            for (int c = nd.nchild - 1; c >= 0; --c) {
-                s_node[wv][sp] = nd.first + c;
-                s_mask[wv][sp] = open;
-                ++sp;
-            }
+            wave_sync();
         }
+        // 4. the next block's records
+        if (lane < pre_n) reinterpret_cast<float4 *>(L.node)[lane] = pre;
+        wave_sync();
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -179,7 +270,9 @@ __global__ __launch_bounds__(256) void k_bh_traverse(
         atomicAdd(&counters[1], cm);
         atomicAdd(&counters[2], cv);
         if (blockIdx.x == 0 && wv == 0) atomicAdd(&counters[3], (u64)meta->n_nodes);
-        (void)status;
+        atomicAdd(&counters[4], (u64)w_steps);
+        atomicAdd(&counters[5], (u64)w_nodes);
+        atomicMax(&counters[6], (u64)w_steps + (u64)w_nodes);
     }
 
     double e = 0.0;
@@ -245,7 +338,7 @@ __global__ void k_state_out(const double *__restrict__ Sq, const double *__restr
 // sequence can be captured in a graph).
 __global__ void k_clear_status(int *__restrict__ status, u64 *__restrict__ counters) {
     if (threadIdx.x == 0) *status = 0;
-    if (threadIdx.x < 4) counters[threadIdx.x] = 0ull;
+    if (threadIdx.x < GS_BH_COUNTERS) counters[threadIdx.x] = 0ull;
 }
 
 inline unsigned nblk(int64_t n, int b = kBlock) { return (unsigned)((n + b - 1) / b); }

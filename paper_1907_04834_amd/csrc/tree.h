@@ -64,7 +64,9 @@ struct TreeBufs {
     unsigned *cstart;          // [n] exclusive scan of nchild
     int *node_of;              // [n] node id of internal rank r
     int *parent_rank;          // [2n] internal rank of a node's parent (-1 root)
-    unsigned *counter;         // [2n] bottom-up arrival counters
+    unsigned *counter;         // [2n] bottom-up arrival counters (adjoint sums)
+    int *node_start;           // [2n] first sorted point of each node
+    char *chunk0, *chunk1;     // range summaries of 64 and 4096 sorted points
     double *nsum;              // [2n][6] FP64 sums of q and p per node
     BhNode *nodes;             // [2n]
     double *adj;               // [2n][6] per-node sums of alpha, beta (backward stage)

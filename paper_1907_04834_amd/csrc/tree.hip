@@ -38,6 +38,7 @@ constexpr int kSortThreads = 256;
 constexpr int kSortPerThread = 8;
 constexpr int kSortTile = kSortThreads * kSortPerThread;  // 2048 keys per block
 constexpr int kScanTile = 2048;                            // items per scan block
+constexpr int kChunk = 64;                                 // points per range summary
 
 inline unsigned nblk(int64_t n, int b = kBlock) { return (unsigned)((n + b - 1) / b); }
 
@@ -156,32 +157,7 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_hist(const u64 *__restrict_
         if (i < n) atomicAdd(&h[(unsigned)(keys[i] >> shift) & 255u], 1u);
     }
     __syncthreads();
-    hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
-}
-
-// Exclusive scan of `count` u32 values in place, by one block of 1024 threads
-// (each thread scans a contiguous run, then the run totals are scanned).
-__global__ __launch_bounds__(1024) void k_scan_small(unsigned *__restrict__ x, int64_t count) {
-    __shared__ unsigned tot[1024];
-    const int t = threadIdx.x;
-    const int64_t per = (count + 1023) / 1024;
-    const int64_t b = t * per, e = b + per < count ? b + per : count;
-    unsigned s = 0;
-    for (int64_t i = b; i < e; ++i) s += x[i];
-    tot[t] = s;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        unsigned v = t >= off ? tot[t - off] : 0u;
-        __syncthreads();
-        tot[t] += v;
-        __syncthreads();
-    }
-    unsigned run = t > 0 ? tot[t - 1] : 0u;
-    for (int64_t i = b; i < e; ++i) {
-        const unsigned v = x[i];
-        x[i] = run;
-        run += v;
-    }
+    hist[(int64_t)blockIdx.x * 256 + threadIdx.x] = h[threadIdx.x];
 }
 
 __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(
@@ -191,7 +167,26 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(
     __shared__ unsigned run[256];
     __shared__ unsigned wcnt[kSortThreads / 64][256];
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    base[t] = hist[(int64_t)t * nb + blockIdx.x];
+    // global offset of (digit t, this block): all keys with a smaller digit
+    // plus keys with digit t in earlier blocks (histograms are block-major)
+    {
+        unsigned before = 0, total = 0;
+        for (int b = 0; b < nb; ++b) {
+            const unsigned h = hist[(int64_t)b * 256 + t];
+            total += h;
+            if (b < (int)blockIdx.x) before += h;
+        }
+        run[t] = total;
+        __syncthreads();
+        for (int off = 1; off < 256; off <<= 1) {
+            const unsigned v = t >= off ? run[t - off] : 0u;
+            __syncthreads();
+            run[t] += v;
+            __syncthreads();
+        }
+        base[t] = run[t] - total + before;
+        __syncthreads();
+    }
     run[t] = 0;
     for (int w = 0; w < kSortThreads / 64; ++w) wcnt[w][t] = 0;
     __syncthreads();
@@ -429,7 +424,7 @@ __global__ void k_root(const u64 *__restrict__ K, int64_t n, int leaf_cap,
                        const unsigned *__restrict__ rank, const unsigned *__restrict__ nchild,
                        const unsigned *__restrict__ cstart, TreeMeta *__restrict__ meta,
                        BhNode *__restrict__ nodes, int *__restrict__ node_of,
-                       int *__restrict__ parent_rank, unsigned *__restrict__ counter) {
+                       int *__restrict__ parent_rank, int *__restrict__ node_start) {
     if (threadIdx.x != 0) return;
     BhNode nd;
     zero_stats(nd);
@@ -453,7 +448,7 @@ __global__ void k_root(const u64 *__restrict__ K, int64_t n, int leaf_cap,
     }
     nodes[0] = nd;
     parent_rank[0] = -1;
-    counter[0] = 0;
+    node_start[0] = 0;
 }
 
 __global__ __launch_bounds__(256) void k_nodes(const u64 *__restrict__ K, int leaf_cap,
@@ -467,7 +462,7 @@ __global__ __launch_bounds__(256) void k_nodes(const u64 *__restrict__ K, int le
                                                const unsigned *__restrict__ cstart,
                                                BhNode *__restrict__ nodes, int *__restrict__ node_of,
                                                int *__restrict__ parent_rank,
-                                               unsigned *__restrict__ counter) {
+                                               int *__restrict__ node_start) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= meta->n_internal || meta->root_leaf) return;
     const unsigned i = rank_bnd[r];
@@ -491,7 +486,7 @@ __global__ __launch_bounds__(256) void k_nodes(const u64 *__restrict__ K, int le
         }
         nodes[id] = nd;
         parent_rank[id] = (int)r;
-        counter[id] = 0;
+        node_start[id] = (int)a;
     }
 }
 
@@ -519,70 +514,127 @@ __device__ inline void finish_node(BhNode &nd, const double *sum, const float *l
     nd.s2 = s * s;
 }
 
-// Bottom-up statistics.  One thread per leaf computes the leaf from its
-// points, then climbs: the last child to arrive at a parent (atomic counter)
-// computes the parent from all its children in child order, so the result
-// does not depend on arrival order.
-__global__ __launch_bounds__(256) void k_stats(const float4 *__restrict__ Qs,
-                                               const float4 *__restrict__ Ps,
-                                               const TreeMeta *__restrict__ meta,
-                                               BhNode *__restrict__ nodes, double *__restrict__ nsum,
-                                               const int *__restrict__ node_of,
-                                               const int *__restrict__ parent_rank,
-                                               unsigned *__restrict__ counter) {
+// Statistics of contiguous ranges of sorted points.  A two-level summary
+// (chunks of 64 points, super-chunks of 64 chunks) lets every node reduce
+// its own range [start, start + n) independently: no inter-node ordering,
+// atomics or fences, and a fixed summation order (bitwise deterministic).
+struct RangeStat {
+    double s[6];  // sums of q (3) and p (3)
+    float lo[3], hi[3];
+};
+
+__device__ inline void rs_init(RangeStat &r) {
+    for (int c = 0; c < 6; ++c) r.s[c] = 0.0;
+    for (int c = 0; c < 3; ++c) {
+        r.lo[c] = INFINITY;
+        r.hi[c] = -INFINITY;
+    }
+}
+__device__ inline void rs_add(RangeStat &r, const RangeStat &o) {
+    for (int c = 0; c < 6; ++c) r.s[c] += o.s[c];
+    for (int c = 0; c < 3; ++c) {
+        r.lo[c] = fminf(r.lo[c], o.lo[c]);
+        r.hi[c] = fmaxf(r.hi[c], o.hi[c]);
+    }
+}
+__device__ inline void rs_point(RangeStat &r, const float4 a, const float4 b) {
+    r.s[0] += a.x;
+    r.s[1] += a.y;
+    r.s[2] += a.z;
+    r.s[3] += b.x;
+    r.s[4] += b.y;
+    r.s[5] += b.z;
+    r.lo[0] = fminf(r.lo[0], a.x);
+    r.lo[1] = fminf(r.lo[1], a.y);
+    r.lo[2] = fminf(r.lo[2], a.z);
+    r.hi[0] = fmaxf(r.hi[0], a.x);
+    r.hi[1] = fmaxf(r.hi[1], a.y);
+    r.hi[2] = fmaxf(r.hi[2], a.z);
+}
+
+// One wave per chunk: lane l takes item l of the chunk; fixed shuffle tree.
+__device__ inline void rs_wave_reduce(RangeStat &r) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) r.s[c] += __shfl_down(r.s[c], off, 64);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            r.lo[c] = fminf(r.lo[c], __shfl_down(r.lo[c], off, 64));
+            r.hi[c] = fmaxf(r.hi[c], __shfl_down(r.hi[c], off, 64));
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_chunks0(const float4 *__restrict__ Qs,
+                                                 const float4 *__restrict__ Ps, int64_t n,
+                                                 RangeStat *__restrict__ c0, int64_t nc0) {
+    const int lane = threadIdx.x & 63;
+    const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (c >= nc0) return;
+    RangeStat r;
+    rs_init(r);
+    const int64_t i = c * kChunk + lane;
+    if (i < n) rs_point(r, Qs[i], Ps[i]);
+    rs_wave_reduce(r);
+    if (lane == 0) c0[c] = r;
+}
+
+__global__ __launch_bounds__(256) void k_chunks1(const RangeStat *__restrict__ c0, int64_t nc0,
+                                                 RangeStat *__restrict__ c1, int64_t nc1) {
+    const int lane = threadIdx.x & 63;
+    const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (c >= nc1) return;
+    RangeStat r;
+    rs_init(r);
+    const int64_t i = c * kChunk + lane;
+    if (i < nc0) r = c0[i];
+    rs_wave_reduce(r);
+    if (lane == 0) c1[c] = r;
+}
+
+// Node statistics from its point range [a, b).
+__global__ __launch_bounds__(256) void k_node_stats(const float4 *__restrict__ Qs,
+                                                    const float4 *__restrict__ Ps,
+                                                    const RangeStat *__restrict__ c0,
+                                                    const RangeStat *__restrict__ c1,
+                                                    const TreeMeta *__restrict__ meta,
+                                                    const int *__restrict__ node_start,
+                                                    BhNode *__restrict__ nodes,
+                                                    double *__restrict__ nsum) {
     const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= meta->n_nodes) return;
     BhNode nd = nodes[id];
-    if (nd.nchild != 0) return;
-    double sum[6] = {0, 0, 0, 0, 0, 0};
-    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    for (int j = nd.first; j < nd.first + nd.n; ++j) {
-        const float4 a = Qs[j], b = Ps[j];
-        sum[0] += a.x;
-        sum[1] += a.y;
-        sum[2] += a.z;
-        sum[3] += b.x;
-        sum[4] += b.y;
-        sum[5] += b.z;
-        lo[0] = fminf(lo[0], a.x);
-        lo[1] = fminf(lo[1], a.y);
-        lo[2] = fminf(lo[2], a.z);
-        hi[0] = fmaxf(hi[0], a.x);
-        hi[1] = fmaxf(hi[1], a.y);
-        hi[2] = fmaxf(hi[2], a.z);
+    int64_t a = node_start[id];
+    const int64_t b = a + nd.n;
+    RangeStat r;
+    rs_init(r);
+    constexpr int64_t C0 = kChunk, C1 = (int64_t)kChunk * kChunk;
+    // points up to a chunk boundary, chunks up to a super-chunk boundary,
+    // super-chunks, then chunks and points of the tail
+    while (a < b && (a % C0 != 0 || a + C0 > b)) {
+        rs_point(r, Qs[a], Ps[a]);
+        ++a;
     }
-    finish_node(nd, sum, lo, hi);
+    while (a < b && a % C1 != 0 && a + C0 <= b) {
+        rs_add(r, c0[a / C0]);
+        a += C0;
+    }
+    while (a + C1 <= b) {
+        rs_add(r, c1[a / C1]);
+        a += C1;
+    }
+    while (a + C0 <= b) {
+        rs_add(r, c0[a / C0]);
+        a += C0;
+    }
+    while (a < b) {
+        rs_point(r, Qs[a], Ps[a]);
+        ++a;
+    }
+    finish_node(nd, r.s, r.lo, r.hi);
     nodes[id] = nd;
-    for (int c = 0; c < 6; ++c) nsum[6 * id + c] = sum[c];
-    int cur = (int)id;
-    while (true) {
-        const int pr = parent_rank[cur];
-        if (pr < 0) break;
-        const int par = node_of[pr];
-        __threadfence();
-        const unsigned old = __hip_atomic_fetch_add(&counter[par], 1u, __ATOMIC_ACQ_REL,
-                                                    __HIP_MEMORY_SCOPE_AGENT);
-        BhNode pn = nodes[par];
-        if (old + 1 != (unsigned)pn.nchild) break;
-        __threadfence();
-        double ps[6] = {0, 0, 0, 0, 0, 0};
-        float plo[3] = {INFINITY, INFINITY, INFINITY}, phi[3] = {-INFINITY, -INFINITY, -INFINITY};
-        for (int k = 0; k < pn.nchild; ++k) {
-            const int ch = pn.first + k;
-            const BhNode cn = nodes[ch];
-            for (int c = 0; c < 6; ++c) ps[c] += nsum[6 * ch + c];
-            plo[0] = fminf(plo[0], cn.lox);
-            plo[1] = fminf(plo[1], cn.loy);
-            plo[2] = fminf(plo[2], cn.loz);
-            phi[0] = fmaxf(phi[0], cn.hix);
-            phi[1] = fmaxf(phi[1], cn.hiy);
-            phi[2] = fmaxf(phi[2], cn.hiz);
-        }
-        finish_node(pn, ps, plo, phi);
-        nodes[par] = pn;
-        for (int c = 0; c < 6; ++c) nsum[6 * par + c] = ps[c];
-        cur = par;
-    }
+    for (int c = 0; c < 6; ++c) nsum[6 * id + c] = r.s[c];
 }
 
 // Node sums of per-point adjoint vectors (original order, [n][3] FP64).
@@ -670,6 +722,10 @@ void carve_tree(Arena &a, int64_t n, TreeBufs &t) {
     t.node_of = a.take<int>(m);
     t.parent_rank = a.take<int>(2 * m);
     t.counter = a.take<unsigned>(2 * m);
+    t.node_start = a.take<int>(2 * m);
+    t.chunk0 = reinterpret_cast<char *>(a.take<RangeStat>((m + kChunk - 1) / kChunk));
+    t.chunk1 = reinterpret_cast<char *>(
+        a.take<RangeStat>((m + kChunk * kChunk - 1) / (kChunk * kChunk)));
     t.nsum = a.take<double>(12 * m);
     t.nodes = a.take<BhNode>(2 * m);
     t.adj = a.take<double>(12 * m);
@@ -689,7 +745,6 @@ gs_status build_tree(const float *q, const float *p, int64_t n, int leaf_cap, Tr
     for (int pass = 0; pass < 8; ++pass) {
         const int shift = 8 * pass;
         hipLaunchKernelGGL(k_rs_hist, dim3(nb), dim3(kSortThreads), 0, s, ki, n, shift, nb, t.hist);
-        hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, s, t.hist, (int64_t)256 * nb);
         hipLaunchKernelGGL(k_rs_scatter, dim3(nb), dim3(kSortThreads), 0, s, ki, vi, ko, vo, n,
                            shift, nb, t.hist);
         u64 *tk = ki;
@@ -717,12 +772,17 @@ gs_status build_tree(const float *q, const float *p, int64_t n, int leaf_cap, Tr
     // affects cstart of ranks that do not exist.
     GS_TRY(scan_u32(t.nchild, t.cstart, n > 1 ? n - 1 : 1, t.scan_part, nullptr, s));
     hipLaunchKernelGGL(k_root, dim3(1), dim3(64), 0, s, K, n, leaf_cap, t.rank, t.nchild,
-                       t.cstart, t.meta, t.nodes, t.node_of, t.parent_rank, t.counter);
+                       t.cstart, t.meta, t.nodes, t.node_of, t.parent_rank, t.node_start);
     hipLaunchKernelGGL(k_nodes, dim3(nblk(n)), dim3(256), 0, s, K, leaf_cap, t.meta, t.lvl,
                        t.rank, t.bnd_s, t.bnd_e, t.rank_bnd, t.nchild, t.cstart, t.nodes,
-                       t.node_of, t.parent_rank, t.counter);
-    hipLaunchKernelGGL(k_stats, dim3(nblk(2 * n)), dim3(256), 0, s, t.Qs, t.Ps, t.meta, t.nodes,
-                       t.nsum, t.node_of, t.parent_rank, t.counter);
+                       t.node_of, t.parent_rank, t.node_start);
+    const int64_t nc0 = (n + kChunk - 1) / kChunk, nc1 = (nc0 + kChunk - 1) / kChunk;
+    RangeStat *c0 = reinterpret_cast<RangeStat *>(t.chunk0);
+    RangeStat *c1 = reinterpret_cast<RangeStat *>(t.chunk1);
+    hipLaunchKernelGGL(k_chunks0, dim3(nblk(nc0, 4)), dim3(256), 0, s, t.Qs, t.Ps, n, c0, nc0);
+    hipLaunchKernelGGL(k_chunks1, dim3(nblk(nc1, 4)), dim3(256), 0, s, c0, nc0, c1, nc1);
+    hipLaunchKernelGGL(k_node_stats, dim3(nblk(2 * n)), dim3(256), 0, s, t.Qs, t.Ps, c0, c1,
+                       t.meta, t.node_start, t.nodes, t.nsum);
     timing_end(KIND_TREE, s);
     GS_LAUNCH_CHECK("nodes/stats");
     return GS_OK;
