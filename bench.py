@@ -84,7 +84,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--leaf-cap", type=int, default=16)
+    ap.add_argument("--leaf-cap", type=int, default=64)
     ap.add_argument("--theta", type=float, default=0.5)
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-targets", type=int, default=20000)

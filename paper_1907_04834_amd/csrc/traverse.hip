@@ -57,18 +57,41 @@ __device__ inline bool decide(const BhNode &nd, double x, double y, double z,
 
 enum Mode { MODE_RHS = 0, MODE_SHOOT = 1, MODE_ENERGY = 2 };
 
-// Per-wave LDS used by the traversal.
+// ---------------------------------------------------------------- layout
+// Work split.  A wave owns 64 consecutive targets of the Morton order (a
+// group).  Phase 1 walks the tree for its group: it takes every decision,
+// adds the monopoles, and records each leaf that some lane must sum exactly
+// as an entry (leaf, lane mask) of the group's list.  Phase 2 runs one wave
+// per chunk of kChunkEntries list entries and adds their exact pairs, so the
+// near-field work of a dense group is spread over many waves.  Phase 3 adds
+// the partial sums of a target in a fixed order (phase 1, then chunk 0, 1,
+// ...): the result does not depend on scheduling.
 constexpr int kBlockStack = 192;  // entries of (first child, count, lane mask)
 constexpr int kStage = 128;       // leaf points staged per round
-struct WaveLds {
+constexpr int kListCap = 512;     // list entries per group (more are summed in phase 1)
+constexpr int kChunkEntries = 32;
+constexpr int kChunks = kListCap / kChunkEntries;
+constexpr int kParts = 1 + kChunks;
+
+struct LeafEntry {
+    u64 mask;
+    int first;
+    int count;
+};
+
+struct StageLds {
+    LeafEntry ent[kChunkEntries];
+    int off[kChunkEntries];
+    float4 lq[kStage + 4];  // staged leaf points (+4 readable pad entries)
+    float4 lp[kStage + 4];  // staged leaf momenta
+};
+
+struct DecideLds {
     u64 mask[kBlockStack];
     int first[kBlockStack];
     int count[kBlockStack];
-    BhNode node[8];      // the sibling block being decided
-    u64 lmask[8];        // leaf children of the block that need exact pairs
-    int lfirst[8], lcount[8], loff[8];
-    float4 lq[kStage + 4];  // staged leaf points (+4 readable pad entries)
-    float4 lp[kStage + 4];  // staged leaf momenta
+    BhNode node[8];  // the sibling block being decided
+    StageLds st;     // list overflow only
 };
 
 // Orders the LDS writes of this wave before its following LDS reads (all
@@ -79,37 +102,109 @@ __device__ inline void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Traversal loop per sibling block:
-//   1. decide every node of the block (monopoles inline), record the leaf
-//      children that some lane opens, push the opened internal children;
-//   2. start loading the node records of the next block (top of stack);
-//   3. load the recorded leaves' points in rounds of kStage (one batch of
-//      loads per round) and add their exact pairs;
-//   4. store the prefetched records for the next iteration.
-// So each block costs about one memory round trip instead of one per node
-// and one per leaf.
+// Exact pairs of the ne leaves in S.ent (lane masks in S.ent[].mask): their
+// points are staged in rounds of kStage with one batch of loads per round.
 template <bool WITH_A>
-__global__ __launch_bounds__(256) void k_bh_traverse(
+__device__ inline void leaf_pairs(StageLds &S, int ne, const float4 *__restrict__ Qs,
+                                  const float4 *__restrict__ Ps, int lane, float4 xq, float4 xp,
+                                  float negc, double *V, double *A, unsigned &steps) {
+    int total = 0;
+    for (int r = 0; r < ne; ++r) {
+        S.off[r] = total;
+        total += S.ent[r].count;
+    }
+    wave_sync();
+    for (int r0 = 0; r0 < total; r0 += kStage) {
+        const int rcnt = total - r0 < kStage ? total - r0 : kStage;
+        for (int e = lane; e < rcnt; e += 64) {
+            const int g = r0 + e;  // position in the concatenated leaves
+            int r = 0;
+            for (int k = 1; k < ne; ++k)
+                if (S.off[k] <= g) r = k;
+            const int j = S.ent[r].first + (g - S.off[r]);
+            S.lq[e] = Qs[j];
+            S.lp[e] = Ps[j];
+        }
+        // the 4 slots after the round are read by the last group of 4 with
+        // a zero weight: keep them finite
+        if (lane < 4) {
+            S.lq[rcnt + lane] = make_float4(0.f, 0.f, 0.f, 0.f);
+            S.lp[rcnt + lane] = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+        wave_sync();
+        for (int r = 0; r < ne; ++r) {
+            const int lo = S.off[r], hi = lo + S.ent[r].count;
+            const int a = lo > r0 ? lo : r0, b = hi < r0 + rcnt ? hi : r0 + rcnt;
+            if (a >= b) continue;
+            steps += (unsigned)(b - a);
+            if (!((S.ent[r].mask >> lane) & 1ull)) continue;
+            float tv[3] = {0.f, 0.f, 0.f}, ta[3] = {0.f, 0.f, 0.f};
+            for (int j = a - r0; j < b - r0; j += 4) {
+                float4 qj[4], pj[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    qj[u] = S.lq[j + u];
+                    pj[u] = S.lp[j + u];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const float dx = xq.x - qj[u].x, dy = xq.y - qj[u].y, dz = xq.z - qj[u].z;
+                    float g = __builtin_amdgcn_exp2f((dx * dx + dy * dy + dz * dz) * negc);
+                    g = (j + u < b - r0) ? g : 0.f;  // past the leaf: zero weight
+                    tv[0] += g * pj[u].x;
+                    tv[1] += g * pj[u].y;
+                    tv[2] += g * pj[u].z;
+                    if (WITH_A) {
+                        const float w = g * (xp.x * pj[u].x + xp.y * pj[u].y + xp.z * pj[u].z);
+                        ta[0] += w * dx;
+                        ta[1] += w * dy;
+                        ta[2] += w * dz;
+                    }
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                V[c] += (double)tv[c];
+                if (WITH_A) A[c] += (double)ta[c];
+            }
+        }
+        wave_sync();
+    }
+}
+
+__device__ inline void write_part(double *__restrict__ part, int slot, int64_t npad, int64_t t,
+                                  const double *V, const double *A) {
+    double *d = part + ((int64_t)slot * npad + t) * 6;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        d[c] = V[c];
+        d[3 + c] = A[c];
+    }
+}
+
+// Phase 1: decisions, monopoles and the group's list of leaves.
+template <bool WITH_A>
+__global__ __launch_bounds__(256) void k_bh_decide(
     const BhNode *__restrict__ nodes, const float4 *__restrict__ Qs, const float4 *__restrict__ Ps,
-    const unsigned *__restrict__ perm, int64_t n, BhParams bp, int mode,
-    float *__restrict__ dq, float *__restrict__ dp, double *__restrict__ Sq,
-    double *__restrict__ Sp, float *__restrict__ q32, float *__restrict__ p32, double dt,
-    double *__restrict__ Hpart, u64 *__restrict__ counters, const TreeMeta *__restrict__ meta,
+    int64_t n, int64_t npad, BhParams bp, LeafEntry *__restrict__ list, int *__restrict__ list_n,
+    double *__restrict__ part, u64 *__restrict__ counters, const TreeMeta *__restrict__ meta,
     int *__restrict__ status) {
-    __shared__ WaveLds lds_all[4];
-    __shared__ double s_red[4];
+    __shared__ DecideLds lds_all[4];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    WaveLds &L = lds_all[wv];
-    const int64_t t = ((int64_t)blockIdx.x * 4 + wv) * 64 + lane;
+    DecideLds &L = lds_all[wv];
+    const int64_t grp = (int64_t)blockIdx.x * 4 + wv;
+    if (grp * 64 >= n) return;  // wave-uniform; this kernel has no block barrier
+    const int64_t t = grp * 64 + lane;
     const bool active = t < n;
     const float4 xq = active ? Qs[t] : make_float4(0.f, 0.f, 0.f, 0.f);
     const float4 xp = active ? Ps[t] : make_float4(0.f, 0.f, 0.f, 0.f);
     const double xd = xq.x, yd = xq.y, zd = xq.z;
+    LeafEntry *mylist = list + grp * kListCap;
 
     double V[3] = {0, 0, 0}, A[3] = {0, 0, 0};
     float mv[3] = {0.f, 0.f, 0.f}, ma[3] = {0.f, 0.f, 0.f};
-    unsigned c_pairs = 0, c_mono = 0, c_visit = 0;
-    unsigned w_steps = 0, w_nodes = 0;  // wave-level leaf-loop steps and node decisions
+    unsigned c_pairs = 0, c_mono = 0, c_visit = 0, w_steps = 0, w_nodes = 0;
+    int nlist = 0;
 
     int sp = 0;
     const u64 live = __ballot(active);
@@ -127,8 +222,6 @@ __global__ __launch_bounds__(256) void k_bh_traverse(
         const int bc = __builtin_amdgcn_readfirstlane(L.count[sp]);
         const u64 m = L.mask[sp];
         const bool mine = (m >> lane) & 1ull;
-        // 1. decisions
-        int nleaf = 0, total = 0;
         w_nodes += (unsigned)bc;
         for (int k = 0; k < bc; ++k) {
             const BhNode nd = L.node[k];
@@ -160,14 +253,28 @@ __global__ __launch_bounds__(256) void k_bh_traverse(
             const int nfirst = __builtin_amdgcn_readfirstlane(nd.first);
             const int ncount = __builtin_amdgcn_readfirstlane(nd.n);
             const int nchild = __builtin_amdgcn_readfirstlane(nd.nchild);
-            if (need) c_pairs += nchild == 0 ? (unsigned)ncount : 0u;
             if (nchild == 0) {
-                L.lmask[nleaf] = open;
-                L.lfirst[nleaf] = nfirst;
-                L.lcount[nleaf] = ncount;
-                L.loff[nleaf] = total;
-                total += ncount;
-                ++nleaf;
+                if (need) c_pairs += (unsigned)ncount;
+                if (nlist < kListCap) {
+                    if (lane == 0) {
+                        LeafEntry e;
+                        e.mask = open;
+                        e.first = nfirst;
+                        e.count = ncount;
+                        mylist[nlist] = e;
+                    }
+                    ++nlist;
+                } else {
+                    // list full: sum this leaf here
+                    wave_sync();
+                    if (lane == 0) {
+                        L.st.ent[0].mask = open;
+                        L.st.ent[0].first = nfirst;
+                        L.st.ent[0].count = ncount;
+                    }
+                    wave_sync();
+                    leaf_pairs<WITH_A>(L.st, 1, Qs, Ps, lane, xq, xp, bp.negc, V, A, w_steps);
+                }
             } else {
                 if (sp >= kBlockStack) {
                     // cannot happen for trees of at most 22 levels; stop safely
@@ -183,79 +290,23 @@ __global__ __launch_bounds__(256) void k_bh_traverse(
         }
         if (sp < 0) break;
         wave_sync();
-        // 2. prefetch the next block's node records (5 x 16 B per node)
-        float4 pre = make_float4(0.f, 0.f, 0.f, 0.f);
-        int pre_n = 0;
+        // the next block's node records (5 x 16 B per node)
         if (sp > 0) {
             const int nf = __builtin_amdgcn_readfirstlane(L.first[sp - 1]);
-            pre_n = 5 * __builtin_amdgcn_readfirstlane(L.count[sp - 1]);
-            if (lane < pre_n) pre = reinterpret_cast<const float4 *>(nodes + nf)[lane];
+            const int pre_n = 5 * __builtin_amdgcn_readfirstlane(L.count[sp - 1]);
+            if (lane < pre_n)
+                reinterpret_cast<float4 *>(L.node)[lane] =
+                    reinterpret_cast<const float4 *>(nodes + nf)[lane];
         }
-        // 3. exact pairs of the recorded leaves, kStage points per round
-        for (int r0 = 0; r0 < total; r0 += kStage) {
-            const int rcnt = total - r0 < kStage ? total - r0 : kStage;
-            for (int e = lane; e < rcnt; e += 64) {
-                const int g = r0 + e;  // position in the concatenated leaves
-                int r = 0;
-                for (int k = 1; k < nleaf; ++k)
-                    if (L.loff[k] <= g) r = k;
-                const int j = L.lfirst[r] + (g - L.loff[r]);
-                L.lq[e] = Qs[j];
-                L.lp[e] = Ps[j];
-            }
-            wave_sync();
-            for (int r = 0; r < nleaf; ++r) {
-                const int lo = L.loff[r], hi = lo + L.lcount[r];
-                const int a = lo > r0 ? lo : r0, b = hi < r0 + rcnt ? hi : r0 + rcnt;
-                if (a >= b) continue;
-                w_steps += (unsigned)(b - a);
-                const bool use = (L.lmask[r] >> lane) & 1ull;
-                if (!use) continue;
-                float tv[3] = {0.f, 0.f, 0.f}, ta[3] = {0.f, 0.f, 0.f};
-                // groups of 4 staged points: all LDS reads of a group are
-                // issued before its arithmetic (points past the leaf are
-                // masked by a zero weight)
-                for (int j = a - r0; j < b - r0; j += 4) {
-                    float4 qj[4], pj[4];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        qj[u] = L.lq[j + u];
-                        pj[u] = L.lp[j + u];
-                    }
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const float dx = xq.x - qj[u].x, dy = xq.y - qj[u].y, dz = xq.z - qj[u].z;
-                        float g = __builtin_amdgcn_exp2f((dx * dx + dy * dy + dz * dz) * bp.negc);
-                        g = (j + u < b - r0) ? g : 0.f;
-                        tv[0] += g * pj[u].x;
-                        tv[1] += g * pj[u].y;
-                        tv[2] += g * pj[u].z;
-                        if (WITH_A) {
-                            const float w =
-                                g * (xp.x * pj[u].x + xp.y * pj[u].y + xp.z * pj[u].z);
-                            ta[0] += w * dx;
-                            ta[1] += w * dy;
-                            ta[2] += w * dz;
-                        }
-                    }
-                }
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    V[c] += (double)tv[c];
-                    if (WITH_A) A[c] += (double)ta[c];
-                }
-            }
-            wave_sync();
-        }
-        // 4. the next block's records
-        if (lane < pre_n) reinterpret_cast<float4 *>(L.node)[lane] = pre;
         wave_sync();
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         V[c] += (double)mv[c];
-        A[c] = (A[c] + (double)ma[c]) * bp.inv_s2;
+        A[c] += (double)ma[c];
     }
+    write_part(part, 0, npad, t, V, A);
+    if (lane == 0) list_n[grp] = nlist;
 
     // counters: wave sums, one atomic per wave (integer, order-free)
     u64 cp = c_pairs, cm = c_mono, cv = c_visit;
@@ -269,20 +320,76 @@ __global__ __launch_bounds__(256) void k_bh_traverse(
         atomicAdd(&counters[0], cp);
         atomicAdd(&counters[1], cm);
         atomicAdd(&counters[2], cv);
-        if (blockIdx.x == 0 && wv == 0) atomicAdd(&counters[3], (u64)meta->n_nodes);
+        if (grp == 0) atomicAdd(&counters[3], (u64)meta->n_nodes);
         atomicAdd(&counters[4], (u64)w_steps);
         atomicAdd(&counters[5], (u64)w_nodes);
         atomicMax(&counters[6], (u64)w_steps + (u64)w_nodes);
     }
+}
 
+// Phase 2: one wave per (group, chunk of kChunkEntries list entries).
+template <bool WITH_A>
+__global__ __launch_bounds__(256) void k_bh_leaves(const float4 *__restrict__ Qs,
+                                                   const float4 *__restrict__ Ps, int64_t n,
+                                                   int64_t npad, float negc,
+                                                   const LeafEntry *__restrict__ list,
+                                                   const int *__restrict__ list_n,
+                                                   double *__restrict__ part,
+                                                   u64 *__restrict__ counters) {
+    __shared__ StageLds lds_all[4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t grp = blockIdx.x;
+    const int chunk = blockIdx.y * 4 + wv;
+    const int cnt = list_n[grp];
+    const int e0 = chunk * kChunkEntries;
+    if (e0 >= cnt) return;  // wave-uniform: this chunk holds no entries
+    const int ne = cnt - e0 < kChunkEntries ? cnt - e0 : kChunkEntries;
+    StageLds &S = lds_all[wv];
+    if (lane < ne) S.ent[lane] = list[grp * kListCap + e0 + lane];
+    const int64_t t = grp * 64 + lane;
+    const bool active = t < n;
+    const float4 xq = active ? Qs[t] : make_float4(0.f, 0.f, 0.f, 0.f);
+    const float4 xp = active ? Ps[t] : make_float4(0.f, 0.f, 0.f, 0.f);
+    double V[3] = {0, 0, 0}, A[3] = {0, 0, 0};
+    unsigned steps = 0;
+    wave_sync();
+    leaf_pairs<WITH_A>(S, ne, Qs, Ps, lane, xq, xp, negc, V, A, steps);
+    write_part(part, 1 + chunk, npad, t, V, A);
+    if (lane == 0 && counters) {
+        atomicAdd(&counters[4], (u64)steps);
+        atomicMax(&counters[6], (u64)steps);
+    }
+}
+
+// Phase 3: fixed-order sum of a target's parts and the output of the mode.
+template <bool WITH_A>
+__global__ __launch_bounds__(256) void k_bh_combine(
+    const double *__restrict__ part, const int *__restrict__ list_n,
+    const unsigned *__restrict__ perm, int64_t n, int64_t npad, double inv_s2, int mode,
+    float *__restrict__ dq, float *__restrict__ dp, double *__restrict__ Sq,
+    double *__restrict__ Sp, float *__restrict__ q32, float *__restrict__ p32, double dt,
+    double *__restrict__ Hpart) {
+    __shared__ double s_red[4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double e = 0.0;
-    if (active) {
+    if (t < n) {
+        const int nch = (list_n[t / 64] + kChunkEntries - 1) / kChunkEntries;
+        double V[3] = {0, 0, 0}, A[3] = {0, 0, 0};
+        for (int s = 0; s <= nch; ++s) {
+            const double *d = part + ((int64_t)s * npad + t) * 6;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                V[c] += d[c];
+                A[c] += d[3 + c];
+            }
+        }
         const int64_t i = perm[t];
         if (mode == MODE_RHS) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 dq[3 * i + c] = (float)V[c];
-                if (WITH_A) dp[3 * i + c] = (float)A[c];
+                if (WITH_A) dp[3 * i + c] = (float)(A[c] * inv_s2);
             }
         } else {
             double q[3], p[3];
@@ -296,7 +403,7 @@ __global__ __launch_bounds__(256) void k_bh_traverse(
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     q[c] += dt * V[c];
-                    p[c] += dt * A[c];
+                    p[c] += dt * (A[c] * inv_s2);
                     Sq[3 * i + c] = q[c];
                     Sp[3 * i + c] = p[c];
                     q32[3 * i + c] = (float)q[c];
@@ -349,6 +456,12 @@ constexpr size_t kStatusOffset = 0;  // status word at the start of the workspac
 
 int traverse_blocks(int64_t n) { return (int)nblk(n > 0 ? n : 1, 256); }
 
+size_t traverse_list_bytes(int64_t n) {
+    return (size_t)((n + 63) / 64) * kListCap * sizeof(LeafEntry);
+}
+
+size_t traverse_part_doubles(int64_t n) { return (size_t)kParts * ((n + 63) / 64) * 64 * 6; }
+
 BhParams make_bh_params(const gs_params &prm) {
     BhParams b{};
     const double s = prm.sigma;
@@ -365,17 +478,27 @@ BhParams make_bh_params(const gs_params &prm) {
 gs_status launch_bh_traverse(const TreeBufs &t, const BhParams &bp, bool with_a,
                              const TraverseOut &o, unsigned long long *counters, hipStream_t s,
                              int mode, int *status) {
-    const unsigned grid = (unsigned)traverse_blocks(t.n);
+    const int64_t groups = (t.n + 63) / 64;
+    const int64_t npad = groups * 64;
+    LeafEntry *list = reinterpret_cast<LeafEntry *>(t.list);
     const int kind = with_a ? KIND_TRAVERSE : KIND_TRAVERSE_V;
     timing_begin(kind, s);
+#define GS_PHASES(A)                                                                            \
+    do {                                                                                        \
+        hipLaunchKernelGGL(k_bh_decide<A>, dim3((unsigned)((groups + 3) / 4)), dim3(256), 0, s, \
+                           t.nodes, t.Qs, t.Ps, t.n, npad, bp, list, t.list_n, t.part,          \
+                           counters, t.meta, status);                                           \
+        hipLaunchKernelGGL(k_bh_leaves<A>, dim3((unsigned)groups, kChunks / 4), dim3(256), 0, s, \
+                           t.Qs, t.Ps, t.n, npad, bp.negc, list, t.list_n, t.part, counters);   \
+        hipLaunchKernelGGL(k_bh_combine<A>, dim3((unsigned)traverse_blocks(t.n)), dim3(256), 0, \
+                           s, t.part, t.list_n, t.valA, t.n, npad, bp.inv_s2, mode, o.dq, o.dp, \
+                           o.Sq, o.Sp, o.q32, o.p32, o.dt, o.Hpart);                            \
+    } while (0)
     if (with_a)
-        hipLaunchKernelGGL(k_bh_traverse<true>, dim3(grid), dim3(256), 0, s, t.nodes, t.Qs, t.Ps,
-                           t.valA, t.n, bp, mode, o.dq, o.dp, o.Sq, o.Sp, o.q32, o.p32, o.dt,
-                           o.Hpart, counters, t.meta, status);
+        GS_PHASES(true);
     else
-        hipLaunchKernelGGL(k_bh_traverse<false>, dim3(grid), dim3(256), 0, s, t.nodes, t.Qs,
-                           t.Ps, t.valA, t.n, bp, mode, o.dq, o.dp, o.Sq, o.Sp, o.q32, o.p32,
-                           o.dt, o.Hpart, counters, t.meta, status);
+        GS_PHASES(false);
+#undef GS_PHASES
     timing_end(kind, s);
     GS_LAUNCH_CHECK("bh_traverse");
     return GS_OK;

@@ -70,7 +70,14 @@ struct TreeBufs {
     double *nsum;              // [2n][6] FP64 sums of q and p per node
     BhNode *nodes;             // [2n]
     double *adj;               // [2n][6] per-node sums of alpha, beta (backward stage)
+    // traversal work split (see traverse.hip)
+    char *list;                // [groups][kListCap] leaf entries of each group
+    int *list_n;               // [groups] entries used
+    double *part;              // [1 + chunks][groups * 64][6] partial (v, a) sums
 };
+// Sizes of the traversal's work-split buffers (defined in traverse.hip).
+size_t traverse_list_bytes(int64_t n);
+size_t traverse_part_doubles(int64_t n);
 void carve_tree(Arena &a, int64_t n, TreeBufs &t);
 
 // Builds the tree of (q, p) (float [n][3]) into t.  `status` (nullable) is an

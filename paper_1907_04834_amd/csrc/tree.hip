@@ -729,6 +729,9 @@ void carve_tree(Arena &a, int64_t n, TreeBufs &t) {
     t.nsum = a.take<double>(12 * m);
     t.nodes = a.take<BhNode>(2 * m);
     t.adj = a.take<double>(12 * m);
+    t.list = a.take<char>(traverse_list_bytes(m));
+    t.list_n = a.take<int>((m + 63) / 64);
+    t.part = a.take<double>(traverse_part_doubles(m));
 }
 
 gs_status build_tree(const float *q, const float *p, int64_t n, int leaf_cap, TreeBufs &t,

@@ -48,7 +48,7 @@ def ellipsoids8_200k(method: str, theta: float = 0.5, leaf_cap: int = 1):
 JOBS = {
     "ellipsoids8_200k_exact": lambda: ellipsoids8_200k("exact"),
     "ellipsoids8_200k_bh05_lc1": lambda: ellipsoids8_200k("bh", 0.5, 1),
-    "ellipsoids8_200k_bh05_lc16": lambda: ellipsoids8_200k("bh", 0.5, 16),
+    "ellipsoids8_200k_bh05_lc64": lambda: ellipsoids8_200k("bh", 0.5, 64),
 }
 
 
