@@ -64,7 +64,7 @@ typedef enum {
     GS_OP_RHS = 0,      /* gs_rhs_exact / gs_rhs_bh / gs_rhs_exact_f64        */
     GS_OP_SHOOT = 1,    /* gs_shoot / gs_shoot_f64                            */
     GS_OP_ADJOINT = 2,  /* gs_shoot_adjoint                                   */
-    GS_OP_FIELD = 3     /* gs_field                                           */
+    GS_OP_FIELD = 3     /* gs_field (pass n = max(targets, sources))          */
 } gs_op;
 
 /* flags */
@@ -142,11 +142,22 @@ gs_status gs_shoot_f64(const double *q0, const double *p0, int64_t n,
 
 /* Objective and gradient (Sec. 2.1 eq. 2; backward stage of Sec. 2.2):
  *   E(p0) = (1/n) sum_i |q_i(1) - target_i|^2 + lambda <p0, K(q0) p0>
- * and grad = dE/dp0 by the discrete adjoint of the Euler scheme.  The forward
- * states are kept every `ckpt_every` steps and the steps in between are
- * recomputed during the backward sweep.  On the Barnes-Hut path the backward
- * stage also uses node sums of the adjoint variables.  objective is a DEVICE
- * double[1]; grad_p0 a DEVICE float[n][3]. */
+ * and grad = dE/dp0 by the discrete adjoint of the Euler scheme:
+ *   alpha(1) = 2 (q(1) - target) / n, beta(1) = 0;
+ *   (alpha, beta)_t = (alpha, beta)_{t+1} + dt J(q_t, p_t)^T (alpha, beta)_{t+1};
+ *   grad = beta(0) + 2 lambda K(q0) p0.
+ * The forward states are kept (FP64) every `ckpt_every` steps and the steps
+ * in between are recomputed during the backward sweep.  With GS_BH the
+ * forward steps are Barnes-Hut steps and the backward products use the tree
+ * of q_t with node sums of alpha and beta: an approximated node contributes
+ * as n_k virtual points carrying the node means of p, alpha and beta (the
+ * paper's backward stage).  objective is a DEVICE double[1]; grad_p0 a
+ * DEVICE float[n][3]; target a DEVICE float[n][3].  ckpt_every >= 1 (values
+ * above nt act as nt); lambda finite.  The workspace comes from
+ * gs_adjoint_workspace_bytes (gs_workspace_bytes with GS_OP_ADJOINT assumes
+ * ckpt_every = 8). */
+size_t gs_adjoint_workspace_bytes(int64_t n, const gs_params *prm, int32_t method,
+                                  int32_t ckpt_every);
 gs_status gs_shoot_adjoint(const float *q0, const float *p0, const float *target,
                            int64_t n, const gs_params *prm, int32_t method,
                            double lambda, int32_t ckpt_every, double *objective,

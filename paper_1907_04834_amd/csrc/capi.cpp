@@ -9,6 +9,7 @@
 #include <mutex>
 #include <vector>
 
+#include "adjoint.h"
 #include "internal.h"
 #include "tree.h"
 
@@ -182,6 +183,14 @@ ShootF64Bufs layout_shoot_f64(Arena &a, int64_t n, int nt) {
     return b;
 }
 
+// Field evaluation: sources packed as for an RHS of max(m, n) points, plus the
+// packed targets.  `big` = max(m, n) bounds both plans.
+float4 *layout_field(Arena &a, int64_t big, ExactBufs &b) {
+    ExactPlan pl = plan_exact(big, big);
+    carve_exact(a, pl, b);
+    return a.take<float4>(pl.ntgt > pl.nsrc ? pl.ntgt : pl.nsrc);
+}
+
 size_t measure_bytes(int64_t n, const gs_params *prm, int32_t method, int32_t op) {
     Arena a{nullptr, kHeader, 0};
     const bool f64 = (prm->flags & GS_FLAG_F64) != 0;
@@ -205,9 +214,14 @@ size_t measure_bytes(int64_t n, const gs_params *prm, int32_t method, int32_t op
                 layout_shoot_bh(a, n, prm->nt);
             }
             break;
+        case GS_OP_ADJOINT: {
+            const int ck = prm->nt < 8 ? prm->nt : 8;
+            layout_adjoint(a, n, prm->nt, ck, method);
+            break;
+        }
         case GS_OP_FIELD: {
             ExactBufs b;
-            carve_exact(a, plan_exact(n, n), b);
+            layout_field(a, n, b);
             break;
         }
         default:
@@ -361,23 +375,80 @@ gs_status gs_rhs_bh(const float *q, const float *p, int64_t n, const gs_params *
     return rhs_bh(q, p, n, *prm, dq, dp, t, static_cast<char *>(ws), stream);
 }
 
+size_t gs_adjoint_workspace_bytes(int64_t n, const gs_params *prm, int32_t method,
+                                  int32_t ckpt_every) {
+    if (check_n(n) != GS_OK || !prm || prm->nt < 1 || ckpt_every < 1) return 0;
+    if (method != GS_EXACT && method != GS_BH) return 0;
+    Arena a{nullptr, kHeader, 0};
+    const int ck = ckpt_every < prm->nt ? ckpt_every : prm->nt;
+    layout_adjoint(a, n, prm->nt, ck, method);
+    return a.off + 256;
+}
+
 gs_status gs_shoot_adjoint(const float *q0, const float *p0, const float *target, int64_t n,
                            const gs_params *prm, int32_t method, double lambda,
                            int32_t ckpt_every, double *objective, float *grad_p0, void *ws,
                            size_t ws_bytes, hipStream_t stream) {
-    (void)q0, (void)p0, (void)target, (void)n, (void)prm, (void)method, (void)lambda;
-    (void)ckpt_every, (void)objective, (void)grad_p0, (void)ws, (void)ws_bytes, (void)stream;
-    set_error("gs_shoot_adjoint: not built yet");
-    return GS_ERR_UNSUPPORTED;
+    GS_TRY(check_n(n));
+    if (method != GS_EXACT && method != GS_BH) {
+        set_error("unknown method %d", method);
+        return GS_ERR_INVALID;
+    }
+    GS_TRY(check_params(prm, true, method == GS_BH));
+    if (!std::isfinite(lambda)) {
+        set_error("lambda must be finite");
+        return GS_ERR_INVALID;
+    }
+    if (ckpt_every < 1) {
+        set_error("ckpt_every must be >= 1 (got %d)", ckpt_every);
+        return GS_ERR_INVALID;
+    }
+    if (n == 0) return GS_OK;
+    GS_TRY(check_ptrs({q0, p0, target, objective, grad_p0}));
+    const size_t need = gs_adjoint_workspace_bytes(n, prm, method, ckpt_every);
+    GS_TRY(check_ws(ws, ws_bytes, need));
+    Arena a{static_cast<char *>(ws), kHeader, ws_bytes};
+    const int ck = ckpt_every < prm->nt ? ckpt_every : prm->nt;
+    AdjointBufs b = layout_adjoint(a, n, prm->nt, ck, method);
+    return shoot_adjoint(q0, p0, target, *prm, lambda, objective, grad_p0, b,
+                         static_cast<char *>(ws), stream);
 }
 
 gs_status gs_field(const float *x, int64_t m, const float *q, const float *p, int64_t n,
                    const gs_params *prm, float *v, void *ws, size_t ws_bytes,
                    hipStream_t stream) {
-    (void)x, (void)m, (void)q, (void)p, (void)n, (void)prm, (void)v, (void)ws, (void)ws_bytes;
-    (void)stream;
-    set_error("gs_field: not built yet");
-    return GS_ERR_UNSUPPORTED;
+    GS_TRY(check_n(m));
+    GS_TRY(check_n(n));
+    GS_TRY(check_params(prm, false, false));
+    if (m == 0) return GS_OK;
+    GS_TRY(check_ptrs({x, v}));
+    if (n == 0) {
+        set_error("gs_field: no sources (n == 0) but m > 0 targets");
+        return GS_ERR_INVALID;
+    }
+    GS_TRY(check_ptrs({q, p}));
+    const int64_t big = m > n ? m : n;
+    gs_params pr = *prm;
+    pr.flags &= ~GS_FLAG_F64;
+    GS_TRY(check_ws(ws, ws_bytes, measure_bytes(big, &pr, GS_EXACT, GS_OP_FIELD)));
+    Arena a{static_cast<char *>(ws), kHeader, ws_bytes};
+    ExactBufs b;
+    float4 *X = layout_field(a, big, b);
+    // the partial sums were sized for max(m, n) x max(m, n); fewer targets may
+    // ask for more source splits, so cap the splits to that capacity
+    const ExactPlan pb = plan_exact(big, big);
+    ExactPlan pl = plan_exact(m, n);
+    const int64_t cap = (int64_t)pb.splits * pb.ntgt;
+    if ((int64_t)pl.splits * pl.ntgt > cap) {
+        const int64_t smax = cap / pl.ntgt;
+        pl.chunk = round_up((pl.nsrc + smax - 1) / smax, pl.chunk_quantum);
+        pl.splits = (int)((pl.nsrc + pl.chunk - 1) / pl.chunk);
+    }
+    const int64_t spad = pl.nsrc;
+    GS_TRY(launch_pack(q, p, n, spad, b.Q, b.P, stream));
+    GS_TRY(launch_pack_pos(x, m, pl.ntgt, X, stream));
+    GS_TRY(launch_exact_pairs(pl, X, nullptr, b.Q, b.P, prm->sigma, false, b.part, stream));
+    return launch_combine_rhs(pl, b.part, prm->sigma, v, nullptr, stream);
 }
 
 gs_status gs_get_status(const void *ws, hipStream_t stream) {

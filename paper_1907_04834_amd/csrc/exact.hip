@@ -74,6 +74,15 @@ __global__ void k_unpack_state(const double *__restrict__ Sq, const double *__re
     p[i] = (float)Sp[i];
 }
 
+// Positions only (targets of the velocity field), zero-padded.
+__global__ void k_pack_pos(const float *__restrict__ x, int64_t m, int64_t npad,
+                           float4 *__restrict__ X) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npad) return;
+    X[i] = i < m ? make_float4(x[3 * i], x[3 * i + 1], x[3 * i + 2], 0.f)
+                 : make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
 __global__ void k_unpack(const float4 *__restrict__ Q, const float4 *__restrict__ P, int64_t n,
                          float *__restrict__ q, float *__restrict__ p) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -447,7 +456,8 @@ __global__ __launch_bounds__(256) void k_combine_euler(const double *__restrict_
                                                        double *__restrict__ Sp,
                                                        float4 *__restrict__ Q,
                                                        float4 *__restrict__ P,
-                                                       double *__restrict__ Hpart) {
+                                                       double *__restrict__ Hpart,
+                                                       double *__restrict__ vout) {
     __shared__ double lds[8];
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double e = 0.0;
@@ -463,6 +473,9 @@ __global__ __launch_bounds__(256) void k_combine_euler(const double *__restrict_
             p[c] = Sp[3 * i + c];
         }
         e = p[0] * acc[0] + p[1] * acc[1] + p[2] * acc[2];
+        if (vout)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) vout[3 * i + c] = acc[c];
         if (dt > 0.0) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
@@ -604,6 +617,7 @@ ExactPlan plan_exact(int64_t n_targets, int64_t n_sources, bool mfma) {
     if (s > max_s) s = max_s;
     if (s > 64) s = 64;
     if (s < 1) s = 1;
+    pl.chunk_quantum = kMTile;
     pl.chunk = round_up((pl.nsrc + s - 1) / s, kMTile);
     pl.splits = (int)((pl.nsrc + pl.chunk - 1) / pl.chunk);
     return pl;
@@ -623,6 +637,12 @@ gs_status launch_pack(const float *q, const float *p, int64_t n, int64_t npad, f
                       float4 *P, hipStream_t s) {
     hipLaunchKernelGGL(k_pack, dim3(nblocks(npad)), dim3(kBlock), 0, s, q, p, n, npad, Q, P);
     GS_LAUNCH_CHECK("pack");
+    return GS_OK;
+}
+
+gs_status launch_pack_pos(const float *x, int64_t m, int64_t npad, float4 *X, hipStream_t s) {
+    hipLaunchKernelGGL(k_pack_pos, dim3(nblocks(npad)), dim3(kBlock), 0, s, x, m, npad, X);
+    GS_LAUNCH_CHECK("pack_pos");
     return GS_OK;
 }
 
@@ -686,9 +706,15 @@ gs_status launch_combine_rhs(const ExactPlan &pl, const double *part, double sig
 gs_status launch_combine_euler(const ExactPlan &pl, const double *part, double sigma, double dt,
                                double *Sq, double *Sp, float4 *Q, float4 *P, double *Hpart,
                                hipStream_t s) {
+    return launch_combine_euler_v(pl, part, sigma, dt, Sq, Sp, Q, P, Hpart, nullptr, s);
+}
+
+gs_status launch_combine_euler_v(const ExactPlan &pl, const double *part, double sigma,
+                                 double dt, double *Sq, double *Sp, float4 *Q, float4 *P,
+                                 double *Hpart, double *vout, hipStream_t s) {
     hipLaunchKernelGGL(k_combine_euler, dim3(nblocks(pl.n)), dim3(kBlock), 0, s, part,
                        pl.splits, pl.ntgt, pl.n, 1.0 / (sigma * sigma), dt, Sq, Sp, Q, P,
-                       Hpart);
+                       Hpart, vout);
     GS_LAUNCH_CHECK("combine_euler");
     return GS_OK;
 }

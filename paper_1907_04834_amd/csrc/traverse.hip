@@ -27,35 +27,6 @@ namespace {
 
 typedef unsigned long long u64;
 
-__device__ inline bool decide(const BhNode &nd, double x, double y, double z,
-                              const BhParams &bp) {
-#pragma clang fp contract(off)
-    double dmin2 = 0.0;
-    {
-        const double below = (double)nd.lox - x, above = x - (double)nd.hix;
-        const double g = below > above ? below : above;
-        if (g > 0.0) dmin2 += g * g;
-    }
-    {
-        const double below = (double)nd.loy - y, above = y - (double)nd.hiy;
-        const double g = below > above ? below : above;
-        if (g > 0.0) dmin2 += g * g;
-    }
-    {
-        const double below = (double)nd.loz - z, above = z - (double)nd.hiz;
-        const double g = below > above ? below : above;
-        if (g > 0.0) dmin2 += g * g;
-    }
-    const bool far = dmin2 >= bp.cut2;
-    const double dx = x - nd.cx, dy = y - nd.cy, dz = z - nd.cz;
-    double d2 = dx * dx;
-    d2 += dy * dy;
-    d2 += dz * dz;
-    const bool mac = bp.theta_inf || (nd.s2 < bp.th2 * d2);
-    return nd.n >= 2 && far && mac;
-}
-
-enum Mode { MODE_RHS = 0, MODE_SHOOT = 1, MODE_ENERGY = 2 };
 
 // ---------------------------------------------------------------- layout
 // Work split.  A wave owns 64 consecutive targets of the Morton order (a
@@ -368,7 +339,7 @@ __global__ __launch_bounds__(256) void k_bh_combine(
     const unsigned *__restrict__ perm, int64_t n, int64_t npad, double inv_s2, int mode,
     float *__restrict__ dq, float *__restrict__ dp, double *__restrict__ Sq,
     double *__restrict__ Sp, float *__restrict__ q32, float *__restrict__ p32, double dt,
-    double *__restrict__ Hpart) {
+    double *__restrict__ Hpart, double *__restrict__ v64) {
     __shared__ double s_red[4];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -385,6 +356,9 @@ __global__ __launch_bounds__(256) void k_bh_combine(
             }
         }
         const int64_t i = perm[t];
+        if (v64)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) v64[3 * i + c] = V[c];
         if (mode == MODE_RHS) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
@@ -492,7 +466,7 @@ gs_status launch_bh_traverse(const TreeBufs &t, const BhParams &bp, bool with_a,
                            t.Qs, t.Ps, t.n, npad, bp.negc, list, t.list_n, t.part, counters);   \
         hipLaunchKernelGGL(k_bh_combine<A>, dim3((unsigned)traverse_blocks(t.n)), dim3(256), 0, \
                            s, t.part, t.list_n, t.valA, t.n, npad, bp.inv_s2, mode, o.dq, o.dp, \
-                           o.Sq, o.Sp, o.q32, o.p32, o.dt, o.Hpart);                            \
+                           o.Sq, o.Sp, o.q32, o.p32, o.dt, o.Hpart, o.v64);                     \
     } while (0)
     if (with_a)
         GS_PHASES(true);

@@ -101,6 +101,39 @@ struct BhParams {
 };
 BhParams make_bh_params(const gs_params &prm);
 
+// The decision for target x and node nd (FP64, in the order of the
+// definition): approximate when the node holds >= 2 points, the distance from
+// x to its tight box is at least kappa sigma, and s_k^2 < theta^2 |x - C_k|^2.
+__device__ __forceinline__ bool decide(const BhNode &nd, double x, double y, double z,
+                              const BhParams &bp) {
+#pragma clang fp contract(off)
+    double dmin2 = 0.0;
+    {
+        const double below = (double)nd.lox - x, above = x - (double)nd.hix;
+        const double g = below > above ? below : above;
+        if (g > 0.0) dmin2 += g * g;
+    }
+    {
+        const double below = (double)nd.loy - y, above = y - (double)nd.hiy;
+        const double g = below > above ? below : above;
+        if (g > 0.0) dmin2 += g * g;
+    }
+    {
+        const double below = (double)nd.loz - z, above = z - (double)nd.hiz;
+        const double g = below > above ? below : above;
+        if (g > 0.0) dmin2 += g * g;
+    }
+    const bool far = dmin2 >= bp.cut2;
+    const double dx = x - nd.cx, dy = y - nd.cy, dz = z - nd.cz;
+    double d2 = dx * dx;
+    d2 += dy * dy;
+    d2 += dz * dz;
+    const bool mac = bp.theta_inf || (nd.s2 < bp.th2 * d2);
+    return nd.n >= 2 && far && mac;
+}
+
+
+
 // Forward traversal.  Writes (v, a) for every point in original order: as FP32
 // into dq/dp when they are non-null, else it advances the FP64 state
 // (Sq += dt v, Sp += dt a), refreshes the FP32 copies q32/p32 and adds
@@ -116,6 +149,16 @@ struct TraverseOut {
 };
 gs_status launch_bh_traverse(const TreeBufs &t, const BhParams &bp, bool with_a,
                              const TraverseOut &o, unsigned long long *counters, hipStream_t s);
+enum Mode { MODE_RHS = 0, MODE_SHOOT = 1, MODE_ENERGY = 2 };
+gs_status launch_bh_traverse(const TreeBufs &t, const BhParams &bp, bool with_a,
+                             const TraverseOut &o, unsigned long long *counters, hipStream_t s,
+                             int mode, int *status);
+
+// Per-node FP64 sums of two per-point vector fields given in Morton order
+// (A, B as float4 [n]); out is [n_nodes][6] (sums of A then B).  Uses the
+// same 64 / 4096-point range summaries as the node statistics.
+gs_status tree_range_sums(const float4 *A, const float4 *B, TreeBufs &t, double *out,
+                          hipStream_t s);
 int traverse_blocks(int64_t n);
 
 struct ShootBhBufs {

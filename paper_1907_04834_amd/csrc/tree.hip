@@ -679,6 +679,45 @@ __global__ __launch_bounds__(256) void k_adj_sums(const double *__restrict__ al,
     }
 }
 
+// Node sums of two fields over node ranges (the sums part of k_node_stats).
+__global__ __launch_bounds__(256) void k_node_sums(const float4 *__restrict__ A,
+                                                   const float4 *__restrict__ B,
+                                                   const RangeStat *__restrict__ c0,
+                                                   const RangeStat *__restrict__ c1,
+                                                   const TreeMeta *__restrict__ meta,
+                                                   const int *__restrict__ node_start,
+                                                   const BhNode *__restrict__ nodes,
+                                                   double *__restrict__ out) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= meta->n_nodes) return;
+    int64_t a = node_start[id];
+    const int64_t b = a + nodes[id].n;
+    RangeStat r;
+    rs_init(r);
+    constexpr int64_t C0 = kChunk, C1 = (int64_t)kChunk * kChunk;
+    while (a < b && (a % C0 != 0 || a + C0 > b)) {
+        rs_point(r, A[a], B[a]);
+        ++a;
+    }
+    while (a < b && a % C1 != 0 && a + C0 <= b) {
+        rs_add(r, c0[a / C0]);
+        a += C0;
+    }
+    while (a + C1 <= b) {
+        rs_add(r, c1[a / C1]);
+        a += C1;
+    }
+    while (a + C0 <= b) {
+        rs_add(r, c0[a / C0]);
+        a += C0;
+    }
+    while (a < b) {
+        rs_point(r, A[a], B[a]);
+        ++a;
+    }
+    for (int c = 0; c < 6; ++c) out[6 * id + c] = r.s[c];
+}
+
 __global__ __launch_bounds__(256) void k_zero_u32(unsigned *__restrict__ x, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) x[i] = 0u;
@@ -798,6 +837,20 @@ gs_status tree_adjoint_sums(const double *alpha, const double *beta, TreeBufs &t
     hipLaunchKernelGGL(k_adj_sums, dim3(nblk(2 * n)), dim3(256), 0, s, alpha, beta, t.valA,
                        t.meta, t.nodes, t.adj, t.node_of, t.parent_rank, t.counter);
     GS_LAUNCH_CHECK("adjoint sums");
+    return GS_OK;
+}
+
+gs_status tree_range_sums(const float4 *A, const float4 *B, TreeBufs &t, double *out,
+                          hipStream_t s) {
+    const int64_t n = t.n;
+    const int64_t nc0 = (n + kChunk - 1) / kChunk, nc1 = (nc0 + kChunk - 1) / kChunk;
+    RangeStat *c0 = reinterpret_cast<RangeStat *>(t.chunk0);
+    RangeStat *c1 = reinterpret_cast<RangeStat *>(t.chunk1);
+    hipLaunchKernelGGL(k_chunks0, dim3(nblk(nc0, 4)), dim3(256), 0, s, A, B, n, c0, nc0);
+    hipLaunchKernelGGL(k_chunks1, dim3(nblk(nc1, 4)), dim3(256), 0, s, c0, nc0, c1, nc1);
+    hipLaunchKernelGGL(k_node_sums, dim3(nblk(2 * n)), dim3(256), 0, s, A, B, c0, c1, t.meta,
+                       t.node_start, t.nodes, out);
+    GS_LAUNCH_CHECK("range sums");
     return GS_OK;
 }
 

@@ -62,6 +62,7 @@ _SIGS = {
     "gs_shoot_f64": (ctypes.c_int, [_vp, _vp, _i64, _PP, _vp, _vp, _vp, _vp, _sz, _vp]),
     "gs_shoot_adjoint": (ctypes.c_int, [_vp, _vp, _vp, _i64, _PP, _i32, _dbl, _i32, _vp,
                                         _vp, _vp, _sz, _vp]),
+    "gs_adjoint_workspace_bytes": (_sz, [_i64, _PP, _i32, _i32]),
     "gs_field": (ctypes.c_int, [_vp, _i64, _vp, _vp, _i64, _PP, _vp, _vp, _sz, _vp]),
     "gs_get_status": (ctypes.c_int, [_vp, _vp]),
     "gs_bh_counters": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(ctypes.c_int64)]),
@@ -199,10 +200,9 @@ def gs_shoot_adjoint(q0, p0, target, prm: Params, method=GS_EXACT, lam=0.01, ckp
     obj = torch.zeros(1, dtype=torch.float64, device=q0.device)
     grad = torch.empty_like(p0)
     if ws is None:
-        pr = Params.from_buffer_copy(prm)
-        nbytes = lib().gs_workspace_bytes(n, ctypes.byref(pr), method, GS_OP_ADJOINT)
+        nbytes = lib().gs_adjoint_workspace_bytes(n, ctypes.byref(prm), method, int(ckpt_every))
         if nbytes == 0:
-            raise GsError(-1, "invalid arguments for gs_workspace_bytes")
+            raise GsError(-1, "invalid arguments for gs_adjoint_workspace_bytes")
         ws = torch.empty(nbytes, dtype=torch.uint8, device=q0.device)
     _check(lib().gs_shoot_adjoint(_ptr(q0), _ptr(p0), _ptr(target), n, ctypes.byref(prm),
                                   method, float(lam), int(ckpt_every), _ptr(obj), _ptr(grad),
@@ -266,3 +266,30 @@ def shoot(q0, p0, sigma, nt=40, method="exact", theta=0.5, leaf_cap=1, cutoff_si
 
 
 INF = math.inf
+
+
+class ShootLoss(torch.autograd.Function):
+    """E(p0) = |q(1) - target|^2 / n + lam <p0, K(q0) p0> as a differentiable
+    function of p0 (float32 (n, 3)); the backward pass returns the
+    gradient computed by gs_shoot_adjoint's discrete adjoint."""
+
+    @staticmethod
+    def forward(ctx, p0, q0, target, sigma, nt=40, lam=0.01, method="exact", theta=0.5,
+                leaf_cap=1, ckpt_every=8):
+        prm = params(sigma, nt=nt, theta=theta, leaf_cap=leaf_cap)
+        m = GS_EXACT if method == "exact" else GS_BH
+        e, g = gs_shoot_adjoint(q0.contiguous(), p0.detach().contiguous(), target.contiguous(),
+                                prm, m, lam, ckpt_every)
+        ctx.save_for_backward(g)
+        return e.clone()
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (g,) = ctx.saved_tensors
+        return (grad_out.to(g.dtype) * g, None, None, None, None, None, None, None, None, None)
+
+
+def shoot_loss(p0, q0, target, sigma, **kw):
+    return ShootLoss.apply(p0, q0, target, sigma, *[kw.get(k, d) for k, d in (
+        ("nt", 40), ("lam", 0.01), ("method", "exact"), ("theta", 0.5), ("leaf_cap", 1),
+        ("ckpt_every", 8))])

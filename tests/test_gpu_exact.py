@@ -143,3 +143,17 @@ def test_shoot_zero_and_single_point():
     np.testing.assert_allclose(_np(q1), _np(q0 + p0), atol=1e-6)
     np.testing.assert_array_equal(_np(p1), _np(p0))
     np.testing.assert_allclose(H.cpu().numpy(), np.full(8, (_np(p0) ** 2).sum()), rtol=1e-7)
+
+
+@pytest.mark.parametrize("m,n", [(1, 1), (333, 5000), (5000, 333), (20000, 20000)])
+def test_field_matches_oracle(oracle, m, n):
+    """Velocity field of eq. (3) at points that are not the sources."""
+    w = W.ellipsoid_20k(n=n)
+    x = (W.ellipsoid_surface(np.random.default_rng(8), m, (1.0, 0.6, 0.4), 0.05)
+         ).astype(np.float32)
+    v = gs.gs_field(_t(x), _t(w.q0), _t(w.p0), gs.params(w.sigma))
+    torch.cuda.synchronize()
+    ov = oracle.field_exact(x.astype(np.float64), w.q0.astype(np.float64),
+                            w.p0.astype(np.float64), w.sigma)
+    floor = 1e-7 * float(np.abs(w.p0).max()) * np.sqrt(ov.size)
+    assert np.linalg.norm(_np(v) - ov) <= 1e-5 * np.linalg.norm(ov) + floor
