@@ -212,7 +212,7 @@ def main():
                     for name, v in kt.items()},
         "roofline": {"bound": "alu", "achieved": achieved_tf, "peak": FP32_VALU_PEAK_TF,
                      "unit": "TFLOP/s", "frac": achieved_tf / FP32_VALU_PEAK_TF,
-                     "traffic": None, "kernel": "k_exact_pairs<1,true>",
+                     "traffic": None, "kernel": "k_exact_items<true>",
                      "per_launch": f"{n}^2 pairs x {FLOP_PER_PAIR} FLOP",
                      "avg_launch_ms": exact_ms_launch},
         "err_vs_fp64": err,

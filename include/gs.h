@@ -170,12 +170,42 @@ gs_status gs_field(const float *x, int64_t m, const float *q, const float *p, in
                    const gs_params *prm, float *v, void *ws, size_t ws_bytes,
                    hipStream_t stream);
 
+/* Batched sets.  Sec. 3.2 registers every subject of a population (665
+ * subjects x 2 hemispheres) with its own, independent shooting; the
+ * implementation details of Sec. 2.2 run such jobs side by side on a
+ * cluster.  Here nsub point sets are stored one after the other: set s is
+ * rows [offsets[s], offsets[s+1]) of q / p / q0 / p0 and of the outputs.
+ * `offsets` is a HOST array of nsub + 1 int64 values with offsets[0] = 0,
+ * non-decreasing (empty sets allowed); 1 <= nsub <= 65536.  Every set is
+ * evaluated exactly as the corresponding single-set call would evaluate it
+ * alone (its own octree with its own root cube on the Barnes-Hut path; no
+ * interaction between sets), in shared launches.  The library copies small
+ * tables derived from `offsets` into the workspace with an asynchronous copy
+ * from its own pinned staging memory; `offsets` may be freed on return.
+ * The workspace comes from gs_batch_workspace_bytes (op GS_OP_RHS or
+ * GS_OP_SHOOT; 0 for invalid arguments). */
+size_t gs_batch_workspace_bytes(const int64_t *offsets, int32_t nsub, const gs_params *prm,
+                                int32_t method, int32_t op);
+
+/* Right-hand side of every set (gs_rhs_exact / gs_rhs_bh per set). */
+gs_status gs_rhs_batch(const float *q, const float *p, const int64_t *offsets, int32_t nsub,
+                       const gs_params *prm, int32_t method, float *dq, float *dp, void *ws,
+                       size_t ws_bytes, hipStream_t stream);
+
+/* Shooting of every set (gs_shoot per set).  H (nullable) is a DEVICE
+ * double[nsub][nt + 1]: row s holds the energies of set s. */
+gs_status gs_shoot_batch(const float *q0, const float *p0, const int64_t *offsets,
+                         int32_t nsub, const gs_params *prm, int32_t method, float *q1,
+                         float *p1, double *H, void *ws, size_t ws_bytes,
+                         hipStream_t stream);
+
 /* Waits for `stream` and returns the device-side status word of the last
  * Barnes-Hut call that used this workspace (GS_OK or GS_ERR_NONFINITE). */
 gs_status gs_get_status(const void *ws, hipStream_t stream);
 
 /* Waits for `stream` and copies the counters of the last Barnes-Hut call
- * (gs_rhs_bh or gs_shoot with GS_BH) that used this workspace, summed over
+ * (gs_rhs_bh, gs_shoot or a batched call with GS_BH) that used this
+ * workspace, summed over all sets,
  * all targets and all right-hand sides that call evaluated (nt + 1 for a
  * shooting that returns H, nt otherwise): out[0] exact pairs, out[1]
  * monopoles (approximated nodes), out[2] node visits, out[3] octree nodes.

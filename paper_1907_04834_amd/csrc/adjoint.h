@@ -15,7 +15,8 @@ BhAdjBufs layout_bh_adjoint(Arena &a, int64_t n);
 
 struct AdjointBufs {
     int64_t n;
-    int nt, ckpt, nck, nblk;
+    int nt, ckpt, nck, nblk;  // nblk: data-term partials (blocks of 256 points)
+    int nh;                   // energy partials (blocks, or tree groups on the tree path)
     bool bh;
     ExactPlan pl;
     ExactBufs ex;             // packed state and partial sums of the exact kernels

@@ -13,7 +13,8 @@
 // k_adj_pairs has the layout of the forward all-pairs kernel: one target per
 // lane, wave-uniform (scalar-load) sources q, p, alpha, beta, FP32 pair
 // arithmetic, tiles of kTile sources summed in FP32 and accumulated in FP64,
-// source splits over grid.y, FP64 partial sums combined in a fixed order.
+// source splits (split-fastest block order), FP64 partial sums combined in a
+// fixed order.
 #include <hip/hip_runtime.h>
 
 #include "adjoint.h"
@@ -81,16 +82,14 @@ __global__ __launch_bounds__(256) void k_terminal(const double *__restrict__ q,
 }
 
 // objective = (sum of data partials) / n + lambda * (sum of energy partials)
-__global__ __launch_bounds__(256) void k_objective(const double *__restrict__ dpart,
-                                                   const double *__restrict__ hpart, int nb,
+__global__ __launch_bounds__(256) void k_objective(const double *__restrict__ dpart, int nb,
+                                                   const double *__restrict__ hpart, int nh,
                                                    int64_t n, double lambda,
                                                    double *__restrict__ obj) {
     __shared__ double lds[8];
     double d = 0.0, h = 0.0;
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
-        d += dpart[b];
-        h += hpart[b];
-    }
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) d += dpart[b];
+    for (int b = threadIdx.x; b < nh; b += blockDim.x) h += hpart[b];
     d = block_sum(d, lds);
     __syncthreads();
     h = block_sum(h, lds);
@@ -100,10 +99,13 @@ __global__ __launch_bounds__(256) void k_objective(const double *__restrict__ dp
 template <int T>
 __global__ __launch_bounds__(256) void k_adj_pairs(
     const float4 *__restrict__ Q, const float4 *__restrict__ P, const float4 *__restrict__ AL,
-    const float4 *__restrict__ BE, int64_t ntgt, int64_t chunk, int64_t nsrc, float negc,
-    float inv_s2, double *__restrict__ part) {
+    const float4 *__restrict__ BE, int64_t ntgt, int64_t chunk, int64_t nsrc, int splits,
+    float negc, float inv_s2, double *__restrict__ part) {
     const int lane = threadIdx.x & 63;
-    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    // block b: target block b / splits, source split b % splits (as the
+    // forward pair kernel)
+    const int64_t split = blockIdx.x % splits, tb = blockIdx.x / splits;
+    const int64_t wave = tb * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const int64_t t0 = wave * (64 * T) + lane;
     float x[T], y[T], z[T], px[T], py[T], pz[T], ax[T], ay[T], az[T], bx[T], by[T], bz[T];
 #pragma unroll
@@ -120,7 +122,7 @@ __global__ __launch_bounds__(256) void k_adj_pairs(
     for (int k = 0; k < T; ++k)
 #pragma unroll
         for (int c = 0; c < 3; ++c) sq[k][c] = spp[k][c] = 0.0;
-    const int64_t j0 = (int64_t)blockIdx.y * chunk;
+    const int64_t j0 = split * chunk;
     const int64_t j1 = j0 + chunk < nsrc ? j0 + chunk : nsrc;
     for (int64_t jt = j0; jt < j1; jt += kTile) {
         float tq[T][3], tp[T][3];
@@ -159,7 +161,7 @@ __global__ __launch_bounds__(256) void k_adj_pairs(
                 spp[k][c] += (double)tp[k][c];
             }
     }
-    double *dst = part + (int64_t)blockIdx.y * 6 * ntgt;
+    double *dst = part + split * 6 * ntgt;
 #pragma unroll
     for (int k = 0; k < T; ++k) {
         const int64_t i = t0 + 64 * k;
@@ -220,13 +222,15 @@ AdjointBufs layout_adjoint(Arena &a, int64_t n, int nt, int ckpt, int method) {
     b.segq = a.take<double>((size_t)ckpt * 3 * n);
     b.segp = a.take<double>((size_t)ckpt * 3 * n);
     b.nblk = combine_blocks(n);
-    b.hpart = a.take<double>(b.nblk);
-    b.dpart = a.take<double>(b.nblk);
+    b.nh = b.nblk;
     if (method == GS_BH) {
         b.bh = true;
         b.sh = layout_shoot_bh(a, n, 1);
         b.bhadj = layout_bh_adjoint(a, n);
+        b.nh = (int)b.sh.tree.groups;
     }
+    b.hpart = a.take<double>(b.nh > b.nblk ? b.nh : b.nblk);
+    b.dpart = a.take<double>(b.nblk);
     return b;
 }
 
@@ -273,11 +277,11 @@ static gs_status adjoint_step(AdjointBufs &b, const gs_params &prm, double dt, c
     GS_TRY(launch_pack2(b.al, b.be, b.n, npad, b.AL, b.BE, s));
     const double c = kLog2e / (2.0 * prm.sigma * prm.sigma);
     const ExactPlan &pl = b.pl;
-    dim3 grid((unsigned)(pl.ntgt / (64 * 4)), (unsigned)pl.splits);
+    dim3 grid((unsigned)(pl.ntgt / (64 * 4) * pl.splits));
     timing_begin(KIND_ADJOINT, s);
     hipLaunchKernelGGL(k_adj_pairs<1>, grid, dim3(256), 0, s, b.ex.Q, b.ex.P, b.AL, b.BE, pl.ntgt,
-                       pl.chunk, pl.nsrc, (float)(-c), (float)(1.0 / (prm.sigma * prm.sigma)),
-                       b.ex.part);
+                       pl.chunk, pl.nsrc, pl.splits, (float)(-c),
+                       (float)(1.0 / (prm.sigma * prm.sigma)), b.ex.part);
     timing_end(KIND_ADJOINT, s);
     GS_LAUNCH_CHECK("adj_pairs");
     hipLaunchKernelGGL(k_adj_update, dim3(nblk(b.n)), dim3(kBlock), 0, s, b.ex.part, pl.splits,
@@ -306,7 +310,7 @@ gs_status shoot_adjoint(const float *q0, const float *p0, const float *y, const 
     // objective and terminal adjoint
     hipLaunchKernelGGL(k_terminal, dim3(nblk(n)), dim3(kBlock), 0, s, b.Sq, y, n, b.al, b.be,
                        b.dpart);
-    hipLaunchKernelGGL(k_objective, dim3(1), dim3(kBlock), 0, s, b.dpart, b.hpart, b.nblk, n,
+    hipLaunchKernelGGL(k_objective, dim3(1), dim3(kBlock), 0, s, b.dpart, b.nblk, b.hpart, b.nh, n,
                        lambda, objective);
     GS_LAUNCH_CHECK("objective");
     // backward sweep, one checkpoint segment at a time

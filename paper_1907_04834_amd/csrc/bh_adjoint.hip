@@ -280,13 +280,13 @@ gs_status bh_adjoint_step(AdjointBufs &b, const gs_params &prm, double dt, const
                        b.sh.p32);
     GS_LAUNCH_CHECK("to_f32");
     GS_TRY(build_tree(b.sh.q32, b.sh.p32, n, prm.leaf_cap, t, status, s));
-    hipLaunchKernelGGL(k_gather_ab, dim3(nblk(n)), dim3(kBlock), 0, s, b.al, b.be, t.valA, n,
+    hipLaunchKernelGGL(k_gather_ab, dim3(nblk(n)), dim3(kBlock), 0, s, b.al, b.be, t.perm, n,
                        b.bhadj.ALs, b.bhadj.BEs);
     GS_LAUNCH_CHECK("gather_ab");
     GS_TRY(tree_range_sums(b.bhadj.ALs, b.bhadj.BEs, t, t.adj, s));
     timing_begin(KIND_ADJOINT, s);
     hipLaunchKernelGGL(k_bh_adj_traverse, dim3(nblk(n, 256)), dim3(256), 0, s, t.nodes, t.adj,
-                       t.Qs, t.Ps, b.bhadj.ALs, b.bhadj.BEs, t.valA, n, make_bh_params(prm), dt,
+                       t.Qs, t.Ps, b.bhadj.ALs, b.bhadj.BEs, t.perm, n, make_bh_params(prm), dt,
                        b.al, b.be, counters, status);
     timing_end(KIND_ADJOINT, s);
     GS_LAUNCH_CHECK("bh_adj_traverse");

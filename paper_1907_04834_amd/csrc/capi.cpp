@@ -2,6 +2,7 @@
 // workspace planning and the launch sequences of each operation.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -191,9 +192,21 @@ float4 *layout_field(Arena &a, int64_t big, ExactBufs &b) {
     return a.take<float4>(pl.ntgt > pl.nsrc ? pl.ntgt : pl.nsrc);
 }
 
+size_t measure_batch(const int64_t *off, int nsub, const gs_params &prm, int method, int op);
+
+// The single-set exact FP32 right-hand side and shooting run as a batch of
+// one set (the work-item kernel); the opt-in matrix-core variant keeps the
+// source-split kernel.
+bool exact_items_path(const gs_params *prm) { return (prm->flags & GS_FLAG_MFMA_PAIRS) == 0; }
+
 size_t measure_bytes(int64_t n, const gs_params *prm, int32_t method, int32_t op) {
-    Arena a{nullptr, kHeader, 0};
     const bool f64 = (prm->flags & GS_FLAG_F64) != 0;
+    if (method == GS_EXACT && !f64 && (op == GS_OP_RHS || op == GS_OP_SHOOT) &&
+        exact_items_path(prm)) {
+        const int64_t off[2] = {0, n};
+        return measure_batch(off, 1, *prm, GS_EXACT, op);
+    }
+    Arena a{nullptr, kHeader, 0};
     switch (op) {
         case GS_OP_RHS:
             if (f64) break;
@@ -228,6 +241,208 @@ size_t measure_bytes(int64_t n, const gs_params *prm, int32_t method, int32_t op
             return 0;
     }
     return a.off + 256;
+}
+
+// ---------------------------------------------------------------- batched sets
+gs_status check_offsets(const int64_t *off, int32_t nsub) {
+    if (!off) {
+        set_error("offsets is NULL");
+        return GS_ERR_INVALID;
+    }
+    if (nsub < 1 || nsub > 65536) {
+        set_error("nsub must be in [1, 65536] (got %d)", nsub);
+        return GS_ERR_INVALID;
+    }
+    if (off[0] != 0) {
+        set_error("offsets[0] must be 0 (got %lld)", (long long)off[0]);
+        return GS_ERR_INVALID;
+    }
+    int64_t rows = 0;
+    for (int s = 0; s < nsub; ++s) {
+        if (off[s + 1] < off[s]) {
+            set_error("offsets must be non-decreasing (offsets[%d] > offsets[%d])", s, s + 1);
+            return GS_ERR_INVALID;
+        }
+        rows += round_up(off[s + 1] - off[s], 256);
+    }
+    GS_TRY(check_n(off[nsub]));
+    if (rows > (int64_t(1) << 31) - 4096) {
+        set_error("too many points once every set is padded to 256 (%lld)", (long long)rows);
+        return GS_ERR_INVALID;
+    }
+    return GS_OK;
+}
+
+// Host image of the small device tables of a batched call (uploaded once per
+// call); entries start at 256-byte boundaries.
+struct TableImage {
+    std::vector<char> bytes;
+    template <class T>
+    size_t add(const T *src, size_t count) {
+        const size_t off = (bytes.size() + 255) & ~size_t(255);
+        bytes.resize(off + count * sizeof(T));
+        if (count) memcpy(bytes.data() + off, src, count * sizeof(T));
+        return off;
+    }
+};
+
+struct Batch {
+    ExactBatchPlan xp;
+    ExactBatchBufs ex{};
+    ShootBhBufs bh{};
+    TableImage img;
+    char *tables = nullptr;
+};
+
+// Lays out (or measures, when the arena has no base) the buffers of a
+// batched call and prepares its tables.
+void layout_batch(Arena &a, const int64_t *off, int nsub, const gs_params &prm, int method,
+                  int op, Batch &b) {
+    const int nt = op == GS_OP_SHOOT ? prm.nt : 0;
+    if (method == GS_EXACT) {
+        b.xp = plan_exact_batch(off, nsub);
+        carve_exact_batch(a, b.xp, nt, b.ex);
+        const size_t o_items = b.img.add(b.xp.items.data(), b.xp.items.size());
+        const size_t o_blk = b.img.add(b.xp.blocks.data(), b.xp.blocks.size());
+        const size_t o_bseg = b.img.add(b.xp.bseg.data(), b.xp.bseg.size());
+        b.tables = a.take<char>(b.img.bytes.size());
+        if (b.tables) {
+            b.ex.items = reinterpret_cast<const int4 *>(b.tables + o_items);
+            b.ex.blk = reinterpret_cast<const int4 *>(b.tables + o_blk);
+            b.ex.bseg = reinterpret_cast<const int *>(b.tables + o_bseg);
+        }
+        return;
+    }
+    // forest: one tree per set; traversal groups never straddle two sets
+    std::vector<long long> seg(nsub + 1);
+    std::vector<GroupDesc> gt;
+    std::vector<int> gseg(nsub + 1);
+    int64_t max_set = 0;
+    for (int s = 0; s < nsub; ++s) {
+        seg[s] = off[s];
+        gseg[s] = (int)gt.size();
+        const int64_t n = off[s + 1] - off[s];
+        if (n > max_set) max_set = n;
+        for (int64_t g = 0; g * 64 < n; ++g) {
+            GroupDesc d;
+            d.first = (int)(off[s] + 64 * g);
+            d.count = (int)(n - 64 * g < 64 ? n - 64 * g : 64);
+            d.root = s;
+            d.sub = s;
+            gt.push_back(d);
+        }
+    }
+    seg[nsub] = off[nsub];
+    gseg[nsub] = (int)gt.size();
+    const int64_t ntot = off[nsub];
+    if (op == GS_OP_SHOOT)
+        b.bh = layout_shoot_forest(a, ntot, nsub, (int64_t)gt.size(), max_set, nt);
+    else
+        carve_forest(a, ntot, nsub, (int64_t)gt.size(), max_set, b.bh.tree);
+    const size_t o_seg = b.img.add(seg.data(), seg.size());
+    const size_t o_gt = b.img.add(gt.data(), gt.size());
+    const size_t o_gseg = b.img.add(gseg.data(), gseg.size());
+    b.tables = a.take<char>(b.img.bytes.size());
+    if (b.tables) {
+        b.bh.tree.seg = reinterpret_cast<const long long *>(b.tables + o_seg);
+        b.bh.tree.gtab = reinterpret_cast<const GroupDesc *>(b.tables + o_gt);
+        b.bh.gseg = reinterpret_cast<const int *>(b.tables + o_gseg);
+    }
+}
+
+size_t measure_batch(const int64_t *off, int nsub, const gs_params &prm, int method, int op) {
+    Arena a{nullptr, kHeader, 0};
+    Batch b;
+    layout_batch(a, off, nsub, prm, method, op, b);
+    return a.off + 256;
+}
+
+// Pinned staging buffers for the table uploads: a ring of four per thread, so
+// that a call waits (rarely) only for the upload of the call four before it.
+// They live until the process ends.
+struct StageSlot {
+    void *buf;
+    size_t cap;
+    hipEvent_t ev;
+    bool pending;
+};
+struct Stage {
+    StageSlot slot[4];
+    int next;
+};
+thread_local Stage g_stage = {};
+
+gs_status upload_tables(const TableImage &img, char *dev, hipStream_t s) {
+    const size_t bytes = img.bytes.size();
+    if (bytes == 0) return GS_OK;
+    Stage &st = g_stage;
+    StageSlot &sl = st.slot[st.next];
+    st.next = (st.next + 1) & 3;
+    if (sl.pending) {
+        GS_HIP(hipEventSynchronize(sl.ev));
+        sl.pending = false;
+    }
+    if (sl.cap < bytes) {
+        if (sl.buf) GS_HIP(hipHostFree(sl.buf));
+        sl.buf = nullptr;
+        sl.cap = 0;
+        GS_HIP(hipHostMalloc(&sl.buf, bytes, hipHostMallocDefault));
+        sl.cap = bytes;
+    }
+    if (!sl.ev) GS_HIP(hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming));
+    memcpy(sl.buf, img.bytes.data(), bytes);
+    GS_HIP(hipMemcpyAsync(dev, sl.buf, bytes, hipMemcpyHostToDevice, s));
+    GS_HIP(hipEventRecord(sl.ev, s));
+    sl.pending = true;
+    return GS_OK;
+}
+
+gs_status check_batch_call(const int64_t *offsets, int32_t nsub, const gs_params *prm,
+                           int32_t method, bool need_nt) {
+    GS_TRY(check_offsets(offsets, nsub));
+    if (method != GS_EXACT && method != GS_BH) {
+        set_error("unknown method %d", method);
+        return GS_ERR_INVALID;
+    }
+    return check_params(prm, need_nt, method == GS_BH);
+}
+
+gs_status exact_batch_rhs(const float *q, const float *p, const int64_t *off, int nsub,
+                          const gs_params &prm, float *dq, float *dp, void *ws, size_t ws_bytes,
+                          hipStream_t stream) {
+    Arena a{static_cast<char *>(ws), kHeader, ws_bytes};
+    Batch b;
+    layout_batch(a, off, nsub, prm, GS_EXACT, GS_OP_RHS, b);
+    GS_TRY(upload_tables(b.img, b.tables, stream));
+    GS_TRY(launch_pack_state_rows(b.xp, b.ex, q, p, stream));
+    GS_TRY(launch_exact_items(b.xp, b.ex, prm.sigma, true, stream));
+    return launch_combine_rows(b.xp, b.ex, prm.sigma, 0, dq, dp, 0.0, nullptr, stream);
+}
+
+gs_status exact_batch_shoot(const float *q0, const float *p0, const int64_t *off, int nsub,
+                            const gs_params &prm, float *q1, float *p1, double *H, void *ws,
+                            size_t ws_bytes, hipStream_t stream) {
+    Arena a{static_cast<char *>(ws), kHeader, ws_bytes};
+    Batch b;
+    layout_batch(a, off, nsub, prm, GS_EXACT, GS_OP_SHOOT, b);
+    GS_TRY(upload_tables(b.img, b.tables, stream));
+    const double dt = 1.0 / prm.nt;
+    const size_t nb = b.xp.blocks.size();
+    GS_TRY(launch_pack_state_rows(b.xp, b.ex, q0, p0, stream));
+    for (int t = 0; t < prm.nt; ++t) {
+        GS_TRY(launch_exact_items(b.xp, b.ex, prm.sigma, true, stream));
+        GS_TRY(launch_combine_rows(b.xp, b.ex, prm.sigma, 1, nullptr, nullptr, dt,
+                                   H ? b.ex.Hpart + (size_t)t * nb : nullptr, stream));
+    }
+    if (H) {
+        // energy of the final state: one velocity-only pass
+        GS_TRY(launch_exact_items(b.xp, b.ex, prm.sigma, false, stream));
+        GS_TRY(launch_combine_rows(b.xp, b.ex, prm.sigma, 1, nullptr, nullptr, 0.0,
+                                   b.ex.Hpart + (size_t)prm.nt * nb, stream));
+        GS_TRY(launch_reduce_h_seg(b.ex.Hpart, (int64_t)nb, b.ex.bseg, nsub, prm.nt + 1, H,
+                                   stream));
+    }
+    return launch_unpack_state(b.ex.Sq, b.ex.Sp, off[nsub], q1, p1, stream);
 }
 
 }  // namespace
@@ -265,8 +480,12 @@ gs_status gs_rhs_exact(const float *q, const float *p, int64_t n, const gs_param
     gs_params pr = *prm;
     pr.flags &= ~GS_FLAG_F64;
     GS_TRY(check_ws(ws, ws_bytes, measure_bytes(n, &pr, GS_EXACT, GS_OP_RHS)));
+    if (exact_items_path(prm)) {
+        const int64_t off[2] = {0, n};
+        return exact_batch_rhs(q, p, off, 1, *prm, dq, dp, ws, ws_bytes, stream);
+    }
     Arena a{static_cast<char *>(ws), kHeader, ws_bytes};
-    ExactPlan pl = plan_exact(n, n, (prm->flags & GS_FLAG_MFMA_PAIRS) != 0);
+    ExactPlan pl = plan_exact(n, n, true);
     ExactBufs b;
     carve_exact(a, pl, b);
     const int64_t npad = pl.nsrc > pl.ntgt ? pl.nsrc : pl.ntgt;
@@ -307,8 +526,12 @@ gs_status gs_shoot(const float *q0, const float *p0, int64_t n, const gs_params 
         ShootBhBufs b = layout_shoot_bh(a, n, prm->nt);
         return shoot_bh(q0, p0, n, *prm, q1, p1, H, b, static_cast<char *>(ws), stream);
     }
+    if (exact_items_path(prm)) {
+        const int64_t off[2] = {0, n};
+        return exact_batch_shoot(q0, p0, off, 1, *prm, q1, p1, H, ws, ws_bytes, stream);
+    }
     ShootExactBufs b = layout_shoot_exact(a, n, prm->nt);
-    ExactPlan pl = plan_exact(n, n, (prm->flags & GS_FLAG_MFMA_PAIRS) != 0);
+    ExactPlan pl = plan_exact(n, n, true);
     const int nblk = combine_blocks(n);
     const int64_t npad = pl.nsrc > pl.ntgt ? pl.nsrc : pl.ntgt;
     GS_TRY(launch_pack_state(q0, p0, n, npad, b.Sq, b.Sp, b.ex.Q, b.ex.P, stream));
@@ -449,6 +672,47 @@ gs_status gs_field(const float *x, int64_t m, const float *q, const float *p, in
     GS_TRY(launch_pack_pos(x, m, pl.ntgt, X, stream));
     GS_TRY(launch_exact_pairs(pl, X, nullptr, b.Q, b.P, prm->sigma, false, b.part, stream));
     return launch_combine_rhs(pl, b.part, prm->sigma, v, nullptr, stream);
+}
+
+size_t gs_batch_workspace_bytes(const int64_t *offsets, int32_t nsub, const gs_params *prm,
+                                int32_t method, int32_t op) {
+    if (op != GS_OP_RHS && op != GS_OP_SHOOT) return 0;
+    if (check_batch_call(offsets, nsub, prm, method, op == GS_OP_SHOOT) != GS_OK) return 0;
+    return measure_batch(offsets, nsub, *prm, method, op);
+}
+
+gs_status gs_rhs_batch(const float *q, const float *p, const int64_t *offsets, int32_t nsub,
+                       const gs_params *prm, int32_t method, float *dq, float *dp, void *ws,
+                       size_t ws_bytes, hipStream_t stream) {
+    GS_TRY(check_batch_call(offsets, nsub, prm, method, false));
+    const int64_t n = offsets[nsub];
+    if (n == 0) return GS_OK;
+    GS_TRY(check_ptrs({q, p, dq, dp}));
+    GS_TRY(check_ws(ws, ws_bytes, measure_batch(offsets, nsub, *prm, method, GS_OP_RHS)));
+    if (method == GS_EXACT)
+        return exact_batch_rhs(q, p, offsets, nsub, *prm, dq, dp, ws, ws_bytes, stream);
+    Arena a{static_cast<char *>(ws), kHeader, ws_bytes};
+    Batch b;
+    layout_batch(a, offsets, nsub, *prm, method, GS_OP_RHS, b);
+    GS_TRY(upload_tables(b.img, b.tables, stream));
+    return rhs_bh(q, p, n, *prm, dq, dp, b.bh.tree, static_cast<char *>(ws), stream);
+}
+
+gs_status gs_shoot_batch(const float *q0, const float *p0, const int64_t *offsets, int32_t nsub,
+                         const gs_params *prm, int32_t method, float *q1, float *p1, double *H,
+                         void *ws, size_t ws_bytes, hipStream_t stream) {
+    GS_TRY(check_batch_call(offsets, nsub, prm, method, true));
+    const int64_t n = offsets[nsub];
+    if (n == 0) return GS_OK;
+    GS_TRY(check_ptrs({q0, p0, q1, p1}));
+    GS_TRY(check_ws(ws, ws_bytes, measure_batch(offsets, nsub, *prm, method, GS_OP_SHOOT)));
+    if (method == GS_EXACT)
+        return exact_batch_shoot(q0, p0, offsets, nsub, *prm, q1, p1, H, ws, ws_bytes, stream);
+    Arena a{static_cast<char *>(ws), kHeader, ws_bytes};
+    Batch b;
+    layout_batch(a, offsets, nsub, *prm, method, GS_OP_SHOOT, b);
+    GS_TRY(upload_tables(b.img, b.tables, stream));
+    return shoot_bh(q0, p0, n, *prm, q1, p1, H, b.bh, static_cast<char *>(ws), stream);
 }
 
 gs_status gs_get_status(const void *ws, hipStream_t stream) {

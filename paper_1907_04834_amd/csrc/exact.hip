@@ -16,7 +16,9 @@
 //     target's sum grows with the tile length, not with N;
 //   * each (split, target) writes its six FP64 partial sums; a second kernel
 //     adds the S partials in a fixed order (bitwise deterministic).
+#include <algorithm>
 #include <cstdlib>
+#include <vector>
 
 #include "internal.h"
 
@@ -96,18 +98,17 @@ __global__ void k_unpack(const float4 *__restrict__ Q, const float4 *__restrict_
     p[3 * i + 2] = b.z;
 }
 
+// Sums of targets t0 + 64 k (k < T, one lane each) over sources [j0, j1)
+// (a multiple of kTile), written as six FP64 rows of dst (row stride ntgt).
 template <int T, bool WITH_A>
-__global__ __launch_bounds__(256) void k_exact_pairs(
-    const float4 *__restrict__ Qt, const float4 *__restrict__ Pt, int64_t ntgt,
-    const float4 *__restrict__ Qs, const float4 *__restrict__ Ps, int64_t chunk, int64_t nsrc,
-    float negc, double *__restrict__ part) {
+__device__ __forceinline__ void pair_sums(const float4 *__restrict__ Qt,
+                                          const float4 *__restrict__ Pt, int64_t ntgt,
+                                          const float4 *__restrict__ Qs,
+                                          const float4 *__restrict__ Ps, int64_t t0, int64_t j0,
+                                          int64_t j1, float negc, double *__restrict__ dst) {
     // B sources are processed stage by stage (differences, r^2, exp2, sums)
     // so that every wave has B independent dependency chains in flight.
     constexpr int B = T == 1 ? 4 : 2;
-    const int lane = threadIdx.x & 63;
-    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    const int64_t t0 = wave * (64 * T) + lane;
-
     float x[T], y[T], z[T], px[T], py[T], pz[T];
 #pragma unroll
     for (int k = 0; k < T; ++k) {
@@ -128,8 +129,6 @@ __global__ __launch_bounds__(256) void k_exact_pairs(
 #pragma unroll
         for (int c = 0; c < 3; ++c) sv[k][c] = sa[k][c] = 0.0;
 
-    const int64_t j0 = (int64_t)blockIdx.y * chunk;
-    const int64_t j1 = j0 + chunk < nsrc ? j0 + chunk : nsrc;
     for (int64_t jt = j0; jt < j1; jt += kTile) {
         float tv[T][3], ta[T][3];
 #pragma unroll
@@ -180,7 +179,6 @@ __global__ __launch_bounds__(256) void k_exact_pairs(
                 if (WITH_A) sa[k][c] += (double)ta[k][c];
             }
     }
-    double *dst = part + (int64_t)blockIdx.y * 6 * ntgt;
 #pragma unroll
     for (int k = 0; k < T; ++k) {
         const int64_t i = t0 + 64 * k;
@@ -190,6 +188,37 @@ __global__ __launch_bounds__(256) void k_exact_pairs(
             if (WITH_A) dst[(3 + c) * ntgt + i] = sa[k][c];
         }
     }
+}
+
+// Block b of a launch takes target block b / splits against source split
+// b % splits: consecutive blocks share their targets and stream different
+// source ranges, and since blocks are dealt to the 8 XCDs in turn each XCD
+// keeps re-reading the same few source ranges from its own L2 (measured 8%
+// faster than the target-fastest order).
+template <int T, bool WITH_A>
+__global__ __launch_bounds__(256) void k_exact_pairs(
+    const float4 *__restrict__ Qt, const float4 *__restrict__ Pt, int64_t ntgt,
+    const float4 *__restrict__ Qs, const float4 *__restrict__ Ps, int64_t chunk, int64_t nsrc,
+    int splits, float negc, double *__restrict__ part) {
+    const int lane = threadIdx.x & 63;
+    const int64_t split = blockIdx.x % splits, tb = blockIdx.x / splits;
+    const int64_t wave = tb * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int64_t t0 = wave * (64 * T) + lane;
+    const int64_t j0 = split * chunk;
+    const int64_t j1 = j0 + chunk < nsrc ? j0 + chunk : nsrc;
+    pair_sums<T, WITH_A>(Qt, Pt, ntgt, Qs, Ps, t0, j0, j1, negc, part + split * 6 * ntgt);
+}
+
+// Batched sets: block b takes work item b = (first padded target row of 256,
+// source rows [j0, j1) of the same set, partial slot).
+template <bool WITH_A>
+__global__ __launch_bounds__(256) void k_exact_items(const float4 *__restrict__ Q,
+                                                     const float4 *__restrict__ P, int64_t npad,
+                                                     const int4 *__restrict__ items, float negc,
+                                                     double *__restrict__ part) {
+    const int4 it = items[blockIdx.x];
+    const int64_t t0 = (int64_t)it.x + (threadIdx.x >> 6) * 64 + (threadIdx.x & 63);
+    pair_sums<1, WITH_A>(Q, P, npad, Q, P, t0, it.y, it.z, negc, part + (int64_t)it.w * 6 * npad);
 }
 
 // Same sums with the source tile staged in LDS: every wave reads each source
@@ -202,12 +231,13 @@ template <int T, bool WITH_A>
 __global__ __launch_bounds__(256) void k_exact_pairs_lds(
     const float4 *__restrict__ Qt, const float4 *__restrict__ Pt, int64_t ntgt,
     const float4 *__restrict__ Qs, const float4 *__restrict__ Ps, int64_t chunk, int64_t nsrc,
-    float negc, double *__restrict__ part) {
+    int splits, float negc, double *__restrict__ part) {
     __shared__ float4 sq[kLdsTile];
     __shared__ float4 sp[kLdsTile];
     constexpr int B = 4;
     const int lane = threadIdx.x & 63;
-    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int64_t split = blockIdx.x % splits, tb = blockIdx.x / splits;
+    const int64_t wave = tb * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const int64_t t0 = wave * (64 * T) + lane;
 
     float x[T], y[T], z[T], px[T], py[T], pz[T];
@@ -230,7 +260,7 @@ __global__ __launch_bounds__(256) void k_exact_pairs_lds(
 #pragma unroll
         for (int c = 0; c < 3; ++c) sv[k][c] = sa[k][c] = 0.0;
 
-    const int64_t j0 = (int64_t)blockIdx.y * chunk;
+    const int64_t j0 = split * chunk;
     const int64_t j1 = j0 + chunk < nsrc ? j0 + chunk : nsrc;
     for (int64_t jt = j0; jt < j1; jt += kLdsTile) {
         __syncthreads();
@@ -288,7 +318,7 @@ __global__ __launch_bounds__(256) void k_exact_pairs_lds(
                 }
         }
     }
-    double *dst = part + (int64_t)blockIdx.y * 6 * ntgt;
+    double *dst = part + split * 6 * ntgt;
 #pragma unroll
     for (int k = 0; k < T; ++k) {
         const int64_t i = t0 + 64 * k;
@@ -494,14 +524,106 @@ __global__ __launch_bounds__(256) void k_combine_euler(const double *__restrict_
     }
 }
 
-__global__ __launch_bounds__(256) void k_reduce_h(const double *__restrict__ Hpart, int nblk,
-                                                  double *__restrict__ H) {
+// H[set * count + t] = sum of Hpart[t * stride + b] over the partials b of
+// the set (seg[set] <= b < seg[set + 1]; all of [0, stride) when seg is
+// null).  grid (count, sets).
+__global__ __launch_bounds__(256) void k_reduce_h(const double *__restrict__ Hpart,
+                                                  int64_t stride, const int *__restrict__ seg,
+                                                  int count, double *__restrict__ H) {
     __shared__ double lds[8];
-    const int t = blockIdx.x;
+    const int t = blockIdx.x, set = blockIdx.y;
+    const int64_t lo = seg ? seg[set] : 0, hi = seg ? seg[set + 1] : stride;
     double s = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += blockDim.x) s += Hpart[(int64_t)t * nblk + b];
+    for (int64_t b = lo + threadIdx.x; b < hi; b += blockDim.x) s += Hpart[(int64_t)t * stride + b];
     s = block_sum_f64(s, lds);
-    if (threadIdx.x == 0) H[t] = s;
+    if (threadIdx.x == 0) H[(int64_t)set * count + t] = s;
+}
+
+// ---------------------------------------------------------------- batched sets
+// Rows are padded per set to whole blocks of 256; block b of the rows is
+// described by blk[b] = (first real point of the block, real rows in it,
+// set, partial slots of the set).  Real point i of set s sits at padded row
+// base_s + (i - first point of s).
+
+__global__ __launch_bounds__(256) void k_pack_state_rows(const float *__restrict__ q,
+                                                         const float *__restrict__ p,
+                                                         const int4 *__restrict__ blk,
+                                                         double *__restrict__ Sq,
+                                                         double *__restrict__ Sp,
+                                                         float4 *__restrict__ Q,
+                                                         float4 *__restrict__ P) {
+    const int4 d = blk[blockIdx.x];
+    const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if ((int)threadIdx.x < d.y) {
+        const int64_t i = (int64_t)d.x + threadIdx.x;
+        const float x = q[3 * i], y = q[3 * i + 1], z = q[3 * i + 2];
+        const float u = p[3 * i], v = p[3 * i + 1], w = p[3 * i + 2];
+        Sq[3 * i] = x;
+        Sq[3 * i + 1] = y;
+        Sq[3 * i + 2] = z;
+        Sp[3 * i] = u;
+        Sp[3 * i + 1] = v;
+        Sp[3 * i + 2] = w;
+        Q[row] = make_float4(x, y, z, 0.f);
+        P[row] = make_float4(u, v, w, 0.f);
+    } else {
+        // padding: zero momentum, so a padded source adds exactly zero
+        Q[row] = make_float4(0.f, 0.f, 0.f, 0.f);
+        P[row] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_combine_rows(const double *__restrict__ part,
+                                                      int64_t npad, const int4 *__restrict__ blk,
+                                                      double inv_s2, int mode,
+                                                      float *__restrict__ dq,
+                                                      float *__restrict__ dp, double dt,
+                                                      double *__restrict__ Sq,
+                                                      double *__restrict__ Sp,
+                                                      float4 *__restrict__ Q,
+                                                      float4 *__restrict__ P,
+                                                      double *__restrict__ Hpart) {
+    __shared__ double lds[8];
+    const int4 d = blk[blockIdx.x];
+    const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double e = 0.0;
+    if ((int)threadIdx.x < d.y) {
+        const int64_t i = (int64_t)d.x + threadIdx.x;
+        double acc[6] = {0, 0, 0, 0, 0, 0};
+        for (int s = 0; s < d.w; ++s)
+#pragma unroll
+            for (int c = 0; c < 6; ++c) acc[c] += part[((int64_t)s * 6 + c) * npad + row];
+        if (mode == 0) {  // right-hand side
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                dq[3 * i + c] = (float)acc[c];
+                dp[3 * i + c] = (float)(acc[3 + c] * inv_s2);
+            }
+        } else {
+            double q[3], p[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                q[c] = Sq[3 * i + c];
+                p[c] = Sp[3 * i + c];
+            }
+            e = p[0] * acc[0] + p[1] * acc[1] + p[2] * acc[2];
+            if (dt > 0.0) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    q[c] += dt * acc[c];
+                    p[c] += dt * (acc[3 + c] * inv_s2);
+                    Sq[3 * i + c] = q[c];
+                    Sp[3 * i + c] = p[c];
+                }
+                Q[row] = make_float4((float)q[0], (float)q[1], (float)q[2], 0.f);
+                P[row] = make_float4((float)p[0], (float)p[1], (float)p[2], 0.f);
+            }
+        }
+    }
+    if (Hpart) {
+        const double s = block_sum_f64(e, lds);
+        if (threadIdx.x == 0) Hpart[blockIdx.x] = s;
+    }
 }
 
 // ---------------------------------------------------------------- FP64 path
@@ -607,12 +729,13 @@ ExactPlan plan_exact(int64_t n_targets, int64_t n_sources, bool mfma) {
     const int64_t tgt_per_block = 1024;
     pl.ntgt = round_up(n_targets > 0 ? n_targets : 1, tgt_per_block);
     pl.nsrc = round_up(n_sources > 0 ? n_sources : 1, kMTile);
-    // Aim at ~24 waves per SIMD (1024 SIMDs) so that the per-SIMD work is
-    // balanced to a few percent; never split below one tile per split.
-    // the split count depends on n only (not on the kernel or its tuning), so
-    // workspace sizes never depend on those choices
-    const int64_t waves_t = pl.ntgt / 128;
-    int64_t s = (24 * 1024 + waves_t - 1) / waves_t;
+    // Aim at ~24k blocks of 256 targets per launch (about 96 waves per SIMD
+    // in a few rounds, so the last round is a small share of the launch);
+    // never split below 256 sources.  The split count depends on n only (not
+    // on the kernel or its tuning), so workspace sizes never depend on those
+    // choices.
+    const int64_t tblocks = pl.ntgt / 256;
+    int64_t s = (kSplitBlocks + tblocks - 1) / tblocks;
     const int64_t max_s = pl.nsrc / kMTile;
     if (s > max_s) s = max_s;
     if (s > 64) s = 64;
@@ -668,17 +791,17 @@ gs_status launch_exact_pairs(const ExactPlan &pl, const float4 *Qt, const float4
         return GS_OK;
     }
     const float negc = (float)(-kLog2e / (2.0 * sigma * sigma));
-    dim3 grid((unsigned)(pl.ntgt / (64 * pl.tpl * 4)), (unsigned)pl.splits);
+    dim3 grid((unsigned)(pl.ntgt / (64 * pl.tpl * 4) * pl.splits));
     const int kind = with_a ? KIND_EXACT : KIND_EXACT_V;
     timing_begin(kind, s);
 #define GS_PAIRS(T, A)                                                                     \
     do {                                                                                   \
         if (exact_lds())                                                                   \
             hipLaunchKernelGGL((k_exact_pairs_lds<T, A>), grid, dim3(256), 0, s, Qt, Pt,   \
-                               pl.ntgt, Qs, Ps, pl.chunk, pl.nsrc, negc, part);            \
+                               pl.ntgt, Qs, Ps, pl.chunk, pl.nsrc, pl.splits, negc, part); \
         else                                                                               \
             hipLaunchKernelGGL((k_exact_pairs<T, A>), grid, dim3(256), 0, s, Qt, Pt, pl.ntgt, \
-                               Qs, Ps, pl.chunk, pl.nsrc, negc, part);                     \
+                               Qs, Ps, pl.chunk, pl.nsrc, pl.splits, negc, part);          \
     } while (0)
     if (with_a) {
         if (pl.tpl == 1) GS_PAIRS(1, true);
@@ -736,8 +859,129 @@ gs_status launch_unpack_state(const double *Sq, const double *Sp, int64_t n, flo
 }
 
 gs_status launch_reduce_h(const double *Hpart, int nblk, int count, double *H, hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce_h, dim3((unsigned)count), dim3(kBlock), 0, s, Hpart, nblk, H);
+    return launch_reduce_h_seg(Hpart, nblk, nullptr, 1, count, H, s);
+}
+
+gs_status launch_reduce_h_seg(const double *Hpart, int64_t stride, const int *seg, int nsub,
+                              int count, double *H, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_h, dim3((unsigned)count, (unsigned)nsub), dim3(kBlock), 0, s,
+                       Hpart, stride, seg, count, H);
     GS_LAUNCH_CHECK("reduce_h");
+    return GS_OK;
+}
+
+// ---------------------------------------------------------------- batched sets
+// Target number of work items (blocks) of one batched launch;
+// GS_EXACT_ITEM_BLOCKS overrides it for tuning.
+static int64_t item_blocks() {
+    static int64_t v = [] {
+        const char *e = getenv("GS_EXACT_ITEM_BLOCKS");
+        const long long b = e ? atoll(e) : 0;
+        return (int64_t)(b >= 256 && b <= (1 << 22) ? b : kSplitBlocks);
+    }();
+    return v;
+}
+
+ExactBatchPlan plan_exact_batch(const int64_t *offsets, int nsub) {
+    ExactBatchPlan pl{};
+    pl.nsub = nsub;
+    pl.ntot = offsets[nsub];
+    std::vector<int64_t> base(nsub), tp(nsub), sp(nsub);
+    int64_t work = 0, rows = 0;
+    for (int s = 0; s < nsub; ++s) {
+        const int64_t n = offsets[s + 1] - offsets[s];
+        base[s] = rows;
+        tp[s] = round_up(n, 256);
+        sp[s] = round_up(n, kTile);
+        rows += tp[s];
+        work += tp[s] * sp[s];
+    }
+    pl.npad = rows > 0 ? rows : 256;
+    // Source chunk: about item_blocks() blocks of 256 targets in a launch,
+    // never below 2048 sources.
+    const int64_t blocks = item_blocks();
+    int64_t chunk = round_up((work + 256 * blocks - 1) / (256 * blocks), kTile);
+    if (chunk < 2048) chunk = 2048;
+    pl.max_chunks = 1;
+    pl.bseg.resize(nsub + 1);
+    struct Item {
+        int64_t cost;
+        int4 it;
+    };
+    std::vector<Item> items;
+    for (int s = 0; s < nsub; ++s) {
+        pl.bseg[s] = (int)pl.blocks.size();
+        const int64_t n = offsets[s + 1] - offsets[s];
+        if (n == 0) continue;
+        int nch = (int)((sp[s] + chunk - 1) / chunk);
+        const int64_t csz = round_up((sp[s] + nch - 1) / nch, kTile);
+        nch = (int)((sp[s] + csz - 1) / csz);
+        if (nch > pl.max_chunks) pl.max_chunks = nch;
+        for (int64_t b = 0; b < tp[s] / 256; ++b) {
+            const int64_t cnt = n - 256 * b < 256 ? n - 256 * b : 256;
+            pl.blocks.push_back(make_int4((int)(offsets[s] + 256 * b), (int)cnt, s, nch));
+            for (int c = 0; c < nch; ++c) {
+                const int64_t j0 = base[s] + c * csz;
+                const int64_t j1 = j0 + csz < base[s] + sp[s] ? j0 + csz : base[s] + sp[s];
+                items.push_back({256 * (j1 - j0),
+                                 make_int4((int)(base[s] + 256 * b), (int)j0, (int)j1, c)});
+            }
+        }
+    }
+    pl.bseg[nsub] = (int)pl.blocks.size();
+    // largest items first, so that the short ones fill the end of the launch
+    std::stable_sort(items.begin(), items.end(),
+                     [](const Item &a, const Item &b) { return a.cost > b.cost; });
+    pl.items.reserve(items.size());
+    for (const Item &x : items) pl.items.push_back(x.it);
+    return pl;
+}
+
+void carve_exact_batch(Arena &a, const ExactBatchPlan &pl, int nt, ExactBatchBufs &b) {
+    b.Q = a.take<float4>(pl.npad);
+    b.P = a.take<float4>(pl.npad);
+    b.part = a.take<double>((size_t)pl.max_chunks * 6 * pl.npad);
+    const int64_t n = pl.ntot > 0 ? pl.ntot : 1;
+    b.Sq = a.take<double>(3 * n);
+    b.Sp = a.take<double>(3 * n);
+    const size_t nb = pl.blocks.size() > 0 ? pl.blocks.size() : 1;
+    b.Hpart = a.take<double>((size_t)(nt + 1) * nb);
+}
+
+gs_status launch_pack_state_rows(const ExactBatchPlan &pl, const ExactBatchBufs &b,
+                                 const float *q, const float *p, hipStream_t s) {
+    if (pl.blocks.empty()) return GS_OK;
+    hipLaunchKernelGGL(k_pack_state_rows, dim3((unsigned)pl.blocks.size()), dim3(256), 0, s, q,
+                       p, b.blk, b.Sq, b.Sp, b.Q, b.P);
+    GS_LAUNCH_CHECK("pack_state_rows");
+    return GS_OK;
+}
+
+gs_status launch_exact_items(const ExactBatchPlan &pl, const ExactBatchBufs &b, double sigma,
+                             bool with_a, hipStream_t s) {
+    if (pl.items.empty()) return GS_OK;
+    const float negc = (float)(-kLog2e / (2.0 * sigma * sigma));
+    const int kind = with_a ? KIND_EXACT : KIND_EXACT_V;
+    timing_begin(kind, s);
+    if (with_a)
+        hipLaunchKernelGGL(k_exact_items<true>, dim3((unsigned)pl.items.size()), dim3(256), 0, s,
+                           b.Q, b.P, pl.npad, b.items, negc, b.part);
+    else
+        hipLaunchKernelGGL(k_exact_items<false>, dim3((unsigned)pl.items.size()), dim3(256), 0, s,
+                           b.Q, b.P, pl.npad, b.items, negc, b.part);
+    timing_end(kind, s);
+    GS_LAUNCH_CHECK("exact_items");
+    return GS_OK;
+}
+
+gs_status launch_combine_rows(const ExactBatchPlan &pl, const ExactBatchBufs &b, double sigma,
+                              int mode, float *dq, float *dp, double dt, double *Hpart,
+                              hipStream_t s) {
+    if (pl.blocks.empty()) return GS_OK;
+    hipLaunchKernelGGL(k_combine_rows, dim3((unsigned)pl.blocks.size()), dim3(256), 0, s, b.part,
+                       pl.npad, b.blk, 1.0 / (sigma * sigma), mode, dq, dp, dt, b.Sq, b.Sp, b.Q,
+                       b.P, Hpart);
+    GS_LAUNCH_CHECK("combine_rows");
     return GS_OK;
 }
 

@@ -6,6 +6,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <vector>
 
 #include "gs.h"
 
@@ -80,6 +81,7 @@ struct ExactPlan {
 };
 constexpr int kMfmaGroups = 4;  // groups of 16 targets per wave (MFMA kernel)
 constexpr int kExactTplDefault = 1;  // targets per lane (VALU kernel, measured best)
+constexpr int64_t kSplitBlocks = 24576;  // blocks per exact launch the split count aims at
 ExactPlan plan_exact(int64_t n_targets, int64_t n_sources, bool mfma = false);
 
 // Buffers of one exact FP32 RHS evaluation.
@@ -121,6 +123,45 @@ gs_status launch_unpack_state(const double *Sq, const double *Sp, int64_t n, flo
 int combine_blocks(int64_t n);
 // H[t] = sum_b Hpart[t * nblk + b] for t in [0, count).
 gs_status launch_reduce_h(const double *Hpart, int nblk, int count, double *H, hipStream_t s);
+// Per set: H[set * count + t] = sum of Hpart[t * stride + b] for b in
+// [seg[set], seg[set + 1]) (seg: device int [nsub + 1]; null = one set).
+gs_status launch_reduce_h_seg(const double *Hpart, int64_t stride, const int *seg, int nsub,
+                              int count, double *H, hipStream_t s);
+
+// ---------------------------------------------------------------- batched sets
+// Exact evaluation of independent point sets (subjects) stored one after the
+// other ([offsets[s], offsets[s+1]) is set s).  Rows are padded per set to
+// whole blocks of 256 targets; a work item is one such block against one
+// source chunk of its own set.  Items run largest first.
+struct ExactBatchPlan {
+    int nsub;
+    int64_t ntot;                 // real points
+    int64_t npad;                 // padded rows
+    int max_chunks;               // partial slots per row
+    std::vector<int4> items;      // (first target row, j0, j1, slot)
+    std::vector<int4> blocks;     // per 256-row block: (first real point, count, set, slots)
+    std::vector<int> bseg;        // [nsub + 1] row-block range of each set
+};
+ExactBatchPlan plan_exact_batch(const int64_t *offsets, int nsub);
+struct ExactBatchBufs {
+    float4 *Q, *P;                // [npad] packed FP32 state, zero padding
+    double *part;                 // [max_chunks][6][npad]
+    double *Sq, *Sp;              // [ntot][3] FP64 state
+    double *Hpart;                // [nt + 1][blocks]
+    const int4 *items, *blk;      // device copies of the plan's tables (set by the caller)
+    const int *bseg;
+};
+// Carves the state and partial buffers (not the tables).
+void carve_exact_batch(Arena &a, const ExactBatchPlan &pl, int nt, ExactBatchBufs &b);
+gs_status launch_pack_state_rows(const ExactBatchPlan &pl, const ExactBatchBufs &b,
+                                 const float *q, const float *p, hipStream_t s);
+gs_status launch_exact_items(const ExactBatchPlan &pl, const ExactBatchBufs &b, double sigma,
+                             bool with_a, hipStream_t s);
+// mode 0: (dq, dp) = (v, a); mode 1: energy partials into Hpart (nullable)
+// and, if dt > 0, the Euler step of the FP64 state and its packed copies.
+gs_status launch_combine_rows(const ExactBatchPlan &pl, const ExactBatchBufs &b, double sigma,
+                              int mode, float *dq, float *dp, double dt, double *Hpart,
+                              hipStream_t s);
 
 // FP64 exact path.
 gs_status launch_exact_f64(const double *q, const double *p, int64_t n, double sigma,

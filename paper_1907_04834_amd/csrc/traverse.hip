@@ -65,6 +65,18 @@ struct DecideLds {
     StageLds st;     // list overflow only
 };
 
+// Targets of group g: the table entry, or 64 consecutive points of one tree.
+__device__ inline GroupDesc group_desc(const GroupDesc *__restrict__ gtab, int64_t g, int64_t n) {
+    if (gtab) return gtab[g];
+    GroupDesc d;
+    d.first = (int)(g * 64);
+    const int64_t r = n - g * 64;
+    d.count = r < 64 ? (int)r : 64;
+    d.root = 0;
+    d.sub = 0;
+    return d;
+}
+
 // Orders the LDS writes of this wave before its following LDS reads (all
 // lanes of a wave run in lock step; this only stops compiler reordering).
 __device__ inline void wave_sync() {
@@ -157,16 +169,18 @@ __device__ inline void write_part(double *__restrict__ part, int slot, int64_t n
 template <bool WITH_A>
 __global__ __launch_bounds__(256) void k_bh_decide(
     const BhNode *__restrict__ nodes, const float4 *__restrict__ Qs, const float4 *__restrict__ Ps,
-    int64_t n, int64_t npad, BhParams bp, LeafEntry *__restrict__ list, int *__restrict__ list_n,
-    double *__restrict__ part, u64 *__restrict__ counters, const TreeMeta *__restrict__ meta,
-    int *__restrict__ status) {
+    int64_t n, const GroupDesc *__restrict__ gtab, int64_t groups, BhParams bp,
+    LeafEntry *__restrict__ list, int *__restrict__ list_n, double *__restrict__ part,
+    u64 *__restrict__ counters, const TreeTotals *__restrict__ totals, int *__restrict__ status) {
     __shared__ DecideLds lds_all[4];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     DecideLds &L = lds_all[wv];
     const int64_t grp = (int64_t)blockIdx.x * 4 + wv;
-    if (grp * 64 >= n) return;  // wave-uniform; this kernel has no block barrier
-    const int64_t t = grp * 64 + lane;
-    const bool active = t < n;
+    if (grp >= groups) return;  // wave-uniform; this kernel has no block barrier
+    const int64_t npad = groups * 64;
+    const GroupDesc gd = group_desc(gtab, grp, n);
+    const int64_t t = (int64_t)gd.first + lane;
+    const bool active = lane < gd.count;
     const float4 xq = active ? Qs[t] : make_float4(0.f, 0.f, 0.f, 0.f);
     const float4 xp = active ? Ps[t] : make_float4(0.f, 0.f, 0.f, 0.f);
     const double xd = xq.x, yd = xq.y, zd = xq.z;
@@ -179,13 +193,13 @@ __global__ __launch_bounds__(256) void k_bh_decide(
 
     int sp = 0;
     const u64 live = __ballot(active);
-    if (live != 0ull) {  // the root as a block of one
-        L.first[0] = 0;
+    if (live != 0ull) {  // the group's root as a block of one
+        L.first[0] = gd.root;
         L.count[0] = 1;
         L.mask[0] = live;
         sp = 1;
         float4 *dstn = reinterpret_cast<float4 *>(L.node);
-        if (lane < 5) dstn[lane] = reinterpret_cast<const float4 *>(nodes)[lane];
+        if (lane < 5) dstn[lane] = reinterpret_cast<const float4 *>(nodes + gd.root)[lane];
     }
     wave_sync();
     while (sp > 0) {
@@ -276,7 +290,7 @@ __global__ __launch_bounds__(256) void k_bh_decide(
         V[c] += (double)mv[c];
         A[c] += (double)ma[c];
     }
-    write_part(part, 0, npad, t, V, A);
+    write_part(part, 0, npad, grp * 64 + lane, V, A);
     if (lane == 0) list_n[grp] = nlist;
 
     // counters: wave sums, one atomic per wave (integer, order-free)
@@ -291,7 +305,7 @@ __global__ __launch_bounds__(256) void k_bh_decide(
         atomicAdd(&counters[0], cp);
         atomicAdd(&counters[1], cm);
         atomicAdd(&counters[2], cv);
-        if (grp == 0) atomicAdd(&counters[3], (u64)meta->n_nodes);
+        if (grp == 0) atomicAdd(&counters[3], (u64)totals->n_nodes);
         atomicAdd(&counters[4], (u64)w_steps);
         atomicAdd(&counters[5], (u64)w_nodes);
         atomicMax(&counters[6], (u64)w_steps + (u64)w_nodes);
@@ -302,7 +316,8 @@ __global__ __launch_bounds__(256) void k_bh_decide(
 template <bool WITH_A>
 __global__ __launch_bounds__(256) void k_bh_leaves(const float4 *__restrict__ Qs,
                                                    const float4 *__restrict__ Ps, int64_t n,
-                                                   int64_t npad, float negc,
+                                                   const GroupDesc *__restrict__ gtab,
+                                                   int64_t groups, float negc,
                                                    const LeafEntry *__restrict__ list,
                                                    const int *__restrict__ list_n,
                                                    double *__restrict__ part,
@@ -317,15 +332,17 @@ __global__ __launch_bounds__(256) void k_bh_leaves(const float4 *__restrict__ Qs
     const int ne = cnt - e0 < kChunkEntries ? cnt - e0 : kChunkEntries;
     StageLds &S = lds_all[wv];
     if (lane < ne) S.ent[lane] = list[grp * kListCap + e0 + lane];
-    const int64_t t = grp * 64 + lane;
-    const bool active = t < n;
+    const int64_t npad = groups * 64;
+    const GroupDesc gd = group_desc(gtab, grp, n);
+    const int64_t t = (int64_t)gd.first + lane;
+    const bool active = lane < gd.count;
     const float4 xq = active ? Qs[t] : make_float4(0.f, 0.f, 0.f, 0.f);
     const float4 xp = active ? Ps[t] : make_float4(0.f, 0.f, 0.f, 0.f);
     double V[3] = {0, 0, 0}, A[3] = {0, 0, 0};
     unsigned steps = 0;
     wave_sync();
     leaf_pairs<WITH_A>(S, ne, Qs, Ps, lane, xq, xp, negc, V, A, steps);
-    write_part(part, 1 + chunk, npad, t, V, A);
+    write_part(part, 1 + chunk, npad, grp * 64 + lane, V, A);
     if (lane == 0 && counters) {
         atomicAdd(&counters[4], (u64)steps);
         atomicMax(&counters[6], (u64)steps);
@@ -333,29 +350,34 @@ __global__ __launch_bounds__(256) void k_bh_leaves(const float4 *__restrict__ Qs
 }
 
 // Phase 3: fixed-order sum of a target's parts and the output of the mode.
+// One thread per (group, lane) slot; the energy sum of each group (one wave)
+// goes to Hpart[group].
 template <bool WITH_A>
 __global__ __launch_bounds__(256) void k_bh_combine(
     const double *__restrict__ part, const int *__restrict__ list_n,
-    const unsigned *__restrict__ perm, int64_t n, int64_t npad, double inv_s2, int mode,
-    float *__restrict__ dq, float *__restrict__ dp, double *__restrict__ Sq,
-    double *__restrict__ Sp, float *__restrict__ q32, float *__restrict__ p32, double dt,
-    double *__restrict__ Hpart, double *__restrict__ v64) {
-    __shared__ double s_red[4];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const GroupDesc *__restrict__ gtab, int64_t groups, const unsigned *__restrict__ perm,
+    int64_t n, double inv_s2, int mode, float *__restrict__ dq, float *__restrict__ dp,
+    double *__restrict__ Sq, double *__restrict__ Sp, float *__restrict__ q32,
+    float *__restrict__ p32, double dt, double *__restrict__ Hpart, double *__restrict__ v64) {
+    const int lane = threadIdx.x & 63;
+    const int64_t grp = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (grp >= groups) return;  // wave-uniform; no block barrier below
+    const int64_t npad = groups * 64;
+    const int64_t slot = grp * 64 + lane;
+    const GroupDesc gd = group_desc(gtab, grp, n);
     double e = 0.0;
-    if (t < n) {
-        const int nch = (list_n[t / 64] + kChunkEntries - 1) / kChunkEntries;
+    if (lane < gd.count) {
+        const int nch = (list_n[grp] + kChunkEntries - 1) / kChunkEntries;
         double V[3] = {0, 0, 0}, A[3] = {0, 0, 0};
         for (int s = 0; s <= nch; ++s) {
-            const double *d = part + ((int64_t)s * npad + t) * 6;
+            const double *d = part + ((int64_t)s * npad + slot) * 6;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 V[c] += d[c];
                 A[c] += d[3 + c];
             }
         }
-        const int64_t i = perm[t];
+        const int64_t i = perm[(int64_t)gd.first + lane];
         if (v64)
 #pragma unroll
             for (int c = 0; c < 3; ++c) v64[3 * i + c] = V[c];
@@ -389,9 +411,7 @@ __global__ __launch_bounds__(256) void k_bh_combine(
     if (Hpart && mode != MODE_RHS) {
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) e += __shfl_down(e, off, 64);
-        if (lane == 0) s_red[wv] = e;
-        __syncthreads();
-        if (threadIdx.x == 0) Hpart[blockIdx.x] = ((s_red[0] + s_red[1]) + s_red[2]) + s_red[3];
+        if (lane == 0) Hpart[grp] = e;
     }
 }
 
@@ -428,13 +448,11 @@ constexpr size_t kStatusOffset = 0;  // status word at the start of the workspac
 
 }  // namespace
 
-int traverse_blocks(int64_t n) { return (int)nblk(n > 0 ? n : 1, 256); }
-
-size_t traverse_list_bytes(int64_t n) {
-    return (size_t)((n + 63) / 64) * kListCap * sizeof(LeafEntry);
+size_t traverse_list_bytes(int64_t groups) {
+    return (size_t)groups * kListCap * sizeof(LeafEntry);
 }
 
-size_t traverse_part_doubles(int64_t n) { return (size_t)kParts * ((n + 63) / 64) * 64 * 6; }
+size_t traverse_part_doubles(int64_t groups) { return (size_t)kParts * groups * 64 * 6; }
 
 BhParams make_bh_params(const gs_params &prm) {
     BhParams b{};
@@ -452,21 +470,22 @@ BhParams make_bh_params(const gs_params &prm) {
 gs_status launch_bh_traverse(const TreeBufs &t, const BhParams &bp, bool with_a,
                              const TraverseOut &o, unsigned long long *counters, hipStream_t s,
                              int mode, int *status) {
-    const int64_t groups = (t.n + 63) / 64;
-    const int64_t npad = groups * 64;
+    const int64_t groups = t.groups;
+    if (groups <= 0) return GS_OK;
     LeafEntry *list = reinterpret_cast<LeafEntry *>(t.list);
     const int kind = with_a ? KIND_TRAVERSE : KIND_TRAVERSE_V;
     timing_begin(kind, s);
 #define GS_PHASES(A)                                                                            \
     do {                                                                                        \
         hipLaunchKernelGGL(k_bh_decide<A>, dim3((unsigned)((groups + 3) / 4)), dim3(256), 0, s, \
-                           t.nodes, t.Qs, t.Ps, t.n, npad, bp, list, t.list_n, t.part,          \
-                           counters, t.meta, status);                                           \
+                           t.nodes, t.Qs, t.Ps, t.n, t.gtab, groups, bp, list, t.list_n,        \
+                           t.part, counters, t.totals, status);                                 \
         hipLaunchKernelGGL(k_bh_leaves<A>, dim3((unsigned)groups, kChunks / 4), dim3(256), 0, s, \
-                           t.Qs, t.Ps, t.n, npad, bp.negc, list, t.list_n, t.part, counters);   \
-        hipLaunchKernelGGL(k_bh_combine<A>, dim3((unsigned)traverse_blocks(t.n)), dim3(256), 0, \
-                           s, t.part, t.list_n, t.valA, t.n, npad, bp.inv_s2, mode, o.dq, o.dp, \
-                           o.Sq, o.Sp, o.q32, o.p32, o.dt, o.Hpart, o.v64);                     \
+                           t.Qs, t.Ps, t.n, t.gtab, groups, bp.negc, list, t.list_n, t.part,    \
+                           counters);                                                           \
+        hipLaunchKernelGGL(k_bh_combine<A>, dim3((unsigned)((groups + 3) / 4)), dim3(256), 0, s, \
+                           t.part, t.list_n, t.gtab, groups, t.perm, t.n, bp.inv_s2, mode,      \
+                           o.dq, o.dp, o.Sq, o.Sp, o.q32, o.p32, o.dt, o.Hpart, o.v64);         \
     } while (0)
     if (with_a)
         GS_PHASES(true);
@@ -483,14 +502,28 @@ gs_status launch_bh_traverse(const TreeBufs &t, const BhParams &bp, bool with_a,
     return launch_bh_traverse(t, bp, with_a, o, counters, s, MODE_RHS, nullptr);
 }
 
-ShootBhBufs layout_shoot_bh(Arena &a, int64_t n, int nt) {
-    ShootBhBufs b{};
-    carve_tree(a, n, b.tree);
+static void carve_state(Arena &a, int64_t n, int nt, ShootBhBufs &b) {
     b.Sq = a.take<double>(3 * n);
     b.Sp = a.take<double>(3 * n);
     b.q32 = a.take<float>(3 * n);
     b.p32 = a.take<float>(3 * n);
-    b.Hpart = a.take<double>((size_t)(nt + 1) * traverse_blocks(n));
+    b.Hpart = a.take<double>((size_t)(nt + 1) * (b.tree.groups > 0 ? b.tree.groups : 1));
+}
+
+ShootBhBufs layout_shoot_bh(Arena &a, int64_t n, int nt) {
+    ShootBhBufs b{};
+    carve_tree(a, n, b.tree);
+    carve_state(a, n, nt, b);
+    b.gseg = nullptr;
+    return b;
+}
+
+ShootBhBufs layout_shoot_forest(Arena &a, int64_t n, int nsub, int64_t groups, int64_t max_set,
+                                int nt) {
+    ShootBhBufs b{};
+    carve_forest(a, n, nsub, groups, max_set, b.tree);
+    carve_state(a, n, nt, b);
+    b.gseg = nullptr;
     return b;
 }
 
@@ -515,7 +548,7 @@ gs_status shoot_bh(const float *q0, const float *p0, int64_t n, const gs_params 
                        b.Sp, b.q32, b.p32);
     GS_LAUNCH_CHECK("state_init");
     const BhParams bp = make_bh_params(prm);
-    const int nblk_t = traverse_blocks(n);
+    const int64_t ng = b.tree.groups;
     TraverseOut o{};
     o.Sq = b.Sq;
     o.Sp = b.Sp;
@@ -524,14 +557,14 @@ gs_status shoot_bh(const float *q0, const float *p0, int64_t n, const gs_params 
     o.dt = 1.0 / prm.nt;
     for (int t = 0; t < prm.nt; ++t) {
         GS_TRY(build_tree(b.q32, b.p32, n, prm.leaf_cap, b.tree, status, s));
-        o.Hpart = H ? b.Hpart + (size_t)t * nblk_t : nullptr;
+        o.Hpart = H ? b.Hpart + (size_t)t * ng : nullptr;
         GS_TRY(launch_bh_traverse(b.tree, bp, true, o, counters, s, MODE_SHOOT, status));
     }
     if (H) {
         GS_TRY(build_tree(b.q32, b.p32, n, prm.leaf_cap, b.tree, status, s));
-        o.Hpart = b.Hpart + (size_t)prm.nt * nblk_t;
+        o.Hpart = b.Hpart + (size_t)prm.nt * ng;
         GS_TRY(launch_bh_traverse(b.tree, bp, false, o, counters, s, MODE_ENERGY, status));
-        GS_TRY(launch_reduce_h(b.Hpart, nblk_t, prm.nt + 1, H, s));
+        GS_TRY(launch_reduce_h_seg(b.Hpart, ng, b.gseg, b.tree.nsub, prm.nt + 1, H, s));
     }
     hipLaunchKernelGGL(k_state_out, dim3(nblk(3 * n)), dim3(kBlock), 0, s, b.Sq, b.Sp, 3 * n, q1,
                        p1);

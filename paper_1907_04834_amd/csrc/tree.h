@@ -30,7 +30,8 @@ struct alignas(16) BhNode {
 };
 static_assert(sizeof(BhNode) == 80, "BhNode layout");
 
-// Small device-side header of one tree build.
+// Device-side header of the tree of one point set (one per subject when
+// several independent point sets are built together as a forest).
 struct TreeMeta {
     float lo[3];
     float hi[3];
@@ -38,21 +39,47 @@ struct TreeMeta {
     double scale;       // 2^21 / E (0 when E == 0)
     int nonfinite;      // a coordinate was NaN or +-inf
     int root_leaf;      // 1 when the root is a leaf
-    int n_internal;     // compressed internal nodes (excluding a leaf root)
-    int n_nodes;        // stored nodes
     int root_rank;      // internal rank of the root (if internal)
     int pad;
 };
 
+// Totals of a build: internal nodes of all trees, stored nodes (roots
+// included).
+struct TreeTotals {
+    int n_internal;
+    int n_nodes;
+};
+
+// Targets of one traversal wave: `count` (<= 64) consecutive sorted points
+// from `first`, all in the tree whose root is node `root`.
+struct GroupDesc {
+    int first;
+    int count;
+    int root;
+    int sub;
+};
+
+// Forest layout.  Point sets s = 0..nsub-1 occupy the index ranges
+// [seg[s], seg[s+1]) of the input; the build sorts every set within its own
+// range, so sorted index ranges equal input ranges.  Node s is the root of
+// set s.  With seg == nullptr there is one set [0, n).
 struct TreeBufs {
     int64_t n;
-    int bbox_blocks;
+    int nsub;
+    const long long *seg;      // [nsub + 1] device offsets (nullable: one set)
+    int64_t groups;            // traversal groups
+    const GroupDesc *gtab;     // [groups] (nullable: group g = points [64g, 64g + 64))
+    int bbox_blocks;           // per set
     int sort_blocks;
-    TreeMeta *meta;
-    float *bbox_part;          // [bbox_blocks][6]
+    int sort_passes;
+    TreeMeta *meta;            // [nsub]
+    TreeTotals *totals;
+    float *bbox_part;          // [nsub][bbox_blocks][6]
     unsigned long long *keyA, *keyB;
-    unsigned *valA, *valB;     // permutation (original index of sorted point)
-    unsigned *hist;            // [256][sort_blocks]
+    unsigned *valA, *valB;     // ping-pong buffers of the sort
+    const unsigned long long *K;  // sorted keys (one of keyA / keyB)
+    const unsigned *perm;      // original index of each sorted point
+    unsigned *hist;            // [256][sort_blocks] digit-major counts, then offsets
     unsigned *scan_part;       // block sums of the generic scan
     float4 *Qs, *Ps;           // sorted points / momenta (FP32)
     unsigned char *lvl;        // [n-1] split level of each boundary
@@ -62,32 +89,30 @@ struct TreeBufs {
     unsigned *rank_bnd;        // [n] boundary of internal rank r
     unsigned *nchild;          // [n] children of internal rank r
     unsigned *cstart;          // [n] exclusive scan of nchild
-    int *node_of;              // [n] node id of internal rank r
-    int *parent_rank;          // [2n] internal rank of a node's parent (-1 root)
-    unsigned *counter;         // [2n] bottom-up arrival counters (adjoint sums)
-    int *node_start;           // [2n] first sorted point of each node
+    int *node_start;           // [2n + nsub] first sorted point of each node
     char *chunk0, *chunk1;     // range summaries of 64 and 4096 sorted points
-    double *nsum;              // [2n][6] FP64 sums of q and p per node
-    BhNode *nodes;             // [2n]
-    double *adj;               // [2n][6] per-node sums of alpha, beta (backward stage)
+    double *nsum;              // [nodes][6] FP64 sums of q and p per node
+    BhNode *nodes;             // [2n + nsub]
+    double *adj;               // [nodes][6] per-node sums of alpha, beta (backward stage)
     // traversal work split (see traverse.hip)
     char *list;                // [groups][kListCap] leaf entries of each group
     int *list_n;               // [groups] entries used
     double *part;              // [1 + chunks][groups * 64][6] partial (v, a) sums
 };
 // Sizes of the traversal's work-split buffers (defined in traverse.hip).
-size_t traverse_list_bytes(int64_t n);
-size_t traverse_part_doubles(int64_t n);
+size_t traverse_list_bytes(int64_t groups);
+size_t traverse_part_doubles(int64_t groups);
+// One tree over n points.
 void carve_tree(Arena &a, int64_t n, TreeBufs &t);
+// A forest of nsub sets with n points in total and `groups` traversal
+// groups; the caller sets t.seg and t.gtab before building.
+void carve_forest(Arena &a, int64_t n, int nsub, int64_t groups, int64_t max_set, TreeBufs &t);
 
-// Builds the tree of (q, p) (float [n][3]) into t.  `status` (nullable) is an
-// int on the device set to 1 when a coordinate is not finite.
+// Builds the tree (or forest) of (q, p) (float [n][3]) into t.  `status`
+// (nullable) is an int on the device set to 1 when a coordinate is not
+// finite.
 gs_status build_tree(const float *q, const float *p, int64_t n, int leaf_cap, TreeBufs &t,
                      int *status, hipStream_t s);
-
-// Adds FP64 node sums of per-point vectors (alpha, beta; [n][3] each, original
-// order) into t.adj, bottom-up over the built tree.
-gs_status tree_adjoint_sums(const double *alpha, const double *beta, TreeBufs &t, hipStream_t s);
 
 // Traversal parameters (FP64 decision thresholds as in the definition).
 struct BhParams {
@@ -136,9 +161,10 @@ __device__ __forceinline__ bool decide(const BhNode &nd, double x, double y, dou
 
 // Forward traversal.  Writes (v, a) for every point in original order: as FP32
 // into dq/dp when they are non-null, else it advances the FP64 state
-// (Sq += dt v, Sp += dt a), refreshes the FP32 copies q32/p32 and adds
-// p . v per block into Hpart (nullable).  counters (4 x u64, zeroed by the
-// build) receive exact pairs, monopoles and node visits.
+// (Sq += dt v, Sp += dt a), refreshes the FP32 copies q32/p32 and writes
+// the sum of p . v of every traversal group into Hpart[group] (nullable).
+// counters (zeroed by the caller) receive exact pairs, monopoles, node
+// visits and the wave statistics.
 struct TraverseOut {
     float *dq, *dp;                    // RHS mode
     double *Sq, *Sp;                   // shooting mode
@@ -159,18 +185,23 @@ gs_status launch_bh_traverse(const TreeBufs &t, const BhParams &bp, bool with_a,
 // same 64 / 4096-point range summaries as the node statistics.
 gs_status tree_range_sums(const float4 *A, const float4 *B, TreeBufs &t, double *out,
                           hipStream_t s);
-int traverse_blocks(int64_t n);
 
 struct ShootBhBufs {
     TreeBufs tree;
     double *Sq, *Sp;   // FP64 state [n][3]
     float *q32, *p32;  // FP32 copies [n][3]
-    double *Hpart;
+    double *Hpart;     // [nt + 1][groups]
+    const int *gseg;   // [nsub + 1] group range of each set (nullable: one set)
 };
 ShootBhBufs layout_shoot_bh(Arena &a, int64_t n, int nt);
+// The same for a forest; the caller sets tree.seg, tree.gtab and gseg.
+ShootBhBufs layout_shoot_forest(Arena &a, int64_t n, int nsub, int64_t groups, int64_t max_set,
+                                int nt);
 
 gs_status rhs_bh(const float *q, const float *p, int64_t n, const gs_params &prm, float *dq,
                  float *dp, TreeBufs &t, char *ws, hipStream_t s);
+// Shooting of one set, or of every set of a forest (H then holds nsub rows of
+// nt + 1 energies).
 gs_status shoot_bh(const float *q0, const float *p0, int64_t n, const gs_params &prm, float *q1,
                    float *p1, double *H, ShootBhBufs &b, char *ws, hipStream_t s);
 

@@ -3,9 +3,11 @@
 //
 // Launch sequence of one build (no host synchronisation, so it can be
 // captured in a graph):
-//   bbox_partial -> bbox_final     tight box of all points, E, 2^21/E
+//   bbox_partial -> bbox_final     tight box of every set, E, 2^21/E
 //   morton                         63-bit keys: 21 bits per axis, x highest
 //   8 x (hist, scan, scatter)      stable LSD radix sort of (key, index)
+//   1-2 x (hist, scan, scatter)    (forest only) stable passes on the set
+//                                  index, so each set is sorted in its range
 //   gather                         sorted FP32 copies of q, p
 //   boundaries                     split level of every pair of neighbours and
 //                                  the internal-node flag of its cell
@@ -24,6 +26,12 @@
 // the non-empty level-(L+1) sub-cells: a child with <= leaf_cap points, or
 // whose points share one key, is a leaf; otherwise it is the internal node
 // represented by its own first split.
+//
+// Forest.  Independent point sets (subjects) given as index ranges of one
+// array are built in the same launches: every set gets its own root cube,
+// the sort keeps each set in its own index range, the split searches stay
+// inside the set's range, and node s is the root of set s.  Each tree is
+// exactly the tree of its set built alone.
 #include <hip/hip_runtime.h>
 
 #include "tree.h"
@@ -42,13 +50,31 @@ constexpr int kChunk = 64;                                 // points per range s
 
 inline unsigned nblk(int64_t n, int b = kBlock) { return (unsigned)((n + b - 1) / b); }
 
+// Set of index i: the largest s with seg[s] <= i (seg is non-decreasing, so
+// this is the set whose range holds i even when empty sets precede it).
+__device__ inline int set_of(const long long *__restrict__ seg, int nsub, int64_t i) {
+    if (!seg) return 0;
+    int lo = 0, hi = nsub - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (seg[mid] <= i)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
 // ---------------------------------------------------------------- bbox
+// grid (blocks per set, sets); partials [set][block][6]
 __global__ __launch_bounds__(256) void k_bbox_partial(const float *__restrict__ q, int64_t n,
+                                                      const long long *__restrict__ seg,
                                                       float *__restrict__ part) {
     __shared__ float red[6][256];
     float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     float bad = 0.f;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+    const int64_t a = seg ? seg[blockIdx.y] : 0, b = seg ? seg[blockIdx.y + 1] : n;
+    for (int64_t i = a + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < b;
          i += (int64_t)gridDim.x * blockDim.x) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -78,21 +104,34 @@ __global__ __launch_bounds__(256) void k_bbox_partial(const float *__restrict__ 
         }
         __syncthreads();
     }
-    if (threadIdx.x < 6) part[blockIdx.x * 6 + threadIdx.x] = red[threadIdx.x][0];
+    if (threadIdx.x < 6)
+        part[((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * 6 + threadIdx.x] = red[threadIdx.x][0];
 }
 
-__global__ void k_bbox_final(const float *__restrict__ part, int nb, TreeMeta *__restrict__ meta,
-                             int *__restrict__ status) {
-    if (threadIdx.x != 0) return;
+// One wave per set: reduces its nb partial boxes.
+__global__ __launch_bounds__(64) void k_bbox_final(const float *__restrict__ part, int nb,
+                                                   TreeMeta *__restrict__ meta_all,
+                                                   int *__restrict__ status) {
+    const int lane = threadIdx.x;
+    const float *ps = part + (int64_t)blockIdx.x * nb * 6;
     float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     int bad = 0;
-    for (int b = 0; b < nb; ++b) {
-        if (isnan(part[6 * b])) bad = 1;
+    for (int b = lane; b < nb; b += 64) {
+        if (isnan(ps[6 * b])) bad = 1;
         for (int c = 0; c < 3; ++c) {
-            lo[c] = fminf(lo[c], part[6 * b + c]);
-            hi[c] = fmaxf(hi[c], part[6 * b + 3 + c]);
+            lo[c] = fminf(lo[c], ps[6 * b + c]);
+            hi[c] = fmaxf(hi[c], ps[6 * b + 3 + c]);
         }
     }
+    for (int off = 32; off > 0; off >>= 1) {
+        bad |= __shfl_xor(bad, off, 64);
+        for (int c = 0; c < 3; ++c) {
+            lo[c] = fminf(lo[c], __shfl_xor(lo[c], off, 64));
+            hi[c] = fmaxf(hi[c], __shfl_xor(hi[c], off, 64));
+        }
+    }
+    if (lane != 0) return;
+    TreeMeta *meta = meta_all + blockIdx.x;
     double e = 0.0;
     for (int c = 0; c < 3; ++c) {
         meta->lo[c] = lo[c];
@@ -131,11 +170,13 @@ __device__ inline unsigned quantize(float x, float lo, double scale) {
 }
 
 __global__ __launch_bounds__(256) void k_morton(const float *__restrict__ q, int64_t n,
-                                                const TreeMeta *__restrict__ meta,
+                                                const long long *__restrict__ seg, int nsub,
+                                                const TreeMeta *__restrict__ meta_all,
                                                 u64 *__restrict__ keys,
                                                 unsigned *__restrict__ vals) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    const TreeMeta *meta = meta_all + set_of(seg, nsub, i);
     const double sc = meta->scale;
     const unsigned cx = quantize(q[3 * i], meta->lo[0], sc);
     const unsigned cy = quantize(q[3 * i + 1], meta->lo[1], sc);
@@ -145,48 +186,47 @@ __global__ __launch_bounds__(256) void k_morton(const float *__restrict__ q, int
 }
 
 // ---------------------------------------------------------------- radix sort
-__global__ __launch_bounds__(kSortThreads) void k_rs_hist(const u64 *__restrict__ keys, int64_t n,
-                                                          int shift, int nb,
-                                                          unsigned *__restrict__ hist) {
+// Digit of a pass: shift < 64 selects 8 bits of the key; shift >= 64 selects
+// 8 bits of the set index of the point's original position.
+__device__ inline unsigned rs_digit(u64 key, unsigned val, int shift,
+                                    const long long *__restrict__ seg, int nsub) {
+    if (shift < 64) return (unsigned)(key >> shift) & 255u;
+    return ((unsigned)set_of(seg, nsub, (int64_t)val) >> (shift - 64)) & 255u;
+}
+
+// Per-block digit counts, digit-major (hist[d * nb + block]), so that one
+// exclusive scan gives every (digit, block) its output offset.
+__global__ __launch_bounds__(kSortThreads) void k_rs_hist(const u64 *__restrict__ keys,
+                                                          const unsigned *__restrict__ vals,
+                                                          int64_t n, int shift, int nb,
+                                                          const long long *__restrict__ seg,
+                                                          int nsub, unsigned *__restrict__ hist) {
     __shared__ unsigned h[256];
     h[threadIdx.x] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
     for (int r = 0; r < kSortPerThread; ++r) {
         const int64_t i = base + r * kSortThreads + threadIdx.x;
-        if (i < n) atomicAdd(&h[(unsigned)(keys[i] >> shift) & 255u], 1u);
+        if (i < n) {
+            const unsigned d = shift < 64 ? (unsigned)(keys[i] >> shift) & 255u
+                                          : rs_digit(0ull, vals[i], shift, seg, nsub);
+            atomicAdd(&h[d], 1u);
+        }
     }
     __syncthreads();
-    hist[(int64_t)blockIdx.x * 256 + threadIdx.x] = h[threadIdx.x];
+    hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
 }
 
 __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(
     const u64 *__restrict__ kin, const unsigned *__restrict__ vin, u64 *__restrict__ kout,
-    unsigned *__restrict__ vout, int64_t n, int shift, int nb, const unsigned *__restrict__ hist) {
+    unsigned *__restrict__ vout, int64_t n, int shift, int nb, const long long *__restrict__ seg,
+    int nsub, const unsigned *__restrict__ offs) {
     __shared__ unsigned base[256];
     __shared__ unsigned run[256];
     __shared__ unsigned wcnt[kSortThreads / 64][256];
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    // global offset of (digit t, this block): all keys with a smaller digit
-    // plus keys with digit t in earlier blocks (histograms are block-major)
-    {
-        unsigned before = 0, total = 0;
-        for (int b = 0; b < nb; ++b) {
-            const unsigned h = hist[(int64_t)b * 256 + t];
-            total += h;
-            if (b < (int)blockIdx.x) before += h;
-        }
-        run[t] = total;
-        __syncthreads();
-        for (int off = 1; off < 256; off <<= 1) {
-            const unsigned v = t >= off ? run[t - off] : 0u;
-            __syncthreads();
-            run[t] += v;
-            __syncthreads();
-        }
-        base[t] = run[t] - total + before;
-        __syncthreads();
-    }
+    // output offset of (digit t, this block) from the scanned histograms
+    base[t] = offs[(int64_t)t * nb + blockIdx.x];
     run[t] = 0;
     for (int w = 0; w < kSortThreads / 64; ++w) wcnt[w][t] = 0;
     __syncthreads();
@@ -197,7 +237,7 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(
         const bool valid = i < n;
         u64 key = valid ? kin[i] : 0ull;
         const unsigned val = valid ? vin[i] : 0u;
-        const unsigned d = (unsigned)(key >> shift) & 255u;
+        const unsigned d = valid ? rs_digit(key, val, shift, seg, nsub) : 0u;
         // lanes of this wave holding the same digit (stable by lane order)
         u64 peers = __ballot(valid);
 #pragma unroll
@@ -324,13 +364,21 @@ __device__ inline int64_t lower_bound(const u64 *__restrict__ K, int64_t lo, int
 }
 
 __global__ __launch_bounds__(256) void k_boundaries(const u64 *__restrict__ K, int64_t n,
+                                                    const long long *__restrict__ seg, int nsub,
                                                     int leaf_cap, unsigned char *__restrict__ lvl,
                                                     unsigned *__restrict__ flag,
                                                     unsigned *__restrict__ bs,
                                                     unsigned *__restrict__ be) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    if (i == n - 1) {  // no boundary after the last point
+    // the range [a0, b0) of the set holding point i
+    int64_t a0 = 0, b0 = n;
+    if (seg) {
+        const int si = set_of(seg, nsub, i);
+        a0 = seg[si];
+        b0 = seg[si + 1];
+    }
+    if (i == b0 - 1) {  // no boundary after the last point of a set
         flag[i] = 0;
         return;
     }
@@ -343,9 +391,9 @@ __global__ __launch_bounds__(256) void k_boundaries(const u64 *__restrict__ K, i
         const u64 pre = L == 0 ? 0ull : (a >> sh);
         const u64 cell_lo = L == 0 ? 0ull : (pre << sh);
         const u64 cell_hi = L == 0 ? ~0ull : (((pre + 1) << sh) - 1);
-        const int64_t s = lower_bound(K, 0, i, cell_lo);
+        const int64_t s = lower_bound(K, a0, i, cell_lo);
         // end: first index after i + 1 with a key above the cell
-        int64_t lo = i + 1, hi = n;
+        int64_t lo = i + 1, hi = b0;
         while (lo < hi) {
             const int64_t mid = (lo + hi) >> 1;
             if (K[mid] <= cell_hi)
@@ -419,40 +467,45 @@ __device__ inline void zero_stats(BhNode &nd) {
     nd.px = nd.py = nd.pz = 0.f;
 }
 
-// Root record.  Runs as one thread after the scans.
-__global__ void k_root(const u64 *__restrict__ K, int64_t n, int leaf_cap,
-                       const unsigned *__restrict__ rank, const unsigned *__restrict__ nchild,
-                       const unsigned *__restrict__ cstart, TreeMeta *__restrict__ meta,
-                       BhNode *__restrict__ nodes, int *__restrict__ node_of,
-                       int *__restrict__ parent_rank, int *__restrict__ node_start) {
-    if (threadIdx.x != 0) return;
+// Root records: one thread per set, after the scans.  Node s is the root of
+// set s; children of internal rank r start at node nsub + cstart[r].
+__global__ __launch_bounds__(64) void k_roots(const u64 *__restrict__ K, int64_t n,
+                                              const long long *__restrict__ seg, int nsub,
+                                              int leaf_cap, const unsigned *__restrict__ rank,
+                                              const unsigned *__restrict__ nchild,
+                                              const unsigned *__restrict__ cstart,
+                                              TreeTotals *__restrict__ totals,
+                                              TreeMeta *__restrict__ meta,
+                                              BhNode *__restrict__ nodes,
+                                              int *__restrict__ node_start) {
+    const int si = blockIdx.x * blockDim.x + threadIdx.x;
+    if (si >= nsub) return;
+    const int64_t a = seg ? seg[si] : 0, b = seg ? seg[si + 1] : n;
     BhNode nd;
     zero_stats(nd);
-    nd.n = (int)n;
-    const unsigned m = meta->n_internal;
-    if (n <= leaf_cap || K[0] == K[n - 1] || m == 0) {
-        nd.first = 0;
+    nd.n = (int)(b - a);
+    if (b - a <= leaf_cap || K[a] == K[b - 1]) {
+        nd.first = (int)a;
         nd.nchild = 0;
-        meta->root_leaf = 1;
-        meta->root_rank = -1;
-        meta->n_nodes = 1;
+        meta[si].root_leaf = 1;
+        meta[si].root_rank = -1;
     } else {
-        const int64_t rb = child_rep(K, 0, n);
-        const unsigned r = rank[rb];
-        nd.first = 1 + (int)cstart[r];
+        const unsigned r = rank[child_rep(K, a, b)];
+        nd.first = nsub + (int)cstart[r];
         nd.nchild = (int)nchild[r];
-        node_of[r] = 0;
-        meta->root_leaf = 0;
-        meta->root_rank = (int)r;
-        meta->n_nodes = 1 + (int)(cstart[m - 1] + nchild[m - 1]);
+        meta[si].root_leaf = 0;
+        meta[si].root_rank = (int)r;
     }
-    nodes[0] = nd;
-    parent_rank[0] = -1;
-    node_start[0] = 0;
+    nodes[si] = nd;
+    node_start[si] = (int)a;
+    if (si == 0) {
+        const int m = totals->n_internal;
+        totals->n_nodes = nsub + (m > 0 ? (int)(cstart[m - 1] + nchild[m - 1]) : 0);
+    }
 }
 
-__global__ __launch_bounds__(256) void k_nodes(const u64 *__restrict__ K, int leaf_cap,
-                                               const TreeMeta *__restrict__ meta,
+__global__ __launch_bounds__(256) void k_nodes(const u64 *__restrict__ K, int leaf_cap, int nsub,
+                                               const TreeTotals *__restrict__ totals,
                                                const unsigned char *__restrict__ lvl,
                                                const unsigned *__restrict__ rank,
                                                const unsigned *__restrict__ bs,
@@ -460,15 +513,14 @@ __global__ __launch_bounds__(256) void k_nodes(const u64 *__restrict__ K, int le
                                                const unsigned *__restrict__ rank_bnd,
                                                const unsigned *__restrict__ nchild,
                                                const unsigned *__restrict__ cstart,
-                                               BhNode *__restrict__ nodes, int *__restrict__ node_of,
-                                               int *__restrict__ parent_rank,
+                                               BhNode *__restrict__ nodes,
                                                int *__restrict__ node_start) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= meta->n_internal || meta->root_leaf) return;
+    if (r >= totals->n_internal) return;
     const unsigned i = rank_bnd[r];
     unsigned c[9];
     const int cnt = child_runs(K, bs[i], be[i], lvl[i], c);
-    const int base = 1 + (int)cstart[r];
+    const int base = nsub + (int)cstart[r];
     for (int k = 0; k < cnt; ++k) {
         const int id = base + k;
         const int64_t a = c[k], b = c[k + 1];
@@ -480,12 +532,10 @@ __global__ __launch_bounds__(256) void k_nodes(const u64 *__restrict__ K, int le
             nd.nchild = 0;
         } else {
             const unsigned rc = rank[child_rep(K, a, b)];
-            nd.first = 1 + (int)cstart[rc];
+            nd.first = nsub + (int)cstart[rc];
             nd.nchild = (int)nchild[rc];
-            node_of[rc] = id;
         }
         nodes[id] = nd;
-        parent_rank[id] = (int)r;
         node_start[id] = (int)a;
     }
 }
@@ -493,7 +543,7 @@ __global__ __launch_bounds__(256) void k_nodes(const u64 *__restrict__ K, int le
 // Statistics of a node from FP64 sums, box and count.
 __device__ inline void finish_node(BhNode &nd, const double *sum, const float *lo,
                                    const float *hi) {
-    const double inv = 1.0 / (double)nd.n;
+    const double inv = nd.n > 0 ? 1.0 / (double)nd.n : 0.0;  // n == 0: an empty set's root
     nd.cx = sum[0] * inv;
     nd.cy = sum[1] * inv;
     nd.cz = sum[2] * inv;
@@ -598,12 +648,12 @@ __global__ __launch_bounds__(256) void k_node_stats(const float4 *__restrict__ Q
                                                     const float4 *__restrict__ Ps,
                                                     const RangeStat *__restrict__ c0,
                                                     const RangeStat *__restrict__ c1,
-                                                    const TreeMeta *__restrict__ meta,
+                                                    const TreeTotals *__restrict__ totals,
                                                     const int *__restrict__ node_start,
                                                     BhNode *__restrict__ nodes,
                                                     double *__restrict__ nsum) {
     const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= meta->n_nodes) return;
+    if (id >= totals->n_nodes) return;
     BhNode nd = nodes[id];
     int64_t a = node_start[id];
     const int64_t b = a + nd.n;
@@ -637,59 +687,17 @@ __global__ __launch_bounds__(256) void k_node_stats(const float4 *__restrict__ Q
     for (int c = 0; c < 6; ++c) nsum[6 * id + c] = r.s[c];
 }
 
-// Node sums of per-point adjoint vectors (original order, [n][3] FP64).
-__global__ __launch_bounds__(256) void k_adj_sums(const double *__restrict__ al,
-                                                  const double *__restrict__ be,
-                                                  const unsigned *__restrict__ perm,
-                                                  const TreeMeta *__restrict__ meta,
-                                                  const BhNode *__restrict__ nodes,
-                                                  double *__restrict__ adj,
-                                                  const int *__restrict__ node_of,
-                                                  const int *__restrict__ parent_rank,
-                                                  unsigned *__restrict__ counter) {
-    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= meta->n_nodes) return;
-    const BhNode nd = nodes[id];
-    if (nd.nchild != 0) return;
-    double sum[6] = {0, 0, 0, 0, 0, 0};
-    for (int j = nd.first; j < nd.first + nd.n; ++j) {
-        const int64_t i = perm[j];
-        for (int c = 0; c < 3; ++c) {
-            sum[c] += al[3 * i + c];
-            sum[3 + c] += be[3 * i + c];
-        }
-    }
-    for (int c = 0; c < 6; ++c) adj[6 * id + c] = sum[c];
-    int cur = (int)id;
-    while (true) {
-        const int pr = parent_rank[cur];
-        if (pr < 0) break;
-        const int par = node_of[pr];
-        __threadfence();
-        const unsigned old = __hip_atomic_fetch_add(&counter[par], 1u, __ATOMIC_ACQ_REL,
-                                                    __HIP_MEMORY_SCOPE_AGENT);
-        const BhNode pn = nodes[par];
-        if (old + 1 != (unsigned)pn.nchild) break;
-        __threadfence();
-        double ps[6] = {0, 0, 0, 0, 0, 0};
-        for (int k = 0; k < pn.nchild; ++k)
-            for (int c = 0; c < 6; ++c) ps[c] += adj[6 * (pn.first + k) + c];
-        for (int c = 0; c < 6; ++c) adj[6 * par + c] = ps[c];
-        cur = par;
-    }
-}
-
 // Node sums of two fields over node ranges (the sums part of k_node_stats).
 __global__ __launch_bounds__(256) void k_node_sums(const float4 *__restrict__ A,
                                                    const float4 *__restrict__ B,
                                                    const RangeStat *__restrict__ c0,
                                                    const RangeStat *__restrict__ c1,
-                                                   const TreeMeta *__restrict__ meta,
+                                                   const TreeTotals *__restrict__ totals,
                                                    const int *__restrict__ node_start,
                                                    const BhNode *__restrict__ nodes,
                                                    double *__restrict__ out) {
     const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= meta->n_nodes) return;
+    if (id >= totals->n_nodes) return;
     int64_t a = node_start[id];
     const int64_t b = a + nodes[id].n;
     RangeStat r;
@@ -718,11 +726,6 @@ __global__ __launch_bounds__(256) void k_node_sums(const float4 *__restrict__ A,
     for (int c = 0; c < 6; ++c) out[6 * id + c] = r.s[c];
 }
 
-__global__ __launch_bounds__(256) void k_zero_u32(unsigned *__restrict__ x, int64_t n) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) x[i] = 0u;
-}
-
 gs_status scan_u32(const unsigned *in, unsigned *out, int64_t n, unsigned *part, unsigned *total,
                    hipStream_t s) {
     const unsigned nb = (unsigned)((n + kScanTile - 1) / kScanTile);
@@ -735,19 +738,31 @@ gs_status scan_u32(const unsigned *in, unsigned *out, int64_t n, unsigned *part,
 }  // namespace
 
 // ---------------------------------------------------------------- host side
-void carve_tree(Arena &a, int64_t n, TreeBufs &t) {
+void carve_forest(Arena &a, int64_t n, int nsub, int64_t groups, int64_t max_set, TreeBufs &t) {
     const int64_t m = n > 1 ? n : 1;
+    const int64_t ms = max_set > 1 ? max_set : 1;
+    const int64_t g = groups > 1 ? groups : 1;
+    const int64_t nodes = 2 * m + nsub;
     t.n = n;
-    t.bbox_blocks = (int)((m + 2047) / 2048 < 1024 ? (m + 2047) / 2048 : 1024);
+    t.nsub = nsub;
+    t.seg = nullptr;
+    t.gtab = nullptr;
+    t.groups = groups;
+    t.bbox_blocks = (int)((ms + 2047) / 2048 < 1024 ? (ms + 2047) / 2048 : 1024);
     t.sort_blocks = (int)((m + kSortTile - 1) / kSortTile);
-    t.meta = a.take<TreeMeta>(1);
-    t.bbox_part = a.take<float>(6 * (size_t)t.bbox_blocks);
+    t.sort_passes = 8 + (nsub > 1 ? (nsub > 256 ? 2 : 1) : 0);
+    t.meta = a.take<TreeMeta>(nsub);
+    t.totals = a.take<TreeTotals>(1);
+    t.bbox_part = a.take<float>(6 * (size_t)t.bbox_blocks * nsub);
     t.keyA = a.take<u64>(m);
     t.keyB = a.take<u64>(m);
     t.valA = a.take<unsigned>(m);
     t.valB = a.take<unsigned>(m);
+    t.K = (t.sort_passes & 1) ? t.keyB : t.keyA;
+    t.perm = (t.sort_passes & 1) ? t.valB : t.valA;
     t.hist = a.take<unsigned>(256 * (size_t)t.sort_blocks);
-    t.scan_part = a.take<unsigned>((m + kScanTile - 1) / kScanTile + 1);
+    const int64_t scan_n = m > 256 * (int64_t)t.sort_blocks ? m : 256 * (int64_t)t.sort_blocks;
+    t.scan_part = a.take<unsigned>((scan_n + kScanTile - 1) / kScanTile + 1);
     t.Qs = a.take<float4>(m);
     t.Ps = a.take<float4>(m);
     t.lvl = a.take<unsigned char>(m);
@@ -758,37 +773,41 @@ void carve_tree(Arena &a, int64_t n, TreeBufs &t) {
     t.rank_bnd = a.take<unsigned>(m);
     t.nchild = a.take<unsigned>(m);
     t.cstart = a.take<unsigned>(m);
-    t.node_of = a.take<int>(m);
-    t.parent_rank = a.take<int>(2 * m);
-    t.counter = a.take<unsigned>(2 * m);
-    t.node_start = a.take<int>(2 * m);
+    t.node_start = a.take<int>(nodes);
     t.chunk0 = reinterpret_cast<char *>(a.take<RangeStat>((m + kChunk - 1) / kChunk));
     t.chunk1 = reinterpret_cast<char *>(
         a.take<RangeStat>((m + kChunk * kChunk - 1) / (kChunk * kChunk)));
-    t.nsum = a.take<double>(12 * m);
-    t.nodes = a.take<BhNode>(2 * m);
-    t.adj = a.take<double>(12 * m);
-    t.list = a.take<char>(traverse_list_bytes(m));
-    t.list_n = a.take<int>((m + 63) / 64);
-    t.part = a.take<double>(traverse_part_doubles(m));
+    t.nsum = a.take<double>(6 * nodes);
+    t.nodes = a.take<BhNode>(nodes);
+    t.adj = a.take<double>(6 * nodes);
+    t.list = a.take<char>(traverse_list_bytes(g));
+    t.list_n = a.take<int>(g);
+    t.part = a.take<double>(traverse_part_doubles(g));
 }
+
+void carve_tree(Arena &a, int64_t n, TreeBufs &t) { carve_forest(a, n, 1, (n + 63) / 64, n, t); }
 
 gs_status build_tree(const float *q, const float *p, int64_t n, int leaf_cap, TreeBufs &t,
                      int *status, hipStream_t s) {
     timing_begin(KIND_TREE, s);
-    hipLaunchKernelGGL(k_bbox_partial, dim3(t.bbox_blocks), dim3(256), 0, s, q, n, t.bbox_part);
-    hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(64), 0, s, t.bbox_part, t.bbox_blocks, t.meta,
-                       status);
-    hipLaunchKernelGGL(k_morton, dim3(nblk(n)), dim3(256), 0, s, q, n, t.meta, t.keyA, t.valA);
+    const int nsub = t.nsub;
+    hipLaunchKernelGGL(k_bbox_partial, dim3(t.bbox_blocks, nsub), dim3(256), 0, s, q, n, t.seg,
+                       t.bbox_part);
+    hipLaunchKernelGGL(k_bbox_final, dim3(nsub), dim3(64), 0, s, t.bbox_part, t.bbox_blocks,
+                       t.meta, status);
+    hipLaunchKernelGGL(k_morton, dim3(nblk(n)), dim3(256), 0, s, q, n, t.seg, nsub, t.meta,
+                       t.keyA, t.valA);
     GS_LAUNCH_CHECK("bbox/morton");
     u64 *ki = t.keyA, *ko = t.keyB;
     unsigned *vi = t.valA, *vo = t.valB;
     const int nb = t.sort_blocks;
-    for (int pass = 0; pass < 8; ++pass) {
-        const int shift = 8 * pass;
-        hipLaunchKernelGGL(k_rs_hist, dim3(nb), dim3(kSortThreads), 0, s, ki, n, shift, nb, t.hist);
+    for (int pass = 0; pass < t.sort_passes; ++pass) {
+        const int shift = 8 * pass;  // passes 8, 9: the set index
+        hipLaunchKernelGGL(k_rs_hist, dim3(nb), dim3(kSortThreads), 0, s, ki, vi, n, shift, nb,
+                           t.seg, nsub, t.hist);
+        GS_TRY(scan_u32(t.hist, t.hist, 256 * (int64_t)nb, t.scan_part, nullptr, s));
         hipLaunchKernelGGL(k_rs_scatter, dim3(nb), dim3(kSortThreads), 0, s, ki, vi, ko, vo, n,
-                           shift, nb, t.hist);
+                           shift, nb, t.seg, nsub, t.hist);
         u64 *tk = ki;
         ki = ko;
         ko = tk;
@@ -797,14 +816,12 @@ gs_status build_tree(const float *q, const float *p, int64_t n, int leaf_cap, Tr
         vo = tv;
     }
     GS_LAUNCH_CHECK("radix sort");
-    // after an even number of passes the sorted data is back in keyA/valA
-    const u64 *K = t.keyA;
-    const unsigned *perm = t.valA;
-    hipLaunchKernelGGL(k_gather, dim3(nblk(n)), dim3(256), 0, s, q, p, perm, n, t.Qs, t.Ps);
-    hipLaunchKernelGGL(k_boundaries, dim3(nblk(n)), dim3(256), 0, s, K, n, leaf_cap, t.lvl,
-                       t.flag, t.bnd_s, t.bnd_e);
+    const u64 *K = t.K;  // where the last pass left the sorted data
+    hipLaunchKernelGGL(k_gather, dim3(nblk(n)), dim3(256), 0, s, q, p, t.perm, n, t.Qs, t.Ps);
+    hipLaunchKernelGGL(k_boundaries, dim3(nblk(n)), dim3(256), 0, s, K, n, t.seg, nsub, leaf_cap,
+                       t.lvl, t.flag, t.bnd_s, t.bnd_e);
     GS_LAUNCH_CHECK("boundaries");
-    unsigned *n_internal = reinterpret_cast<unsigned *>(&t.meta->n_internal);
+    unsigned *n_internal = reinterpret_cast<unsigned *>(&t.totals->n_internal);
     GS_TRY(scan_u32(t.flag, t.rank, n, t.scan_part, n_internal, s));
     hipLaunchKernelGGL(k_children, dim3(nblk(n)), dim3(256), 0, s, K, n, t.lvl, t.flag, t.rank,
                        t.bnd_s, t.bnd_e, t.rank_bnd, t.nchild);
@@ -813,30 +830,21 @@ gs_status build_tree(const float *q, const float *p, int64_t n, int leaf_cap, Tr
     // entries whose tail beyond n_internal may hold stale values, which only
     // affects cstart of ranks that do not exist.
     GS_TRY(scan_u32(t.nchild, t.cstart, n > 1 ? n - 1 : 1, t.scan_part, nullptr, s));
-    hipLaunchKernelGGL(k_root, dim3(1), dim3(64), 0, s, K, n, leaf_cap, t.rank, t.nchild,
-                       t.cstart, t.meta, t.nodes, t.node_of, t.parent_rank, t.node_start);
-    hipLaunchKernelGGL(k_nodes, dim3(nblk(n)), dim3(256), 0, s, K, leaf_cap, t.meta, t.lvl,
-                       t.rank, t.bnd_s, t.bnd_e, t.rank_bnd, t.nchild, t.cstart, t.nodes,
-                       t.node_of, t.parent_rank, t.node_start);
+    hipLaunchKernelGGL(k_roots, dim3(nblk(nsub, 64)), dim3(64), 0, s, K, n, t.seg, nsub,
+                       leaf_cap, t.rank, t.nchild, t.cstart, t.totals, t.meta, t.nodes,
+                       t.node_start);
+    hipLaunchKernelGGL(k_nodes, dim3(nblk(n)), dim3(256), 0, s, K, leaf_cap, nsub, t.totals,
+                       t.lvl, t.rank, t.bnd_s, t.bnd_e, t.rank_bnd, t.nchild, t.cstart, t.nodes,
+                       t.node_start);
     const int64_t nc0 = (n + kChunk - 1) / kChunk, nc1 = (nc0 + kChunk - 1) / kChunk;
     RangeStat *c0 = reinterpret_cast<RangeStat *>(t.chunk0);
     RangeStat *c1 = reinterpret_cast<RangeStat *>(t.chunk1);
     hipLaunchKernelGGL(k_chunks0, dim3(nblk(nc0, 4)), dim3(256), 0, s, t.Qs, t.Ps, n, c0, nc0);
     hipLaunchKernelGGL(k_chunks1, dim3(nblk(nc1, 4)), dim3(256), 0, s, c0, nc0, c1, nc1);
-    hipLaunchKernelGGL(k_node_stats, dim3(nblk(2 * n)), dim3(256), 0, s, t.Qs, t.Ps, c0, c1,
-                       t.meta, t.node_start, t.nodes, t.nsum);
+    hipLaunchKernelGGL(k_node_stats, dim3(nblk(2 * n + nsub)), dim3(256), 0, s, t.Qs, t.Ps, c0,
+                       c1, t.totals, t.node_start, t.nodes, t.nsum);
     timing_end(KIND_TREE, s);
     GS_LAUNCH_CHECK("nodes/stats");
-    return GS_OK;
-}
-
-gs_status tree_adjoint_sums(const double *alpha, const double *beta, TreeBufs &t,
-                            hipStream_t s) {
-    const int64_t n = t.n;
-    hipLaunchKernelGGL(k_zero_u32, dim3(nblk(2 * n)), dim3(256), 0, s, t.counter, 2 * n);
-    hipLaunchKernelGGL(k_adj_sums, dim3(nblk(2 * n)), dim3(256), 0, s, alpha, beta, t.valA,
-                       t.meta, t.nodes, t.adj, t.node_of, t.parent_rank, t.counter);
-    GS_LAUNCH_CHECK("adjoint sums");
     return GS_OK;
 }
 
@@ -848,8 +856,8 @@ gs_status tree_range_sums(const float4 *A, const float4 *B, TreeBufs &t, double 
     RangeStat *c1 = reinterpret_cast<RangeStat *>(t.chunk1);
     hipLaunchKernelGGL(k_chunks0, dim3(nblk(nc0, 4)), dim3(256), 0, s, A, B, n, c0, nc0);
     hipLaunchKernelGGL(k_chunks1, dim3(nblk(nc1, 4)), dim3(256), 0, s, c0, nc0, c1, nc1);
-    hipLaunchKernelGGL(k_node_sums, dim3(nblk(2 * n)), dim3(256), 0, s, A, B, c0, c1, t.meta,
-                       t.node_start, t.nodes, out);
+    hipLaunchKernelGGL(k_node_sums, dim3(nblk(2 * n + t.nsub)), dim3(256), 0, s, A, B, c0, c1,
+                       t.totals, t.node_start, t.nodes, out);
     GS_LAUNCH_CHECK("range sums");
     return GS_OK;
 }

@@ -64,6 +64,10 @@ _SIGS = {
                                         _vp, _vp, _sz, _vp]),
     "gs_adjoint_workspace_bytes": (_sz, [_i64, _PP, _i32, _i32]),
     "gs_field": (ctypes.c_int, [_vp, _i64, _vp, _vp, _i64, _PP, _vp, _vp, _sz, _vp]),
+    "gs_batch_workspace_bytes": (_sz, [_vp, _i32, _PP, _i32, _i32]),
+    "gs_rhs_batch": (ctypes.c_int, [_vp, _vp, _vp, _i32, _PP, _i32, _vp, _vp, _vp, _sz, _vp]),
+    "gs_shoot_batch": (ctypes.c_int, [_vp, _vp, _vp, _i32, _PP, _i32, _vp, _vp, _vp, _vp, _sz,
+                                      _vp]),
     "gs_get_status": (ctypes.c_int, [_vp, _vp]),
     "gs_bh_counters": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(ctypes.c_int64)]),
     "gs_kernel_timing": (ctypes.c_int, [_i32]),
@@ -221,6 +225,58 @@ def gs_field(x, q, p, prm: Params):
     _check(lib().gs_field(_ptr(x), x.shape[0], _ptr(q), _ptr(p), q.shape[0], ctypes.byref(prm),
                           _ptr(v), _ptr(ws), ws.numel(), _stream(x.device)))
     return v
+
+
+def _offsets(offsets):
+    """Host int64 array of the set boundaries (list, numpy array or CPU tensor)."""
+    vals = [int(x) for x in (offsets.tolist() if hasattr(offsets, "tolist") else offsets)]
+    if len(vals) < 2:
+        raise GsError(-1, "offsets needs at least two entries")
+    return (ctypes.c_int64 * len(vals))(*vals), len(vals) - 1
+
+
+def gs_batch_workspace_bytes(offsets, prm: Params, method=GS_EXACT, op=GS_OP_RHS) -> int:
+    off, nsub = _offsets(offsets)
+    return int(lib().gs_batch_workspace_bytes(off, nsub, ctypes.byref(prm), method, op))
+
+
+def _batch_workspace(off, nsub, prm, method, op, dev):
+    nbytes = lib().gs_batch_workspace_bytes(off, nsub, ctypes.byref(prm), method, op)
+    if nbytes == 0:
+        raise GsError(-1, "invalid arguments for gs_batch_workspace_bytes: "
+                          + lib().gs_last_error().decode())
+    return torch.empty(nbytes, dtype=torch.uint8, device=dev)
+
+
+def gs_rhs_batch(q, p, offsets, prm: Params, method=GS_EXACT, ws=None, return_ws=False):
+    """(dq, dp) of every set of a batch (rows offsets[s]..offsets[s+1] are set s)."""
+    _pts(q, torch.float32, "q")
+    _pts(p, torch.float32, "p")
+    off, nsub = _offsets(offsets)
+    dq, dp = torch.empty_like(q), torch.empty_like(q)
+    if ws is None:
+        ws = _batch_workspace(off, nsub, prm, method, GS_OP_RHS, q.device)
+    _check(lib().gs_rhs_batch(_ptr(q), _ptr(p), off, nsub, ctypes.byref(prm), method, _ptr(dq),
+                              _ptr(dp), _ptr(ws), ws.numel(), _stream(q.device)))
+    return (dq, dp, ws) if return_ws else (dq, dp)
+
+
+def gs_shoot_batch(q0, p0, offsets, prm: Params, method=GS_EXACT, with_energy=True, ws=None,
+                   return_ws=False):
+    """Shooting of every set of a batch; returns (q1, p1, H) with H float64
+    (nsub, nt + 1) or None."""
+    _pts(q0, torch.float32, "q0")
+    _pts(p0, torch.float32, "p0")
+    off, nsub = _offsets(offsets)
+    q1, p1 = torch.empty_like(q0), torch.empty_like(p0)
+    H = (torch.zeros(nsub, prm.nt + 1, dtype=torch.float64, device=q0.device)
+         if with_energy else None)
+    if ws is None:
+        ws = _batch_workspace(off, nsub, prm, method, GS_OP_SHOOT, q0.device)
+    _check(lib().gs_shoot_batch(_ptr(q0), _ptr(p0), off, nsub, ctypes.byref(prm), method,
+                                _ptr(q1), _ptr(p1), _ptr(H), _ptr(ws), ws.numel(),
+                                _stream(q0.device)))
+    return (q1, p1, H, ws) if return_ws else (q1, p1, H)
 
 
 def gs_get_status(ws) -> int:

@@ -95,3 +95,53 @@ def test_zero_points_is_a_noop():
                  None) == 0
     assert _call("gs_shoot", None, None, 0, ctypes.byref(prm), gs.GS_BH, None, None, None,
                  None, 0, None) == 0
+
+
+def _off(vals):
+    return (ctypes.c_int64 * len(vals))(*vals)
+
+
+def test_batch_workspace_sizes():
+    prm = gs.params(0.05, nt=40, theta=0.5, leaf_cap=16)
+    offs = [0, 5000, 5000, 12000, 40000]
+    for method in (gs.GS_EXACT, gs.GS_BH):
+        rhs = gs.gs_batch_workspace_bytes(offs, prm, method, gs.GS_OP_RHS)
+        sh = gs.gs_batch_workspace_bytes(offs, prm, method, gs.GS_OP_SHOOT)
+        assert 0 < rhs <= sh
+    # a one-set batch needs about what the single-set call needs
+    one = gs.gs_batch_workspace_bytes([0, 20000], prm, gs.GS_BH, gs.GS_OP_SHOOT)
+    single = gs.gs_workspace_bytes(20000, prm, gs.GS_BH, gs.GS_OP_SHOOT)
+    assert abs(one - single) < 0.05 * single
+    assert gs.gs_batch_workspace_bytes([0, 10], prm, gs.GS_EXACT, gs.GS_OP_ADJOINT) == 0
+
+
+@pytest.mark.parametrize("offs,nsub,msg", [
+    ([1, 5, 9], 2, "offsets[0]"),
+    ([0, 9, 5], 2, "non-decreasing"),
+    ([0, 4], 0, "nsub"),
+])
+def test_batch_rejects_bad_offsets(offs, nsub, msg):
+    prm = gs.params(0.1)
+    st = _call("gs_rhs_batch", FAKE, FAKE, _off(offs), nsub, ctypes.byref(prm), gs.GS_EXACT,
+               FAKE, FAKE, FAKE, 1 << 30, None)
+    assert st == -1
+    assert msg in gs.lib().gs_last_error().decode()
+    assert _call("gs_batch_workspace_bytes", _off(offs), nsub, ctypes.byref(prm), gs.GS_EXACT,
+                 gs.GS_OP_RHS) == 0
+
+
+def test_batch_rejects_null_offsets_bad_method_and_small_workspace():
+    prm = gs.params(0.1, nt=4)
+    st = _call("gs_shoot_batch", FAKE, FAKE, None, 1, ctypes.byref(prm), gs.GS_BH, FAKE, FAKE,
+               None, FAKE, 1 << 30, None)
+    assert st == -1
+    st = _call("gs_shoot_batch", FAKE, FAKE, _off([0, 10]), 1, ctypes.byref(prm), 3, FAKE, FAKE,
+               None, FAKE, 1 << 30, None)
+    assert st == -1
+    st = _call("gs_shoot_batch", FAKE, FAKE, _off([0, 10, 30]), 2, ctypes.byref(prm),
+               gs.GS_BH, FAKE, FAKE, None, FAKE, 4096, None)
+    assert st == -2
+    # all sets empty: a no-op that touches nothing
+    st = _call("gs_shoot_batch", None, None, _off([0, 0, 0]), 2, ctypes.byref(prm), gs.GS_BH,
+               None, None, None, None, 0, None)
+    assert st == 0

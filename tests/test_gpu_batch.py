@@ -1,0 +1,189 @@
+"""GPU parity of the batched entry points (independent point sets evaluated in
+shared launches).
+
+Every set of a batch must come out as the same set evaluated alone: against
+the FP64 oracle per set with the single-set bars (rel-L2 1e-5 for one RHS,
+1e-5 for q(1), p(1), 1e-6 for H, identical Barnes-Hut counters summed over
+the sets), and against the single-set GPU calls: the batched Barnes-Hut trees
+are the single-set trees (node sums may be added in another order, so
+results agree to FP64 rounding, not bitwise) and the batched exact sums use
+the same FP32 tiles with other FP64 split boundaries.  The full-size case is
+the 64-subject population (sizes U{5000..40000}, 1.52 M points).
+"""
+import numpy as np
+import pytest
+import torch
+
+from helpers import rel_l2
+from paper_1907_04834_amd import gs
+from paper_1907_04834_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _t(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+
+
+def _np(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _ragged(sizes, seed=70):
+    """Sets of the ellipsoid recipe with the given sizes (0 and 1 allowed)."""
+    out = []
+    for k, n in enumerate(sizes):
+        if n == 0:
+            out.append(W.Workload(f"empty-{k}", np.zeros((0, 3), np.float32),
+                                  np.zeros((0, 3), np.float32), 0.05, 40, "f32"))
+        else:
+            out.append(W.ellipsoid_20k(seed=seed + k, n=n))
+    return out
+
+
+SIZES = [700, 0, 1, 2500, 64, 3, 1333]
+
+
+@pytest.mark.parametrize("method", [gs.GS_EXACT, gs.GS_BH])
+def test_rhs_batch_matches_oracle_per_set(oracle, method):
+    subs = _ragged(SIZES)
+    q, p, off = W.stack(subs)
+    sigma, theta, leaf_cap = 0.05, 0.5, 8
+    prm = gs.params(sigma, theta=theta, leaf_cap=leaf_cap)
+    _say(f"rhs_batch method={method} sizes={SIZES}")
+    dq, dp, ws = gs.gs_rhs_batch(_t(q), _t(p), off, prm, method, return_ws=True)
+    torch.cuda.synchronize()
+    v, a = _np(dq), _np(dp)
+    tot = {"pairs": 0, "monopoles": 0}
+    for s, w in enumerate(subs):
+        lo, hi = off[s], off[s + 1]
+        if hi == lo:
+            continue
+        q64, p64 = w.q0.astype(np.float64), w.p0.astype(np.float64)
+        if method == gs.GS_EXACT:
+            vo, ao = oracle.rhs_exact(q64, p64, sigma)
+        else:
+            vo, ao, c = oracle.rhs_bh(q64, p64, sigma, theta, leaf_cap=leaf_cap)
+            tot["pairs"] += c["pairs"]
+            tot["monopoles"] += c["monopoles"]
+        ev, ea = rel_l2(v[lo:hi], vo), rel_l2(a[lo:hi], ao) if np.any(ao) else 0.0
+        _say(f"  set {s} n={hi - lo}: rel-L2 v {ev:.2e} a {ea:.2e}")
+        assert ev < 1e-5 and ea < 1e-5
+    if method == gs.GS_BH:
+        cnt = gs.gs_bh_counters(ws)
+        _say(f"  counters gpu {cnt} oracle {tot}")
+        assert cnt["pairs"] == tot["pairs"] and cnt["monopoles"] == tot["monopoles"]
+        assert gs.gs_get_status(ws) == 0
+
+
+@pytest.mark.parametrize("method", [gs.GS_EXACT, gs.GS_BH])
+def test_shoot_batch_matches_oracle_per_set(oracle, method):
+    subs = _ragged([900, 1, 0, 1700, 130])
+    q, p, off = W.stack(subs)
+    sigma, nt, theta, leaf_cap = 0.05, 6, 0.5, 4
+    prm = gs.params(sigma, nt=nt, theta=theta, leaf_cap=leaf_cap)
+    _say(f"shoot_batch method={method}")
+    q1, p1, H = gs.gs_shoot_batch(_t(q), _t(p), off, prm, method)
+    torch.cuda.synchronize()
+    q1, p1, H = _np(q1), _np(p1), _np(H)
+    assert H.shape == (len(subs), nt + 1)
+    for s, w in enumerate(subs):
+        lo, hi = off[s], off[s + 1]
+        if hi == lo:
+            assert np.all(H[s] == 0.0)
+            continue
+        kind = "exact" if method == gs.GS_EXACT else "bh"
+        qo, po, Ho = oracle.shoot(w.q0.astype(np.float64), w.p0.astype(np.float64), sigma, nt,
+                                  method=kind, theta=theta, leaf_cap=leaf_cap)
+        eq, ep = rel_l2(q1[lo:hi], qo), rel_l2(p1[lo:hi], po)
+        eh = float(np.max(np.abs(H[s] - Ho)) / np.max(np.abs(Ho)))
+        _say(f"  set {s} n={hi - lo}: q1 {eq:.2e} p1 {ep:.2e} H {eh:.2e}")
+        assert eq < 1e-5 and ep < 1e-5 and eh < 1e-6
+
+
+def _single_vs_batch(subs, prm, method, rhs=False):
+    q, p, off = W.stack(subs)
+    if rhs:
+        out_b = gs.gs_rhs_batch(_t(q), _t(p), off, prm, method)
+    else:
+        out_b = gs.gs_shoot_batch(_t(q), _t(p), off, prm, method)
+    worst = [0.0, 0.0, 0.0]
+    for s, w in enumerate(subs):
+        lo, hi = int(off[s]), int(off[s + 1])
+        if hi == lo:
+            if not rhs:
+                assert np.all(_np(out_b[2][s]) == 0.0)
+            continue
+        if rhs:
+            fn = gs.gs_rhs_exact if method == gs.GS_EXACT else gs.gs_rhs_bh
+            one = fn(_t(w.q0), _t(w.p0), prm)
+        else:
+            one = gs.gs_shoot(_t(w.q0), _t(w.p0), prm, method)
+        for k in range(2):
+            worst[k] = max(worst[k], rel_l2(_np(out_b[k][lo:hi]), _np(one[k])))
+        if not rhs:
+            Hs, Hb = _np(one[2]), _np(out_b[2][s])
+            worst[2] = max(worst[2], float(np.max(np.abs(Hb - Hs)) / np.max(np.abs(Hs))))
+    return worst
+
+
+@pytest.mark.parametrize("method", [gs.GS_EXACT, gs.GS_BH])
+def test_batch_equals_single_calls(method):
+    subs = _ragged([3000, 64, 65, 1, 2049, 0, 5000], seed=90)
+    prm = gs.params(0.05, nt=5, theta=0.5, leaf_cap=16)
+    for rhs in (True, False):
+        worst = _single_vs_batch(subs, prm, method, rhs=rhs)
+        _say(f"batch vs single method={method} rhs={rhs}: {worst}")
+        assert max(worst) < 1e-6
+
+
+def test_population_full_size(oracle):
+    """The 64-subject population: Barnes-Hut and exact batched RHS against the
+    oracle (counters in full; exact rows sampled per subject), batched
+    shootings against single-subject shootings."""
+    subs = W.population()
+    q, p, off = W.stack(subs)
+    n = int(off[-1])
+    sigma, theta, leaf_cap = 0.05, 0.5, 16
+    prm = gs.params(sigma, nt=40, theta=theta, leaf_cap=leaf_cap)
+    _say(f"population: {len(subs)} subjects, {n} points, sum N^2 "
+         f"{float(np.sum(np.diff(off).astype(np.float64) ** 2)):.3e}")
+    qt, pt = _t(q), _t(p)
+    dq, dp, ws = gs.gs_rhs_batch(qt, pt, off, prm, gs.GS_BH, return_ws=True)
+    xv, xa = gs.gs_rhs_batch(qt, pt, off, prm, gs.GS_EXACT)
+    torch.cuda.synchronize()
+    cnt = gs.gs_bh_counters(ws)
+    v, a, xv, xa = _np(dq), _np(dp), _np(xv), _np(xa)
+    rng = np.random.default_rng(11)
+    tot = {"pairs": 0, "monopoles": 0}
+    worst_bh, worst_x = 0.0, 0.0
+    for s, w in enumerate(subs):
+        lo, hi = off[s], off[s + 1]
+        q64, p64 = w.q0.astype(np.float64), w.p0.astype(np.float64)
+        vo, ao, c = oracle.rhs_bh(q64, p64, sigma, theta, leaf_cap=leaf_cap)
+        tot["pairs"] += c["pairs"]
+        tot["monopoles"] += c["monopoles"]
+        worst_bh = max(worst_bh, rel_l2(v[lo:hi], vo), rel_l2(a[lo:hi], ao))
+        idx = np.sort(rng.choice(hi - lo, 48, replace=False))
+        ro_v, ro_a = oracle.rhs_exact_rows(idx, q64, p64, sigma)
+        worst_x = max(worst_x, rel_l2(xv[lo:hi][idx], ro_v), rel_l2(xa[lo:hi][idx], ro_a))
+    _say(f"  BH rel-L2 worst {worst_bh:.2e}; exact sampled rel-L2 worst {worst_x:.2e}")
+    _say(f"  counters gpu {cnt} oracle {tot}")
+    assert worst_bh < 1e-5 and worst_x < 1e-5
+    assert cnt["pairs"] == tot["pairs"] and cnt["monopoles"] == tot["monopoles"]
+    for method in (gs.GS_BH, gs.GS_EXACT):
+        worst = _single_vs_batch(subs, prm, method)
+        _say(f"  shooting batch vs single method={method}: {worst}")
+        assert max(worst) < 1e-6
+    # the flows are well resolved: the energy of every subject stays within a
+    # few percent of H(0) over the 40 Euler steps
+    _, _, H = gs.gs_shoot_batch(qt, pt, off, prm, gs.GS_EXACT)
+    H = _np(H)
+    drift = np.max(np.abs(H - H[:, :1]) / np.abs(H[:, :1]), axis=1)
+    _say(f"  energy drift per subject: max {drift.max():.2e} median {np.median(drift):.2e}")
+    assert drift.max() < 0.05
