@@ -79,6 +79,38 @@ def cpu_baseline(w, theta, leaf_cap, exact_interactions, bh_interactions, target
     }
 
 
+def population_rates(gs, W, torch, dev, theta, leaf_cap):
+    """Batched shooting of the 64-subject population (sizes U{5000..40000},
+    sigma 0.05, 40 steps): one warmup and one timed call per method."""
+    subs = W.population()
+    q, p, off = W.stack(subs)
+    qt, pt = torch.from_numpy(q).to(dev), torch.from_numpy(p).to(dev)
+    n2 = float(np.sum(np.diff(off).astype(np.float64) ** 2))
+    out = {"subjects": len(subs), "points": int(off[-1]), "sum_n2": n2, "nt": subs[0].nt,
+           "sigma": subs[0].sigma}
+    for name, method in (("exact", gs.GS_EXACT), ("bh", gs.GS_BH)):
+        prm = gs.params(subs[0].sigma, nt=subs[0].nt, theta=theta, leaf_cap=leaf_cap)
+        ws = torch.empty(gs.gs_batch_workspace_bytes(off, prm, method, gs.GS_OP_SHOOT),
+                         dtype=torch.uint8, device=dev)
+        gs.gs_shoot_batch(qt, pt, off, prm, method, ws=ws)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        gs.gs_shoot_batch(qt, pt, off, prm, method, ws=ws)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        rec = {"ms_per_batch_shooting": ms, "subject_shootings_per_s": len(subs) / (ms / 1e3)}
+        if method == gs.GS_EXACT:
+            rec["pair_interactions_per_s"] = (subs[0].nt + 1) * n2 / (ms / 1e3)
+        else:
+            c = gs.gs_bh_counters(ws)
+            rec["interactions_per_s"] = (c["pairs"] + c["monopoles"]) / (ms / 1e3)
+            rec["theta"], rec["leaf_cap"] = theta, leaf_cap
+        out[name] = rec
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -88,6 +120,8 @@ def main():
     ap.add_argument("--theta", type=float, default=0.5)
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-targets", type=int, default=100000)
+    ap.add_argument("--population", type=int, default=1,
+                    help="also time batched shooting of the 64-subject population")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -218,6 +252,8 @@ def main():
         "err_vs_fp64": err,
         "wall_seconds_timed": t_wall,
     }
+    if args.population:
+        out["population"] = population_rates(gs, W, torch, dev, args.theta, args.leaf_cap)
     if args.cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.theta, args.leaf_cap,
                                            exact_inter, bh_inter, args.cpu_targets)

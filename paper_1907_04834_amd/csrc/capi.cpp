@@ -414,7 +414,7 @@ gs_status exact_batch_rhs(const float *q, const float *p, const int64_t *off, in
     Batch b;
     layout_batch(a, off, nsub, prm, GS_EXACT, GS_OP_RHS, b);
     GS_TRY(upload_tables(b.img, b.tables, stream));
-    GS_TRY(launch_pack_state_rows(b.xp, b.ex, q, p, stream));
+    GS_TRY(launch_pack_state_rows(b.xp, b.ex, q, p, prm.sigma, stream));
     GS_TRY(launch_exact_items(b.xp, b.ex, prm.sigma, true, stream));
     return launch_combine_rows(b.xp, b.ex, prm.sigma, 0, dq, dp, 0.0, nullptr, stream);
 }
@@ -428,7 +428,7 @@ gs_status exact_batch_shoot(const float *q0, const float *p0, const int64_t *off
     GS_TRY(upload_tables(b.img, b.tables, stream));
     const double dt = 1.0 / prm.nt;
     const size_t nb = b.xp.blocks.size();
-    GS_TRY(launch_pack_state_rows(b.xp, b.ex, q0, p0, stream));
+    GS_TRY(launch_pack_state_rows(b.xp, b.ex, q0, p0, prm.sigma, stream));
     for (int t = 0; t < prm.nt; ++t) {
         GS_TRY(launch_exact_items(b.xp, b.ex, prm.sigma, true, stream));
         GS_TRY(launch_combine_rows(b.xp, b.ex, prm.sigma, 1, nullptr, nullptr, dt,

@@ -100,7 +100,11 @@ __global__ void k_unpack(const float4 *__restrict__ Q, const float4 *__restrict_
 
 // Sums of targets t0 + 64 k (k < T, one lane each) over sources [j0, j1)
 // (a multiple of kTile), written as six FP64 rows of dst (row stride ntgt).
-template <int T, bool WITH_A>
+// With SCALED the positions are stored multiplied by k = sqrt(c),
+// c = log2(e) / (2 sigma^2), so that G = exp2(-|q'_i - q'_j|^2) needs no
+// scaling multiply (negc is then unused) and the a-sums come out multiplied
+// by k.
+template <int T, bool WITH_A, bool SCALED = false>
 __device__ __forceinline__ void pair_sums(const float4 *__restrict__ Qt,
                                           const float4 *__restrict__ Pt, int64_t ntgt,
                                           const float4 *__restrict__ Qs,
@@ -153,9 +157,10 @@ __device__ __forceinline__ void pair_sums(const float4 *__restrict__ Qt,
                     dz[b] = z[k] - qj[b].z;
                 }
 #pragma unroll
-                for (int b = 0; b < B; ++b)
-                    g[b] = __builtin_amdgcn_exp2f((dx[b] * dx[b] + dy[b] * dy[b] + dz[b] * dz[b]) *
-                                                  negc);
+                for (int b = 0; b < B; ++b) {
+                    const float r2 = dx[b] * dx[b] + dy[b] * dy[b] + dz[b] * dz[b];
+                    g[b] = __builtin_amdgcn_exp2f(SCALED ? -r2 : r2 * negc);
+                }
 #pragma unroll
                 for (int b = 0; b < B; ++b) {
                     tv[k][0] += g[b] * pj[b].x;
@@ -210,15 +215,17 @@ __global__ __launch_bounds__(256) void k_exact_pairs(
 }
 
 // Batched sets: block b takes work item b = (first padded target row of 256,
-// source rows [j0, j1) of the same set, partial slot).
+// source rows [j0, j1) of the same set, partial slot).  Positions are stored
+// scaled by sqrt(log2(e) / (2 sigma^2)).
 template <bool WITH_A>
 __global__ __launch_bounds__(256) void k_exact_items(const float4 *__restrict__ Q,
                                                      const float4 *__restrict__ P, int64_t npad,
-                                                     const int4 *__restrict__ items, float negc,
+                                                     const int4 *__restrict__ items,
                                                      double *__restrict__ part) {
     const int4 it = items[blockIdx.x];
     const int64_t t0 = (int64_t)it.x + (threadIdx.x >> 6) * 64 + (threadIdx.x & 63);
-    pair_sums<1, WITH_A>(Q, P, npad, Q, P, t0, it.y, it.z, negc, part + (int64_t)it.w * 6 * npad);
+    pair_sums<1, WITH_A, true>(Q, P, npad, Q, P, t0, it.y, it.z, 0.f,
+                               part + (int64_t)it.w * 6 * npad);
 }
 
 // Same sums with the source tile staged in LDS: every wave reads each source
@@ -548,7 +555,7 @@ __global__ __launch_bounds__(256) void k_reduce_h(const double *__restrict__ Hpa
 __global__ __launch_bounds__(256) void k_pack_state_rows(const float *__restrict__ q,
                                                          const float *__restrict__ p,
                                                          const int4 *__restrict__ blk,
-                                                         double *__restrict__ Sq,
+                                                         double ks, double *__restrict__ Sq,
                                                          double *__restrict__ Sp,
                                                          float4 *__restrict__ Q,
                                                          float4 *__restrict__ P) {
@@ -564,7 +571,7 @@ __global__ __launch_bounds__(256) void k_pack_state_rows(const float *__restrict
         Sp[3 * i] = u;
         Sp[3 * i + 1] = v;
         Sp[3 * i + 2] = w;
-        Q[row] = make_float4(x, y, z, 0.f);
+        Q[row] = make_float4((float)(ks * x), (float)(ks * y), (float)(ks * z), 0.f);
         P[row] = make_float4(u, v, w, 0.f);
     } else {
         // padding: zero momentum, so a padded source adds exactly zero
@@ -573,9 +580,10 @@ __global__ __launch_bounds__(256) void k_pack_state_rows(const float *__restrict
     }
 }
 
+// inv_s2 here is 1 / (k sigma^2): the a-sums were taken on scaled positions.
 __global__ __launch_bounds__(256) void k_combine_rows(const double *__restrict__ part,
                                                       int64_t npad, const int4 *__restrict__ blk,
-                                                      double inv_s2, int mode,
+                                                      double inv_s2, double ks, int mode,
                                                       float *__restrict__ dq,
                                                       float *__restrict__ dp, double dt,
                                                       double *__restrict__ Sq,
@@ -615,7 +623,8 @@ __global__ __launch_bounds__(256) void k_combine_rows(const double *__restrict__
                     Sq[3 * i + c] = q[c];
                     Sp[3 * i + c] = p[c];
                 }
-                Q[row] = make_float4((float)q[0], (float)q[1], (float)q[2], 0.f);
+                Q[row] = make_float4((float)(ks * q[0]), (float)(ks * q[1]), (float)(ks * q[2]),
+                                     0.f);
                 P[row] = make_float4((float)p[0], (float)p[1], (float)p[2], 0.f);
             }
         }
@@ -948,27 +957,30 @@ void carve_exact_batch(Arena &a, const ExactBatchPlan &pl, int nt, ExactBatchBuf
     b.Hpart = a.take<double>((size_t)(nt + 1) * nb);
 }
 
+// k = sqrt(log2(e) / (2 sigma^2)): the items kernel works on k q.
+static double position_scale(double sigma) { return sqrt(kLog2e / (2.0 * sigma * sigma)); }
+
 gs_status launch_pack_state_rows(const ExactBatchPlan &pl, const ExactBatchBufs &b,
-                                 const float *q, const float *p, hipStream_t s) {
+                                 const float *q, const float *p, double sigma, hipStream_t s) {
     if (pl.blocks.empty()) return GS_OK;
     hipLaunchKernelGGL(k_pack_state_rows, dim3((unsigned)pl.blocks.size()), dim3(256), 0, s, q,
-                       p, b.blk, b.Sq, b.Sp, b.Q, b.P);
+                       p, b.blk, position_scale(sigma), b.Sq, b.Sp, b.Q, b.P);
     GS_LAUNCH_CHECK("pack_state_rows");
     return GS_OK;
 }
 
 gs_status launch_exact_items(const ExactBatchPlan &pl, const ExactBatchBufs &b, double sigma,
                              bool with_a, hipStream_t s) {
+    (void)sigma;  // the scale is in the stored positions
     if (pl.items.empty()) return GS_OK;
-    const float negc = (float)(-kLog2e / (2.0 * sigma * sigma));
     const int kind = with_a ? KIND_EXACT : KIND_EXACT_V;
     timing_begin(kind, s);
     if (with_a)
         hipLaunchKernelGGL(k_exact_items<true>, dim3((unsigned)pl.items.size()), dim3(256), 0, s,
-                           b.Q, b.P, pl.npad, b.items, negc, b.part);
+                           b.Q, b.P, pl.npad, b.items, b.part);
     else
         hipLaunchKernelGGL(k_exact_items<false>, dim3((unsigned)pl.items.size()), dim3(256), 0, s,
-                           b.Q, b.P, pl.npad, b.items, negc, b.part);
+                           b.Q, b.P, pl.npad, b.items, b.part);
     timing_end(kind, s);
     GS_LAUNCH_CHECK("exact_items");
     return GS_OK;
@@ -978,9 +990,10 @@ gs_status launch_combine_rows(const ExactBatchPlan &pl, const ExactBatchBufs &b,
                               int mode, float *dq, float *dp, double dt, double *Hpart,
                               hipStream_t s) {
     if (pl.blocks.empty()) return GS_OK;
+    const double ks = position_scale(sigma);
     hipLaunchKernelGGL(k_combine_rows, dim3((unsigned)pl.blocks.size()), dim3(256), 0, s, b.part,
-                       pl.npad, b.blk, 1.0 / (sigma * sigma), mode, dq, dp, dt, b.Sq, b.Sp, b.Q,
-                       b.P, Hpart);
+                       pl.npad, b.blk, 1.0 / (ks * sigma * sigma), ks, mode, dq, dp, dt, b.Sq,
+                       b.Sp, b.Q, b.P, Hpart);
     GS_LAUNCH_CHECK("combine_rows");
     return GS_OK;
 }

@@ -144,7 +144,7 @@ struct ExactBatchPlan {
 };
 ExactBatchPlan plan_exact_batch(const int64_t *offsets, int nsub);
 struct ExactBatchBufs {
-    float4 *Q, *P;                // [npad] packed FP32 state, zero padding
+    float4 *Q, *P;                // [npad] packed FP32 state (scaled positions), zero padding
     double *part;                 // [max_chunks][6][npad]
     double *Sq, *Sp;              // [ntot][3] FP64 state
     double *Hpart;                // [nt + 1][blocks]
@@ -153,8 +153,10 @@ struct ExactBatchBufs {
 };
 // Carves the state and partial buffers (not the tables).
 void carve_exact_batch(Arena &a, const ExactBatchPlan &pl, int nt, ExactBatchBufs &b);
+// Packs the FP64 state and its FP32 copies (positions scaled by
+// sqrt(log2(e) / (2 sigma^2)), zero padding).
 gs_status launch_pack_state_rows(const ExactBatchPlan &pl, const ExactBatchBufs &b,
-                                 const float *q, const float *p, hipStream_t s);
+                                 const float *q, const float *p, double sigma, hipStream_t s);
 gs_status launch_exact_items(const ExactBatchPlan &pl, const ExactBatchBufs &b, double sigma,
                              bool with_a, hipStream_t s);
 // mode 0: (dq, dp) = (v, a); mode 1: energy partials into Hpart (nullable)
