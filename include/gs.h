@@ -199,6 +199,20 @@ gs_status gs_shoot_batch(const float *q0, const float *p0, const int64_t *offset
                          float *p1, double *H, void *ws, size_t ws_bytes,
                          hipStream_t stream);
 
+/* Tuning of the Barnes-Hut leaf capacity for given inputs (one set: offsets
+ * {0, n}, nsub 1; or a batch).  Times one right-hand side for each leaf_cap
+ * in {8, 16, 32, 48, 64} (after a warm-up run, best of two) on `stream`,
+ * waiting for each, and writes the fastest into prm->leaf_cap (other fields
+ * unchanged) and its time in milliseconds into *best_ms (nullable).  Larger
+ * leaves only turn approximated interactions into exact pairs, so the
+ * choice never makes the result less accurate.  dq, dp (DEVICE float[n][3])
+ * receive the trial right-hand sides; the workspace is that of
+ * gs_batch_workspace_bytes(offsets, nsub, prm, GS_BH, GS_OP_RHS) (it does
+ * not depend on leaf_cap).  Synchronous: a set-up call, not a hot-path one. */
+gs_status gs_autotune_leaf_cap(const float *q, const float *p, const int64_t *offsets,
+                               int32_t nsub, gs_params *prm, float *dq, float *dp, void *ws,
+                               size_t ws_bytes, hipStream_t stream, double *best_ms);
+
 /* Waits for `stream` and returns the device-side status word of the last
  * Barnes-Hut call that used this workspace (GS_OK or GS_ERR_NONFINITE). */
 gs_status gs_get_status(const void *ws, hipStream_t stream);

@@ -715,6 +715,57 @@ gs_status gs_shoot_batch(const float *q0, const float *p0, const int64_t *offset
     return shoot_bh(q0, p0, n, *prm, q1, p1, H, b.bh, static_cast<char *>(ws), stream);
 }
 
+gs_status gs_autotune_leaf_cap(const float *q, const float *p, const int64_t *offsets,
+                               int32_t nsub, gs_params *prm, float *dq, float *dp, void *ws,
+                               size_t ws_bytes, hipStream_t stream, double *best_ms) {
+    GS_TRY(check_batch_call(offsets, nsub, prm, GS_BH, false));
+    const int64_t n = offsets[nsub];
+    if (n == 0) return GS_OK;
+    GS_TRY(check_ptrs({q, p, dq, dp}));
+    GS_TRY(check_ws(ws, ws_bytes, measure_batch(offsets, nsub, *prm, GS_BH, GS_OP_RHS)));
+    hipEvent_t e0, e1;
+    GS_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        set_error("autotune: hipEventCreate failed");
+        return GS_ERR_HIP;
+    }
+    static const int caps[] = {8, 16, 32, 48, 64};
+    gs_params trial = *prm;
+    double best = 1e300;
+    int best_cap = prm->leaf_cap;
+    gs_status st = GS_OK;
+    for (int cap : caps) {
+        trial.leaf_cap = cap;
+        float ms_min = 1e30f;
+        for (int rep = 0; rep < 3 && st == GS_OK; ++rep) {  // the first run warms up
+            if (hipEventRecord(e0, stream) != hipSuccess) st = GS_ERR_HIP;
+            if (st == GS_OK)
+                st = gs_rhs_batch(q, p, offsets, nsub, &trial, GS_BH, dq, dp, ws, ws_bytes,
+                                  stream);
+            if (st == GS_OK && hipEventRecord(e1, stream) != hipSuccess) st = GS_ERR_HIP;
+            if (st == GS_OK && hipEventSynchronize(e1) != hipSuccess) st = GS_ERR_HIP;
+            float ms = 0.f;
+            if (st == GS_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = GS_ERR_HIP;
+            if (st == GS_OK && rep > 0 && ms < ms_min) ms_min = ms;
+        }
+        if (st != GS_OK) break;
+        if (ms_min < best) {
+            best = ms_min;
+            best_cap = cap;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != GS_OK) {
+        if (st == GS_ERR_HIP) set_error("autotune: a HIP call failed");
+        return st;
+    }
+    prm->leaf_cap = best_cap;
+    if (best_ms) *best_ms = best;
+    return GS_OK;
+}
+
 gs_status gs_get_status(const void *ws, hipStream_t stream) {
     if (!ws) {
         set_error("workspace is NULL");

