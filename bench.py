@@ -120,6 +120,9 @@ def main():
     ap.add_argument("--theta", type=float, default=0.5)
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-targets", type=int, default=100000)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run one device-to-device copy of this many MiB before the timed "
+                         "region (a kernel of known traffic for calibrating HBM counters)")
     ap.add_argument("--population", type=int, default=1,
                     help="also time batched shooting of the 64-subject population")
     args = ap.parse_args()
@@ -155,6 +158,13 @@ def main():
 
     for _ in range(args.warmup):
         step()
+    if args.calib_copy_mib > 0:
+        # one elementwise kernel that reads N and writes N bytes
+        src = torch.ones(args.calib_copy_mib << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        torch.add(src, 1, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
     torch.cuda.synchronize()
 
     gs.gs_kernel_timing(True)

@@ -223,6 +223,7 @@ __global__ __launch_bounds__(256) void k_exact_items(const float4 *__restrict__ 
                                                      const int4 *__restrict__ items,
                                                      double *__restrict__ part) {
     const int4 it = items[blockIdx.x];
+    if (it.w < 0) return;  // padding item (keeps the XCD interleave aligned)
     const int64_t t0 = (int64_t)it.x + (threadIdx.x >> 6) * 64 + (threadIdx.x & 63);
     pair_sums<1, WITH_A, true>(Q, P, npad, Q, P, t0, it.y, it.z, 0.f,
                                part + (int64_t)it.w * 6 * npad);
@@ -913,11 +914,11 @@ ExactBatchPlan plan_exact_batch(const int64_t *offsets, int nsub) {
     if (chunk < 2048) chunk = 2048;
     pl.max_chunks = 1;
     pl.bseg.resize(nsub + 1);
-    struct Item {
-        int64_t cost;
-        int4 it;
+    struct Chunk {
+        int set, c;
+        int64_t j0, j1, work;
     };
-    std::vector<Item> items;
+    std::vector<Chunk> chunks;
     for (int s = 0; s < nsub; ++s) {
         pl.bseg[s] = (int)pl.blocks.size();
         const int64_t n = offsets[s + 1] - offsets[s];
@@ -929,20 +930,52 @@ ExactBatchPlan plan_exact_batch(const int64_t *offsets, int nsub) {
         for (int64_t b = 0; b < tp[s] / 256; ++b) {
             const int64_t cnt = n - 256 * b < 256 ? n - 256 * b : 256;
             pl.blocks.push_back(make_int4((int)(offsets[s] + 256 * b), (int)cnt, s, nch));
-            for (int c = 0; c < nch; ++c) {
-                const int64_t j0 = base[s] + c * csz;
-                const int64_t j1 = j0 + csz < base[s] + sp[s] ? j0 + csz : base[s] + sp[s];
-                items.push_back({256 * (j1 - j0),
-                                 make_int4((int)(base[s] + 256 * b), (int)j0, (int)j1, c)});
-            }
+        }
+        for (int c = 0; c < nch; ++c) {
+            const int64_t j0 = base[s] + c * csz;
+            const int64_t j1 = j0 + csz < base[s] + sp[s] ? j0 + csz : base[s] + sp[s];
+            chunks.push_back({s, c, j0, j1, tp[s] * (j1 - j0)});
         }
     }
     pl.bseg[nsub] = (int)pl.blocks.size();
-    // largest items first, so that the short ones fill the end of the launch
-    std::stable_sort(items.begin(), items.end(),
-                     [](const Item &a, const Item &b) { return a.cost > b.cost; });
-    pl.items.reserve(items.size());
-    for (const Item &x : items) pl.items.push_back(x.it);
+    // Every source chunk gets a home XCD (the largest chunks first, each to
+    // the least loaded XCD), so that an XCD streams only its own chunks and
+    // they stay in its L2.  Workgroups are dealt to the 8 XCDs in turn, so
+    // item i of the launch runs on XCD i % 8: the launch interleaves the 8
+    // queues, largest items first in each, and pads a short queue with empty
+    // items (slot -1) to keep the interleave aligned.
+    std::vector<int> order(chunks.size());
+    for (size_t k = 0; k < order.size(); ++k) order[k] = (int)k;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return chunks[a].work > chunks[b].work; });
+    int64_t load[kXcds] = {};
+    struct Item {
+        int64_t cost;
+        int4 it;
+    };
+    std::vector<Item> queue[kXcds];
+    for (int k : order) {
+        int x = 0;
+        for (int y = 1; y < kXcds; ++y)
+            if (load[y] < load[x]) x = y;
+        const Chunk &ch = chunks[k];
+        load[x] += ch.work;
+        for (int64_t b = 0; b < tp[ch.set] / 256; ++b)
+            queue[x].push_back({256 * (ch.j1 - ch.j0),
+                                make_int4((int)(base[ch.set] + 256 * b), (int)ch.j0, (int)ch.j1,
+                                          ch.c)});
+    }
+    size_t longest = 0;
+    for (int x = 0; x < kXcds; ++x) {
+        std::stable_sort(queue[x].begin(), queue[x].end(),
+                         [](const Item &a, const Item &b) { return a.cost > b.cost; });
+        if (queue[x].size() > longest) longest = queue[x].size();
+    }
+    pl.items.reserve(longest * kXcds);
+    for (size_t i = 0; i < longest; ++i)
+        for (int x = 0; x < kXcds; ++x)
+            pl.items.push_back(i < queue[x].size() ? queue[x][i].it : make_int4(0, 0, 0, -1));
+    while (!pl.items.empty() && pl.items.back().w < 0) pl.items.pop_back();
     return pl;
 }
 

@@ -82,6 +82,7 @@ struct ExactPlan {
 constexpr int kMfmaGroups = 4;  // groups of 16 targets per wave (MFMA kernel)
 constexpr int kExactTplDefault = 1;  // targets per lane (VALU kernel, measured best)
 constexpr int64_t kSplitBlocks = 24576;  // blocks per exact launch the split count aims at
+constexpr int kXcds = 8;                 // MI355X: workgroups are dealt to 8 XCDs in turn
 ExactPlan plan_exact(int64_t n_targets, int64_t n_sources, bool mfma = false);
 
 // Buffers of one exact FP32 RHS evaluation.
@@ -132,13 +133,14 @@ gs_status launch_reduce_h_seg(const double *Hpart, int64_t stride, const int *se
 // Exact evaluation of independent point sets (subjects) stored one after the
 // other ([offsets[s], offsets[s+1]) is set s).  Rows are padded per set to
 // whole blocks of 256 targets; a work item is one such block against one
-// source chunk of its own set.  Items run largest first.
+// source chunk of its own set.  Each source chunk has a home XCD; items run
+// on their chunk's XCD, largest first.
 struct ExactBatchPlan {
     int nsub;
     int64_t ntot;                 // real points
     int64_t npad;                 // padded rows
     int max_chunks;               // partial slots per row
-    std::vector<int4> items;      // (first target row, j0, j1, slot)
+    std::vector<int4> items;      // (first target row, j0, j1, slot); slot -1: padding
     std::vector<int4> blocks;     // per 256-row block: (first real point, count, set, slots)
     std::vector<int> bseg;        // [nsub + 1] row-block range of each set
 };
