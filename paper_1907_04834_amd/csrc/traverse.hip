@@ -14,7 +14,8 @@
 // Node records are read with wave-uniform addresses (scalar loads); the
 // decisions are taken in FP64 from the FP32 target position, the node's
 // exact FP32 box and FP64 centre, as in the definition; the contributions
-// are FP32 with per-leaf sums accumulated in FP64.
+// are FP32 with per-leaf sums accumulated in FP64.  Leaf points are streamed
+// with wave-uniform (scalar) loads, lanes outside a leaf's mask switched off.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -38,7 +39,6 @@ typedef unsigned long long u64;
 // the partial sums of a target in a fixed order (phase 1, then chunk 0, 1,
 // ...): the result does not depend on scheduling.
 constexpr int kBlockStack = 192;  // entries of (first child, count, lane mask)
-constexpr int kStage = 128;       // leaf points staged per round
 constexpr int kListCap = 512;     // list entries per group (more are summed in phase 1)
 constexpr int kChunkEntries = 32;
 constexpr int kChunks = kListCap / kChunkEntries;
@@ -50,19 +50,12 @@ struct LeafEntry {
     int count;
 };
 
-struct StageLds {
-    LeafEntry ent[kChunkEntries];
-    int off[kChunkEntries];
-    float4 lq[kStage + 4];  // staged leaf points (+4 readable pad entries)
-    float4 lp[kStage + 4];  // staged leaf momenta
-};
 
 struct DecideLds {
     u64 mask[kBlockStack];
     int first[kBlockStack];
     int count[kBlockStack];
     BhNode node[8];  // the sibling block being decided
-    StageLds st;     // list overflow only
 };
 
 // Targets of group g: the table entry, or 64 consecutive points of one tree.
@@ -85,73 +78,68 @@ __device__ inline void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Exact pairs of the ne leaves in S.ent (lane masks in S.ent[].mask): their
-// points are staged in rounds of kStage with one batch of loads per round.
+// Exact pairs of one leaf, sorted points [first, first + count), for the
+// lanes with `mine` set.  first and count are wave-uniform, so the points are
+// read with wave-uniform addresses (scalar loads straight into SGPRs, as in
+// the all-pairs kernel); lanes outside the leaf's mask are switched off by
+// the branch.  The leaf is summed in FP32 and added to the FP64 sums.
 template <bool WITH_A>
-__device__ inline void leaf_pairs(StageLds &S, int ne, const float4 *__restrict__ Qs,
-                                  const float4 *__restrict__ Ps, int lane, float4 xq, float4 xp,
-                                  float negc, double *V, double *A, unsigned &steps) {
-    int total = 0;
-    for (int r = 0; r < ne; ++r) {
-        S.off[r] = total;
-        total += S.ent[r].count;
+__device__ __forceinline__ void leaf_direct(const float4 *__restrict__ Qs,
+                                            const float4 *__restrict__ Ps, int first, int count,
+                                            bool mine, float4 xq, float4 xp, float negc,
+                                            double *V, double *A) {
+    if (!mine) return;
+    float tv[3] = {0.f, 0.f, 0.f}, ta[3] = {0.f, 0.f, 0.f};
+    const int end = first + count;
+    int j = first;
+    for (; j + 4 <= end; j += 4) {
+        float4 qj[4], pj[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            qj[u] = Qs[j + u];
+            pj[u] = Ps[j + u];
+        }
+        float dx[4], dy[4], dz[4], g[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            dx[u] = xq.x - qj[u].x;
+            dy[u] = xq.y - qj[u].y;
+            dz[u] = xq.z - qj[u].z;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            g[u] = __builtin_amdgcn_exp2f((dx[u] * dx[u] + dy[u] * dy[u] + dz[u] * dz[u]) * negc);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            tv[0] += g[u] * pj[u].x;
+            tv[1] += g[u] * pj[u].y;
+            tv[2] += g[u] * pj[u].z;
+            if (WITH_A) {
+                const float w = g[u] * (xp.x * pj[u].x + xp.y * pj[u].y + xp.z * pj[u].z);
+                ta[0] += w * dx[u];
+                ta[1] += w * dy[u];
+                ta[2] += w * dz[u];
+            }
+        }
     }
-    wave_sync();
-    for (int r0 = 0; r0 < total; r0 += kStage) {
-        const int rcnt = total - r0 < kStage ? total - r0 : kStage;
-        for (int e = lane; e < rcnt; e += 64) {
-            const int g = r0 + e;  // position in the concatenated leaves
-            int r = 0;
-            for (int k = 1; k < ne; ++k)
-                if (S.off[k] <= g) r = k;
-            const int j = S.ent[r].first + (g - S.off[r]);
-            S.lq[e] = Qs[j];
-            S.lp[e] = Ps[j];
+    for (; j < end; ++j) {
+        const float4 qj = Qs[j], pj = Ps[j];
+        const float dx = xq.x - qj.x, dy = xq.y - qj.y, dz = xq.z - qj.z;
+        const float g = __builtin_amdgcn_exp2f((dx * dx + dy * dy + dz * dz) * negc);
+        tv[0] += g * pj.x;
+        tv[1] += g * pj.y;
+        tv[2] += g * pj.z;
+        if (WITH_A) {
+            const float w = g * (xp.x * pj.x + xp.y * pj.y + xp.z * pj.z);
+            ta[0] += w * dx;
+            ta[1] += w * dy;
+            ta[2] += w * dz;
         }
-        // the 4 slots after the round are read by the last group of 4 with
-        // a zero weight: keep them finite
-        if (lane < 4) {
-            S.lq[rcnt + lane] = make_float4(0.f, 0.f, 0.f, 0.f);
-            S.lp[rcnt + lane] = make_float4(0.f, 0.f, 0.f, 0.f);
-        }
-        wave_sync();
-        for (int r = 0; r < ne; ++r) {
-            const int lo = S.off[r], hi = lo + S.ent[r].count;
-            const int a = lo > r0 ? lo : r0, b = hi < r0 + rcnt ? hi : r0 + rcnt;
-            if (a >= b) continue;
-            steps += (unsigned)(b - a);
-            if (!((S.ent[r].mask >> lane) & 1ull)) continue;
-            float tv[3] = {0.f, 0.f, 0.f}, ta[3] = {0.f, 0.f, 0.f};
-            for (int j = a - r0; j < b - r0; j += 4) {
-                float4 qj[4], pj[4];
+    }
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    qj[u] = S.lq[j + u];
-                    pj[u] = S.lp[j + u];
-                }
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const float dx = xq.x - qj[u].x, dy = xq.y - qj[u].y, dz = xq.z - qj[u].z;
-                    float g = __builtin_amdgcn_exp2f((dx * dx + dy * dy + dz * dz) * negc);
-                    g = (j + u < b - r0) ? g : 0.f;  // past the leaf: zero weight
-                    tv[0] += g * pj[u].x;
-                    tv[1] += g * pj[u].y;
-                    tv[2] += g * pj[u].z;
-                    if (WITH_A) {
-                        const float w = g * (xp.x * pj[u].x + xp.y * pj[u].y + xp.z * pj[u].z);
-                        ta[0] += w * dx;
-                        ta[1] += w * dy;
-                        ta[2] += w * dz;
-                    }
-                }
-            }
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                V[c] += (double)tv[c];
-                if (WITH_A) A[c] += (double)ta[c];
-            }
-        }
-        wave_sync();
+    for (int c = 0; c < 3; ++c) {
+        V[c] += (double)tv[c];
+        if (WITH_A) A[c] += (double)ta[c];
     }
 }
 
@@ -251,14 +239,8 @@ __global__ __launch_bounds__(256) void k_bh_decide(
                     ++nlist;
                 } else {
                     // list full: sum this leaf here
-                    wave_sync();
-                    if (lane == 0) {
-                        L.st.ent[0].mask = open;
-                        L.st.ent[0].first = nfirst;
-                        L.st.ent[0].count = ncount;
-                    }
-                    wave_sync();
-                    leaf_pairs<WITH_A>(L.st, 1, Qs, Ps, lane, xq, xp, bp.negc, V, A, w_steps);
+                    w_steps += (unsigned)ncount;
+                    leaf_direct<WITH_A>(Qs, Ps, nfirst, ncount, need, xq, xp, bp.negc, V, A);
                 }
             } else {
                 if (sp >= kBlockStack) {
@@ -322,7 +304,6 @@ __global__ __launch_bounds__(256) void k_bh_leaves(const float4 *__restrict__ Qs
                                                    const int *__restrict__ list_n,
                                                    double *__restrict__ part,
                                                    u64 *__restrict__ counters) {
-    __shared__ StageLds lds_all[4];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t grp = blockIdx.x;
     const int chunk = blockIdx.y * 4 + wv;
@@ -330,8 +311,7 @@ __global__ __launch_bounds__(256) void k_bh_leaves(const float4 *__restrict__ Qs
     const int e0 = chunk * kChunkEntries;
     if (e0 >= cnt) return;  // wave-uniform: this chunk holds no entries
     const int ne = cnt - e0 < kChunkEntries ? cnt - e0 : kChunkEntries;
-    StageLds &S = lds_all[wv];
-    if (lane < ne) S.ent[lane] = list[grp * kListCap + e0 + lane];
+    const LeafEntry *ent = list + grp * kListCap + e0;
     const int64_t npad = groups * 64;
     const GroupDesc gd = group_desc(gtab, grp, n);
     const int64_t t = (int64_t)gd.first + lane;
@@ -340,8 +320,14 @@ __global__ __launch_bounds__(256) void k_bh_leaves(const float4 *__restrict__ Qs
     const float4 xp = active ? Ps[t] : make_float4(0.f, 0.f, 0.f, 0.f);
     double V[3] = {0, 0, 0}, A[3] = {0, 0, 0};
     unsigned steps = 0;
-    wave_sync();
-    leaf_pairs<WITH_A>(S, ne, Qs, Ps, lane, xq, xp, negc, V, A, steps);
+    for (int r = 0; r < ne; ++r) {
+        const LeafEntry e = ent[r];  // wave-uniform
+        const int first = __builtin_amdgcn_readfirstlane(e.first);
+        const int count = __builtin_amdgcn_readfirstlane(e.count);
+        steps += (unsigned)count;
+        leaf_direct<WITH_A>(Qs, Ps, first, count, ((e.mask >> lane) & 1ull) != 0, xq, xp, negc, V,
+                            A);
+    }
     write_part(part, 1 + chunk, npad, grp * 64 + lane, V, A);
     if (lane == 0 && counters) {
         atomicAdd(&counters[4], (u64)steps);
