@@ -35,6 +35,13 @@ METRIC = "pair-interactions/s & shootings/s, BH vs exact FP32 at N=200k; err vs 
 FLOP_PER_PAIR = 28          # algorithmic FLOP of one (v, a) pair interaction
 FP32_VALU_PEAK_TF = 157.3   # MI355X published FP32 vector peak (TFLOP/s)
 GOLDEN = os.path.join(ROOT, "tests", "golden")
+# HBM bytes per launch of the exact work-item kernel at 200k points, from
+# rocprofv3 FETCH_SIZE and WRITE_SIZE runs (each scaled by what the counter
+# reads for an elementwise kernel of known traffic: x2.0 fetch, x1.0 write).
+# Valid only for the kernel source they were taken on (sha256 prefix).
+EXACT_TRAFFIC_BYTES = 517362305
+EXACT_TRAFFIC_SOURCE = "512ddf3d65232675"
+EXACT_SOURCE = os.path.join(ROOT, "paper_1907_04834_amd", "csrc", "exact.hip")
 
 
 def _digest(*arrays):
@@ -42,6 +49,13 @@ def _digest(*arrays):
     for a in arrays:
         h.update(np.ascontiguousarray(a).tobytes())
     return h.hexdigest()
+
+
+def _traffic():
+    """The measured traffic while the kernel source is the measured one."""
+    with open(EXACT_SOURCE, "rb") as f:
+        h = hashlib.sha256(f.read()).hexdigest()[:16]
+    return EXACT_TRAFFIC_BYTES if h == EXACT_TRAFFIC_SOURCE else None
 
 
 def _rel(x, y):
@@ -256,7 +270,8 @@ def main():
                     for name, v in kt.items()},
         "roofline": {"bound": "alu", "achieved": achieved_tf, "peak": FP32_VALU_PEAK_TF,
                      "unit": "TFLOP/s", "frac": achieved_tf / FP32_VALU_PEAK_TF,
-                     "traffic": None, "kernel": "k_exact_items<true>",
+                     "traffic": _traffic(), "traffic_unit": "B",
+                     "kernel": "k_exact_items<true>",
                      "per_launch": f"{n}^2 pairs x {FLOP_PER_PAIR} FLOP",
                      "avg_launch_ms": exact_ms_launch},
         "err_vs_fp64": err,

@@ -20,7 +20,12 @@
  *     ...), float32 unless the name ends in _f64.  The caller owns them.
  *   - `ws` is a caller-owned DEVICE workspace of at least gs_workspace_bytes()
  *     bytes (256-byte aligned).  The library allocates no device memory and
- *     keeps no pointer after a call returns.
+ *     keeps no pointer after a call returns.  Calls that plan work on the
+ *     host (the batched calls and the FP32 exact right-hand side and
+ *     shooting) copy their small tables into the workspace from a ring of
+ *     four pinned host buffers per thread, allocated on first use and kept
+ *     until the process ends; a fifth such call waits for the first one's
+ *     copy to finish before reusing its buffer.
  *   - `stream` is the HIP stream every kernel is enqueued on.  Calls only
  *     enqueue work and return; results are valid once the stream reaches the
  *     point after the call.  The library never synchronises the stream
