@@ -125,6 +125,42 @@ def population_rates(gs, W, torch, dev, theta, leaf_cap):
     return out
 
 
+def _timed(torch, fn):
+    """One warm-up call, then one call timed with HIP events (ms)."""
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def adjoint_and_field_rates(gs, W, torch, dev, theta, leaf_cap):
+    """Objective + gradient by the discrete adjoint (50k template, 40 steps,
+    checkpoints every 8), exact and Barnes-Hut; and the velocity field of the
+    200k point set at 200k other points."""
+    out = {}
+    w = W.adjoint_50k()
+    q0, p0 = torch.from_numpy(w.q0).to(dev), torch.from_numpy(w.p0).to(dev)
+    y = torch.from_numpy(w.extra["target"]).to(dev)
+    for name, method in (("exact", gs.GS_EXACT), ("bh", gs.GS_BH)):
+        prm = gs.params(w.sigma, nt=w.nt, theta=theta, leaf_cap=leaf_cap)
+        ms = _timed(torch, lambda: gs.gs_shoot_adjoint(q0, p0, y, prm, method, w.extra["lam"],
+                                                       w.extra["ckpt"]))
+        out[f"adjoint_{name}"] = {"n": w.n, "nt": w.nt, "ckpt_every": w.extra["ckpt"],
+                                  "ms_per_gradient": ms, "gradients_per_s": 1e3 / ms}
+    src = W.ellipsoids_200k()
+    x = torch.rand(200000, 3, generator=torch.Generator(device="cpu").manual_seed(7)).to(dev)
+    q, p = torch.from_numpy(src.q0).to(dev), torch.from_numpy(src.p0).to(dev)
+    prm = gs.params(src.sigma)
+    ms = _timed(torch, lambda: gs.gs_field(x, q, p, prm))
+    out["field"] = {"targets": 200000, "sources": src.n, "ms": ms,
+                    "pair_evaluations_per_s": 200000 * src.n / (ms / 1e3)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -137,6 +173,8 @@ def main():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB before the timed "
                          "region (a kernel of known traffic for calibrating HBM counters)")
+    ap.add_argument("--next-rows", type=int, default=1,
+                    help="also time the adjoint gradient (50k) and the dense field (200k)")
     ap.add_argument("--population", type=int, default=1,
                     help="also time batched shooting of the 64-subject population")
     args = ap.parse_args()
@@ -279,6 +317,8 @@ def main():
     }
     if args.population:
         out["population"] = population_rates(gs, W, torch, dev, args.theta, args.leaf_cap)
+    if args.next_rows:
+        out.update(adjoint_and_field_rates(gs, W, torch, dev, args.theta, args.leaf_cap))
     if args.cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.theta, args.leaf_cap,
                                            exact_inter, bh_inter, args.cpu_targets)
