@@ -205,3 +205,41 @@ def test_autotune_leaf_cap_picks_a_valid_fast_setting():
     tb, msb = gs.gs_autotune_leaf_cap(_t(qq), _t(pp), gs.params(0.05, theta=0.5), offsets=off)
     _say(f"autotune batch leaf_cap -> {tb.leaf_cap} ({msb:.3f} ms per batched RHS)")
     assert tb.leaf_cap in (8, 16, 32, 48, 64)
+
+
+@pytest.mark.parametrize("method", [gs.GS_EXACT, gs.GS_BH])
+def test_many_tiny_sets(oracle, method):
+    """300 sets of 0..40 points: more than 256 sets take two radix passes on
+    the set index; every set must still come out as the set alone."""
+    rng = np.random.default_rng(300)
+    sizes = [int(x) for x in rng.integers(0, 41, size=300)]
+    subs = _ragged(sizes, seed=1000)
+    q, p, off = W.stack(subs)
+    sigma, theta, leaf_cap = 0.05, 0.5, 4
+    prm = gs.params(sigma, nt=3, theta=theta, leaf_cap=leaf_cap)
+    _say(f"many tiny sets: {len(sizes)} sets, {int(off[-1])} points, method={method}")
+    dq, dp, ws = gs.gs_rhs_batch(_t(q), _t(p), off, prm, method, return_ws=True)
+    q1, p1, H = gs.gs_shoot_batch(_t(q), _t(p), off, prm, method)
+    torch.cuda.synchronize()
+    v, a, q1, p1, H = _np(dq), _np(dp), _np(q1), _np(p1), _np(H)
+    pairs = 0
+    for s, w in enumerate(subs):
+        lo, hi = off[s], off[s + 1]
+        if hi == lo:
+            assert np.all(H[s] == 0.0)
+            continue
+        q64, p64 = w.q0.astype(np.float64), w.p0.astype(np.float64)
+        if method == gs.GS_EXACT:
+            vo, ao = oracle.rhs_exact(q64, p64, sigma)
+        else:
+            vo, ao, c = oracle.rhs_bh(q64, p64, sigma, theta, leaf_cap=leaf_cap)
+            pairs += c["pairs"]
+        assert np.allclose(v[lo:hi], vo, rtol=1e-5, atol=1e-7 * np.abs(vo).max())
+        assert np.allclose(a[lo:hi], ao, rtol=1e-4, atol=1e-6 * (np.abs(ao).max() + 1e-30))
+        kind = "exact" if method == gs.GS_EXACT else "bh"
+        qo, po, Ho = oracle.shoot(q64, p64, sigma, 3, method=kind, theta=theta,
+                                  leaf_cap=leaf_cap)
+        assert rel_l2(q1[lo:hi], qo) < 1e-5
+        assert np.max(np.abs(H[s] - Ho)) <= 1e-6 * np.max(np.abs(Ho))
+    if method == gs.GS_BH:
+        assert gs.gs_bh_counters(ws)["pairs"] == pairs
