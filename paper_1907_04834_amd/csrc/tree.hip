@@ -283,63 +283,72 @@ __global__ __launch_bounds__(256) void k_gather(const float *__restrict__ q,
 // ---------------------------------------------------------------- generic scan
 // Exclusive scan of n u32 values: per-block totals, then each block adds the
 // totals of the blocks before it.  out may equal in.  *total (nullable)
-// receives the sum.
+// receives the sum.  A block covers kScanTile = 256 threads x 8 contiguous
+// values; a thread scans its 8 values serially, a wave scans its 64 thread
+// sums with shuffles, and the 4 wave sums are combined through LDS.
+constexpr int kScanPer = kScanTile / 256;  // values per thread
+
 __global__ __launch_bounds__(256) void k_scan_blocksum(const unsigned *__restrict__ in,
                                                        int64_t n, unsigned *__restrict__ part) {
-    __shared__ unsigned red[256];
-    const int64_t b = (int64_t)blockIdx.x * kScanTile;
+    __shared__ unsigned wsum[4];
+    const int t = threadIdx.x;
+    const int64_t i0 = (int64_t)blockIdx.x * kScanTile + (int64_t)t * kScanPer;
     unsigned s = 0;
-    for (int k = 0; k < kScanTile / 256; ++k) {
-        const int64_t i = b + k * 256 + threadIdx.x;
-        if (i < n) s += in[i];
-    }
-    red[threadIdx.x] = s;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k)
+        if (i0 + k < n) s += in[i0 + k];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if ((t & 63) == 0) wsum[t >> 6] = s;
     __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+    if (t == 0) part[blockIdx.x] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
 }
 
 __global__ __launch_bounds__(256) void k_scan_apply(const unsigned *__restrict__ in,
                                                     unsigned *__restrict__ out, int64_t n,
                                                     const unsigned *__restrict__ part,
                                                     unsigned *__restrict__ total) {
-    __shared__ unsigned sc[256];
-    __shared__ unsigned carry;
-    const int t = threadIdx.x;
+    __shared__ unsigned wsum[4];
+    __shared__ unsigned carry_s;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     // offset of this block: sum of the previous block totals
     unsigned off = 0;
     for (int b = t; b < (int)blockIdx.x; b += 256) off += part[b];
-    sc[t] = off;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) off += __shfl_down(off, o, 64);
+    if (lane == 0) wsum[wv] = off;
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (t < s) sc[t] += sc[t + s];
-        __syncthreads();
-    }
-    if (t == 0) carry = sc[0];
+    if (t == 0) carry_s = wsum[0] + wsum[1] + wsum[2] + wsum[3];
     __syncthreads();
-    const int64_t b = (int64_t)blockIdx.x * kScanTile;
-    for (int k = 0; k < kScanTile / 256; ++k) {
-        const int64_t i = b + k * 256 + t;
-        const unsigned v = i < n ? in[i] : 0u;
-        sc[t] = v;
-        __syncthreads();
-        for (int o = 1; o < 256; o <<= 1) {
-            const unsigned u = t >= o ? sc[t - o] : 0u;
-            __syncthreads();
-            sc[t] += u;
-            __syncthreads();
-        }
-        const unsigned incl = sc[t];
-        const unsigned c = carry;
-        if (i < n) out[i] = c + incl - v;
-        __syncthreads();
-        if (t == 255) carry = c + incl;
-        __syncthreads();
+    const unsigned carry = carry_s;
+    __syncthreads();  // wsum is reused below
+    const int64_t i0 = (int64_t)blockIdx.x * kScanTile + (int64_t)t * kScanPer;
+    unsigned v[kScanPer];
+    unsigned run = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        v[k] = i0 + k < n ? in[i0 + k] : 0u;
+        run += v[k];
     }
-    if (total && blockIdx.x == gridDim.x - 1 && t == 0) *total = carry;
+    // inclusive scan of the thread sums within the wave
+    unsigned incl = run;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const unsigned u = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += u;
+    }
+    if (lane == 63) wsum[wv] = incl;
+    __syncthreads();
+    unsigned base = carry;
+    for (int w = 0; w < wv; ++w) base += wsum[w];
+    base += incl - run;  // exclusive prefix of this thread
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        if (i0 + k < n) out[i0 + k] = base;
+        base += v[k];
+    }
+    if (total && blockIdx.x == gridDim.x - 1 && t == 255)
+        *total = carry + wsum[0] + wsum[1] + wsum[2] + wsum[3];
 }
 
 // ---------------------------------------------------------------- tree
