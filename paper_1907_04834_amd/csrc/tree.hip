@@ -50,6 +50,13 @@ constexpr int kChunk = 64;                                 // points per range s
 
 inline unsigned nblk(int64_t n, int b = kBlock) { return (unsigned)((n + b - 1) / b); }
 
+// Blocks of 4 waves for one-wave-per-node kernels over at most max_nodes.
+constexpr unsigned kNodeBlocks = 4096;
+inline unsigned node_blocks(int64_t max_nodes) {
+    const unsigned b = nblk(max_nodes, 4);
+    return b < kNodeBlocks ? b : kNodeBlocks;
+}
+
 // Set of index i: the largest s with seg[s] <= i (seg is non-decreasing, so
 // this is the set whose range holds i even when empty sets precede it).
 __device__ inline int set_of(const long long *__restrict__ seg, int nsub, int64_t i) {
@@ -652,7 +659,33 @@ __global__ __launch_bounds__(256) void k_chunks1(const RangeStat *__restrict__ c
     if (lane == 0) c1[c] = r;
 }
 
-// Node statistics from its point range [a, b).
+// Statistics of the sorted range [a, b) by one wave: the range splits into
+// points up to the first chunk boundary, chunks up to the first super-chunk
+// boundary, super-chunks, chunks and points; the lanes take the items of
+// each part in turn and the wave adds its lanes in a fixed shuffle tree
+// (bitwise deterministic).
+__device__ inline void wave_range_stat(const float4 *__restrict__ A, const float4 *__restrict__ B,
+                                       const RangeStat *__restrict__ c0,
+                                       const RangeStat *__restrict__ c1, int64_t a, int64_t b,
+                                       int lane, RangeStat &r) {
+    constexpr int64_t C0 = kChunk, C1 = (int64_t)kChunk * kChunk;
+    const int64_t ra = (a + C0 - 1) / C0 * C0, rb = b / C0 * C0;
+    const int64_t p0 = ra < b ? ra : b;        // end of the leading points
+    const int64_t p1 = rb > p0 ? rb : p0;      // start of the trailing points
+    const int64_t sa = (p0 + C1 - 1) / C1 * C1, sb = p1 / C1 * C1;
+    const int64_t s0 = sa < p1 ? sa : p1;      // end of the leading chunks
+    const int64_t s1 = sb > s0 ? sb : s0;      // start of the trailing chunks
+    rs_init(r);
+    for (int64_t i = a + lane; i < p0; i += 64) rs_point(r, A[i], B[i]);
+    for (int64_t c = p0 / C0 + lane; c < s0 / C0; c += 64) rs_add(r, c0[c]);
+    for (int64_t c = s0 / C1 + lane; c < s1 / C1; c += 64) rs_add(r, c1[c]);
+    for (int64_t c = s1 / C0 + lane; c < p1 / C0; c += 64) rs_add(r, c0[c]);
+    for (int64_t i = p1 + lane; i < b; i += 64) rs_point(r, A[i], B[i]);
+    rs_wave_reduce(r);
+}
+
+// Node statistics from its point range, one wave per node (a grid of at
+// most kNodeBlocks blocks loops over the nodes).
 __global__ __launch_bounds__(256) void k_node_stats(const float4 *__restrict__ Qs,
                                                     const float4 *__restrict__ Ps,
                                                     const RangeStat *__restrict__ c0,
@@ -661,39 +694,19 @@ __global__ __launch_bounds__(256) void k_node_stats(const float4 *__restrict__ Q
                                                     const int *__restrict__ node_start,
                                                     BhNode *__restrict__ nodes,
                                                     double *__restrict__ nsum) {
-    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= totals->n_nodes) return;
-    BhNode nd = nodes[id];
-    int64_t a = node_start[id];
-    const int64_t b = a + nd.n;
-    RangeStat r;
-    rs_init(r);
-    constexpr int64_t C0 = kChunk, C1 = (int64_t)kChunk * kChunk;
-    // points up to a chunk boundary, chunks up to a super-chunk boundary,
-    // super-chunks, then chunks and points of the tail
-    while (a < b && (a % C0 != 0 || a + C0 > b)) {
-        rs_point(r, Qs[a], Ps[a]);
-        ++a;
+    const int lane = threadIdx.x & 63;
+    const int64_t nn = totals->n_nodes, waves = (int64_t)gridDim.x * 4;
+    for (int64_t id = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); id < nn; id += waves) {
+        BhNode nd = nodes[id];
+        const int64_t a = node_start[id];
+        RangeStat r;
+        wave_range_stat(Qs, Ps, c0, c1, a, a + nd.n, lane, r);
+        if (lane == 0) {
+            finish_node(nd, r.s, r.lo, r.hi);
+            nodes[id] = nd;
+            for (int c = 0; c < 6; ++c) nsum[6 * id + c] = r.s[c];
+        }
     }
-    while (a < b && a % C1 != 0 && a + C0 <= b) {
-        rs_add(r, c0[a / C0]);
-        a += C0;
-    }
-    while (a + C1 <= b) {
-        rs_add(r, c1[a / C1]);
-        a += C1;
-    }
-    while (a + C0 <= b) {
-        rs_add(r, c0[a / C0]);
-        a += C0;
-    }
-    while (a < b) {
-        rs_point(r, Qs[a], Ps[a]);
-        ++a;
-    }
-    finish_node(nd, r.s, r.lo, r.hi);
-    nodes[id] = nd;
-    for (int c = 0; c < 6; ++c) nsum[6 * id + c] = r.s[c];
 }
 
 // Node sums of two fields over node ranges (the sums part of k_node_stats).
@@ -705,34 +718,15 @@ __global__ __launch_bounds__(256) void k_node_sums(const float4 *__restrict__ A,
                                                    const int *__restrict__ node_start,
                                                    const BhNode *__restrict__ nodes,
                                                    double *__restrict__ out) {
-    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= totals->n_nodes) return;
-    int64_t a = node_start[id];
-    const int64_t b = a + nodes[id].n;
-    RangeStat r;
-    rs_init(r);
-    constexpr int64_t C0 = kChunk, C1 = (int64_t)kChunk * kChunk;
-    while (a < b && (a % C0 != 0 || a + C0 > b)) {
-        rs_point(r, A[a], B[a]);
-        ++a;
+    const int lane = threadIdx.x & 63;
+    const int64_t nn = totals->n_nodes, waves = (int64_t)gridDim.x * 4;
+    for (int64_t id = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); id < nn; id += waves) {
+        const int64_t a = node_start[id];
+        RangeStat r;
+        wave_range_stat(A, B, c0, c1, a, a + nodes[id].n, lane, r);
+        if (lane == 0)
+            for (int c = 0; c < 6; ++c) out[6 * id + c] = r.s[c];
     }
-    while (a < b && a % C1 != 0 && a + C0 <= b) {
-        rs_add(r, c0[a / C0]);
-        a += C0;
-    }
-    while (a + C1 <= b) {
-        rs_add(r, c1[a / C1]);
-        a += C1;
-    }
-    while (a + C0 <= b) {
-        rs_add(r, c0[a / C0]);
-        a += C0;
-    }
-    while (a < b) {
-        rs_point(r, A[a], B[a]);
-        ++a;
-    }
-    for (int c = 0; c < 6; ++c) out[6 * id + c] = r.s[c];
 }
 
 gs_status scan_u32(const unsigned *in, unsigned *out, int64_t n, unsigned *part, unsigned *total,
@@ -850,7 +844,7 @@ gs_status build_tree(const float *q, const float *p, int64_t n, int leaf_cap, Tr
     RangeStat *c1 = reinterpret_cast<RangeStat *>(t.chunk1);
     hipLaunchKernelGGL(k_chunks0, dim3(nblk(nc0, 4)), dim3(256), 0, s, t.Qs, t.Ps, n, c0, nc0);
     hipLaunchKernelGGL(k_chunks1, dim3(nblk(nc1, 4)), dim3(256), 0, s, c0, nc0, c1, nc1);
-    hipLaunchKernelGGL(k_node_stats, dim3(nblk(2 * n + nsub)), dim3(256), 0, s, t.Qs, t.Ps, c0,
+    hipLaunchKernelGGL(k_node_stats, dim3(node_blocks(2 * n + nsub)), dim3(256), 0, s, t.Qs, t.Ps, c0,
                        c1, t.totals, t.node_start, t.nodes, t.nsum);
     timing_end(KIND_TREE, s);
     GS_LAUNCH_CHECK("nodes/stats");
@@ -865,7 +859,7 @@ gs_status tree_range_sums(const float4 *A, const float4 *B, TreeBufs &t, double 
     RangeStat *c1 = reinterpret_cast<RangeStat *>(t.chunk1);
     hipLaunchKernelGGL(k_chunks0, dim3(nblk(nc0, 4)), dim3(256), 0, s, A, B, n, c0, nc0);
     hipLaunchKernelGGL(k_chunks1, dim3(nblk(nc1, 4)), dim3(256), 0, s, c0, nc0, c1, nc1);
-    hipLaunchKernelGGL(k_node_sums, dim3(nblk(2 * n + t.nsub)), dim3(256), 0, s, A, B, c0, c1,
+    hipLaunchKernelGGL(k_node_sums, dim3(node_blocks(2 * n + t.nsub)), dim3(256), 0, s, A, B, c0, c1,
                        t.totals, t.node_start, t.nodes, out);
     GS_LAUNCH_CHECK("range sums");
     return GS_OK;
