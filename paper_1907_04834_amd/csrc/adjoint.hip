@@ -141,16 +141,25 @@ __global__ __launch_bounds__(256) void k_adj_pairs(
                 const float pa = pj.x * ax[k] + pj.y * ay[k] + pj.z * az[k];
                 const float ap = px[k] * aj.x + py[k] * aj.y + pz[k] * aj.z;
                 const float dbx = bx[k] - bj.x, dby = by[k] - bj.y, dbz = bz[k] - bj.z;
-                const float ddb = dx * dbx + dy * dby + dz * dbz;
-                const float w1 = g * (-(pa + ap) - s * ddb * inv_s2);
+                const float c2 = (dx * dbx + dy * dby + dz * dbz) * inv_s2;
+                // w1 = -G ((p_j . alpha_k) + (p_k . alpha_j) + s (d . dbeta) / sigma^2)
+                const float w1 = -g * fmaf(s, c2, pa + ap);
                 const float w2 = g * s;
-                const float w3 = g * ddb * inv_s2;
-                tq[k][0] += w1 * dx + w2 * dbx;
-                tq[k][1] += w1 * dy + w2 * dby;
-                tq[k][2] += w1 * dz + w2 * dbz;
-                tp[k][0] += g * aj.x + w3 * pj.x;
-                tp[k][1] += g * aj.y + w3 * pj.y;
-                tp[k][2] += g * aj.z + w3 * pj.z;
+                const float w3 = g * c2;
+                // each sum as two chained FMAs (written as one expression the
+                // products would be added first and cost an extra add)
+                tq[k][0] = fmaf(w1, dx, tq[k][0]);
+                tq[k][1] = fmaf(w1, dy, tq[k][1]);
+                tq[k][2] = fmaf(w1, dz, tq[k][2]);
+                tq[k][0] = fmaf(w2, dbx, tq[k][0]);
+                tq[k][1] = fmaf(w2, dby, tq[k][1]);
+                tq[k][2] = fmaf(w2, dbz, tq[k][2]);
+                tp[k][0] = fmaf(g, aj.x, tp[k][0]);
+                tp[k][1] = fmaf(g, aj.y, tp[k][1]);
+                tp[k][2] = fmaf(g, aj.z, tp[k][2]);
+                tp[k][0] = fmaf(w3, pj.x, tp[k][0]);
+                tp[k][1] = fmaf(w3, pj.y, tp[k][1]);
+                tp[k][2] = fmaf(w3, pj.z, tp[k][2]);
             }
         }
 #pragma unroll

@@ -75,16 +75,23 @@ __device__ inline void adj_pair(float4 x, float4 px, float4 ax, float4 bx, float
     const float cross = pj.x * ax.x + pj.y * ax.y + pj.z * ax.z + px.x * aj.x + px.y * aj.y +
                         px.z * aj.z;
     const float dbx = bx.x - bj.x, dby = bx.y - bj.y, dbz = bx.z - bj.z;
-    const float ddb = dx * dbx + dy * dby + dz * dbz;
-    const float w1 = g * (-cross - s * ddb * inv_s2);
+    const float c2 = (dx * dbx + dy * dby + dz * dbz) * inv_s2;
+    const float w1 = -g * fmaf(s, c2, cross);
     const float w2 = g * s;
-    const float w3 = g * ddb * inv_s2;
-    gq[0] += w1 * dx + w2 * dbx;
-    gq[1] += w1 * dy + w2 * dby;
-    gq[2] += w1 * dz + w2 * dbz;
-    gp[0] += g * aj.x + w3 * pj.x;
-    gp[1] += g * aj.y + w3 * pj.y;
-    gp[2] += g * aj.z + w3 * pj.z;
+    const float w3 = g * c2;
+    // each sum as two chained FMAs
+    gq[0] = fmaf(w1, dx, gq[0]);
+    gq[1] = fmaf(w1, dy, gq[1]);
+    gq[2] = fmaf(w1, dz, gq[2]);
+    gq[0] = fmaf(w2, dbx, gq[0]);
+    gq[1] = fmaf(w2, dby, gq[1]);
+    gq[2] = fmaf(w2, dbz, gq[2]);
+    gp[0] = fmaf(g, aj.x, gp[0]);
+    gp[1] = fmaf(g, aj.y, gp[1]);
+    gp[2] = fmaf(g, aj.z, gp[2]);
+    gp[0] = fmaf(w3, pj.x, gp[0]);
+    gp[1] = fmaf(w3, pj.y, gp[1]);
+    gp[2] = fmaf(w3, pj.z, gp[2]);
 }
 
 __global__ __launch_bounds__(256) void k_bh_adj_traverse(
