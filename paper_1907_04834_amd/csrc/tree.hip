@@ -43,8 +43,8 @@ namespace {
 typedef unsigned long long u64;
 
 constexpr int kSortThreads = 256;
-constexpr int kSortPerThread = 8;
-constexpr int kSortTile = kSortThreads * kSortPerThread;  // 2048 keys per block
+constexpr int kSortPerThread = 2;
+constexpr int kSortTile = kSortThreads * kSortPerThread;  // 512 keys per block (measured best of 256..2048)
 constexpr int kScanTile = 2048;                            // items per scan block
 constexpr int kChunk = 64;                                 // points per range summary
 
