@@ -89,6 +89,7 @@ struct TreeBufs {
     unsigned *rank_bnd;        // [n] boundary of internal rank r
     unsigned *nchild;          // [n] children of internal rank r
     unsigned *cstart;          // [n] exclusive scan of nchild
+    unsigned *crun;            // [n][9] child starts of internal rank r, then the cell end
     int *node_start;           // [2n + nsub] first sorted point of each node
     char *chunk0, *chunk1;     // range summaries of 64 and 4096 sorted points
     double *nsum;              // [nodes][6] FP64 sums of q and p per node

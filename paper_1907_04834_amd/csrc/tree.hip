@@ -430,27 +430,6 @@ __global__ __launch_bounds__(256) void k_boundaries(const u64 *__restrict__ K, i
     flag[i] = f;
 }
 
-// Child runs of the internal cell [s, e) split at level L: up to 8 non-empty
-// level-(L+1) sub-cells in octant order.  Returns their count; c[k], c[k+1]
-// bound child k.
-__device__ inline int child_runs(const u64 *__restrict__ K, int64_t s, int64_t e, int L,
-                                 unsigned *c) {
-    const u64 pre = L == 0 ? 0ull : (K[s] >> level_shift(L));
-    const int sh = level_shift(L + 1);
-    int cnt = 0;
-    int64_t prev = s;
-    for (int d = 1; d < 8; ++d) {
-        const int64_t pos = lower_bound(K, prev, e, ((pre << 3) | (u64)d) << sh);
-        if (pos > prev) {
-            c[cnt++] = (unsigned)prev;
-            prev = pos;
-        }
-    }
-    if (prev < e) c[cnt++] = (unsigned)prev;
-    c[cnt] = (unsigned)e;
-    return cnt;
-}
-
 // Representative boundary of the compressed internal node covering [a, b)
 // (b - a > leaf_cap, keys not all equal).
 __device__ inline int64_t child_rep(const u64 *__restrict__ K, int64_t a, int64_t b) {
@@ -460,21 +439,51 @@ __device__ inline int64_t child_rep(const u64 *__restrict__ K, int64_t a, int64_
     return lower_bound(K, a, b, (pre + 1) << sh) - 1;
 }
 
-__global__ __launch_bounds__(256) void k_children(const u64 *__restrict__ K, int64_t n,
-                                                  const unsigned char *__restrict__ lvl,
-                                                  const unsigned *__restrict__ flag,
+// Boundary of each internal rank.
+__global__ __launch_bounds__(256) void k_rank_bnd(int64_t n, const unsigned *__restrict__ flag,
                                                   const unsigned *__restrict__ rank,
+                                                  unsigned *__restrict__ rank_bnd) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n - 1 && flag[i]) rank_bnd[rank[i]] = (unsigned)i;
+}
+
+// Child runs of every internal node, one wave per node: lane d (1..7)
+// searches where octant d starts, so the searches run side by side; the
+// non-empty octants in order are the children.  crun[9 r + k] is the first
+// sorted point of child k of rank r, crun[9 r + nchild] the end of the cell.
+__global__ __launch_bounds__(256) void k_children(const u64 *__restrict__ K,
+                                                  const unsigned char *__restrict__ lvl,
+                                                  const TreeTotals *__restrict__ totals,
                                                   const unsigned *__restrict__ bs,
                                                   const unsigned *__restrict__ be,
-                                                  unsigned *__restrict__ rank_bnd,
-                                                  unsigned *__restrict__ nchild) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n - 1 || !flag[i]) return;
-    unsigned c[9];
-    const int cnt = child_runs(K, bs[i], be[i], lvl[i], c);
-    const unsigned r = rank[i];
-    rank_bnd[r] = (unsigned)i;
-    nchild[r] = (unsigned)cnt;
+                                                  const unsigned *__restrict__ rank_bnd,
+                                                  unsigned *__restrict__ nchild,
+                                                  unsigned *__restrict__ crun) {
+    const int lane = threadIdx.x & 63;
+    const int64_t nint = totals->n_internal, waves = (int64_t)gridDim.x * 4;
+    for (int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); r < nint; r += waves) {
+        const unsigned i = rank_bnd[r];
+        const int64_t s = bs[i], e = be[i];
+        const int L = lvl[i];
+        const u64 pre = L == 0 ? 0ull : (K[s] >> level_shift(L));
+        const int sh = level_shift(L + 1);
+        // start of octant `lane` (lanes 0..8; octant 0 starts at s, "octant 8" at e)
+        int64_t pos = s;
+        if (lane >= 1 && lane <= 7) pos = lower_bound(K, s, e, ((pre << 3) | (u64)lane) << sh);
+        if (lane == 8) pos = e;
+        const int64_t next = __shfl_down(pos, 1, 64);
+        const bool nonempty = lane < 8 && next > pos;
+        const u64 m = __ballot(nonempty);
+        const int cnt = __popcll(m);
+        if (nonempty) {
+            const int k = __popcll(m & ((1ull << lane) - 1ull));
+            crun[9 * r + k] = (unsigned)pos;
+        }
+        if (lane == 0) {
+            crun[9 * r + cnt] = (unsigned)e;
+            nchild[r] = (unsigned)cnt;
+        }
+    }
 }
 
 __device__ inline void zero_stats(BhNode &nd) {
@@ -520,26 +529,23 @@ __global__ __launch_bounds__(64) void k_roots(const u64 *__restrict__ K, int64_t
     }
 }
 
+// Node records of the children of every internal node, one wave per node:
+// lane k builds child k (its representative found by its own search).
 __global__ __launch_bounds__(256) void k_nodes(const u64 *__restrict__ K, int leaf_cap, int nsub,
                                                const TreeTotals *__restrict__ totals,
-                                               const unsigned char *__restrict__ lvl,
                                                const unsigned *__restrict__ rank,
-                                               const unsigned *__restrict__ bs,
-                                               const unsigned *__restrict__ be,
-                                               const unsigned *__restrict__ rank_bnd,
                                                const unsigned *__restrict__ nchild,
                                                const unsigned *__restrict__ cstart,
+                                               const unsigned *__restrict__ crun,
                                                BhNode *__restrict__ nodes,
                                                int *__restrict__ node_start) {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= totals->n_internal) return;
-    const unsigned i = rank_bnd[r];
-    unsigned c[9];
-    const int cnt = child_runs(K, bs[i], be[i], lvl[i], c);
-    const int base = nsub + (int)cstart[r];
-    for (int k = 0; k < cnt; ++k) {
-        const int id = base + k;
-        const int64_t a = c[k], b = c[k + 1];
+    const int lane = threadIdx.x & 63;
+    const int64_t nint = totals->n_internal, waves = (int64_t)gridDim.x * 4;
+    for (int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); r < nint; r += waves) {
+        const int cnt = (int)nchild[r];
+        if (lane >= cnt) continue;
+        const int id = nsub + (int)cstart[r] + lane;
+        const int64_t a = crun[9 * r + lane], b = crun[9 * r + lane + 1];
         BhNode nd;
         zero_stats(nd);
         nd.n = (int)(b - a);
@@ -776,6 +782,7 @@ void carve_forest(Arena &a, int64_t n, int nsub, int64_t groups, int64_t max_set
     t.rank_bnd = a.take<unsigned>(m);
     t.nchild = a.take<unsigned>(m);
     t.cstart = a.take<unsigned>(m);
+    t.crun = a.take<unsigned>(9 * (size_t)m);
     t.node_start = a.take<int>(nodes);
     t.chunk0 = reinterpret_cast<char *>(a.take<RangeStat>((m + kChunk - 1) / kChunk));
     t.chunk1 = reinterpret_cast<char *>(
@@ -826,8 +833,9 @@ gs_status build_tree(const float *q, const float *p, int64_t n, int leaf_cap, Tr
     GS_LAUNCH_CHECK("boundaries");
     unsigned *n_internal = reinterpret_cast<unsigned *>(&t.totals->n_internal);
     GS_TRY(scan_u32(t.flag, t.rank, n, t.scan_part, n_internal, s));
-    hipLaunchKernelGGL(k_children, dim3(nblk(n)), dim3(256), 0, s, K, n, t.lvl, t.flag, t.rank,
-                       t.bnd_s, t.bnd_e, t.rank_bnd, t.nchild);
+    hipLaunchKernelGGL(k_rank_bnd, dim3(nblk(n)), dim3(256), 0, s, n, t.flag, t.rank, t.rank_bnd);
+    hipLaunchKernelGGL(k_children, dim3(node_blocks(n)), dim3(256), 0, s, K, t.lvl, t.totals,
+                       t.bnd_s, t.bnd_e, t.rank_bnd, t.nchild, t.crun);
     GS_LAUNCH_CHECK("children");
     // nchild of ranks >= n_internal is never read; the scan covers n - 1
     // entries whose tail beyond n_internal may hold stale values, which only
@@ -836,9 +844,8 @@ gs_status build_tree(const float *q, const float *p, int64_t n, int leaf_cap, Tr
     hipLaunchKernelGGL(k_roots, dim3(nblk(nsub, 64)), dim3(64), 0, s, K, n, t.seg, nsub,
                        leaf_cap, t.rank, t.nchild, t.cstart, t.totals, t.meta, t.nodes,
                        t.node_start);
-    hipLaunchKernelGGL(k_nodes, dim3(nblk(n)), dim3(256), 0, s, K, leaf_cap, nsub, t.totals,
-                       t.lvl, t.rank, t.bnd_s, t.bnd_e, t.rank_bnd, t.nchild, t.cstart, t.nodes,
-                       t.node_start);
+    hipLaunchKernelGGL(k_nodes, dim3(node_blocks(n)), dim3(256), 0, s, K, leaf_cap, nsub,
+                       t.totals, t.rank, t.nchild, t.cstart, t.crun, t.nodes, t.node_start);
     const int64_t nc0 = (n + kChunk - 1) / kChunk, nc1 = (nc0 + kChunk - 1) / kChunk;
     RangeStat *c0 = reinterpret_cast<RangeStat *>(t.chunk0);
     RangeStat *c1 = reinterpret_cast<RangeStat *>(t.chunk1);
