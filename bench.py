@@ -169,7 +169,7 @@ def main():
     ap.add_argument("--leaf-cap", type=int, default=64)
     ap.add_argument("--theta", type=float, default=0.5)
     ap.add_argument("--cpu-baseline", type=int, default=1)
-    ap.add_argument("--cpu-targets", type=int, default=100000)
+    ap.add_argument("--cpu-targets", type=int, default=150000)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB before the timed "
                          "region (a kernel of known traffic for calibrating HBM counters)")

@@ -33,6 +33,10 @@ gs_status hip_fail(hipError_t e, const char *what) {
 
 // ---------------------------------------------------------------- timing
 namespace {
+// set while a launch sequence is being captured into a graph: the timing
+// events are then left out
+thread_local bool g_capturing = false;
+
 struct TimingState {
     std::mutex mu;
     bool on = false;
@@ -46,6 +50,7 @@ TimingState &timing() {
 }  // namespace
 
 void timing_begin(int kind, hipStream_t s) {
+    if (g_capturing) return;
     TimingState &t = timing();
     std::lock_guard<std::mutex> g(t.mu);
     if (!t.on) return;
@@ -56,6 +61,7 @@ void timing_begin(int kind, hipStream_t s) {
 }
 
 void timing_end(int kind, hipStream_t s) {
+    if (g_capturing) return;
     TimingState &t = timing();
     std::lock_guard<std::mutex> g(t.mu);
     if (!t.on || !t.open[kind]) return;
@@ -421,11 +427,11 @@ gs_status exact_batch_rhs(const float *q, const float *p, const int64_t *off, in
 
 gs_status exact_batch_shoot(const float *q0, const float *p0, const int64_t *off, int nsub,
                             const gs_params &prm, float *q1, float *p1, double *H, void *ws,
-                            size_t ws_bytes, hipStream_t stream) {
+                            size_t ws_bytes, hipStream_t stream, bool upload = true) {
     Arena a{static_cast<char *>(ws), kHeader, ws_bytes};
     Batch b;
     layout_batch(a, off, nsub, prm, GS_EXACT, GS_OP_SHOOT, b);
-    GS_TRY(upload_tables(b.img, b.tables, stream));
+    if (upload) GS_TRY(upload_tables(b.img, b.tables, stream));
     const double dt = 1.0 / prm.nt;
     const size_t nb = b.xp.blocks.size();
     GS_TRY(launch_pack_state_rows(b.xp, b.ex, q0, p0, prm.sigma, stream));
@@ -443,6 +449,101 @@ gs_status exact_batch_shoot(const float *q0, const float *p0, const int64_t *off
                                    stream));
     }
     return launch_unpack_state(b.ex.Sq, b.ex.Sp, off[nsub], q1, p1, stream);
+}
+
+// ---------------------------------------------------------------- graphs
+// With GS_FLAG_GRAPH a call's kernel sequence is captured once into a HIP
+// graph and replayed by later calls with the same arguments.  Capture runs on
+// a library stream (the caller's stream may be the null stream, which cannot
+// be captured); the graph is then launched on the caller's stream.  The
+// small host-planned tables are uploaded by every call, before the graph, so
+// a workspace that served other calls in between is refreshed.
+struct GraphKey {
+    int entry = 0;
+    int device = 0;
+    std::vector<uintptr_t> ptrs;
+    std::vector<int64_t> ints;
+    std::vector<double> dbls;
+    bool operator==(const GraphKey &o) const {
+        return entry == o.entry && device == o.device && ptrs == o.ptrs && ints == o.ints &&
+               dbls == o.dbls;
+    }
+};
+
+struct GraphCache {
+    std::mutex mu;
+    struct Entry {
+        GraphKey key;
+        hipGraphExec_t exec;
+        uint64_t used;
+    };
+    std::vector<Entry> entries;
+    uint64_t clock = 0;
+    hipStream_t cap[64] = {};  // capture stream per device
+};
+GraphCache &graphs() {
+    static GraphCache *c = new GraphCache;  // lives until the process ends
+    return *c;
+}
+constexpr size_t kMaxGraphs = 16;
+
+GraphKey graph_key(int entry, std::initializer_list<const void *> ptrs,
+                   std::initializer_list<int64_t> ints, const gs_params &prm) {
+    GraphKey k;
+    k.entry = entry;
+    (void)hipGetDevice(&k.device);
+    for (const void *p : ptrs) k.ptrs.push_back(reinterpret_cast<uintptr_t>(p));
+    k.ints.assign(ints.begin(), ints.end());
+    k.ints.push_back(prm.leaf_cap);
+    k.ints.push_back(prm.nt);
+    k.ints.push_back((int64_t)prm.flags);
+    k.dbls = {prm.sigma, prm.cutoff_sigmas, prm.theta};
+    return k;
+}
+
+// Replays the graph of `key`, capturing it first from `launches(stream)`.
+template <class F>
+gs_status run_graphed(GraphKey &&key, hipStream_t stream, F &&launches) {
+    GraphCache &c = graphs();
+    std::lock_guard<std::mutex> g(c.mu);
+    ++c.clock;
+    for (auto &e : c.entries)
+        if (e.key == key) {
+            e.used = c.clock;
+            GS_HIP(hipGraphLaunch(e.exec, stream));
+            return GS_OK;
+        }
+    if (key.device < 0 || key.device >= 64) {
+        set_error("graph: device index out of range");
+        return GS_ERR_UNSUPPORTED;
+    }
+    hipStream_t &cs = c.cap[key.device];
+    if (!cs) GS_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    GS_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    g_capturing = true;
+    const gs_status st = launches(cs);
+    g_capturing = false;
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(cs, &graph);
+    if (st != GS_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+    }
+    if (ec != hipSuccess) return hip_fail(ec, "hipStreamEndCapture");
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) return hip_fail(ei, "hipGraphInstantiate");
+    if (c.entries.size() >= kMaxGraphs) {  // drop the least recently used graph
+        size_t old = 0;
+        for (size_t i = 1; i < c.entries.size(); ++i)
+            if (c.entries[i].used < c.entries[old].used) old = i;
+        (void)hipGraphExecDestroy(c.entries[old].exec);
+        c.entries.erase(c.entries.begin() + (long)old);
+    }
+    c.entries.push_back({std::move(key), exec, c.clock});
+    GS_HIP(hipGraphLaunch(exec, stream));
+    return GS_OK;
 }
 
 }  // namespace
@@ -520,6 +621,27 @@ gs_status gs_shoot(const float *q0, const float *p0, int64_t n, const gs_params 
     gs_params pr = *prm;
     pr.flags &= ~GS_FLAG_F64;
     GS_TRY(check_ws(ws, ws_bytes, measure_bytes(n, &pr, method, GS_OP_SHOOT)));
+    if (prm->flags & GS_FLAG_GRAPH) {
+        const int64_t off[2] = {0, n};
+        const bool items = method == GS_EXACT && exact_items_path(prm);
+        if (items) {  // the tables, outside the graph
+            Arena a{static_cast<char *>(ws), kHeader, ws_bytes};
+            Batch b;
+            layout_batch(a, off, 1, *prm, GS_EXACT, GS_OP_SHOOT, b);
+            GS_TRY(upload_tables(b.img, b.tables, stream));
+        }
+        gs_params body = *prm;
+        body.flags &= ~GS_FLAG_GRAPH;
+        return run_graphed(graph_key(1, {q0, p0, q1, p1, H, ws}, {n, method, (int64_t)ws_bytes},
+                                     *prm),
+                           stream, [&](hipStream_t s) -> gs_status {
+                               if (items)
+                                   return exact_batch_shoot(q0, p0, off, 1, body, q1, p1, H, ws,
+                                                            ws_bytes, s, false);
+                               return gs_shoot(q0, p0, n, &body, method, q1, p1, H, ws,
+                                               ws_bytes, s);
+                           });
+    }
     Arena a{static_cast<char *>(ws), kHeader, ws_bytes};
     const double dt = 1.0 / prm->nt;
     if (method == GS_BH) {
@@ -706,13 +828,23 @@ gs_status gs_shoot_batch(const float *q0, const float *p0, const int64_t *offset
     if (n == 0) return GS_OK;
     GS_TRY(check_ptrs({q0, p0, q1, p1}));
     GS_TRY(check_ws(ws, ws_bytes, measure_batch(offsets, nsub, *prm, method, GS_OP_SHOOT)));
-    if (method == GS_EXACT)
-        return exact_batch_shoot(q0, p0, offsets, nsub, *prm, q1, p1, H, ws, ws_bytes, stream);
     Arena a{static_cast<char *>(ws), kHeader, ws_bytes};
     Batch b;
     layout_batch(a, offsets, nsub, *prm, method, GS_OP_SHOOT, b);
     GS_TRY(upload_tables(b.img, b.tables, stream));
-    return shoot_bh(q0, p0, n, *prm, q1, p1, H, b.bh, static_cast<char *>(ws), stream);
+    auto body = [&](hipStream_t s) -> gs_status {
+        if (method == GS_EXACT)
+            return exact_batch_shoot(q0, p0, offsets, nsub, *prm, q1, p1, H, ws, ws_bytes, s,
+                                     false);
+        return shoot_bh(q0, p0, n, *prm, q1, p1, H, b.bh, static_cast<char *>(ws), s);
+    };
+    if (!(prm->flags & GS_FLAG_GRAPH)) return body(stream);
+    std::initializer_list<int64_t> none = {};
+    (void)none;
+    GraphKey key = graph_key(2, {q0, p0, q1, p1, H, ws}, {n, method, (int64_t)ws_bytes, nsub},
+                             *prm);
+    key.ints.insert(key.ints.end(), offsets, offsets + nsub + 1);
+    return run_graphed(std::move(key), stream, body);
 }
 
 gs_status gs_autotune_leaf_cap(const float *q, const float *p, const int64_t *offsets,

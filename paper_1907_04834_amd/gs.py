@@ -22,6 +22,7 @@ GS_EXACT, GS_BH = 0, 1
 GS_OP_RHS, GS_OP_SHOOT, GS_OP_ADJOINT, GS_OP_FIELD = 0, 1, 2, 3
 GS_FLAG_F64 = 1
 GS_FLAG_MFMA_PAIRS = 2
+GS_FLAG_GRAPH = 4
 STATUS = {0: "GS_OK", -1: "GS_ERR_INVALID", -2: "GS_ERR_WORKSPACE", -3: "GS_ERR_HIP",
           -4: "GS_ERR_NONFINITE", -5: "GS_ERR_UNSUPPORTED"}
 
@@ -168,13 +169,30 @@ def gs_rhs_bh(q, p, prm: Params, ws=None, return_ws=False):
     return (dq, dp, ws) if return_ws else (dq, dp)
 
 
-def gs_shoot(q0, p0, prm: Params, method=GS_EXACT, with_energy=True, ws=None):
-    """Forward-Euler shooting; returns (q1, p1, H) with H float64 (nt+1,) or None."""
+def _outputs(out, q0, hshape, with_energy):
+    """(q1, p1, H): the caller's buffers `out`, checked, or new ones.  Passing
+    the same buffers again lets a GS_FLAG_GRAPH call replay its graph."""
+    if out is None:
+        H = torch.zeros(hshape, dtype=torch.float64, device=q0.device) if with_energy else None
+        return torch.empty_like(q0), torch.empty_like(q0), H
+    q1, p1, H = out
+    _pts(q1, torch.float32, "q1")
+    _pts(p1, torch.float32, "p1")
+    if q1.shape != q0.shape or p1.shape != q0.shape:
+        raise ValueError("q1 / p1 must have the shape of q0")
+    if H is not None and (H.dtype != torch.float64 or tuple(H.shape) != tuple(hshape)
+                          or not H.is_contiguous()):
+        raise ValueError(f"H must be contiguous float64 of shape {tuple(hshape)}")
+    return q1, p1, H
+
+
+def gs_shoot(q0, p0, prm: Params, method=GS_EXACT, with_energy=True, ws=None, out=None):
+    """Forward-Euler shooting; returns (q1, p1, H) with H float64 (nt+1,) or None.
+    `out` = (q1, p1, H or None) writes into the caller's buffers."""
     _pts(q0, torch.float32, "q0")
     _pts(p0, torch.float32, "p0")
     n = q0.shape[0]
-    q1, p1 = torch.empty_like(q0), torch.empty_like(p0)
-    H = torch.zeros(prm.nt + 1, dtype=torch.float64, device=q0.device) if with_energy else None
+    q1, p1, H = _outputs(out, q0, (prm.nt + 1,), with_energy)
     if ws is None:
         ws = _workspace(n, prm, method, GS_OP_SHOOT, q0.device)
     _check(lib().gs_shoot(_ptr(q0), _ptr(p0), n, ctypes.byref(prm), method, _ptr(q1),
@@ -264,15 +282,13 @@ def gs_rhs_batch(q, p, offsets, prm: Params, method=GS_EXACT, ws=None, return_ws
 
 
 def gs_shoot_batch(q0, p0, offsets, prm: Params, method=GS_EXACT, with_energy=True, ws=None,
-                   return_ws=False):
+                   return_ws=False, out=None):
     """Shooting of every set of a batch; returns (q1, p1, H) with H float64
-    (nsub, nt + 1) or None."""
+    (nsub, nt + 1) or None.  `out` = (q1, p1, H or None) as in gs_shoot."""
     _pts(q0, torch.float32, "q0")
     _pts(p0, torch.float32, "p0")
     off, nsub = _offsets(offsets)
-    q1, p1 = torch.empty_like(q0), torch.empty_like(p0)
-    H = (torch.zeros(nsub, prm.nt + 1, dtype=torch.float64, device=q0.device)
-         if with_energy else None)
+    q1, p1, H = _outputs(out, q0, (nsub, prm.nt + 1), with_energy)
     if ws is None:
         ws = _batch_workspace(off, nsub, prm, method, GS_OP_SHOOT, q0.device)
     _check(lib().gs_shoot_batch(_ptr(q0), _ptr(p0), off, nsub, ctypes.byref(prm), method,
