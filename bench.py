@@ -95,10 +95,13 @@ def cpu_baseline(w, theta, leaf_cap, exact_interactions, bh_interactions, target
 
 def population_rates(gs, W, torch, dev, theta, leaf_cap):
     """Batched shooting of the 64-subject population (sizes U{5000..40000},
-    sigma 0.05, 40 steps): one warmup and one timed call per method."""
+    sigma 0.05, 40 steps), and its objectives and gradients (forward plus
+    backward stage, checkpoints every 8 steps): one warmup and one timed call
+    per method."""
     subs = W.population()
     q, p, off = W.stack(subs)
     qt, pt = torch.from_numpy(q).to(dev), torch.from_numpy(p).to(dev)
+    yt = torch.from_numpy(np.concatenate(W.population_targets(subs))).to(dev)
     n2 = float(np.sum(np.diff(off).astype(np.float64) ** 2))
     out = {"subjects": len(subs), "points": int(off[-1]), "sum_n2": n2, "nt": subs[0].nt,
            "sigma": subs[0].sigma}
@@ -121,6 +124,13 @@ def population_rates(gs, W, torch, dev, theta, leaf_cap):
             c = gs.gs_bh_counters(ws)
             rec["interactions_per_s"] = (c["pairs"] + c["monopoles"]) / (ms / 1e3)
             rec["theta"], rec["leaf_cap"] = theta, leaf_cap
+        wa = torch.empty(gs.gs_batch_workspace_bytes(off, prm, method, gs.GS_OP_ADJOINT),
+                         dtype=torch.uint8, device=dev)
+        ms = _timed(torch, lambda: gs.gs_shoot_adjoint_batch(qt, pt, yt, off, prm, method, 0.01,
+                                                             8, ws=wa))
+        rec["adjoint"] = {"ckpt_every": 8, "lambda": 0.01, "ms_per_batch_gradient": ms,
+                          "subject_gradients_per_s": len(subs) / (ms / 1e3)}
+        del wa
         out[name] = rec
     return out
 

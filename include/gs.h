@@ -195,8 +195,9 @@ gs_status gs_field(const float *x, int64_t m, const float *q, const float *p, in
  * interaction between sets), in shared launches.  The library copies small
  * tables derived from `offsets` into the workspace with an asynchronous copy
  * from its own pinned staging memory; `offsets` may be freed on return.
- * The workspace comes from gs_batch_workspace_bytes (op GS_OP_RHS or
- * GS_OP_SHOOT; 0 for invalid arguments). */
+ * The workspace comes from gs_batch_workspace_bytes (op GS_OP_RHS,
+ * GS_OP_SHOOT or GS_OP_ADJOINT, the last with ckpt_every = 8; 0 for invalid
+ * arguments). */
 size_t gs_batch_workspace_bytes(const int64_t *offsets, int32_t nsub, const gs_params *prm,
                                 int32_t method, int32_t op);
 
@@ -211,6 +212,24 @@ gs_status gs_shoot_batch(const float *q0, const float *p0, const int64_t *offset
                          int32_t nsub, const gs_params *prm, int32_t method, float *q1,
                          float *p1, double *H, void *ws, size_t ws_bytes,
                          hipStream_t stream);
+
+/* Objective and gradient of every set (gs_shoot_adjoint per set, Sec. 2.1
+ * eq. 2 and the backward stage of Sec. 2.2; subjects of a population are
+ * registered independently, Sec. 3.2).  Set s has
+ *   E_s = (1/n_s) sum_{i in s} |q_i(1) - target_i|^2 + lambda <p0, K(q0) p0>_s
+ * with n_s its number of points; grad_p0 rows of set s hold dE_s/dp0.
+ * objective is a DEVICE double[nsub] (0 for an empty set); target and grad_p0
+ * are DEVICE float[n][3], n = offsets[nsub] (n == 0: no-op).  Checkpoints as
+ * in gs_shoot_adjoint.  The workspace comes from
+ * gs_adjoint_batch_workspace_bytes (0 for invalid arguments). */
+size_t gs_adjoint_batch_workspace_bytes(const int64_t *offsets, int32_t nsub,
+                                        const gs_params *prm, int32_t method,
+                                        int32_t ckpt_every);
+gs_status gs_shoot_adjoint_batch(const float *q0, const float *p0, const float *target,
+                                 const int64_t *offsets, int32_t nsub, const gs_params *prm,
+                                 int32_t method, double lambda, int32_t ckpt_every,
+                                 double *objective, float *grad_p0, void *ws, size_t ws_bytes,
+                                 hipStream_t stream);
 
 /* Tuning of the Barnes-Hut leaf capacity for given inputs (one set: offsets
  * {0, n}, nsub 1; or a batch).  Times one right-hand side for each leaf_cap

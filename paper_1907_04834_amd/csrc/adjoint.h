@@ -1,4 +1,6 @@
-// adjoint.h -- backward stage (discrete adjoint of the Euler flow).
+// adjoint.h -- backward stage (discrete adjoint of the Euler flow) of one
+// point set or of a batch of independent sets stored one after the other
+// (set s = points [offsets[s], offsets[s+1])); one set is a batch of one.
 #pragma once
 
 #include "internal.h"
@@ -6,38 +8,51 @@
 
 namespace gs {
 
-// Buffers of the Barnes-Hut backward stage.
+// Buffers of the Barnes-Hut backward products.
 struct BhAdjBufs {
     float4 *ALs, *BEs;  // alpha, beta in Morton order (FP32)
-    double *gq, *gp;    // per-target products J^T (alpha, beta) (original order)
 };
 BhAdjBufs layout_bh_adjoint(Arena &a, int64_t n);
 
 struct AdjointBufs {
-    int64_t n;
-    int nt, ckpt, nck, nblk;  // nblk: data-term partials (blocks of 256 points)
-    int nh;                   // energy partials (blocks, or tree groups on the tree path)
+    int64_t n;                // points of all sets
+    int nsub, nt, ckpt, nck;
     bool bh;
-    ExactPlan pl;
-    ExactBufs ex;             // packed state and partial sums of the exact kernels
-    float4 *AL, *BE;          // packed adjoint variables (exact path)
-    double *Sq, *Sp;          // FP64 state
-    double *al, *be;          // FP64 adjoint variables
-    double *v0;               // velocity at t = 0
+    // exact path: the work-item plan, its packed state and partial sums
+    const ExactBatchPlan *xp;
+    ExactBatchBufs ex;
+    float4 *AL, *BE;          // [npad] packed adjoint variables (alpha / k, beta)
+    // Barnes-Hut path: the forest, its FP32 copies and traversal buffers
+    ShootBhBufs sh;
+    BhAdjBufs bhadj;
+    // both paths
+    double *Sq, *Sp;          // FP64 state [n][3] (ex.Sq / sh.Sq)
+    double *al, *be;          // FP64 adjoint variables [n][3]
+    double *v0;               // velocity at t = 0 [n][3]
     double *ckq, *ckp;        // checkpoints [nck][n][3]
     double *segq, *segp;      // states of one segment [ckpt][n][3]
-    double *hpart, *dpart;    // energy and data-term block partials
-    ShootBhBufs sh;           // Barnes-Hut forward buffers (tree, FP32 copies)
-    BhAdjBufs bhadj;
+    double *hpart;            // energy partials of step 0 (exact: row blocks, BH: groups)
+    int nh;
+    const int *hseg;          // [nsub + 1] partial range of each set
+    double *dpart;            // data-term partials, one per unit
+    int nunits;
+    const int4 *units;        // [nunits] (first point, count <= 256, set, -)
+    const int *useg;          // [nsub + 1] unit range of each set
+    const double *setn;       // [nsub] points of each set
+    double *dsum, *hsum;      // [nsub] data term and energy of each set
 };
-AdjointBufs layout_adjoint(Arena &a, int64_t n, int nt, int ckpt, int method);
+// Carves the buffers that both paths add to their forward buffers; the
+// caller fills the path-specific members and the tables.
+void carve_adjoint_common(Arena &a, int64_t n, int nsub, int nt, int ckpt, int nunits,
+                          AdjointBufs &b);
 
+// objective: DEVICE double[nsub]; grad: float [n][3].
 gs_status shoot_adjoint(const float *q0, const float *p0, const float *y, const gs_params &prm,
                         double lambda, double *objective, float *grad, AdjointBufs &b, char *ws,
                         hipStream_t s);
 
 // Barnes-Hut hooks (bh_adjoint.hip).
-gs_status bh_adjoint_begin(AdjointBufs &b, char *ws, hipStream_t s);
+gs_status bh_adjoint_begin(char *ws, hipStream_t s);
 gs_status bh_adjoint_forward_step(AdjointBufs &b, const gs_params &prm, double dt, double *v0,
                                   char *ws, hipStream_t s);
 gs_status bh_adjoint_step(AdjointBufs &b, const gs_params &prm, double dt, const double *sq,

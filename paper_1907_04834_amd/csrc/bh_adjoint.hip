@@ -94,18 +94,35 @@ __device__ inline void adj_pair(float4 x, float4 px, float4 ax, float4 bx, float
     gp[2] = fmaf(w3, pj.z, gp[2]);
 }
 
+// One wave per traversal group: `count` consecutive sorted targets from
+// `first`, all in the tree whose root is node `root` (gtab null: group g is
+// targets [64 g, 64 g + 64) of the single tree rooted at node 0).
 __global__ __launch_bounds__(256) void k_bh_adj_traverse(
     const BhNode *__restrict__ nodes, const double *__restrict__ adj,
     const float4 *__restrict__ Qs, const float4 *__restrict__ Ps, const float4 *__restrict__ As,
-    const float4 *__restrict__ Bs, const unsigned *__restrict__ perm, int64_t n, BhParams bp,
-    double dt, double *__restrict__ al, double *__restrict__ be, u64 *__restrict__ counters,
+    const float4 *__restrict__ Bs, const unsigned *__restrict__ perm, int64_t n,
+    const GroupDesc *__restrict__ gtab, int64_t groups, BhParams bp, double dt,
+    double *__restrict__ al, double *__restrict__ be, u64 *__restrict__ counters,
     int *__restrict__ status) {
     __shared__ AdjLds lds_all[4];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     AdjLds &L = lds_all[wv];
-    const int64_t t = ((int64_t)blockIdx.x * 4 + wv) * 64 + lane;
-    if ((t - lane) >= n) return;  // wave-uniform; no block barrier in this kernel
-    const bool active = t < n;
+    const int64_t grp = (int64_t)blockIdx.x * 4 + wv;
+    if (grp >= groups) return;  // wave-uniform; no block barrier in this kernel
+    int64_t first, count;
+    int root;
+    if (gtab) {
+        const GroupDesc d = gtab[grp];
+        first = d.first;
+        count = d.count;
+        root = d.root;
+    } else {
+        first = grp * 64;
+        count = n - first < 64 ? n - first : 64;
+        root = 0;
+    }
+    const int64_t t = first + lane;
+    const bool active = lane < count;
     const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
     const float4 xq = active ? Qs[t] : z4, xp = active ? Ps[t] : z4;
     const float4 xa = active ? As[t] : z4, xb = active ? Bs[t] : z4;
@@ -117,7 +134,7 @@ __global__ __launch_bounds__(256) void k_bh_adj_traverse(
     int sp = 0;
     const u64 live = __ballot(active);
     if (live != 0ull) {
-        L.first[0] = 0;
+        L.first[0] = root;
         L.count[0] = 1;
         L.mask[0] = live;
         sp = 1;
@@ -243,13 +260,10 @@ BhAdjBufs layout_bh_adjoint(Arena &a, int64_t n) {
     const int64_t m = n > 1 ? n : 1;
     b.ALs = a.take<float4>(m);
     b.BEs = a.take<float4>(m);
-    b.gq = nullptr;
-    b.gp = nullptr;
     return b;
 }
 
-gs_status bh_adjoint_begin(AdjointBufs &b, char *ws, hipStream_t s) {
-    (void)b;
+gs_status bh_adjoint_begin(char *ws, hipStream_t s) {
     hipLaunchKernelGGL(k_clear, dim3(1), dim3(64), 0, s, reinterpret_cast<int *>(ws),
                        reinterpret_cast<u64 *>(ws + 8));
     GS_LAUNCH_CHECK("clear");
@@ -292,9 +306,9 @@ gs_status bh_adjoint_step(AdjointBufs &b, const gs_params &prm, double dt, const
     GS_LAUNCH_CHECK("gather_ab");
     GS_TRY(tree_range_sums(b.bhadj.ALs, b.bhadj.BEs, t, t.adj, s));
     timing_begin(KIND_ADJOINT, s);
-    hipLaunchKernelGGL(k_bh_adj_traverse, dim3(nblk(n, 256)), dim3(256), 0, s, t.nodes, t.adj,
-                       t.Qs, t.Ps, b.bhadj.ALs, b.bhadj.BEs, t.perm, n, make_bh_params(prm), dt,
-                       b.al, b.be, counters, status);
+    hipLaunchKernelGGL(k_bh_adj_traverse, dim3(nblk(t.groups, 4)), dim3(256), 0, s, t.nodes,
+                       t.adj, t.Qs, t.Ps, b.bhadj.ALs, b.bhadj.BEs, t.perm, n, t.gtab, t.groups,
+                       make_bh_params(prm), dt, b.al, b.be, counters, status);
     timing_end(KIND_ADJOINT, s);
     GS_LAUNCH_CHECK("bh_adj_traverse");
     return GS_OK;

@@ -198,7 +198,8 @@ float4 *layout_field(Arena &a, int64_t big, ExactBufs &b) {
     return a.take<float4>(pl.ntgt > pl.nsrc ? pl.ntgt : pl.nsrc);
 }
 
-size_t measure_batch(const int64_t *off, int nsub, const gs_params &prm, int method, int op);
+size_t measure_batch(const int64_t *off, int nsub, const gs_params &prm, int method, int op,
+                     int ckpt = 8);
 
 // The single-set exact FP32 right-hand side and shooting run as a batch of
 // one set (the work-item kernel); the opt-in matrix-core variant keeps the
@@ -234,9 +235,8 @@ size_t measure_bytes(int64_t n, const gs_params *prm, int32_t method, int32_t op
             }
             break;
         case GS_OP_ADJOINT: {
-            const int ck = prm->nt < 8 ? prm->nt : 8;
-            layout_adjoint(a, n, prm->nt, ck, method);
-            break;
+            const int64_t off[2] = {0, n};
+            return measure_batch(off, 1, *prm, method, GS_OP_ADJOINT);
         }
         case GS_OP_FIELD: {
             ExactBufs b;
@@ -296,26 +296,54 @@ struct Batch {
     ExactBatchPlan xp;
     ExactBatchBufs ex{};
     ShootBhBufs bh{};
+    AdjointBufs adj{};
     TableImage img;
     char *tables = nullptr;
 };
 
 // Lays out (or measures, when the arena has no base) the buffers of a
-// batched call and prepares its tables.
+// batched call and prepares its tables.  `ckpt` is the checkpoint interval
+// of op GS_OP_ADJOINT.  The Batch must stay where it is while in use
+// (b.adj points at b.xp).
 void layout_batch(Arena &a, const int64_t *off, int nsub, const gs_params &prm, int method,
-                  int op, Batch &b) {
+                  int op, Batch &b, int ckpt = 8) {
     const int nt = op == GS_OP_SHOOT ? prm.nt : 0;
+    const bool adj = op == GS_OP_ADJOINT;
+    const int ck = ckpt < prm.nt ? ckpt : prm.nt;
+    std::vector<double> setn;  // points of each set (backward stage)
+    if (adj)
+        for (int s = 0; s < nsub; ++s) setn.push_back((double)(off[s + 1] - off[s]));
     if (method == GS_EXACT) {
         b.xp = plan_exact_batch(off, nsub);
         carve_exact_batch(a, b.xp, nt, b.ex);
+        const int nb = (int)b.xp.blocks.size();
+        if (adj) {
+            b.adj.AL = a.take<float4>(b.xp.npad);
+            b.adj.BE = a.take<float4>(b.xp.npad);
+            carve_adjoint_common(a, off[nsub], nsub, prm.nt, ck, nb, b.adj);
+        }
         const size_t o_items = b.img.add(b.xp.items.data(), b.xp.items.size());
         const size_t o_blk = b.img.add(b.xp.blocks.data(), b.xp.blocks.size());
         const size_t o_bseg = b.img.add(b.xp.bseg.data(), b.xp.bseg.size());
+        const size_t o_setn = b.img.add(setn.data(), setn.size());
         b.tables = a.take<char>(b.img.bytes.size());
         if (b.tables) {
             b.ex.items = reinterpret_cast<const int4 *>(b.tables + o_items);
             b.ex.blk = reinterpret_cast<const int4 *>(b.tables + o_blk);
             b.ex.bseg = reinterpret_cast<const int *>(b.tables + o_bseg);
+        }
+        if (adj) {  // reduction units: the row blocks, which never straddle two sets
+            b.adj.bh = false;
+            b.adj.xp = &b.xp;
+            b.adj.ex = b.ex;
+            b.adj.Sq = b.ex.Sq;
+            b.adj.Sp = b.ex.Sp;
+            b.adj.hpart = b.ex.Hpart;
+            b.adj.nh = nb;
+            b.adj.hseg = b.ex.bseg;
+            b.adj.units = b.ex.blk;
+            b.adj.useg = b.ex.bseg;
+            b.adj.setn = b.tables ? reinterpret_cast<const double *>(b.tables + o_setn) : nullptr;
         }
         return;
     }
@@ -341,25 +369,58 @@ void layout_batch(Arena &a, const int64_t *off, int nsub, const gs_params &prm, 
     seg[nsub] = off[nsub];
     gseg[nsub] = (int)gt.size();
     const int64_t ntot = off[nsub];
-    if (op == GS_OP_SHOOT)
+    if (op == GS_OP_SHOOT || adj)
         b.bh = layout_shoot_forest(a, ntot, nsub, (int64_t)gt.size(), max_set, nt);
     else
         carve_forest(a, ntot, nsub, (int64_t)gt.size(), max_set, b.bh.tree);
+    // reduction units of the backward stage: blocks of <= 256 points of one set
+    std::vector<int4> units;
+    std::vector<int> useg(nsub + 1);
+    if (adj) {
+        for (int s = 0; s < nsub; ++s) {
+            useg[s] = (int)units.size();
+            for (int64_t i = off[s]; i < off[s + 1]; i += 256)
+                units.push_back(make_int4((int)i, (int)(off[s + 1] - i < 256 ? off[s + 1] - i : 256),
+                                          s, 0));
+        }
+        useg[nsub] = (int)units.size();
+        b.adj.bhadj = layout_bh_adjoint(a, ntot);
+        carve_adjoint_common(a, ntot, nsub, prm.nt, ck, (int)units.size(), b.adj);
+    }
     const size_t o_seg = b.img.add(seg.data(), seg.size());
     const size_t o_gt = b.img.add(gt.data(), gt.size());
     const size_t o_gseg = b.img.add(gseg.data(), gseg.size());
+    const size_t o_units = b.img.add(units.data(), units.size());
+    const size_t o_useg = b.img.add(useg.data(), adj ? useg.size() : 0);
+    const size_t o_setn = b.img.add(setn.data(), setn.size());
     b.tables = a.take<char>(b.img.bytes.size());
     if (b.tables) {
         b.bh.tree.seg = reinterpret_cast<const long long *>(b.tables + o_seg);
         b.bh.tree.gtab = reinterpret_cast<const GroupDesc *>(b.tables + o_gt);
         b.bh.gseg = reinterpret_cast<const int *>(b.tables + o_gseg);
     }
+    if (adj) {
+        b.adj.bh = true;
+        b.adj.xp = nullptr;
+        b.adj.sh = b.bh;
+        b.adj.Sq = b.bh.Sq;
+        b.adj.Sp = b.bh.Sp;
+        b.adj.hpart = b.bh.Hpart;
+        b.adj.nh = (int)gt.size();
+        b.adj.hseg = b.bh.gseg;
+        if (b.tables) {
+            b.adj.units = reinterpret_cast<const int4 *>(b.tables + o_units);
+            b.adj.useg = reinterpret_cast<const int *>(b.tables + o_useg);
+            b.adj.setn = reinterpret_cast<const double *>(b.tables + o_setn);
+        }
+    }
 }
 
-size_t measure_batch(const int64_t *off, int nsub, const gs_params &prm, int method, int op) {
+size_t measure_batch(const int64_t *off, int nsub, const gs_params &prm, int method, int op,
+                     int ckpt) {
     Arena a{nullptr, kHeader, 0};
     Batch b;
-    layout_batch(a, off, nsub, prm, method, op, b);
+    layout_batch(a, off, nsub, prm, method, op, b, ckpt);
     return a.off + 256;
 }
 
@@ -411,6 +472,20 @@ gs_status check_batch_call(const int64_t *offsets, int32_t nsub, const gs_params
         return GS_ERR_INVALID;
     }
     return check_params(prm, need_nt, method == GS_BH);
+}
+
+// Objective and gradient of every set (one set: a batch of one).
+gs_status adjoint_batch_call(const float *q0, const float *p0, const float *y,
+                             const int64_t *off, int nsub, const gs_params &prm, int method,
+                             double lambda, int ckpt, double *objective, float *grad, void *ws,
+                             size_t ws_bytes, hipStream_t stream) {
+    GS_TRY(check_ws(ws, ws_bytes, measure_batch(off, nsub, prm, method, GS_OP_ADJOINT, ckpt)));
+    Arena a{static_cast<char *>(ws), kHeader, ws_bytes};
+    Batch b;
+    layout_batch(a, off, nsub, prm, method, GS_OP_ADJOINT, b, ckpt);
+    GS_TRY(upload_tables(b.img, b.tables, stream));
+    return shoot_adjoint(q0, p0, y, prm, lambda, objective, grad, b.adj, static_cast<char *>(ws),
+                         stream);
 }
 
 gs_status exact_batch_rhs(const float *q, const float *p, const int64_t *off, int nsub,
@@ -724,10 +799,8 @@ size_t gs_adjoint_workspace_bytes(int64_t n, const gs_params *prm, int32_t metho
                                   int32_t ckpt_every) {
     if (check_n(n) != GS_OK || !prm || prm->nt < 1 || ckpt_every < 1) return 0;
     if (method != GS_EXACT && method != GS_BH) return 0;
-    Arena a{nullptr, kHeader, 0};
-    const int ck = ckpt_every < prm->nt ? ckpt_every : prm->nt;
-    layout_adjoint(a, n, prm->nt, ck, method);
-    return a.off + 256;
+    const int64_t off[2] = {0, n};
+    return measure_batch(off, 1, *prm, method, GS_OP_ADJOINT, ckpt_every);
 }
 
 gs_status gs_shoot_adjoint(const float *q0, const float *p0, const float *target, int64_t n,
@@ -750,13 +823,36 @@ gs_status gs_shoot_adjoint(const float *q0, const float *p0, const float *target
     }
     if (n == 0) return GS_OK;
     GS_TRY(check_ptrs({q0, p0, target, objective, grad_p0}));
-    const size_t need = gs_adjoint_workspace_bytes(n, prm, method, ckpt_every);
-    GS_TRY(check_ws(ws, ws_bytes, need));
-    Arena a{static_cast<char *>(ws), kHeader, ws_bytes};
-    const int ck = ckpt_every < prm->nt ? ckpt_every : prm->nt;
-    AdjointBufs b = layout_adjoint(a, n, prm->nt, ck, method);
-    return shoot_adjoint(q0, p0, target, *prm, lambda, objective, grad_p0, b,
-                         static_cast<char *>(ws), stream);
+    const int64_t off[2] = {0, n};
+    return adjoint_batch_call(q0, p0, target, off, 1, *prm, method, lambda, ckpt_every,
+                              objective, grad_p0, ws, ws_bytes, stream);
+}
+
+size_t gs_adjoint_batch_workspace_bytes(const int64_t *offsets, int32_t nsub,
+                                        const gs_params *prm, int32_t method,
+                                        int32_t ckpt_every) {
+    if (check_batch_call(offsets, nsub, prm, method, true) != GS_OK || ckpt_every < 1) return 0;
+    return measure_batch(offsets, nsub, *prm, method, GS_OP_ADJOINT, ckpt_every);
+}
+
+gs_status gs_shoot_adjoint_batch(const float *q0, const float *p0, const float *target,
+                                 const int64_t *offsets, int32_t nsub, const gs_params *prm,
+                                 int32_t method, double lambda, int32_t ckpt_every,
+                                 double *objective, float *grad_p0, void *ws, size_t ws_bytes,
+                                 hipStream_t stream) {
+    GS_TRY(check_batch_call(offsets, nsub, prm, method, true));
+    if (!std::isfinite(lambda)) {
+        set_error("lambda must be finite");
+        return GS_ERR_INVALID;
+    }
+    if (ckpt_every < 1) {
+        set_error("ckpt_every must be >= 1 (got %d)", ckpt_every);
+        return GS_ERR_INVALID;
+    }
+    if (offsets[nsub] == 0) return GS_OK;
+    GS_TRY(check_ptrs({q0, p0, target, objective, grad_p0}));
+    return adjoint_batch_call(q0, p0, target, offsets, nsub, *prm, method, lambda, ckpt_every,
+                              objective, grad_p0, ws, ws_bytes, stream);
 }
 
 gs_status gs_field(const float *x, int64_t m, const float *q, const float *p, int64_t n,
@@ -798,8 +894,8 @@ gs_status gs_field(const float *x, int64_t m, const float *q, const float *p, in
 
 size_t gs_batch_workspace_bytes(const int64_t *offsets, int32_t nsub, const gs_params *prm,
                                 int32_t method, int32_t op) {
-    if (op != GS_OP_RHS && op != GS_OP_SHOOT) return 0;
-    if (check_batch_call(offsets, nsub, prm, method, op == GS_OP_SHOOT) != GS_OK) return 0;
+    if (op != GS_OP_RHS && op != GS_OP_SHOOT && op != GS_OP_ADJOINT) return 0;
+    if (check_batch_call(offsets, nsub, prm, method, op != GS_OP_RHS) != GS_OK) return 0;
     return measure_batch(offsets, nsub, *prm, method, op);
 }
 
@@ -839,8 +935,6 @@ gs_status gs_shoot_batch(const float *q0, const float *p0, const int64_t *offset
         return shoot_bh(q0, p0, n, *prm, q1, p1, H, b.bh, static_cast<char *>(ws), s);
     };
     if (!(prm->flags & GS_FLAG_GRAPH)) return body(stream);
-    std::initializer_list<int64_t> none = {};
-    (void)none;
     GraphKey key = graph_key(2, {q0, p0, q1, p1, H, ws}, {n, method, (int64_t)ws_bytes, nsub},
                              *prm);
     key.ints.insert(key.ints.end(), offsets, offsets + nsub + 1);

@@ -584,6 +584,25 @@ __global__ __launch_bounds__(256) void k_pack_state_rows(const float *__restrict
     }
 }
 
+// FP64 [n][3] pair (a, b) -> packed FP32 rows (sa a, b), zero padding.
+__global__ __launch_bounds__(256) void k_pack_rows64(const double *__restrict__ a,
+                                                     const double *__restrict__ b,
+                                                     const int4 *__restrict__ blk, double sa,
+                                                     float4 *__restrict__ A,
+                                                     float4 *__restrict__ B) {
+    const int4 d = blk[blockIdx.x];
+    const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if ((int)threadIdx.x < d.y) {
+        const int64_t i = (int64_t)d.x + threadIdx.x;
+        A[row] = make_float4((float)(sa * a[3 * i]), (float)(sa * a[3 * i + 1]),
+                             (float)(sa * a[3 * i + 2]), 0.f);
+        B[row] = make_float4((float)b[3 * i], (float)b[3 * i + 1], (float)b[3 * i + 2], 0.f);
+    } else {
+        A[row] = make_float4(0.f, 0.f, 0.f, 0.f);
+        B[row] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+}
+
 // inv_s2 here is 1 / (k sigma^2): the a-sums were taken on scaled positions.
 __global__ __launch_bounds__(256) void k_combine_rows(const double *__restrict__ part,
                                                       int64_t npad, const int4 *__restrict__ blk,
@@ -594,7 +613,8 @@ __global__ __launch_bounds__(256) void k_combine_rows(const double *__restrict__
                                                       double *__restrict__ Sp,
                                                       float4 *__restrict__ Q,
                                                       float4 *__restrict__ P,
-                                                      double *__restrict__ Hpart) {
+                                                      double *__restrict__ Hpart,
+                                                      double *__restrict__ vout) {
     __shared__ double lds[8];
     const int4 d = blk[blockIdx.x];
     const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -619,6 +639,9 @@ __global__ __launch_bounds__(256) void k_combine_rows(const double *__restrict__
                 p[c] = Sp[3 * i + c];
             }
             e = p[0] * acc[0] + p[1] * acc[1] + p[2] * acc[2];
+            if (vout)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) vout[3 * i + c] = acc[c];
             if (dt > 0.0) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
@@ -994,7 +1017,16 @@ void carve_exact_batch(Arena &a, const ExactBatchPlan &pl, int nt, ExactBatchBuf
 }
 
 // k = sqrt(log2(e) / (2 sigma^2)): the items kernel works on k q.
-static double position_scale(double sigma) { return sqrt(kLog2e / (2.0 * sigma * sigma)); }
+double position_scale(double sigma) { return sqrt(kLog2e / (2.0 * sigma * sigma)); }
+
+gs_status launch_pack_rows64(const ExactBatchPlan &pl, const int4 *blk, const double *a,
+                             const double *b, double sa, float4 *A, float4 *B, hipStream_t s) {
+    if (pl.blocks.empty()) return GS_OK;
+    hipLaunchKernelGGL(k_pack_rows64, dim3((unsigned)pl.blocks.size()), dim3(256), 0, s, a, b,
+                       blk, sa, A, B);
+    GS_LAUNCH_CHECK("pack_rows64");
+    return GS_OK;
+}
 
 gs_status launch_pack_state_rows(const ExactBatchPlan &pl, const ExactBatchBufs &b,
                                  const float *q, const float *p, double sigma, hipStream_t s) {
@@ -1024,12 +1056,12 @@ gs_status launch_exact_items(const ExactBatchPlan &pl, const ExactBatchBufs &b, 
 
 gs_status launch_combine_rows(const ExactBatchPlan &pl, const ExactBatchBufs &b, double sigma,
                               int mode, float *dq, float *dp, double dt, double *Hpart,
-                              hipStream_t s) {
+                              hipStream_t s, double *vout) {
     if (pl.blocks.empty()) return GS_OK;
     const double ks = position_scale(sigma);
     hipLaunchKernelGGL(k_combine_rows, dim3((unsigned)pl.blocks.size()), dim3(256), 0, s, b.part,
                        pl.npad, b.blk, 1.0 / (ks * sigma * sigma), ks, mode, dq, dp, dt, b.Sq,
-                       b.Sp, b.Q, b.P, Hpart);
+                       b.Sp, b.Q, b.P, Hpart, vout);
     GS_LAUNCH_CHECK("combine_rows");
     return GS_OK;
 }

@@ -161,11 +161,18 @@ gs_status launch_pack_state_rows(const ExactBatchPlan &pl, const ExactBatchBufs 
                                  const float *q, const float *p, double sigma, hipStream_t s);
 gs_status launch_exact_items(const ExactBatchPlan &pl, const ExactBatchBufs &b, double sigma,
                              bool with_a, hipStream_t s);
-// mode 0: (dq, dp) = (v, a); mode 1: energy partials into Hpart (nullable)
-// and, if dt > 0, the Euler step of the FP64 state and its packed copies.
+// mode 0: (dq, dp) = (v, a); mode 1: energy partials into Hpart (nullable),
+// the velocity into vout (FP64 [ntot][3], nullable) and, if dt > 0, the
+// Euler step of the FP64 state and its packed copies.
 gs_status launch_combine_rows(const ExactBatchPlan &pl, const ExactBatchBufs &b, double sigma,
                               int mode, float *dq, float *dp, double dt, double *Hpart,
-                              hipStream_t s);
+                              hipStream_t s, double *vout = nullptr);
+// k = sqrt(log2(e) / (2 sigma^2)), the factor of the stored positions.
+double position_scale(double sigma);
+// Packs FP64 [ntot][3] arrays (a, b) into rows (sa a, b) as float4 (zero
+// padding), with the row blocks `blk` of the plan (device table).
+gs_status launch_pack_rows64(const ExactBatchPlan &pl, const int4 *blk, const double *a,
+                             const double *b, double sa, float4 *A, float4 *B, hipStream_t s);
 
 // FP64 exact path.
 gs_status launch_exact_f64(const double *q, const double *p, int64_t n, double sigma,

@@ -69,6 +69,9 @@ _SIGS = {
     "gs_rhs_batch": (ctypes.c_int, [_vp, _vp, _vp, _i32, _PP, _i32, _vp, _vp, _vp, _sz, _vp]),
     "gs_shoot_batch": (ctypes.c_int, [_vp, _vp, _vp, _i32, _PP, _i32, _vp, _vp, _vp, _vp, _sz,
                                       _vp]),
+    "gs_adjoint_batch_workspace_bytes": (_sz, [_vp, _i32, _PP, _i32, _i32]),
+    "gs_shoot_adjoint_batch": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i32, _PP, _i32, _dbl, _i32,
+                                              _vp, _vp, _vp, _sz, _vp]),
     "gs_autotune_leaf_cap": (ctypes.c_int, [_vp, _vp, _vp, _i32, _PP, _vp, _vp, _vp, _sz,
                                             _vp, ctypes.POINTER(ctypes.c_double)]),
     "gs_get_status": (ctypes.c_int, [_vp, _vp]),
@@ -295,6 +298,30 @@ def gs_shoot_batch(q0, p0, offsets, prm: Params, method=GS_EXACT, with_energy=Tr
                                 _ptr(q1), _ptr(p1), _ptr(H), _ptr(ws), ws.numel(),
                                 _stream(q0.device)))
     return (q1, p1, H, ws) if return_ws else (q1, p1, H)
+
+
+def gs_shoot_adjoint_batch(q0, p0, target, offsets, prm: Params, method=GS_EXACT, lam=0.01,
+                           ckpt_every=8, ws=None):
+    """Per-set objectives E_s (float64 (nsub,)) and dE_s/dp0 of every set
+    (float32 (n, 3), rows of set s from its own objective)."""
+    _pts(q0, torch.float32, "q0")
+    _pts(p0, torch.float32, "p0")
+    _pts(target, torch.float32, "target")
+    off, nsub = _offsets(offsets)
+    obj = torch.zeros(nsub, dtype=torch.float64, device=q0.device)
+    grad = torch.empty_like(p0)
+    if ws is None:
+        nbytes = lib().gs_adjoint_batch_workspace_bytes(off, nsub, ctypes.byref(prm), method,
+                                                        int(ckpt_every))
+        if nbytes == 0:
+            raise GsError(-1, "invalid arguments for gs_adjoint_batch_workspace_bytes: "
+                              + lib().gs_last_error().decode())
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=q0.device)
+    _check(lib().gs_shoot_adjoint_batch(_ptr(q0), _ptr(p0), _ptr(target), off, nsub,
+                                        ctypes.byref(prm), method, float(lam), int(ckpt_every),
+                                        _ptr(obj), _ptr(grad), _ptr(ws), ws.numel(),
+                                        _stream(q0.device)))
+    return obj, grad
 
 
 def gs_autotune_leaf_cap(q, p, prm: Params, offsets=None, ws=None):

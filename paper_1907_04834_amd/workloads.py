@@ -183,6 +183,19 @@ def population(seed=5000, subjects=64, nmin=5000, nmax=40000):
     return out
 
 
+def population_targets(subjects, seed=6000):
+    """Registration targets of a population: each subject's template moved
+    by its own smooth displacement (16 Gaussian bumps of width 0.3,
+    amplitude 0.03), as the target of the gradient workload."""
+    out = []
+    for s, w in enumerate(subjects):
+        rng = np.random.default_rng(seed + s)
+        q = w.q0.astype(np.float64)
+        y = q + bump_field(rng, q, m=16, width=0.3, amp=0.03) if w.n else q
+        out.append(_round(y, "f32"))
+    return out
+
+
 def stack(subjects):
     """Concatenates the point sets of a batch: (q, p, offsets) with set s in
     rows offsets[s]..offsets[s+1] (float32 (N, 3) arrays, int64 offsets)."""

@@ -112,7 +112,18 @@ def test_batch_workspace_sizes():
     one = gs.gs_batch_workspace_bytes([0, 20000], prm, gs.GS_BH, gs.GS_OP_SHOOT)
     single = gs.gs_workspace_bytes(20000, prm, gs.GS_BH, gs.GS_OP_SHOOT)
     assert abs(one - single) < 0.05 * single
-    assert gs.gs_batch_workspace_bytes([0, 10], prm, gs.GS_EXACT, gs.GS_OP_ADJOINT) == 0
+    # the backward stage: GS_OP_ADJOINT sizes for checkpoints every 8 steps
+    for method in (gs.GS_EXACT, gs.GS_BH):
+        adj = gs.gs_batch_workspace_bytes(offs, prm, method, gs.GS_OP_ADJOINT)
+        assert adj == gs.lib().gs_adjoint_batch_workspace_bytes(_off(offs), len(offs) - 1,
+                                                                ctypes.byref(prm), method, 8)
+        assert adj > gs.gs_batch_workspace_bytes(offs, prm, method, gs.GS_OP_SHOOT) // 2
+        # a one-set batch is what the single-set call uses
+        assert (gs.lib().gs_adjoint_batch_workspace_bytes(_off([0, 7000]), 1, ctypes.byref(prm),
+                                                          method, 5)
+                == gs.lib().gs_adjoint_workspace_bytes(7000, ctypes.byref(prm), method, 5))
+    assert gs.lib().gs_adjoint_batch_workspace_bytes(_off(offs), len(offs) - 1,
+                                                     ctypes.byref(prm), gs.GS_BH, 0) == 0
 
 
 @pytest.mark.parametrize("offs,nsub,msg", [
@@ -145,3 +156,23 @@ def test_batch_rejects_null_offsets_bad_method_and_small_workspace():
     st = _call("gs_shoot_batch", None, None, _off([0, 0, 0]), 2, ctypes.byref(prm), gs.GS_BH,
                None, None, None, None, 0, None)
     assert st == 0
+
+
+def test_adjoint_batch_rejects_bad_arguments():
+    prm = gs.params(0.1, nt=4)
+    off = _off([0, 10, 30])
+
+    def call(offs, nsub, lam=0.01, ck=2, method=gs.GS_EXACT, ws_bytes=1 << 30, q=FAKE):
+        return _call("gs_shoot_adjoint_batch", q, FAKE, FAKE, offs, nsub, ctypes.byref(prm),
+                     method, ctypes.c_double(lam), ck, FAKE, FAKE, FAKE, ws_bytes, None)
+
+    assert call(off, 2, lam=math.nan) == -1 and "lambda" in gs.lib().gs_last_error().decode()
+    assert call(off, 2, ck=0) == -1 and "ckpt" in gs.lib().gs_last_error().decode()
+    assert call(_off([0, 9, 5]), 2) == -1
+    assert call(off, 2, method=5) == -1
+    assert call(off, 2, q=None) == -1
+    assert call(off, 2, method=gs.GS_BH, ws_bytes=4096) == -2
+    # all sets empty: a no-op that touches nothing
+    assert _call("gs_shoot_adjoint_batch", None, None, None, _off([0, 0]), 1,
+                 ctypes.byref(prm), gs.GS_BH, ctypes.c_double(0.01), 2, None, None, None, 0,
+                 None) == 0

@@ -243,3 +243,95 @@ def test_many_tiny_sets(oracle, method):
         assert np.max(np.abs(H[s] - Ho)) <= 1e-6 * np.max(np.abs(Ho))
     if method == gs.GS_BH:
         assert gs.gs_bh_counters(ws)["pairs"] == pairs
+
+
+def _adjoint_sets(sizes, seed=80):
+    """Ragged sets of the gradient workload (template, p0, target)."""
+    subs = []
+    for k, n in enumerate(sizes):
+        if n == 0:
+            z = np.zeros((0, 3), np.float32)
+            subs.append(W.Workload(f"empty-{k}", z, z, 0.05, 40, "f32", {"target": z}))
+        else:
+            subs.append(W.adjoint_50k(seed=seed + k, n=n))
+    q, p, off = W.stack(subs)
+    y = np.concatenate([w.extra["target"] for w in subs])
+    return subs, q, p, y, off
+
+
+@pytest.mark.parametrize("method", [gs.GS_EXACT, gs.GS_BH])
+def test_adjoint_batch_matches_oracle_per_set(oracle, method):
+    """Per-set objective and gradient against the oracle's, at the single-set
+    bars (exact: 1e-6 objective, rel-L2 1e-5 gradient; Barnes-Hut:
+    max(1e-4, 0.1 eps) against the oracle's Barnes-Hut gradient)."""
+    subs, q, p, y, off = _adjoint_sets([700, 0, 1, 1300, 64])
+    sigma, nt, lam, ck, theta, leaf_cap = 0.05, 6, 0.01, 4, 0.5, 4
+    prm = gs.params(sigma, nt=nt, theta=theta, leaf_cap=leaf_cap)
+    _say(f"adjoint batch method={method}")
+    E, G = gs.gs_shoot_adjoint_batch(_t(q), _t(p), _t(y), off, prm, method, lam, ck)
+    torch.cuda.synchronize()
+    E, G = _np(E), _np(G)
+    kind = "exact" if method == gs.GS_EXACT else "bh"
+    for s, w in enumerate(subs):
+        lo, hi = off[s], off[s + 1]
+        if hi == lo:
+            assert E[s] == 0.0
+            continue
+        q64, p64, y64 = (x.astype(np.float64) for x in (w.q0, w.p0, w.extra["target"]))
+        oe, og = oracle.objective_grad(q64, p64, y64, sigma, nt, lam, method=kind, theta=theta,
+                                       leaf_cap=leaf_cap)
+        eg, ee = rel_l2(G[lo:hi], og), abs(E[s] - oe) / abs(oe)
+        if method == gs.GS_EXACT:
+            _say(f"  set {s} n={hi - lo}: objective {ee:.2e} grad {eg:.2e}")
+            assert ee <= 1e-6 and eg < 1e-5
+        else:
+            _, xg = oracle.objective_grad(q64, p64, y64, sigma, nt, lam)
+            eps = rel_l2(og, xg)
+            _say(f"  set {s} n={hi - lo}: objective {ee:.2e} grad {eg:.2e} eps {eps:.2e}")
+            assert ee <= 1e-5 and eg <= max(1e-4, 0.1 * eps)
+
+
+@pytest.mark.parametrize("method", [gs.GS_EXACT, gs.GS_BH])
+def test_adjoint_batch_equals_single_calls(method):
+    subs, q, p, y, off = _adjoint_sets([3000, 64, 65, 1, 2049, 0, 5000], seed=120)
+    prm = gs.params(0.05, nt=5, theta=0.5, leaf_cap=16)
+    E, G = gs.gs_shoot_adjoint_batch(_t(q), _t(p), _t(y), off, prm, method, 0.01, 2)
+    E, G = _np(E), _np(G)
+    worst = 0.0
+    for s, w in enumerate(subs):
+        lo, hi = off[s], off[s + 1]
+        if hi == lo:
+            continue
+        e1, g1 = gs.gs_shoot_adjoint(_t(w.q0), _t(w.p0), _t(w.extra["target"]), prm, method,
+                                     0.01, 2)
+        worst = max(worst, abs(E[s] - float(e1)) / abs(float(e1)), rel_l2(G[lo:hi], _np(g1)))
+    _say(f"adjoint batch vs single method={method}: {worst:.2e}")
+    assert worst < 1e-6
+
+
+def test_population_adjoint_full_size():
+    """Forward plus backward stage of the 64-subject population (40 steps,
+    checkpoints every 8): the batched objective and gradient of sampled
+    subjects equal their single-subject calls (which the oracle pins at
+    smaller sizes)."""
+    subs = W.population()
+    ys = W.population_targets(subs)
+    q, p, off = W.stack(subs)
+    y = np.concatenate(ys)
+    prm = gs.params(0.05, nt=40, theta=0.5, leaf_cap=16)
+    qt, pt, yt = _t(q), _t(p), _t(y)
+    sizes = np.diff(off)
+    picks = [int(np.argmin(sizes)), int(np.argmax(sizes)), 17]
+    for method in (gs.GS_BH, gs.GS_EXACT):
+        _say(f"population adjoint method={method}")
+        E, G = gs.gs_shoot_adjoint_batch(qt, pt, yt, off, prm, method, 0.01, 8)
+        E, G = _np(E), _np(G)
+        assert np.all(np.isfinite(E)) and np.all(E > 0) and np.all(np.isfinite(G))
+        for s in picks:
+            lo, hi = off[s], off[s + 1]
+            e1, g1 = gs.gs_shoot_adjoint(_t(subs[s].q0), _t(subs[s].p0), _t(ys[s]), prm, method,
+                                         0.01, 8)
+            de = abs(E[s] - float(e1)) / abs(float(e1))
+            dg = rel_l2(G[lo:hi], _np(g1))
+            _say(f"  subject {s} n={hi - lo}: objective {de:.2e} grad {dg:.2e}")
+            assert de < 1e-6 and dg < 1e-6
