@@ -584,11 +584,11 @@ __global__ __launch_bounds__(256) void k_pack_state_rows(const float *__restrict
     }
 }
 
-// FP64 [n][3] pair (a, b) -> packed FP32 rows (sa a, b), zero padding.
+// FP64 [n][3] pair (a, b) -> packed FP32 rows (sa a, sb b), zero padding.
 __global__ __launch_bounds__(256) void k_pack_rows64(const double *__restrict__ a,
                                                      const double *__restrict__ b,
                                                      const int4 *__restrict__ blk, double sa,
-                                                     float4 *__restrict__ A,
+                                                     double sb, float4 *__restrict__ A,
                                                      float4 *__restrict__ B) {
     const int4 d = blk[blockIdx.x];
     const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -596,7 +596,8 @@ __global__ __launch_bounds__(256) void k_pack_rows64(const double *__restrict__ 
         const int64_t i = (int64_t)d.x + threadIdx.x;
         A[row] = make_float4((float)(sa * a[3 * i]), (float)(sa * a[3 * i + 1]),
                              (float)(sa * a[3 * i + 2]), 0.f);
-        B[row] = make_float4((float)b[3 * i], (float)b[3 * i + 1], (float)b[3 * i + 2], 0.f);
+        B[row] = make_float4((float)(sb * b[3 * i]), (float)(sb * b[3 * i + 1]),
+                             (float)(sb * b[3 * i + 2]), 0.f);
     } else {
         A[row] = make_float4(0.f, 0.f, 0.f, 0.f);
         B[row] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -1020,10 +1021,11 @@ void carve_exact_batch(Arena &a, const ExactBatchPlan &pl, int nt, ExactBatchBuf
 double position_scale(double sigma) { return sqrt(kLog2e / (2.0 * sigma * sigma)); }
 
 gs_status launch_pack_rows64(const ExactBatchPlan &pl, const int4 *blk, const double *a,
-                             const double *b, double sa, float4 *A, float4 *B, hipStream_t s) {
+                             const double *b, double sa, float4 *A, float4 *B, hipStream_t s,
+                             double sb) {
     if (pl.blocks.empty()) return GS_OK;
     hipLaunchKernelGGL(k_pack_rows64, dim3((unsigned)pl.blocks.size()), dim3(256), 0, s, a, b,
-                       blk, sa, A, B);
+                       blk, sa, sb, A, B);
     GS_LAUNCH_CHECK("pack_rows64");
     return GS_OK;
 }

@@ -169,10 +169,11 @@ gs_status launch_combine_rows(const ExactBatchPlan &pl, const ExactBatchBufs &b,
                               hipStream_t s, double *vout = nullptr);
 // k = sqrt(log2(e) / (2 sigma^2)), the factor of the stored positions.
 double position_scale(double sigma);
-// Packs FP64 [ntot][3] arrays (a, b) into rows (sa a, b) as float4 (zero
+// Packs FP64 [ntot][3] arrays (a, b) into rows (sa a, sb b) as float4 (zero
 // padding), with the row blocks `blk` of the plan (device table).
 gs_status launch_pack_rows64(const ExactBatchPlan &pl, const int4 *blk, const double *a,
-                             const double *b, double sa, float4 *A, float4 *B, hipStream_t s);
+                             const double *b, double sa, float4 *A, float4 *B, hipStream_t s,
+                             double sb = 1.0);
 
 // FP64 exact path.
 gs_status launch_exact_f64(const double *q, const double *p, int64_t n, double sigma,
