@@ -100,11 +100,7 @@ __global__ void k_unpack(const float4 *__restrict__ Q, const float4 *__restrict_
 
 // Sums of targets t0 + 64 k (k < T, one lane each) over sources [j0, j1)
 // (a multiple of kTile), written as six FP64 rows of dst (row stride ntgt).
-// With SCALED the positions are stored multiplied by k = sqrt(c),
-// c = log2(e) / (2 sigma^2), so that G = exp2(-|q'_i - q'_j|^2) needs no
-// scaling multiply (negc is then unused) and the a-sums come out multiplied
-// by k.
-template <int T, bool WITH_A, bool SCALED = false>
+template <int T, bool WITH_A>
 __device__ __forceinline__ void pair_sums(const float4 *__restrict__ Qt,
                                           const float4 *__restrict__ Pt, int64_t ntgt,
                                           const float4 *__restrict__ Qs,
@@ -159,7 +155,7 @@ __device__ __forceinline__ void pair_sums(const float4 *__restrict__ Qt,
 #pragma unroll
                 for (int b = 0; b < B; ++b) {
                     const float r2 = dx[b] * dx[b] + dy[b] * dy[b] + dz[b] * dz[b];
-                    g[b] = __builtin_amdgcn_exp2f(SCALED ? -r2 : r2 * negc);
+                    g[b] = __builtin_amdgcn_exp2f(r2 * negc);
                 }
 #pragma unroll
                 for (int b = 0; b < B; ++b) {
@@ -199,7 +195,7 @@ __device__ __forceinline__ void pair_sums(const float4 *__restrict__ Qt,
 // b % splits: consecutive blocks share their targets and stream different
 // source ranges.
 //
-// Occupancy hint (also on k_exact_items): allowing at most 7 waves per SIMD
+// Occupancy hint: allowing at most 7 waves per SIMD
 // lets the compiler keep the scalar loads of 8 sources in flight (66 VGPRs);
 // aiming at 8 waves it splits each batch of 8 sources into two halves with a
 // full wait each, measured 16.4 vs 14.7 ms per 200k right-hand side.
@@ -219,17 +215,96 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 7))) voi
 
 // Batched sets: block b takes work item b = (first padded target row of 256,
 // source rows [j0, j1) of the same set, partial slot).  Positions are stored
-// scaled by sqrt(log2(e) / (2 sigma^2)).
+// scaled by k = sqrt(log2(e) / (2 sigma^2)), so that G = exp2(-|q'_i -
+// q'_j|^2) needs no scaling multiply and the a-sums come out multiplied by
+// k.  One target per lane; the sources are wave-uniform (scalar loads), FP32
+// pair terms are summed per tile of kTile sources and the tile sums
+// accumulated in FP64.
+//
+// The sources of the next group of four are loaded while the current four
+// are evaluated (software pipelining through SGPRs): without it every group
+// waits for its own loads.  With at most 64 VGPRs (8 waves per SIMD) this
+// measured 13.3 ms per 200k right-hand side, against 14.4 ms for groups of
+// eight loaded and then evaluated (7 waves per SIMD) and 13.4 ms for the
+// pipelined loop at 7 waves.
 template <bool WITH_A>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 7))) void k_exact_items(const float4 *__restrict__ Q,
-                                                     const float4 *__restrict__ P, int64_t npad,
-                                                     const int4 *__restrict__ items,
-                                                     double *__restrict__ part) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_exact_items(
+    const float4 *__restrict__ Q, const float4 *__restrict__ P, int64_t npad,
+    const int4 *__restrict__ items, double *__restrict__ part) {
+    constexpr int B = 4;  // sources per pipeline stage (kTile is a multiple)
     const int4 it = items[blockIdx.x];
     if (it.w < 0) return;  // padding item (keeps the XCD interleave aligned)
     const int64_t t0 = (int64_t)it.x + (threadIdx.x >> 6) * 64 + (threadIdx.x & 63);
-    pair_sums<1, WITH_A, true>(Q, P, npad, Q, P, t0, it.y, it.z, 0.f,
-                               part + (int64_t)it.w * 6 * npad);
+    const float4 a = Q[t0];
+    const float x = a.x, y = a.y, z = a.z;
+    float px = 0.f, py = 0.f, pz = 0.f;
+    if (WITH_A) {
+        const float4 b = P[t0];
+        px = b.x;
+        py = b.y;
+        pz = b.z;
+    }
+    double sv[3] = {0, 0, 0}, sa[3] = {0, 0, 0};
+    const int64_t j0 = it.y, j1 = it.z;
+    float4 qn[B], pn[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        qn[b] = Q[j0 + b];
+        pn[b] = P[j0 + b];
+    }
+    for (int64_t jt = j0; jt < j1; jt += kTile) {
+        float tv[3] = {0.f, 0.f, 0.f}, ta[3] = {0.f, 0.f, 0.f};
+#pragma unroll 1
+        for (int u = 0; u < kTile; u += B) {
+            float4 qj[B], pj[B];
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                qj[b] = qn[b];
+                pj[b] = pn[b];
+            }
+            // next group (the last group reloads itself: j1 - j0 >= kTile >= B)
+            int64_t jn = jt + u + B;
+            jn = jn < j1 - B ? jn : j1 - B;
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                qn[b] = Q[jn + b];
+                pn[b] = P[jn + b];
+            }
+            float dx[B], dy[B], dz[B], g[B];
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                dx[b] = x - qj[b].x;
+                dy[b] = y - qj[b].y;
+                dz[b] = z - qj[b].z;
+            }
+#pragma unroll
+            for (int b = 0; b < B; ++b)
+                g[b] = __builtin_amdgcn_exp2f(-(dx[b] * dx[b] + dy[b] * dy[b] + dz[b] * dz[b]));
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                tv[0] += g[b] * pj[b].x;
+                tv[1] += g[b] * pj[b].y;
+                tv[2] += g[b] * pj[b].z;
+                if (WITH_A) {
+                    const float w = g[b] * (px * pj[b].x + py * pj[b].y + pz * pj[b].z);
+                    ta[0] += w * dx[b];
+                    ta[1] += w * dy[b];
+                    ta[2] += w * dz[b];
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            sv[c] += (double)tv[c];
+            if (WITH_A) sa[c] += (double)ta[c];
+        }
+    }
+    double *dst = part + (int64_t)it.w * 6 * npad;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        dst[c * npad + t0] = sv[c];
+        if (WITH_A) dst[(3 + c) * npad + t0] = sa[c];
+    }
 }
 
 // Same sums with the source tile staged in LDS: every wave reads each source
