@@ -43,7 +43,8 @@ inline unsigned nblk(int64_t n, int b = kBlock) { return (unsigned)((n + b - 1) 
 
 __global__ void k_clear(int *__restrict__ status, u64 *__restrict__ counters) {
     if (threadIdx.x == 0) *status = 0;
-    if (threadIdx.x < GS_BH_COUNTERS) counters[threadIdx.x] = 0ull;
+    for (int i = threadIdx.x; i < kCounterSlots * GS_BH_COUNTERS; i += blockDim.x)
+        counters[i] = 0ull;
 }
 
 __global__ void k_to_f32(const double *__restrict__ a, const double *__restrict__ b, int64_t n3,
@@ -248,8 +249,9 @@ __global__ __launch_bounds__(256) void k_bh_adj_traverse(
         cm += __shfl_down(cm, off, 64);
     }
     if (lane == 0 && counters) {
-        atomicAdd(&counters[0], cp);
-        atomicAdd(&counters[1], cm);
+        u64 *c = counter_slot(counters, blockIdx.x);
+        if (cp) atomicAdd(&c[0], cp);
+        if (cm) atomicAdd(&c[1], cm);
     }
 }
 
@@ -265,7 +267,7 @@ BhAdjBufs layout_bh_adjoint(Arena &a, int64_t n) {
 
 gs_status bh_adjoint_begin(char *ws, hipStream_t s) {
     hipLaunchKernelGGL(k_clear, dim3(1), dim3(64), 0, s, reinterpret_cast<int *>(ws),
-                       reinterpret_cast<u64 *>(ws + 8));
+                       reinterpret_cast<u64 *>(ws + kCountersOffset));
     GS_LAUNCH_CHECK("clear");
     return GS_OK;
 }
@@ -273,7 +275,7 @@ gs_status bh_adjoint_begin(char *ws, hipStream_t s) {
 gs_status bh_adjoint_forward_step(AdjointBufs &b, const gs_params &prm, double dt, double *v0,
                                   char *ws, hipStream_t s) {
     int *status = reinterpret_cast<int *>(ws);
-    u64 *counters = reinterpret_cast<u64 *>(ws + 8);
+    u64 *counters = reinterpret_cast<u64 *>(ws + kCountersOffset);
     const int64_t n3 = 3 * b.n;
     hipLaunchKernelGGL(k_to_f32, dim3(nblk(n3)), dim3(kBlock), 0, s, b.Sq, b.Sp, n3, b.sh.q32,
                        b.sh.p32);
@@ -294,7 +296,7 @@ gs_status bh_adjoint_forward_step(AdjointBufs &b, const gs_params &prm, double d
 gs_status bh_adjoint_step(AdjointBufs &b, const gs_params &prm, double dt, const double *sq,
                           const double *sp, char *ws, hipStream_t s) {
     int *status = reinterpret_cast<int *>(ws);
-    u64 *counters = reinterpret_cast<u64 *>(ws + 8);
+    u64 *counters = reinterpret_cast<u64 *>(ws + kCountersOffset);
     const int64_t n = b.n, n3 = 3 * n;
     TreeBufs &t = b.sh.tree;
     hipLaunchKernelGGL(k_to_f32, dim3(nblk(n3)), dim3(kBlock), 0, s, sq, sp, n3, b.sh.q32,

@@ -78,15 +78,9 @@ using namespace gs;
 
 namespace {
 
-// Workspace header: status word and Barnes-Hut counters live in the first
-// 256 bytes of every workspace.
-struct WsHeader {
-    int32_t status;
-    int32_t pad;
-    unsigned long long counters[GS_BH_COUNTERS];
-};
-static_assert(sizeof(WsHeader) <= 256, "workspace header");
-constexpr size_t kHeader = 256;
+// Every workspace starts with the status word and the Barnes-Hut counters
+// (kWsHeader bytes).
+constexpr size_t kHeader = kWsHeader;
 
 bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 
@@ -998,9 +992,9 @@ gs_status gs_get_status(const void *ws, hipStream_t stream) {
         return GS_ERR_INVALID;
     }
     GS_HIP(hipStreamSynchronize(stream));
-    WsHeader h;
-    GS_HIP(hipMemcpy(&h, ws, sizeof(h), hipMemcpyDeviceToHost));
-    if (h.status != 0) {
+    int32_t status = 0;
+    GS_HIP(hipMemcpy(&status, ws, sizeof(status), hipMemcpyDeviceToHost));
+    if (status != 0) {
         set_error("non-finite coordinates met while building the octree");
         return GS_ERR_NONFINITE;
     }
@@ -1013,9 +1007,15 @@ gs_status gs_bh_counters(const void *ws, hipStream_t stream, int64_t out[GS_BH_C
         return GS_ERR_INVALID;
     }
     GS_HIP(hipStreamSynchronize(stream));
-    WsHeader h;
-    GS_HIP(hipMemcpy(&h, ws, sizeof(h), hipMemcpyDeviceToHost));
-    for (int k = 0; k < GS_BH_COUNTERS; ++k) out[k] = (int64_t)h.counters[k];
+    unsigned long long c[kCounterSlots][GS_BH_COUNTERS];
+    GS_HIP(hipMemcpy(c, static_cast<const char *>(ws) + kCountersOffset, sizeof(c),
+                     hipMemcpyDeviceToHost));
+    for (int k = 0; k < GS_BH_COUNTERS; ++k) {
+        unsigned long long v = 0;
+        for (int s = 0; s < kCounterSlots; ++s)
+            v = k == 6 ? (c[s][k] > v ? c[s][k] : v) : v + c[s][k];
+        out[k] = (int64_t)v;
+    }
     return GS_OK;
 }
 

@@ -63,6 +63,15 @@ struct Arena {
 };
 
 constexpr int kTile = 64;       // sources per compensated tile (exact FP32 kernel)
+
+// Workspace header: the status word at offset 0 and the Barnes-Hut counters
+// at kCountersOffset, kCounterSlots copies of the GS_BH_COUNTERS values (a
+// block adds into the copy of its slot; readers sum the copies, and take
+// the largest for the per-wave maximum), so that the counter atomics of a
+// launch do not all meet on the same addresses.
+constexpr int kCounterSlots = 64;
+constexpr size_t kCountersOffset = 256;
+constexpr size_t kWsHeader = kCountersOffset + (size_t)kCounterSlots * GS_BH_COUNTERS * 8;
 constexpr int kBlock = 256;     // threads per block for O(N) kernels
 
 inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }

@@ -30,19 +30,26 @@ typedef unsigned long long u64;
 
 
 // ---------------------------------------------------------------- layout
-// Work split.  A wave owns 64 consecutive targets of the Morton order (a
-// group).  Phase 1 walks the tree for its group: it takes every decision,
-// adds the monopoles, and records each leaf that some lane must sum exactly
-// as an entry (leaf, lane mask) of the group's list.  Phase 2 runs one wave
-// per chunk of kChunkEntries list entries and adds their exact pairs, so the
-// near-field work of a dense group is spread over many waves.  Phase 3 adds
-// the partial sums of a target in a fixed order (phase 1, then chunk 0, 1,
-// ...): the result does not depend on scheduling.
+// Work split.  A group is 64 consecutive targets of the Morton order (one
+// wave's lanes).  Phase 1 walks the tree for a group with kSub waves that
+// share out the children of the tree's root (the root contains every target
+// of its tree, so it is never approximated and every target opens it): each
+// wave takes the decisions in its children's subtrees, adds the monopoles,
+// and records each leaf that some lane must sum exactly as an entry (leaf,
+// lane mask) of its own list segment.  Measured at 200k points (theta 0.5,
+// leaf_cap 64), with 1, 2, 4 and 8 waves per group: 1.18, 1.10, 1.07 and
+// 1.41 ms per traversal (at leaf_cap 16: 1.83, 1.85, 1.92, 2.25 ms).  Phase 2 splits the group's entries, taken segment by
+// segment, into at most kMaxChunks chunks of at least kMinChunk entries and
+// adds their exact pairs with one wave per chunk, so the near-field work of
+// a dense group is spread over many waves.  Phase 3 adds the partial sums of
+// a target in a fixed order (the phase-1 waves, then the chunks): the result
+// does not depend on scheduling.
 constexpr int kBlockStack = 192;  // entries of (first child, count, lane mask)
-constexpr int kListCap = 512;     // list entries per group (more are summed in phase 1)
-constexpr int kChunkEntries = 32;
-constexpr int kChunks = kListCap / kChunkEntries;
-constexpr int kParts = 1 + kChunks;
+constexpr int kSub = 4;           // phase-1 waves per group (the root's children split among them)
+constexpr int kSegCap = 2048 / kSub;  // list entries per phase-1 wave (more are summed in phase 1)
+constexpr int kMaxChunks = 16;    // phase-2 waves per group
+constexpr int kMinChunk = 32;     // entries per phase-2 wave, at least (unless fewer in all)
+constexpr int kParts = kSub + kMaxChunks;
 
 struct LeafEntry {
     u64 mask;
@@ -163,7 +170,9 @@ __global__ __launch_bounds__(256) void k_bh_decide(
     __shared__ DecideLds lds_all[4];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     DecideLds &L = lds_all[wv];
-    const int64_t grp = (int64_t)blockIdx.x * 4 + wv;
+    const int64_t wave = (int64_t)blockIdx.x * 4 + wv;
+    const int64_t grp = wave / kSub;
+    const int sub = (int)(wave % kSub);
     if (grp >= groups) return;  // wave-uniform; this kernel has no block barrier
     const int64_t npad = groups * 64;
     const GroupDesc gd = group_desc(gtab, grp, n);
@@ -172,22 +181,34 @@ __global__ __launch_bounds__(256) void k_bh_decide(
     const float4 xq = active ? Qs[t] : make_float4(0.f, 0.f, 0.f, 0.f);
     const float4 xp = active ? Ps[t] : make_float4(0.f, 0.f, 0.f, 0.f);
     const double xd = xq.x, yd = xq.y, zd = xq.z;
-    LeafEntry *mylist = list + grp * kListCap;
+    LeafEntry *mylist = list + (grp * kSub + sub) * kSegCap;
 
     double V[3] = {0, 0, 0}, A[3] = {0, 0, 0};
     float mv[3] = {0.f, 0.f, 0.f}, ma[3] = {0.f, 0.f, 0.f};
     unsigned c_pairs = 0, c_mono = 0, c_visit = 0, w_steps = 0, w_nodes = 0;
     int nlist = 0;
 
+    // this wave's start: its share [lo, hi) of the root's children as one
+    // block, or the root itself when it is a leaf (wave 0 only); a wave with
+    // no share is idle
+    const int rchild = __builtin_amdgcn_readfirstlane(nodes[gd.root].nchild);
+    const int rfirst = __builtin_amdgcn_readfirstlane(nodes[gd.root].first);
+    const int lo = sub * rchild / kSub, hi = (sub + 1) * rchild / kSub;
+    const int start = rchild == 0 ? (sub == 0 ? gd.root : -1) : (hi > lo ? rfirst + lo : -1);
+    const int start_n = rchild == 0 ? 1 : hi - lo;
+    if (rchild > 0 && sub == 0) {  // the root's visit, counted once
+        if (active) ++c_visit;
+        ++w_nodes;
+    }
     int sp = 0;
     const u64 live = __ballot(active);
-    if (live != 0ull) {  // the group's root as a block of one
-        L.first[0] = gd.root;
-        L.count[0] = 1;
+    if (live != 0ull && start >= 0) {  // the start block
+        L.first[0] = start;
+        L.count[0] = start_n;
         L.mask[0] = live;
         sp = 1;
         float4 *dstn = reinterpret_cast<float4 *>(L.node);
-        if (lane < 5) dstn[lane] = reinterpret_cast<const float4 *>(nodes + gd.root)[lane];
+        if (lane < 5 * start_n) dstn[lane] = reinterpret_cast<const float4 *>(nodes + start)[lane];
     }
     wave_sync();
     while (sp > 0) {
@@ -228,7 +249,7 @@ __global__ __launch_bounds__(256) void k_bh_decide(
             const int nchild = __builtin_amdgcn_readfirstlane(nd.nchild);
             if (nchild == 0) {
                 if (need) c_pairs += (unsigned)ncount;
-                if (nlist < kListCap) {
+                if (nlist < kSegCap) {
                     if (lane == 0) {
                         LeafEntry e;
                         e.mask = open;
@@ -272,8 +293,8 @@ __global__ __launch_bounds__(256) void k_bh_decide(
         V[c] += (double)mv[c];
         A[c] += (double)ma[c];
     }
-    write_part(part, 0, npad, grp * 64 + lane, V, A);
-    if (lane == 0) list_n[grp] = nlist;
+    write_part(part, sub, npad, grp * 64 + lane, V, A);
+    if (lane == 0) list_n[grp * kSub + sub] = nlist;
 
     // counters: wave sums, one atomic per wave (integer, order-free)
     u64 cp = c_pairs, cm = c_mono, cv = c_visit;
@@ -283,18 +304,38 @@ __global__ __launch_bounds__(256) void k_bh_decide(
         cm += __shfl_down(cm, off, 64);
         cv += __shfl_down(cv, off, 64);
     }
-    if (lane == 0 && counters) {
-        atomicAdd(&counters[0], cp);
-        atomicAdd(&counters[1], cm);
-        atomicAdd(&counters[2], cv);
-        if (grp == 0) atomicAdd(&counters[3], (u64)totals->n_nodes);
-        atomicAdd(&counters[4], (u64)w_steps);
-        atomicAdd(&counters[5], (u64)w_nodes);
-        atomicMax(&counters[6], (u64)w_steps + (u64)w_nodes);
+    if (lane == 0 && counters && (cv != 0 || w_nodes != 0)) {
+        u64 *c = counter_slot(counters, blockIdx.x);
+        if (cp) atomicAdd(&c[0], cp);
+        if (cm) atomicAdd(&c[1], cm);
+        atomicAdd(&c[2], cv);
+        if (grp == 0 && sub == 0) atomicAdd(&c[3], (u64)totals->n_nodes);
+        if (w_steps) atomicAdd(&c[4], (u64)w_steps);
+        atomicAdd(&c[5], (u64)w_nodes);
+        atomicMax(&c[6], (u64)w_steps + (u64)w_nodes);
+    } else if (lane == 0 && counters && grp == 0 && sub == 0) {
+        atomicAdd(&counter_slot(counters, blockIdx.x)[3], (u64)totals->n_nodes);
     }
 }
 
-// Phase 2: one wave per (group, chunk of kChunkEntries list entries).
+// The phase-2 split of a group: its list entries (segments 0..kSub-1 one
+// after the other) in `chunks` chunks of `per` entries (the last one
+// shorter).
+struct ChunkSplit {
+    int total, chunks, per;
+};
+__device__ inline ChunkSplit chunk_split(const int *__restrict__ list_n, int64_t grp) {
+    ChunkSplit c;
+    c.total = 0;
+#pragma unroll
+    for (int k = 0; k < kSub; ++k) c.total += list_n[grp * kSub + k];
+    c.chunks = (c.total + kMinChunk - 1) / kMinChunk;
+    if (c.chunks > kMaxChunks) c.chunks = kMaxChunks;
+    c.per = c.chunks > 0 ? (c.total + c.chunks - 1) / c.chunks : 0;
+    return c;
+}
+
+// Phase 2: one wave per (group, chunk of its list entries).
 template <bool WITH_A>
 __global__ __launch_bounds__(256) void k_bh_leaves(const float4 *__restrict__ Qs,
                                                    const float4 *__restrict__ Ps, int64_t n,
@@ -307,11 +348,17 @@ __global__ __launch_bounds__(256) void k_bh_leaves(const float4 *__restrict__ Qs
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t grp = blockIdx.x;
     const int chunk = blockIdx.y * 4 + wv;
-    const int cnt = list_n[grp];
-    const int e0 = chunk * kChunkEntries;
-    if (e0 >= cnt) return;  // wave-uniform: this chunk holds no entries
-    const int ne = cnt - e0 < kChunkEntries ? cnt - e0 : kChunkEntries;
-    const LeafEntry *ent = list + grp * kListCap + e0;
+    const ChunkSplit cs = chunk_split(list_n, grp);
+    int v0 = chunk * cs.per;
+    if (chunk >= cs.chunks || v0 >= cs.total) return;  // wave-uniform: no entries here
+    const int v1 = v0 + cs.per < cs.total ? v0 + cs.per : cs.total;
+    // the segment holding entry v0 of the group's concatenated list
+    int seg = 0, segn = list_n[grp * kSub];
+    while (v0 >= segn && seg < kSub - 1) {
+        v0 -= segn;
+        ++seg;
+        segn = list_n[grp * kSub + seg];
+    }
     const int64_t npad = groups * 64;
     const GroupDesc gd = group_desc(gtab, grp, n);
     const int64_t t = (int64_t)gd.first + lane;
@@ -320,18 +367,25 @@ __global__ __launch_bounds__(256) void k_bh_leaves(const float4 *__restrict__ Qs
     const float4 xp = active ? Ps[t] : make_float4(0.f, 0.f, 0.f, 0.f);
     double V[3] = {0, 0, 0}, A[3] = {0, 0, 0};
     unsigned steps = 0;
-    for (int r = 0; r < ne; ++r) {
-        const LeafEntry e = ent[r];  // wave-uniform
+    for (int r = chunk * cs.per; r < v1; ++r) {
+        while (v0 >= segn && seg < kSub - 1) {  // next non-empty segment
+            v0 = 0;
+            ++seg;
+            segn = list_n[grp * kSub + seg];
+        }
+        const LeafEntry e = list[(grp * kSub + seg) * kSegCap + v0];  // wave-uniform
+        ++v0;
         const int first = __builtin_amdgcn_readfirstlane(e.first);
         const int count = __builtin_amdgcn_readfirstlane(e.count);
         steps += (unsigned)count;
         leaf_direct<WITH_A>(Qs, Ps, first, count, ((e.mask >> lane) & 1ull) != 0, xq, xp, negc, V,
                             A);
     }
-    write_part(part, 1 + chunk, npad, grp * 64 + lane, V, A);
+    write_part(part, kSub + chunk, npad, grp * 64 + lane, V, A);
     if (lane == 0 && counters) {
-        atomicAdd(&counters[4], (u64)steps);
-        atomicMax(&counters[6], (u64)steps);
+        u64 *c = counter_slot(counters, blockIdx.x, blockIdx.y);
+        atomicAdd(&c[4], (u64)steps);
+        atomicMax(&c[6], (u64)steps);
     }
 }
 
@@ -353,9 +407,9 @@ __global__ __launch_bounds__(256) void k_bh_combine(
     const GroupDesc gd = group_desc(gtab, grp, n);
     double e = 0.0;
     if (lane < gd.count) {
-        const int nch = (list_n[grp] + kChunkEntries - 1) / kChunkEntries;
+        const int nslots = kSub + chunk_split(list_n, grp).chunks;
         double V[3] = {0, 0, 0}, A[3] = {0, 0, 0};
-        for (int s = 0; s <= nch; ++s) {
+        for (int s = 0; s < nslots; ++s) {
             const double *d = part + ((int64_t)s * npad + slot) * 6;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
@@ -425,7 +479,8 @@ __global__ void k_state_out(const double *__restrict__ Sq, const double *__restr
 // sequence can be captured in a graph).
 __global__ void k_clear_status(int *__restrict__ status, u64 *__restrict__ counters) {
     if (threadIdx.x == 0) *status = 0;
-    if (threadIdx.x < GS_BH_COUNTERS) counters[threadIdx.x] = 0ull;
+    for (int i = threadIdx.x; i < kCounterSlots * GS_BH_COUNTERS; i += blockDim.x)
+        counters[i] = 0ull;
 }
 
 inline unsigned nblk(int64_t n, int b = kBlock) { return (unsigned)((n + b - 1) / b); }
@@ -435,8 +490,10 @@ constexpr size_t kStatusOffset = 0;  // status word at the start of the workspac
 }  // namespace
 
 size_t traverse_list_bytes(int64_t groups) {
-    return (size_t)groups * kListCap * sizeof(LeafEntry);
+    return (size_t)groups * kSub * kSegCap * sizeof(LeafEntry);
 }
+
+size_t traverse_count_ints(int64_t groups) { return (size_t)groups * kSub; }
 
 size_t traverse_part_doubles(int64_t groups) { return (size_t)kParts * groups * 64 * 6; }
 
@@ -463,10 +520,12 @@ gs_status launch_bh_traverse(const TreeBufs &t, const BhParams &bp, bool with_a,
     timing_begin(kind, s);
 #define GS_PHASES(A)                                                                            \
     do {                                                                                        \
-        hipLaunchKernelGGL(k_bh_decide<A>, dim3((unsigned)((groups + 3) / 4)), dim3(256), 0, s, \
+        hipLaunchKernelGGL(k_bh_decide<A>, dim3((unsigned)((groups * kSub + 3) / 4)), dim3(256), \
+                           0, s,                                                                \
                            t.nodes, t.Qs, t.Ps, t.n, t.gtab, groups, bp, list, t.list_n,        \
                            t.part, counters, t.totals, status);                                 \
-        hipLaunchKernelGGL(k_bh_leaves<A>, dim3((unsigned)groups, kChunks / 4), dim3(256), 0, s, \
+        hipLaunchKernelGGL(k_bh_leaves<A>, dim3((unsigned)groups, kMaxChunks / 4), dim3(256), 0, \
+                           s,                                                                   \
                            t.Qs, t.Ps, t.n, t.gtab, groups, bp.negc, list, t.list_n, t.part,    \
                            counters);                                                           \
         hipLaunchKernelGGL(k_bh_combine<A>, dim3((unsigned)((groups + 3) / 4)), dim3(256), 0, s, \
@@ -516,8 +575,8 @@ ShootBhBufs layout_shoot_forest(Arena &a, int64_t n, int nsub, int64_t groups, i
 gs_status rhs_bh(const float *q, const float *p, int64_t n, const gs_params &prm, float *dq,
                  float *dp, TreeBufs &t, char *ws, hipStream_t s) {
     int *status = reinterpret_cast<int *>(ws + kStatusOffset);
-    u64 *counters = reinterpret_cast<u64 *>(ws + 8);
-    hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(64), 0, s, status, counters);
+    u64 *counters = reinterpret_cast<u64 *>(ws + kCountersOffset);
+    hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(256), 0, s, status, counters);
     GS_TRY(build_tree(q, p, n, prm.leaf_cap, t, status, s));
     TraverseOut o{};
     o.dq = dq;
@@ -528,8 +587,8 @@ gs_status rhs_bh(const float *q, const float *p, int64_t n, const gs_params &prm
 gs_status shoot_bh(const float *q0, const float *p0, int64_t n, const gs_params &prm, float *q1,
                    float *p1, double *H, ShootBhBufs &b, char *ws, hipStream_t s) {
     int *status = reinterpret_cast<int *>(ws + kStatusOffset);
-    u64 *counters = reinterpret_cast<u64 *>(ws + 8);
-    hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(64), 0, s, status, counters);
+    u64 *counters = reinterpret_cast<u64 *>(ws + kCountersOffset);
+    hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(256), 0, s, status, counters);
     hipLaunchKernelGGL(k_state_init, dim3(nblk(3 * n)), dim3(kBlock), 0, s, q0, p0, 3 * n, b.Sq,
                        b.Sp, b.q32, b.p32);
     GS_LAUNCH_CHECK("state_init");

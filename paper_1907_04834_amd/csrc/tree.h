@@ -17,6 +17,12 @@ namespace gs {
 
 constexpr int kLevels = 21;
 
+// The counter copy that block (bx, by) adds into.
+__device__ inline unsigned long long *counter_slot(unsigned long long *c, unsigned bx,
+                                                   unsigned by = 0) {
+    return c + (size_t)((bx + by) % kCounterSlots) * GS_BH_COUNTERS;
+}
+
 // One node as the traversal reads it (80 bytes; wave-uniform loads).
 struct alignas(16) BhNode {
     double cx, cy, cz;  // centre of the member positions (mean, FP64)
@@ -96,12 +102,13 @@ struct TreeBufs {
     BhNode *nodes;             // [2n + nsub]
     double *adj;               // [nodes][6] per-node sums of alpha, beta (backward stage)
     // traversal work split (see traverse.hip)
-    char *list;                // [groups][kListCap] leaf entries of each group
-    int *list_n;               // [groups] entries used
+    char *list;                // leaf entries of each group, one segment per phase-1 wave
+    int *list_n;               // entries used per segment
     double *part;              // [1 + chunks][groups * 64][6] partial (v, a) sums
 };
 // Sizes of the traversal's work-split buffers (defined in traverse.hip).
 size_t traverse_list_bytes(int64_t groups);
+size_t traverse_count_ints(int64_t groups);
 size_t traverse_part_doubles(int64_t groups);
 // One tree over n points.
 void carve_tree(Arena &a, int64_t n, TreeBufs &t);

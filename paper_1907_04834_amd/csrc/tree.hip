@@ -791,7 +791,7 @@ void carve_forest(Arena &a, int64_t n, int nsub, int64_t groups, int64_t max_set
     t.nodes = a.take<BhNode>(nodes);
     t.adj = a.take<double>(6 * nodes);
     t.list = a.take<char>(traverse_list_bytes(g));
-    t.list_n = a.take<int>(g);
+    t.list_n = a.take<int>(traverse_count_ints(g));
     t.part = a.take<double>(traverse_part_doubles(g));
 }
 
