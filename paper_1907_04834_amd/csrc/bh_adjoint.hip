@@ -4,40 +4,27 @@
 //
 // At every backward step the octree of q_t is rebuilt, each node gets the
 // FP64 sums A_k = sum alpha_i and B_k = sum beta_i of its members, and every
-// target walks the tree with the forward decisions.  An approximated node
+// target walks the tree with the forward decisions, in the three phases of
+// the forward traversal (decisions and approximated nodes with the list of
+// leaves to sum exactly; the leaves' exact pairs; a fixed-order combine).
+// An approximated node
 // acts as n_k virtual points at C_k carrying the mean momentum P_k / n_k and
 // the mean derivatives A_k / n_k, B_k / n_k, which gives, with d = x - C_k,
 // G = G(|d|), s = p_x . P_k, db = beta_x - B_k / n_k:
 //   g_q += sigma^-2 G { -d [ P_k . alpha_x + p_x . A_k ] + s [ db - d (d . db) / sigma^2 ] }
 //   g_p += G A_k + sigma^-2 G P_k (d . db)
 // A leaf that is not approximated contributes the exact adjoint pairs.  The
-// kernel adds dt (g_q, g_p) to (alpha, beta) of its targets in place.
+// combine adds dt (g_q, g_p) to (alpha, beta) of its targets in place.
 #include <hip/hip_runtime.h>
 
 #include "adjoint.h"
+#include "traverse.h"
 
 namespace gs {
 
 namespace {
 
-typedef unsigned long long u64;
-constexpr int kAdjStack = 192;
-constexpr int kAdjStage = 64;
-
-struct AdjLds {
-    u64 mask[kAdjStack];
-    int first[kAdjStack];
-    int count[kAdjStack];
-    BhNode node[8];
-    double adj[8][6];
-    float4 lq[kAdjStage], lp[kAdjStage], la[kAdjStage], lb[kAdjStage];
-};
-
-__device__ inline void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
+using namespace trav;
 
 inline unsigned nblk(int64_t n, int b = kBlock) { return (unsigned)((n + b - 1) / b); }
 
@@ -95,68 +82,129 @@ __device__ inline void adj_pair(float4 x, float4 px, float4 ax, float4 bx, float
     gp[2] = fmaf(w3, pj.z, gp[2]);
 }
 
-// One wave per traversal group: `count` consecutive sorted targets from
-// `first`, all in the tree whose root is node `root` (gtab null: group g is
-// targets [64 g, 64 g + 64) of the single tree rooted at node 0).
-__global__ __launch_bounds__(256) void k_bh_adj_traverse(
+// Exact adjoint pairs of one leaf, sorted points [first, first + count), for
+// the lanes with `mine` set; wave-uniform (scalar) source loads, the leaf
+// summed in FP32 and added to the FP64 sums.
+__device__ __forceinline__ void leaf_adjoint(const float4 *__restrict__ Qs,
+                                             const float4 *__restrict__ Ps,
+                                             const float4 *__restrict__ As,
+                                             const float4 *__restrict__ Bs, int first, int count,
+                                             bool mine, float4 x, float4 px, float4 ax, float4 bx,
+                                             float negc, float inv_s2, double *GQ, double *GP) {
+    if (!mine) return;
+    float gq[3] = {0.f, 0.f, 0.f}, gp[3] = {0.f, 0.f, 0.f};
+    for (int j = first; j < first + count; ++j)
+        adj_pair(x, px, ax, bx, Qs[j], Ps[j], As[j], Bs[j], negc, inv_s2, gq, gp);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        GQ[c] += (double)gq[c];
+        GP[c] += (double)gp[c];
+    }
+}
+
+// The same with the leaf's points staged in LDS, 64 at a time: each lane
+// loads one point (q, p, alpha, beta), then every lane reads them back with
+// wave-uniform LDS addresses.  All lanes of the wave must call it.
+__device__ __forceinline__ void leaf_adjoint_staged(
+    const float4 *__restrict__ Qs, const float4 *__restrict__ Ps, const float4 *__restrict__ As,
+    const float4 *__restrict__ Bs, int first, int count, bool mine, float4 x, float4 px,
+    float4 ax, float4 bx, float negc, float inv_s2, double *GQ, double *GP, float4 (*st)[64],
+    int lane) {
+    float gq[3] = {0.f, 0.f, 0.f}, gp[3] = {0.f, 0.f, 0.f};
+    for (int j0 = 0; j0 < count; j0 += 64) {
+        const int cnt = count - j0 < 64 ? count - j0 : 64;
+        wave_sync();
+        if (lane < cnt) {
+            const int j = first + j0 + lane;
+            st[0][lane] = Qs[j];
+            st[1][lane] = Ps[j];
+            st[2][lane] = As[j];
+            st[3][lane] = Bs[j];
+        }
+        wave_sync();
+        if (mine)
+            for (int j = 0; j < cnt; ++j)
+                adj_pair(x, px, ax, bx, st[0][j], st[1][j], st[2][j], st[3][j], negc, inv_s2, gq,
+                         gp);
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        GQ[c] += (double)gq[c];
+        GP[c] += (double)gp[c];
+    }
+}
+
+struct AdjDecideLds {
+    DecideLds d;
+    double adj[8][6];  // A_k, B_k of the sibling block being decided
+};
+
+// Loads the node records and adjoint sums of the block of `count` nodes
+// from `first` into the wave's LDS.
+__device__ inline void load_block(const BhNode *__restrict__ nodes,
+                                  const double *__restrict__ adj, int first, int count, int lane,
+                                  AdjDecideLds &L) {
+    if (lane < 5 * count)
+        reinterpret_cast<float4 *>(L.d.node)[lane] =
+            reinterpret_cast<const float4 *>(nodes + first)[lane];
+    if (lane < 3 * count)
+        reinterpret_cast<float4 *>(&L.adj[0][0])[lane] =
+            reinterpret_cast<const float4 *>(adj + 6 * (int64_t)first)[lane];
+}
+
+// Phase 1 of the backward products (the work split of the forward
+// traversal): the decisions, the approximated nodes' contributions and the
+// list of leaves to sum exactly.
+__global__ __launch_bounds__(256) void k_adj_decide(
     const BhNode *__restrict__ nodes, const double *__restrict__ adj,
     const float4 *__restrict__ Qs, const float4 *__restrict__ Ps, const float4 *__restrict__ As,
-    const float4 *__restrict__ Bs, const unsigned *__restrict__ perm, int64_t n,
-    const GroupDesc *__restrict__ gtab, int64_t groups, BhParams bp, double dt,
-    double *__restrict__ al, double *__restrict__ be, u64 *__restrict__ counters,
-    int *__restrict__ status) {
-    __shared__ AdjLds lds_all[4];
+    const float4 *__restrict__ Bs, int64_t n, const GroupDesc *__restrict__ gtab, int64_t groups,
+    TravSplit split, BhParams bp, LeafEntry *__restrict__ list, int *__restrict__ list_n,
+    double *__restrict__ part, u64 *__restrict__ counters, int *__restrict__ status) {
+    __shared__ AdjDecideLds lds_all[4];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    AdjLds &L = lds_all[wv];
-    const int64_t grp = (int64_t)blockIdx.x * 4 + wv;
-    if (grp >= groups) return;  // wave-uniform; no block barrier in this kernel
-    int64_t first, count;
-    int root;
-    if (gtab) {
-        const GroupDesc d = gtab[grp];
-        first = d.first;
-        count = d.count;
-        root = d.root;
-    } else {
-        first = grp * 64;
-        count = n - first < 64 ? n - first : 64;
-        root = 0;
-    }
-    const int64_t t = first + lane;
-    const bool active = lane < count;
+    AdjDecideLds &L = lds_all[wv];
+    const int64_t wave = (int64_t)blockIdx.x * 4 + wv;
+    const int64_t grp = wave / split.nsub;
+    const int sub = (int)(wave % split.nsub);
+    if (grp >= groups) return;  // wave-uniform; this kernel has no block barrier
+    const int64_t npad = groups * 64;
+    const GroupDesc gd = group_desc(gtab, grp, n);
+    const int64_t t = (int64_t)gd.first + lane;
+    const bool active = lane < gd.count;
     const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
     const float4 xq = active ? Qs[t] : z4, xp = active ? Ps[t] : z4;
     const float4 xa = active ? As[t] : z4, xb = active ? Bs[t] : z4;
     const double xd = xq.x, yd = xq.y, zd = xq.z;
     const float inv_s2 = bp.inv_s2f;
+    LeafEntry *mylist = list + (grp * kSub + sub) * kSegCap;
     double GQ[3] = {0, 0, 0}, GP[3] = {0, 0, 0};
     unsigned c_pairs = 0, c_mono = 0;
+    int nlist = 0;
 
+    // this wave's share of the root's children (the root when it is a leaf)
+    const int rchild = __builtin_amdgcn_readfirstlane(nodes[gd.root].nchild);
+    const int rfirst = __builtin_amdgcn_readfirstlane(nodes[gd.root].first);
+    const int lo = sub * rchild / split.nsub, hi = (sub + 1) * rchild / split.nsub;
+    const int start = rchild == 0 ? (sub == 0 ? gd.root : -1) : (hi > lo ? rfirst + lo : -1);
+    const int start_n = rchild == 0 ? 1 : hi - lo;
     int sp = 0;
     const u64 live = __ballot(active);
-    if (live != 0ull) {
-        L.first[0] = root;
-        L.count[0] = 1;
-        L.mask[0] = live;
+    if (live != 0ull && start >= 0) {
+        L.d.first[0] = start;
+        L.d.count[0] = start_n;
+        L.d.mask[0] = live;
         sp = 1;
+        load_block(nodes, adj, start, start_n, lane, L);
     }
     wave_sync();
     while (sp > 0) {
         --sp;
-        const int bf = __builtin_amdgcn_readfirstlane(L.first[sp]);
-        const int bc = __builtin_amdgcn_readfirstlane(L.count[sp]);
-        const u64 m = L.mask[sp];
-        // the block's node records and adjoint sums (5 + 3 float4 per node)
-        if (lane < 5 * bc)
-            reinterpret_cast<float4 *>(L.node)[lane] =
-                reinterpret_cast<const float4 *>(nodes + bf)[lane];
-        if (lane < 3 * bc)
-            reinterpret_cast<float4 *>(&L.adj[0][0])[lane] =
-                reinterpret_cast<const float4 *>(adj + 6 * (int64_t)bf)[lane];
-        wave_sync();
+        const int bc = __builtin_amdgcn_readfirstlane(L.d.count[sp]);
+        const u64 m = L.d.mask[sp];
         const bool mine = (m >> lane) & 1ull;
         for (int k = 0; k < bc; ++k) {
-            const BhNode nd = L.node[k];
+            const BhNode nd = L.d.node[k];
             bool need = false;
             if (mine) {
                 if (decide(nd, xd, yd, zd, bp)) {
@@ -196,62 +244,116 @@ __global__ __launch_bounds__(256) void k_bh_adj_traverse(
             const int nchild = __builtin_amdgcn_readfirstlane(nd.nchild);
             if (nchild == 0) {
                 if (need) c_pairs += (unsigned)ncount;
-                for (int j0 = 0; j0 < ncount; j0 += kAdjStage) {
-                    const int cnt = ncount - j0 < kAdjStage ? ncount - j0 : kAdjStage;
-                    wave_sync();
-                    if (lane < cnt) {
-                        const int j = nfirst + j0 + lane;
-                        L.lq[lane] = Qs[j];
-                        L.lp[lane] = Ps[j];
-                        L.la[lane] = As[j];
-                        L.lb[lane] = Bs[j];
+                if (nlist < kSegCap) {
+                    if (lane == 0) {
+                        LeafEntry e;
+                        e.mask = open;
+                        e.first = nfirst;
+                        e.count = ncount;
+                        mylist[nlist] = e;
                     }
-                    wave_sync();
-                    if (need) {
-                        float gq[3] = {0.f, 0.f, 0.f}, gp[3] = {0.f, 0.f, 0.f};
-                        for (int j = 0; j < cnt; ++j)
-                            adj_pair(xq, xp, xa, xb, L.lq[j], L.lp[j], L.la[j], L.lb[j], bp.negc,
-                                     inv_s2, gq, gp);
-#pragma unroll
-                        for (int c = 0; c < 3; ++c) {
-                            GQ[c] += (double)gq[c];
-                            GP[c] += (double)gp[c];
-                        }
-                    }
+                    ++nlist;
+                } else {  // segment full: sum this leaf here
+                    leaf_adjoint(Qs, Ps, As, Bs, nfirst, ncount, need, xq, xp, xa, xb, bp.negc,
+                                 inv_s2, GQ, GP);
                 }
             } else {
-                if (sp >= kAdjStack) {
+                if (sp >= kBlockStack) {
+                    // cannot happen for trees of at most 22 levels; stop safely
                     if (lane == 0 && status) *status = 2;
                     sp = -1;
                     break;
                 }
-                L.first[sp] = nfirst;
-                L.count[sp] = nchild;
-                L.mask[sp] = open;
+                L.d.first[sp] = nfirst;
+                L.d.count[sp] = nchild;
+                L.d.mask[sp] = open;
                 ++sp;
             }
         }
         if (sp < 0) break;
         wave_sync();
+        if (sp > 0)
+            load_block(nodes, adj, __builtin_amdgcn_readfirstlane(L.d.first[sp - 1]),
+                       __builtin_amdgcn_readfirstlane(L.d.count[sp - 1]), lane, L);
+        wave_sync();
     }
-    if (active) {
-        const int64_t i = perm[t];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            al[3 * i + c] += dt * (GQ[c] * bp.inv_s2);
-            be[3 * i + c] += dt * GP[c];
-        }
-    }
+    write_part(part, sub, npad, grp * 64 + lane, GQ, GP);
+    if (lane == 0) list_n[grp * kSub + sub] = nlist;
     u64 cp = c_pairs, cm = c_mono;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
         cp += __shfl_down(cp, off, 64);
         cm += __shfl_down(cm, off, 64);
     }
-    if (lane == 0 && counters) {
+    if (lane == 0 && counters && (cp != 0 || cm != 0)) {
         u64 *c = counter_slot(counters, blockIdx.x);
         if (cp) atomicAdd(&c[0], cp);
         if (cm) atomicAdd(&c[1], cm);
+    }
+}
+
+// Phase 2: one wave per (group, chunk of its list entries).
+__global__ __launch_bounds__(256) void k_adj_leaves(
+    const float4 *__restrict__ Qs, const float4 *__restrict__ Ps, const float4 *__restrict__ As,
+    const float4 *__restrict__ Bs, int64_t n, const GroupDesc *__restrict__ gtab, int64_t groups,
+    TravSplit split, float negc, float inv_s2, const LeafEntry *__restrict__ list,
+    const int *__restrict__ list_n,
+    double *__restrict__ part) {
+    __shared__ float4 stage[4][4][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t grp = blockIdx.x;
+    const int chunk = blockIdx.y * 4 + wv;
+    const ChunkSplit cs = chunk_split(list_n, grp, split);
+    const int v0 = chunk * cs.per;
+    if (chunk >= cs.chunks || v0 >= cs.total) return;  // wave-uniform: no entries here
+    const int v1 = v0 + cs.per < cs.total ? v0 + cs.per : cs.total;
+    ListCursor cur = list_seek(list_n, grp, split.nsub, v0);
+    const int64_t npad = groups * 64;
+    const GroupDesc gd = group_desc(gtab, grp, n);
+    const int64_t t = (int64_t)gd.first + lane;
+    const bool active = lane < gd.count;
+    const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    const float4 xq = active ? Qs[t] : z4, xp = active ? Ps[t] : z4;
+    const float4 xa = active ? As[t] : z4, xb = active ? Bs[t] : z4;
+    double GQ[3] = {0, 0, 0}, GP[3] = {0, 0, 0};
+    for (int r = v0; r < v1; ++r) {
+        const LeafEntry e = list_take(list, list_n, grp, split.nsub, cur);
+        const int first = __builtin_amdgcn_readfirstlane(e.first);
+        const int count = __builtin_amdgcn_readfirstlane(e.count);
+        leaf_adjoint_staged(Qs, Ps, As, Bs, first, count, ((e.mask >> lane) & 1ull) != 0, xq, xp,
+                            xa, xb, negc, inv_s2, GQ, GP, stage[wv], lane);
+    }
+    write_part(part, split.nsub + chunk, npad, grp * 64 + lane, GQ, GP);
+}
+
+// Phase 3: fixed-order sum of a target's parts; (alpha, beta) += dt
+// (sigma^-2 g_q, g_p) in original order.
+__global__ __launch_bounds__(256) void k_adj_combine(
+    const double *__restrict__ part, const int *__restrict__ list_n,
+    const GroupDesc *__restrict__ gtab, int64_t groups, TravSplit split,
+    const unsigned *__restrict__ perm, int64_t n, double inv_s2, double dt,
+    double *__restrict__ al, double *__restrict__ be) {
+    const int lane = threadIdx.x & 63;
+    const int64_t grp = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (grp >= groups) return;
+    const GroupDesc gd = group_desc(gtab, grp, n);
+    if (lane >= gd.count) return;
+    const int64_t npad = groups * 64, slot = grp * 64 + lane;
+    const int nslots = split.nsub + chunk_split(list_n, grp, split).chunks;
+    double GQ[3] = {0, 0, 0}, GP[3] = {0, 0, 0};
+    for (int s = 0; s < nslots; ++s) {
+        const double *d = part + ((int64_t)s * npad + slot) * 6;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            GQ[c] += d[c];
+            GP[c] += d[3 + c];
+        }
+    }
+    const int64_t i = perm[(int64_t)gd.first + lane];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        al[3 * i + c] += dt * (GQ[c] * inv_s2);
+        be[3 * i + c] += dt * GP[c];
     }
 }
 
@@ -307,12 +409,21 @@ gs_status bh_adjoint_step(AdjointBufs &b, const gs_params &prm, double dt, const
                        b.bhadj.ALs, b.bhadj.BEs);
     GS_LAUNCH_CHECK("gather_ab");
     GS_TRY(tree_range_sums(b.bhadj.ALs, b.bhadj.BEs, t, t.adj, s));
+    const BhParams bp = make_bh_params(prm);
+    LeafEntry *list = reinterpret_cast<LeafEntry *>(t.list);
+    const TravSplit split = traverse_split(t.groups);
     timing_begin(KIND_ADJOINT, s);
-    hipLaunchKernelGGL(k_bh_adj_traverse, dim3(nblk(t.groups, 4)), dim3(256), 0, s, t.nodes,
-                       t.adj, t.Qs, t.Ps, b.bhadj.ALs, b.bhadj.BEs, t.perm, n, t.gtab, t.groups,
-                       make_bh_params(prm), dt, b.al, b.be, counters, status);
+    hipLaunchKernelGGL(k_adj_decide, dim3((unsigned)((t.groups * split.nsub + 3) / 4)), dim3(256), 0,
+                       s, t.nodes, t.adj, t.Qs, t.Ps, b.bhadj.ALs, b.bhadj.BEs, n, t.gtab,
+                       t.groups, split, bp, list, t.list_n, t.part, counters, status);
+    hipLaunchKernelGGL(k_adj_leaves, dim3((unsigned)t.groups, (split.maxc + 3) / 4), dim3(256), 0, s,
+                       t.Qs, t.Ps, b.bhadj.ALs, b.bhadj.BEs, n, t.gtab, t.groups, split, bp.negc,
+                       bp.inv_s2f, list, t.list_n, t.part);
+    hipLaunchKernelGGL(k_adj_combine, dim3((unsigned)((t.groups + 3) / 4)), dim3(256), 0, s,
+                       t.part, t.list_n, t.gtab, t.groups, split, t.perm, n, bp.inv_s2, dt, b.al,
+                       b.be);
     timing_end(KIND_ADJOINT, s);
-    GS_LAUNCH_CHECK("bh_adj_traverse");
+    GS_LAUNCH_CHECK("bh_adjoint phases");
     return GS_OK;
 }
 

@@ -1,0 +1,138 @@
+// traverse.h -- work split of the Barnes-Hut traversals (forward and
+// backward stage): group layout, leaf lists and partial-sum slots shared by
+// traverse.hip and bh_adjoint.hip.
+#pragma once
+
+#include "tree.h"
+
+namespace gs {
+namespace trav {
+
+typedef unsigned long long u64;
+
+// ---------------------------------------------------------------- layout
+// Work split.  A group is 64 consecutive targets of the Morton order (one
+// wave's lanes).  Phase 1 walks the tree for a group with kSub waves that
+// share out the children of the tree's root (the root contains every target
+// of its tree, so it is never approximated and every target opens it): each
+// wave takes the decisions in its children's subtrees, adds the monopoles,
+// and records each leaf that some lane must sum exactly as an entry (leaf,
+// lane mask) of its own list segment.  Measured at 200k points (theta 0.5,
+// leaf_cap 64), with 1, 2, 4 and 8 waves per group: 1.18, 1.10, 1.07 and
+// 1.41 ms per traversal (at leaf_cap 16: 1.83, 1.85, 1.92, 2.25 ms).
+// Phase 2 splits the group's entries, taken segment by segment, into at
+// most kMaxChunks chunks of at least kMinChunk entries and adds their exact
+// pairs with one wave per chunk, so the near-field work of a dense group is
+// spread over many waves.  Phase 3 adds the partial sums of a target in a
+// fixed order (the phase-1 waves, then the chunks): the result does not
+// depend on scheduling.
+//
+// How many phase-1 and phase-2 waves a group gets depends on the number of
+// groups (TravSplit, chosen on the host): when there are many groups the
+// launch is full anyway and splitting only adds partial sums to write and
+// read back.
+constexpr int kBlockStack = 192;  // entries of (first child, count, lane mask)
+constexpr int kSub = 4;           // phase-1 waves per group, at most
+constexpr int kSegCap = 2048 / kSub;  // list entries per phase-1 wave (more are summed in phase 1)
+constexpr int kMaxChunks = 16;    // phase-2 waves per group, at most
+constexpr int kMinChunk = 32;     // entries per phase-2 wave, at least (unless fewer in all)
+constexpr int kParts = kSub + kMaxChunks;
+
+// Waves per group: nsub (<= kSub) in phase 1, at most maxc (<= kMaxChunks) in
+// phase 2.  Partial-sum slots: 0..nsub-1 for phase 1, then nsub + chunk.
+struct TravSplit {
+    int nsub, maxc;
+};
+TravSplit traverse_split(int64_t groups);
+
+struct LeafEntry {
+    u64 mask;
+    int first;
+    int count;
+};
+
+struct DecideLds {
+    u64 mask[kBlockStack];
+    int first[kBlockStack];
+    int count[kBlockStack];
+    BhNode node[8];  // the sibling block being decided
+};
+
+// Targets of group g: the table entry, or 64 consecutive points of one tree.
+__device__ inline GroupDesc group_desc(const GroupDesc *__restrict__ gtab, int64_t g, int64_t n) {
+    if (gtab) return gtab[g];
+    GroupDesc d;
+    d.first = (int)(g * 64);
+    const int64_t r = n - g * 64;
+    d.count = r < 64 ? (int)r : 64;
+    d.root = 0;
+    d.sub = 0;
+    return d;
+}
+
+// Orders the LDS writes of this wave before its following LDS reads (all
+// lanes of a wave run in lock step; this only stops compiler reordering).
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline void write_part(double *__restrict__ part, int slot, int64_t npad, int64_t t,
+                                  const double *V, const double *A) {
+    double *d = part + ((int64_t)slot * npad + t) * 6;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        d[c] = V[c];
+        d[3 + c] = A[c];
+    }
+}
+
+// The phase-2 split of a group: its list entries (segments 0..kSub-1 one
+// after the other) in `chunks` chunks of `per` entries (the last one
+// shorter).
+struct ChunkSplit {
+    int total, chunks, per;
+};
+__device__ inline ChunkSplit chunk_split(const int *__restrict__ list_n, int64_t grp,
+                                         TravSplit split) {
+    ChunkSplit c;
+    c.total = 0;
+    for (int k = 0; k < split.nsub; ++k) c.total += list_n[grp * kSub + k];
+    c.chunks = (c.total + kMinChunk - 1) / kMinChunk;
+    if (c.chunks > split.maxc) c.chunks = split.maxc;
+    c.per = c.chunks > 0 ? (c.total + c.chunks - 1) / c.chunks : 0;
+    return c;
+}
+
+// A position (segment, offset) in a group's concatenated list segments.
+struct ListCursor {
+    int seg, off, segn;
+};
+__device__ inline void list_normalize(const int *__restrict__ list_n, int64_t grp, int nsub,
+                                      ListCursor &c) {
+    while (c.off >= c.segn && c.seg < nsub - 1) {
+        c.off -= c.segn;
+        ++c.seg;
+        c.segn = list_n[grp * kSub + c.seg];
+    }
+}
+// The cursor at entry v (< the group's total) of the concatenated list.
+__device__ inline ListCursor list_seek(const int *__restrict__ list_n, int64_t grp, int nsub,
+                                      int v) {
+    ListCursor c{0, v, list_n[grp * kSub]};
+    list_normalize(list_n, grp, nsub, c);
+    return c;
+}
+// The entry under the cursor (wave-uniform); the cursor moves to the next.
+__device__ inline LeafEntry list_take(const LeafEntry *__restrict__ list,
+                                      const int *__restrict__ list_n, int64_t grp, int nsub,
+                                      ListCursor &c) {
+    const LeafEntry e = list[(grp * kSub + c.seg) * kSegCap + c.off];
+    ++c.off;
+    list_normalize(list_n, grp, nsub, c);
+    return e;
+}
+
+}  // namespace trav
+}  // namespace gs

@@ -18,72 +18,18 @@
 // with wave-uniform (scalar) loads, lanes outside a leaf's mask switched off.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
+#include <cstdlib>
 
-#include "tree.h"
+#include "traverse.h"
 
 namespace gs {
 
 namespace {
 
-typedef unsigned long long u64;
+using namespace trav;
 
-
-// ---------------------------------------------------------------- layout
-// Work split.  A group is 64 consecutive targets of the Morton order (one
-// wave's lanes).  Phase 1 walks the tree for a group with kSub waves that
-// share out the children of the tree's root (the root contains every target
-// of its tree, so it is never approximated and every target opens it): each
-// wave takes the decisions in its children's subtrees, adds the monopoles,
-// and records each leaf that some lane must sum exactly as an entry (leaf,
-// lane mask) of its own list segment.  Measured at 200k points (theta 0.5,
-// leaf_cap 64), with 1, 2, 4 and 8 waves per group: 1.18, 1.10, 1.07 and
-// 1.41 ms per traversal (at leaf_cap 16: 1.83, 1.85, 1.92, 2.25 ms).  Phase 2 splits the group's entries, taken segment by
-// segment, into at most kMaxChunks chunks of at least kMinChunk entries and
-// adds their exact pairs with one wave per chunk, so the near-field work of
-// a dense group is spread over many waves.  Phase 3 adds the partial sums of
-// a target in a fixed order (the phase-1 waves, then the chunks): the result
-// does not depend on scheduling.
-constexpr int kBlockStack = 192;  // entries of (first child, count, lane mask)
-constexpr int kSub = 4;           // phase-1 waves per group (the root's children split among them)
-constexpr int kSegCap = 2048 / kSub;  // list entries per phase-1 wave (more are summed in phase 1)
-constexpr int kMaxChunks = 16;    // phase-2 waves per group
-constexpr int kMinChunk = 32;     // entries per phase-2 wave, at least (unless fewer in all)
-constexpr int kParts = kSub + kMaxChunks;
-
-struct LeafEntry {
-    u64 mask;
-    int first;
-    int count;
-};
-
-
-struct DecideLds {
-    u64 mask[kBlockStack];
-    int first[kBlockStack];
-    int count[kBlockStack];
-    BhNode node[8];  // the sibling block being decided
-};
-
-// Targets of group g: the table entry, or 64 consecutive points of one tree.
-__device__ inline GroupDesc group_desc(const GroupDesc *__restrict__ gtab, int64_t g, int64_t n) {
-    if (gtab) return gtab[g];
-    GroupDesc d;
-    d.first = (int)(g * 64);
-    const int64_t r = n - g * 64;
-    d.count = r < 64 ? (int)r : 64;
-    d.root = 0;
-    d.sub = 0;
-    return d;
-}
-
-// Orders the LDS writes of this wave before its following LDS reads (all
-// lanes of a wave run in lock step; this only stops compiler reordering).
-__device__ inline void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // Exact pairs of one leaf, sorted points [first, first + count), for the
 // lanes with `mine` set.  first and count are wave-uniform, so the points are
@@ -150,29 +96,20 @@ __device__ __forceinline__ void leaf_direct(const float4 *__restrict__ Qs,
     }
 }
 
-__device__ inline void write_part(double *__restrict__ part, int slot, int64_t npad, int64_t t,
-                                  const double *V, const double *A) {
-    double *d = part + ((int64_t)slot * npad + t) * 6;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        d[c] = V[c];
-        d[3 + c] = A[c];
-    }
-}
 
 // Phase 1: decisions, monopoles and the group's list of leaves.
 template <bool WITH_A>
 __global__ __launch_bounds__(256) void k_bh_decide(
     const BhNode *__restrict__ nodes, const float4 *__restrict__ Qs, const float4 *__restrict__ Ps,
-    int64_t n, const GroupDesc *__restrict__ gtab, int64_t groups, BhParams bp,
+    int64_t n, const GroupDesc *__restrict__ gtab, int64_t groups, TravSplit split, BhParams bp,
     LeafEntry *__restrict__ list, int *__restrict__ list_n, double *__restrict__ part,
     u64 *__restrict__ counters, const TreeTotals *__restrict__ totals, int *__restrict__ status) {
     __shared__ DecideLds lds_all[4];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     DecideLds &L = lds_all[wv];
     const int64_t wave = (int64_t)blockIdx.x * 4 + wv;
-    const int64_t grp = wave / kSub;
-    const int sub = (int)(wave % kSub);
+    const int64_t grp = wave / split.nsub;
+    const int sub = (int)(wave % split.nsub);
     if (grp >= groups) return;  // wave-uniform; this kernel has no block barrier
     const int64_t npad = groups * 64;
     const GroupDesc gd = group_desc(gtab, grp, n);
@@ -193,7 +130,7 @@ __global__ __launch_bounds__(256) void k_bh_decide(
     // no share is idle
     const int rchild = __builtin_amdgcn_readfirstlane(nodes[gd.root].nchild);
     const int rfirst = __builtin_amdgcn_readfirstlane(nodes[gd.root].first);
-    const int lo = sub * rchild / kSub, hi = (sub + 1) * rchild / kSub;
+    const int lo = sub * rchild / split.nsub, hi = (sub + 1) * rchild / split.nsub;
     const int start = rchild == 0 ? (sub == 0 ? gd.root : -1) : (hi > lo ? rfirst + lo : -1);
     const int start_n = rchild == 0 ? 1 : hi - lo;
     if (rchild > 0 && sub == 0) {  // the root's visit, counted once
@@ -318,29 +255,13 @@ __global__ __launch_bounds__(256) void k_bh_decide(
     }
 }
 
-// The phase-2 split of a group: its list entries (segments 0..kSub-1 one
-// after the other) in `chunks` chunks of `per` entries (the last one
-// shorter).
-struct ChunkSplit {
-    int total, chunks, per;
-};
-__device__ inline ChunkSplit chunk_split(const int *__restrict__ list_n, int64_t grp) {
-    ChunkSplit c;
-    c.total = 0;
-#pragma unroll
-    for (int k = 0; k < kSub; ++k) c.total += list_n[grp * kSub + k];
-    c.chunks = (c.total + kMinChunk - 1) / kMinChunk;
-    if (c.chunks > kMaxChunks) c.chunks = kMaxChunks;
-    c.per = c.chunks > 0 ? (c.total + c.chunks - 1) / c.chunks : 0;
-    return c;
-}
 
 // Phase 2: one wave per (group, chunk of its list entries).
 template <bool WITH_A>
 __global__ __launch_bounds__(256) void k_bh_leaves(const float4 *__restrict__ Qs,
                                                    const float4 *__restrict__ Ps, int64_t n,
                                                    const GroupDesc *__restrict__ gtab,
-                                                   int64_t groups, float negc,
+                                                   int64_t groups, TravSplit split, float negc,
                                                    const LeafEntry *__restrict__ list,
                                                    const int *__restrict__ list_n,
                                                    double *__restrict__ part,
@@ -348,17 +269,11 @@ __global__ __launch_bounds__(256) void k_bh_leaves(const float4 *__restrict__ Qs
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t grp = blockIdx.x;
     const int chunk = blockIdx.y * 4 + wv;
-    const ChunkSplit cs = chunk_split(list_n, grp);
-    int v0 = chunk * cs.per;
+    const ChunkSplit cs = chunk_split(list_n, grp, split);
+    const int v0 = chunk * cs.per;
     if (chunk >= cs.chunks || v0 >= cs.total) return;  // wave-uniform: no entries here
     const int v1 = v0 + cs.per < cs.total ? v0 + cs.per : cs.total;
-    // the segment holding entry v0 of the group's concatenated list
-    int seg = 0, segn = list_n[grp * kSub];
-    while (v0 >= segn && seg < kSub - 1) {
-        v0 -= segn;
-        ++seg;
-        segn = list_n[grp * kSub + seg];
-    }
+    ListCursor cur = list_seek(list_n, grp, split.nsub, v0);
     const int64_t npad = groups * 64;
     const GroupDesc gd = group_desc(gtab, grp, n);
     const int64_t t = (int64_t)gd.first + lane;
@@ -367,21 +282,15 @@ __global__ __launch_bounds__(256) void k_bh_leaves(const float4 *__restrict__ Qs
     const float4 xp = active ? Ps[t] : make_float4(0.f, 0.f, 0.f, 0.f);
     double V[3] = {0, 0, 0}, A[3] = {0, 0, 0};
     unsigned steps = 0;
-    for (int r = chunk * cs.per; r < v1; ++r) {
-        while (v0 >= segn && seg < kSub - 1) {  // next non-empty segment
-            v0 = 0;
-            ++seg;
-            segn = list_n[grp * kSub + seg];
-        }
-        const LeafEntry e = list[(grp * kSub + seg) * kSegCap + v0];  // wave-uniform
-        ++v0;
+    for (int r = v0; r < v1; ++r) {
+        const LeafEntry e = list_take(list, list_n, grp, split.nsub, cur);
         const int first = __builtin_amdgcn_readfirstlane(e.first);
         const int count = __builtin_amdgcn_readfirstlane(e.count);
         steps += (unsigned)count;
         leaf_direct<WITH_A>(Qs, Ps, first, count, ((e.mask >> lane) & 1ull) != 0, xq, xp, negc, V,
                             A);
     }
-    write_part(part, kSub + chunk, npad, grp * 64 + lane, V, A);
+    write_part(part, split.nsub + chunk, npad, grp * 64 + lane, V, A);
     if (lane == 0 && counters) {
         u64 *c = counter_slot(counters, blockIdx.x, blockIdx.y);
         atomicAdd(&c[4], (u64)steps);
@@ -395,8 +304,8 @@ __global__ __launch_bounds__(256) void k_bh_leaves(const float4 *__restrict__ Qs
 template <bool WITH_A>
 __global__ __launch_bounds__(256) void k_bh_combine(
     const double *__restrict__ part, const int *__restrict__ list_n,
-    const GroupDesc *__restrict__ gtab, int64_t groups, const unsigned *__restrict__ perm,
-    int64_t n, double inv_s2, int mode, float *__restrict__ dq, float *__restrict__ dp,
+    const GroupDesc *__restrict__ gtab, int64_t groups, TravSplit split,
+    const unsigned *__restrict__ perm, int64_t n, double inv_s2, int mode, float *__restrict__ dq, float *__restrict__ dp,
     double *__restrict__ Sq, double *__restrict__ Sp, float *__restrict__ q32,
     float *__restrict__ p32, double dt, double *__restrict__ Hpart, double *__restrict__ v64) {
     const int lane = threadIdx.x & 63;
@@ -407,7 +316,7 @@ __global__ __launch_bounds__(256) void k_bh_combine(
     const GroupDesc gd = group_desc(gtab, grp, n);
     double e = 0.0;
     if (lane < gd.count) {
-        const int nslots = kSub + chunk_split(list_n, grp).chunks;
+        const int nslots = split.nsub + chunk_split(list_n, grp, split).chunks;
         double V[3] = {0, 0, 0}, A[3] = {0, 0, 0};
         for (int s = 0; s < nslots; ++s) {
             const double *d = part + ((int64_t)s * npad + slot) * 6;
@@ -495,6 +404,27 @@ size_t traverse_list_bytes(int64_t groups) {
 
 size_t traverse_count_ints(int64_t groups) { return (size_t)groups * kSub; }
 
+// Phase-1 waves aim at about GS_BH_DECIDE_WAVES waves in all (default 12288,
+// 12 per SIMD), phase-2 waves at GS_BH_LEAF_WAVES (default 65536); the
+// environment overrides are for tuning sweeps.
+static int64_t env_waves(const char *name, int64_t dflt) {
+    const char *e = getenv(name);
+    const long long v = e ? atoll(e) : 0;
+    return v >= 1 && v <= (1 << 24) ? (int64_t)v : dflt;
+}
+
+namespace trav {
+TravSplit traverse_split(int64_t groups) {
+    static const int64_t w1 = env_waves("GS_BH_DECIDE_WAVES", 12288);
+    static const int64_t w2 = env_waves("GS_BH_LEAF_WAVES", 65536);
+    const int64_t g = groups > 0 ? groups : 1;
+    TravSplit split;
+    split.nsub = (int)std::min<int64_t>(kSub, std::max<int64_t>(1, (w1 + g - 1) / g));
+    split.maxc = (int)std::min<int64_t>(kMaxChunks, std::max<int64_t>(1, (w2 + g - 1) / g));
+    return split;
+}
+}  // namespace trav
+
 size_t traverse_part_doubles(int64_t groups) { return (size_t)kParts * groups * 64 * 6; }
 
 BhParams make_bh_params(const gs_params &prm) {
@@ -517,20 +447,20 @@ gs_status launch_bh_traverse(const TreeBufs &t, const BhParams &bp, bool with_a,
     if (groups <= 0) return GS_OK;
     LeafEntry *list = reinterpret_cast<LeafEntry *>(t.list);
     const int kind = with_a ? KIND_TRAVERSE : KIND_TRAVERSE_V;
+    const TravSplit split = traverse_split(groups);
+    const dim3 g1((unsigned)((groups * split.nsub + 3) / 4)), g2((unsigned)groups, (split.maxc + 3) / 4),
+        g3((unsigned)((groups + 3) / 4));
     timing_begin(kind, s);
-#define GS_PHASES(A)                                                                            \
-    do {                                                                                        \
-        hipLaunchKernelGGL(k_bh_decide<A>, dim3((unsigned)((groups * kSub + 3) / 4)), dim3(256), \
-                           0, s,                                                                \
-                           t.nodes, t.Qs, t.Ps, t.n, t.gtab, groups, bp, list, t.list_n,        \
-                           t.part, counters, t.totals, status);                                 \
-        hipLaunchKernelGGL(k_bh_leaves<A>, dim3((unsigned)groups, kMaxChunks / 4), dim3(256), 0, \
-                           s,                                                                   \
-                           t.Qs, t.Ps, t.n, t.gtab, groups, bp.negc, list, t.list_n, t.part,    \
-                           counters);                                                           \
-        hipLaunchKernelGGL(k_bh_combine<A>, dim3((unsigned)((groups + 3) / 4)), dim3(256), 0, s, \
-                           t.part, t.list_n, t.gtab, groups, t.perm, t.n, bp.inv_s2, mode,      \
-                           o.dq, o.dp, o.Sq, o.Sp, o.q32, o.p32, o.dt, o.Hpart, o.v64);         \
+#define GS_PHASES(A)                                                                         \
+    do {                                                                                     \
+        hipLaunchKernelGGL(k_bh_decide<A>, g1, dim3(256), 0, s, t.nodes, t.Qs, t.Ps, t.n,     \
+                           t.gtab, groups, split, bp, list, t.list_n, t.part, counters,        \
+                           t.totals, status);                                               \
+        hipLaunchKernelGGL(k_bh_leaves<A>, g2, dim3(256), 0, s, t.Qs, t.Ps, t.n, t.gtab,      \
+                           groups, split, bp.negc, list, t.list_n, t.part, counters);          \
+        hipLaunchKernelGGL(k_bh_combine<A>, g3, dim3(256), 0, s, t.part, t.list_n, t.gtab,    \
+                           groups, split, t.perm, t.n, bp.inv_s2, mode, o.dq, o.dp, o.Sq, o.Sp, \
+                           o.q32, o.p32, o.dt, o.Hpart, o.v64);                             \
     } while (0)
     if (with_a)
         GS_PHASES(true);
