@@ -113,6 +113,23 @@ def test_bh_adjoint(oracle):
         assert abs(e - be) <= 1e-5 * abs(be)
 
 
+def test_bh_adjoint_long_leaf_lists(oracle):
+    """Single-point leaves on a dense set: a group's list of leaves to sum
+    exactly outgrows its segment, and the rest is summed in the decide
+    phase; the gradient must still match the oracle's Barnes-Hut gradient."""
+    w = W.adjoint_50k(n=20000)
+    nt, lam = 2, 0.01
+    q, p, y = (x.astype(np.float64) for x in (w.q0, w.p0, w.extra["target"]))
+    e, g = _adj(w, nt, lam, 1, gs.GS_BH, theta=0.5, leaf_cap=1)
+    be, bg = oracle.objective_grad(q, p, y, w.sigma, nt, lam, method="bh", theta=0.5, leaf_cap=1)
+    _, xg = oracle.objective_grad(q, p, y, w.sigma, nt, lam)
+    eps = rel_l2(bg, xg)
+    _say(f"  bh leaf_cap 1, n=20000: eps {eps:.3e} gpu-vs-bh {rel_l2(g, bg):.3e} "
+         f"objective {abs(e - be) / abs(be):.3e}")
+    assert rel_l2(g, bg) <= max(1e-4, 0.1 * eps)
+    assert abs(e - be) <= 1e-5 * abs(be)
+
+
 def test_autograd_function():
     w = W.adjoint_50k(n=800)
     p0 = _t(w.p0).requires_grad_(True)
