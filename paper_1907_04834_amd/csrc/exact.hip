@@ -85,19 +85,6 @@ __global__ void k_pack_pos(const float *__restrict__ x, int64_t m, int64_t npad,
                  : make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
-__global__ void k_unpack(const float4 *__restrict__ Q, const float4 *__restrict__ P, int64_t n,
-                         float *__restrict__ q, float *__restrict__ p) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    float4 a = Q[i], b = P[i];
-    q[3 * i] = a.x;
-    q[3 * i + 1] = a.y;
-    q[3 * i + 2] = a.z;
-    p[3 * i] = b.x;
-    p[3 * i + 1] = b.y;
-    p[3 * i + 2] = b.z;
-}
-
 // Sums of targets t0 + 64 k (k < T, one lane each) over sources [j0, j1)
 // (a multiple of kTile), written as six FP64 rows of dst (row stride ntgt).
 template <int T, bool WITH_A>
@@ -572,8 +559,7 @@ __global__ __launch_bounds__(256) void k_combine_euler(const double *__restrict_
                                                        double *__restrict__ Sp,
                                                        float4 *__restrict__ Q,
                                                        float4 *__restrict__ P,
-                                                       double *__restrict__ Hpart,
-                                                       double *__restrict__ vout) {
+                                                       double *__restrict__ Hpart) {
     __shared__ double lds[8];
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double e = 0.0;
@@ -589,9 +575,6 @@ __global__ __launch_bounds__(256) void k_combine_euler(const double *__restrict_
             p[c] = Sp[3 * i + c];
         }
         e = p[0] * acc[0] + p[1] * acc[1] + p[2] * acc[2];
-        if (vout)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) vout[3 * i + c] = acc[c];
         if (dt > 0.0) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
@@ -881,13 +864,6 @@ gs_status launch_pack_pos(const float *x, int64_t m, int64_t npad, float4 *X, hi
     return GS_OK;
 }
 
-gs_status launch_unpack(const float4 *Q, const float4 *P, int64_t n, float *q, float *p,
-                        hipStream_t s) {
-    hipLaunchKernelGGL(k_unpack, dim3(nblocks(n)), dim3(kBlock), 0, s, Q, P, n, q, p);
-    GS_LAUNCH_CHECK("unpack");
-    return GS_OK;
-}
-
 gs_status launch_exact_pairs(const ExactPlan &pl, const float4 *Qt, const float4 *Pt,
                              const float4 *Qs, const float4 *Ps, double sigma, bool with_a,
                              double *part, hipStream_t s) {
@@ -941,15 +917,9 @@ gs_status launch_combine_rhs(const ExactPlan &pl, const double *part, double sig
 gs_status launch_combine_euler(const ExactPlan &pl, const double *part, double sigma, double dt,
                                double *Sq, double *Sp, float4 *Q, float4 *P, double *Hpart,
                                hipStream_t s) {
-    return launch_combine_euler_v(pl, part, sigma, dt, Sq, Sp, Q, P, Hpart, nullptr, s);
-}
-
-gs_status launch_combine_euler_v(const ExactPlan &pl, const double *part, double sigma,
-                                 double dt, double *Sq, double *Sp, float4 *Q, float4 *P,
-                                 double *Hpart, double *vout, hipStream_t s) {
     hipLaunchKernelGGL(k_combine_euler, dim3(nblocks(pl.n)), dim3(kBlock), 0, s, part,
                        pl.splits, pl.ntgt, pl.n, 1.0 / (sigma * sigma), dt, Sq, Sp, Q, P,
-                       Hpart, vout);
+                       Hpart);
     GS_LAUNCH_CHECK("combine_euler");
     return GS_OK;
 }

@@ -107,8 +107,6 @@ void carve_exact(Arena &a, const ExactPlan &pl, ExactBufs &b);
 gs_status launch_pack(const float *q, const float *p, int64_t n, int64_t npad, float4 *Q,
                       float4 *P, hipStream_t s);
 gs_status launch_pack_pos(const float *x, int64_t m, int64_t npad, float4 *X, hipStream_t s);
-gs_status launch_unpack(const float4 *Q, const float4 *P, int64_t n, float *q, float *p,
-                        hipStream_t s);
 gs_status launch_exact_pairs(const ExactPlan &pl, const float4 *Qt, const float4 *Pt,
                              const float4 *Qs, const float4 *Ps, double sigma, bool with_a,
                              double *part, hipStream_t s);
@@ -121,10 +119,6 @@ gs_status launch_combine_rhs(const ExactPlan &pl, const double *part, double sig
 gs_status launch_combine_euler(const ExactPlan &pl, const double *part, double sigma,
                                double dt, double *Sq, double *Sp, float4 *Q, float4 *P,
                                double *Hpart, hipStream_t s);
-// The same, also storing the summed velocity in vout (FP64 [n][3], nullable).
-gs_status launch_combine_euler_v(const ExactPlan &pl, const double *part, double sigma,
-                                 double dt, double *Sq, double *Sp, float4 *Q, float4 *P,
-                                 double *Hpart, double *vout, hipStream_t s);
 // FP64 state from float [n][3] inputs, plus its FP32 packed copies.
 gs_status launch_pack_state(const float *q, const float *p, int64_t n, int64_t npad, double *Sq,
                             double *Sp, float4 *Q, float4 *P, hipStream_t s);
