@@ -99,7 +99,12 @@ typedef struct {
                               1 = the paper's single-point leaves            */
     int32_t nt;            /* forward-Euler steps over t in [0, 1], >= 1     */
     uint32_t flags;        /* GS_FLAG_*                                       */
-    int32_t reserved;      /* must be 0                                       */
+    int32_t exact_items;   /* exact FP32 path: work items (blocks of 256
+                              targets x one source chunk) that a launch aims
+                              at; 0 = the library default (24576), else
+                              256..4194304.  Changes speed and workspace
+                              size, not results beyond FP64 summation order;
+                              gs_autotune_exact picks it.                    */
 } gs_params;
 
 /* Library version string (static storage). */
@@ -244,6 +249,21 @@ gs_status gs_shoot_adjoint_batch(const float *q0, const float *p0, const float *
 gs_status gs_autotune_leaf_cap(const float *q, const float *p, const int64_t *offsets,
                                int32_t nsub, gs_params *prm, float *dq, float *dp, void *ws,
                                size_t ws_bytes, hipStream_t stream, double *best_ms);
+
+/* Tuning of the exact FP32 path (gs_rhs_exact, gs_shoot, gs_shoot_adjoint
+ * and the batched calls with GS_EXACT) for given inputs: times one
+ * right-hand side for each exact_items in {6144, 12288, 24576, 49152} whose
+ * workspace fits ws_bytes (after a warm-up run, best of two) on `stream`,
+ * waiting for each, and writes the fastest into prm->exact_items (other
+ * fields unchanged) and its time in milliseconds into *best_ms (nullable).
+ * offsets / nsub as for the batched calls (one set: {0, n}, 1).  dq, dp
+ * (DEVICE float[n][3]) receive the trial right-hand sides.  A workspace of
+ * gs_batch_workspace_bytes(offsets, nsub, prm, GS_EXACT, GS_OP_RHS) with
+ * prm->exact_items = 49152 fits every candidate.  Synchronous: a set-up
+ * call. */
+gs_status gs_autotune_exact(const float *q, const float *p, const int64_t *offsets, int32_t nsub,
+                            gs_params *prm, float *dq, float *dp, void *ws, size_t ws_bytes,
+                            hipStream_t stream, double *best_ms);
 
 /* Waits for `stream` and returns the device-side status word of the last
  * Barnes-Hut call that used this workspace (GS_OK or GS_ERR_NONFINITE). */

@@ -111,8 +111,8 @@ gs_status check_params(const gs_params *prm, bool need_nt, bool need_tree) {
             return GS_ERR_INVALID;
         }
     }
-    if (prm->reserved != 0) {
-        set_error("params.reserved must be 0");
+    if (prm->exact_items != 0 && (prm->exact_items < 256 || prm->exact_items > (1 << 22))) {
+        set_error("exact_items must be 0 or in [256, 4194304] (got %d)", prm->exact_items);
         return GS_ERR_INVALID;
     }
     return GS_OK;
@@ -308,7 +308,7 @@ void layout_batch(Arena &a, const int64_t *off, int nsub, const gs_params &prm, 
     if (adj)
         for (int s = 0; s < nsub; ++s) setn.push_back((double)(off[s + 1] - off[s]));
     if (method == GS_EXACT) {
-        b.xp = plan_exact_batch(off, nsub);
+        b.xp = plan_exact_batch(off, nsub, prm.exact_items);
         carve_exact_batch(a, b.xp, nt, b.ex);
         const int nb = (int)b.xp.blocks.size();
         if (adj) {
@@ -566,6 +566,7 @@ GraphKey graph_key(int entry, std::initializer_list<const void *> ptrs,
     k.ints.push_back(prm.leaf_cap);
     k.ints.push_back(prm.nt);
     k.ints.push_back((int64_t)prm.flags);
+    k.ints.push_back(prm.exact_items);
     k.dbls = {prm.sigma, prm.cutoff_sigmas, prm.theta};
     return k;
 }
@@ -631,7 +632,7 @@ void gs_params_default(gs_params *p) {
     p->leaf_cap = 1;
     p->nt = 40;
     p->flags = 0;
-    p->reserved = 0;
+    p->exact_items = 0;
 }
 
 size_t gs_workspace_bytes(int64_t n, const gs_params *prm, int32_t method, int32_t op) {
@@ -982,6 +983,68 @@ gs_status gs_autotune_leaf_cap(const float *q, const float *p, const int64_t *of
         return st;
     }
     prm->leaf_cap = best_cap;
+    if (best_ms) *best_ms = best;
+    return GS_OK;
+}
+
+gs_status gs_autotune_exact(const float *q, const float *p, const int64_t *offsets, int32_t nsub,
+                            gs_params *prm, float *dq, float *dp, void *ws, size_t ws_bytes,
+                            hipStream_t stream, double *best_ms) {
+    GS_TRY(check_batch_call(offsets, nsub, prm, GS_EXACT, false));
+    const int64_t n = offsets[nsub];
+    if (n == 0) return GS_OK;
+    GS_TRY(check_ptrs({q, p, dq, dp, ws}));
+    static const int cands[] = {6144, 12288, 24576, 49152};
+    gs_params trial = *prm;
+    bool fits[4], any = false;
+    for (int k = 0; k < 4; ++k) {
+        trial.exact_items = cands[k];
+        fits[k] = measure_batch(offsets, nsub, trial, GS_EXACT, GS_OP_RHS) <= ws_bytes;
+        any = any || fits[k];
+    }
+    if (!any) {
+        set_error("autotune: the workspace fits none of the candidates");
+        return GS_ERR_WORKSPACE;
+    }
+    hipEvent_t e0, e1;
+    GS_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        set_error("autotune: hipEventCreate failed");
+        return GS_ERR_HIP;
+    }
+    double best = 1e300;
+    int best_items = cands[0];
+    gs_status st = GS_OK;
+    for (int k = 0; k < 4; ++k) {
+        if (!fits[k]) continue;
+        const int items = cands[k];
+        trial.exact_items = items;
+        float ms_min = 1e30f;
+        for (int rep = 0; rep < 3 && st == GS_OK; ++rep) {  // the first run warms up
+            if (hipEventRecord(e0, stream) != hipSuccess) st = GS_ERR_HIP;
+            if (st == GS_OK)
+                st = gs_rhs_batch(q, p, offsets, nsub, &trial, GS_EXACT, dq, dp, ws, ws_bytes,
+                                  stream);
+            if (st == GS_OK && hipEventRecord(e1, stream) != hipSuccess) st = GS_ERR_HIP;
+            if (st == GS_OK && hipEventSynchronize(e1) != hipSuccess) st = GS_ERR_HIP;
+            float ms = 0.f;
+            if (st == GS_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = GS_ERR_HIP;
+            if (st == GS_OK && rep > 0 && ms < ms_min) ms_min = ms;
+        }
+        if (st != GS_OK) break;
+        if (ms_min < best) {
+            best = ms_min;
+            best_items = items;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != GS_OK) {
+        if (st == GS_ERR_HIP) set_error("autotune: a HIP call failed");
+        return st;
+    }
+    prm->exact_items = best_items;
     if (best_ms) *best_ms = best;
     return GS_OK;
 }

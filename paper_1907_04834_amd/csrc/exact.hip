@@ -964,7 +964,7 @@ static int64_t item_blocks() {
     return v;
 }
 
-ExactBatchPlan plan_exact_batch(const int64_t *offsets, int nsub) {
+ExactBatchPlan plan_exact_batch(const int64_t *offsets, int nsub, int64_t items) {
     ExactBatchPlan pl{};
     pl.nsub = nsub;
     pl.ntot = offsets[nsub];
@@ -979,11 +979,13 @@ ExactBatchPlan plan_exact_batch(const int64_t *offsets, int nsub) {
         work += tp[s] * sp[s];
     }
     pl.npad = rows > 0 ? rows : 256;
-    // Source chunk: about item_blocks() blocks of 256 targets in a launch,
-    // never below 2048 sources.
-    const int64_t blocks = item_blocks();
+    // Source chunk: about `items` blocks of 256 targets in a launch, never
+    // below 256 sources (4 tiles).  Small sets need the short chunks to fill
+    // the GPU: one RHS of 5000 / 20 000 points took 0.119 / 0.308 ms with
+    // chunks of at least 2048 sources, 0.025 / 0.152 ms with at least 256.
+    const int64_t blocks = items > 0 ? items : item_blocks();
     int64_t chunk = round_up((work + 256 * blocks - 1) / (256 * blocks), kTile);
-    if (chunk < 2048) chunk = 2048;
+    if (chunk < 256) chunk = 256;
     pl.max_chunks = 1;
     pl.bseg.resize(nsub + 1);
     struct Chunk {

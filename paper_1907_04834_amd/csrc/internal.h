@@ -147,7 +147,9 @@ struct ExactBatchPlan {
     std::vector<int4> blocks;     // per 256-row block: (first real point, count, set, slots)
     std::vector<int> bseg;        // [nsub + 1] row-block range of each set
 };
-ExactBatchPlan plan_exact_batch(const int64_t *offsets, int nsub);
+// `items`: work items a launch aims at (0: the default, or the
+// GS_EXACT_ITEM_BLOCKS environment override).
+ExactBatchPlan plan_exact_batch(const int64_t *offsets, int nsub, int64_t items = 0);
 struct ExactBatchBufs {
     float4 *Q, *P;                // [npad] packed FP32 state (scaled positions), zero padding
     double *part;                 // [max_chunks][6][npad]

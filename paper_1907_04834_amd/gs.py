@@ -37,12 +37,13 @@ class Params(ctypes.Structure):
     _fields_ = [("sigma", ctypes.c_double), ("cutoff_sigmas", ctypes.c_double),
                 ("theta", ctypes.c_double), ("leaf_cap", ctypes.c_int32),
                 ("nt", ctypes.c_int32), ("flags", ctypes.c_uint32),
-                ("reserved", ctypes.c_int32)]
+                ("exact_items", ctypes.c_int32)]
 
 
-def params(sigma, nt=40, theta=0.5, cutoff_sigmas=3.0, leaf_cap=1, flags=0) -> Params:
+def params(sigma, nt=40, theta=0.5, cutoff_sigmas=3.0, leaf_cap=1, flags=0,
+           exact_items=0) -> Params:
     return Params(float(sigma), float(cutoff_sigmas), float(theta), int(leaf_cap),
-                  int(nt), int(flags), 0)
+                  int(nt), int(flags), int(exact_items))
 
 
 _lib = None
@@ -74,6 +75,8 @@ _SIGS = {
                                               _vp, _vp, _vp, _sz, _vp]),
     "gs_autotune_leaf_cap": (ctypes.c_int, [_vp, _vp, _vp, _i32, _PP, _vp, _vp, _vp, _sz,
                                             _vp, ctypes.POINTER(ctypes.c_double)]),
+    "gs_autotune_exact": (ctypes.c_int, [_vp, _vp, _vp, _i32, _PP, _vp, _vp, _vp, _sz, _vp,
+                                         ctypes.POINTER(ctypes.c_double)]),
     "gs_get_status": (ctypes.c_int, [_vp, _vp]),
     "gs_bh_counters": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(ctypes.c_int64)]),
     "gs_kernel_timing": (ctypes.c_int, [_i32]),
@@ -338,6 +341,25 @@ def gs_autotune_leaf_cap(q, p, prm: Params, offsets=None, ws=None):
     _check(lib().gs_autotune_leaf_cap(_ptr(q), _ptr(p), off, nsub, ctypes.byref(out), _ptr(dq),
                                       _ptr(dp), _ptr(ws), ws.numel(), _stream(q.device),
                                       ctypes.byref(ms)))
+    return out, ms.value
+
+
+def gs_autotune_exact(q, p, prm: Params, offsets=None, ws=None):
+    """Picks the fastest exact_items for these inputs (exact FP32 path);
+    returns a copy of prm with it set, and the time of one RHS (ms)."""
+    _pts(q, torch.float32, "q")
+    _pts(p, torch.float32, "p")
+    off, nsub = _offsets([0, q.shape[0]] if offsets is None else offsets)
+    out = Params.from_buffer_copy(prm)
+    if ws is None:
+        big = Params.from_buffer_copy(prm)
+        big.exact_items = 49152  # the largest candidate needs the largest workspace
+        ws = _batch_workspace(off, nsub, big, GS_EXACT, GS_OP_RHS, q.device)
+    ms = ctypes.c_double(0.0)
+    dq, dp = torch.empty_like(q), torch.empty_like(q)
+    _check(lib().gs_autotune_exact(_ptr(q), _ptr(p), off, nsub, ctypes.byref(out), _ptr(dq),
+                                   _ptr(dp), _ptr(ws), ws.numel(), _stream(q.device),
+                                   ctypes.byref(ms)))
     return out, ms.value
 
 

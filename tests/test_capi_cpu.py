@@ -101,6 +101,27 @@ def _off(vals):
     return (ctypes.c_int64 * len(vals))(*vals)
 
 
+def test_exact_items_parameter():
+    prm = gs.params(0.05, nt=4)
+    for bad in (-1, 100, 255, (1 << 22) + 1):
+        prm.exact_items = bad
+        st = _call("gs_rhs_exact", FAKE, FAKE, 10, ctypes.byref(prm), FAKE, FAKE, FAKE, 1 << 30,
+                   None)
+        assert st == -1 and "exact_items" in gs.lib().gs_last_error().decode()
+    # more work items per launch: smaller source chunks, more partial sums
+    sizes = []
+    for items in (6144, 24576, 49152):
+        prm.exact_items = items
+        sizes.append(gs.gs_workspace_bytes(200000, prm, gs.GS_EXACT, gs.GS_OP_RHS))
+    assert sizes[0] < sizes[1] < sizes[2]
+    prm.exact_items = 0
+    assert gs.gs_workspace_bytes(200000, prm, gs.GS_EXACT, gs.GS_OP_RHS) == sizes[1]
+    # the tuner needs a workspace that fits at least one candidate
+    st = _call("gs_autotune_exact", FAKE, FAKE, _off([0, 5000]), 1, ctypes.byref(prm), FAKE,
+               FAKE, FAKE, 4096, None, None)
+    assert st == -2
+
+
 def test_batch_workspace_sizes():
     prm = gs.params(0.05, nt=40, theta=0.5, leaf_cap=16)
     offs = [0, 5000, 5000, 12000, 40000]

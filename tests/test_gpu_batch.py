@@ -207,6 +207,34 @@ def test_autotune_leaf_cap_picks_a_valid_fast_setting():
     assert tb.leaf_cap in (8, 16, 32, 48, 64)
 
 
+def test_autotune_exact_picks_a_candidate_and_keeps_parity(oracle):
+    """The exact-path tuner returns one of its candidates; the tuned setting
+    only moves FP64 chunk boundaries (FP32 tiles are unchanged), so the RHS
+    agrees with the default one to FP32 rounding and with the oracle."""
+    w = W.ellipsoid_20k(n=20000)
+    q, p = _t(w.q0), _t(w.p0)
+    prm = gs.params(w.sigma)
+    tuned, ms = gs.gs_autotune_exact(q, p, prm)
+    _say(f"autotune exact -> exact_items {tuned.exact_items} ({ms:.3f} ms per RHS)")
+    assert tuned.exact_items in (6144, 12288, 24576, 49152) and ms > 0
+    assert (tuned.sigma, tuned.leaf_cap, tuned.nt) == (prm.sigma, prm.leaf_cap, prm.nt)
+    ref = [_np(x) for x in gs.gs_rhs_exact(q, p, prm)]
+    for items in (6144, 49152):
+        other = gs.Params.from_buffer_copy(prm)
+        other.exact_items = items
+        got = [_np(x) for x in gs.gs_rhs_exact(q, p, other)]
+        assert rel_l2(got[0], ref[0]) < 1e-7 and rel_l2(got[1], ref[1]) < 1e-7, items
+    idx = np.sort(np.random.default_rng(3).choice(w.n, 64, replace=False))
+    vo, ao = oracle.rhs_exact_rows(idx, w.q0.astype(np.float64), w.p0.astype(np.float64), w.sigma)
+    got = [_np(x) for x in gs.gs_rhs_exact(q, p, tuned)]
+    assert rel_l2(got[0][idx], vo) < 1e-5 and rel_l2(got[1][idx], ao) < 1e-5
+    subs = W.population(subjects=6)
+    qq, pp, off = W.stack(subs)
+    tb, msb = gs.gs_autotune_exact(_t(qq), _t(pp), gs.params(0.05), offsets=off)
+    _say(f"autotune exact batch -> exact_items {tb.exact_items} ({msb:.3f} ms per batched RHS)")
+    assert tb.exact_items in (6144, 12288, 24576, 49152)
+
+
 @pytest.mark.parametrize("method", [gs.GS_EXACT, gs.GS_BH])
 def test_many_tiny_sets(oracle, method):
     """300 sets of 0..40 points: more than 256 sets take two radix passes on
