@@ -78,16 +78,28 @@ def cpu_baseline(w, theta, leaf_cap, exact_interactions, bh_interactions, target
     t_bh = time.perf_counter() - t0
     r_bh = (c["pairs"] + c["monopoles"]) / t_bh
     t_step = exact_interactions / r_exact + bh_interactions / r_bh
+    # one thread, as the paper's CPU runs: a smaller exact sample
+    cores = int(O.threads())
+    idx1 = idx[: max(1, targets // 50)]
+    O.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        O.rhs_exact_rows(idx1, q64, p64, w.sigma)
+        r_exact1 = len(idx1) * w.n / (time.perf_counter() - t0)
+    finally:
+        O.set_threads(cores)
     return {
         "value": (exact_interactions + bh_interactions) / t_step,
         "unit": "pair-interactions/s",
-        "cores": int(O.threads()),
+        "cores": cores,
         "kind": "oracle",
         "sample": (f"exact FP64 RHS of {targets} random targets x {w.n} sources "
                    f"({targets * w.n:.2e} pairs, {t_exact:.1f} s) and one full Barnes-Hut "
                    f"FP64 RHS at theta {theta}, leaf_cap {leaf_cap} ({t_bh:.1f} s); rates "
                    f"scaled to one step"),
         "exact_pairs_per_s": r_exact,
+        "exact_pairs_per_s_one_thread": r_exact1,
+        "one_thread_sample": f"{len(idx1)} targets x {w.n} sources",
         "bh_interactions_per_s": r_bh,
         "step_seconds_extrapolated": t_step,
     }

@@ -69,6 +69,8 @@ def lib():
         L.or_objective_grad.restype = _dbl
         L.or_version.restype = ctypes.c_char_p
         L.or_threads.restype = ctypes.c_int
+        L.or_set_threads.argtypes = [_i32]
+        L.or_set_threads.restype = None
         _lib = L
     return _lib
 
@@ -227,6 +229,11 @@ def int_coords(q):
 def threads() -> int:
     """OpenMP threads the oracle's parallel loops use."""
     return int(lib().or_threads())
+
+
+def set_threads(n: int) -> None:
+    """Sets the OpenMP threads of the oracle's parallel loops (for timing)."""
+    lib().or_set_threads(int(n))
 
 
 def version() -> str:
