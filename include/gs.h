@@ -21,11 +21,15 @@
  *   - `ws` is a caller-owned DEVICE workspace of at least gs_workspace_bytes()
  *     bytes (256-byte aligned).  The library allocates no device memory and
  *     keeps no pointer after a call returns.  Calls that plan work on the
- *     host (the batched calls and the FP32 exact right-hand side and
- *     shooting) copy their small tables into the workspace from a ring of
- *     four pinned host buffers per thread, allocated on first use and kept
- *     until the process ends; a fifth such call waits for the first one's
- *     copy to finish before reusing its buffer.
+ *     host (the batched calls, the FP32 exact right-hand side and shooting,
+ *     and the gradient calls) copy their small tables into the workspace
+ *     from a ring of four pinned host buffers per thread, allocated on first
+ *     use and kept until the process ends; a fifth such call waits for the
+ *     first one's copy to finish before reusing its buffer.  Such a call
+ *     must not be captured into a caller's own HIP graph (the captured copy
+ *     would read a buffer that later calls reuse); GS_FLAG_GRAPH captures
+ *     shootings safely (the tables are copied by every call, outside the
+ *     graph).
  *   - `stream` is the HIP stream every kernel is enqueued on.  Calls only
  *     enqueue work and return; results are valid once the stream reaches the
  *     point after the call.  The library never synchronises the stream
