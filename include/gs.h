@@ -81,7 +81,8 @@ typedef enum {
 #define GS_FLAG_MFMA_PAIRS 2u /* exact FP32 (v, a) sums accumulated on the
                                  matrix cores (v_mfma_f32_16x16x4_f32)
                                  instead of the vector ALU                    */
-#define GS_FLAG_GRAPH 4u      /* gs_shoot / gs_shoot_batch: capture the call's
+#define GS_FLAG_GRAPH 4u      /* gs_shoot, gs_shoot_batch, gs_shoot_adjoint,
+                                 gs_shoot_adjoint_batch: capture the call's
                                  kernel sequence into a HIP graph on first use
                                  and replay it on later calls with the same
                                  arguments (pointers, sizes, offsets and

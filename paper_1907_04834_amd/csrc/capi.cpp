@@ -468,20 +468,6 @@ gs_status check_batch_call(const int64_t *offsets, int32_t nsub, const gs_params
     return check_params(prm, need_nt, method == GS_BH);
 }
 
-// Objective and gradient of every set (one set: a batch of one).
-gs_status adjoint_batch_call(const float *q0, const float *p0, const float *y,
-                             const int64_t *off, int nsub, const gs_params &prm, int method,
-                             double lambda, int ckpt, double *objective, float *grad, void *ws,
-                             size_t ws_bytes, hipStream_t stream) {
-    GS_TRY(check_ws(ws, ws_bytes, measure_batch(off, nsub, prm, method, GS_OP_ADJOINT, ckpt)));
-    Arena a{static_cast<char *>(ws), kHeader, ws_bytes};
-    Batch b;
-    layout_batch(a, off, nsub, prm, method, GS_OP_ADJOINT, b, ckpt);
-    GS_TRY(upload_tables(b.img, b.tables, stream));
-    return shoot_adjoint(q0, p0, y, prm, lambda, objective, grad, b.adj, static_cast<char *>(ws),
-                         stream);
-}
-
 gs_status exact_batch_rhs(const float *q, const float *p, const int64_t *off, int nsub,
                           const gs_params &prm, float *dq, float *dp, void *ws, size_t ws_bytes,
                           hipStream_t stream) {
@@ -614,6 +600,29 @@ gs_status run_graphed(GraphKey &&key, hipStream_t stream, F &&launches) {
     c.entries.push_back({std::move(key), exec, c.clock});
     GS_HIP(hipGraphLaunch(exec, stream));
     return GS_OK;
+}
+
+// Objective and gradient of every set (one set: a batch of one); with
+// GS_FLAG_GRAPH the kernel sequence is replayed from a graph.
+gs_status adjoint_batch_call(const float *q0, const float *p0, const float *y,
+                             const int64_t *off, int nsub, const gs_params &prm, int method,
+                             double lambda, int ckpt, double *objective, float *grad, void *ws,
+                             size_t ws_bytes, hipStream_t stream) {
+    GS_TRY(check_ws(ws, ws_bytes, measure_batch(off, nsub, prm, method, GS_OP_ADJOINT, ckpt)));
+    Arena a{static_cast<char *>(ws), kHeader, ws_bytes};
+    Batch b;
+    layout_batch(a, off, nsub, prm, method, GS_OP_ADJOINT, b, ckpt);
+    GS_TRY(upload_tables(b.img, b.tables, stream));
+    auto body = [&](hipStream_t s) -> gs_status {
+        return shoot_adjoint(q0, p0, y, prm, lambda, objective, grad, b.adj,
+                             static_cast<char *>(ws), s);
+    };
+    if (!(prm.flags & GS_FLAG_GRAPH)) return body(stream);
+    GraphKey key = graph_key(3, {q0, p0, y, objective, grad, ws},
+                             {method, (int64_t)ws_bytes, nsub, ckpt}, prm);
+    key.ints.insert(key.ints.end(), off, off + nsub + 1);
+    key.dbls.push_back(lambda);
+    return run_graphed(std::move(key), stream, body);
 }
 
 }  // namespace

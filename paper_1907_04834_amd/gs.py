@@ -220,15 +220,29 @@ def gs_shoot_f64(q0, p0, prm: Params, with_energy=True):
     return q1, p1, H
 
 
+def _grad_outputs(out, q0, nobj):
+    """(objective, grad): the caller's buffers `out`, checked, or new ones.
+    Passing the same buffers again lets a GS_FLAG_GRAPH call replay."""
+    if out is None:
+        return torch.zeros(nobj, dtype=torch.float64, device=q0.device), torch.empty_like(q0)
+    obj, grad = out
+    _pts(grad, torch.float32, "grad")
+    if grad.shape != q0.shape:
+        raise ValueError("grad must have the shape of q0")
+    if obj.dtype != torch.float64 or obj.numel() != nobj or not obj.is_contiguous():
+        raise ValueError(f"objective must be contiguous float64 with {nobj} entries")
+    return obj, grad
+
+
 def gs_shoot_adjoint(q0, p0, target, prm: Params, method=GS_EXACT, lam=0.01, ckpt_every=8,
-                     ws=None):
-    """Objective E(p0) (float64 scalar tensor) and dE/dp0 (float32 (n, 3))."""
+                     ws=None, out=None):
+    """Objective E(p0) (float64 scalar tensor) and dE/dp0 (float32 (n, 3)).
+    `out` = (objective (1,) float64, grad) writes into the caller's buffers."""
     _pts(q0, torch.float32, "q0")
     _pts(p0, torch.float32, "p0")
     _pts(target, torch.float32, "target")
     n = q0.shape[0]
-    obj = torch.zeros(1, dtype=torch.float64, device=q0.device)
-    grad = torch.empty_like(p0)
+    obj, grad = _grad_outputs(out, q0, 1)
     if ws is None:
         nbytes = lib().gs_adjoint_workspace_bytes(n, ctypes.byref(prm), method, int(ckpt_every))
         if nbytes == 0:
@@ -304,15 +318,15 @@ def gs_shoot_batch(q0, p0, offsets, prm: Params, method=GS_EXACT, with_energy=Tr
 
 
 def gs_shoot_adjoint_batch(q0, p0, target, offsets, prm: Params, method=GS_EXACT, lam=0.01,
-                           ckpt_every=8, ws=None):
+                           ckpt_every=8, ws=None, out=None):
     """Per-set objectives E_s (float64 (nsub,)) and dE_s/dp0 of every set
-    (float32 (n, 3), rows of set s from its own objective)."""
+    (float32 (n, 3), rows of set s from its own objective).  `out` =
+    (objectives, grad) writes into the caller's buffers."""
     _pts(q0, torch.float32, "q0")
     _pts(p0, torch.float32, "p0")
     _pts(target, torch.float32, "target")
     off, nsub = _offsets(offsets)
-    obj = torch.zeros(nsub, dtype=torch.float64, device=q0.device)
-    grad = torch.empty_like(p0)
+    obj, grad = _grad_outputs(out, q0, nsub)
     if ws is None:
         nbytes = lib().gs_adjoint_batch_workspace_bytes(off, nsub, ctypes.byref(prm), method,
                                                         int(ckpt_every))

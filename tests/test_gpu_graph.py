@@ -1,4 +1,4 @@
-"""GPU checks of graph-replayed shooting (GS_FLAG_GRAPH).
+"""GPU checks of graph-replayed shootings and gradients (GS_FLAG_GRAPH).
 
 A call with GS_FLAG_GRAPH captures its kernel sequence once and replays it on
 later calls with the same arguments; the kernels and their arguments are
@@ -8,6 +8,7 @@ share the workspace (so the per-call table upload is exercised) and with new
 values written into the same input buffers.  One case is also held to the
 FP64 oracle at the single-set bars (rel-L2 1e-5 on q(1), p(1), 1e-6 on H).
 """
+import ctypes
 import time
 
 import numpy as np
@@ -134,3 +135,44 @@ def test_graph_replay_time_small_problem(method):
     eager, graph = per_call(prm), per_call(gprm)
     _say(f"n=2000 nt=40 method={method}: eager {eager:.3f} ms, graph {graph:.3f} ms per call")
     assert graph < 1.25 * eager + 0.05
+
+
+@pytest.mark.parametrize("method", [gs.GS_EXACT, gs.GS_BH])
+def test_graph_gradients_replay_equal_eager(method):
+    """Graph-replayed objective and gradient (single set and batch) equal the
+    eager calls bit for bit, with eager work on the same workspace between
+    replays."""
+    a = W.adjoint_50k(seed=7, n=3000)
+    b = W.adjoint_50k(seed=8, n=3000)
+    prm = gs.params(a.sigma, nt=6, theta=0.5, leaf_cap=8)
+    gprm = _graph_params(prm)
+    q0, p0, y = _t(a.q0), _t(a.p0), _t(a.extra["target"])
+    nb = gs.lib().gs_adjoint_workspace_bytes(3000, ctypes.byref(prm), method, 2)
+    ws = torch.empty(nb, dtype=torch.uint8, device=DEV)
+    out = (torch.zeros(1, dtype=torch.float64, device=DEV), torch.empty_like(q0))
+    _say(f"graph gradient method={method} n=3000 nt=6")
+    ref = gs.gs_shoot_adjoint(q0, p0, y, prm, method, 0.01, 2, ws=ws)
+    for rep in range(3):
+        got = gs.gs_shoot_adjoint(q0, p0, y, gprm, method, 0.01, 2, ws=ws, out=out)
+        torch.cuda.synchronize()
+        assert torch.equal(got[0], ref[0]) and torch.equal(got[1], ref[1]), rep
+        gs.gs_shoot_adjoint(_t(b.q0), _t(b.p0), _t(b.extra["target"]), prm, method, 0.01, 2,
+                            ws=ws)
+        torch.cuda.synchronize()
+    # a batch of two ragged sets
+    q = np.concatenate([a.q0, b.q0[:1700]])
+    p = np.concatenate([a.p0, b.p0[:1700]])
+    yy = np.concatenate([a.extra["target"], b.extra["target"][:1700]])
+    off = [0, 3000, 4700]
+    qd, pd, yd = _t(q), _t(p), _t(yy)
+    offs = (ctypes.c_int64 * 3)(*off)
+    wsb = torch.empty(gs.lib().gs_adjoint_batch_workspace_bytes(offs, 2, ctypes.byref(prm),
+                                                                method, 2),
+                      dtype=torch.uint8, device=DEV)
+    refb = gs.gs_shoot_adjoint_batch(qd, pd, yd, off, prm, method, 0.01, 2, ws=wsb)
+    outb = (torch.zeros(2, dtype=torch.float64, device=DEV), torch.empty_like(qd))
+    for rep in range(3):
+        got = gs.gs_shoot_adjoint_batch(qd, pd, yd, off, gprm, method, 0.01, 2, ws=wsb,
+                                        out=outb)
+        torch.cuda.synchronize()
+        assert torch.equal(got[0], refb[0]) and torch.equal(got[1], refb[1]), rep
