@@ -177,7 +177,7 @@ __global__ __launch_bounds__(256) void k_adj_decide(
     const float4 xa = active ? As[t] : z4, xb = active ? Bs[t] : z4;
     const double xd = xq.x, yd = xq.y, zd = xq.z;
     const float inv_s2 = bp.inv_s2f;
-    LeafEntry *mylist = list + (grp * kSub + sub) * kSegCap;
+    LeafEntry *mylist = list + grp * kListPerGroup + (int64_t)sub * split.segcap;
     double GQ[3] = {0, 0, 0}, GP[3] = {0, 0, 0};
     unsigned c_pairs = 0, c_mono = 0;
     int nlist = 0;
@@ -244,7 +244,7 @@ __global__ __launch_bounds__(256) void k_adj_decide(
             const int nchild = __builtin_amdgcn_readfirstlane(nd.nchild);
             if (nchild == 0) {
                 if (need) c_pairs += (unsigned)ncount;
-                if (nlist < kSegCap) {
+                if (nlist < split.segcap) {
                     if (lane == 0) {
                         LeafEntry e;
                         e.mask = open;
@@ -307,7 +307,7 @@ __global__ __launch_bounds__(256) void k_adj_leaves(
     const int v0 = chunk * cs.per;
     if (chunk >= cs.chunks || v0 >= cs.total) return;  // wave-uniform: no entries here
     const int v1 = v0 + cs.per < cs.total ? v0 + cs.per : cs.total;
-    ListCursor cur = list_seek(list_n, grp, split.nsub, v0);
+    ListCursor cur = list_seek(list_n, grp, split, v0);
     const int64_t npad = groups * 64;
     const GroupDesc gd = group_desc(gtab, grp, n);
     const int64_t t = (int64_t)gd.first + lane;
@@ -317,7 +317,7 @@ __global__ __launch_bounds__(256) void k_adj_leaves(
     const float4 xa = active ? As[t] : z4, xb = active ? Bs[t] : z4;
     double GQ[3] = {0, 0, 0}, GP[3] = {0, 0, 0};
     for (int r = v0; r < v1; ++r) {
-        const LeafEntry e = list_take(list, list_n, grp, split.nsub, cur);
+        const LeafEntry e = list_take(list, list_n, grp, split, cur);
         const int first = __builtin_amdgcn_readfirstlane(e.first);
         const int count = __builtin_amdgcn_readfirstlane(e.count);
         leaf_adjoint_staged(Qs, Ps, As, Bs, first, count, ((e.mask >> lane) & 1ull) != 0, xq, xp,

@@ -33,15 +33,17 @@ typedef unsigned long long u64;
 // read back.
 constexpr int kBlockStack = 192;  // entries of (first child, count, lane mask)
 constexpr int kSub = 4;           // phase-1 waves per group, at most
-constexpr int kSegCap = 2048 / kSub;  // list entries per phase-1 wave (more are summed in phase 1)
+constexpr int kListPerGroup = 4096;  // list entries of a group, shared out among its phase-1 waves
 constexpr int kMaxChunks = 16;    // phase-2 waves per group, at most
 constexpr int kMinChunk = 32;     // entries per phase-2 wave, at least (unless fewer in all)
 constexpr int kParts = kSub + kMaxChunks;
 
-// Waves per group: nsub (<= kSub) in phase 1, at most maxc (<= kMaxChunks) in
-// phase 2.  Partial-sum slots: 0..nsub-1 for phase 1, then nsub + chunk.
+// Waves per group: nsub (<= kSub) in phase 1, each with a list segment of
+// segcap = kListPerGroup / nsub entries (a leaf beyond it is summed in phase
+// 1), and at most maxc (<= kMaxChunks) in phase 2.  Partial-sum slots:
+// 0..nsub-1 for phase 1, then nsub + chunk.
 struct TravSplit {
-    int nsub, maxc;
+    int nsub, maxc, segcap;
 };
 TravSplit traverse_split(int64_t groups);
 
@@ -118,19 +120,19 @@ __device__ inline void list_normalize(const int *__restrict__ list_n, int64_t gr
     }
 }
 // The cursor at entry v (< the group's total) of the concatenated list.
-__device__ inline ListCursor list_seek(const int *__restrict__ list_n, int64_t grp, int nsub,
-                                      int v) {
+__device__ inline ListCursor list_seek(const int *__restrict__ list_n, int64_t grp,
+                                      TravSplit split, int v) {
     ListCursor c{0, v, list_n[grp * kSub]};
-    list_normalize(list_n, grp, nsub, c);
+    list_normalize(list_n, grp, split.nsub, c);
     return c;
 }
 // The entry under the cursor (wave-uniform); the cursor moves to the next.
 __device__ inline LeafEntry list_take(const LeafEntry *__restrict__ list,
-                                      const int *__restrict__ list_n, int64_t grp, int nsub,
-                                      ListCursor &c) {
-    const LeafEntry e = list[(grp * kSub + c.seg) * kSegCap + c.off];
+                                      const int *__restrict__ list_n, int64_t grp,
+                                      TravSplit split, ListCursor &c) {
+    const LeafEntry e = list[grp * kListPerGroup + (int64_t)c.seg * split.segcap + c.off];
     ++c.off;
-    list_normalize(list_n, grp, nsub, c);
+    list_normalize(list_n, grp, split.nsub, c);
     return e;
 }
 

@@ -118,7 +118,7 @@ __global__ __launch_bounds__(256) void k_bh_decide(
     const float4 xq = active ? Qs[t] : make_float4(0.f, 0.f, 0.f, 0.f);
     const float4 xp = active ? Ps[t] : make_float4(0.f, 0.f, 0.f, 0.f);
     const double xd = xq.x, yd = xq.y, zd = xq.z;
-    LeafEntry *mylist = list + (grp * kSub + sub) * kSegCap;
+    LeafEntry *mylist = list + grp * kListPerGroup + (int64_t)sub * split.segcap;
 
     double V[3] = {0, 0, 0}, A[3] = {0, 0, 0};
     float mv[3] = {0.f, 0.f, 0.f}, ma[3] = {0.f, 0.f, 0.f};
@@ -186,7 +186,7 @@ __global__ __launch_bounds__(256) void k_bh_decide(
             const int nchild = __builtin_amdgcn_readfirstlane(nd.nchild);
             if (nchild == 0) {
                 if (need) c_pairs += (unsigned)ncount;
-                if (nlist < kSegCap) {
+                if (nlist < split.segcap) {
                     if (lane == 0) {
                         LeafEntry e;
                         e.mask = open;
@@ -273,7 +273,7 @@ __global__ __launch_bounds__(256) void k_bh_leaves(const float4 *__restrict__ Qs
     const int v0 = chunk * cs.per;
     if (chunk >= cs.chunks || v0 >= cs.total) return;  // wave-uniform: no entries here
     const int v1 = v0 + cs.per < cs.total ? v0 + cs.per : cs.total;
-    ListCursor cur = list_seek(list_n, grp, split.nsub, v0);
+    ListCursor cur = list_seek(list_n, grp, split, v0);
     const int64_t npad = groups * 64;
     const GroupDesc gd = group_desc(gtab, grp, n);
     const int64_t t = (int64_t)gd.first + lane;
@@ -283,7 +283,7 @@ __global__ __launch_bounds__(256) void k_bh_leaves(const float4 *__restrict__ Qs
     double V[3] = {0, 0, 0}, A[3] = {0, 0, 0};
     unsigned steps = 0;
     for (int r = v0; r < v1; ++r) {
-        const LeafEntry e = list_take(list, list_n, grp, split.nsub, cur);
+        const LeafEntry e = list_take(list, list_n, grp, split, cur);
         const int first = __builtin_amdgcn_readfirstlane(e.first);
         const int count = __builtin_amdgcn_readfirstlane(e.count);
         steps += (unsigned)count;
@@ -399,7 +399,7 @@ constexpr size_t kStatusOffset = 0;  // status word at the start of the workspac
 }  // namespace
 
 size_t traverse_list_bytes(int64_t groups) {
-    return (size_t)groups * kSub * kSegCap * sizeof(LeafEntry);
+    return (size_t)groups * kListPerGroup * sizeof(LeafEntry);
 }
 
 size_t traverse_count_ints(int64_t groups) { return (size_t)groups * kSub; }
@@ -421,6 +421,7 @@ TravSplit traverse_split(int64_t groups) {
     TravSplit split;
     split.nsub = (int)std::min<int64_t>(kSub, std::max<int64_t>(1, (w1 + g - 1) / g));
     split.maxc = (int)std::min<int64_t>(kMaxChunks, std::max<int64_t>(1, (w2 + g - 1) / g));
+    split.segcap = kListPerGroup / split.nsub;
     return split;
 }
 }  // namespace trav
