@@ -208,7 +208,10 @@ def main():
         sys.exit(2)
 
     import torch
+    from paper_1907_04834_amd import build as hip_build
     from paper_1907_04834_amd import gs
+
+    hip_build.ensure_built()
     from paper_1907_04834_amd import workloads as W
 
     dev = torch.device("cuda:0")

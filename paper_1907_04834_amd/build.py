@@ -49,6 +49,12 @@ def _compile(src: str) -> str:
     return obj
 
 
+def ensure_built() -> str:
+    """Builds the library only when it is missing (tests, smoke and the
+    benchmark use what is built; the binding itself never builds)."""
+    return LIB if os.path.exists(LIB) else build()
+
+
 def build(jobs: int = 8) -> str:
     """Compile every source and link the shared library; returns its path."""
     os.makedirs(BUILD, exist_ok=True)

@@ -11,6 +11,9 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU")
     config.addinivalue_line("markers", "slow: long-running oracle case")
+    from paper_1907_04834_amd import build
+
+    build.ensure_built()
 
 
 @pytest.fixture(scope="session")
