@@ -738,7 +738,8 @@ __global__ __launch_bounds__(256) void k_node_sums(const float4 *__restrict__ A,
 gs_status scan_u32(const unsigned *in, unsigned *out, int64_t n, unsigned *part, unsigned *total,
                    hipStream_t s) {
     const unsigned nb = (unsigned)((n + kScanTile - 1) / kScanTile);
-    hipLaunchKernelGGL(k_scan_blocksum, dim3(nb), dim3(256), 0, s, in, n, part);
+    // one block needs no block totals (its carry is zero)
+    if (nb > 1) hipLaunchKernelGGL(k_scan_blocksum, dim3(nb), dim3(256), 0, s, in, n, part);
     hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(256), 0, s, in, out, n, part, total);
     GS_LAUNCH_CHECK("scan");
     return GS_OK;
