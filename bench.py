@@ -180,6 +180,26 @@ def adjoint_and_field_rates(gs, W, torch, dev, theta, leaf_cap):
     ms = _timed(torch, lambda: gs.gs_field(x, q, p, prm))
     out["field"] = {"targets": 200000, "sources": src.n, "ms": ms,
                     "pair_evaluations_per_s": 200000 * src.n / (ms / 1e3)}
+    # one right-hand side of the 20k ellipsoid: exact, and Barnes-Hut at each
+    # opening angle of that workload (leaf_cap 1 as in its parity cases, and
+    # the tuned leaf_cap)
+    e20 = W.ellipsoid_20k()
+    q20, p20 = torch.from_numpy(e20.q0).to(dev), torch.from_numpy(e20.p0).to(dev)
+    rec = {"n": e20.n, "sigma": e20.sigma}
+    prm = gs.params(e20.sigma)
+    ms = _timed(torch, lambda: gs.gs_rhs_exact(q20, p20, prm))
+    rec["exact"] = {"ms_per_rhs": ms, "rhs_per_s": 1e3 / ms,
+                    "pair_interactions_per_s": e20.n ** 2 / (ms / 1e3)}
+    for th in (0.3, 0.5, 0.8):
+        for lc in (1, 48):
+            prm = gs.params(e20.sigma, theta=th, leaf_cap=lc)
+            ws = torch.empty(gs.gs_workspace_bytes(e20.n, prm, gs.GS_BH, gs.GS_OP_RHS),
+                             dtype=torch.uint8, device=dev)
+            ms = _timed(torch, lambda: gs.gs_rhs_bh(q20, p20, prm, ws=ws))
+            c = gs.gs_bh_counters(ws)
+            rec[f"bh_theta{th}_lc{lc}"] = {"ms_per_rhs": ms, "rhs_per_s": 1e3 / ms,
+                                           "interactions": c["pairs"] + c["monopoles"]}
+    out["rhs_20k"] = rec
     return out
 
 

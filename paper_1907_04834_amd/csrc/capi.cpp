@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <vector>
 
@@ -286,8 +287,47 @@ struct TableImage {
     }
 };
 
+// Work-item plans of the exact path, kept for repeated calls with the same
+// set sizes: planning takes host time (about 0.1 ms for 20 000 points,
+// 0.5 ms for 200 000) that a short call would otherwise wait for, and every
+// call plans twice (workspace check and layout).  At most 8 plans are kept,
+// least recently used dropped; the cache lives until the process ends.
+struct PlanCache {
+    std::mutex mu;
+    struct Entry {
+        std::vector<int64_t> key;
+        std::shared_ptr<const ExactBatchPlan> plan;
+        uint64_t used;
+    };
+    std::vector<Entry> entries;
+    uint64_t clock = 0;
+};
+
+std::shared_ptr<const ExactBatchPlan> exact_plan(const int64_t *off, int nsub, int64_t items) {
+    static PlanCache *c = new PlanCache;
+    std::vector<int64_t> key(off, off + nsub + 1);
+    key.push_back(items);
+    std::lock_guard<std::mutex> g(c->mu);
+    ++c->clock;
+    for (auto &e : c->entries)
+        if (e.key == key) {
+            e.used = c->clock;
+            return e.plan;
+        }
+    auto plan = std::make_shared<const ExactBatchPlan>(plan_exact_batch(off, nsub, items));
+    if (c->entries.size() >= 8) {
+        size_t old = 0;
+        for (size_t i = 1; i < c->entries.size(); ++i)
+            if (c->entries[i].used < c->entries[old].used) old = i;
+        c->entries.erase(c->entries.begin() + (long)old);
+    }
+    c->entries.push_back({std::move(key), plan, c->clock});
+    return plan;
+}
+
 struct Batch {
-    ExactBatchPlan xp;
+    std::shared_ptr<const ExactBatchPlan> plan;  // keeps *xp alive
+    const ExactBatchPlan *xp = nullptr;
     ExactBatchBufs ex{};
     ShootBhBufs bh{};
     AdjointBufs adj{};
@@ -298,7 +338,7 @@ struct Batch {
 // Lays out (or measures, when the arena has no base) the buffers of a
 // batched call and prepares its tables.  `ckpt` is the checkpoint interval
 // of op GS_OP_ADJOINT.  The Batch must stay where it is while in use
-// (b.adj points at b.xp).
+// (b.adj points into it).
 void layout_batch(Arena &a, const int64_t *off, int nsub, const gs_params &prm, int method,
                   int op, Batch &b, int ckpt = 8) {
     const int nt = op == GS_OP_SHOOT ? prm.nt : 0;
@@ -308,17 +348,18 @@ void layout_batch(Arena &a, const int64_t *off, int nsub, const gs_params &prm, 
     if (adj)
         for (int s = 0; s < nsub; ++s) setn.push_back((double)(off[s + 1] - off[s]));
     if (method == GS_EXACT) {
-        b.xp = plan_exact_batch(off, nsub, prm.exact_items);
-        carve_exact_batch(a, b.xp, nt, b.ex);
-        const int nb = (int)b.xp.blocks.size();
+        b.plan = exact_plan(off, nsub, prm.exact_items);
+        b.xp = b.plan.get();
+        carve_exact_batch(a, *b.xp, nt, b.ex);
+        const int nb = (int)b.xp->blocks.size();
         if (adj) {
-            b.adj.AL = a.take<float4>(b.xp.npad);
-            b.adj.BE = a.take<float4>(b.xp.npad);
+            b.adj.AL = a.take<float4>(b.xp->npad);
+            b.adj.BE = a.take<float4>(b.xp->npad);
             carve_adjoint_common(a, off[nsub], nsub, prm.nt, ck, nb, b.adj);
         }
-        const size_t o_items = b.img.add(b.xp.items.data(), b.xp.items.size());
-        const size_t o_blk = b.img.add(b.xp.blocks.data(), b.xp.blocks.size());
-        const size_t o_bseg = b.img.add(b.xp.bseg.data(), b.xp.bseg.size());
+        const size_t o_items = b.img.add(b.xp->items.data(), b.xp->items.size());
+        const size_t o_blk = b.img.add(b.xp->blocks.data(), b.xp->blocks.size());
+        const size_t o_bseg = b.img.add(b.xp->bseg.data(), b.xp->bseg.size());
         const size_t o_setn = b.img.add(setn.data(), setn.size());
         b.tables = a.take<char>(b.img.bytes.size());
         if (b.tables) {
@@ -328,7 +369,7 @@ void layout_batch(Arena &a, const int64_t *off, int nsub, const gs_params &prm, 
         }
         if (adj) {  // reduction units: the row blocks, which never straddle two sets
             b.adj.bh = false;
-            b.adj.xp = &b.xp;
+            b.adj.xp = b.xp;
             b.adj.ex = b.ex;
             b.adj.Sq = b.ex.Sq;
             b.adj.Sp = b.ex.Sp;
@@ -475,9 +516,9 @@ gs_status exact_batch_rhs(const float *q, const float *p, const int64_t *off, in
     Batch b;
     layout_batch(a, off, nsub, prm, GS_EXACT, GS_OP_RHS, b);
     GS_TRY(upload_tables(b.img, b.tables, stream));
-    GS_TRY(launch_pack_state_rows(b.xp, b.ex, q, p, prm.sigma, stream));
-    GS_TRY(launch_exact_items(b.xp, b.ex, prm.sigma, true, stream));
-    return launch_combine_rows(b.xp, b.ex, prm.sigma, 0, dq, dp, 0.0, nullptr, stream);
+    GS_TRY(launch_pack_state_rows(*b.xp, b.ex, q, p, prm.sigma, stream));
+    GS_TRY(launch_exact_items(*b.xp, b.ex, prm.sigma, true, stream));
+    return launch_combine_rows(*b.xp, b.ex, prm.sigma, 0, dq, dp, 0.0, nullptr, stream);
 }
 
 gs_status exact_batch_shoot(const float *q0, const float *p0, const int64_t *off, int nsub,
@@ -488,17 +529,17 @@ gs_status exact_batch_shoot(const float *q0, const float *p0, const int64_t *off
     layout_batch(a, off, nsub, prm, GS_EXACT, GS_OP_SHOOT, b);
     if (upload) GS_TRY(upload_tables(b.img, b.tables, stream));
     const double dt = 1.0 / prm.nt;
-    const size_t nb = b.xp.blocks.size();
-    GS_TRY(launch_pack_state_rows(b.xp, b.ex, q0, p0, prm.sigma, stream));
+    const size_t nb = b.xp->blocks.size();
+    GS_TRY(launch_pack_state_rows(*b.xp, b.ex, q0, p0, prm.sigma, stream));
     for (int t = 0; t < prm.nt; ++t) {
-        GS_TRY(launch_exact_items(b.xp, b.ex, prm.sigma, true, stream));
-        GS_TRY(launch_combine_rows(b.xp, b.ex, prm.sigma, 1, nullptr, nullptr, dt,
+        GS_TRY(launch_exact_items(*b.xp, b.ex, prm.sigma, true, stream));
+        GS_TRY(launch_combine_rows(*b.xp, b.ex, prm.sigma, 1, nullptr, nullptr, dt,
                                    H ? b.ex.Hpart + (size_t)t * nb : nullptr, stream));
     }
     if (H) {
         // energy of the final state: one velocity-only pass
-        GS_TRY(launch_exact_items(b.xp, b.ex, prm.sigma, false, stream));
-        GS_TRY(launch_combine_rows(b.xp, b.ex, prm.sigma, 1, nullptr, nullptr, 0.0,
+        GS_TRY(launch_exact_items(*b.xp, b.ex, prm.sigma, false, stream));
+        GS_TRY(launch_combine_rows(*b.xp, b.ex, prm.sigma, 1, nullptr, nullptr, 0.0,
                                    b.ex.Hpart + (size_t)prm.nt * nb, stream));
         GS_TRY(launch_reduce_h_seg(b.ex.Hpart, (int64_t)nb, b.ex.bseg, nsub, prm.nt + 1, H,
                                    stream));
