@@ -363,3 +363,43 @@ def test_population_adjoint_full_size():
             dg = rel_l2(G[lo:hi], _np(g1))
             _say(f"  subject {s} n={hi - lo}: objective {de:.2e} grad {dg:.2e}")
             assert de < 1e-6 and dg < 1e-6
+
+
+@pytest.mark.parametrize("subjects", [14, 20])
+def test_bh_split_for_mid_sized_batches(oracle, subjects):
+    """The decide waves per group depend on the group count (4 below about
+    3 000 groups, 1 above 12 000): batches of 14 and 20 subjects (about 4 900
+    and 7 000 groups) take 3 and 2 waves per group.  Every subject must still
+    match the oracle's Barnes-Hut RHS and its counters, and its gradient the
+    single-subject call."""
+    subs = W.population(subjects=subjects)
+    q, p, off = W.stack(subs)
+    groups = sum((w.n + 63) // 64 for w in subs)
+    sigma, theta, leaf_cap = 0.05, 0.5, 16
+    prm = gs.params(sigma, nt=3, theta=theta, leaf_cap=leaf_cap)
+    _say(f"bh split: {subjects} subjects, {int(off[-1])} points, {groups} groups")
+    dq, dp, ws = gs.gs_rhs_batch(_t(q), _t(p), off, prm, gs.GS_BH, return_ws=True)
+    cnt = gs.gs_bh_counters(ws)
+    v, a = _np(dq), _np(dp)
+    pairs = mono = 0
+    worst = 0.0
+    for s_, w in enumerate(subs):
+        lo, hi = off[s_], off[s_ + 1]
+        vo, ao, c = oracle.rhs_bh(w.q0.astype(np.float64), w.p0.astype(np.float64), sigma, theta,
+                                  leaf_cap=leaf_cap)
+        pairs += c["pairs"]
+        mono += c["monopoles"]
+        worst = max(worst, rel_l2(v[lo:hi], vo), rel_l2(a[lo:hi], ao))
+    _say(f"  worst rel-L2 {worst:.2e}; counters gpu {cnt['pairs']} / {cnt['monopoles']}, "
+         f"oracle {pairs} / {mono}")
+    assert worst < 1e-5 and cnt["pairs"] == pairs and cnt["monopoles"] == mono
+    ys = W.population_targets(subs)
+    E, G = gs.gs_shoot_adjoint_batch(_t(q), _t(p), _t(np.concatenate(ys)), off, prm, gs.GS_BH,
+                                     0.01, 2)
+    E, G = _np(E), _np(G)
+    for s_ in (0, subjects - 1):
+        lo, hi = off[s_], off[s_ + 1]
+        e1, g1 = gs.gs_shoot_adjoint(_t(subs[s_].q0), _t(subs[s_].p0), _t(ys[s_]), prm, gs.GS_BH,
+                                     0.01, 2)
+        assert abs(E[s_] - float(e1)) <= 1e-6 * abs(float(e1))
+        assert rel_l2(G[lo:hi], _np(g1)) < 1e-6
