@@ -276,15 +276,56 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(
     }
 }
 
-__global__ __launch_bounds__(256) void k_gather(const float *__restrict__ q,
-                                                const float *__restrict__ p,
-                                                const unsigned *__restrict__ perm, int64_t n,
-                                                float4 *__restrict__ Qs, float4 *__restrict__ Ps) {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n) return;
-    const int64_t i = perm[t];
-    Qs[t] = make_float4(q[3 * i], q[3 * i + 1], q[3 * i + 2], 0.f);
-    Ps[t] = make_float4(p[3 * i], p[3 * i + 1], p[3 * i + 2], 0.f);
+// Statistics of contiguous ranges of sorted points.  A two-level summary
+// (chunks of 64 points, super-chunks of 64 chunks) lets every node reduce
+// its own range [start, start + n) independently: no inter-node ordering,
+// atomics or fences, and a fixed summation order (bitwise deterministic).
+struct RangeStat {
+    double s[6];  // sums of q (3) and p (3)
+    float lo[3], hi[3];
+};
+
+__device__ inline void rs_init(RangeStat &r) {
+    for (int c = 0; c < 6; ++c) r.s[c] = 0.0;
+    for (int c = 0; c < 3; ++c) {
+        r.lo[c] = INFINITY;
+        r.hi[c] = -INFINITY;
+    }
+}
+__device__ inline void rs_add(RangeStat &r, const RangeStat &o) {
+    for (int c = 0; c < 6; ++c) r.s[c] += o.s[c];
+    for (int c = 0; c < 3; ++c) {
+        r.lo[c] = fminf(r.lo[c], o.lo[c]);
+        r.hi[c] = fmaxf(r.hi[c], o.hi[c]);
+    }
+}
+__device__ inline void rs_point(RangeStat &r, const float4 a, const float4 b) {
+    r.s[0] += a.x;
+    r.s[1] += a.y;
+    r.s[2] += a.z;
+    r.s[3] += b.x;
+    r.s[4] += b.y;
+    r.s[5] += b.z;
+    r.lo[0] = fminf(r.lo[0], a.x);
+    r.lo[1] = fminf(r.lo[1], a.y);
+    r.lo[2] = fminf(r.lo[2], a.z);
+    r.hi[0] = fmaxf(r.hi[0], a.x);
+    r.hi[1] = fmaxf(r.hi[1], a.y);
+    r.hi[2] = fmaxf(r.hi[2], a.z);
+}
+
+// One wave per chunk: lane l takes item l of the chunk; fixed shuffle tree.
+__device__ inline void rs_wave_reduce(RangeStat &r) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) r.s[c] += __shfl_down(r.s[c], off, 64);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            r.lo[c] = fminf(r.lo[c], __shfl_down(r.lo[c], off, 64));
+            r.hi[c] = fmaxf(r.hi[c], __shfl_down(r.hi[c], off, 64));
+        }
+    }
 }
 
 // ---------------------------------------------------------------- generic scan
@@ -379,13 +420,37 @@ __device__ inline int64_t lower_bound(const u64 *__restrict__ K, int64_t lo, int
     return lo;
 }
 
+// Per sorted position i: the gathered point (Qs, Ps), the summary of each
+// 64-point chunk (one wave per chunk), and the boundary after i (its split
+// level and, for the first split of an over-full cell, the cell's range).
 __global__ __launch_bounds__(256) void k_boundaries(const u64 *__restrict__ K, int64_t n,
                                                     const long long *__restrict__ seg, int nsub,
-                                                    int leaf_cap, unsigned char *__restrict__ lvl,
+                                                    int leaf_cap, const float *__restrict__ q,
+                                                    const float *__restrict__ p,
+                                                    const unsigned *__restrict__ perm,
+                                                    float4 *__restrict__ Qs,
+                                                    float4 *__restrict__ Ps,
+                                                    RangeStat *__restrict__ c0, int64_t nc0,
+                                                    unsigned char *__restrict__ lvl,
                                                     unsigned *__restrict__ flag,
                                                     unsigned *__restrict__ bs,
                                                     unsigned *__restrict__ be) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    {
+        RangeStat r;
+        rs_init(r);
+        if (i < n) {
+            const int64_t src = perm[i];
+            const float4 a = make_float4(q[3 * src], q[3 * src + 1], q[3 * src + 2], 0.f);
+            const float4 b = make_float4(p[3 * src], p[3 * src + 1], p[3 * src + 2], 0.f);
+            Qs[i] = a;
+            Ps[i] = b;
+            rs_point(r, a, b);
+        }
+        rs_wave_reduce(r);  // the wave's 64 positions are chunk i / kChunk
+        const int64_t c = i / kChunk;
+        if ((threadIdx.x & 63) == 0 && c < nc0) c0[c] = r;
+    }
     if (i >= n) return;
     // the range [a0, b0) of the set holding point i
     int64_t a0 = 0, b0 = n;
@@ -494,17 +559,18 @@ __device__ inline void zero_stats(BhNode &nd) {
 
 // Root records: one thread per set, after the scans.  Node s is the root of
 // set s; children of internal rank r start at node nsub + cstart[r].
-__global__ __launch_bounds__(64) void k_roots(const u64 *__restrict__ K, int64_t n,
-                                              const long long *__restrict__ seg, int nsub,
-                                              int leaf_cap, const unsigned *__restrict__ rank,
-                                              const unsigned *__restrict__ nchild,
-                                              const unsigned *__restrict__ cstart,
-                                              TreeTotals *__restrict__ totals,
-                                              TreeMeta *__restrict__ meta,
-                                              BhNode *__restrict__ nodes,
-                                              int *__restrict__ node_start) {
-    const int si = blockIdx.x * blockDim.x + threadIdx.x;
-    if (si >= nsub) return;
+
+// Node records of the children of every internal node, one wave per node:
+// lane k builds child k (its representative found by its own search).
+// The root of set si (node si): a leaf, or the internal node of its first
+// split.
+__device__ inline void make_root(int si, const u64 *__restrict__ K, int64_t n,
+                                 const long long *__restrict__ seg, int nsub, int leaf_cap,
+                                 const unsigned *__restrict__ rank,
+                                 const unsigned *__restrict__ nchild,
+                                 const unsigned *__restrict__ cstart,
+                                 TreeTotals *__restrict__ totals, TreeMeta *__restrict__ meta,
+                                 BhNode *__restrict__ nodes, int *__restrict__ node_start) {
     const int64_t a = seg ? seg[si] : 0, b = seg ? seg[si + 1] : n;
     BhNode nd;
     zero_stats(nd);
@@ -529,16 +595,22 @@ __global__ __launch_bounds__(64) void k_roots(const u64 *__restrict__ K, int64_t
     }
 }
 
-// Node records of the children of every internal node, one wave per node:
-// lane k builds child k (its representative found by its own search).
-__global__ __launch_bounds__(256) void k_nodes(const u64 *__restrict__ K, int leaf_cap, int nsub,
-                                               const TreeTotals *__restrict__ totals,
+// Node records: the roots (one thread each), then the children of every
+// internal rank (one wave per rank, a lane per child).
+__global__ __launch_bounds__(256) void k_nodes(const u64 *__restrict__ K, int64_t n,
+                                               const long long *__restrict__ seg, int leaf_cap,
+                                               int nsub, TreeTotals *__restrict__ totals,
+                                               TreeMeta *__restrict__ meta,
                                                const unsigned *__restrict__ rank,
                                                const unsigned *__restrict__ nchild,
                                                const unsigned *__restrict__ cstart,
                                                const unsigned *__restrict__ crun,
                                                BhNode *__restrict__ nodes,
                                                int *__restrict__ node_start) {
+    for (int si = blockIdx.x * blockDim.x + threadIdx.x; si < nsub;
+         si += gridDim.x * blockDim.x)
+        make_root(si, K, n, seg, nsub, leaf_cap, rank, nchild, cstart, totals, meta, nodes,
+                  node_start);
     const int lane = threadIdx.x & 63;
     const int64_t nint = totals->n_internal, waves = (int64_t)gridDim.x * 4;
     for (int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); r < nint; r += waves) {
@@ -584,58 +656,6 @@ __device__ inline void finish_node(BhNode &nd, const double *sum, const float *l
         if (side > s) s = side;
     }
     nd.s2 = s * s;
-}
-
-// Statistics of contiguous ranges of sorted points.  A two-level summary
-// (chunks of 64 points, super-chunks of 64 chunks) lets every node reduce
-// its own range [start, start + n) independently: no inter-node ordering,
-// atomics or fences, and a fixed summation order (bitwise deterministic).
-struct RangeStat {
-    double s[6];  // sums of q (3) and p (3)
-    float lo[3], hi[3];
-};
-
-__device__ inline void rs_init(RangeStat &r) {
-    for (int c = 0; c < 6; ++c) r.s[c] = 0.0;
-    for (int c = 0; c < 3; ++c) {
-        r.lo[c] = INFINITY;
-        r.hi[c] = -INFINITY;
-    }
-}
-__device__ inline void rs_add(RangeStat &r, const RangeStat &o) {
-    for (int c = 0; c < 6; ++c) r.s[c] += o.s[c];
-    for (int c = 0; c < 3; ++c) {
-        r.lo[c] = fminf(r.lo[c], o.lo[c]);
-        r.hi[c] = fmaxf(r.hi[c], o.hi[c]);
-    }
-}
-__device__ inline void rs_point(RangeStat &r, const float4 a, const float4 b) {
-    r.s[0] += a.x;
-    r.s[1] += a.y;
-    r.s[2] += a.z;
-    r.s[3] += b.x;
-    r.s[4] += b.y;
-    r.s[5] += b.z;
-    r.lo[0] = fminf(r.lo[0], a.x);
-    r.lo[1] = fminf(r.lo[1], a.y);
-    r.lo[2] = fminf(r.lo[2], a.z);
-    r.hi[0] = fmaxf(r.hi[0], a.x);
-    r.hi[1] = fmaxf(r.hi[1], a.y);
-    r.hi[2] = fmaxf(r.hi[2], a.z);
-}
-
-// One wave per chunk: lane l takes item l of the chunk; fixed shuffle tree.
-__device__ inline void rs_wave_reduce(RangeStat &r) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-#pragma unroll
-        for (int c = 0; c < 6; ++c) r.s[c] += __shfl_down(r.s[c], off, 64);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            r.lo[c] = fminf(r.lo[c], __shfl_down(r.lo[c], off, 64));
-            r.hi[c] = fmaxf(r.hi[c], __shfl_down(r.hi[c], off, 64));
-        }
-    }
 }
 
 __global__ __launch_bounds__(256) void k_chunks0(const float4 *__restrict__ Qs,
@@ -828,9 +848,11 @@ gs_status build_tree(const float *q, const float *p, int64_t n, int leaf_cap, Tr
     }
     GS_LAUNCH_CHECK("radix sort");
     const u64 *K = t.K;  // where the last pass left the sorted data
-    hipLaunchKernelGGL(k_gather, dim3(nblk(n)), dim3(256), 0, s, q, p, t.perm, n, t.Qs, t.Ps);
+    const int64_t nc0 = (n + kChunk - 1) / kChunk, nc1 = (nc0 + kChunk - 1) / kChunk;
+    RangeStat *c0 = reinterpret_cast<RangeStat *>(t.chunk0);
+    RangeStat *c1 = reinterpret_cast<RangeStat *>(t.chunk1);
     hipLaunchKernelGGL(k_boundaries, dim3(nblk(n)), dim3(256), 0, s, K, n, t.seg, nsub, leaf_cap,
-                       t.lvl, t.flag, t.bnd_s, t.bnd_e);
+                       q, p, t.perm, t.Qs, t.Ps, c0, nc0, t.lvl, t.flag, t.bnd_s, t.bnd_e);
     GS_LAUNCH_CHECK("boundaries");
     unsigned *n_internal = reinterpret_cast<unsigned *>(&t.totals->n_internal);
     GS_TRY(scan_u32(t.flag, t.rank, n, t.scan_part, n_internal, s));
@@ -842,15 +864,9 @@ gs_status build_tree(const float *q, const float *p, int64_t n, int leaf_cap, Tr
     // entries whose tail beyond n_internal may hold stale values, which only
     // affects cstart of ranks that do not exist.
     GS_TRY(scan_u32(t.nchild, t.cstart, n > 1 ? n - 1 : 1, t.scan_part, nullptr, s));
-    hipLaunchKernelGGL(k_roots, dim3(nblk(nsub, 64)), dim3(64), 0, s, K, n, t.seg, nsub,
-                       leaf_cap, t.rank, t.nchild, t.cstart, t.totals, t.meta, t.nodes,
+    hipLaunchKernelGGL(k_nodes, dim3(node_blocks(n)), dim3(256), 0, s, K, n, t.seg, leaf_cap,
+                       nsub, t.totals, t.meta, t.rank, t.nchild, t.cstart, t.crun, t.nodes,
                        t.node_start);
-    hipLaunchKernelGGL(k_nodes, dim3(node_blocks(n)), dim3(256), 0, s, K, leaf_cap, nsub,
-                       t.totals, t.rank, t.nchild, t.cstart, t.crun, t.nodes, t.node_start);
-    const int64_t nc0 = (n + kChunk - 1) / kChunk, nc1 = (nc0 + kChunk - 1) / kChunk;
-    RangeStat *c0 = reinterpret_cast<RangeStat *>(t.chunk0);
-    RangeStat *c1 = reinterpret_cast<RangeStat *>(t.chunk1);
-    hipLaunchKernelGGL(k_chunks0, dim3(nblk(nc0, 4)), dim3(256), 0, s, t.Qs, t.Ps, n, c0, nc0);
     hipLaunchKernelGGL(k_chunks1, dim3(nblk(nc1, 4)), dim3(256), 0, s, c0, nc0, c1, nc1);
     hipLaunchKernelGGL(k_node_stats, dim3(node_blocks(2 * n + nsub)), dim3(256), 0, s, t.Qs, t.Ps, c0,
                        c1, t.totals, t.node_start, t.nodes, t.nsum);
