@@ -162,7 +162,7 @@ __global__ __launch_bounds__(256) void k_adj_decide(
     TravSplit split, BhParams bp, LeafEntry *__restrict__ list, int *__restrict__ list_n,
     double *__restrict__ part, u64 *__restrict__ counters, int *__restrict__ status) {
     __shared__ AdjDecideLds lds_all[4];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wv = wave_in_block();
     AdjDecideLds &L = lds_all[wv];
     const int64_t wave = (int64_t)blockIdx.x * 4 + wv;
     const int64_t grp = wave / split.nsub;
@@ -182,18 +182,19 @@ __global__ __launch_bounds__(256) void k_adj_decide(
     unsigned c_pairs = 0, c_mono = 0;
     int nlist = 0;
 
-    // this wave's share of the root's children (the root when it is a leaf)
+    // the start block: the root's children (decided by every wave, their
+    // grandchildren dealt out by node index), or the root when it is a leaf
     const int rchild = __builtin_amdgcn_readfirstlane(nodes[gd.root].nchild);
     const int rfirst = __builtin_amdgcn_readfirstlane(nodes[gd.root].first);
-    const int lo = sub * rchild / split.nsub, hi = (sub + 1) * rchild / split.nsub;
-    const int start = rchild == 0 ? (sub == 0 ? gd.root : -1) : (hi > lo ? rfirst + lo : -1);
-    const int start_n = rchild == 0 ? 1 : hi - lo;
+    const int start = rchild == 0 ? (sub == 0 ? gd.root : -1) : rfirst;
+    const int start_n = rchild == 0 ? 1 : rchild;
     int sp = 0;
     const u64 live = __ballot(active);
     if (live != 0ull && start >= 0) {
         L.d.first[0] = start;
         L.d.count[0] = start_n;
         L.d.mask[0] = live;
+        L.d.own[0] = rchild == 0 ? kOwnAll : kOwnTop;
         sp = 1;
         load_block(nodes, adj, start, start_n, lane, L);
     }
@@ -201,13 +202,20 @@ __global__ __launch_bounds__(256) void k_adj_decide(
     while (sp > 0) {
         --sp;
         const int bc = __builtin_amdgcn_readfirstlane(L.d.count[sp]);
+        const int bfirst = __builtin_amdgcn_readfirstlane(L.d.first[sp]);
+        const int own = __builtin_amdgcn_readfirstlane(L.d.own[sp]);
         const u64 m = L.d.mask[sp];
         const bool mine = (m >> lane) & 1ull;
+        const bool rec = own != kOwnTop || sub == 0;  // this wave records the block's results
+        const int child_own = own == kOwnTop ? kOwnDealt : kOwnAll;
         for (int k = 0; k < bc; ++k) {
+            if (own == kOwnDealt && (bfirst + k) % split.nsub != sub) continue;  // another wave's
             const BhNode nd = L.d.node[k];
             bool need = false;
             if (mine) {
-                if (decide(nd, xd, yd, zd, bp)) {
+                if (!decide(nd, xd, yd, zd, bp)) {
+                    need = true;
+                } else if (rec) {
                     // n_k virtual points: (C, P / n, A / n, B / n)
                     const float Ax = (float)L.adj[k][0], Ay = (float)L.adj[k][1],
                                 Az = (float)L.adj[k][2];
@@ -233,8 +241,6 @@ __global__ __launch_bounds__(256) void k_adj_decide(
                     GP[1] += (double)(g * Ay + w3 * nd.py);
                     GP[2] += (double)(g * Az + w3 * nd.pz);
                     ++c_mono;
-                } else {
-                    need = true;
                 }
             }
             const u64 open = __ballot(need);
@@ -243,6 +249,7 @@ __global__ __launch_bounds__(256) void k_adj_decide(
             const int ncount = __builtin_amdgcn_readfirstlane(nd.n);
             const int nchild = __builtin_amdgcn_readfirstlane(nd.nchild);
             if (nchild == 0) {
+                if (!rec) continue;
                 if (need) c_pairs += (unsigned)ncount;
                 if (nlist < split.segcap) {
                     if (lane == 0) {
@@ -267,6 +274,7 @@ __global__ __launch_bounds__(256) void k_adj_decide(
                 L.d.first[sp] = nfirst;
                 L.d.count[sp] = nchild;
                 L.d.mask[sp] = open;
+                L.d.own[sp] = child_own;
                 ++sp;
             }
         }
@@ -300,7 +308,7 @@ __global__ __launch_bounds__(256) void k_adj_leaves(
     const int *__restrict__ list_n,
     double *__restrict__ part) {
     __shared__ float4 stage[4][4][64];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wv = wave_in_block();
     const int64_t grp = blockIdx.x;
     const int chunk = blockIdx.y * 4 + wv;
     const ChunkSplit cs = chunk_split(list_n, grp, split);
@@ -334,7 +342,7 @@ __global__ __launch_bounds__(256) void k_adj_combine(
     const unsigned *__restrict__ perm, int64_t n, double inv_s2, double dt,
     double *__restrict__ al, double *__restrict__ be) {
     const int lane = threadIdx.x & 63;
-    const int64_t grp = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t grp = (int64_t)blockIdx.x * 4 + wave_in_block();
     if (grp >= groups) return;
     const GroupDesc gd = group_desc(gtab, grp, n);
     if (lane >= gd.count) return;

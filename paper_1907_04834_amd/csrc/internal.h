@@ -12,6 +12,11 @@
 
 namespace gs {
 
+// Index of the calling wave in its block as a wave-uniform value: the compiler
+// does not prove threadIdx.x >> 6 uniform, and addresses derived from it would
+// otherwise be computed per lane and loaded through the vector memory path.
+__device__ inline int wave_in_block() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+
 // ---------------------------------------------------------------- errors
 void set_error(const char *fmt, ...);
 gs_status hip_fail(hipError_t e, const char *what);

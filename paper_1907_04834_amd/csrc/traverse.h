@@ -12,14 +12,18 @@ typedef unsigned long long u64;
 
 // ---------------------------------------------------------------- layout
 // Work split.  A group is 64 consecutive targets of the Morton order (one
-// wave's lanes).  Phase 1 walks the tree for a group with kSub waves that
-// share out the children of the tree's root (the root contains every target
-// of its tree, so it is never approximated and every target opens it): each
-// wave takes the decisions in its children's subtrees, adds the monopoles,
-// and records each leaf that some lane must sum exactly as an entry (leaf,
-// lane mask) of its own list segment.  Measured at 200k points (theta 0.5,
-// leaf_cap 64), with 1, 2, 4 and 8 waves per group: 1.18, 1.10, 1.07 and
-// 1.41 ms per traversal (at leaf_cap 16: 1.83, 1.85, 1.92, 2.25 ms).
+// wave's lanes).  Phase 1 walks the tree for a group with up to kSub waves
+// (the root contains every target of its tree, so it is never approximated
+// and every target opens it).  Every wave decides the root's children; the
+// children of those (the nodes two levels below the root) are dealt out by
+// node index, node i to wave i % nsub, and each wave takes every decision
+// below its nodes, adds the monopoles, and records each leaf that some lane
+// must sum exactly as an entry (leaf, lane mask) of its own list segment.
+// Dealing out by index mixes the group's dense near field with far nodes in
+// every wave; an earlier split, each wave taking a contiguous share of the
+// root's children, left most of a group's work to the wave holding the
+// group's own region (at 200k points, theta 0.5, leaf_cap 64: 1143 node
+// decisions in the busiest wave against 195 on average).
 // Phase 2 splits the group's entries, taken segment by segment, into at
 // most kMaxChunks chunks of at least kMinChunk entries and adds their exact
 // pairs with one wave per chunk, so the near-field work of a dense group is
@@ -53,10 +57,17 @@ struct LeafEntry {
     int count;
 };
 
+// Ownership of a block of sibling nodes among the phase-1 waves of a group.
+constexpr int kOwnAll = 0;    // this wave's own subtree: it takes every node
+constexpr int kOwnTop = 1;    // the root's children: every wave decides them,
+                              // wave 0 records their monopoles, leaves, visits
+constexpr int kOwnDealt = 2;  // their children: node i belongs to wave i % nsub
+
 struct DecideLds {
     u64 mask[kBlockStack];
     int first[kBlockStack];
     int count[kBlockStack];
+    int own[kBlockStack];
     BhNode node[8];  // the sibling block being decided
 };
 

@@ -31,6 +31,45 @@ namespace {
 using namespace trav;
 
 
+// A wave-uniform value passed through readfirstlane (a no-op on it).  Used on
+// the first loads of a software-pipelined source loop: the compiler otherwise
+// folds "first group, or the group loaded ahead" back into one load at the
+// top of the loop, and the pipeline is lost.
+__device__ __forceinline__ float uniform_f(float x) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+__device__ __forceinline__ float4 uniform_f4(float4 v) {
+    return make_float4(uniform_f(v.x), uniform_f(v.y), uniform_f(v.z), uniform_f(v.w));
+}
+
+// Pair sums of B = 4 sources (FP32 partial sums of one leaf).
+template <bool WITH_A, int B>
+__device__ __forceinline__ void group_pairs(const float4 *qj, const float4 *pj, float4 xq,
+                                            float4 xp, float negc, float *tv, float *ta) {
+    float dx[B], dy[B], dz[B], g[B];
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+        dx[u] = xq.x - qj[u].x;
+        dy[u] = xq.y - qj[u].y;
+        dz[u] = xq.z - qj[u].z;
+    }
+#pragma unroll
+    for (int u = 0; u < B; ++u)
+        g[u] = __builtin_amdgcn_exp2f((dx[u] * dx[u] + dy[u] * dy[u] + dz[u] * dz[u]) * negc);
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+        tv[0] += g[u] * pj[u].x;
+        tv[1] += g[u] * pj[u].y;
+        tv[2] += g[u] * pj[u].z;
+        if (WITH_A) {
+            const float w = g[u] * (xp.x * pj[u].x + xp.y * pj[u].y + xp.z * pj[u].z);
+            ta[0] += w * dx[u];
+            ta[1] += w * dy[u];
+            ta[2] += w * dz[u];
+        }
+    }
+}
+
 // Exact pairs of one leaf, sorted points [first, first + count), for the
 // lanes with `mine` set.  first and count are wave-uniform, so the points are
 // read with wave-uniform addresses (scalar loads straight into SGPRs, as in
@@ -42,52 +81,38 @@ __device__ __forceinline__ void leaf_direct(const float4 *__restrict__ Qs,
                                             bool mine, float4 xq, float4 xp, float negc,
                                             double *V, double *A) {
     if (!mine) return;
+    constexpr int B = 4;  // sources per pipeline stage
     float tv[3] = {0.f, 0.f, 0.f}, ta[3] = {0.f, 0.f, 0.f};
     const int end = first + count;
     int j = first;
-    for (; j + 4 <= end; j += 4) {
-        float4 qj[4], pj[4];
+    if (count >= B) {
+        // groups of B: the next group is loaded while the current one is
+        // evaluated (the last group reloads the leaf's last B points)
+        float4 qn[B], pn[B];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            qj[u] = Qs[j + u];
-            pj[u] = Ps[j + u];
+        for (int u = 0; u < B; ++u) {
+            qn[u] = uniform_f4(Qs[j + u]);
+            pn[u] = uniform_f4(Ps[j + u]);
         }
-        float dx[4], dy[4], dz[4], g[4];
+        for (; j + B <= end; j += B) {
+            float4 qj[B], pj[B];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            dx[u] = xq.x - qj[u].x;
-            dy[u] = xq.y - qj[u].y;
-            dz[u] = xq.z - qj[u].z;
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-            g[u] = __builtin_amdgcn_exp2f((dx[u] * dx[u] + dy[u] * dy[u] + dz[u] * dz[u]) * negc);
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            tv[0] += g[u] * pj[u].x;
-            tv[1] += g[u] * pj[u].y;
-            tv[2] += g[u] * pj[u].z;
-            if (WITH_A) {
-                const float w = g[u] * (xp.x * pj[u].x + xp.y * pj[u].y + xp.z * pj[u].z);
-                ta[0] += w * dx[u];
-                ta[1] += w * dy[u];
-                ta[2] += w * dz[u];
+            for (int u = 0; u < B; ++u) {
+                qj[u] = qn[u];
+                pj[u] = pn[u];
             }
+            const int jn = j + B < end - B ? j + B : end - B;
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                qn[u] = Qs[jn + u];
+                pn[u] = Ps[jn + u];
+            }
+            group_pairs<WITH_A, B>(qj, pj, xq, xp, negc, tv, ta);
         }
     }
     for (; j < end; ++j) {
         const float4 qj = Qs[j], pj = Ps[j];
-        const float dx = xq.x - qj.x, dy = xq.y - qj.y, dz = xq.z - qj.z;
-        const float g = __builtin_amdgcn_exp2f((dx * dx + dy * dy + dz * dz) * negc);
-        tv[0] += g * pj.x;
-        tv[1] += g * pj.y;
-        tv[2] += g * pj.z;
-        if (WITH_A) {
-            const float w = g * (xp.x * pj.x + xp.y * pj.y + xp.z * pj.z);
-            ta[0] += w * dx;
-            ta[1] += w * dy;
-            ta[2] += w * dz;
-        }
+        group_pairs<WITH_A, 1>(&qj, &pj, xq, xp, negc, tv, ta);
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -96,6 +121,130 @@ __device__ __forceinline__ void leaf_direct(const float4 *__restrict__ Qs,
     }
 }
 
+// A group's list entries v0 <= v < v1 (of its concatenated segments) read 64
+// at a time: lane l loads entry vb + l, and entry v is then taken from lane
+// v - vb with readlane (v is wave-uniform), one vector load per 64 leaves.
+struct EntryBatch {
+    int64_t base;     // the group's first list slot
+    int segn[kSub];   // segment lengths
+    int nsub, segcap, vb, v1;
+    int first, count, mlo, mhi;  // lane l: entry vb + l
+};
+__device__ inline void batch_load(EntryBatch &b, const LeafEntry *__restrict__ list, int vb,
+                                  int lane) {
+    b.vb = vb;
+    int v = vb + lane, s = 0;
+    if (v < b.v1) {
+#pragma unroll
+        for (int k = 0; k < kSub - 1; ++k) {  // constant indices: segn stays in registers
+            if (s == k && k < b.nsub - 1 && v >= b.segn[k]) {
+                v -= b.segn[k];
+                s = k + 1;
+            }
+        }
+        const LeafEntry e = list[b.base + (int64_t)s * b.segcap + v];
+        b.first = e.first;
+        b.count = e.count;
+        b.mlo = (int)(unsigned)e.mask;
+        b.mhi = (int)(unsigned)(e.mask >> 32);
+    } else {
+        b.first = b.count = b.mlo = b.mhi = 0;
+    }
+}
+__device__ inline void batch_get(const EntryBatch &b, int v, int &first, int &count, u64 &mask) {
+    const int i = v - b.vb;
+    first = __builtin_amdgcn_readlane(b.first, i);
+    count = __builtin_amdgcn_readlane(b.count, i);
+    mask = ((u64)(unsigned)__builtin_amdgcn_readlane(b.mhi, i) << 32) |
+           (u64)(unsigned)__builtin_amdgcn_readlane(b.mlo, i);
+}
+
+// The leaves of list entries [v0, v1) as one stream of source groups: the
+// next group of B sources (the next leaf's first group at the end of a leaf)
+// is loaded while the current group is evaluated.  Every lane evaluates
+// every leaf and adds the leaf's FP32 sums to its FP64 sums only when the
+// leaf's mask holds it; per leaf the sums are those of leaf_direct (groups of
+// B in order, then single sources).
+template <bool WITH_A>
+__device__ __forceinline__ void leaf_stream(const float4 *__restrict__ Qs,
+                                            const float4 *__restrict__ Ps,
+                                            const LeafEntry *__restrict__ list,
+                                            const int *__restrict__ list_n, int64_t grp,
+                                            TravSplit split, int v0, int v1, int lane, float4 xq,
+                                            float4 xp, float negc, double *V, double *A,
+                                            unsigned &steps) {
+    constexpr int B = 4;
+    if (v0 >= v1) return;
+    EntryBatch eb;
+    eb.base = grp * kListPerGroup;
+    eb.nsub = split.nsub;
+    eb.segcap = split.segcap;
+    eb.v1 = v1;
+#pragma unroll
+    for (int k = 0; k < kSub; ++k) eb.segn[k] = k < split.nsub ? list_n[grp * kSub + k] : 0;
+    batch_load(eb, list, v0, lane);
+    int first, count;
+    u64 mask;
+    batch_get(eb, v0, first, count, mask);
+    float4 qn[B], pn[B];
+    if (count >= B) {
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            qn[u] = uniform_f4(Qs[first + u]);
+            pn[u] = uniform_f4(Ps[first + u]);
+        }
+    }
+    for (int v = v0; v < v1; ++v) {
+        int nfirst = 0, ncount = 0;
+        u64 nmask = 0ull;
+        if (v + 1 < v1) {
+            if (v + 1 - eb.vb == 64) batch_load(eb, list, v + 1, lane);
+            batch_get(eb, v + 1, nfirst, ncount, nmask);
+        }
+        steps += (unsigned)count;
+        const int end = first + count;
+        float tv[3] = {0.f, 0.f, 0.f}, ta[3] = {0.f, 0.f, 0.f};
+        int j = first;
+        for (; j + B <= end; j += B) {
+            float4 qj[B], pj[B];
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                qj[u] = qn[u];
+                pj[u] = pn[u];
+            }
+            // ahead: this leaf's next group, else the next leaf's first group,
+            // else (nothing to load) this leaf's last B points again
+            const int jn = j + 2 * B <= end ? j + B : (ncount >= B ? nfirst : end - B);
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                qn[u] = Qs[jn + u];
+                pn[u] = Ps[jn + u];
+            }
+            group_pairs<WITH_A, B>(qj, pj, xq, xp, negc, tv, ta);
+        }
+        for (; j < end; ++j) {
+            const float4 qj = Qs[j], pj = Ps[j];
+            group_pairs<WITH_A, 1>(&qj, &pj, xq, xp, negc, tv, ta);
+        }
+        if (count < B && ncount >= B) {  // the loop above did not load ahead
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                qn[u] = uniform_f4(Qs[nfirst + u]);
+                pn[u] = uniform_f4(Ps[nfirst + u]);
+            }
+        }
+        if ((mask >> lane) & 1ull) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                V[c] += (double)tv[c];
+                if (WITH_A) A[c] += (double)ta[c];
+            }
+        }
+        first = nfirst;
+        count = ncount;
+        mask = nmask;
+    }
+}
 
 // Phase 1: decisions, monopoles and the group's list of leaves.
 template <bool WITH_A>
@@ -105,7 +254,7 @@ __global__ __launch_bounds__(256) void k_bh_decide(
     LeafEntry *__restrict__ list, int *__restrict__ list_n, double *__restrict__ part,
     u64 *__restrict__ counters, const TreeTotals *__restrict__ totals, int *__restrict__ status) {
     __shared__ DecideLds lds_all[4];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wv = wave_in_block();
     DecideLds &L = lds_all[wv];
     const int64_t wave = (int64_t)blockIdx.x * 4 + wv;
     const int64_t grp = wave / split.nsub;
@@ -125,24 +274,23 @@ __global__ __launch_bounds__(256) void k_bh_decide(
     unsigned c_pairs = 0, c_mono = 0, c_visit = 0, w_steps = 0, w_nodes = 0;
     int nlist = 0;
 
-    // this wave's start: its share [lo, hi) of the root's children as one
-    // block, or the root itself when it is a leaf (wave 0 only); a wave with
-    // no share is idle
+    // the start block: the root's children (decided by every wave), or the
+    // root itself when it is a leaf (wave 0 only)
     const int rchild = __builtin_amdgcn_readfirstlane(nodes[gd.root].nchild);
     const int rfirst = __builtin_amdgcn_readfirstlane(nodes[gd.root].first);
-    const int lo = sub * rchild / split.nsub, hi = (sub + 1) * rchild / split.nsub;
-    const int start = rchild == 0 ? (sub == 0 ? gd.root : -1) : (hi > lo ? rfirst + lo : -1);
-    const int start_n = rchild == 0 ? 1 : hi - lo;
+    const int start = rchild == 0 ? (sub == 0 ? gd.root : -1) : rfirst;
+    const int start_n = rchild == 0 ? 1 : rchild;
     if (rchild > 0 && sub == 0) {  // the root's visit, counted once
         if (active) ++c_visit;
         ++w_nodes;
     }
     int sp = 0;
     const u64 live = __ballot(active);
-    if (live != 0ull && start >= 0) {  // the start block
+    if (live != 0ull && start >= 0) {
         L.first[0] = start;
         L.count[0] = start_n;
         L.mask[0] = live;
+        L.own[0] = rchild == 0 ? kOwnAll : kOwnTop;
         sp = 1;
         float4 *dstn = reinterpret_cast<float4 *>(L.node);
         if (lane < 5 * start_n) dstn[lane] = reinterpret_cast<const float4 *>(nodes + start)[lane];
@@ -151,15 +299,22 @@ __global__ __launch_bounds__(256) void k_bh_decide(
     while (sp > 0) {
         --sp;
         const int bc = __builtin_amdgcn_readfirstlane(L.count[sp]);
+        const int bfirst = __builtin_amdgcn_readfirstlane(L.first[sp]);
+        const int own = __builtin_amdgcn_readfirstlane(L.own[sp]);
         const u64 m = L.mask[sp];
         const bool mine = (m >> lane) & 1ull;
-        w_nodes += (unsigned)bc;
+        const bool rec = own != kOwnTop || sub == 0;  // this wave records the block's results
+        const int child_own = own == kOwnTop ? kOwnDealt : kOwnAll;
         for (int k = 0; k < bc; ++k) {
+            if (own == kOwnDealt && (bfirst + k) % split.nsub != sub) continue;  // another wave's
+            ++w_nodes;
             const BhNode nd = L.node[k];
             bool need = false;
             if (mine) {
-                ++c_visit;
-                if (decide(nd, xd, yd, zd, bp)) {
+                if (rec) ++c_visit;
+                if (!decide(nd, xd, yd, zd, bp)) {
+                    need = true;
+                } else if (rec) {
                     // n_k virtual points at C_k, momentum P_k / n_k each
                     const float dx = xq.x - (float)nd.cx, dy = xq.y - (float)nd.cy,
                                 dz = xq.z - (float)nd.cz;
@@ -175,8 +330,6 @@ __global__ __launch_bounds__(256) void k_bh_decide(
                         ma[2] += w * dz;
                     }
                     ++c_mono;
-                } else {
-                    need = true;
                 }
             }
             const u64 open = __ballot(need);
@@ -185,6 +338,7 @@ __global__ __launch_bounds__(256) void k_bh_decide(
             const int ncount = __builtin_amdgcn_readfirstlane(nd.n);
             const int nchild = __builtin_amdgcn_readfirstlane(nd.nchild);
             if (nchild == 0) {
+                if (!rec) continue;
                 if (need) c_pairs += (unsigned)ncount;
                 if (nlist < split.segcap) {
                     if (lane == 0) {
@@ -210,6 +364,7 @@ __global__ __launch_bounds__(256) void k_bh_decide(
                 L.first[sp] = nfirst;
                 L.count[sp] = nchild;
                 L.mask[sp] = open;
+                L.own[sp] = child_own;
                 ++sp;
             }
         }
@@ -266,14 +421,13 @@ __global__ __launch_bounds__(256) void k_bh_leaves(const float4 *__restrict__ Qs
                                                    const int *__restrict__ list_n,
                                                    double *__restrict__ part,
                                                    u64 *__restrict__ counters) {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wv = wave_in_block();
     const int64_t grp = blockIdx.x;
     const int chunk = blockIdx.y * 4 + wv;
     const ChunkSplit cs = chunk_split(list_n, grp, split);
     const int v0 = chunk * cs.per;
     if (chunk >= cs.chunks || v0 >= cs.total) return;  // wave-uniform: no entries here
     const int v1 = v0 + cs.per < cs.total ? v0 + cs.per : cs.total;
-    ListCursor cur = list_seek(list_n, grp, split, v0);
     const int64_t npad = groups * 64;
     const GroupDesc gd = group_desc(gtab, grp, n);
     const int64_t t = (int64_t)gd.first + lane;
@@ -282,14 +436,8 @@ __global__ __launch_bounds__(256) void k_bh_leaves(const float4 *__restrict__ Qs
     const float4 xp = active ? Ps[t] : make_float4(0.f, 0.f, 0.f, 0.f);
     double V[3] = {0, 0, 0}, A[3] = {0, 0, 0};
     unsigned steps = 0;
-    for (int r = v0; r < v1; ++r) {
-        const LeafEntry e = list_take(list, list_n, grp, split, cur);
-        const int first = __builtin_amdgcn_readfirstlane(e.first);
-        const int count = __builtin_amdgcn_readfirstlane(e.count);
-        steps += (unsigned)count;
-        leaf_direct<WITH_A>(Qs, Ps, first, count, ((e.mask >> lane) & 1ull) != 0, xq, xp, negc, V,
-                            A);
-    }
+    leaf_stream<WITH_A>(Qs, Ps, list, list_n, grp, split, v0, v1, lane, xq, xp, negc, V, A,
+                        steps);
     write_part(part, split.nsub + chunk, npad, grp * 64 + lane, V, A);
     if (lane == 0 && counters) {
         u64 *c = counter_slot(counters, blockIdx.x, blockIdx.y);
@@ -309,7 +457,7 @@ __global__ __launch_bounds__(256) void k_bh_combine(
     double *__restrict__ Sq, double *__restrict__ Sp, float *__restrict__ q32,
     float *__restrict__ p32, double dt, double *__restrict__ Hpart, double *__restrict__ v64) {
     const int lane = threadIdx.x & 63;
-    const int64_t grp = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t grp = (int64_t)blockIdx.x * 4 + wave_in_block();
     if (grp >= groups) return;  // wave-uniform; no block barrier below
     const int64_t npad = groups * 64;
     const int64_t slot = grp * 64 + lane;
