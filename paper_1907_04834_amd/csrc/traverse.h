@@ -36,7 +36,7 @@ typedef unsigned long long u64;
 // launch is full anyway and splitting only adds partial sums to write and
 // read back.
 constexpr int kBlockStack = 192;  // entries of (first child, count, lane mask)
-constexpr int kSub = 4;           // phase-1 waves per group, at most
+constexpr int kSub = 8;           // phase-1 waves per group, at most
 constexpr int kListPerGroup = 4096;  // list entries of a group, shared out among its phase-1 waves
 constexpr int kMaxChunks = 16;    // phase-2 waves per group, at most
 constexpr int kMinChunk = 32;     // entries per phase-2 wave, at least (unless fewer in all)

@@ -367,9 +367,9 @@ def test_population_adjoint_full_size():
 
 @pytest.mark.parametrize("subjects", [14, 20])
 def test_bh_split_for_mid_sized_batches(oracle, subjects):
-    """The decide waves per group depend on the group count (4 below about
-    3 000 groups, 1 above 12 000): batches of 14 and 20 subjects (about 4 900
-    and 7 000 groups) take 3 and 2 waves per group.  Every subject must still
+    """The decide waves per group depend on the group count (8 below about
+    1 500 groups, 4 at 3 000, 1 above 12 000): batches of 14 and 20 subjects
+    (about 4 900 and 7 000 groups) take 3 and 2 waves per group.  Every subject must still
     match the oracle's Barnes-Hut RHS and its counters, and its gradient the
     single-subject call."""
     subs = W.population(subjects=subjects)
