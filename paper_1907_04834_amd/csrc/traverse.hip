@@ -11,11 +11,12 @@
 //   * otherwise a leaf contributes its exact pairs;
 //   * otherwise its children are pushed with the mask of the lanes that
 //     opened it, so a lane that approximated a node never sees its subtree.
-// Node records are read with wave-uniform addresses (scalar loads); the
-// decisions are taken in FP64 from the FP32 target position, the node's
-// exact FP32 box and FP64 centre, as in the definition; the contributions
-// are FP32 with per-leaf sums accumulated in FP64.  Leaf points are streamed
-// with wave-uniform (scalar) loads, lanes outside a leaf's mask switched off.
+// The node records of a block of siblings are staged in LDS with one vector
+// load and read back as broadcasts; the decisions are taken in FP64 from the
+// FP32 target position, the node's exact FP32 box and FP64 centre, as in the
+// definition; the contributions are FP32 with per-leaf sums accumulated in
+// FP64.  Leaf points are streamed with wave-uniform (scalar) loads; a leaf's
+// sums are added only by the lanes in its mask.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

@@ -8,14 +8,16 @@
 //   8 x (hist, scan, scatter)      stable LSD radix sort of (key, index)
 //   1-2 x (hist, scan, scatter)    (forest only) stable passes on the set
 //                                  index, so each set is sorted in its range
-//   gather                         sorted FP32 copies of q, p
-//   boundaries                     split level of every pair of neighbours and
-//                                  the internal-node flag of its cell
+//   boundaries                     sorted FP32 copies of q, p, summaries of
+//                                  64-point chunks, the split level of every
+//                                  pair of neighbours and the internal-node
+//                                  flag of its cell
 //   scan(flag)                     internal-node ranks
 //   children                       child count of every internal node
 //   scan(nchild)                   contiguous child blocks
-//   root, nodes                    node records (ranges, child links)
-//   stats                          bottom-up FP64 sums, tight boxes, centres
+//   nodes                          node records (roots, ranges, child links)
+//   chunks1, stats                 summaries of 4096 points; FP64 sums, tight
+//                                  boxes, centres of every node
 //
 // Tree semantics.  For sorted keys K, the boundary between points i and i+1
 // has split level L = floor(lcp(K_i, K_i+1) / 3) (21 when the keys are equal).
