@@ -77,6 +77,7 @@ struct TreeBufs {
     const GroupDesc *gtab;     // [groups] (nullable: group g = points [64g, 64g + 64))
     int bbox_blocks;           // per set
     int sort_blocks;
+    int sort_per;              // keys per thread of a sort block (tile = 256 x sort_per)
     int sort_passes;
     TreeMeta *meta;            // [nsub]
     TreeTotals *totals;
