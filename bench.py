@@ -223,8 +223,8 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: the shooting of one point set runs on a "
-              "single MI355X in this build (see DESIGN.md for how it would shard); "
-              f"--gpus {args.gpus} is not supported", file=sys.stderr)
+              "single MI355X; there is no multi-GPU path, "
+              f"so --gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
 
     import torch
