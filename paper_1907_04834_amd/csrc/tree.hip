@@ -12,7 +12,8 @@
 //                                  64-point chunks, the split level of every
 //                                  pair of neighbours and the internal-node
 //                                  flag of its cell
-//   scan(flag)                     internal-node ranks
+//   scan(flag)                     internal-node ranks and the boundary of
+//                                  every rank
 //   children                       child count of every internal node
 //   scan(nchild)                   contiguous child blocks
 //   nodes                          node records (roots, ranges, child links)
@@ -362,10 +363,14 @@ __global__ __launch_bounds__(256) void k_scan_blocksum(const unsigned *__restric
     if (t == 0) part[blockIdx.x] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
 }
 
+// With `scatter` (nullable), every i < nscatter with in[i] != 0 also writes i
+// to scatter[out[i]] (for 0/1 flags: the position of the flag of each rank).
 __global__ __launch_bounds__(256) void k_scan_apply(const unsigned *__restrict__ in,
                                                     unsigned *__restrict__ out, int64_t n,
                                                     const unsigned *__restrict__ part,
-                                                    unsigned *__restrict__ total) {
+                                                    unsigned *__restrict__ total,
+                                                    unsigned *__restrict__ scatter,
+                                                    int64_t nscatter) {
     __shared__ unsigned wsum[4];
     __shared__ unsigned carry_s;
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
@@ -403,6 +408,7 @@ __global__ __launch_bounds__(256) void k_scan_apply(const unsigned *__restrict__
 #pragma unroll
     for (int k = 0; k < kScanPer; ++k) {
         if (i0 + k < n) out[i0 + k] = base;
+        if (scatter && v[k] != 0u && i0 + k < nscatter) scatter[base] = (unsigned)(i0 + k);
         base += v[k];
     }
     if (total && blockIdx.x == gridDim.x - 1 && t == 255)
@@ -512,14 +518,6 @@ __device__ inline int64_t child_rep(const u64 *__restrict__ K, int64_t a, int64_
     const int sh = level_shift(L + 1);
     const u64 pre = K[a] >> sh;
     return lower_bound(K, a, b, (pre + 1) << sh) - 1;
-}
-
-// Boundary of each internal rank.
-__global__ __launch_bounds__(256) void k_rank_bnd(int64_t n, const unsigned *__restrict__ flag,
-                                                  const unsigned *__restrict__ rank,
-                                                  unsigned *__restrict__ rank_bnd) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n - 1 && flag[i]) rank_bnd[rank[i]] = (unsigned)i;
 }
 
 // Child runs of every internal node, one wave per node: lane d (1..7)
@@ -766,11 +764,12 @@ __global__ __launch_bounds__(256) void k_node_sums(const float4 *__restrict__ A,
 }
 
 gs_status scan_u32(const unsigned *in, unsigned *out, int64_t n, unsigned *part, unsigned *total,
-                   hipStream_t s) {
+                   hipStream_t s, unsigned *scatter = nullptr, int64_t nscatter = 0) {
     const unsigned nb = (unsigned)((n + kScanTile - 1) / kScanTile);
     // one block needs no block totals (its carry is zero)
     if (nb > 1) hipLaunchKernelGGL(k_scan_blocksum, dim3(nb), dim3(256), 0, s, in, n, part);
-    hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(256), 0, s, in, out, n, part, total);
+    hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(256), 0, s, in, out, n, part, total, scatter,
+                       nscatter);
     GS_LAUNCH_CHECK("scan");
     return GS_OK;
 }
@@ -875,8 +874,8 @@ gs_status build_tree(const float *q, const float *p, int64_t n, int leaf_cap, Tr
                        q, p, t.perm, t.Qs, t.Ps, c0, nc0, t.lvl, t.flag, t.bnd_s, t.bnd_e);
     GS_LAUNCH_CHECK("boundaries");
     unsigned *n_internal = reinterpret_cast<unsigned *>(&t.totals->n_internal);
-    GS_TRY(scan_u32(t.flag, t.rank, n, t.scan_part, n_internal, s));
-    hipLaunchKernelGGL(k_rank_bnd, dim3(nblk(n)), dim3(256), 0, s, n, t.flag, t.rank, t.rank_bnd);
+    // ranks of the internal boundaries, and the boundary of every rank
+    GS_TRY(scan_u32(t.flag, t.rank, n, t.scan_part, n_internal, s, t.rank_bnd, n - 1));
     hipLaunchKernelGGL(k_children, dim3(node_blocks(n)), dim3(256), 0, s, K, t.lvl, t.totals,
                        t.bnd_s, t.bnd_e, t.rank_bnd, t.nchild, t.crun);
     GS_LAUNCH_CHECK("children");
