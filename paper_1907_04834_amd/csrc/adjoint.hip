@@ -112,7 +112,7 @@ __global__ __launch_bounds__(256) void k_adj_items(const float4 *__restrict__ Q,
     const float ax = aa.x, ay = aa.y, az = aa.z;
     const float bx = ba.x, by = ba.y, bz = ba.z;
     double sq[3] = {0, 0, 0}, spp[3] = {0, 0, 0};
-    for (int64_t jt = it.y; jt < it.z; jt += kTile) {
+    for (int jt = it.y; jt < it.z; jt += kTile) {  // 32-bit: scalar-unit compares
         float tq[3] = {0.f, 0.f, 0.f}, tb[3] = {0.f, 0.f, 0.f}, tp[3] = {0.f, 0.f, 0.f};
 #pragma unroll 1
         for (int u = 0; u < kTile; ++u) {

@@ -232,14 +232,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
         pz = b.z;
     }
     double sv[3] = {0, 0, 0}, sa[3] = {0, 0, 0};
-    const int64_t j0 = it.y, j1 = it.z;
+    // 32-bit source indices: the loop and prefetch-clamp compares then run on
+    // the scalar unit (there is no 64-bit scalar less-than)
+    const int j0 = it.y, j1 = it.z;
     float4 qn[B], pn[B];
 #pragma unroll
     for (int b = 0; b < B; ++b) {
         qn[b] = Q[j0 + b];
         pn[b] = P[j0 + b];
     }
-    for (int64_t jt = j0; jt < j1; jt += kTile) {
+    for (int jt = j0; jt < j1; jt += kTile) {
         float tv[3] = {0.f, 0.f, 0.f}, ta[3] = {0.f, 0.f, 0.f};
 #pragma unroll 1
         for (int u = 0; u < kTile; u += B) {
@@ -250,7 +252,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
                 pj[b] = pn[b];
             }
             // next group (the last group reloads itself: j1 - j0 >= kTile >= B)
-            int64_t jn = jt + u + B;
+            int jn = jt + u + B;
             jn = jn < j1 - B ? jn : j1 - B;
 #pragma unroll
             for (int b = 0; b < B; ++b) {
