@@ -35,7 +35,7 @@ typedef unsigned long long u64;
 // groups (TravSplit, chosen on the host): when there are many groups the
 // launch is full anyway and splitting only adds partial sums to write and
 // read back.
-constexpr int kBlockStack = 192;  // entries of (first child, count, lane mask)
+constexpr int kBlockStack = 192;  // entries of (first child, count, lane mask, ownership)
 constexpr int kSub = 8;           // phase-1 waves per group, at most
 constexpr int kListPerGroup = 4096;  // list entries of a group, shared out among its phase-1 waves
 constexpr int kMaxChunks = 16;    // phase-2 waves per group, at most
