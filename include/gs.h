@@ -20,24 +20,36 @@
  *     ...), float32 unless the name ends in _f64.  The caller owns them.
  *   - `ws` is a caller-owned DEVICE workspace of at least gs_workspace_bytes()
  *     bytes (256-byte aligned).  The library allocates no device memory and
- *     keeps no pointer after a call returns.  Calls that plan work on the
- *     host (the batched calls, the FP32 exact right-hand side and shooting,
- *     and the gradient calls) copy their small tables into the workspace
- *     from a ring of four pinned host buffers per thread, allocated on first
- *     use and kept until the process ends; a fifth such call waits for the
- *     first one's copy to finish before reusing its buffer.  Such a call
+ *     keeps no pointer to it after a call returns.  Calls on one point set
+ *     take everything they need from their sizes and copy nothing from the
+ *     host.  Calls on several sets (the batched calls with nsub > 1) and the
+ *     velocity field copy small host-planned tables into the workspace with
+ *     one asynchronous copy from pinned staging buffers of the library (per
+ *     thread, allocated on first use, kept until the process ends): a call
+ *     takes a buffer whose previous copy has completed, the pool grows to at
+ *     most 32 buffers, and only a call issued while 32 earlier copies of its
+ *     thread are still queued waits on the host for the oldest.  Such a call
  *     must not be captured into a caller's own HIP graph (the captured copy
  *     would read a buffer that later calls reuse); GS_FLAG_GRAPH captures
- *     shootings safely (the tables are copied by every call, outside the
- *     graph).
+ *     shootings and gradients safely (their tables are copied by every call,
+ *     outside the graph).
+ *   - Process-lifetime state of the library, none of it device memory: the
+ *     staging buffers above, up to 8 cached work-item plans of batched exact
+ *     calls (keyed by the set sizes), and up to 16 graphs of GS_FLAG_GRAPH
+ *     calls (keyed by every pointer, size and parameter of the call).
  *   - `stream` is the HIP stream every kernel is enqueued on.  Calls only
  *     enqueue work and return; results are valid once the stream reaches the
  *     point after the call.  The library never synchronises the stream
  *     except in gs_get_status / gs_bh_counters / gs_kernel_timing_read.
  *   - Argument errors are reported before any device work is enqueued:
  *     n < 0, non-finite or non-positive sigma, nt < 1, theta < 0 or NaN,
- *     cutoff_sigmas <= 0 or NaN, leaf_cap outside [1, 64], a NULL array when
- *     n > 0, or a workspace that is too small.  n == 0 is a no-op (GS_OK).
+ *     cutoff_sigmas <= 0 or NaN, leaf_cap outside [1, 64], unknown flags, a
+ *     NULL array when n > 0, or a workspace that is too small.  n == 0 is a
+ *     no-op (GS_OK).
+ *   - Accuracy does not depend on where a point set lies: the FP32 kernels
+ *     work on positions relative to the FP64 centre of each set's box (the
+ *     method depends only on differences q_i - q_j), and the Barnes-Hut
+ *     decisions are taken in FP64 on the positions as given.
  *   - Outputs must not alias inputs, except q1/p1 which may equal q0/p0.
  *   - gs_last_error() returns a thread-local message for the last failure.
  *   - Calls are reentrant when they use distinct workspaces.
@@ -60,7 +72,8 @@ typedef enum {
     GS_ERR_WORKSPACE = -2,   /* workspace pointer NULL or too small         */
     GS_ERR_HIP = -3,         /* a HIP call or kernel launch failed          */
     GS_ERR_NONFINITE = -4,   /* non-finite coordinates met on the tree path */
-    GS_ERR_UNSUPPORTED = -5  /* combination of options not implemented      */
+    GS_ERR_UNSUPPORTED = -5, /* combination of options not implemented      */
+    GS_ERR_OVERFLOW = -6     /* a Barnes-Hut traversal stack overflowed      */
 } gs_status;
 
 typedef enum {
@@ -73,14 +86,12 @@ typedef enum {
     GS_OP_RHS = 0,      /* gs_rhs_exact / gs_rhs_bh / gs_rhs_exact_f64        */
     GS_OP_SHOOT = 1,    /* gs_shoot / gs_shoot_f64                            */
     GS_OP_ADJOINT = 2,  /* gs_shoot_adjoint                                   */
-    GS_OP_FIELD = 3     /* gs_field (pass n = max(targets, sources))          */
+    GS_OP_FIELD = 3     /* gs_field with n targets and n sources; for other
+                           sizes use gs_field_workspace_bytes                 */
 } gs_op;
 
 /* flags */
 #define GS_FLAG_F64 1u        /* size the workspace for the _f64 entry points */
-#define GS_FLAG_MFMA_PAIRS 2u /* exact FP32 (v, a) sums accumulated on the
-                                 matrix cores (v_mfma_f32_16x16x4_f32)
-                                 instead of the vector ALU                    */
 #define GS_FLAG_GRAPH 4u      /* gs_shoot, gs_shoot_batch, gs_shoot_adjoint,
                                  gs_shoot_adjoint_batch: capture the call's
                                  kernel sequence into a HIP graph on first use
@@ -104,9 +115,10 @@ typedef struct {
                               1 = the paper's single-point leaves            */
     int32_t nt;            /* forward-Euler steps over t in [0, 1], >= 1     */
     uint32_t flags;        /* GS_FLAG_*                                       */
-    int32_t exact_items;   /* exact FP32 path: work items (blocks of 256
-                              targets x one source chunk) that a launch aims
-                              at; 0 = the library default (24576), else
+    int32_t exact_items;   /* exact FP32 path: work items (one block: 64
+                              targets x one source chunk, split among its
+                              waves) that a launch aims at; 0 = the library
+                              default (24576), else
                               256..4194304.  Changes speed and workspace
                               size, not results beyond FP64 summation order;
                               gs_autotune_exact picks it.                    */
@@ -132,7 +144,9 @@ size_t gs_workspace_bytes(int64_t n, const gs_params *prm, int32_t method, int32
 gs_status gs_rhs_exact(const float *q, const float *p, int64_t n, const gs_params *prm,
                        float *dq, float *dp, void *ws, size_t ws_bytes, hipStream_t stream);
 
-/* The same in FP64 (q, p, dq, dp are double[n][3]). */
+/* The same in FP64 (q, p, dq, dp are double[n][3]).  The workspace is that
+ * of gs_workspace_bytes(n, prm with GS_FLAG_F64, GS_EXACT, GS_OP_RHS) (its
+ * header only: the status word). */
 gs_status gs_rhs_exact_f64(const double *q, const double *p, int64_t n,
                            const gs_params *prm, double *dq, double *dp, void *ws,
                            size_t ws_bytes, hipStream_t stream);
@@ -188,7 +202,11 @@ gs_status gs_shoot_adjoint(const float *q0, const float *p0, const float *target
                            hipStream_t stream);
 
 /* Velocity field of eq. (3) at m arbitrary points x (DEVICE float[m][3]):
- * v(x) = sum_j G(|x - q_j|) p_j over the n sources (q, p).  Exact sum. */
+ * v(x) = sum_j G(|x - q_j|) p_j over the n sources (q, p).  Exact sum, FP32
+ * pairs with FP64 accumulation, positions relative to the sources' box
+ * centre.  The workspace comes from gs_field_workspace_bytes (0 for invalid
+ * arguments). */
+size_t gs_field_workspace_bytes(int64_t m, int64_t n, const gs_params *prm);
 gs_status gs_field(const float *x, int64_t m, const float *q, const float *p, int64_t n,
                    const gs_params *prm, float *v, void *ws, size_t ws_bytes,
                    hipStream_t stream);
@@ -271,7 +289,10 @@ gs_status gs_autotune_exact(const float *q, const float *p, const int64_t *offse
                             hipStream_t stream, double *best_ms);
 
 /* Waits for `stream` and returns the device-side status word of the last
- * Barnes-Hut call that used this workspace (GS_OK or GS_ERR_NONFINITE). */
+ * Barnes-Hut call that used this workspace: GS_OK; GS_ERR_NONFINITE when a
+ * coordinate was NaN or infinite (the results are not meaningful); or
+ * GS_ERR_OVERFLOW when a traversal stack overflowed (the results of that call
+ * are incomplete; trees of at most 22 levels cannot overflow it). */
 gs_status gs_get_status(const void *ws, hipStream_t stream);
 
 /* Waits for `stream` and copies the counters of the last Barnes-Hut call

@@ -36,9 +36,10 @@ struct AdjointBufs {
     const int *hseg;          // [nsub + 1] partial range of each set
     double *dpart;            // data-term partials, one per unit
     int nunits;
-    const int4 *units;        // [nunits] (first point, count <= 256, set, -)
+    const int4 *units;        // [nunits] (first point, count <= 256, set, -); null: the
+    RowGeom urows;            // row blocks of one set (urows)
     const int *useg;          // [nsub + 1] unit range of each set
-    const double *setn;       // [nsub] points of each set
+    const double *setn;       // [nsub] points of each set (null: one set of n points)
     double *dsum, *hsum;      // [nsub] data term and energy of each set
 };
 // Carves the buffers that both paths add to their forward buffers; the
@@ -52,7 +53,7 @@ gs_status shoot_adjoint(const float *q0, const float *p0, const float *y, const 
                         hipStream_t s);
 
 // Barnes-Hut hooks (bh_adjoint.hip).
-gs_status bh_adjoint_begin(char *ws, hipStream_t s);
+gs_status bh_adjoint_begin(const float *q0, AdjointBufs &b, char *ws, hipStream_t s);
 gs_status bh_adjoint_forward_step(AdjointBufs &b, const gs_params &prm, double dt, double *v0,
                                   char *ws, hipStream_t s);
 gs_status bh_adjoint_step(AdjointBufs &b, const gs_params &prm, double dt, const double *sq,

@@ -56,17 +56,17 @@ __global__ void k_state64(const float *__restrict__ q, const float *__restrict__
 // beta = 0, and the unit's sum of |q - y|^2.
 __global__ __launch_bounds__(256) void k_terminal_units(const double *__restrict__ q,
                                                         const float *__restrict__ y,
-                                                        const int4 *__restrict__ units,
+                                                        const int4 *__restrict__ units, RowGeom rg,
                                                         const double *__restrict__ setn,
-                                                        double *__restrict__ al,
+                                                        double n1, double *__restrict__ al,
                                                         double *__restrict__ be,
                                                         double *__restrict__ part) {
     __shared__ double lds[8];
-    const int4 d = units[blockIdx.x];
+    const int4 d = row_block(units, rg, blockIdx.x);
     double e = 0.0;
     if ((int)threadIdx.x < d.y) {
         const int64_t i = (int64_t)d.x + threadIdx.x;
-        const double ns = setn[d.z];
+        const double ns = setn ? setn[d.z] : n1;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const double r = q[3 * i + c] - (double)y[3 * i + c];
@@ -82,37 +82,46 @@ __global__ __launch_bounds__(256) void k_terminal_units(const double *__restrict
 // objective[s] = data[s] / n_s + lambda H[s] (0 for an empty set).
 __global__ void k_objective_sets(const double *__restrict__ dsum,
                                  const double *__restrict__ hsum,
-                                 const double *__restrict__ setn, int nsub, double lambda,
-                                 double *__restrict__ obj) {
+                                 const double *__restrict__ setn, double n1, int nsub,
+                                 double lambda, double *__restrict__ obj) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= nsub) return;
-    obj[s] = setn[s] > 0.0 ? dsum[s] / setn[s] + lambda * hsum[s] : 0.0;
+    const double ns = setn ? setn[s] : n1;
+    obj[s] = ns > 0.0 ? dsum[s] / ns + lambda * hsum[s] : 0.0;
 }
 
-// Block b takes work item b = (first target row of 256, source rows [j0, j1)
-// of the same set, partial slot; slot -1: padding item).  One target per
-// lane, wave-uniform sources, FP32 pairs summed per tile of kTile sources
+// Work item b = (first target row, source rows [j0, j1) of the same set,
+// partial slot; slot -1: padding item), with the layout of the forward pair
+// kernel: wave (group g, split w) takes targets it.x + 64 g + lane and the
+// w-th share (whole tiles) of the chunk; the waves of a group add their
+// sums in LDS in split order.  FP32 pairs summed per tile of kTile sources
 // and accumulated in FP64.  Padding rows hold zero p, alpha', beta' and add
 // exactly zero.  bscale = k^2 sigma^2.  The source loop is not unrolled:
 // measured at 50k points, 2.01 ms per launch against 2.39 ms unrolled by 4
 // (76 VGPRs, 6 waves per SIMD) and 2.45 ms with the source tile staged in
 // LDS.
-__global__ __launch_bounds__(256) void k_adj_items(const float4 *__restrict__ Q,
-                                                   const float4 *__restrict__ P,
-                                                   const float4 *__restrict__ AL,
-                                                   const float4 *__restrict__ BE, int64_t npad,
-                                                   const int4 *__restrict__ items,
-                                                   double bscale, double *__restrict__ part) {
-    const int4 it = items[blockIdx.x];
-    if (it.w < 0) return;
-    const int64_t i = (int64_t)it.x + threadIdx.x;
+__global__ __launch_bounds__(kItemThreads) void k_adj_items(
+    const float4 *__restrict__ Q, const float4 *__restrict__ P, const float4 *__restrict__ AL,
+    const float4 *__restrict__ BE, int64_t npad, const int4 *__restrict__ items, ItemGeom geom,
+    double bscale, double *__restrict__ part) {
+    __shared__ double red[kItemSplit > 1 ? kItemSplit - 1 : 1][6][kItemRows];
+    const int4 it = work_item(items, geom, blockIdx.x);
+    if (it.w < 0) return;  // padding item: the whole block leaves before any barrier
+    const int wv = wave_in_block();
+    const int grp = wv % kItemGroups, w = wv / kItemGroups;
+    const int r = grp * 64 + (threadIdx.x & 63);
+    const int64_t i = (int64_t)it.x + r;
     const float4 qa = Q[i], pa4 = P[i], aa = AL[i], ba = BE[i];
     const float x = qa.x, y = qa.y, z = qa.z;
     const float px = pa4.x, py = pa4.y, pz = pa4.z;
     const float ax = aa.x, ay = aa.y, az = aa.z;
     const float bx = ba.x, by = ba.y, bz = ba.z;
     double sq[3] = {0, 0, 0}, spp[3] = {0, 0, 0};
-    for (int jt = it.y; jt < it.z; jt += kTile) {  // 32-bit: scalar-unit compares
+    const int ntile = (it.z - it.y) / kTile;
+    const int per = (ntile + kItemSplit - 1) / kItemSplit;
+    const int j0 = it.y + min(w * per, ntile) * kTile;
+    const int j1 = it.y + min((w + 1) * per, ntile) * kTile;
+    for (int jt = j0; jt < j1; jt += kTile) {  // 32-bit: scalar-unit compares
         float tq[3] = {0.f, 0.f, 0.f}, tb[3] = {0.f, 0.f, 0.f}, tp[3] = {0.f, 0.f, 0.f};
 #pragma unroll 1
         for (int u = 0; u < kTile; ++u) {
@@ -146,6 +155,23 @@ __global__ __launch_bounds__(256) void k_adj_items(const float4 *__restrict__ Q,
             spp[c] += (double)tp[c];
         }
     }
+    if (kItemSplit > 1) {
+        if (w > 0)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                red[w - 1][c][r] = sq[c];
+                red[w - 1][3 + c][r] = spp[c];
+            }
+        __syncthreads();
+        if (w == 0)
+            for (int k = 0; k < kItemSplit - 1; ++k)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    sq[c] += red[k][c][r];
+                    spp[c] += red[k][3 + c][r];
+                }
+    }
+    if (w != 0) return;
     double *dst = part + (int64_t)it.w * 6 * npad;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -157,11 +183,11 @@ __global__ __launch_bounds__(256) void k_adj_items(const float4 *__restrict__ Q,
 // (alpha, beta) += dt (sigma^-2 S_q, k S_p) from the partial slots of each row.
 __global__ __launch_bounds__(256) void k_adj_update_rows(const double *__restrict__ part,
                                                          int64_t npad,
-                                                         const int4 *__restrict__ blk,
+                                                         const int4 *__restrict__ blk, RowGeom rg,
                                                          double inv_s2, double ks, double dt,
                                                          double *__restrict__ al,
                                                          double *__restrict__ be) {
-    const int4 d = blk[blockIdx.x];
+    const int4 d = row_block(blk, rg, blockIdx.x);
     if ((int)threadIdx.x >= d.y) return;
     const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int64_t i = (int64_t)d.x + threadIdx.x;
@@ -209,8 +235,8 @@ void carve_adjoint_common(Arena &a, int64_t n, int nsub, int nt, int ckpt, int n
 
 // Restores the packed FP32 rows of the exact path from the FP64 state.
 static gs_status exact_repack(AdjointBufs &b, const gs_params &prm, hipStream_t s) {
-    return launch_pack_rows64(*b.xp, b.ex.blk, b.Sq, b.Sp, position_scale(prm.sigma), b.ex.Q,
-                              b.ex.P, s);
+    return launch_pack_rows64(*b.xp, b.ex, b.Sq, b.Sp, position_scale(prm.sigma), b.ex.Q, b.ex.P,
+                              s, 1.0, true);
 }
 
 // One forward Euler step of the chosen method from the FP64 state (b.Sq,
@@ -219,7 +245,7 @@ static gs_status exact_repack(AdjointBufs &b, const gs_params &prm, hipStream_t 
 static gs_status forward_step(AdjointBufs &b, const gs_params &prm, double dt, double *v0,
                               char *ws, hipStream_t s) {
     if (b.bh) return bh_adjoint_forward_step(b, prm, dt, v0, ws, s);
-    GS_TRY(launch_exact_items(*b.xp, b.ex, prm.sigma, true, s));
+    GS_TRY(launch_exact_items(*b.xp, b.ex, true, s));
     return launch_combine_rows(*b.xp, b.ex, prm.sigma, 1, nullptr, nullptr, dt,
                                v0 ? b.hpart : nullptr, s, v0);
 }
@@ -229,19 +255,22 @@ static gs_status adjoint_step(AdjointBufs &b, const gs_params &prm, double dt, c
                               const double *sp, char *ws, hipStream_t s) {
     if (b.bh) return bh_adjoint_step(b, prm, dt, sq, sp, ws, s);
     const ExactBatchPlan &pl = *b.xp;
-    if (pl.items.empty()) return GS_OK;
+    const int64_t ni = plan_item_count(pl);
+    if (ni == 0) return GS_OK;
     const double ks = position_scale(prm.sigma);
-    GS_TRY(launch_pack_rows64(pl, b.ex.blk, sq, sp, ks, b.ex.Q, b.ex.P, s));
+    GS_TRY(launch_pack_rows64(pl, b.ex, sq, sp, ks, b.ex.Q, b.ex.P, s, 1.0, true));
     const double bscale = ks * ks * prm.sigma * prm.sigma;
-    GS_TRY(launch_pack_rows64(pl, b.ex.blk, b.al, b.be, 1.0 / ks, b.AL, b.BE, s, 1.0 / bscale));
+    GS_TRY(launch_pack_rows64(pl, b.ex, b.al, b.be, 1.0 / ks, b.AL, b.BE, s, 1.0 / bscale,
+                              false));
     timing_begin(KIND_ADJOINT, s);
-    hipLaunchKernelGGL(k_adj_items, dim3((unsigned)pl.items.size()), dim3(256), 0, s, b.ex.Q,
-                       b.ex.P, b.AL, b.BE, pl.npad, b.ex.items, bscale, b.ex.part);
+    hipLaunchKernelGGL(k_adj_items, dim3((unsigned)ni), dim3(kItemThreads), 0, s, b.ex.Q, b.ex.P,
+                       b.AL, b.BE, pl.npad, pl.single ? nullptr : b.ex.items, pl.geom, bscale,
+                       b.ex.part);
     timing_end(KIND_ADJOINT, s);
     GS_LAUNCH_CHECK("adj_items");
-    hipLaunchKernelGGL(k_adj_update_rows, dim3((unsigned)pl.blocks.size()), dim3(256), 0, s,
-                       b.ex.part, pl.npad, b.ex.blk, 1.0 / (prm.sigma * prm.sigma), ks, dt, b.al,
-                       b.be);
+    hipLaunchKernelGGL(k_adj_update_rows, dim3((unsigned)plan_block_count(pl)), dim3(256), 0, s,
+                       b.ex.part, pl.npad, b.ex.blk, pl.rows, 1.0 / (prm.sigma * prm.sigma), ks,
+                       dt, b.al, b.be);
     GS_LAUNCH_CHECK("adj_update_rows");
     return GS_OK;
 }
@@ -253,7 +282,7 @@ gs_status shoot_adjoint(const float *q0, const float *p0, const float *y, const 
     const double dt = 1.0 / prm.nt;
     if (n3 > 0) {
         if (b.bh) {
-            GS_TRY(bh_adjoint_begin(ws, s));
+            GS_TRY(bh_adjoint_begin(q0, b, ws, s));
             hipLaunchKernelGGL(k_state64, dim3(nblk(n3)), dim3(kBlock), 0, s, q0, p0, n3, b.Sq,
                                b.Sp);
             GS_LAUNCH_CHECK("state64");
@@ -272,14 +301,14 @@ gs_status shoot_adjoint(const float *q0, const float *p0, const float *y, const 
         // terminal adjoint and the per-set data term
         if (b.nunits > 0) {
             hipLaunchKernelGGL(k_terminal_units, dim3((unsigned)b.nunits), dim3(256), 0, s, b.Sq,
-                               y, b.units, b.setn, b.al, b.be, b.dpart);
+                               y, b.units, b.urows, b.setn, (double)b.n, b.al, b.be, b.dpart);
             GS_LAUNCH_CHECK("terminal");
         }
     }
     GS_TRY(launch_reduce_h_seg(b.dpart, b.nunits, b.useg, b.nsub, 1, b.dsum, s));
     GS_TRY(launch_reduce_h_seg(b.hpart, b.nh, b.hseg, b.nsub, 1, b.hsum, s));
     hipLaunchKernelGGL(k_objective_sets, dim3(nblk(b.nsub)), dim3(kBlock), 0, s, b.dsum, b.hsum,
-                       b.setn, b.nsub, lambda, objective);
+                       b.setn, (double)b.n, b.nsub, lambda, objective);
     GS_LAUNCH_CHECK("objective");
     if (n3 == 0) return GS_OK;
     // backward sweep, one checkpoint segment at a time

@@ -34,14 +34,6 @@ __global__ void k_clear(int *__restrict__ status, u64 *__restrict__ counters) {
         counters[i] = 0ull;
 }
 
-__global__ void k_to_f32(const double *__restrict__ a, const double *__restrict__ b, int64_t n3,
-                         float *__restrict__ fa, float *__restrict__ fb) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n3) return;
-    fa[i] = (float)a[i];
-    fb[i] = (float)b[i];
-}
-
 // alpha, beta (original order, FP64) -> Morton order FP32 float4
 __global__ void k_gather_ab(const double *__restrict__ al, const double *__restrict__ be,
                             const unsigned *__restrict__ perm, int64_t n,
@@ -157,7 +149,8 @@ __device__ inline void load_block(const BhNode *__restrict__ nodes,
 // list of leaves to sum exactly.
 __global__ __launch_bounds__(256) void k_adj_decide(
     const BhNode *__restrict__ nodes, const double *__restrict__ adj,
-    const float4 *__restrict__ Qs, const float4 *__restrict__ Ps, const float4 *__restrict__ As,
+    const float4 *__restrict__ Qs, const float4 *__restrict__ Qc,
+    const float4 *__restrict__ Ps, const float4 *__restrict__ As,
     const float4 *__restrict__ Bs, int64_t n, const GroupDesc *__restrict__ gtab, int64_t groups,
     TravSplit split, BhParams bp, LeafEntry *__restrict__ list, int *__restrict__ list_n,
     double *__restrict__ part, u64 *__restrict__ counters, int *__restrict__ status) {
@@ -173,9 +166,9 @@ __global__ __launch_bounds__(256) void k_adj_decide(
     const int64_t t = (int64_t)gd.first + lane;
     const bool active = lane < gd.count;
     const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
-    const float4 xq = active ? Qs[t] : z4, xp = active ? Ps[t] : z4;
+    const float4 xs = active ? Qs[t] : z4, xp = active ? Ps[t] : z4;
     const float4 xa = active ? As[t] : z4, xb = active ? Bs[t] : z4;
-    const double xd = xq.x, yd = xq.y, zd = xq.z;
+    const double xd = xs.x, yd = xs.y, zd = xs.z;
     const float inv_s2 = bp.inv_s2f;
     LeafEntry *mylist = list + grp * kListPerGroup + (int64_t)sub * split.segcap;
     double GQ[3] = {0, 0, 0}, GP[3] = {0, 0, 0};
@@ -222,8 +215,8 @@ __global__ __launch_bounds__(256) void k_adj_decide(
                     const float inv_n = 1.f / (float)nd.n;
                     const float mbx = (float)L.adj[k][3] * inv_n, mby = (float)L.adj[k][4] * inv_n,
                                 mbz = (float)L.adj[k][5] * inv_n;
-                    const float dx = xq.x - (float)nd.cx, dy = xq.y - (float)nd.cy,
-                                dz = xq.z - (float)nd.cz;
+                    const float dx = (float)(xd - nd.cx), dy = (float)(yd - nd.cy),
+                                dz = (float)(zd - nd.cz);
                     const float g =
                         __builtin_amdgcn_exp2f((dx * dx + dy * dy + dz * dz) * bp.negc);
                     const float s = xp.x * nd.px + xp.y * nd.py + xp.z * nd.pz;
@@ -261,13 +254,14 @@ __global__ __launch_bounds__(256) void k_adj_decide(
                     }
                     ++nlist;
                 } else {  // segment full: sum this leaf here
-                    leaf_adjoint(Qs, Ps, As, Bs, nfirst, ncount, need, xq, xp, xa, xb, bp.negc,
+                    const float4 xc = active ? Qc[t] : z4;
+                    leaf_adjoint(Qc, Ps, As, Bs, nfirst, ncount, need, xc, xp, xa, xb, bp.negc,
                                  inv_s2, GQ, GP);
                 }
             } else {
                 if (sp >= kBlockStack) {
                     // cannot happen for trees of at most 22 levels; stop safely
-                    if (lane == 0 && status) *status = 2;
+                    if (lane == 0 && status) *status = kStatusOverflow;
                     sp = -1;
                     break;
                 }
@@ -300,7 +294,8 @@ __global__ __launch_bounds__(256) void k_adj_decide(
     }
 }
 
-// Phase 2: one wave per (group, chunk of its list entries).
+// Phase 2: one wave per (group, chunk of its list entries), on the positions
+// relative to the set's box centre.
 __global__ __launch_bounds__(256) void k_adj_leaves(
     const float4 *__restrict__ Qs, const float4 *__restrict__ Ps, const float4 *__restrict__ As,
     const float4 *__restrict__ Bs, int64_t n, const GroupDesc *__restrict__ gtab, int64_t groups,
@@ -375,27 +370,26 @@ BhAdjBufs layout_bh_adjoint(Arena &a, int64_t n) {
     return b;
 }
 
-gs_status bh_adjoint_begin(char *ws, hipStream_t s) {
+gs_status bh_adjoint_begin(const float *q0, AdjointBufs &b, char *ws, hipStream_t s) {
     hipLaunchKernelGGL(k_clear, dim3(1), dim3(64), 0, s, reinterpret_cast<int *>(ws),
                        reinterpret_cast<u64 *>(ws + kCountersOffset));
     GS_LAUNCH_CHECK("clear");
-    return GS_OK;
+    // the frame of the FP32 copies: box centres of q0, fixed for the call
+    return tree_set_centres(q0, b.sh.tree, b.sh.c0, reinterpret_cast<int *>(ws), s);
 }
 
 gs_status bh_adjoint_forward_step(AdjointBufs &b, const gs_params &prm, double dt, double *v0,
                                   char *ws, hipStream_t s) {
     int *status = reinterpret_cast<int *>(ws);
     u64 *counters = reinterpret_cast<u64 *>(ws + kCountersOffset);
-    const int64_t n3 = 3 * b.n;
-    hipLaunchKernelGGL(k_to_f32, dim3(nblk(n3)), dim3(kBlock), 0, s, b.Sq, b.Sp, n3, b.sh.q32,
-                       b.sh.p32);
-    GS_LAUNCH_CHECK("to_f32");
+    GS_TRY(launch_state_to_f32(b.Sq, b.Sp, b.sh.tree, b.sh.c0, b.sh.q32, b.sh.p32, s));
     GS_TRY(build_tree(b.sh.q32, b.sh.p32, b.n, prm.leaf_cap, b.sh.tree, status, s));
     TraverseOut o{};
     o.Sq = b.Sq;
     o.Sp = b.Sp;
     o.q32 = b.sh.q32;
     o.p32 = b.sh.p32;
+    o.c0 = b.sh.c0;
     o.dt = dt;
     o.Hpart = v0 ? b.hpart : nullptr;
     o.v64 = v0;
@@ -407,11 +401,9 @@ gs_status bh_adjoint_step(AdjointBufs &b, const gs_params &prm, double dt, const
                           const double *sp, char *ws, hipStream_t s) {
     int *status = reinterpret_cast<int *>(ws);
     u64 *counters = reinterpret_cast<u64 *>(ws + kCountersOffset);
-    const int64_t n = b.n, n3 = 3 * n;
+    const int64_t n = b.n;
     TreeBufs &t = b.sh.tree;
-    hipLaunchKernelGGL(k_to_f32, dim3(nblk(n3)), dim3(kBlock), 0, s, sq, sp, n3, b.sh.q32,
-                       b.sh.p32);
-    GS_LAUNCH_CHECK("to_f32");
+    GS_TRY(launch_state_to_f32(sq, sp, t, b.sh.c0, b.sh.q32, b.sh.p32, s));
     GS_TRY(build_tree(b.sh.q32, b.sh.p32, n, prm.leaf_cap, t, status, s));
     hipLaunchKernelGGL(k_gather_ab, dim3(nblk(n)), dim3(kBlock), 0, s, b.al, b.be, t.perm, n,
                        b.bhadj.ALs, b.bhadj.BEs);
@@ -422,10 +414,10 @@ gs_status bh_adjoint_step(AdjointBufs &b, const gs_params &prm, double dt, const
     const TravSplit split = traverse_split(t.groups);
     timing_begin(KIND_ADJOINT, s);
     hipLaunchKernelGGL(k_adj_decide, dim3((unsigned)((t.groups * split.nsub + 3) / 4)), dim3(256), 0,
-                       s, t.nodes, t.adj, t.Qs, t.Ps, b.bhadj.ALs, b.bhadj.BEs, n, t.gtab,
+                       s, t.nodes, t.adj, t.Qs, t.Qc, t.Ps, b.bhadj.ALs, b.bhadj.BEs, n, t.gtab,
                        t.groups, split, bp, list, t.list_n, t.part, counters, status);
     hipLaunchKernelGGL(k_adj_leaves, dim3((unsigned)t.groups, (split.maxc + 3) / 4), dim3(256), 0, s,
-                       t.Qs, t.Ps, b.bhadj.ALs, b.bhadj.BEs, n, t.gtab, t.groups, split, bp.negc,
+                       t.Qc, t.Ps, b.bhadj.ALs, b.bhadj.BEs, n, t.gtab, t.groups, split, bp.negc,
                        bp.inv_s2f, list, t.list_n, t.part);
     hipLaunchKernelGGL(k_adj_combine, dim3((unsigned)((t.groups + 3) / 4)), dim3(256), 0, s,
                        t.part, t.list_n, t.gtab, t.groups, split, t.perm, n, bp.inv_s2, dt, b.al,

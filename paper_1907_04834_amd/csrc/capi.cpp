@@ -112,6 +112,10 @@ gs_status check_params(const gs_params *prm, bool need_nt, bool need_tree) {
             return GS_ERR_INVALID;
         }
     }
+    if (prm->flags & ~(uint32_t)(GS_FLAG_F64 | GS_FLAG_GRAPH)) {
+        set_error("unknown flags 0x%x", (unsigned)prm->flags);
+        return GS_ERR_INVALID;
+    }
     if (prm->exact_items != 0 && (prm->exact_items < 256 || prm->exact_items > (1 << 22))) {
         set_error("exact_items must be 0 or in [256, 4194304] (got %d)", prm->exact_items);
         return GS_ERR_INVALID;
@@ -155,22 +159,6 @@ gs_status check_ws(void *ws, size_t have, size_t need) {
 // ---------------------------------------------------------------- layouts
 // Every operation lays out its buffers with the same code whether it is
 // measuring (base == nullptr) or carving the caller's workspace.
-struct ShootExactBufs {
-    ExactBufs ex;
-    double *Sq, *Sp;  // FP64 state [n][3]
-    double *Hpart;
-};
-
-ShootExactBufs layout_shoot_exact(Arena &a, int64_t n, int nt) {
-    ShootExactBufs b{};
-    ExactPlan pl = plan_exact(n, n);
-    carve_exact(a, pl, b.ex);
-    b.Sq = a.take<double>(3 * n);
-    b.Sp = a.take<double>(3 * n);
-    b.Hpart = a.take<double>((size_t)(nt + 1) * combine_blocks(n));
-    return b;
-}
-
 struct ShootF64Bufs {
     double *q, *p, *v, *a, *Hpart;
 };
@@ -185,63 +173,22 @@ ShootF64Bufs layout_shoot_f64(Arena &a, int64_t n, int nt) {
     return b;
 }
 
-// Field evaluation: sources packed as for an RHS of max(m, n) points, plus the
-// packed targets.  `big` = max(m, n) bounds both plans.
-float4 *layout_field(Arena &a, int64_t big, ExactBufs &b) {
-    ExactPlan pl = plan_exact(big, big);
-    carve_exact(a, pl, b);
-    return a.take<float4>(pl.ntgt > pl.nsrc ? pl.ntgt : pl.nsrc);
-}
-
 size_t measure_batch(const int64_t *off, int nsub, const gs_params &prm, int method, int op,
                      int ckpt = 8);
-
-// The single-set exact FP32 right-hand side and shooting run as a batch of
-// one set (the work-item kernel); the opt-in matrix-core variant keeps the
-// source-split kernel.
-bool exact_items_path(const gs_params *prm) { return (prm->flags & GS_FLAG_MFMA_PAIRS) == 0; }
+size_t measure_field(int64_t m, int64_t n, const gs_params &prm);
 
 size_t measure_bytes(int64_t n, const gs_params *prm, int32_t method, int32_t op) {
     const bool f64 = (prm->flags & GS_FLAG_F64) != 0;
-    if (method == GS_EXACT && !f64 && (op == GS_OP_RHS || op == GS_OP_SHOOT) &&
-        exact_items_path(prm)) {
-        const int64_t off[2] = {0, n};
-        return measure_batch(off, 1, *prm, GS_EXACT, op);
+    if (op == GS_OP_FIELD) return measure_field(n, n, *prm);
+    if (f64) {
+        if (method != GS_EXACT) return 0;
+        Arena a{nullptr, kHeader, 0};
+        if (op == GS_OP_SHOOT) layout_shoot_f64(a, n, prm->nt);
+        return op == GS_OP_RHS || op == GS_OP_SHOOT ? a.off + 256 : 0;
     }
-    Arena a{nullptr, kHeader, 0};
-    switch (op) {
-        case GS_OP_RHS:
-            if (f64) break;
-            if (method == GS_EXACT) {
-                ExactBufs b;
-                carve_exact(a, plan_exact(n, n), b);
-            } else {
-                TreeBufs t;
-                carve_tree(a, n, t);
-            }
-            break;
-        case GS_OP_SHOOT:
-            if (f64) {
-                layout_shoot_f64(a, n, prm->nt);
-            } else if (method == GS_EXACT) {
-                layout_shoot_exact(a, n, prm->nt);
-            } else {
-                layout_shoot_bh(a, n, prm->nt);
-            }
-            break;
-        case GS_OP_ADJOINT: {
-            const int64_t off[2] = {0, n};
-            return measure_batch(off, 1, *prm, method, GS_OP_ADJOINT);
-        }
-        case GS_OP_FIELD: {
-            ExactBufs b;
-            layout_field(a, n, b);
-            break;
-        }
-        default:
-            return 0;
-    }
-    return a.off + 256;
+    if (op != GS_OP_RHS && op != GS_OP_SHOOT && op != GS_OP_ADJOINT) return 0;
+    const int64_t off[2] = {0, n};
+    return measure_batch(off, 1, *prm, method, op);
 }
 
 // ---------------------------------------------------------------- batched sets
@@ -326,7 +273,8 @@ std::shared_ptr<const ExactBatchPlan> exact_plan(const int64_t *off, int nsub, i
 }
 
 struct Batch {
-    std::shared_ptr<const ExactBatchPlan> plan;  // keeps *xp alive
+    std::shared_ptr<const ExactBatchPlan> plan;  // keeps *xp alive (several sets)
+    ExactBatchPlan own;                          // one set: no tables
     const ExactBatchPlan *xp = nullptr;
     ExactBatchBufs ex{};
     ShootBhBufs bh{};
@@ -337,31 +285,43 @@ struct Batch {
 
 // Lays out (or measures, when the arena has no base) the buffers of a
 // batched call and prepares its tables.  `ckpt` is the checkpoint interval
-// of op GS_OP_ADJOINT.  The Batch must stay where it is while in use
-// (b.adj points into it).
+// of op GS_OP_ADJOINT.  One set (nsub == 1) needs no tables: its kernels
+// compute the work items, row blocks and traversal groups from its size, so
+// such a call copies nothing from the host.  The Batch must stay where it is
+// while in use (b.adj points into it).
 void layout_batch(Arena &a, const int64_t *off, int nsub, const gs_params &prm, int method,
                   int op, Batch &b, int ckpt = 8) {
     const int nt = op == GS_OP_SHOOT ? prm.nt : 0;
     const bool adj = op == GS_OP_ADJOINT;
+    const bool single = nsub == 1;
     const int ck = ckpt < prm.nt ? ckpt : prm.nt;
+    const int64_t ntot = off[nsub];
     std::vector<double> setn;  // points of each set (backward stage)
-    if (adj)
+    if (adj && !single)
         for (int s = 0; s < nsub; ++s) setn.push_back((double)(off[s + 1] - off[s]));
     if (method == GS_EXACT) {
-        b.plan = exact_plan(off, nsub, prm.exact_items);
-        b.xp = b.plan.get();
+        if (single) {
+            b.own = plan_exact_single(ntot, prm.exact_items);
+            b.xp = &b.own;
+        } else {
+            b.plan = exact_plan(off, nsub, prm.exact_items);
+            b.xp = b.plan.get();
+        }
         carve_exact_batch(a, *b.xp, nt, b.ex);
-        const int nb = (int)b.xp->blocks.size();
+        const int nb = (int)plan_block_count(*b.xp);
         if (adj) {
             b.adj.AL = a.take<float4>(b.xp->npad);
             b.adj.BE = a.take<float4>(b.xp->npad);
-            carve_adjoint_common(a, off[nsub], nsub, prm.nt, ck, nb, b.adj);
+            carve_adjoint_common(a, ntot, nsub, prm.nt, ck, nb, b.adj);
         }
-        const size_t o_items = b.img.add(b.xp->items.data(), b.xp->items.size());
-        const size_t o_blk = b.img.add(b.xp->blocks.data(), b.xp->blocks.size());
-        const size_t o_bseg = b.img.add(b.xp->bseg.data(), b.xp->bseg.size());
-        const size_t o_setn = b.img.add(setn.data(), setn.size());
-        b.tables = a.take<char>(b.img.bytes.size());
+        size_t o_items = 0, o_blk = 0, o_bseg = 0, o_setn = 0;
+        if (!single) {
+            o_items = b.img.add(b.xp->items.data(), b.xp->items.size());
+            o_blk = b.img.add(b.xp->blocks.data(), b.xp->blocks.size());
+            o_bseg = b.img.add(b.xp->bseg.data(), b.xp->bseg.size());
+            o_setn = b.img.add(setn.data(), setn.size());
+            b.tables = a.take<char>(b.img.bytes.size());
+        }
         if (b.tables) {
             b.ex.items = reinterpret_cast<const int4 *>(b.tables + o_items);
             b.ex.blk = reinterpret_cast<const int4 *>(b.tables + o_blk);
@@ -377,6 +337,7 @@ void layout_batch(Arena &a, const int64_t *off, int nsub, const gs_params &prm, 
             b.adj.nh = nb;
             b.adj.hseg = b.ex.bseg;
             b.adj.units = b.ex.blk;
+            b.adj.urows = b.xp->rows;
             b.adj.useg = b.ex.bseg;
             b.adj.setn = b.tables ? reinterpret_cast<const double *>(b.tables + o_setn) : nullptr;
         }
@@ -386,13 +347,14 @@ void layout_batch(Arena &a, const int64_t *off, int nsub, const gs_params &prm, 
     std::vector<long long> seg(nsub + 1);
     std::vector<GroupDesc> gt;
     std::vector<int> gseg(nsub + 1);
-    int64_t max_set = 0;
+    int64_t max_set = 0, ngroups = 0;
     for (int s = 0; s < nsub; ++s) {
         seg[s] = off[s];
-        gseg[s] = (int)gt.size();
+        gseg[s] = (int)ngroups;
         const int64_t n = off[s + 1] - off[s];
         if (n > max_set) max_set = n;
-        for (int64_t g = 0; g * 64 < n; ++g) {
+        for (int64_t g = 0; g * 64 < n; ++g, ++ngroups) {
+            if (single) continue;  // group g of one set: points [64 g, 64 g + 64)
             GroupDesc d;
             d.first = (int)(off[s] + 64 * g);
             d.count = (int)(n - 64 * g < 64 ? n - 64 * g : 64);
@@ -402,33 +364,37 @@ void layout_batch(Arena &a, const int64_t *off, int nsub, const gs_params &prm, 
         }
     }
     seg[nsub] = off[nsub];
-    gseg[nsub] = (int)gt.size();
-    const int64_t ntot = off[nsub];
+    gseg[nsub] = (int)ngroups;
     if (op == GS_OP_SHOOT || adj)
-        b.bh = layout_shoot_forest(a, ntot, nsub, (int64_t)gt.size(), max_set, nt);
+        b.bh = layout_shoot_forest(a, ntot, nsub, ngroups, max_set, nt);
     else
-        carve_forest(a, ntot, nsub, (int64_t)gt.size(), max_set, b.bh.tree);
+        carve_forest(a, ntot, nsub, ngroups, max_set, b.bh.tree);
     // reduction units of the backward stage: blocks of <= 256 points of one set
     std::vector<int4> units;
     std::vector<int> useg(nsub + 1);
+    int64_t nunits = 0;
     if (adj) {
         for (int s = 0; s < nsub; ++s) {
-            useg[s] = (int)units.size();
-            for (int64_t i = off[s]; i < off[s + 1]; i += 256)
-                units.push_back(make_int4((int)i, (int)(off[s + 1] - i < 256 ? off[s + 1] - i : 256),
-                                          s, 0));
+            useg[s] = (int)nunits;
+            for (int64_t i = off[s]; i < off[s + 1]; i += 256, ++nunits)
+                if (!single)
+                    units.push_back(make_int4((int)i, (int)std::min<int64_t>(256, off[s + 1] - i),
+                                              s, 0));
         }
-        useg[nsub] = (int)units.size();
+        useg[nsub] = (int)nunits;
         b.adj.bhadj = layout_bh_adjoint(a, ntot);
-        carve_adjoint_common(a, ntot, nsub, prm.nt, ck, (int)units.size(), b.adj);
+        carve_adjoint_common(a, ntot, nsub, prm.nt, ck, (int)nunits, b.adj);
     }
-    const size_t o_seg = b.img.add(seg.data(), seg.size());
-    const size_t o_gt = b.img.add(gt.data(), gt.size());
-    const size_t o_gseg = b.img.add(gseg.data(), gseg.size());
-    const size_t o_units = b.img.add(units.data(), units.size());
-    const size_t o_useg = b.img.add(useg.data(), adj ? useg.size() : 0);
-    const size_t o_setn = b.img.add(setn.data(), setn.size());
-    b.tables = a.take<char>(b.img.bytes.size());
+    size_t o_seg = 0, o_gt = 0, o_gseg = 0, o_units = 0, o_useg = 0, o_setn = 0;
+    if (!single) {
+        o_seg = b.img.add(seg.data(), seg.size());
+        o_gt = b.img.add(gt.data(), gt.size());
+        o_gseg = b.img.add(gseg.data(), gseg.size());
+        o_units = b.img.add(units.data(), units.size());
+        o_useg = b.img.add(useg.data(), adj ? useg.size() : 0);
+        o_setn = b.img.add(setn.data(), setn.size());
+        b.tables = a.take<char>(b.img.bytes.size());
+    }
     if (b.tables) {
         b.bh.tree.seg = reinterpret_cast<const long long *>(b.tables + o_seg);
         b.bh.tree.gtab = reinterpret_cast<const GroupDesc *>(b.tables + o_gt);
@@ -441,12 +407,17 @@ void layout_batch(Arena &a, const int64_t *off, int nsub, const gs_params &prm, 
         b.adj.Sq = b.bh.Sq;
         b.adj.Sp = b.bh.Sp;
         b.adj.hpart = b.bh.Hpart;
-        b.adj.nh = (int)gt.size();
+        b.adj.nh = (int)ngroups;
         b.adj.hseg = b.bh.gseg;
+        b.adj.urows = row_geom(ntot, 0);
         if (b.tables) {
             b.adj.units = reinterpret_cast<const int4 *>(b.tables + o_units);
             b.adj.useg = reinterpret_cast<const int *>(b.tables + o_useg);
             b.adj.setn = reinterpret_cast<const double *>(b.tables + o_setn);
+        } else {
+            b.adj.units = nullptr;
+            b.adj.useg = nullptr;
+            b.adj.setn = nullptr;
         }
     }
 }
@@ -459,43 +430,99 @@ size_t measure_batch(const int64_t *off, int nsub, const gs_params &prm, int met
     return a.off + 256;
 }
 
-// Pinned staging buffers for the table uploads: a ring of four per thread, so
-// that a call waits (rarely) only for the upload of the call four before it.
-// They live until the process ends.
+// Buffers and tables of the velocity field (m targets, n sources).
+struct Field {
+    ExactBatchPlan plan;
+    ExactBatchBufs ex{};
+    TableImage img;
+    char *tables = nullptr;
+};
+
+void layout_field(Arena &a, int64_t m, int64_t n, const gs_params &prm, Field &f) {
+    f.plan = plan_exact_field(m, n, prm.exact_items);
+    carve_exact_field(a, f.plan, f.ex);
+    const size_t o_items = f.img.add(f.plan.items.data(), f.plan.items.size());
+    const size_t o_blk = f.img.add(f.plan.blocks.data(), f.plan.blocks.size());
+    const size_t o_sblk = f.img.add(f.plan.sblocks.data(), f.plan.sblocks.size());
+    const size_t o_sbseg = f.img.add(f.plan.sbseg.data(), f.plan.sbseg.size());
+    f.tables = a.take<char>(f.img.bytes.size());
+    if (f.tables) {
+        f.ex.items = reinterpret_cast<const int4 *>(f.tables + o_items);
+        f.ex.blk = reinterpret_cast<const int4 *>(f.tables + o_blk);
+        f.ex.sblk = reinterpret_cast<const int4 *>(f.tables + o_sblk);
+        f.ex.sbseg = reinterpret_cast<const int *>(f.tables + o_sbseg);
+        f.ex.bseg = nullptr;
+    }
+}
+
+size_t measure_field(int64_t m, int64_t n, const gs_params &prm) {
+    Arena a{nullptr, kHeader, 0};
+    Field f;
+    layout_field(a, m, n, prm, f);
+    return a.off + 256;
+}
+
+// Pinned staging buffers for the table uploads of batched calls (several
+// sets) and of the velocity field, per thread.  A call takes the next buffer
+// whose previous copy has completed (hipEventQuery, no waiting); when every
+// buffer is still in flight the ring grows, up to kStageMax buffers, so a
+// call waits on the host only when it is issued while kStageMax earlier
+// uploads of its thread are still queued on the device.  The buffers live
+// until the process ends.
+constexpr size_t kStageMax = 32;
 struct StageSlot {
-    void *buf;
-    size_t cap;
-    hipEvent_t ev;
-    bool pending;
+    void *buf = nullptr;
+    size_t cap = 0;
+    hipEvent_t ev = nullptr;
+    bool pending = false;
 };
 struct Stage {
-    StageSlot slot[4];
-    int next;
+    std::vector<StageSlot> slot;
+    size_t next = 0;
 };
-thread_local Stage g_stage = {};
+thread_local Stage g_stage;
 
 gs_status upload_tables(const TableImage &img, char *dev, hipStream_t s) {
     const size_t bytes = img.bytes.size();
     if (bytes == 0) return GS_OK;
     Stage &st = g_stage;
-    StageSlot &sl = st.slot[st.next];
-    st.next = (st.next + 1) & 3;
-    if (sl.pending) {
-        GS_HIP(hipEventSynchronize(sl.ev));
-        sl.pending = false;
+    StageSlot *sl = nullptr;
+    for (size_t k = 0; k < st.slot.size() && !sl; ++k) {
+        const size_t i = (st.next + k) % st.slot.size();
+        StageSlot &c = st.slot[i];
+        if (c.pending) {
+            const hipError_t q = hipEventQuery(c.ev);
+            if (q == hipErrorNotReady) continue;
+            if (q != hipSuccess) return hip_fail(q, "hipEventQuery");
+            c.pending = false;
+        }
+        sl = &c;
+        st.next = i + 1;
     }
-    if (sl.cap < bytes) {
-        if (sl.buf) GS_HIP(hipHostFree(sl.buf));
-        sl.buf = nullptr;
-        sl.cap = 0;
-        GS_HIP(hipHostMalloc(&sl.buf, bytes, hipHostMallocDefault));
-        sl.cap = bytes;
+    if (!sl && st.slot.size() < kStageMax) {
+        st.slot.emplace_back();
+        sl = &st.slot.back();
+        st.next = st.slot.size();
     }
-    if (!sl.ev) GS_HIP(hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming));
-    memcpy(sl.buf, img.bytes.data(), bytes);
-    GS_HIP(hipMemcpyAsync(dev, sl.buf, bytes, hipMemcpyHostToDevice, s));
-    GS_HIP(hipEventRecord(sl.ev, s));
-    sl.pending = true;
+    if (!sl) {  // kStageMax uploads in flight: wait for the oldest
+        const size_t i = st.next % st.slot.size();
+        sl = &st.slot[i];
+        GS_HIP(hipEventSynchronize(sl->ev));
+        sl->pending = false;
+        st.next = i + 1;
+    }
+    if (sl->cap < bytes) {
+        if (sl->buf) GS_HIP(hipHostFree(sl->buf));
+        sl->buf = nullptr;
+        sl->cap = 0;
+        GS_HIP(hipHostMalloc(&sl->buf, bytes, hipHostMallocDefault));
+        sl->cap = bytes;
+    }
+    if (!sl->ev) GS_HIP(hipEventCreateWithFlags(&sl->ev, hipEventDisableTiming));
+    memcpy(sl->buf, img.bytes.data(), bytes);
+    GS_HIP(hipMemcpyAsync(dev, sl->buf, bytes, hipMemcpyHostToDevice, s));
+    GS_HIP(hipEventRecord(sl->ev, s));
+    sl->pending = true;
     return GS_OK;
 }
 
@@ -517,7 +544,7 @@ gs_status exact_batch_rhs(const float *q, const float *p, const int64_t *off, in
     layout_batch(a, off, nsub, prm, GS_EXACT, GS_OP_RHS, b);
     GS_TRY(upload_tables(b.img, b.tables, stream));
     GS_TRY(launch_pack_state_rows(*b.xp, b.ex, q, p, prm.sigma, stream));
-    GS_TRY(launch_exact_items(*b.xp, b.ex, prm.sigma, true, stream));
+    GS_TRY(launch_exact_items(*b.xp, b.ex, true, stream));
     return launch_combine_rows(*b.xp, b.ex, prm.sigma, 0, dq, dp, 0.0, nullptr, stream);
 }
 
@@ -529,16 +556,16 @@ gs_status exact_batch_shoot(const float *q0, const float *p0, const int64_t *off
     layout_batch(a, off, nsub, prm, GS_EXACT, GS_OP_SHOOT, b);
     if (upload) GS_TRY(upload_tables(b.img, b.tables, stream));
     const double dt = 1.0 / prm.nt;
-    const size_t nb = b.xp->blocks.size();
+    const size_t nb = (size_t)plan_block_count(*b.xp);
     GS_TRY(launch_pack_state_rows(*b.xp, b.ex, q0, p0, prm.sigma, stream));
     for (int t = 0; t < prm.nt; ++t) {
-        GS_TRY(launch_exact_items(*b.xp, b.ex, prm.sigma, true, stream));
+        GS_TRY(launch_exact_items(*b.xp, b.ex, true, stream));
         GS_TRY(launch_combine_rows(*b.xp, b.ex, prm.sigma, 1, nullptr, nullptr, dt,
                                    H ? b.ex.Hpart + (size_t)t * nb : nullptr, stream));
     }
     if (H) {
         // energy of the final state: one velocity-only pass
-        GS_TRY(launch_exact_items(*b.xp, b.ex, prm.sigma, false, stream));
+        GS_TRY(launch_exact_items(*b.xp, b.ex, false, stream));
         GS_TRY(launch_combine_rows(*b.xp, b.ex, prm.sigma, 1, nullptr, nullptr, 0.0,
                                    b.ex.Hpart + (size_t)prm.nt * nb, stream));
         GS_TRY(launch_reduce_h_seg(b.ex.Hpart, (int64_t)nb, b.ex.bseg, nsub, prm.nt + 1, H,
@@ -701,29 +728,20 @@ gs_status gs_rhs_exact(const float *q, const float *p, int64_t n, const gs_param
     gs_params pr = *prm;
     pr.flags &= ~GS_FLAG_F64;
     GS_TRY(check_ws(ws, ws_bytes, measure_bytes(n, &pr, GS_EXACT, GS_OP_RHS)));
-    if (exact_items_path(prm)) {
-        const int64_t off[2] = {0, n};
-        return exact_batch_rhs(q, p, off, 1, *prm, dq, dp, ws, ws_bytes, stream);
-    }
-    Arena a{static_cast<char *>(ws), kHeader, ws_bytes};
-    ExactPlan pl = plan_exact(n, n, true);
-    ExactBufs b;
-    carve_exact(a, pl, b);
-    const int64_t npad = pl.nsrc > pl.ntgt ? pl.nsrc : pl.ntgt;
-    GS_TRY(launch_pack(q, p, n, npad, b.Q, b.P, stream));
-    GS_TRY(launch_exact_pairs(pl, b.Q, b.P, b.Q, b.P, prm->sigma, true, b.part, stream));
-    return launch_combine_rhs(pl, b.part, prm->sigma, dq, dp, stream);
+    const int64_t off[2] = {0, n};
+    return exact_batch_rhs(q, p, off, 1, pr, dq, dp, ws, ws_bytes, stream);
 }
 
 gs_status gs_rhs_exact_f64(const double *q, const double *p, int64_t n, const gs_params *prm,
                            double *dq, double *dp, void *ws, size_t ws_bytes,
                            hipStream_t stream) {
-    (void)ws;
-    (void)ws_bytes;
     GS_TRY(check_n(n));
     GS_TRY(check_params(prm, false, false));
     if (n == 0) return GS_OK;
     GS_TRY(check_ptrs({q, p, dq, dp}));
+    gs_params pr = *prm;
+    pr.flags |= GS_FLAG_F64;
+    GS_TRY(check_ws(ws, ws_bytes, measure_bytes(n, &pr, GS_EXACT, GS_OP_RHS)));
     return launch_exact_f64(q, p, n, prm->sigma, true, dq, dp, stream);
 }
 
@@ -739,59 +757,20 @@ gs_status gs_shoot(const float *q0, const float *p0, int64_t n, const gs_params 
     if (n == 0) return GS_OK;
     GS_TRY(check_ptrs({q0, p0, q1, p1}));
     gs_params pr = *prm;
-    pr.flags &= ~GS_FLAG_F64;
+    pr.flags &= ~(GS_FLAG_F64 | GS_FLAG_GRAPH);
     GS_TRY(check_ws(ws, ws_bytes, measure_bytes(n, &pr, method, GS_OP_SHOOT)));
-    if (prm->flags & GS_FLAG_GRAPH) {
-        const int64_t off[2] = {0, n};
-        const bool items = method == GS_EXACT && exact_items_path(prm);
-        if (items) {  // the tables, outside the graph
-            Arena a{static_cast<char *>(ws), kHeader, ws_bytes};
-            Batch b;
-            layout_batch(a, off, 1, *prm, GS_EXACT, GS_OP_SHOOT, b);
-            GS_TRY(upload_tables(b.img, b.tables, stream));
-        }
-        gs_params body = *prm;
-        body.flags &= ~GS_FLAG_GRAPH;
-        return run_graphed(graph_key(1, {q0, p0, q1, p1, H, ws}, {n, method, (int64_t)ws_bytes},
-                                     *prm),
-                           stream, [&](hipStream_t s) -> gs_status {
-                               if (items)
-                                   return exact_batch_shoot(q0, p0, off, 1, body, q1, p1, H, ws,
-                                                            ws_bytes, s, false);
-                               return gs_shoot(q0, p0, n, &body, method, q1, p1, H, ws,
-                                               ws_bytes, s);
-                           });
-    }
-    Arena a{static_cast<char *>(ws), kHeader, ws_bytes};
-    const double dt = 1.0 / prm->nt;
-    if (method == GS_BH) {
-        ShootBhBufs b = layout_shoot_bh(a, n, prm->nt);
-        return shoot_bh(q0, p0, n, *prm, q1, p1, H, b, static_cast<char *>(ws), stream);
-    }
-    if (exact_items_path(prm)) {
-        const int64_t off[2] = {0, n};
-        return exact_batch_shoot(q0, p0, off, 1, *prm, q1, p1, H, ws, ws_bytes, stream);
-    }
-    ShootExactBufs b = layout_shoot_exact(a, n, prm->nt);
-    ExactPlan pl = plan_exact(n, n, true);
-    const int nblk = combine_blocks(n);
-    const int64_t npad = pl.nsrc > pl.ntgt ? pl.nsrc : pl.ntgt;
-    GS_TRY(launch_pack_state(q0, p0, n, npad, b.Sq, b.Sp, b.ex.Q, b.ex.P, stream));
-    for (int t = 0; t < prm->nt; ++t) {
-        GS_TRY(launch_exact_pairs(pl, b.ex.Q, b.ex.P, b.ex.Q, b.ex.P, prm->sigma, true,
-                                  b.ex.part, stream));
-        GS_TRY(launch_combine_euler(pl, b.ex.part, prm->sigma, dt, b.Sq, b.Sp, b.ex.Q, b.ex.P,
-                                    H ? b.Hpart + (size_t)t * nblk : nullptr, stream));
-    }
-    if (H) {
-        // energy of the final state: one velocity-only pass
-        GS_TRY(launch_exact_pairs(pl, b.ex.Q, b.ex.P, b.ex.Q, b.ex.P, prm->sigma, false,
-                                  b.ex.part, stream));
-        GS_TRY(launch_combine_euler(pl, b.ex.part, prm->sigma, 0.0, b.Sq, b.Sp, b.ex.Q, b.ex.P,
-                                    b.Hpart + (size_t)prm->nt * nblk, stream));
-        GS_TRY(launch_reduce_h(b.Hpart, nblk, prm->nt + 1, H, stream));
-    }
-    return launch_unpack_state(b.Sq, b.Sp, n, q1, p1, stream);
+    const int64_t off[2] = {0, n};
+    // one set: no host tables, so the whole call is its kernel sequence
+    auto body = [&](hipStream_t s) -> gs_status {
+        if (method == GS_EXACT)
+            return exact_batch_shoot(q0, p0, off, 1, pr, q1, p1, H, ws, ws_bytes, s, false);
+        Arena a{static_cast<char *>(ws), kHeader, ws_bytes};
+        ShootBhBufs b = layout_shoot_bh(a, n, pr.nt);
+        return shoot_bh(q0, p0, n, pr, q1, p1, H, b, static_cast<char *>(ws), s);
+    };
+    if (!(prm->flags & GS_FLAG_GRAPH)) return body(stream);
+    return run_graphed(graph_key(1, {q0, p0, q1, p1, H, ws}, {n, method, (int64_t)ws_bytes}, *prm),
+                       stream, body);
 }
 
 gs_status gs_shoot_f64(const double *q0, const double *p0, int64_t n, const gs_params *prm,
@@ -900,6 +879,11 @@ gs_status gs_shoot_adjoint_batch(const float *q0, const float *p0, const float *
                               objective, grad_p0, ws, ws_bytes, stream);
 }
 
+size_t gs_field_workspace_bytes(int64_t m, int64_t n, const gs_params *prm) {
+    if (check_n(m) != GS_OK || check_n(n) != GS_OK || !prm) return 0;
+    return measure_field(m, n, *prm);
+}
+
 gs_status gs_field(const float *x, int64_t m, const float *q, const float *p, int64_t n,
                    const gs_params *prm, float *v, void *ws, size_t ws_bytes,
                    hipStream_t stream) {
@@ -913,28 +897,14 @@ gs_status gs_field(const float *x, int64_t m, const float *q, const float *p, in
         return GS_ERR_INVALID;
     }
     GS_TRY(check_ptrs({q, p}));
-    const int64_t big = m > n ? m : n;
-    gs_params pr = *prm;
-    pr.flags &= ~GS_FLAG_F64;
-    GS_TRY(check_ws(ws, ws_bytes, measure_bytes(big, &pr, GS_EXACT, GS_OP_FIELD)));
+    GS_TRY(check_ws(ws, ws_bytes, measure_field(m, n, *prm)));
     Arena a{static_cast<char *>(ws), kHeader, ws_bytes};
-    ExactBufs b;
-    float4 *X = layout_field(a, big, b);
-    // the partial sums were sized for max(m, n) x max(m, n); fewer targets may
-    // ask for more source splits, so cap the splits to that capacity
-    const ExactPlan pb = plan_exact(big, big);
-    ExactPlan pl = plan_exact(m, n);
-    const int64_t cap = (int64_t)pb.splits * pb.ntgt;
-    if ((int64_t)pl.splits * pl.ntgt > cap) {
-        const int64_t smax = cap / pl.ntgt;
-        pl.chunk = round_up((pl.nsrc + smax - 1) / smax, pl.chunk_quantum);
-        pl.splits = (int)((pl.nsrc + pl.chunk - 1) / pl.chunk);
-    }
-    const int64_t spad = pl.nsrc;
-    GS_TRY(launch_pack(q, p, n, spad, b.Q, b.P, stream));
-    GS_TRY(launch_pack_pos(x, m, pl.ntgt, X, stream));
-    GS_TRY(launch_exact_pairs(pl, X, nullptr, b.Q, b.P, prm->sigma, false, b.part, stream));
-    return launch_combine_rhs(pl, b.part, prm->sigma, v, nullptr, stream);
+    Field f;
+    layout_field(a, m, n, *prm, f);
+    GS_TRY(upload_tables(f.img, f.tables, stream));
+    GS_TRY(launch_pack_field(f.plan, f.ex, x, q, p, prm->sigma, stream));
+    GS_TRY(launch_exact_items(f.plan, f.ex, false, stream));
+    return launch_combine_rows(f.plan, f.ex, prm->sigma, 0, v, nullptr, 0.0, nullptr, stream);
 }
 
 size_t gs_batch_workspace_bytes(const int64_t *offsets, int32_t nsub, const gs_params *prm,
@@ -1107,9 +1077,17 @@ gs_status gs_get_status(const void *ws, hipStream_t stream) {
     GS_HIP(hipStreamSynchronize(stream));
     int32_t status = 0;
     GS_HIP(hipMemcpy(&status, ws, sizeof(status), hipMemcpyDeviceToHost));
-    if (status != 0) {
+    if (status == kStatusNonfinite) {
         set_error("non-finite coordinates met while building the octree");
         return GS_ERR_NONFINITE;
+    }
+    if (status == kStatusOverflow) {
+        set_error("a Barnes-Hut traversal stack overflowed (its results are incomplete)");
+        return GS_ERR_OVERFLOW;
+    }
+    if (status != 0) {
+        set_error("unknown device status %d", (int)status);
+        return GS_ERR_HIP;
     }
     return GS_OK;
 }

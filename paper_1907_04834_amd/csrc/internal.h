@@ -79,54 +79,144 @@ constexpr size_t kCountersOffset = 256;
 constexpr size_t kWsHeader = kCountersOffset + (size_t)kCounterSlots * GS_BH_COUNTERS * 8;
 constexpr int kBlock = 256;     // threads per block for O(N) kernels
 
+// Values of the device status word (workspace offset 0).
+constexpr int kStatusNonfinite = 1;  // a coordinate was NaN or infinite (tree path)
+constexpr int kStatusOverflow = 2;   // a traversal stack overflowed (cannot happen for
+                                     // trees of at most 22 levels)
+
 inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
-// Source split of the exact all-pairs kernel: number of source ranges that
-// the targets' sums are split over so that a launch has enough waves.
-struct ExactPlan {
-    int64_t n;        // real points
-    int64_t nsrc;     // padded source count (multiple of kTile)
-    int64_t ntgt;     // padded target count
-    int splits;       // S
-    int64_t chunk;    // sources per split (multiple of kTile)
-    int tpl;          // targets per lane (VALU kernel)
-    int64_t chunk_quantum;  // chunks are multiples of this many sources
-    bool mfma;        // (v, a) sums on the matrix cores
-};
-constexpr int kMfmaGroups = 4;  // groups of 16 targets per wave (MFMA kernel)
-constexpr int kExactTplDefault = 1;  // targets per lane (VALU kernel, measured best)
-constexpr int64_t kSplitBlocks = 24576;  // blocks per exact launch the split count aims at
-constexpr int kXcds = 8;                 // MI355X: workgroups are dealt to 8 XCDs in turn
-ExactPlan plan_exact(int64_t n_targets, int64_t n_sources, bool mfma = false);
+// ---------------------------------------------------------------- exact path
+// Work items of the exact FP32 kernel.  One work item is one block of
+// kItemGroups x kItemSplit waves: kItemGroups groups of 64 consecutive target
+// rows, each against one chunk of source rows split among kItemSplit waves
+// whose sums are added in LDS, so the chunk count (the FP64 partial slots per
+// target) is kItemSplit times smaller than with one wave per chunk.  The
+// defaults are the measured best; other shapes are compiled only by a tuning
+// build.
+#ifndef GS_ITEM_GROUPS
+#define GS_ITEM_GROUPS 1
+#endif
+#ifndef GS_ITEM_SPLIT
+#define GS_ITEM_SPLIT 4
+#endif
+constexpr int kItemGroups = GS_ITEM_GROUPS;
+constexpr int kItemSplit = GS_ITEM_SPLIT;
+constexpr int kItemRows = 64 * kItemGroups;                  // target rows per item
+constexpr int kItemThreads = kItemRows * kItemSplit;
+constexpr int kMinWaveSources = 256;    // sources per wave of an item, at least
+constexpr int64_t kItemsDefault = 24576;  // work items per launch the chunk length aims at
+constexpr int kXcds = 8;                // MI355X: workgroups are dealt to 8 XCDs in turn
+static_assert(kItemThreads <= 1024, "work item too large");
 
-// Buffers of one exact FP32 RHS evaluation.
-struct ExactBufs {
-    float4 *Q;        // [nsrc] x, y, z, 0
-    float4 *P;        // [nsrc] px, py, pz, 0
-    double *part;     // [S][6][ntgt]
+// Work items of one point set without tables: the ones plan_exact_batch
+// gives for offsets {0, n}, computed from this geometry.
+struct ItemGeom {
+    int n;     // points
+    int ng;    // target groups of kItemRows rows
+    int nch;   // source chunks (partial slots)
+    int csz;   // sources per chunk (multiple of kTile)
+    int sp;    // sources padded to kTile
+    int qlen;  // items in the queue of XCD 0 (the longest)
 };
-void carve_exact(Arena &a, const ExactPlan &pl, ExactBufs &b);
+// Row blocks of 256 rows of one point set without tables.
+struct RowGeom {
+    int n;      // points
+    int slots;  // partial slots
+};
 
-// ---------------------------------------------------------------- launchers
-// exact.hip
-gs_status launch_pack(const float *q, const float *p, int64_t n, int64_t npad, float4 *Q,
-                      float4 *P, hipStream_t s);
-gs_status launch_pack_pos(const float *x, int64_t m, int64_t npad, float4 *X, hipStream_t s);
-gs_status launch_exact_pairs(const ExactPlan &pl, const float4 *Qt, const float4 *Pt,
-                             const float4 *Qs, const float4 *Ps, double sigma, bool with_a,
-                             double *part, hipStream_t s);
-// Sums the split partials of target i and writes (v, a) as float [n][3].
-gs_status launch_combine_rhs(const ExactPlan &pl, const double *part, double sigma,
-                             float *dq, float *dp, hipStream_t s);
-// Sums the partials, adds p_i . v_i of each block into Hpart (nullable), and,
-// if dt > 0, advances the FP64 state (Sq += dt v, Sp += dt a) and refreshes
-// its FP32 copies Q, P.
-gs_status launch_combine_euler(const ExactPlan &pl, const double *part, double sigma,
-                               double dt, double *Sq, double *Sp, float4 *Q, float4 *P,
-                               double *Hpart, hipStream_t s);
-// FP64 state from float [n][3] inputs, plus its FP32 packed copies.
-gs_status launch_pack_state(const float *q, const float *p, int64_t n, int64_t npad, double *Sq,
-                            double *Sp, float4 *Q, float4 *P, hipStream_t s);
+// Work item b: (first target row, source rows [j0, j1), slot); slot -1 is a
+// padding item.  Source chunk c of a single set has home XCD c % 8 (equal
+// chunks, largest first, least-loaded XCD); XCD x's queue holds its chunks'
+// items chunk by chunk, and item b comes from the queue of XCD b % 8.
+__device__ inline int4 work_item(const int4 *__restrict__ items, const ItemGeom &g, int64_t b) {
+    if (items) return items[b];
+    const int x = (int)(b % kXcds), k = (int)(b / kXcds);
+    if (x >= g.nch) return make_int4(0, 0, 0, -1);
+    const int nq = (g.nch - x + kXcds - 1) / kXcds;
+    if (k >= nq * g.ng) return make_int4(0, 0, 0, -1);
+    const int c = x + kXcds * (k / g.ng), grp = k % g.ng;
+    const int j0 = c * g.csz;
+    const int j1 = j0 + g.csz < g.sp ? j0 + g.csz : g.sp;
+    return make_int4(grp * kItemRows, j0, j1, c);
+}
+// Row block b: (first real point, real rows in it, set, partial slots).
+__device__ inline int4 row_block(const int4 *__restrict__ blk, const RowGeom &r, int64_t b) {
+    if (blk) return blk[b];
+    const int first = (int)(256 * b);
+    const int cnt = r.n - first < 256 ? r.n - first : 256;
+    return make_int4(first, cnt, 0, r.slots);
+}
+
+// Evaluation plan of independent point sets (subjects) stored one after the
+// other ([offsets[s], offsets[s+1]) is set s), or of the velocity field (m
+// targets, n sources).  Rows are padded per set to whole blocks of 256.
+struct ExactBatchPlan {
+    int nsub = 0;
+    int64_t ntot = 0;             // real target points
+    int64_t npad = 0;             // padded target rows
+    int64_t nsrc = 0;             // real source points (ntot except for the field)
+    int64_t spad = 0;             // padded source rows
+    int max_chunks = 1;           // partial slots per row
+    bool single = false;          // one set, no tables (geom / rows)
+    bool field = false;           // targets are not the sources
+    ItemGeom geom{};
+    RowGeom rows{};
+    int64_t nitems = 0, nblocks = 0;   // single: grid sizes
+    std::vector<int4> items;      // (first target row, j0, j1, slot); slot -1: padding
+    std::vector<int4> blocks;     // per 256 target rows: (first real point, count, set, slots)
+    std::vector<int> bseg;        // [nsub + 1] row-block range of each set
+    std::vector<int4> sblocks;    // field: per 256 source rows
+    std::vector<int> sbseg;       // field: {0, source blocks}
+};
+// `items`: work items a launch aims at (0: the default).
+ExactBatchPlan plan_exact_batch(const int64_t *offsets, int nsub, int64_t items = 0);
+ExactBatchPlan plan_exact_single(int64_t n, int64_t items = 0);
+ExactBatchPlan plan_exact_field(int64_t m, int64_t n, int64_t items = 0);
+ItemGeom item_geom(int64_t n, int64_t items);
+RowGeom row_geom(int64_t n, int slots);
+int64_t plan_item_count(const ExactBatchPlan &pl);
+int64_t plan_block_count(const ExactBatchPlan &pl);
+struct ExactBatchBufs {
+    float4 *Q, *P;                // [spad] packed FP32 sources k (q - c), p; zero padding
+    float4 *X;                    // target rows (Q itself except for the field)
+    double *part;                 // [max_chunks][6][npad]
+    double *Sq, *Sp;              // [ntot][3] FP64 state
+    double *Hpart;                // [nt + 1][blocks]
+    float *bpart;                 // [source blocks][6] boxes of the row blocks
+    double *cen;                  // [nsub][3] FP64 centres of the sets' boxes
+    const int4 *items = nullptr, *blk = nullptr;   // device tables (null: single set)
+    const int *bseg = nullptr;
+    const int4 *sblk = nullptr;   // field: source row blocks
+    const int *sbseg = nullptr;
+};
+// Carves the state and partial buffers (not the tables).
+void carve_exact_batch(Arena &a, const ExactBatchPlan &pl, int nt, ExactBatchBufs &b);
+void carve_exact_field(Arena &a, const ExactBatchPlan &pl, ExactBatchBufs &b);
+// Centres of the sets' boxes (of the field's sources) into b.cen.
+gs_status launch_set_centres(const ExactBatchPlan &pl, const ExactBatchBufs &b, const float *q,
+                             hipStream_t s);
+// Set centres, the FP64 state and its FP32 copies (positions k (q - c)).
+gs_status launch_pack_state_rows(const ExactBatchPlan &pl, const ExactBatchBufs &b,
+                                 const float *q, const float *p, double sigma, hipStream_t s);
+// Field: source centre, packed sources and targets.
+gs_status launch_pack_field(const ExactBatchPlan &pl, const ExactBatchBufs &b, const float *x,
+                            const float *q, const float *p, double sigma, hipStream_t s);
+gs_status launch_exact_items(const ExactBatchPlan &pl, const ExactBatchBufs &b, bool with_a,
+                             hipStream_t s);
+// mode 0: (dq, dp) = (v, a) (dp nullable); mode 1: energy partials into Hpart
+// (nullable), the velocity into vout (FP64 [ntot][3], nullable) and, if
+// dt > 0, the Euler step of the FP64 state and its packed copies.
+gs_status launch_combine_rows(const ExactBatchPlan &pl, const ExactBatchBufs &b, double sigma,
+                              int mode, float *dq, float *dp, double dt, double *Hpart,
+                              hipStream_t s, double *vout = nullptr);
+// k = sqrt(log2(e) / (2 sigma^2)), the factor of the stored positions.
+double position_scale(double sigma);
+// Packs FP64 [ntot][3] arrays (a, b) into rows (sa (a - c), sb b) as float4
+// (zero padding); c is the set's centre when `centre`, else 0.
+gs_status launch_pack_rows64(const ExactBatchPlan &pl, const ExactBatchBufs &b, const double *a,
+                             const double *bb, double sa, float4 *A, float4 *B, hipStream_t s,
+                             double sb, bool centre);
 gs_status launch_unpack_state(const double *Sq, const double *Sp, int64_t n, float *q, float *p,
                               hipStream_t s);
 int combine_blocks(int64_t n);
@@ -136,54 +226,6 @@ gs_status launch_reduce_h(const double *Hpart, int nblk, int count, double *H, h
 // [seg[set], seg[set + 1]) (seg: device int [nsub + 1]; null = one set).
 gs_status launch_reduce_h_seg(const double *Hpart, int64_t stride, const int *seg, int nsub,
                               int count, double *H, hipStream_t s);
-
-// ---------------------------------------------------------------- batched sets
-// Exact evaluation of independent point sets (subjects) stored one after the
-// other ([offsets[s], offsets[s+1]) is set s).  Rows are padded per set to
-// whole blocks of 256 targets; a work item is one such block against one
-// source chunk of its own set.  Each source chunk has a home XCD; items run
-// on their chunk's XCD, largest first.
-struct ExactBatchPlan {
-    int nsub;
-    int64_t ntot;                 // real points
-    int64_t npad;                 // padded rows
-    int max_chunks;               // partial slots per row
-    std::vector<int4> items;      // (first target row, j0, j1, slot); slot -1: padding
-    std::vector<int4> blocks;     // per 256-row block: (first real point, count, set, slots)
-    std::vector<int> bseg;        // [nsub + 1] row-block range of each set
-};
-// `items`: work items a launch aims at (0: the default, or the
-// GS_EXACT_ITEM_BLOCKS environment override).
-ExactBatchPlan plan_exact_batch(const int64_t *offsets, int nsub, int64_t items = 0);
-struct ExactBatchBufs {
-    float4 *Q, *P;                // [npad] packed FP32 state (scaled positions), zero padding
-    double *part;                 // [max_chunks][6][npad]
-    double *Sq, *Sp;              // [ntot][3] FP64 state
-    double *Hpart;                // [nt + 1][blocks]
-    const int4 *items, *blk;      // device copies of the plan's tables (set by the caller)
-    const int *bseg;
-};
-// Carves the state and partial buffers (not the tables).
-void carve_exact_batch(Arena &a, const ExactBatchPlan &pl, int nt, ExactBatchBufs &b);
-// Packs the FP64 state and its FP32 copies (positions scaled by
-// sqrt(log2(e) / (2 sigma^2)), zero padding).
-gs_status launch_pack_state_rows(const ExactBatchPlan &pl, const ExactBatchBufs &b,
-                                 const float *q, const float *p, double sigma, hipStream_t s);
-gs_status launch_exact_items(const ExactBatchPlan &pl, const ExactBatchBufs &b, double sigma,
-                             bool with_a, hipStream_t s);
-// mode 0: (dq, dp) = (v, a); mode 1: energy partials into Hpart (nullable),
-// the velocity into vout (FP64 [ntot][3], nullable) and, if dt > 0, the
-// Euler step of the FP64 state and its packed copies.
-gs_status launch_combine_rows(const ExactBatchPlan &pl, const ExactBatchBufs &b, double sigma,
-                              int mode, float *dq, float *dp, double dt, double *Hpart,
-                              hipStream_t s, double *vout = nullptr);
-// k = sqrt(log2(e) / (2 sigma^2)), the factor of the stored positions.
-double position_scale(double sigma);
-// Packs FP64 [ntot][3] arrays (a, b) into rows (sa a, sb b) as float4 (zero
-// padding), with the row blocks `blk` of the plan (device table).
-gs_status launch_pack_rows64(const ExactBatchPlan &pl, const int4 *blk, const double *a,
-                             const double *b, double sa, float4 *A, float4 *B, hipStream_t s,
-                             double sb = 1.0);
 
 // FP64 exact path.
 gs_status launch_exact_f64(const double *q, const double *p, int64_t n, double sigma,

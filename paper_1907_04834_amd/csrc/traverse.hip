@@ -13,10 +13,13 @@
 //     opened it, so a lane that approximated a node never sees its subtree.
 // The node records of a block of siblings are staged in LDS with one vector
 // load and read back as broadcasts; the decisions are taken in FP64 from the
-// FP32 target position, the node's exact FP32 box and FP64 centre, as in the
-// definition; the contributions are FP32 with per-leaf sums accumulated in
-// FP64.  Leaf points are streamed with wave-uniform (scalar) loads; a leaf's
-// sums are added only by the lanes in its mask.
+// FP32 target position as given, the node's exact FP32 box and FP64 centre,
+// as in the definition.  The contributions are FP32 with per-leaf sums
+// accumulated in FP64: exact pairs use the positions relative to the set's
+// box centre (Qc), and a monopole's offset x - C_k is taken in FP64 and
+// rounded once, so no difference loses precision to the set's distance from
+// the origin.  Leaf points are streamed with wave-uniform (scalar) loads; a
+// leaf's sums are added only by the lanes in its mask.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -250,8 +253,8 @@ __device__ __forceinline__ void leaf_stream(const float4 *__restrict__ Qs,
 // Phase 1: decisions, monopoles and the group's list of leaves.
 template <bool WITH_A>
 __global__ __launch_bounds__(256) void k_bh_decide(
-    const BhNode *__restrict__ nodes, const float4 *__restrict__ Qs, const float4 *__restrict__ Ps,
-    int64_t n, const GroupDesc *__restrict__ gtab, int64_t groups, TravSplit split, BhParams bp,
+    const BhNode *__restrict__ nodes, const float4 *__restrict__ Qs,
+    const float4 *__restrict__ Qc, const float4 *__restrict__ Ps, int64_t n, const GroupDesc *__restrict__ gtab, int64_t groups, TravSplit split, BhParams bp,
     LeafEntry *__restrict__ list, int *__restrict__ list_n, double *__restrict__ part,
     u64 *__restrict__ counters, const TreeTotals *__restrict__ totals, int *__restrict__ status) {
     __shared__ DecideLds lds_all[4];
@@ -265,9 +268,9 @@ __global__ __launch_bounds__(256) void k_bh_decide(
     const GroupDesc gd = group_desc(gtab, grp, n);
     const int64_t t = (int64_t)gd.first + lane;
     const bool active = lane < gd.count;
-    const float4 xq = active ? Qs[t] : make_float4(0.f, 0.f, 0.f, 0.f);
+    const float4 xa = active ? Qs[t] : make_float4(0.f, 0.f, 0.f, 0.f);
     const float4 xp = active ? Ps[t] : make_float4(0.f, 0.f, 0.f, 0.f);
-    const double xd = xq.x, yd = xq.y, zd = xq.z;
+    const double xd = xa.x, yd = xa.y, zd = xa.z;
     LeafEntry *mylist = list + grp * kListPerGroup + (int64_t)sub * split.segcap;
 
     double V[3] = {0, 0, 0}, A[3] = {0, 0, 0};
@@ -317,8 +320,8 @@ __global__ __launch_bounds__(256) void k_bh_decide(
                     need = true;
                 } else if (rec) {
                     // n_k virtual points at C_k, momentum P_k / n_k each
-                    const float dx = xq.x - (float)nd.cx, dy = xq.y - (float)nd.cy,
-                                dz = xq.z - (float)nd.cz;
+                    const float dx = (float)(xd - nd.cx), dy = (float)(yd - nd.cy),
+                                dz = (float)(zd - nd.cz);
                     const float g =
                         __builtin_amdgcn_exp2f((dx * dx + dy * dy + dz * dz) * bp.negc);
                     mv[0] += g * nd.px;
@@ -353,12 +356,13 @@ __global__ __launch_bounds__(256) void k_bh_decide(
                 } else {
                     // list full: sum this leaf here
                     w_steps += (unsigned)ncount;
-                    leaf_direct<WITH_A>(Qs, Ps, nfirst, ncount, need, xq, xp, bp.negc, V, A);
+                    const float4 xc = active ? Qc[t] : make_float4(0.f, 0.f, 0.f, 0.f);
+                    leaf_direct<WITH_A>(Qc, Ps, nfirst, ncount, need, xc, xp, bp.negc, V, A);
                 }
             } else {
                 if (sp >= kBlockStack) {
                     // cannot happen for trees of at most 22 levels; stop safely
-                    if (lane == 0 && status) *status = 2;
+                    if (lane == 0 && status) *status = kStatusOverflow;
                     sp = -1;
                     break;
                 }
@@ -412,9 +416,10 @@ __global__ __launch_bounds__(256) void k_bh_decide(
 }
 
 
-// Phase 2: one wave per (group, chunk of its list entries).
+// Phase 2: one wave per (group, chunk of its list entries), on the positions
+// relative to the set's box centre.
 template <bool WITH_A>
-__global__ __launch_bounds__(256) void k_bh_leaves(const float4 *__restrict__ Qs,
+__global__ __launch_bounds__(256) void k_bh_leaves(const float4 *__restrict__ Qc,
                                                    const float4 *__restrict__ Ps, int64_t n,
                                                    const GroupDesc *__restrict__ gtab,
                                                    int64_t groups, TravSplit split, float negc,
@@ -433,11 +438,11 @@ __global__ __launch_bounds__(256) void k_bh_leaves(const float4 *__restrict__ Qs
     const GroupDesc gd = group_desc(gtab, grp, n);
     const int64_t t = (int64_t)gd.first + lane;
     const bool active = lane < gd.count;
-    const float4 xq = active ? Qs[t] : make_float4(0.f, 0.f, 0.f, 0.f);
+    const float4 xq = active ? Qc[t] : make_float4(0.f, 0.f, 0.f, 0.f);
     const float4 xp = active ? Ps[t] : make_float4(0.f, 0.f, 0.f, 0.f);
     double V[3] = {0, 0, 0}, A[3] = {0, 0, 0};
     unsigned steps = 0;
-    leaf_stream<WITH_A>(Qs, Ps, list, list_n, grp, split, v0, v1, lane, xq, xp, negc, V, A,
+    leaf_stream<WITH_A>(Qc, Ps, list, list_n, grp, split, v0, v1, lane, xq, xp, negc, V, A,
                         steps);
     write_part(part, split.nsub + chunk, npad, grp * 64 + lane, V, A);
     if (lane == 0 && counters) {
@@ -454,9 +459,11 @@ template <bool WITH_A>
 __global__ __launch_bounds__(256) void k_bh_combine(
     const double *__restrict__ part, const int *__restrict__ list_n,
     const GroupDesc *__restrict__ gtab, int64_t groups, TravSplit split,
-    const unsigned *__restrict__ perm, int64_t n, double inv_s2, int mode, float *__restrict__ dq, float *__restrict__ dp,
-    double *__restrict__ Sq, double *__restrict__ Sp, float *__restrict__ q32,
-    float *__restrict__ p32, double dt, double *__restrict__ Hpart, double *__restrict__ v64) {
+    const unsigned *__restrict__ perm, int64_t n, double inv_s2, int mode,
+    float *__restrict__ dq, float *__restrict__ dp, double *__restrict__ Sq,
+    double *__restrict__ Sp, float *__restrict__ q32, float *__restrict__ p32,
+    const double *__restrict__ c0, double dt, double *__restrict__ Hpart,
+    double *__restrict__ v64) {
     const int lane = threadIdx.x & 63;
     const int64_t grp = (int64_t)blockIdx.x * 4 + wave_in_block();
     if (grp >= groups) return;  // wave-uniform; no block barrier below
@@ -494,13 +501,14 @@ __global__ __launch_bounds__(256) void k_bh_combine(
             }
             e = p[0] * V[0] + p[1] * V[1] + p[2] * V[2];
             if (mode == MODE_SHOOT) {
+                const double *cs = c0 + 3 * gd.sub;  // the shooting's frame of this set
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     q[c] += dt * V[c];
                     p[c] += dt * (A[c] * inv_s2);
                     Sq[3 * i + c] = q[c];
                     Sp[3 * i + c] = p[c];
-                    q32[3 * i + c] = (float)q[c];
+                    q32[3 * i + c] = (float)(q[c] - cs[c]);
                     p32[3 * i + c] = (float)p[c];
                 }
             }
@@ -511,18 +519,6 @@ __global__ __launch_bounds__(256) void k_bh_combine(
         for (int off = 32; off > 0; off >>= 1) e += __shfl_down(e, off, 64);
         if (lane == 0) Hpart[grp] = e;
     }
-}
-
-__global__ void k_state_init(const float *__restrict__ q, const float *__restrict__ p, int64_t n3,
-                             double *__restrict__ Sq, double *__restrict__ Sp,
-                             float *__restrict__ q32, float *__restrict__ p32) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n3) return;
-    const float a = q[i], b = p[i];
-    Sq[i] = a;
-    Sp[i] = b;
-    q32[i] = a;
-    p32[i] = b;
 }
 
 __global__ void k_state_out(const double *__restrict__ Sq, const double *__restrict__ Sp,
@@ -603,14 +599,14 @@ gs_status launch_bh_traverse(const TreeBufs &t, const BhParams &bp, bool with_a,
     timing_begin(kind, s);
 #define GS_PHASES(A)                                                                         \
     do {                                                                                     \
-        hipLaunchKernelGGL(k_bh_decide<A>, g1, dim3(256), 0, s, t.nodes, t.Qs, t.Ps, t.n,     \
-                           t.gtab, groups, split, bp, list, t.list_n, t.part, counters,        \
+        hipLaunchKernelGGL(k_bh_decide<A>, g1, dim3(256), 0, s, t.nodes, t.Qs, t.Qc, t.Ps,    \
+                           t.n, t.gtab, groups, split, bp, list, t.list_n, t.part, counters,   \
                            t.totals, status);                                               \
-        hipLaunchKernelGGL(k_bh_leaves<A>, g2, dim3(256), 0, s, t.Qs, t.Ps, t.n, t.gtab,      \
+        hipLaunchKernelGGL(k_bh_leaves<A>, g2, dim3(256), 0, s, t.Qc, t.Ps, t.n, t.gtab,      \
                            groups, split, bp.negc, list, t.list_n, t.part, counters);          \
         hipLaunchKernelGGL(k_bh_combine<A>, g3, dim3(256), 0, s, t.part, t.list_n, t.gtab,    \
                            groups, split, t.perm, t.n, bp.inv_s2, mode, o.dq, o.dp, o.Sq, o.Sp, \
-                           o.q32, o.p32, o.dt, o.Hpart, o.v64);                             \
+                           o.q32, o.p32, o.c0, o.dt, o.Hpart, o.v64);                       \
     } while (0)
     if (with_a)
         GS_PHASES(true);
@@ -628,6 +624,7 @@ gs_status launch_bh_traverse(const TreeBufs &t, const BhParams &bp, bool with_a,
 }
 
 static void carve_state(Arena &a, int64_t n, int nt, ShootBhBufs &b) {
+    b.c0 = a.take<double>(3 * (size_t)b.tree.nsub);
     b.Sq = a.take<double>(3 * n);
     b.Sp = a.take<double>(3 * n);
     b.q32 = a.take<float>(3 * n);
@@ -669,9 +666,11 @@ gs_status shoot_bh(const float *q0, const float *p0, int64_t n, const gs_params 
     int *status = reinterpret_cast<int *>(ws + kStatusOffset);
     u64 *counters = reinterpret_cast<u64 *>(ws + kCountersOffset);
     hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(256), 0, s, status, counters);
-    hipLaunchKernelGGL(k_state_init, dim3(nblk(3 * n)), dim3(kBlock), 0, s, q0, p0, 3 * n, b.Sq,
-                       b.Sp, b.q32, b.p32);
-    GS_LAUNCH_CHECK("state_init");
+    // the FP32 copies that every step's tree and pairs are built from are kept
+    // relative to the box centre of q0 (fixed for the call), so their rounding
+    // does not depend on where the set lies
+    GS_TRY(tree_set_centres(q0, b.tree, b.c0, status, s));
+    GS_TRY(launch_state_init(q0, p0, b.tree, b.c0, b.Sq, b.Sp, b.q32, b.p32, s));
     const BhParams bp = make_bh_params(prm);
     const int64_t ng = b.tree.groups;
     TraverseOut o{};
@@ -679,6 +678,7 @@ gs_status shoot_bh(const float *q0, const float *p0, int64_t n, const gs_params 
     o.Sp = b.Sp;
     o.q32 = b.q32;
     o.p32 = b.p32;
+    o.c0 = b.c0;
     o.dt = 1.0 / prm.nt;
     for (int t = 0; t < prm.nt; ++t) {
         GS_TRY(build_tree(b.q32, b.p32, n, prm.leaf_cap, b.tree, status, s));

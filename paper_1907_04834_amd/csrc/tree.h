@@ -43,6 +43,7 @@ struct TreeMeta {
     float hi[3];
     double extent;      // E
     double scale;       // 2^21 / E (0 when E == 0)
+    double cen[3];      // centre (lo + hi) / 2 of the box (FP64; 0 if not finite)
     int nonfinite;      // a coordinate was NaN or +-inf
     int root_leaf;      // 1 when the root is a leaf
     int root_rank;      // internal rank of the root (if internal)
@@ -88,7 +89,8 @@ struct TreeBufs {
     const unsigned *perm;      // original index of each sorted point
     unsigned *hist;            // [256][sort_blocks] digit-major counts, then offsets
     unsigned *scan_part;       // block sums of the generic scan
-    float4 *Qs, *Ps;           // sorted points / momenta (FP32)
+    float4 *Qs, *Ps;           // sorted points / momenta (FP32, as given: the decisions)
+    float4 *Qc;                // sorted points minus their set's box centre (FP32, pairs)
     unsigned char *lvl;        // [n-1] split level of each boundary
     unsigned *flag;            // [n] internal-node flag per boundary, then rank
     unsigned *rank;            // [n] exclusive scan of flag
@@ -122,6 +124,16 @@ void carve_forest(Arena &a, int64_t n, int nsub, int64_t groups, int64_t max_set
 // finite.
 gs_status build_tree(const float *q, const float *p, int64_t n, int leaf_cap, TreeBufs &t,
                      int *status, hipStream_t s);
+// Box centre of every set of q (FP32 [n][3]) into c0 (FP64 [nsub][3]); uses
+// the tree's box buffers and sets `status` for non-finite coordinates.
+gs_status tree_set_centres(const float *q, TreeBufs &t, double *c0, int *status, hipStream_t s);
+// The FP64 state of float inputs (Sq, Sp) and its FP32 copies q32 = q - c0[set],
+// p32 = p; one thread per point.
+gs_status launch_state_init(const float *q0, const float *p0, const TreeBufs &t, const double *c0,
+                            double *Sq, double *Sp, float *q32, float *p32, hipStream_t s);
+// FP32 copies q32 = Sq - c0[set], p32 = Sp of an FP64 state.
+gs_status launch_state_to_f32(const double *Sq, const double *Sp, const TreeBufs &t,
+                              const double *c0, float *q32, float *p32, hipStream_t s);
 
 // Traversal parameters (FP64 decision thresholds as in the definition).
 struct BhParams {
@@ -177,7 +189,8 @@ __device__ __forceinline__ bool decide(const BhNode &nd, double x, double y, dou
 struct TraverseOut {
     float *dq, *dp;                    // RHS mode
     double *Sq, *Sp;                   // shooting mode
-    float *q32, *p32;
+    float *q32, *p32;                  // FP32 copies: q32 = Sq - c0[set]
+    const double *c0;                  // [nsub][3] centres of the shooting's frame
     double dt;
     double *Hpart;
     double *v64;                       // velocity only (energy pass), nullable
@@ -198,7 +211,8 @@ gs_status tree_range_sums(const float4 *A, const float4 *B, TreeBufs &t, double 
 struct ShootBhBufs {
     TreeBufs tree;
     double *Sq, *Sp;   // FP64 state [n][3]
-    float *q32, *p32;  // FP32 copies [n][3]
+    float *q32, *p32;  // FP32 copies [n][3], q32 relative to c0
+    double *c0;        // [nsub][3] box centres of q0, fixed for the call
     double *Hpart;     // [nt + 1][groups]
     const int *gseg;   // [nsub + 1] group range of each set (nullable: one set)
 };

@@ -159,6 +159,8 @@ __global__ __launch_bounds__(64) void k_bbox_final(const float *__restrict__ par
         bad = 1;
         e = 0.0;  // degenerate tree: one leaf (results are not meaningful)
     }
+    for (int c = 0; c < 3; ++c)
+        meta->cen[c] = bad ? 0.0 : 0.5 * ((double)meta->lo[c] + (double)meta->hi[c]);
     meta->extent = e;
     meta->scale = e > 0.0 ? 2097152.0 / e : 0.0;
     meta->nonfinite = bad;
@@ -444,8 +446,10 @@ __global__ __launch_bounds__(256) void k_boundaries(const u64 *__restrict__ K, i
                                                     int leaf_cap, const float *__restrict__ q,
                                                     const float *__restrict__ p,
                                                     const unsigned *__restrict__ perm,
+                                                    const TreeMeta *__restrict__ meta,
                                                     float4 *__restrict__ Qs,
                                                     float4 *__restrict__ Ps,
+                                                    float4 *__restrict__ Qc,
                                                     RangeStat *__restrict__ c0, int64_t nc0,
                                                     unsigned char *__restrict__ lvl,
                                                     unsigned *__restrict__ flag,
@@ -461,6 +465,11 @@ __global__ __launch_bounds__(256) void k_boundaries(const u64 *__restrict__ K, i
             const float4 b = make_float4(p[3 * src], p[3 * src + 1], p[3 * src + 2], 0.f);
             Qs[i] = a;
             Ps[i] = b;
+            // pair arithmetic works relative to the set's box centre (FP64 difference,
+            // rounded once), so its accuracy does not depend on where the set lies
+            const double *cen = meta[set_of(seg, nsub, i)].cen;
+            Qc[i] = make_float4((float)((double)a.x - cen[0]), (float)((double)a.y - cen[1]),
+                                (float)((double)a.z - cen[2]), 0.f);
             rs_point(r, a, b);
         }
         rs_wave_reduce(r);  // the wave's 64 positions are chunk i / kChunk
@@ -763,6 +772,42 @@ __global__ __launch_bounds__(256) void k_node_sums(const float4 *__restrict__ A,
     }
 }
 
+__global__ void k_copy_centres(const TreeMeta *__restrict__ meta, int nsub,
+                               double *__restrict__ c0) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < 3 * nsub) c0[i] = meta[i / 3].cen[i % 3];
+}
+
+__global__ void k_state_init(const float *__restrict__ q, const float *__restrict__ p, int64_t n,
+                             const long long *__restrict__ seg, int nsub,
+                             const double *__restrict__ c0, double *__restrict__ Sq,
+                             double *__restrict__ Sp, float *__restrict__ q32,
+                             float *__restrict__ p32) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double *c = c0 + 3 * set_of(seg, nsub, i);
+    for (int k = 0; k < 3; ++k) {
+        const float a = q[3 * i + k], b = p[3 * i + k];
+        Sq[3 * i + k] = a;
+        Sp[3 * i + k] = b;
+        q32[3 * i + k] = (float)((double)a - c[k]);
+        p32[3 * i + k] = b;
+    }
+}
+
+__global__ void k_state_to_f32(const double *__restrict__ Sq, const double *__restrict__ Sp,
+                               int64_t n, const long long *__restrict__ seg, int nsub,
+                               const double *__restrict__ c0, float *__restrict__ q32,
+                               float *__restrict__ p32) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double *c = c0 + 3 * set_of(seg, nsub, i);
+    for (int k = 0; k < 3; ++k) {
+        q32[3 * i + k] = (float)(Sq[3 * i + k] - c[k]);
+        p32[3 * i + k] = (float)Sp[3 * i + k];
+    }
+}
+
 gs_status scan_u32(const unsigned *in, unsigned *out, int64_t n, unsigned *part, unsigned *total,
                    hipStream_t s, unsigned *scatter = nullptr, int64_t nscatter = 0) {
     const unsigned nb = (unsigned)((n + kScanTile - 1) / kScanTile);
@@ -806,6 +851,7 @@ void carve_forest(Arena &a, int64_t n, int nsub, int64_t groups, int64_t max_set
     t.scan_part = a.take<unsigned>((scan_n + kScanTile - 1) / kScanTile + 1);
     t.Qs = a.take<float4>(m);
     t.Ps = a.take<float4>(m);
+    t.Qc = a.take<float4>(m);
     t.lvl = a.take<unsigned char>(m);
     t.flag = a.take<unsigned>(m);
     t.rank = a.take<unsigned>(m);
@@ -871,7 +917,8 @@ gs_status build_tree(const float *q, const float *p, int64_t n, int leaf_cap, Tr
     RangeStat *c0 = reinterpret_cast<RangeStat *>(t.chunk0);
     RangeStat *c1 = reinterpret_cast<RangeStat *>(t.chunk1);
     hipLaunchKernelGGL(k_boundaries, dim3(nblk(n)), dim3(256), 0, s, K, n, t.seg, nsub, leaf_cap,
-                       q, p, t.perm, t.Qs, t.Ps, c0, nc0, t.lvl, t.flag, t.bnd_s, t.bnd_e);
+                       q, p, t.perm, t.meta, t.Qs, t.Ps, t.Qc, c0, nc0, t.lvl, t.flag, t.bnd_s,
+                       t.bnd_e);
     GS_LAUNCH_CHECK("boundaries");
     unsigned *n_internal = reinterpret_cast<unsigned *>(&t.totals->n_internal);
     // ranks of the internal boundaries, and the boundary of every rank
@@ -891,6 +938,36 @@ gs_status build_tree(const float *q, const float *p, int64_t n, int leaf_cap, Tr
                        c1, t.totals, t.node_start, t.nodes, t.nsum);
     timing_end(KIND_TREE, s);
     GS_LAUNCH_CHECK("nodes/stats");
+    return GS_OK;
+}
+
+gs_status tree_set_centres(const float *q, TreeBufs &t, double *c0, int *status, hipStream_t s) {
+    const int nsub = t.nsub;
+    hipLaunchKernelGGL(k_bbox_partial, dim3(t.bbox_blocks, nsub), dim3(256), 0, s, q, t.n, t.seg,
+                       t.bbox_part);
+    hipLaunchKernelGGL(k_bbox_final, dim3(nsub), dim3(64), 0, s, t.bbox_part, t.bbox_blocks,
+                       t.meta, status);
+    hipLaunchKernelGGL(k_copy_centres, dim3(nblk(3 * (int64_t)nsub)), dim3(256), 0, s, t.meta,
+                       nsub, c0);
+    GS_LAUNCH_CHECK("set_centres");
+    return GS_OK;
+}
+
+gs_status launch_state_init(const float *q0, const float *p0, const TreeBufs &t, const double *c0,
+                            double *Sq, double *Sp, float *q32, float *p32, hipStream_t s) {
+    if (t.n == 0) return GS_OK;
+    hipLaunchKernelGGL(k_state_init, dim3(nblk(t.n)), dim3(256), 0, s, q0, p0, t.n, t.seg, t.nsub,
+                       c0, Sq, Sp, q32, p32);
+    GS_LAUNCH_CHECK("state_init");
+    return GS_OK;
+}
+
+gs_status launch_state_to_f32(const double *Sq, const double *Sp, const TreeBufs &t,
+                              const double *c0, float *q32, float *p32, hipStream_t s) {
+    if (t.n == 0) return GS_OK;
+    hipLaunchKernelGGL(k_state_to_f32, dim3(nblk(t.n)), dim3(256), 0, s, Sq, Sp, t.n, t.seg,
+                       t.nsub, c0, q32, p32);
+    GS_LAUNCH_CHECK("state_to_f32");
     return GS_OK;
 }
 

@@ -21,10 +21,9 @@ LIB_PATH = os.path.join(_PKG, "libgsbh.so")
 GS_EXACT, GS_BH = 0, 1
 GS_OP_RHS, GS_OP_SHOOT, GS_OP_ADJOINT, GS_OP_FIELD = 0, 1, 2, 3
 GS_FLAG_F64 = 1
-GS_FLAG_MFMA_PAIRS = 2
 GS_FLAG_GRAPH = 4
 STATUS = {0: "GS_OK", -1: "GS_ERR_INVALID", -2: "GS_ERR_WORKSPACE", -3: "GS_ERR_HIP",
-          -4: "GS_ERR_NONFINITE", -5: "GS_ERR_UNSUPPORTED"}
+          -4: "GS_ERR_NONFINITE", -5: "GS_ERR_UNSUPPORTED", -6: "GS_ERR_OVERFLOW"}
 
 
 class GsError(RuntimeError):
@@ -65,6 +64,7 @@ _SIGS = {
     "gs_shoot_adjoint": (ctypes.c_int, [_vp, _vp, _vp, _i64, _PP, _i32, _dbl, _i32, _vp,
                                         _vp, _vp, _sz, _vp]),
     "gs_adjoint_workspace_bytes": (_sz, [_i64, _PP, _i32, _i32]),
+    "gs_field_workspace_bytes": (_sz, [_i64, _i64, _PP]),
     "gs_field": (ctypes.c_int, [_vp, _i64, _vp, _vp, _i64, _PP, _vp, _vp, _sz, _vp]),
     "gs_batch_workspace_bytes": (_sz, [_vp, _i32, _PP, _i32, _i32]),
     "gs_rhs_batch": (ctypes.c_int, [_vp, _vp, _vp, _i32, _PP, _i32, _vp, _vp, _vp, _sz, _vp]),
@@ -157,8 +157,11 @@ def gs_rhs_exact_f64(q, p, prm: Params):
     _pts(p, torch.float64, "p")
     n = q.shape[0]
     dq, dp = torch.empty_like(q), torch.empty_like(q)
+    pr = Params.from_buffer_copy(prm)
+    pr.flags |= GS_FLAG_F64
+    ws = _workspace(n, pr, GS_EXACT, GS_OP_RHS, q.device)
     _check(lib().gs_rhs_exact_f64(_ptr(q), _ptr(p), n, ctypes.byref(prm), _ptr(dq),
-                                  _ptr(dp), None, 0, _stream(q.device)))
+                                  _ptr(dp), _ptr(ws), ws.numel(), _stream(q.device)))
     return dq, dp
 
 
@@ -260,8 +263,10 @@ def gs_field(x, q, p, prm: Params):
     _pts(q, torch.float32, "q")
     _pts(p, torch.float32, "p")
     v = torch.empty_like(x)
-    nmax = max(x.shape[0], q.shape[0])
-    ws = _workspace(nmax, prm, GS_EXACT, GS_OP_FIELD, x.device)
+    nbytes = lib().gs_field_workspace_bytes(x.shape[0], q.shape[0], ctypes.byref(prm))
+    if nbytes == 0:
+        raise GsError(-1, "invalid arguments for gs_field_workspace_bytes")
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=x.device)
     _check(lib().gs_field(_ptr(x), x.shape[0], _ptr(q), _ptr(p), q.shape[0], ctypes.byref(prm),
                           _ptr(v), _ptr(ws), ws.numel(), _stream(x.device)))
     return v

@@ -197,3 +197,38 @@ def test_adjoint_batch_rejects_bad_arguments():
     assert _call("gs_shoot_adjoint_batch", None, None, None, _off([0, 0]), 1,
                  ctypes.byref(prm), gs.GS_BH, ctypes.c_double(0.01), 2, None, None, None, 0,
                  None) == 0
+
+
+def test_rejects_unknown_flags():
+    prm = gs.params(0.1, flags=2)  # no such flag
+    st = _call("gs_rhs_exact", FAKE, FAKE, 10, ctypes.byref(prm), FAKE, FAKE, FAKE, 1 << 30,
+               None)
+    assert st == -1 and "flags" in gs.lib().gs_last_error().decode()
+
+
+def test_f64_rhs_checks_its_workspace():
+    """gs_rhs_exact_f64 needs the (header-only) workspace that
+    gs_workspace_bytes reports for GS_FLAG_F64, like every other call."""
+    prm = gs.params(0.1, flags=gs.GS_FLAG_F64)
+    need = gs.gs_workspace_bytes(10, prm, gs.GS_EXACT, gs.GS_OP_RHS)
+    assert need > 0
+    st = _call("gs_rhs_exact_f64", FAKE, FAKE, 10, ctypes.byref(prm), FAKE, FAKE, None, 0, None)
+    assert st == -2
+    st = _call("gs_rhs_exact_f64", FAKE, FAKE, 10, ctypes.byref(prm), FAKE, FAKE, FAKE, need - 1,
+               None)
+    assert st == -2
+
+
+def test_field_workspace_grows_with_both_sizes():
+    prm = gs.params(0.05)
+    f = gs.lib().gs_field_workspace_bytes
+    assert 0 < f(1000, 1000, ctypes.byref(prm)) < f(200000, 1000, ctypes.byref(prm))
+    assert f(1000, 1000, ctypes.byref(prm)) < f(1000, 200000, ctypes.byref(prm))
+    assert f(-1, 10, ctypes.byref(prm)) == 0
+    # GS_OP_FIELD sizes the square case
+    assert gs.gs_workspace_bytes(5000, prm, gs.GS_EXACT, gs.GS_OP_FIELD) == f(
+        5000, 5000, ctypes.byref(prm))
+
+
+def test_status_codes_are_distinct():
+    assert gs.STATUS[-6] == "GS_ERR_OVERFLOW" and gs.STATUS[-4] == "GS_ERR_NONFINITE"

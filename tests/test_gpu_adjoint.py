@@ -5,8 +5,9 @@ Tolerances: the GPU adjoint uses FP32 pair arithmetic with FP64 sums and an
 FP64 state, like the forward: gradient rel-L2 1e-5 against the oracle's
 exact adjoint; directional derivatives within 1e-4 relative of central
 differences (h = 1e-4) of the FP64 GPU forward; the Barnes-Hut backward stage
-within max(1e-4, 0.1 eps) of the oracle's Barnes-Hut gradient, eps being the
-oracle's own Barnes-Hut vs exact gradient difference.
+within 1e-5 of the oracle's Barnes-Hut gradient (measured ~5e-8; the
+oracle's own Barnes-Hut vs exact gradient difference eps is printed beside
+it).
 """
 import numpy as np
 import pytest
@@ -109,7 +110,7 @@ def test_bh_adjoint(oracle):
         eps = rel_l2(bg, xg)
         _say(f"  bh theta={theta}: eps {eps:.3e} gpu-vs-bh {rel_l2(g, bg):.3e} "
              f"objective {abs(e - be) / abs(be):.3e}")
-        assert rel_l2(g, bg) <= max(1e-4, 0.1 * eps)
+        assert rel_l2(g, bg) <= 1e-5
         assert abs(e - be) <= 1e-5 * abs(be)
 
 
@@ -126,7 +127,7 @@ def test_bh_adjoint_long_leaf_lists(oracle):
     eps = rel_l2(bg, xg)
     _say(f"  bh leaf_cap 1, n=20000: eps {eps:.3e} gpu-vs-bh {rel_l2(g, bg):.3e} "
          f"objective {abs(e - be) / abs(be):.3e}")
-    assert rel_l2(g, bg) <= max(1e-4, 0.1 * eps)
+    assert rel_l2(g, bg) <= 1e-5
     assert abs(e - be) <= 1e-5 * abs(be)
 
 

@@ -33,25 +33,18 @@ def _say(msg):
     print(msg, flush=True)
 
 
-KERNELS = {"valu": 0, "mfma": gs.GS_FLAG_MFMA_PAIRS}
-
-
-@pytest.mark.parametrize("kernel", list(KERNELS))
 @pytest.mark.parametrize("n", [1, 5, 64, 777, 4097])
-def test_rhs_exact_f32_matches_oracle(oracle, n, kernel):
+def test_rhs_exact_f32_matches_oracle(oracle, n):
     w = W.ellipsoid_20k(n=n)
-    _say(f"rhs_exact f32 n={n} kernel={kernel}")
-    dq, dp = gs.gs_rhs_exact(_t(w.q0), _t(w.p0), gs.params(w.sigma, flags=KERNELS[kernel]))
+    _say(f"rhs_exact f32 n={n}")
+    dq, dp = gs.gs_rhs_exact(_t(w.q0), _t(w.p0), gs.params(w.sigma))
     torch.cuda.synchronize()
     v, a = oracle.rhs_exact(w.q0.astype(np.float64), w.p0.astype(np.float64), w.sigma)
     ev, ea = rel_l2(_np(dq), v), rel_l2(_np(dp), a) if n > 1 else 0.0
     _say(f"  rel-L2 v {ev:.3e} a {ea:.3e}")
     # absolute floor for tiny sets whose pairs are many sigma apart (a ~ 0):
-    # a fraction of the scale |p|^2 / sigma of one pair term (the matrix-core
-    # kernel rounds each p_c s_d product to FP32 before summing, so its floor
-    # is set by 2^-24 |p|^2 |s| / sigma with |s| up to ~20)
-    frac = 1e-7 if kernel == "valu" else 4e-6
-    floor = frac * float(np.abs(w.p0).max()) ** 2 / w.sigma * np.sqrt(a.size)
+    # a fraction of the scale |p|^2 / sigma of one pair term
+    floor = 1e-7 * float(np.abs(w.p0).max()) ** 2 / w.sigma * np.sqrt(a.size)
     assert ev < 1e-5
     assert np.linalg.norm(_np(dp) - a) <= 1e-5 * np.linalg.norm(a) + floor
     if n == 1:
@@ -59,13 +52,12 @@ def test_rhs_exact_f32_matches_oracle(oracle, n, kernel):
         assert np.abs(_np(dp)).max() <= 1e-12 * np.abs(w.p0).max()
 
 
-@pytest.mark.parametrize("kernel", list(KERNELS))
-def test_rhs_exact_f32_deterministic_and_coincident(oracle, kernel):
+def test_rhs_exact_f32_deterministic_and_coincident(oracle):
     rng = np.random.default_rng(3)
     q = rng.random((2000, 3)).astype(np.float32)
     q[100:600] = q[50]  # 500 coincident points
     p = (0.02 * rng.standard_normal((2000, 3))).astype(np.float32)
-    prm = gs.params(0.05, flags=KERNELS[kernel])
+    prm = gs.params(0.05)
     a1 = gs.gs_rhs_exact(_t(q), _t(p), prm)
     a2 = gs.gs_rhs_exact(_t(q), _t(p), prm)
     torch.cuda.synchronize()
@@ -74,13 +66,12 @@ def test_rhs_exact_f32_deterministic_and_coincident(oracle, kernel):
     assert rel_l2(_np(a1[0]), v) < 1e-5 and rel_l2(_np(a1[1]), a) < 1e-5
 
 
-@pytest.mark.parametrize("kernel", list(KERNELS))
-def test_rhs_exact_f32_full_size_sampled(oracle, kernel):
+def test_rhs_exact_f32_full_size_sampled(oracle):
     """200k points: the launch configuration the benchmark times, checked on
     1024 sampled targets computed one by one by the oracle."""
     w = W.ellipsoids_200k()
-    _say(f"rhs_exact f32 n=200000 (sampled) kernel={kernel}")
-    dq, dp = gs.gs_rhs_exact(_t(w.q0), _t(w.p0), gs.params(w.sigma, flags=KERNELS[kernel]))
+    _say("rhs_exact f32 n=200000 (sampled)")
+    dq, dp = gs.gs_rhs_exact(_t(w.q0), _t(w.p0), gs.params(w.sigma))
     torch.cuda.synchronize()
     idx = np.sort(np.random.default_rng(7).choice(w.n, 1024, replace=False))
     v, a = oracle.rhs_exact_rows(idx, w.q0.astype(np.float64), w.p0.astype(np.float64),
@@ -112,13 +103,11 @@ def test_shoot_f64_sphere_1024(oracle):
     np.testing.assert_allclose(H.cpu().numpy(), oH, rtol=1e-12)
 
 
-@pytest.mark.parametrize("kernel", list(KERNELS))
-def test_shoot_f32_exact_ellipsoid_20k(oracle, kernel):
+def test_shoot_f32_exact_ellipsoid_20k(oracle):
     """N = 20000 noisy ellipsoid, sigma 0.05, 40 steps: FP32 GPU vs FP64 oracle."""
     w = W.ellipsoid_20k()
-    _say(f"shoot f32 exact n=20000 kernel={kernel}")
-    q1, p1, H = gs.gs_shoot(_t(w.q0), _t(w.p0),
-                            gs.params(w.sigma, nt=w.nt, flags=KERNELS[kernel]))
+    _say("shoot f32 exact n=20000")
+    q1, p1, H = gs.gs_shoot(_t(w.q0), _t(w.p0), gs.params(w.sigma, nt=w.nt))
     torch.cuda.synchronize()
     oq, op, oH = oracle.shoot(w.q0.astype(np.float64), w.p0.astype(np.float64), w.sigma,
                               w.nt)
@@ -126,12 +115,7 @@ def test_shoot_f32_exact_ellipsoid_20k(oracle, kernel):
     ed = rel_l2(_np(q1) - w.q0, oq - w.q0)
     eh = np.abs(H.cpu().numpy() - oH).max() / np.abs(oH).max()
     _say(f"  rel-L2 q1 {eq:.3e} p1 {ep:.3e} disp {ed:.3e} H {eh:.3e}")
-    if kernel == "valu":
-        assert eq < 1e-5 and ep < 1e-5 and eh < 1e-6
-    else:
-        # opt-in matrix-core kernel: FP32-rounded p_c s_d products give ~1e-6
-        # per RHS on a (vs ~1e-7), which the flow carries to p(1) and H
-        assert eq < 1e-5 and ep < 3e-5 and eh < 5e-6
+    assert eq < 1e-5 and ep < 1e-5 and eh < 1e-6
 
 
 def test_shoot_zero_and_single_point():
