@@ -288,6 +288,30 @@ gs_status gs_autotune_exact(const float *q, const float *p, const int64_t *offse
                             gs_params *prm, float *dq, float *dp, void *ws, size_t ws_bytes,
                             hipStream_t stream, double *best_ms);
 
+/* Diagnostic (for checking the octree against its definition; not a
+ * hot-path call): builds the octree of (q, p) exactly as gs_rhs_bh does
+ * (Sec. 2.2, octree representation) in `ws` (the workspace of gs_rhs_bh),
+ * waits for `stream` and copies it to HOST arrays:
+ *   keys[n]   the sorted 63-bit Morton keys (21 bits per axis interleaved,
+ *             x highest in each triple of bits);
+ *   perm[n]   the input index of each sorted point;
+ *   *n_nodes  the number of stored nodes.  The stored tree is the compressed
+ *             octree: a chain of single-child cells is stored as its deepest
+ *             cell (they hold the same points); node 0 is the root; the
+ *             children of a node are contiguous.
+ * When *n_nodes <= max_nodes it also writes, per node k: node_start[k] its
+ * first sorted point (its points are perm[node_start[k] ..
+ * node_start[k] + node_count[k] - 1]), node_count[k], node_first[k] (its
+ * first child node; for a leaf, its first sorted point), node_nchild[k] (0
+ * for a leaf) and node_stats[13 k ..] = centre C (3, FP64), momentum sum P
+ * (3, as stored in FP32), tight box lo (3), hi (3) and the square of its
+ * largest side.  Synchronous. */
+gs_status gs_tree_export(const float *q, const float *p, int64_t n, const gs_params *prm,
+                         void *ws, size_t ws_bytes, hipStream_t stream, int64_t max_nodes,
+                         int64_t *n_nodes, uint64_t *keys, uint32_t *perm, int32_t *node_start,
+                         int32_t *node_count, int32_t *node_first, int32_t *node_nchild,
+                         double *node_stats);
+
 /* Waits for `stream` and returns the device-side status word of the last
  * Barnes-Hut call that used this workspace: GS_OK; GS_ERR_NONFINITE when a
  * coordinate was NaN or infinite (the results are not meaningful); or

@@ -1069,6 +1069,56 @@ gs_status gs_autotune_exact(const float *q, const float *p, const int64_t *offse
     return GS_OK;
 }
 
+gs_status gs_tree_export(const float *q, const float *p, int64_t n, const gs_params *prm,
+                         void *ws, size_t ws_bytes, hipStream_t stream, int64_t max_nodes,
+                         int64_t *n_nodes, uint64_t *keys, uint32_t *perm, int32_t *node_start,
+                         int32_t *node_count, int32_t *node_first, int32_t *node_nchild,
+                         double *node_stats) {
+    GS_TRY(check_n(n));
+    GS_TRY(check_params(prm, false, true));
+    if (!n_nodes) {
+        set_error("n_nodes is NULL");
+        return GS_ERR_INVALID;
+    }
+    *n_nodes = 0;
+    if (n == 0) return GS_OK;
+    GS_TRY(check_ptrs({q, p, keys, perm}));
+    if (max_nodes < 0) {
+        set_error("max_nodes must be >= 0");
+        return GS_ERR_INVALID;
+    }
+    if (max_nodes > 0)
+        GS_TRY(check_ptrs({node_start, node_count, node_first, node_nchild, node_stats}));
+    gs_params pr = *prm;
+    pr.flags &= ~(GS_FLAG_F64 | GS_FLAG_GRAPH);
+    GS_TRY(check_ws(ws, ws_bytes, measure_bytes(n, &pr, GS_BH, GS_OP_RHS)));
+    Arena a{static_cast<char *>(ws), kHeader, ws_bytes};
+    TreeBufs t;
+    carve_tree(a, n, t);
+    GS_TRY(build_tree(q, p, n, pr.leaf_cap, t, reinterpret_cast<int *>(ws), stream));
+    GS_HIP(hipStreamSynchronize(stream));
+    TreeTotals tot;
+    GS_HIP(hipMemcpy(&tot, t.totals, sizeof(tot), hipMemcpyDeviceToHost));
+    *n_nodes = tot.n_nodes;
+    GS_HIP(hipMemcpy(keys, t.K, (size_t)n * sizeof(uint64_t), hipMemcpyDeviceToHost));
+    GS_HIP(hipMemcpy(perm, t.perm, (size_t)n * sizeof(uint32_t), hipMemcpyDeviceToHost));
+    if (tot.n_nodes > max_nodes) return GS_OK;
+    std::vector<BhNode> nodes((size_t)tot.n_nodes);
+    GS_HIP(hipMemcpy(nodes.data(), t.nodes, nodes.size() * sizeof(BhNode), hipMemcpyDeviceToHost));
+    GS_HIP(hipMemcpy(node_start, t.node_start, nodes.size() * sizeof(int32_t),
+                     hipMemcpyDeviceToHost));
+    for (size_t k = 0; k < nodes.size(); ++k) {
+        const BhNode &d = nodes[k];
+        node_count[k] = d.n;
+        node_first[k] = d.first;
+        node_nchild[k] = d.nchild;
+        const double st[13] = {d.cx, d.cy, d.cz, d.px, d.py, d.pz, d.lox, d.loy, d.loz,
+                               d.hix, d.hiy, d.hiz, d.s2};
+        memcpy(node_stats + 13 * k, st, sizeof(st));
+    }
+    return GS_OK;
+}
+
 gs_status gs_get_status(const void *ws, hipStream_t stream) {
     if (!ws) {
         set_error("workspace is NULL");

@@ -77,6 +77,9 @@ _SIGS = {
                                             _vp, ctypes.POINTER(ctypes.c_double)]),
     "gs_autotune_exact": (ctypes.c_int, [_vp, _vp, _vp, _i32, _PP, _vp, _vp, _vp, _sz, _vp,
                                          ctypes.POINTER(ctypes.c_double)]),
+    "gs_tree_export": (ctypes.c_int, [_vp, _vp, _i64, _PP, _vp, _sz, _vp, _i64,
+                                      ctypes.POINTER(ctypes.c_int64), _vp, _vp, _vp, _vp, _vp,
+                                      _vp, _vp]),
     "gs_get_status": (ctypes.c_int, [_vp, _vp]),
     "gs_bh_counters": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(ctypes.c_int64)]),
     "gs_kernel_timing": (ctypes.c_int, [_i32]),
@@ -380,6 +383,31 @@ def gs_autotune_exact(q, p, prm: Params, offsets=None, ws=None):
                                    _ptr(dp), _ptr(ws), ws.numel(), _stream(q.device),
                                    ctypes.byref(ms)))
     return out, ms.value
+
+
+def gs_tree_export(q, p, prm: Params) -> dict:
+    """The octree gs_rhs_bh builds for (q, p), copied to the host (numpy
+    arrays): sorted keys, permutation and per-node records."""
+    import numpy as np
+    _pts(q, torch.float32, "q")
+    _pts(p, torch.float32, "p")
+    n = q.shape[0]
+    ws = _workspace(n, prm, GS_BH, GS_OP_RHS, q.device)
+    keys = np.zeros(n, np.uint64)
+    perm = np.zeros(n, np.uint32)
+    nn = ctypes.c_int64(0)
+    args = [_ptr(q), _ptr(p), n, ctypes.byref(prm), _ptr(ws), ws.numel(), _stream(q.device)]
+    _check(lib().gs_tree_export(*args, 0, ctypes.byref(nn), keys.ctypes.data, perm.ctypes.data,
+                                None, None, None, None, None))
+    m = nn.value
+    start, count, first, nchild = (np.zeros(m, np.int32) for _ in range(4))
+    stats = np.zeros((m, 13))
+    _check(lib().gs_tree_export(*args, m, ctypes.byref(nn), keys.ctypes.data, perm.ctypes.data,
+                                start.ctypes.data, count.ctypes.data, first.ctypes.data,
+                                nchild.ctypes.data, stats.ctypes.data))
+    return {"keys": keys, "perm": perm, "start": start, "count": count, "first": first,
+            "nchild": nchild, "C": stats[:, 0:3], "P": stats[:, 3:6], "lo": stats[:, 6:9],
+            "hi": stats[:, 9:12], "s2": stats[:, 12]}
 
 
 def gs_get_status(ws) -> int:

@@ -1,0 +1,106 @@
+"""The GPU octree against its definition (Sec. 2.2, octree representation;
+readings R6-R9): keys, node point sets, counts and statistics.
+
+gs_tree_export copies the tree that gs_rhs_bh builds.  Its sorted keys must
+de-interleave to the oracle's 21-bit integer coordinates of every point; its
+node point sets must be exactly the distinct point sets of the oracle's
+recursive-insertion tree (the GPU stores the compressed tree: a chain of
+single-child cells holds one point set and is stored once), obtained from the
+brute-force Morton cells, which test_oracle_pins.py pins to the oracle's tree;
+children partition their parent; leaves hold at most leaf_cap points (or
+points sharing one level-21 cell); and each node's statistics equal the
+oracle's dump of the same cell: tight box exactly, centre to 1e-15 relative
+to the extent, momentum sum to FP32 rounding.
+"""
+import numpy as np
+import pytest
+import torch
+
+from helpers import canonical_octree
+from paper_1907_04834_amd import gs
+from paper_1907_04834_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _t(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+
+
+def _deinterleave(keys):
+    k = keys.astype(np.uint64)
+    c = np.zeros((k.size, 3), np.int64)
+    for b in range(21):
+        for ax in range(3):
+            bit = (k >> np.uint64(3 * b + 2 - ax)) & np.uint64(1)
+            c[:, ax] |= bit.astype(np.int64) << b
+    return c
+
+
+def _cases():
+    rng = np.random.default_rng(40)
+    q = W.ellipsoid_surface(rng, 1500, (1.0, 0.6, 0.4), 0.01)
+    q[:7] = q[7]  # coincident points
+    p = 0.02 * rng.standard_normal(q.shape)
+    yield "ellipsoid-1500", q.astype(np.float32), p.astype(np.float32)
+    g = np.stack(np.meshgrid(*[np.arange(6)] * 3, indexing="ij"), -1).reshape(-1, 3) / 6.0
+    yield "lattice-216", g.astype(np.float32), (0.01 * rng.standard_normal(g.shape)).astype(
+        np.float32)
+    c = np.repeat(rng.random((9, 3)), 40, axis=0)
+    yield "clusters-360", c.astype(np.float32), (0.01 * rng.standard_normal(c.shape)).astype(
+        np.float32)
+    w = W.ellipsoid_20k(n=2000)
+    yield "ellipsoid20k-2000+100", (w.q0.astype(np.float64) + 100.0).astype(np.float32), w.p0
+
+
+@pytest.mark.parametrize("leaf_cap", [1, 3, 8])
+def test_tree_matches_definition(oracle, leaf_cap):
+    for name, q, p in _cases():
+        n = q.shape[0]
+        t = gs.gs_tree_export(_t(q), _t(p), gs.params(0.05, leaf_cap=leaf_cap))
+        q64, p64 = q.astype(np.float64), p.astype(np.float64)
+        # keys: sorted, a permutation, and the oracle's integer coordinates
+        perm = t["perm"].astype(np.int64)
+        assert np.array_equal(np.sort(perm), np.arange(n)), name
+        assert (np.diff(t["keys"].astype(np.uint64)) >= 0).all() if n > 1 else True
+        ic = oracle.int_coords(q64).astype(np.int64)
+        assert np.array_equal(_deinterleave(t["keys"]), ic[perm]), name
+        # node point sets = the distinct point sets of the oracle's tree
+        brute = canonical_octree(ic, leaf_cap)
+        cells = {}
+        for key, mem in brute.items():  # deepest cell of each distinct point set
+            if mem not in cells or key[0] > cells[mem][0]:
+                cells[mem] = key
+        m = len(t["count"])
+        got = {}
+        for k in range(m):
+            mem = tuple(sorted(perm[t["start"][k]:t["start"][k] + t["count"][k]].tolist()))
+            assert mem not in got, (name, "point set stored twice")
+            got[mem] = k
+        assert set(got) == set(cells), (name, len(got), len(cells))
+        dump = oracle.tree_dump(q64, p64, leaf_cap=leaf_cap)
+        where = {(int(l), int(pf)): i for i, (l, pf) in
+                 enumerate(zip(dump["level"], dump["prefix"]))}
+        extent = float((q64.max(0) - q64.min(0)).max())
+        for mem, k in got.items():
+            i = where[cells[mem]]
+            cnt = t["count"][k]
+            assert cnt == dump["count"][i] == len(mem)
+            # children partition the node; leaves respect leaf_cap
+            if t["nchild"][k] > 0:
+                kids = range(t["first"][k], t["first"][k] + t["nchild"][k])
+                assert sum(t["count"][c] for c in kids) == cnt
+                assert all(t["start"][c] >= t["start"][k] for c in kids)
+            else:
+                same = len(set(map(tuple, ic[list(mem)]))) == 1
+                assert cnt <= leaf_cap or same, (name, cnt)
+            np.testing.assert_array_equal(t["lo"][k], dump["lo"][i])
+            np.testing.assert_array_equal(t["hi"][k], dump["hi"][i])
+            assert np.abs(t["C"][k] - dump["C"][i]).max() <= 1e-15 * max(extent, 1.0) + \
+                1e-15 * np.abs(dump["C"][i]).max()
+            pn = np.abs(p64[list(mem)]).sum(0)
+            assert (np.abs(t["P"][k] - dump["P"][i]) <= 1e-6 * pn + 1e-30).all()
+            side = (dump["hi"][i] - dump["lo"][i]).max()
+            assert t["s2"][k] == side * side
+        print(f"{name} leaf_cap={leaf_cap}: {m} nodes, all equal", flush=True)
