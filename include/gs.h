@@ -47,9 +47,13 @@
  *     NULL array when n > 0, or a workspace that is too small.  n == 0 is a
  *     no-op (GS_OK).
  *   - Accuracy does not depend on where a point set lies: the FP32 kernels
- *     work on positions relative to the FP64 centre of each set's box (the
- *     method depends only on differences q_i - q_j), and the Barnes-Hut
- *     decisions are taken in FP64 on the positions as given.
+ *     work on positions relative to an FP64 origin per set (the method
+ *     depends only on differences q_i - q_j): the exact all-pairs path uses
+ *     the centre of the set's box, the Barnes-Hut path that centre rounded to
+ *     a multiple of the smallest power of two not below the box side (0 for
+ *     a set around the origin, so that its differences are those of the
+ *     inputs).  The Barnes-Hut decisions are taken in FP64 on the positions
+ *     as given.
  *   - Outputs must not alias inputs, except q1/p1 which may equal q0/p0.
  *   - gs_last_error() returns a thread-local message for the last failure.
  *   - Calls are reentrant when they use distinct workspaces.

@@ -295,7 +295,7 @@ __global__ __launch_bounds__(256) void k_adj_decide(
 }
 
 // Phase 2: one wave per (group, chunk of its list entries), on the positions
-// relative to the set's box centre.
+// relative to the set's frame origin.
 __global__ __launch_bounds__(256) void k_adj_leaves(
     const float4 *__restrict__ Qs, const float4 *__restrict__ Ps, const float4 *__restrict__ As,
     const float4 *__restrict__ Bs, int64_t n, const GroupDesc *__restrict__ gtab, int64_t groups,
@@ -374,7 +374,7 @@ gs_status bh_adjoint_begin(const float *q0, AdjointBufs &b, char *ws, hipStream_
     hipLaunchKernelGGL(k_clear, dim3(1), dim3(64), 0, s, reinterpret_cast<int *>(ws),
                        reinterpret_cast<u64 *>(ws + kCountersOffset));
     GS_LAUNCH_CHECK("clear");
-    // the frame of the FP32 copies: box centres of q0, fixed for the call
+    // the frame of the FP32 copies: frame origins of q0, fixed for the call
     return tree_set_centres(q0, b.sh.tree, b.sh.c0, reinterpret_cast<int *>(ws), s);
 }
 

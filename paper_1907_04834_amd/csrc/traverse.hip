@@ -16,15 +16,15 @@
 // FP32 target position as given, the node's exact FP32 box and FP64 centre,
 // as in the definition.  The contributions are FP32 with per-leaf sums
 // accumulated in FP64: exact pairs use the positions relative to the set's
-// box centre (Qc), and a monopole's offset x - C_k is taken in FP64 and
-// rounded once, so no difference loses precision to the set's distance from
-// the origin.  Leaf points are streamed with wave-uniform (scalar) loads; a
+// frame origin (Qc; the box centre rounded to a multiple of a power of two,
+// 0 for a set around the origin), and a monopole's offset x - C_k is taken
+// in FP64 and rounded once, so no difference loses precision to the set's
+// distance from the origin.  Leaf points are streamed with wave-uniform (scalar) loads; a
 // leaf's sums are added only by the lanes in its mask.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
-#include <cstdlib>
 
 #include "traverse.h"
 
@@ -417,7 +417,7 @@ __global__ __launch_bounds__(256) void k_bh_decide(
 
 
 // Phase 2: one wave per (group, chunk of its list entries), on the positions
-// relative to the set's box centre.
+// relative to the set's frame origin.
 template <bool WITH_A>
 __global__ __launch_bounds__(256) void k_bh_leaves(const float4 *__restrict__ Qc,
                                                    const float4 *__restrict__ Ps, int64_t n,
@@ -549,23 +549,18 @@ size_t traverse_list_bytes(int64_t groups) {
 
 size_t traverse_count_ints(int64_t groups) { return (size_t)groups * kSub; }
 
-// Phase-1 waves aim at about GS_BH_DECIDE_WAVES waves in all (default 12288,
-// 12 per SIMD), phase-2 waves at GS_BH_LEAF_WAVES (default 65536); the
-// environment overrides are for tuning sweeps.
-static int64_t env_waves(const char *name, int64_t dflt) {
-    const char *e = getenv(name);
-    const long long v = e ? atoll(e) : 0;
-    return v >= 1 && v <= (1 << 24) ? (int64_t)v : dflt;
-}
+// Phase-1 waves aim at about kDecideWaves waves in all (12 per SIMD), phase-2
+// waves at kLeafWaves; a sweep of both on the 200k ellipsoids and on the
+// 64-subject population found these best.
+constexpr int64_t kDecideWaves = 12288;
+constexpr int64_t kLeafWaves = 65536;
 
 namespace trav {
 TravSplit traverse_split(int64_t groups) {
-    static const int64_t w1 = env_waves("GS_BH_DECIDE_WAVES", 12288);
-    static const int64_t w2 = env_waves("GS_BH_LEAF_WAVES", 65536);
     const int64_t g = groups > 0 ? groups : 1;
     TravSplit split;
-    split.nsub = (int)std::min<int64_t>(kSub, std::max<int64_t>(1, (w1 + g - 1) / g));
-    split.maxc = (int)std::min<int64_t>(kMaxChunks, std::max<int64_t>(1, (w2 + g - 1) / g));
+    split.nsub = (int)std::min<int64_t>(kSub, std::max<int64_t>(1, (kDecideWaves + g - 1) / g));
+    split.maxc = (int)std::min<int64_t>(kMaxChunks, std::max<int64_t>(1, (kLeafWaves + g - 1) / g));
     split.segcap = kListPerGroup / split.nsub;
     return split;
 }
@@ -667,7 +662,7 @@ gs_status shoot_bh(const float *q0, const float *p0, int64_t n, const gs_params 
     u64 *counters = reinterpret_cast<u64 *>(ws + kCountersOffset);
     hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(256), 0, s, status, counters);
     // the FP32 copies that every step's tree and pairs are built from are kept
-    // relative to the box centre of q0 (fixed for the call), so their rounding
+    // relative to the frame origin of q0 (fixed for the call), so their rounding
     // does not depend on where the set lies
     GS_TRY(tree_set_centres(q0, b.tree, b.c0, status, s));
     GS_TRY(launch_state_init(q0, p0, b.tree, b.c0, b.Sq, b.Sp, b.q32, b.p32, s));

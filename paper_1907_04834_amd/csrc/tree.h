@@ -90,7 +90,7 @@ struct TreeBufs {
     unsigned *hist;            // [256][sort_blocks] digit-major counts, then offsets
     unsigned *scan_part;       // block sums of the generic scan
     float4 *Qs, *Ps;           // sorted points / momenta (FP32, as given: the decisions)
-    float4 *Qc;                // sorted points minus their set's box centre (FP32, pairs)
+    float4 *Qc;                // sorted points minus their set's frame origin (FP32, pairs)
     unsigned char *lvl;        // [n-1] split level of each boundary
     unsigned *flag;            // [n] internal-node flag per boundary, then rank
     unsigned *rank;            // [n] exclusive scan of flag
@@ -124,7 +124,8 @@ void carve_forest(Arena &a, int64_t n, int nsub, int64_t groups, int64_t max_set
 // finite.
 gs_status build_tree(const float *q, const float *p, int64_t n, int leaf_cap, TreeBufs &t,
                      int *status, hipStream_t s);
-// Box centre of every set of q (FP32 [n][3]) into c0 (FP64 [nsub][3]); uses
+// Frame origin of every set of q (FP32 [n][3]; its box centre rounded to a
+// multiple of a power of two, see frame_origin) into c0 (FP64 [nsub][3]); uses
 // the tree's box buffers and sets `status` for non-finite coordinates.
 gs_status tree_set_centres(const float *q, TreeBufs &t, double *c0, int *status, hipStream_t s);
 // The FP64 state of float inputs (Sq, Sp) and its FP32 copies q32 = q - c0[set],
@@ -212,7 +213,7 @@ struct ShootBhBufs {
     TreeBufs tree;
     double *Sq, *Sp;   // FP64 state [n][3]
     float *q32, *p32;  // FP32 copies [n][3], q32 relative to c0
-    double *c0;        // [nsub][3] box centres of q0, fixed for the call
+    double *c0;        // [nsub][3] frame origins of q0, fixed for the call
     double *Hpart;     // [nt + 1][groups]
     const int *gseg;   // [nsub + 1] group range of each set (nullable: one set)
 };

@@ -81,6 +81,21 @@ __device__ inline int set_of(const long long *__restrict__ seg, int nsub, int64_
     return lo;
 }
 
+// Origin of the FP32 frame of a set along one axis (the tree path's pair
+// positions q - c): the box centre rounded to a multiple of 2^m, the
+// smallest power of two not below the box side.  A set whose box lies within
+// half a side of the origin gets c = 0, so its FP32 differences are taken on
+// the inputs themselves; for a set far from the origin, q and c lie within a
+// factor of two of each other and q - c is exact (Sterbenz).  Either way the
+// rounding no longer depends on the set's distance from the origin.
+__device__ inline double frame_origin(float lo, float hi) {
+    const double l = lo, h = hi, side = h - l, mid = 0.5 * (l + h);
+    if (!(side > 0.0)) return mid;  // one value on this axis: q - c = 0
+    int e;
+    frexp(side, &e);  // side = f 2^e with f in [0.5, 1), so 2^e >= side
+    return ldexp(rint(ldexp(mid, -e)), e);
+}
+
 // ---------------------------------------------------------------- bbox
 // grid (blocks per set, sets); partials [set][block][6]
 __global__ __launch_bounds__(256) void k_bbox_partial(const float *__restrict__ q, int64_t n,
@@ -159,8 +174,7 @@ __global__ __launch_bounds__(64) void k_bbox_final(const float *__restrict__ par
         bad = 1;
         e = 0.0;  // degenerate tree: one leaf (results are not meaningful)
     }
-    for (int c = 0; c < 3; ++c)
-        meta->cen[c] = bad ? 0.0 : 0.5 * ((double)meta->lo[c] + (double)meta->hi[c]);
+    for (int c = 0; c < 3; ++c) meta->cen[c] = bad ? 0.0 : frame_origin(lo[c], hi[c]);
     meta->extent = e;
     meta->scale = e > 0.0 ? 2097152.0 / e : 0.0;
     meta->nonfinite = bad;
@@ -465,7 +479,7 @@ __global__ __launch_bounds__(256) void k_boundaries(const u64 *__restrict__ K, i
             const float4 b = make_float4(p[3 * src], p[3 * src + 1], p[3 * src + 2], 0.f);
             Qs[i] = a;
             Ps[i] = b;
-            // pair arithmetic works relative to the set's box centre (FP64 difference,
+            // pair arithmetic works relative to the set's frame origin (FP64 difference,
             // rounded once), so its accuracy does not depend on where the set lies
             const double *cen = meta[set_of(seg, nsub, i)].cen;
             Qc[i] = make_float4((float)((double)a.x - cen[0]), (float)((double)a.y - cen[1]),

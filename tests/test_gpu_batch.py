@@ -251,6 +251,16 @@ def test_many_tiny_sets(oracle, method):
     torch.cuda.synchronize()
     v, a, q1, p1, H = _np(dq), _np(dp), _np(q1), _np(p1), _np(H)
     pairs = 0
+    # Elementwise bar on v (the contract itself is rel-L2 1e-5 per set).  The
+    # exact kernel stores k (q - c) rounded once to FP32 (k^2 = log2(e) /
+    # 2 sigma^2), so a pair's weight carries a relative error of about
+    # 2 |d'| ulp(k extent / 2), d' = k (q_i - q_j); with 40 points, one near
+    # pair can dominate a small component.  A float32 emulation of that
+    # storage on 900 such sets gives up to 5e-7 max|v| (with the centre, or
+    # with no centre at all), hence 1e-6 max|v|.  The Barnes-Hut leaf pairs
+    # take differences of the inputs themselves (frame origin 0 around the
+    # origin) and keep 1e-7 max|v|.
+    v_atol = 1e-6 if method == gs.GS_EXACT else 1e-7
     for s, w in enumerate(subs):
         lo, hi = off[s], off[s + 1]
         if hi == lo:
@@ -262,7 +272,7 @@ def test_many_tiny_sets(oracle, method):
         else:
             vo, ao, c = oracle.rhs_bh(q64, p64, sigma, theta, leaf_cap=leaf_cap)
             pairs += c["pairs"]
-        assert np.allclose(v[lo:hi], vo, rtol=1e-5, atol=1e-7 * np.abs(vo).max())
+        assert np.allclose(v[lo:hi], vo, rtol=1e-5, atol=v_atol * np.abs(vo).max())
         assert np.allclose(a[lo:hi], ao, rtol=1e-4, atol=1e-6 * (np.abs(ao).max() + 1e-30))
         kind = "exact" if method == gs.GS_EXACT else "bh"
         qo, po, Ho = oracle.shoot(q64, p64, sigma, 3, method=kind, theta=theta,
