@@ -316,6 +316,27 @@ gs_status gs_tree_export(const float *q, const float *p, int64_t n, const gs_par
                          int32_t *node_count, int32_t *node_first, int32_t *node_nchild,
                          double *node_stats);
 
+/* Exact right-hand side that allocates nothing, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation.  Computes what gs_rhs_exact computes,
+ * with its workspace in a static device array of the library of
+ * GS_STATIC_SCRATCH_BYTES (64 MiB), which every device the library runs on
+ * holds until the process ends; the array's device address is looked up on
+ * the first call on each device, with that device current.  n must be at
+ * most GS_STATIC_MAX_N (500 000): larger n returns GS_ERR_WORKSPACE before any
+ * device work.  The work-item target (prm->exact_items, 0 = the default) is
+ * halved, not below 256, until the workspace fits the array, which changes
+ * only the FP64 summation order.  The call copies nothing from the host and
+ * only enqueues kernels on `stream`, so it may be captured into a HIP graph.
+ * Every call on a device shares that device's array, which keeps the last
+ * call's contents (no result depends on them): calls that overlap on one
+ * device (other streams, other threads, graph replays still running) race
+ * and corrupt each other's results, so the caller must serialise them. */
+#define GS_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+#define GS_STATIC_MAX_N ((int64_t)500000)
+gs_status gs_rhs_exact_static(const float *q, const float *p, int64_t n, const gs_params *prm,
+                              float *dq, float *dp, hipStream_t stream);
+
 /* Waits for `stream` and returns the device-side status word of the last
  * Barnes-Hut call that used this workspace: GS_OK; GS_ERR_NONFINITE when a
  * coordinate was NaN or infinite (the results are not meaningful); or

@@ -80,6 +80,7 @@ _SIGS = {
     "gs_tree_export": (ctypes.c_int, [_vp, _vp, _i64, _PP, _vp, _sz, _vp, _i64,
                                       ctypes.POINTER(ctypes.c_int64), _vp, _vp, _vp, _vp, _vp,
                                       _vp, _vp]),
+    "gs_rhs_exact_static": (ctypes.c_int, [_vp, _vp, _i64, _PP, _vp, _vp, _vp]),
     "gs_get_status": (ctypes.c_int, [_vp, _vp]),
     "gs_bh_counters": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(ctypes.c_int64)]),
     "gs_kernel_timing": (ctypes.c_int, [_i32]),
@@ -153,6 +154,28 @@ def gs_rhs_exact(q, p, prm: Params, ws=None):
     _check(lib().gs_rhs_exact(_ptr(q), _ptr(p), n, ctypes.byref(prm), _ptr(dq), _ptr(dp),
                               _ptr(ws), ws.numel(), _stream(q.device)))
     return dq, dp
+
+
+def gs_rhs_exact_static(q, p, prm: Params, out=None):
+    """gs_rhs_exact with the library's static device workspace (no workspace
+    argument, no device allocation by the library; n <= GS_STATIC_MAX_N).
+    `out` = (dq, dp) lets a caller that cannot allocate pass its own outputs."""
+    _pts(q, torch.float32, "q")
+    _pts(p, torch.float32, "p")
+    n = q.shape[0]
+    if out is None:
+        dq, dp = torch.empty_like(q), torch.empty_like(q)
+    else:
+        dq, dp = _pts(out[0], torch.float32, "dq"), _pts(out[1], torch.float32, "dp")
+        if dq.shape != q.shape or dp.shape != q.shape:
+            raise ValueError("dq / dp must have the shape of q")
+    _check(lib().gs_rhs_exact_static(_ptr(q), _ptr(p), n, ctypes.byref(prm), _ptr(dq),
+                                     _ptr(dp), _stream(q.device)))
+    return dq, dp
+
+
+GS_STATIC_SCRATCH_BYTES = 64 << 20
+GS_STATIC_MAX_N = 500000
 
 
 def gs_rhs_exact_f64(q, p, prm: Params):

@@ -232,3 +232,27 @@ def test_field_workspace_grows_with_both_sizes():
 
 def test_status_codes_are_distinct():
     assert gs.STATUS[-6] == "GS_ERR_OVERFLOW" and gs.STATUS[-4] == "GS_ERR_NONFINITE"
+
+
+def test_static_workspace_entry_checks_before_device_work():
+    """gs_rhs_exact_static: size limit, parameter and pointer checks, n = 0,
+    all before any device work; every n up to the limit fits the array with
+    the smallest work-item target."""
+    prm = gs.params(0.05)
+    st = _call("gs_rhs_exact_static", FAKE, FAKE, gs.GS_STATIC_MAX_N + 1, ctypes.byref(prm),
+               FAKE, FAKE, None)
+    assert st == -2 and "GS_STATIC_MAX_N" in gs.lib().gs_last_error().decode()
+    assert _call("gs_rhs_exact_static", None, None, 0, ctypes.byref(prm), None, None,
+                 None) == 0
+    assert _call("gs_rhs_exact_static", FAKE, FAKE, 10, None, FAKE, FAKE, None) == -1
+    assert _call("gs_rhs_exact_static", None, FAKE, 10, ctypes.byref(prm), FAKE, FAKE,
+                 None) == -1
+    bad = gs.params(-1.0)
+    assert _call("gs_rhs_exact_static", FAKE, FAKE, 10, ctypes.byref(bad), FAKE, FAKE,
+                 None) == -1
+    prm.exact_items = 100
+    st = _call("gs_rhs_exact_static", FAKE, FAKE, 10, ctypes.byref(prm), FAKE, FAKE, None)
+    assert st == -1 and "exact_items" in gs.lib().gs_last_error().decode()
+    prm.exact_items = 256
+    assert gs.gs_workspace_bytes(gs.GS_STATIC_MAX_N, prm, gs.GS_EXACT,
+                                 gs.GS_OP_RHS) <= gs.GS_STATIC_SCRATCH_BYTES
