@@ -353,7 +353,7 @@ gs_status gs_get_status(const void *ws, hipStream_t stream);
  * Wave-level diagnostics of the GPU traversal: out[4] leaf-point steps
  * executed by waves (each serves up to 64 targets), out[5] node records
  * decided by waves, out[6] the largest out[4] + out[5] of a single wave,
- * out[7] reserved (0). */
+ * out[7] the largest out[5] of a single phase-1 (decision) wave. */
 #define GS_BH_COUNTERS 8
 gs_status gs_bh_counters(const void *ws, hipStream_t stream, int64_t out[GS_BH_COUNTERS]);
 

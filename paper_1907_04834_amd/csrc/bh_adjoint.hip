@@ -136,7 +136,7 @@ struct AdjDecideLds {
 __device__ inline void load_block(const BhNode *__restrict__ nodes,
                                   const double *__restrict__ adj, int first, int count, int lane,
                                   AdjDecideLds &L) {
-    if (lane < 5 * count)
+    if (lane < kNodeF4 * count)
         reinterpret_cast<float4 *>(L.d.node)[lane] =
             reinterpret_cast<const float4 *>(nodes + first)[lane];
     if (lane < 3 * count)
@@ -172,7 +172,7 @@ __global__ __launch_bounds__(256) void k_adj_decide(
     const float inv_s2 = bp.inv_s2f;
     LeafEntry *mylist = list + grp * kListPerGroup + (int64_t)sub * split.segcap;
     double GQ[3] = {0, 0, 0}, GP[3] = {0, 0, 0};
-    unsigned c_pairs = 0, c_mono = 0;
+    u64 c_pairs = 0, c_mono = 0;  // wave totals (scalars)
     int nlist = 0;
 
     // the start block: the root's children (decided by every wave, their
@@ -187,7 +187,7 @@ __global__ __launch_bounds__(256) void k_adj_decide(
         L.d.first[0] = start;
         L.d.count[0] = start_n;
         L.d.mask[0] = live;
-        L.d.own[0] = rchild == 0 ? kOwnAll : kOwnTop;
+        L.d.own[0] = rchild == 0 ? kOwnAll : 0;
         sp = 1;
         load_block(nodes, adj, start, start_n, lane, L);
     }
@@ -197,26 +197,27 @@ __global__ __launch_bounds__(256) void k_adj_decide(
         const int bc = __builtin_amdgcn_readfirstlane(L.d.count[sp]);
         const int bfirst = __builtin_amdgcn_readfirstlane(L.d.first[sp]);
         const int own = __builtin_amdgcn_readfirstlane(L.d.own[sp]);
-        const u64 m = L.d.mask[sp];
+        const u64 m = uniform_u64(L.d.mask[sp]);
         const bool mine = (m >> lane) & 1ull;
-        const bool rec = own != kOwnTop || sub == 0;  // this wave records the block's results
-        const int child_own = own == kOwnTop ? kOwnDealt : kOwnAll;
+        const bool rec = own < 0 || sub == 0;  // this wave records the block's results
+        const int child_own = child_ownership(own);
         for (int k = 0; k < bc; ++k) {
             if (own == kOwnDealt && (bfirst + k) % split.nsub != sub) continue;  // another wave's
             const BhNode nd = L.d.node[k];
-            bool need = false;
-            if (mine) {
-                if (!decide(nd, xd, yd, zd, bp)) {
-                    need = true;
-                } else if (rec) {
+            const int nn = __builtin_amdgcn_readfirstlane(nd.n);
+            u64 approx = 0ull;
+            if (nn >= 2) {  // a single point is never approximated
+                double d[3];
+                const bool ap = decide_far(nd, xd, yd, zd, bp, d) && mine;
+                approx = __ballot(ap);
+                if (rec && ap) {
                     // n_k virtual points: (C, P / n, A / n, B / n)
                     const float Ax = (float)L.adj[k][0], Ay = (float)L.adj[k][1],
                                 Az = (float)L.adj[k][2];
-                    const float inv_n = 1.f / (float)nd.n;
+                    const float inv_n = 1.f / (float)nn;
                     const float mbx = (float)L.adj[k][3] * inv_n, mby = (float)L.adj[k][4] * inv_n,
                                 mbz = (float)L.adj[k][5] * inv_n;
-                    const float dx = (float)(xd - nd.cx), dy = (float)(yd - nd.cy),
-                                dz = (float)(zd - nd.cz);
+                    const float dx = (float)d[0], dy = (float)d[1], dz = (float)d[2];
                     const float g =
                         __builtin_amdgcn_exp2f((dx * dx + dy * dy + dz * dz) * bp.negc);
                     const float s = xp.x * nd.px + xp.y * nd.py + xp.z * nd.pz;
@@ -233,30 +234,29 @@ __global__ __launch_bounds__(256) void k_adj_decide(
                     GP[0] += (double)(g * Ax + w3 * nd.px);
                     GP[1] += (double)(g * Ay + w3 * nd.py);
                     GP[2] += (double)(g * Az + w3 * nd.pz);
-                    ++c_mono;
                 }
             }
-            const u64 open = __ballot(need);
+            const u64 open = m & ~approx;
+            if (rec) c_mono += (u64)__popcll(approx);
             if (open == 0ull) continue;
             const int nfirst = __builtin_amdgcn_readfirstlane(nd.first);
-            const int ncount = __builtin_amdgcn_readfirstlane(nd.n);
             const int nchild = __builtin_amdgcn_readfirstlane(nd.nchild);
             if (nchild == 0) {
                 if (!rec) continue;
-                if (need) c_pairs += (unsigned)ncount;
+                c_pairs += (u64)__popcll(open) * (u64)nn;
                 if (nlist < split.segcap) {
                     if (lane == 0) {
                         LeafEntry e;
                         e.mask = open;
                         e.first = nfirst;
-                        e.count = ncount;
+                        e.count = nn;
                         mylist[nlist] = e;
                     }
                     ++nlist;
                 } else {  // segment full: sum this leaf here
                     const float4 xc = active ? Qc[t] : z4;
-                    leaf_adjoint(Qc, Ps, As, Bs, nfirst, ncount, need, xc, xp, xa, xb, bp.negc,
-                                 inv_s2, GQ, GP);
+                    leaf_adjoint(Qc, Ps, As, Bs, nfirst, nn, (open >> lane) & 1ull, xc, xp, xa,
+                                 xb, bp.negc, inv_s2, GQ, GP);
                 }
             } else {
                 if (sp >= kBlockStack) {
@@ -281,16 +281,10 @@ __global__ __launch_bounds__(256) void k_adj_decide(
     }
     write_part(part, sub, npad, grp * 64 + lane, GQ, GP);
     if (lane == 0) list_n[grp * kSub + sub] = nlist;
-    u64 cp = c_pairs, cm = c_mono;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        cp += __shfl_down(cp, off, 64);
-        cm += __shfl_down(cm, off, 64);
-    }
-    if (lane == 0 && counters && (cp != 0 || cm != 0)) {
+    if (lane == 0 && counters && (c_pairs != 0 || c_mono != 0)) {
         u64 *c = counter_slot(counters, blockIdx.x);
-        if (cp) atomicAdd(&c[0], cp);
-        if (cm) atomicAdd(&c[1], cm);
+        if (c_pairs) atomicAdd(&c[0], c_pairs);
+        if (c_mono) atomicAdd(&c[1], c_mono);
     }
 }
 

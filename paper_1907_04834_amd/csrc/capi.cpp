@@ -1112,8 +1112,8 @@ gs_status gs_tree_export(const float *q, const float *p, int64_t n, const gs_par
         node_count[k] = d.n;
         node_first[k] = d.first;
         node_nchild[k] = d.nchild;
-        const double st[13] = {d.cx, d.cy, d.cz, d.px, d.py, d.pz, d.lox, d.loy, d.loz,
-                               d.hix, d.hiy, d.hiz, d.s2};
+        const double st[13] = {d.cx, d.cy, d.cz, d.px, d.py, d.pz, d.lo[0], d.lo[1], d.lo[2],
+                               d.hi[0], d.hi[1], d.hi[2], d.s2};
         memcpy(node_stats + 13 * k, st, sizeof(st));
     }
     return GS_OK;
@@ -1154,7 +1154,7 @@ gs_status gs_bh_counters(const void *ws, hipStream_t stream, int64_t out[GS_BH_C
     for (int k = 0; k < GS_BH_COUNTERS; ++k) {
         unsigned long long v = 0;
         for (int s = 0; s < kCounterSlots; ++s)
-            v = k == 6 ? (c[s][k] > v ? c[s][k] : v) : v + c[s][k];
+            v = k >= 6 ? (c[s][k] > v ? c[s][k] : v) : v + c[s][k];
         out[k] = (int64_t)v;
     }
     return GS_OK;

@@ -58,10 +58,23 @@ struct LeafEntry {
 };
 
 // Ownership of a block of sibling nodes among the phase-1 waves of a group.
-constexpr int kOwnAll = 0;    // this wave's own subtree: it takes every node
-constexpr int kOwnTop = 1;    // the root's children: every wave decides them,
-                              // wave 0 records their monopoles, leaves, visits
-constexpr int kOwnDealt = 2;  // their children: node i belongs to wave i % nsub
+// A block at depth d >= 0 below the root (the root's children are depth 0)
+// with d < kDealDepth is decided by every wave, and wave 0 records its
+// monopoles, leaves and visits; the blocks at depth kDealDepth are dealt out,
+// node i to wave i % nsub; below those, a wave takes every node of its own
+// subtrees.
+#ifndef GS_DEAL_DEPTH
+#define GS_DEAL_DEPTH 1
+#endif
+constexpr int kDealDepth = GS_DEAL_DEPTH;
+static_assert(kDealDepth >= 1, "the root's children are decided by every wave");
+constexpr int kOwnAll = -2;    // this wave's own subtree: it takes every node
+constexpr int kOwnDealt = -1;  // node i belongs to wave i % nsub
+// (own >= 0: a shared block at that depth)
+__device__ __forceinline__ int child_ownership(int own) {
+    if (own < 0) return kOwnAll;
+    return own + 1 < kDealDepth ? own + 1 : kOwnDealt;
+}
 
 struct DecideLds {
     u64 mask[kBlockStack];

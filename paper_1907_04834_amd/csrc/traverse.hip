@@ -250,7 +250,11 @@ __device__ __forceinline__ void leaf_stream(const float4 *__restrict__ Qs,
     }
 }
 
-// Phase 1: decisions, monopoles and the group's list of leaves.
+// Phase 1: decisions, monopoles and the group's list of leaves.  Every lane
+// evaluates the decision of every node the wave reaches (the VALU issues for
+// the whole wave either way); the ballot restricted to the block's mask gives
+// the lanes that approximate it, and the wave's counters are kept as scalars
+// from the masks.
 template <bool WITH_A>
 __global__ __launch_bounds__(256) void k_bh_decide(
     const BhNode *__restrict__ nodes, const float4 *__restrict__ Qs,
@@ -275,7 +279,8 @@ __global__ __launch_bounds__(256) void k_bh_decide(
 
     double V[3] = {0, 0, 0}, A[3] = {0, 0, 0};
     float mv[3] = {0.f, 0.f, 0.f}, ma[3] = {0.f, 0.f, 0.f};
-    unsigned c_pairs = 0, c_mono = 0, c_visit = 0, w_steps = 0, w_nodes = 0;
+    u64 c_pairs = 0, c_mono = 0, c_visit = 0;  // wave totals (scalars)
+    unsigned w_steps = 0, w_nodes = 0;
     int nlist = 0;
 
     // the start block: the root's children (decided by every wave), or the
@@ -284,20 +289,21 @@ __global__ __launch_bounds__(256) void k_bh_decide(
     const int rfirst = __builtin_amdgcn_readfirstlane(nodes[gd.root].first);
     const int start = rchild == 0 ? (sub == 0 ? gd.root : -1) : rfirst;
     const int start_n = rchild == 0 ? 1 : rchild;
+    const u64 live = __ballot(active);
     if (rchild > 0 && sub == 0) {  // the root's visit, counted once
-        if (active) ++c_visit;
+        c_visit += (u64)__popcll(live);
         ++w_nodes;
     }
     int sp = 0;
-    const u64 live = __ballot(active);
     if (live != 0ull && start >= 0) {
         L.first[0] = start;
         L.count[0] = start_n;
         L.mask[0] = live;
-        L.own[0] = rchild == 0 ? kOwnAll : kOwnTop;
+        L.own[0] = rchild == 0 ? kOwnAll : 0;
         sp = 1;
         float4 *dstn = reinterpret_cast<float4 *>(L.node);
-        if (lane < 5 * start_n) dstn[lane] = reinterpret_cast<const float4 *>(nodes + start)[lane];
+        if (lane < kNodeF4 * start_n)
+            dstn[lane] = reinterpret_cast<const float4 *>(nodes + start)[lane];
     }
     wave_sync();
     while (sp > 0) {
@@ -305,23 +311,23 @@ __global__ __launch_bounds__(256) void k_bh_decide(
         const int bc = __builtin_amdgcn_readfirstlane(L.count[sp]);
         const int bfirst = __builtin_amdgcn_readfirstlane(L.first[sp]);
         const int own = __builtin_amdgcn_readfirstlane(L.own[sp]);
-        const u64 m = L.mask[sp];
+        const u64 m = uniform_u64(L.mask[sp]);
         const bool mine = (m >> lane) & 1ull;
-        const bool rec = own != kOwnTop || sub == 0;  // this wave records the block's results
-        const int child_own = own == kOwnTop ? kOwnDealt : kOwnAll;
+        const bool rec = own < 0 || sub == 0;  // this wave records the block's results
+        const int child_own = child_ownership(own);
         for (int k = 0; k < bc; ++k) {
             if (own == kOwnDealt && (bfirst + k) % split.nsub != sub) continue;  // another wave's
             ++w_nodes;
             const BhNode nd = L.node[k];
-            bool need = false;
-            if (mine) {
-                if (rec) ++c_visit;
-                if (!decide(nd, xd, yd, zd, bp)) {
-                    need = true;
-                } else if (rec) {
+            const int nn = __builtin_amdgcn_readfirstlane(nd.n);
+            u64 approx = 0ull;
+            if (nn >= 2) {  // a single point is never approximated
+                double d[3];
+                const bool ap = decide_far(nd, xd, yd, zd, bp, d) && mine;
+                approx = __ballot(ap);
+                if (rec && ap) {
                     // n_k virtual points at C_k, momentum P_k / n_k each
-                    const float dx = (float)(xd - nd.cx), dy = (float)(yd - nd.cy),
-                                dz = (float)(zd - nd.cz);
+                    const float dx = (float)d[0], dy = (float)d[1], dz = (float)d[2];
                     const float g =
                         __builtin_amdgcn_exp2f((dx * dx + dy * dy + dz * dz) * bp.negc);
                     mv[0] += g * nd.px;
@@ -333,31 +339,34 @@ __global__ __launch_bounds__(256) void k_bh_decide(
                         ma[1] += w * dy;
                         ma[2] += w * dz;
                     }
-                    ++c_mono;
                 }
             }
-            const u64 open = __ballot(need);
+            const u64 open = m & ~approx;
+            if (rec) {
+                c_visit += (u64)__popcll(m);
+                c_mono += (u64)__popcll(approx);
+            }
             if (open == 0ull) continue;
             const int nfirst = __builtin_amdgcn_readfirstlane(nd.first);
-            const int ncount = __builtin_amdgcn_readfirstlane(nd.n);
             const int nchild = __builtin_amdgcn_readfirstlane(nd.nchild);
             if (nchild == 0) {
                 if (!rec) continue;
-                if (need) c_pairs += (unsigned)ncount;
+                c_pairs += (u64)__popcll(open) * (u64)nn;
                 if (nlist < split.segcap) {
                     if (lane == 0) {
                         LeafEntry e;
                         e.mask = open;
                         e.first = nfirst;
-                        e.count = ncount;
+                        e.count = nn;
                         mylist[nlist] = e;
                     }
                     ++nlist;
                 } else {
                     // list full: sum this leaf here
-                    w_steps += (unsigned)ncount;
+                    w_steps += (unsigned)nn;
                     const float4 xc = active ? Qc[t] : make_float4(0.f, 0.f, 0.f, 0.f);
-                    leaf_direct<WITH_A>(Qc, Ps, nfirst, ncount, need, xc, xp, bp.negc, V, A);
+                    leaf_direct<WITH_A>(Qc, Ps, nfirst, nn, (open >> lane) & 1ull, xc, xp,
+                                        bp.negc, V, A);
                 }
             } else {
                 if (sp >= kBlockStack) {
@@ -375,10 +384,10 @@ __global__ __launch_bounds__(256) void k_bh_decide(
         }
         if (sp < 0) break;
         wave_sync();
-        // the next block's node records (5 x 16 B per node)
+        // the next block's node records
         if (sp > 0) {
             const int nf = __builtin_amdgcn_readfirstlane(L.first[sp - 1]);
-            const int pre_n = 5 * __builtin_amdgcn_readfirstlane(L.count[sp - 1]);
+            const int pre_n = kNodeF4 * __builtin_amdgcn_readfirstlane(L.count[sp - 1]);
             if (lane < pre_n)
                 reinterpret_cast<float4 *>(L.node)[lane] =
                     reinterpret_cast<const float4 *>(nodes + nf)[lane];
@@ -393,23 +402,17 @@ __global__ __launch_bounds__(256) void k_bh_decide(
     write_part(part, sub, npad, grp * 64 + lane, V, A);
     if (lane == 0) list_n[grp * kSub + sub] = nlist;
 
-    // counters: wave sums, one atomic per wave (integer, order-free)
-    u64 cp = c_pairs, cm = c_mono, cv = c_visit;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        cp += __shfl_down(cp, off, 64);
-        cm += __shfl_down(cm, off, 64);
-        cv += __shfl_down(cv, off, 64);
-    }
-    if (lane == 0 && counters && (cv != 0 || w_nodes != 0)) {
+    // counters: one atomic per wave and counter (integer, order-free)
+    if (lane == 0 && counters && (c_visit != 0 || w_nodes != 0)) {
         u64 *c = counter_slot(counters, blockIdx.x);
-        if (cp) atomicAdd(&c[0], cp);
-        if (cm) atomicAdd(&c[1], cm);
-        atomicAdd(&c[2], cv);
+        if (c_pairs) atomicAdd(&c[0], c_pairs);
+        if (c_mono) atomicAdd(&c[1], c_mono);
+        atomicAdd(&c[2], c_visit);
         if (grp == 0 && sub == 0) atomicAdd(&c[3], (u64)totals->n_nodes);
         if (w_steps) atomicAdd(&c[4], (u64)w_steps);
         atomicAdd(&c[5], (u64)w_nodes);
         atomicMax(&c[6], (u64)w_steps + (u64)w_nodes);
+        atomicMax(&c[7], (u64)w_nodes);
     } else if (lane == 0 && counters && grp == 0 && sub == 0) {
         atomicAdd(&counter_slot(counters, blockIdx.x)[3], (u64)totals->n_nodes);
     }
@@ -551,9 +554,16 @@ size_t traverse_count_ints(int64_t groups) { return (size_t)groups * kSub; }
 
 // Phase-1 waves aim at about kDecideWaves waves in all (12 per SIMD), phase-2
 // waves at kLeafWaves; a sweep of both on the 200k ellipsoids and on the
-// 64-subject population found these best.
-constexpr int64_t kDecideWaves = 12288;
-constexpr int64_t kLeafWaves = 65536;
+// 64-subject population found these best (other values are compiled only by
+// a tuning build).
+#ifndef GS_DECIDE_WAVES
+#define GS_DECIDE_WAVES 12288
+#endif
+#ifndef GS_LEAF_WAVES
+#define GS_LEAF_WAVES 65536
+#endif
+constexpr int64_t kDecideWaves = GS_DECIDE_WAVES;
+constexpr int64_t kLeafWaves = GS_LEAF_WAVES;
 
 namespace trav {
 TravSplit traverse_split(int64_t groups) {

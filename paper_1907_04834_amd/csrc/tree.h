@@ -23,18 +23,22 @@ __device__ inline unsigned long long *counter_slot(unsigned long long *c, unsign
     return c + (size_t)((bx + by) % kCounterSlots) * GS_BH_COUNTERS;
 }
 
-// One node as the traversal reads it (80 bytes; wave-uniform loads).
+// One node as the traversal reads it (112 bytes, staged as 7 float4s).  The
+// tight box is stored in FP64: it is the exact FP32 box, converted once here
+// instead of at every decision.
 struct alignas(16) BhNode {
     double cx, cy, cz;  // centre of the member positions (mean, FP64)
     double s2;          // (largest side of the tight box)^2, FP64
-    float lox, loy, loz, hix;
-    float hiy, hiz, px, py;  // tight box (exact), total momentum (FP32)
-    float pz;
-    int n;       // number of points
-    int first;   // leaf: first sorted point; internal: first child node
-    int nchild;  // 0 for a leaf
+    double lo[3];       // tight box (exact: FP64 of the FP32 bounds)
+    double hi[3];
+    float px, py, pz;   // total momentum (FP32)
+    int n;              // number of points
+    int first;          // leaf: first sorted point; internal: first child node
+    int nchild;         // 0 for a leaf
+    int pad0, pad1;
 };
-static_assert(sizeof(BhNode) == 80, "BhNode layout");
+static_assert(sizeof(BhNode) == 112, "BhNode layout");
+constexpr int kNodeF4 = (int)(sizeof(BhNode) / 16);  // float4s per node record
 
 // Device-side header of the tree of one point set (one per subject when
 // several independent point sets are built together as a forest).
@@ -148,38 +152,39 @@ struct BhParams {
 };
 BhParams make_bh_params(const gs_params &prm);
 
-// The decision for target x and node nd (FP64, in the order of the
-// definition): approximate when the node holds >= 2 points, the distance from
-// x to its tight box is at least kappa sigma, and s_k^2 < theta^2 |x - C_k|^2.
-__device__ __forceinline__ bool decide(const BhNode &nd, double x, double y, double z,
-                              const BhParams &bp) {
+// The decision for target x and node nd with n_k >= 2 (FP64, in the order of
+// the definition; n_k is the same for every target, so callers test it once):
+// approximate when the distance from x to the node's tight box is at least
+// kappa sigma and s_k^2 < theta^2 |x - C_k|^2.  d receives x - C_k (FP64).
+// The distance to the box adds, per axis in order, the square of
+// max(lo - x, x - hi) when it is positive; adding the square of max(that, 0)
+// instead gives the same FP64 sum (a skipped term adds an exact zero).
+__device__ __forceinline__ bool decide_far(const BhNode &nd, double x, double y, double z,
+                                          const BhParams &bp, double *d) {
 #pragma clang fp contract(off)
-    double dmin2 = 0.0;
-    {
-        const double below = (double)nd.lox - x, above = x - (double)nd.hix;
-        const double g = below > above ? below : above;
-        if (g > 0.0) dmin2 += g * g;
-    }
-    {
-        const double below = (double)nd.loy - y, above = y - (double)nd.hiy;
-        const double g = below > above ? below : above;
-        if (g > 0.0) dmin2 += g * g;
-    }
-    {
-        const double below = (double)nd.loz - z, above = z - (double)nd.hiz;
-        const double g = below > above ? below : above;
-        if (g > 0.0) dmin2 += g * g;
-    }
+    const double gx = fmax(fmax(nd.lo[0] - x, x - nd.hi[0]), 0.0);
+    const double gy = fmax(fmax(nd.lo[1] - y, y - nd.hi[1]), 0.0);
+    const double gz = fmax(fmax(nd.lo[2] - z, z - nd.hi[2]), 0.0);
+    double dmin2 = gx * gx;
+    dmin2 += gy * gy;
+    dmin2 += gz * gz;
+    d[0] = x - nd.cx;
+    d[1] = y - nd.cy;
+    d[2] = z - nd.cz;
+    double d2 = d[0] * d[0];
+    d2 += d[1] * d[1];
+    d2 += d[2] * d[2];
     const bool far = dmin2 >= bp.cut2;
-    const double dx = x - nd.cx, dy = y - nd.cy, dz = z - nd.cz;
-    double d2 = dx * dx;
-    d2 += dy * dy;
-    d2 += dz * dz;
     const bool mac = bp.theta_inf || (nd.s2 < bp.th2 * d2);
-    return nd.n >= 2 && far && mac;
+    return far && mac;
 }
 
-
+// A wave-uniform 64-bit value held in LDS or VGPRs, as scalars.
+__device__ __forceinline__ unsigned long long uniform_u64(unsigned long long v) {
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)v);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(v >> 32));
+    return ((unsigned long long)hi << 32) | lo;
+}
 
 // Forward traversal.  Writes (v, a) for every point in original order: as FP32
 // into dq/dp when they are non-null, else it advances the FP64 state

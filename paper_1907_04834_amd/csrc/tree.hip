@@ -584,8 +584,9 @@ __global__ __launch_bounds__(256) void k_children(const u64 *__restrict__ K,
 
 __device__ inline void zero_stats(BhNode &nd) {
     nd.cx = nd.cy = nd.cz = nd.s2 = 0.0;
-    nd.lox = nd.loy = nd.loz = nd.hix = nd.hiy = nd.hiz = 0.f;
+    for (int c = 0; c < 3; ++c) nd.lo[c] = nd.hi[c] = 0.0;
     nd.px = nd.py = nd.pz = 0.f;
+    nd.pad0 = nd.pad1 = 0;
 }
 
 // Root records: one thread per set, after the scans.  Node s is the root of
@@ -675,14 +676,10 @@ __device__ inline void finish_node(BhNode &nd, const double *sum, const float *l
     nd.px = (float)sum[3];
     nd.py = (float)sum[4];
     nd.pz = (float)sum[5];
-    nd.lox = lo[0];
-    nd.loy = lo[1];
-    nd.loz = lo[2];
-    nd.hix = hi[0];
-    nd.hiy = hi[1];
-    nd.hiz = hi[2];
     double s = 0.0;
     for (int c = 0; c < 3; ++c) {
+        nd.lo[c] = (double)lo[c];
+        nd.hi[c] = (double)hi[c];
         const double side = (double)hi[c] - (double)lo[c];
         if (side > s) s = side;
     }

@@ -441,7 +441,8 @@ def gs_bh_counters(ws) -> dict:
     out = (ctypes.c_int64 * 8)()
     _check(lib().gs_bh_counters(_ptr(ws), _stream(ws.device), out))
     return {"pairs": out[0], "monopoles": out[1], "visits": out[2], "nodes": out[3],
-            "wave_leaf_steps": out[4], "wave_node_decisions": out[5], "max_wave_work": out[6]}
+            "wave_leaf_steps": out[4], "wave_node_decisions": out[5], "max_wave_work": out[6],
+            "max_decide_wave_nodes": out[7]}
 
 
 def gs_kernel_timing(enable: bool):
