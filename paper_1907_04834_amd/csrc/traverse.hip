@@ -163,23 +163,38 @@ __device__ inline void batch_get(const EntryBatch &b, int v, int &first, int &co
            (u64)(unsigned)__builtin_amdgcn_readlane(b.mlo, i);
 }
 
-// The leaves of list entries [v0, v1) as one stream of source groups: the
-// next group of B sources (the next leaf's first group at the end of a leaf)
-// is loaded while the current group is evaluated.  Every lane evaluates
-// every leaf and adds the leaf's FP32 sums to its FP64 sums only when the
-// leaf's mask holds it; per leaf the sums are those of leaf_direct (groups of
-// B in order, then single sources).
-template <bool WITH_A>
-__device__ __forceinline__ void leaf_stream(const float4 *__restrict__ Qs,
-                                            const float4 *__restrict__ Ps,
-                                            const LeafEntry *__restrict__ list,
-                                            const int *__restrict__ list_n, int64_t grp,
-                                            TravSplit split, int v0, int v1, int lane, float4 xq,
-                                            float4 xp, float negc, double *V, double *A,
-                                            unsigned &steps) {
-    constexpr int B = 4;
-    if (v0 >= v1) return;
-    EntryBatch eb;
+// List entries needed by at most kSparseMax of the wave's targets, of at
+// most 64 points, are summed compacted (see leaf_sparse); the others by every
+// lane (leaf_dense).  (A leaf can exceed leaf_cap only when its points share
+// one level-21 cell.)
+constexpr int kSparseMax = 32;
+__device__ inline bool sparse_entry(int count, u64 mask) {
+    return __popcll(mask) <= kSparseMax && count <= 64;
+}
+
+struct LeafLds {
+    float4 tq[64], tp[64];  // the wave's targets (positions in the set's frame, momenta)
+    float4 sq[64], sp[64];  // the sources of the sparse entry being summed
+    int slot[64];           // the lanes of the entry's mask, by rank
+};
+
+// The next dense entry at or after v (v1 if none); its fields in first /
+// count / mask.
+__device__ inline int next_dense(EntryBatch &eb, const LeafEntry *__restrict__ list, int v,
+                                 int lane, int &first, int &count, u64 &mask) {
+    for (; v < eb.v1; ++v) {
+        if (v - eb.vb >= 64) batch_load(eb, list, v, lane);
+        batch_get(eb, v, first, count, mask);
+        if (!sparse_entry(count, mask)) return v;
+    }
+    first = count = 0;
+    mask = 0ull;
+    return v;
+}
+
+__device__ inline void entry_batch_init(EntryBatch &eb, const LeafEntry *__restrict__ list,
+                                        const int *__restrict__ list_n, int64_t grp,
+                                        TravSplit split, int v0, int v1, int lane) {
     eb.base = grp * kListPerGroup;
     eb.nsub = split.nsub;
     eb.segcap = split.segcap;
@@ -187,24 +202,41 @@ __device__ __forceinline__ void leaf_stream(const float4 *__restrict__ Qs,
 #pragma unroll
     for (int k = 0; k < kSub; ++k) eb.segn[k] = k < split.nsub ? list_n[grp * kSub + k] : 0;
     batch_load(eb, list, v0, lane);
+}
+
+// The dense entries of [v0, v1) as one stream of source groups: the next
+// group of B sources (the next dense leaf's first group at the end of a leaf)
+// is loaded while the current group is evaluated.  Every lane evaluates every
+// leaf and adds the leaf's FP32 sums to its FP64 sums only when the leaf's
+// mask holds it; per leaf the sums are those of leaf_direct (groups of B in
+// order, then single sources).
+template <bool WITH_A>
+__device__ __forceinline__ void leaf_dense(const float4 *__restrict__ Qs,
+                                           const float4 *__restrict__ Ps,
+                                           const LeafEntry *__restrict__ list,
+                                           const int *__restrict__ list_n, int64_t grp,
+                                           TravSplit split, int v0, int v1, int lane, float4 xq,
+                                           float4 xp, float negc, double *V, double *A,
+                                           unsigned &steps) {
+    constexpr int B = 4;
+    if (v0 >= v1) return;
+    EntryBatch eb;
+    entry_batch_init(eb, list, list_n, grp, split, v0, v1, lane);
     int first, count;
     u64 mask;
-    batch_get(eb, v0, first, count, mask);
+    int v = next_dense(eb, list, v0, lane, first, count, mask);
     float4 qn[B], pn[B];
-    if (count >= B) {
+    if (v < v1 && count >= B) {
 #pragma unroll
         for (int u = 0; u < B; ++u) {
             qn[u] = uniform_f4(Qs[first + u]);
             pn[u] = uniform_f4(Ps[first + u]);
         }
     }
-    for (int v = v0; v < v1; ++v) {
+    while (v < v1) {
         int nfirst = 0, ncount = 0;
         u64 nmask = 0ull;
-        if (v + 1 < v1) {
-            if (v + 1 - eb.vb == 64) batch_load(eb, list, v + 1, lane);
-            batch_get(eb, v + 1, nfirst, ncount, nmask);
-        }
+        const int vn = next_dense(eb, list, v + 1, lane, nfirst, ncount, nmask);
         steps += (unsigned)count;
         const int end = first + count;
         float tv[3] = {0.f, 0.f, 0.f}, ta[3] = {0.f, 0.f, 0.f};
@@ -216,8 +248,8 @@ __device__ __forceinline__ void leaf_stream(const float4 *__restrict__ Qs,
                 qj[u] = qn[u];
                 pj[u] = pn[u];
             }
-            // ahead: this leaf's next group, else the next leaf's first group,
-            // else (nothing to load) this leaf's last B points again
+            // ahead: this leaf's next group, else the next dense leaf's first
+            // group, else (nothing to load) this leaf's last B points again
             const int jn = j + 2 * B <= end ? j + B : (ncount >= B ? nfirst : end - B);
 #pragma unroll
             for (int u = 0; u < B; ++u) {
@@ -244,6 +276,104 @@ __device__ __forceinline__ void leaf_stream(const float4 *__restrict__ Qs,
                 if (WITH_A) A[c] += (double)ta[c];
             }
         }
+        first = nfirst;
+        count = ncount;
+        mask = nmask;
+        v = vn;
+    }
+}
+
+// The sparse entries of [v0, v1), compacted: with k targets in the mask and
+// k' the power of two >= k, lane l takes target slot i = l mod k' (the i-th
+// lane of the mask) and source rows r = l / k' + R j, R = 64 / k', so R rows
+// run side by side; the leaf's points are staged in LDS (the next sparse
+// leaf's points are loaded while the current one is summed).  The R partial
+// sums of a target are added across lanes (butterfly over the row bits) and
+// moved to the target's lane, which adds them to its FP64 sums.
+template <bool WITH_A>
+__device__ __forceinline__ void leaf_sparse(const float4 *__restrict__ Qs,
+                                            const float4 *__restrict__ Ps,
+                                            const LeafEntry *__restrict__ list,
+                                            const int *__restrict__ list_n, int64_t grp,
+                                            TravSplit split, int v0, int v1, int lane,
+                                            float negc, LeafLds &L, double *V, double *A,
+                                            unsigned &steps) {
+    if (v0 >= v1) return;
+    EntryBatch eb;
+    entry_batch_init(eb, list, list_n, grp, split, v0, v1, lane);
+    const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    // the first sparse entry and its points (in registers, lane l: point l)
+    int v = v0, first = 0, count = 0;
+    u64 mask = 0ull;
+    for (; v < v1; ++v) {
+        if (v - eb.vb >= 64) batch_load(eb, list, v, lane);
+        batch_get(eb, v, first, count, mask);
+        if (sparse_entry(count, mask)) break;
+    }
+    float4 rq = z4, rp = z4;
+    if (v < v1 && lane < count) {
+        rq = Qs[first + lane];
+        rp = Ps[first + lane];
+    }
+    while (v < v1) {
+        // stage this entry's points, then look for the next sparse entry and
+        // load its points while this one is summed
+        wave_sync();
+        L.sq[lane] = rq;
+        L.sp[lane] = rp;
+        const int k = __popcll(mask);
+        const u64 below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+        if ((mask >> lane) & 1ull) L.slot[__popcll(mask & below)] = lane;
+        int vn = v + 1, nfirst = 0, ncount = 0;
+        u64 nmask = 0ull;
+        for (; vn < v1; ++vn) {
+            if (vn - eb.vb >= 64) batch_load(eb, list, vn, lane);
+            batch_get(eb, vn, nfirst, ncount, nmask);
+            if (sparse_entry(ncount, nmask)) break;
+        }
+        if (vn < v1 && lane < ncount) {
+            rq = Qs[nfirst + lane];
+            rp = Ps[nfirst + lane];
+        }
+        wave_sync();
+        const int lg = k <= 1 ? 0 : 32 - __clz(k - 1);  // k' = 2^lg >= k
+        const int R = 64 >> lg;
+        const int i = lane & ((1 << lg) - 1), r = lane >> lg;
+        const bool valid = i < k;
+        const int tl = valid ? L.slot[i] : 0;
+        const float4 xq = L.tq[tl], xp = L.tp[tl];
+        float tv[3] = {0.f, 0.f, 0.f}, ta[3] = {0.f, 0.f, 0.f};
+        if (valid)
+            for (int j = r; j < count; j += R) {
+                const float4 qj = L.sq[j], pj = L.sp[j];
+                group_pairs<WITH_A, 1>(&qj, &pj, xq, xp, negc, tv, ta);
+            }
+        steps += (unsigned)((count + R - 1) / R);
+        // add the R rows of each target slot (lanes i + k' r)
+        for (int off = 1 << lg; off < 64; off <<= 1) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                tv[c] += __shfl_xor(tv[c], off, 64);
+                if (WITH_A) ta[c] += __shfl_xor(ta[c], off, 64);
+            }
+        }
+        // lane of mask rank s holds slot s's sums in lane s
+        const int rank = __popcll(mask & below);
+        const bool mine = (mask >> lane) & 1ull;
+        float gv[3], ga[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            gv[c] = __shfl(tv[c], rank, 64);
+            ga[c] = WITH_A ? __shfl(ta[c], rank, 64) : 0.f;
+        }
+        if (mine) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                V[c] += (double)gv[c];
+                if (WITH_A) A[c] += (double)ga[c];
+            }
+        }
+        v = vn;
         first = nfirst;
         count = ncount;
         mask = nmask;
@@ -443,10 +573,15 @@ __global__ __launch_bounds__(256) void k_bh_leaves(const float4 *__restrict__ Qc
     const bool active = lane < gd.count;
     const float4 xq = active ? Qc[t] : make_float4(0.f, 0.f, 0.f, 0.f);
     const float4 xp = active ? Ps[t] : make_float4(0.f, 0.f, 0.f, 0.f);
+    __shared__ LeafLds lds_all[4];
+    LeafLds &L = lds_all[wv];
+    L.tq[lane] = xq;
+    L.tp[lane] = xp;
     double V[3] = {0, 0, 0}, A[3] = {0, 0, 0};
     unsigned steps = 0;
-    leaf_stream<WITH_A>(Qc, Ps, list, list_n, grp, split, v0, v1, lane, xq, xp, negc, V, A,
-                        steps);
+    leaf_dense<WITH_A>(Qc, Ps, list, list_n, grp, split, v0, v1, lane, xq, xp, negc, V, A,
+                       steps);
+    leaf_sparse<WITH_A>(Qc, Ps, list, list_n, grp, split, v0, v1, lane, negc, L, V, A, steps);
     write_part(part, split.nsub + chunk, npad, grp * 64 + lane, V, A);
     if (lane == 0 && counters) {
         u64 *c = counter_slot(counters, blockIdx.x, blockIdx.y);
