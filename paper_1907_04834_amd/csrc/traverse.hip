@@ -167,7 +167,10 @@ __device__ inline void batch_get(const EntryBatch &b, int v, int &first, int &co
 // most 64 points, are summed compacted (see leaf_sparse); the others by every
 // lane (leaf_dense).  (A leaf can exceed leaf_cap only when its points share
 // one level-21 cell.)
-constexpr int kSparseMax = 32;
+#ifndef GS_SPARSE_MAX
+#define GS_SPARSE_MAX 32
+#endif
+constexpr int kSparseMax = GS_SPARSE_MAX;  // a tuning build may change it (at most 32)
 __device__ inline bool sparse_entry(int count, u64 mask) {
     return __popcll(mask) <= kSparseMax && count <= 64;
 }

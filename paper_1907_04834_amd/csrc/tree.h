@@ -81,8 +81,9 @@ struct TreeBufs {
     int64_t groups;            // traversal groups
     const GroupDesc *gtab;     // [groups] (nullable: group g = points [64g, 64g + 64))
     int bbox_blocks;           // per set
-    int sort_blocks;
-    int sort_per;              // keys per thread of a sort block (tile = 256 x sort_per)
+    int sort_per;              // radix-sort keys per thread (tiles of 256 x sort_per)
+    int sort_tiles;            // radix-sort tiles
+    int sort_sbs;              // superblocks of 16 tiles
     int sort_passes;
     TreeMeta *meta;            // [nsub]
     TreeTotals *totals;
@@ -91,7 +92,8 @@ struct TreeBufs {
     unsigned *valA, *valB;     // ping-pong buffers of the sort
     const unsigned long long *K;  // sorted keys (one of keyA / keyB)
     const unsigned *perm;      // original index of each sorted point
-    unsigned *hist;            // [256][sort_blocks] digit-major counts, then offsets
+    unsigned *hist;            // [sort_tiles][512] digit counts of each tile
+    unsigned *sb;              // [2][sort_sbs][512] digit counts of each superblock
     unsigned *scan_part;       // block sums of the generic scan
     float4 *Qs, *Ps;           // sorted points / momenta (FP32, as given: the decisions)
     float4 *Qc;                // sorted points minus their set's frame origin (FP32, pairs)

@@ -4,9 +4,12 @@
 // Launch sequence of one build (no host synchronisation, so it can be
 // captured in a graph):
 //   bbox_partial -> bbox_final     tight box of every set, E, 2^21/E
-//   morton                         63-bit keys: 21 bits per axis, x highest
-//   8 x (hist, scan, scatter)      stable LSD radix sort of (key, index)
-//   1-2 x (hist, scan, scatter)    (forest only) stable passes on the set
+//   morton_hist                    63-bit keys: 21 bits per axis, x highest,
+//                                  and the first pass's digit counts
+//   7 x ([hist,] scatter)          stable LSD radix sort of (key, index),
+//                                  9-bit digits (the first pass's counts come
+//                                  from morton_hist)
+//   1-2 x (hist, scatter)          (forest only) stable passes on the set
 //                                  index, so each set is sorted in its range
 //   boundaries                     sorted FP32 copies of q, p, summaries of
 //                                  64-point chunks, the split level of every
@@ -17,8 +20,11 @@
 //   children                       child count of every internal node
 //   scan(nchild)                   contiguous child blocks
 //   nodes                          node records (roots, ranges, child links)
-//   chunks1, stats                 summaries of 4096 points; FP64 sums, tight
-//                                  boxes, centres of every node
+//                                  and summaries of 4096 points
+//   stats                          FP64 sums, tight boxes, centres of every
+//                                  node
+// (24 launches for one set; the scans skip their first launch below 2049
+// values.)
 //
 // Tree semantics.  For sorted keys K, the boundary between points i and i+1
 // has split level L = floor(lcp(K_i, K_i+1) / 3) (21 when the keys are equal).
@@ -45,15 +51,6 @@ namespace {
 
 typedef unsigned long long u64;
 
-constexpr int kSortThreads = 256;
-// Keys per thread of a sort block: 2 (tiles of 512 keys) below kSortLargeFrom
-// points, 8 (2048) from there on.  Measured per build: 0.218 / 0.225 / 0.259 ms
-// at 200k and 0.165 / 0.185 / 0.222 ms at 20k points with tiles of 512 / 1024 /
-// 2048 keys, but 0.720 / 0.660 / 0.642 ms for the 1.5M points of a 64-subject
-// batch (fewer blocks, a 4x smaller histogram to scan).
-constexpr int kSortPerSmall = 2;
-constexpr int kSortPerLarge = 8;
-constexpr int64_t kSortLargeFrom = 1000000;
 constexpr int kScanTile = 2048;                            // items per scan block
 constexpr int kChunk = 64;                                 // points per range summary
 
@@ -98,10 +95,19 @@ __device__ inline double frame_origin(float lo, float hi) {
 
 // ---------------------------------------------------------------- bbox
 // grid (blocks per set, sets); partials [set][block][6]
+// With `clear` (nullable) the kernel also zeroes clear[0 .. nclear) (the
+// sort's first superblock counts, before the Morton-key kernel adds into them).
 __global__ __launch_bounds__(256) void k_bbox_partial(const float *__restrict__ q, int64_t n,
                                                       const long long *__restrict__ seg,
-                                                      float *__restrict__ part) {
+                                                      float *__restrict__ part,
+                                                      unsigned *__restrict__ clear,
+                                                      int64_t nclear) {
     __shared__ float red[6][256];
+    if (clear) {
+        const int64_t nb = (int64_t)gridDim.x * gridDim.y;
+        const int64_t b = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+        for (int64_t i = b * 256 + threadIdx.x; i < nclear; i += nb * 256) clear[i] = 0;
+    }
     float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     float bad = 0.f;
     const int64_t a = seg ? seg[blockIdx.y] : 0, b = seg ? seg[blockIdx.y + 1] : n;
@@ -201,105 +207,233 @@ __device__ inline unsigned quantize(float x, float lo, double scale) {
     return (unsigned)f;
 }
 
-__global__ __launch_bounds__(256) void k_morton(const float *__restrict__ q, int64_t n,
-                                                const long long *__restrict__ seg, int nsub,
-                                                const TreeMeta *__restrict__ meta_all,
-                                                u64 *__restrict__ keys,
-                                                unsigned *__restrict__ vals) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const TreeMeta *meta = meta_all + set_of(seg, nsub, i);
-    const double sc = meta->scale;
-    const unsigned cx = quantize(q[3 * i], meta->lo[0], sc);
-    const unsigned cy = quantize(q[3 * i + 1], meta->lo[1], sc);
-    const unsigned cz = quantize(q[3 * i + 2], meta->lo[2], sc);
-    keys[i] = (spread3(cx) << 2) | (spread3(cy) << 1) | spread3(cz);
-    vals[i] = (unsigned)i;
-}
-
 // ---------------------------------------------------------------- radix sort
-// Digit of a pass: shift < 64 selects 8 bits of the key; shift >= 64 selects
-// 8 bits of the set index of the point's original position.
-__device__ inline unsigned rs_digit(u64 key, unsigned val, int shift,
+// Stable LSD radix sort of (key, original index) with 9-bit digits: 7 passes
+// over the 63-bit keys, then (forests) 1 or 2 passes over the set index of
+// the original position, so that each set ends up sorted in its own range.
+// A pass is two launches over tiles of 256 x PER keys:
+//   k_os_hist     per-tile digit counts (one row of kOsBins per tile), also
+//                 added into the row of the tile's superblock (kSbTiles
+//                 consecutive tiles);
+//   k_os_scatter  each tile takes its output offsets from the superblock rows
+//                 before it, the tile rows before it in its own superblock and
+//                 the digit totals (the sum of all superblock rows), ranks its
+//                 keys stably within the tile and writes them.
+// No block waits for another; a tile reads at most (superblocks + 15) rows.
+// The counts of pass 0 are taken by the Morton-key kernel.
+constexpr int kOsBits = 9;
+constexpr int kOsBins = 1 << kOsBits;
+// Keys per thread: 4 (tiles of 1024 keys) below kOsLargeFrom points, 8 (2048)
+// from there on.  Measured per 200k-point build: 0.213 / 0.179 / 0.175 ms
+// with tiles of 2048 / 1024 / 512 keys; per 1.5M-point population build:
+// 0.650 / 0.683 / 1.05 ms (more tiles, more prefix rows to read).
+constexpr int kOsPerSmall = 4;
+constexpr int kOsPerLarge = 8;
+constexpr int64_t kOsLargeFrom = 1000000;
+constexpr int kSbTiles = 16;                    // tiles per superblock
+constexpr int kKeyPasses = 7;                   // 7 x 9 bits cover the 63-bit key
+
+__device__ inline unsigned os_digit(int pass, u64 key, unsigned val,
                                     const long long *__restrict__ seg, int nsub) {
-    if (shift < 64) return (unsigned)(key >> shift) & 255u;
-    return ((unsigned)set_of(seg, nsub, (int64_t)val) >> (shift - 64)) & 255u;
+    if (pass < kKeyPasses) return (unsigned)(key >> (kOsBits * pass)) & (kOsBins - 1);
+    return ((unsigned)set_of(seg, nsub, (int64_t)val) >> (kOsBits * (pass - kKeyPasses))) &
+           (kOsBins - 1);
 }
 
-// Per-block digit counts, digit-major (hist[d * nb + block]), so that one
-// exclusive scan gives every (digit, block) its output offset.
+// The tile's LDS counts -> its row and its superblock's row.
+__device__ inline void os_flush(const unsigned *h, unsigned *__restrict__ hist,
+                                unsigned *__restrict__ sb, int tile) {
+    for (int d = threadIdx.x; d < kOsBins; d += 256) {
+        const unsigned c = h[d];
+        hist[(int64_t)tile * kOsBins + d] = c;
+        if (c) atomicAdd(&sb[(int64_t)(tile / kSbTiles) * kOsBins + d], c);
+    }
+}
+
+// 63-bit Morton keys of a tile (21 bits per axis, x highest), their original
+// indices, and the tile's pass-0 digit counts.
 template <int PER>
-__global__ __launch_bounds__(kSortThreads) void k_rs_hist(const u64 *__restrict__ keys,
-                                                          const unsigned *__restrict__ vals,
-                                                          int64_t n, int shift, int nb,
-                                                          const long long *__restrict__ seg,
-                                                          int nsub, unsigned *__restrict__ hist) {
-    __shared__ unsigned h[256];
-    h[threadIdx.x] = 0;
+__global__ __launch_bounds__(256) void k_morton_hist(const float *__restrict__ q, int64_t n,
+                                                     const long long *__restrict__ seg, int nsub,
+                                                     const TreeMeta *__restrict__ meta_all,
+                                                     u64 *__restrict__ keys,
+                                                     unsigned *__restrict__ vals,
+                                                     unsigned *__restrict__ hist,
+                                                     unsigned *__restrict__ sb) {
+    __shared__ unsigned h[kOsBins];
+    for (int d = threadIdx.x; d < kOsBins; d += 256) h[d] = 0;
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * (kSortThreads * PER);
+    const int64_t base = (int64_t)blockIdx.x * (256 * PER);
     for (int r = 0; r < PER; ++r) {
-        const int64_t i = base + r * kSortThreads + threadIdx.x;
+        const int64_t i = base + r * 256 + threadIdx.x;
         if (i < n) {
-            const unsigned d = shift < 64 ? (unsigned)(keys[i] >> shift) & 255u
-                                          : rs_digit(0ull, vals[i], shift, seg, nsub);
-            atomicAdd(&h[d], 1u);
+            const TreeMeta *meta = meta_all + set_of(seg, nsub, i);
+            const double sc = meta->scale;
+            const unsigned cx = quantize(q[3 * i], meta->lo[0], sc);
+            const unsigned cy = quantize(q[3 * i + 1], meta->lo[1], sc);
+            const unsigned cz = quantize(q[3 * i + 2], meta->lo[2], sc);
+            const u64 key = (spread3(cx) << 2) | (spread3(cy) << 1) | spread3(cz);
+            keys[i] = key;
+            vals[i] = (unsigned)i;
+            atomicAdd(&h[(unsigned)key & (kOsBins - 1)], 1u);
         }
     }
     __syncthreads();
-    hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+    os_flush(h, hist, sb, blockIdx.x);
 }
 
 template <int PER>
-__global__ __launch_bounds__(kSortThreads) void k_rs_scatter(
-    const u64 *__restrict__ kin, const unsigned *__restrict__ vin, u64 *__restrict__ kout,
-    unsigned *__restrict__ vout, int64_t n, int shift, int nb, const long long *__restrict__ seg,
-    int nsub, const unsigned *__restrict__ offs) {
-    __shared__ unsigned base[256];
-    __shared__ unsigned run[256];
-    __shared__ unsigned wcnt[kSortThreads / 64][256];
-    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    // output offset of (digit t, this block) from the scanned histograms
-    base[t] = offs[(int64_t)t * nb + blockIdx.x];
-    run[t] = 0;
-    for (int w = 0; w < kSortThreads / 64; ++w) wcnt[w][t] = 0;
+__global__ __launch_bounds__(256) void k_os_hist(const u64 *__restrict__ keys,
+                                                 const unsigned *__restrict__ vals, int64_t n,
+                                                 int pass, const long long *__restrict__ seg,
+                                                 int nsub, unsigned *__restrict__ hist,
+                                                 unsigned *__restrict__ sb) {
+    __shared__ unsigned h[kOsBins];
+    for (int d = threadIdx.x; d < kOsBins; d += 256) h[d] = 0;
     __syncthreads();
-    const u64 lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const int64_t tile = (int64_t)blockIdx.x * (kSortThreads * PER);
+    const int64_t base = (int64_t)blockIdx.x * (256 * PER);
+    u64 key[PER];
+    unsigned val[PER];
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {  // loads first, then the counts
+        const int64_t i = base + r * 256 + threadIdx.x;
+        key[r] = i < n ? keys[i] : 0ull;
+        val[r] = i < n && pass >= kKeyPasses ? vals[i] : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < PER; ++r)
+        if (base + r * 256 + threadIdx.x < n)
+            atomicAdd(&h[os_digit(pass, key[r], val[r], seg, nsub)], 1u);
+    __syncthreads();
+    os_flush(h, hist, sb, blockIdx.x);
+}
+
+// One pass's scatter.  sb_next (the other superblock buffer) is cleared for
+// the next pass's counts.
+template <int PER>
+__global__ __launch_bounds__(256) void k_os_scatter(
+    const u64 *__restrict__ kin, const unsigned *__restrict__ vin, u64 *__restrict__ kout,
+    unsigned *__restrict__ vout, int64_t n, int pass, const long long *__restrict__ seg,
+    int nsub, const unsigned *__restrict__ hist, const unsigned *__restrict__ sb, int nsb,
+    unsigned *__restrict__ sb_next) {
+    __shared__ unsigned dbase[kOsBins];  // output offset of each digit for this tile
+    __shared__ unsigned run[kOsBins];    // keys of each digit ranked so far
+    __shared__ unsigned wcnt[4][kOsBins];
+    __shared__ unsigned wsum[4];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int tile = blockIdx.x, mysb = tile / kSbTiles;
+    // this thread's keys first, so that their loads overlap the prefix reads
+    const int64_t base = (int64_t)tile * (256 * PER);
+    u64 key[PER];
+    unsigned val[PER];
+#pragma unroll
     for (int r = 0; r < PER; ++r) {
-        const int64_t i = tile + r * kSortThreads + t;
+        const int64_t i = base + r * 256 + t;
+        key[r] = i < n ? kin[i] : 0ull;
+        val[r] = i < n ? vin[i] : 0u;
+    }
+    for (int64_t i = (int64_t)blockIdx.x * 256 + t; i < (int64_t)nsb * kOsBins;
+         i += (int64_t)gridDim.x * 256)
+        sb_next[i] = 0;
+    // digits 2t, 2t + 1: totals, and the counts of the tiles before this one
+    // (every row load is issued before any is added)
+    unsigned tot[2] = {0, 0}, pre[2] = {0, 0};
+    {
+        const int j0 = mysb * kSbTiles;
+        uint2 h[kSbTiles];
+#pragma unroll
+        for (int u = 0; u < kSbTiles; ++u)
+            h[u] = j0 + u < tile
+                       ? *reinterpret_cast<const uint2 *>(hist + (int64_t)(j0 + u) * kOsBins + 2 * t)
+                       : make_uint2(0u, 0u);
+        for (int b0 = 0; b0 < nsb; b0 += 16) {
+            uint2 v[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u)
+                v[u] = b0 + u < nsb ? *reinterpret_cast<const uint2 *>(
+                                          sb + (int64_t)(b0 + u) * kOsBins + 2 * t)
+                                    : make_uint2(0u, 0u);
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                tot[0] += v[u].x;
+                tot[1] += v[u].y;
+                if (b0 + u < mysb) {
+                    pre[0] += v[u].x;
+                    pre[1] += v[u].y;
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kSbTiles; ++u) {
+            pre[0] += h[u].x;
+            pre[1] += h[u].y;
+        }
+    }
+    // exclusive scan of the totals over the digits (thread t holds 2t, 2t+1)
+    const unsigned s2 = tot[0] + tot[1];
+    unsigned incl = s2;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const unsigned u = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += u;
+    }
+    if (lane == 63) wsum[wv] = incl;
+    for (int d = t; d < kOsBins; d += 256) run[d] = 0;
+    for (int w = 0; w < 4; ++w)
+        for (int d = t; d < kOsBins; d += 256) wcnt[w][d] = 0;
+    __syncthreads();
+    unsigned ex = incl - s2;
+    for (int w = 0; w < wv; ++w) ex += wsum[w];
+    dbase[2 * t] = ex + pre[0];
+    dbase[2 * t + 1] = ex + tot[0] + pre[1];
+    __syncthreads();
+    // stable ranks within the tile: rounds in index order, lanes in order
+    const u64 lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    unsigned dig[PER], rank[PER];
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+        const unsigned d = base + r * 256 + t < n ? os_digit(pass, key[r], val[r], seg, nsub) : 0u;
+        dig[r] = d;
+    }
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+        const int64_t i = base + r * 256 + t;
         const bool valid = i < n;
-        u64 key = valid ? kin[i] : 0ull;
-        const unsigned val = valid ? vin[i] : 0u;
-        const unsigned d = valid ? rs_digit(key, val, shift, seg, nsub) : 0u;
-        // lanes of this wave holding the same digit (stable by lane order)
+        const unsigned d = dig[r];
         u64 peers = __ballot(valid);
 #pragma unroll
-        for (int b = 0; b < 8; ++b) {
+        for (int b = 0; b < kOsBits; ++b) {
             const u64 m = __ballot((d >> b) & 1u);
             peers &= ((d >> b) & 1u) ? m : ~m;
         }
         const unsigned lr = __popcll(peers & lt);
         if (valid && lr == 0) wcnt[wv][d] = __popcll(peers);
         __syncthreads();
-        unsigned rank = 0;
+        unsigned rk = 0;
         if (valid) {
-            rank = run[d] + lr;
-            for (int w = 0; w < wv; ++w) rank += wcnt[w][d];
+            rk = run[d] + lr;
+            for (int w = 0; w < wv; ++w) rk += wcnt[w][d];
+        }
+        rank[r] = rk;
+        __syncthreads();
+        for (int d2 = t; d2 < kOsBins; d2 += 256) {
+            unsigned add = 0;
+            for (int w = 0; w < 4; ++w) {
+                add += wcnt[w][d2];
+                wcnt[w][d2] = 0;
+            }
+            run[d2] += add;
         }
         __syncthreads();
-        unsigned add = 0;
-        for (int w = 0; w < kSortThreads / 64; ++w) {
-            add += wcnt[w][t];
-            wcnt[w][t] = 0;
+    }
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+        const int64_t i = base + r * 256 + t;
+        if (i < n) {
+            const unsigned pos = dbase[dig[r]] + rank[r];
+            kout[pos] = key[r];
+            vout[pos] = val[r];
         }
-        run[t] += add;
-        if (valid) {
-            const unsigned pos = base[d] + rank;
-            kout[pos] = key;
-            vout[pos] = val;
-        }
-        __syncthreads();
     }
 }
 
@@ -638,7 +772,20 @@ __global__ __launch_bounds__(256) void k_nodes(const u64 *__restrict__ K, int64_
                                                const unsigned *__restrict__ cstart,
                                                const unsigned *__restrict__ crun,
                                                BhNode *__restrict__ nodes,
-                                               int *__restrict__ node_start) {
+                                               int *__restrict__ node_start,
+                                               const RangeStat *__restrict__ c0, int64_t nc0,
+                                               RangeStat *__restrict__ c1, int64_t nc1) {
+    {  // summaries of 4096 sorted points (one wave each), for the statistics
+        const int64_t waves = (int64_t)gridDim.x * 4;
+        for (int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); c < nc1; c += waves) {
+            RangeStat r;
+            rs_init(r);
+            const int64_t i = c * kChunk + (threadIdx.x & 63);
+            if (i < nc0) r = c0[i];
+            rs_wave_reduce(r);
+            if ((threadIdx.x & 63) == 0) c1[c] = r;
+        }
+    }
     for (int si = blockIdx.x * blockDim.x + threadIdx.x; si < nsub;
          si += gridDim.x * blockDim.x)
         make_root(si, K, n, seg, nsub, leaf_cap, rank, nchild, cstart, totals, meta, nodes,
@@ -844,10 +991,10 @@ void carve_forest(Arena &a, int64_t n, int nsub, int64_t groups, int64_t max_set
     t.gtab = nullptr;
     t.groups = groups;
     t.bbox_blocks = (int)((ms + 2047) / 2048 < 1024 ? (ms + 2047) / 2048 : 1024);
-    t.sort_per = m >= kSortLargeFrom ? kSortPerLarge : kSortPerSmall;
-    const int64_t sort_tile = (int64_t)kSortThreads * t.sort_per;
-    t.sort_blocks = (int)((m + sort_tile - 1) / sort_tile);
-    t.sort_passes = 8 + (nsub > 1 ? (nsub > 256 ? 2 : 1) : 0);
+    t.sort_per = m >= kOsLargeFrom ? kOsPerLarge : kOsPerSmall;
+    t.sort_tiles = (int)((m + 256 * t.sort_per - 1) / (256 * t.sort_per));
+    t.sort_sbs = (t.sort_tiles + kSbTiles - 1) / kSbTiles;
+    t.sort_passes = kKeyPasses + (nsub > 1 ? (nsub > kOsBins ? 2 : 1) : 0);
     t.meta = a.take<TreeMeta>(nsub);
     t.totals = a.take<TreeTotals>(1);
     t.bbox_part = a.take<float>(6 * (size_t)t.bbox_blocks * nsub);
@@ -857,9 +1004,9 @@ void carve_forest(Arena &a, int64_t n, int nsub, int64_t groups, int64_t max_set
     t.valB = a.take<unsigned>(m);
     t.K = (t.sort_passes & 1) ? t.keyB : t.keyA;
     t.perm = (t.sort_passes & 1) ? t.valB : t.valA;
-    t.hist = a.take<unsigned>(256 * (size_t)t.sort_blocks);
-    const int64_t scan_n = m > 256 * (int64_t)t.sort_blocks ? m : 256 * (int64_t)t.sort_blocks;
-    t.scan_part = a.take<unsigned>((scan_n + kScanTile - 1) / kScanTile + 1);
+    t.hist = a.take<unsigned>((size_t)kOsBins * t.sort_tiles);
+    t.sb = a.take<unsigned>((size_t)2 * kOsBins * t.sort_sbs);
+    t.scan_part = a.take<unsigned>((m + kScanTile - 1) / kScanTile + 1);
     t.Qs = a.take<float4>(m);
     t.Ps = a.take<float4>(m);
     t.Qc = a.take<float4>(m);
@@ -890,31 +1037,37 @@ gs_status build_tree(const float *q, const float *p, int64_t n, int leaf_cap, Tr
                      int *status, hipStream_t s) {
     timing_begin(KIND_TREE, s);
     const int nsub = t.nsub;
+    const int64_t sbn = (int64_t)kOsBins * t.sort_sbs;  // counts per superblock buffer
     hipLaunchKernelGGL(k_bbox_partial, dim3(t.bbox_blocks, nsub), dim3(256), 0, s, q, n, t.seg,
-                       t.bbox_part);
+                       t.bbox_part, t.sb, sbn);
     hipLaunchKernelGGL(k_bbox_final, dim3(nsub), dim3(64), 0, s, t.bbox_part, t.bbox_blocks,
                        t.meta, status);
-    hipLaunchKernelGGL(k_morton, dim3(nblk(n)), dim3(256), 0, s, q, n, t.seg, nsub, t.meta,
-                       t.keyA, t.valA);
+    const unsigned tiles = (unsigned)t.sort_tiles;
+    const bool large = t.sort_per == kOsPerLarge;
+    if (large)
+        hipLaunchKernelGGL(k_morton_hist<kOsPerLarge>, dim3(tiles), dim3(256), 0, s, q, n, t.seg,
+                           nsub, t.meta, t.keyA, t.valA, t.hist, t.sb);
+    else
+        hipLaunchKernelGGL(k_morton_hist<kOsPerSmall>, dim3(tiles), dim3(256), 0, s, q, n, t.seg,
+                           nsub, t.meta, t.keyA, t.valA, t.hist, t.sb);
     GS_LAUNCH_CHECK("bbox/morton");
     u64 *ki = t.keyA, *ko = t.keyB;
     unsigned *vi = t.valA, *vo = t.valB;
-    const int nb = t.sort_blocks;
     for (int pass = 0; pass < t.sort_passes; ++pass) {
-        const int shift = 8 * pass;  // passes 8, 9: the set index
-        if (t.sort_per == kSortPerLarge)
-            hipLaunchKernelGGL(k_rs_hist<kSortPerLarge>, dim3(nb), dim3(kSortThreads), 0, s, ki, vi,
-                               n, shift, nb, t.seg, nsub, t.hist);
+        unsigned *sb_cur = t.sb + (pass & 1) * sbn, *sb_next = t.sb + ((pass + 1) & 1) * sbn;
+#define GS_OS_PASS(PER)                                                                       \
+    do {                                                                                      \
+        if (pass > 0)                                                                         \
+            hipLaunchKernelGGL(k_os_hist<PER>, dim3(tiles), dim3(256), 0, s, ki, vi, n, pass,  \
+                               t.seg, nsub, t.hist, sb_cur);                                  \
+        hipLaunchKernelGGL(k_os_scatter<PER>, dim3(tiles), dim3(256), 0, s, ki, vi, ko, vo, n, \
+                           pass, t.seg, nsub, t.hist, sb_cur, t.sort_sbs, sb_next);           \
+    } while (0)
+        if (large)
+            GS_OS_PASS(kOsPerLarge);
         else
-            hipLaunchKernelGGL(k_rs_hist<kSortPerSmall>, dim3(nb), dim3(kSortThreads), 0, s, ki, vi,
-                               n, shift, nb, t.seg, nsub, t.hist);
-        GS_TRY(scan_u32(t.hist, t.hist, 256 * (int64_t)nb, t.scan_part, nullptr, s));
-        if (t.sort_per == kSortPerLarge)
-            hipLaunchKernelGGL(k_rs_scatter<kSortPerLarge>, dim3(nb), dim3(kSortThreads), 0, s, ki,
-                               vi, ko, vo, n, shift, nb, t.seg, nsub, t.hist);
-        else
-            hipLaunchKernelGGL(k_rs_scatter<kSortPerSmall>, dim3(nb), dim3(kSortThreads), 0, s, ki,
-                               vi, ko, vo, n, shift, nb, t.seg, nsub, t.hist);
+            GS_OS_PASS(kOsPerSmall);
+#undef GS_OS_PASS
         u64 *tk = ki;
         ki = ko;
         ko = tk;
@@ -943,8 +1096,7 @@ gs_status build_tree(const float *q, const float *p, int64_t n, int leaf_cap, Tr
     GS_TRY(scan_u32(t.nchild, t.cstart, n > 1 ? n - 1 : 1, t.scan_part, nullptr, s));
     hipLaunchKernelGGL(k_nodes, dim3(node_blocks(n)), dim3(256), 0, s, K, n, t.seg, leaf_cap,
                        nsub, t.totals, t.meta, t.rank, t.nchild, t.cstart, t.crun, t.nodes,
-                       t.node_start);
-    hipLaunchKernelGGL(k_chunks1, dim3(nblk(nc1, 4)), dim3(256), 0, s, c0, nc0, c1, nc1);
+                       t.node_start, c0, nc0, c1, nc1);
     hipLaunchKernelGGL(k_node_stats, dim3(node_blocks(2 * n + nsub)), dim3(256), 0, s, t.Qs, t.Ps, c0,
                        c1, t.totals, t.node_start, t.nodes, t.nsum);
     timing_end(KIND_TREE, s);
@@ -955,7 +1107,7 @@ gs_status build_tree(const float *q, const float *p, int64_t n, int leaf_cap, Tr
 gs_status tree_set_centres(const float *q, TreeBufs &t, double *c0, int *status, hipStream_t s) {
     const int nsub = t.nsub;
     hipLaunchKernelGGL(k_bbox_partial, dim3(t.bbox_blocks, nsub), dim3(256), 0, s, q, t.n, t.seg,
-                       t.bbox_part);
+                       t.bbox_part, nullptr, (int64_t)0);
     hipLaunchKernelGGL(k_bbox_final, dim3(nsub), dim3(64), 0, s, t.bbox_part, t.bbox_blocks,
                        t.meta, status);
     hipLaunchKernelGGL(k_copy_centres, dim3(nblk(3 * (int64_t)nsub)), dim3(256), 0, s, t.meta,
