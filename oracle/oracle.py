@@ -19,7 +19,10 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# GS_ORACLE_LIB selects another build (the sanitized one of the sanitizer
+# checks, see build_sanitized); by default the in-tree liboracle.so.
+_ALT = os.environ.get("GS_ORACLE_LIB")
+_LIB = _ALT or os.path.join(_HERE, "liboracle.so")
 
 # No FMA contraction, no fast-math: every operation is the IEEE double one.
 GCC_CMD = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
@@ -28,11 +31,27 @@ GCC_CMD = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
 
 def build(force: bool = False) -> str:
     """Compile liboracle.so with gcc (when missing or stale, or if forced)."""
+    if _ALT:
+        return _LIB
     stale = (not os.path.exists(_LIB)
              or os.path.getmtime(_LIB) < os.path.getmtime(_SRC))
     if force or stale:
         subprocess.run(GCC_CMD, check=True)
     return _LIB
+
+
+CLANG = "/opt/rocm/lib/llvm/bin/clang"
+
+
+def build_sanitized(out: str) -> str:
+    """The oracle built with AddressSanitizer and UndefinedBehaviorSanitizer
+    (clang, the runtime of the host-sanitized GPU library build; serial:
+    without OpenMP), for the sanitizer checks of the test suite."""
+    subprocess.run([CLANG, "-O1", "-g", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+                    "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+                    "-fno-omit-frame-pointer", "-shared-libasan", "-Wno-unknown-pragmas",
+                    "-fPIC", "-shared", "-o", out, _SRC, "-lm"], check=True)
+    return out
 
 
 _lib = None

@@ -70,6 +70,34 @@ def build(jobs: int = 8) -> str:
     return LIB
 
 
+SAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-sanitize-recover=all", "-Xarch_host", "-fno-omit-frame-pointer"]
+
+
+def build_sanitized(out_dir: str, jobs: int = 8) -> str:
+    """The library with its host code built with AddressSanitizer and
+    UndefinedBehaviorSanitizer (device code as usual), into out_dir; for the
+    sanitizer checks of the test suite, which load it with the clang ASan
+    runtime preloaded.  Returns the library path."""
+    global BUILD, LIB, FLAGS
+    saved = (BUILD, LIB, FLAGS)
+    try:
+        BUILD = out_dir
+        LIB = os.path.join(out_dir, "libgsbh_asan.so")
+        FLAGS = FLAGS + SAN_FLAGS
+        os.makedirs(BUILD, exist_ok=True)
+        with cf.ThreadPoolExecutor(max_workers=max(1, min(jobs, 16))) as ex:
+            objs = list(ex.map(_compile, sources()))
+        cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-shared-libasan", *SAN_FLAGS,
+               "-o", LIB, *objs]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"link failed:\n{r.stderr}")
+        return LIB
+    finally:
+        BUILD, LIB, FLAGS = saved
+
+
 def asm(src_name: str, out: str) -> None:
     """Write the gfx950 assembly of one source (for inspection)."""
     src = os.path.join(CSRC, src_name)

@@ -16,7 +16,9 @@ from dataclasses import dataclass
 import torch
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libgsbh.so")
+# GSBH_LIB selects another build of the library (the host-sanitized build of
+# the sanitizer checks); by default the in-tree libgsbh.so.
+LIB_PATH = os.environ.get("GSBH_LIB") or os.path.join(_PKG, "libgsbh.so")
 
 GS_EXACT, GS_BH = 0, 1
 GS_OP_RHS, GS_OP_SHOOT, GS_OP_ADJOINT, GS_OP_FIELD = 0, 1, 2, 3
