@@ -207,6 +207,13 @@ def stack(subjects):
     return np.ascontiguousarray(q), np.ascontiguousarray(p), offsets
 
 
+def field_targets(n=200000, seed=7):
+    """Points at which the velocity field is evaluated: uniform in [0, 1]^3
+    (the box of the 200k ellipsoids), FP32."""
+    rng = np.random.default_rng(seed)
+    return _round(rng.random((n, 3)), "f32")
+
+
 def directions(seed, n, k):
     """k unit directions in R^(3n) (for finite-difference checks)."""
     rng = np.random.default_rng(seed)

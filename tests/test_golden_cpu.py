@@ -12,7 +12,8 @@ import pytest
 from paper_1907_04834_amd import workloads as W
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
-FILES = sorted(glob.glob(os.path.join(GOLD, "ellipsoids8_200k_*.npz")))
+FILES = sorted(glob.glob(os.path.join(GOLD, "ellipsoids8_200k_exact.npz")) +
+               glob.glob(os.path.join(GOLD, "ellipsoids8_200k_bh05_*.npz")))
 
 
 def _digest(*arrays):
@@ -53,3 +54,55 @@ def test_golden_bh_close_to_exact():
         gb = np.load(f)
         e = np.linalg.norm(gb["p1"] - gx["p1"]) / np.linalg.norm(gx["p1"])
         assert 1e-6 < e < 0.1, (f, e)
+
+
+def _load(name):
+    path = os.path.join(GOLD, name + ".npz")
+    if not os.path.exists(path):
+        pytest.skip(f"{name}.npz not written (tests/golden/make_golden.py {name})")
+    return np.load(path)
+
+
+def test_golden_rhs_20k_matches_generator():
+    g = _load("ellipsoid_20k_rhs")
+    w = W.ellipsoid_20k()
+    assert str(g["digest"]) == _digest(w.q0, w.p0)
+    idx = g["idx"]
+    assert np.all(np.diff(idx) > 0) and idx[-1] < w.n
+    for th in (0.3, 0.5, 0.8):
+        for lc in (1, 48):
+            v, a = g[f"v_bh_{th}_{lc}"], g[f"a_bh_{th}_{lc}"]
+            assert v.shape == (len(idx), 3) and np.all(np.isfinite(v)) and np.all(np.isfinite(a))
+            # the approximation moves the result by a small fraction only
+            assert np.linalg.norm(v - g["v_exact"]) < 0.05 * np.linalg.norm(g["v_exact"])
+
+
+def test_golden_field_matches_generator():
+    g = _load("ellipsoids8_200k_field")
+    w = W.ellipsoids_200k()
+    x = W.field_targets()
+    assert str(g["digest"]) == _digest(w.q0, w.p0, x)
+    assert g["v"].shape == (len(g["idx"]), 3) and np.all(np.isfinite(g["v"]))
+
+
+def test_golden_adjoint_matches_generator():
+    g = _load("adjoint_50k_grad")
+    w = W.adjoint_50k()
+    assert str(g["digest"]) == _digest(w.q0, w.p0, w.extra["target"])
+    for m in ("exact", "bh"):
+        assert np.isfinite(float(g[f"E_{m}"])) and float(g[f"E_{m}"]) > 0
+        assert np.all(np.isfinite(g[f"g_{m}"]))
+    # Barnes-Hut objective within a few percent of the exact one
+    assert abs(float(g["E_bh"]) - float(g["E_exact"])) < 0.05 * float(g["E_exact"])
+
+
+def test_golden_population_subjects_match_generator():
+    g = _load("population_subjects")
+    subs = W.population()
+    ys = W.population_targets(subs)
+    dig = [_digest(subs[s].q0, subs[s].p0, ys[s]) for s in g["subjects"]]
+    assert str(g["digest"]) == _digest(*[np.frombuffer(d.encode(), np.uint8) for d in dig])
+    for s in g["subjects"]:
+        for m in ("exact", "bh"):
+            H = g[f"H_{m}_{s}"]
+            assert np.all(np.isfinite(H)) and abs(H[-1] - H[0]) < 0.1 * H[0]
