@@ -262,14 +262,17 @@ static gs_status adjoint_step(AdjointBufs &b, const gs_params &prm, double dt, c
     const double bscale = ks * ks * prm.sigma * prm.sigma;
     GS_TRY(launch_pack_rows64(pl, b.ex, b.al, b.be, 1.0 / ks, b.AL, b.BE, s, 1.0 / bscale,
                               false));
+    // the backward products keep FP64 partial sums (in the forward partials'
+    // memory: 8 bytes a value either way)
+    double *part = reinterpret_cast<double *>(b.ex.part);
     timing_begin(KIND_ADJOINT, s);
     hipLaunchKernelGGL(k_adj_items, dim3((unsigned)ni), dim3(kItemThreads), 0, s, b.ex.Q, b.ex.P,
                        b.AL, b.BE, pl.npad, pl.single ? nullptr : b.ex.items, pl.geom, bscale,
-                       b.ex.part);
+                       part);
     timing_end(KIND_ADJOINT, s);
     GS_LAUNCH_CHECK("adj_items");
     hipLaunchKernelGGL(k_adj_update_rows, dim3((unsigned)plan_block_count(pl)), dim3(256), 0, s,
-                       b.ex.part, pl.npad, b.ex.blk, pl.rows, 1.0 / (prm.sigma * prm.sigma), ks,
+                       part, pl.npad, b.ex.blk, pl.rows, 1.0 / (prm.sigma * prm.sigma), ks,
                        dt, b.al, b.be);
     GS_LAUNCH_CHECK("adj_update_rows");
     return GS_OK;

@@ -369,7 +369,7 @@ gs_status bh_adjoint_begin(const float *q0, AdjointBufs &b, char *ws, hipStream_
                        reinterpret_cast<u64 *>(ws + kCountersOffset));
     GS_LAUNCH_CHECK("clear");
     // the frame of the FP32 copies: frame origins of q0, fixed for the call
-    return tree_set_centres(q0, b.sh.tree, b.sh.c0, reinterpret_cast<int *>(ws), s);
+    return tree_set_centres(q0, b.sh.tree, b.sh.c0, nullptr, reinterpret_cast<int *>(ws), s);
 }
 
 gs_status bh_adjoint_forward_step(AdjointBufs &b, const gs_params &prm, double dt, double *v0,

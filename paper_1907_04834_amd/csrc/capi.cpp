@@ -307,7 +307,8 @@ void layout_batch(Arena &a, const int64_t *off, int nsub, const gs_params &prm, 
             b.plan = exact_plan(off, nsub, prm.exact_items);
             b.xp = b.plan.get();
         }
-        carve_exact_batch(a, *b.xp, nt, b.ex);
+        carve_exact_batch(a, *b.xp, nt,
+                          op == GS_OP_SHOOT ? kStateFF : (adj ? kStateF64 : kStateNone), b.ex);
         const int nb = (int)plan_block_count(*b.xp);
         if (adj) {
             b.adj.AL = a.take<float4>(b.xp->npad);
@@ -366,7 +367,8 @@ void layout_batch(Arena &a, const int64_t *off, int nsub, const gs_params &prm, 
     seg[nsub] = off[nsub];
     gseg[nsub] = (int)ngroups;
     if (op == GS_OP_SHOOT || adj)
-        b.bh = layout_shoot_forest(a, ntot, nsub, ngroups, max_set, nt);
+        b.bh = layout_shoot_forest(a, ntot, nsub, ngroups, max_set, nt,
+                                   adj ? kStateF64 : kStateFF);
     else
         carve_forest(a, ntot, nsub, ngroups, max_set, b.bh.tree);
     // reduction units of the backward stage: blocks of <= 256 points of one set
@@ -571,7 +573,7 @@ gs_status exact_batch_shoot(const float *q0, const float *p0, const int64_t *off
         GS_TRY(launch_reduce_h_seg(b.ex.Hpart, (int64_t)nb, b.ex.bseg, nsub, prm.nt + 1, H,
                                    stream));
     }
-    return launch_unpack_state(b.ex.Sq, b.ex.Sp, off[nsub], q1, p1, stream);
+    return launch_unpack_state(b.ex.Fq, b.ex.Fp, off[nsub], q1, p1, stream);
 }
 
 // ---------------------------------------------------------------- graphs

@@ -19,8 +19,13 @@
 //     the accuracy does not depend on where the set lies (the method depends
 //     only on differences q_i - q_j);
 //   * per pair 16 VALU operations and one v_exp_f32; each tile of kTile
-//     sources is summed in FP32 and the tile sums are accumulated in FP64,
-//     so a target's rounding error grows with the tile length, not with N.
+//     sources is summed in FP32 and the tile sums are accumulated with
+//     Kahan's compensation in FP32, and the partials and their sum are kept
+//     as double-float (hi, lo) pairs, so a target's rounding error grows with
+//     the tile length, not with N; FP64 serves only the energy reduction (and
+//     the backward stage's own state).
+//   * a shooting keeps its state as FP32 hi+lo pairs and takes the Euler step
+//     in double-float arithmetic.
 #include <algorithm>
 #include <vector>
 
@@ -87,7 +92,8 @@ __global__ __launch_bounds__(256) void k_box_rows(const float *__restrict__ q,
 // wave per set; 0 for a set without finite points.
 __global__ __launch_bounds__(64) void k_box_sets(const float *__restrict__ bpart,
                                                  const int *__restrict__ bseg, int nblk,
-                                                 double *__restrict__ cen) {
+                                                 double *__restrict__ cen,
+                                                 float2 *__restrict__ cenf) {
     const int lane = threadIdx.x, set = blockIdx.x;
     const int b0 = bseg ? bseg[set] : 0, b1 = bseg ? bseg[set + 1] : nblk;
     float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
@@ -107,7 +113,10 @@ __global__ __launch_bounds__(64) void k_box_sets(const float *__restrict__ bpart
     if (lane < 3) {
         const float l = lane == 0 ? lo[0] : (lane == 1 ? lo[1] : lo[2]);
         const float h = lane == 0 ? hi[0] : (lane == 1 ? hi[1] : hi[2]);
-        cen[3 * set + lane] = l <= h ? 0.5 * ((double)l + (double)h) : 0.0;
+        const double c = l <= h ? 0.5 * ((double)l + (double)h) : 0.0;
+        cen[3 * set + lane] = c;
+        const float ch = (float)c;
+        cenf[3 * set + lane] = make_float2(ch, (float)(c - (double)ch));  // exact split
     }
 }
 
@@ -119,12 +128,15 @@ __global__ __launch_bounds__(64) void k_box_sets(const float *__restrict__ bpart
 
 // FP32 source (and target) rows k (q - c_set), p; with Sq non-null also the
 // FP64 state copy of (q, p).
+// With Fq non-null also the hi+lo state ((hi, lo) = (the input, 0)).
 __global__ __launch_bounds__(256) void k_pack_state_rows(const float *__restrict__ q,
                                                          const float *__restrict__ p,
                                                          const int4 *__restrict__ blk, RowGeom rg,
                                                          double ks, const double *__restrict__ cen,
                                                          double *__restrict__ Sq,
                                                          double *__restrict__ Sp,
+                                                         float2 *__restrict__ Fq,
+                                                         float2 *__restrict__ Fp,
                                                          float4 *__restrict__ Q,
                                                          float4 *__restrict__ P) {
     const int4 d = row_block(blk, rg, blockIdx.x);
@@ -134,6 +146,14 @@ __global__ __launch_bounds__(256) void k_pack_state_rows(const float *__restrict
         const double *c = cen + 3 * d.z;
         const float x = q[3 * i], y = q[3 * i + 1], z = q[3 * i + 2];
         const float u = p[3 * i], v = p[3 * i + 1], w = p[3 * i + 2];
+        if (Fq) {
+            const float qs[3] = {x, y, z}, ps[3] = {u, v, w};
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                Fq[3 * i + k] = make_float2(qs[k], 0.f);
+                Fp[3 * i + k] = make_float2(ps[k], 0.f);
+            }
+        }
         if (Sq) {
             Sq[3 * i] = x;
             Sq[3 * i + 1] = y;
@@ -193,12 +213,13 @@ __global__ __launch_bounds__(256) void k_pack_rows64(const double *__restrict__ 
     }
 }
 
-__global__ void k_unpack_state(const double *__restrict__ Sq, const double *__restrict__ Sp,
+// q = hi + lo of the hi+lo state, rounded to FP32.
+__global__ void k_unpack_state(const float2 *__restrict__ Fq, const float2 *__restrict__ Fp,
                                int64_t n, float *__restrict__ q, float *__restrict__ p) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= 3 * n) return;
-    q[i] = (float)Sq[i];
-    p[i] = (float)Sp[i];
+    q[i] = Fq[i].x + Fq[i].y;
+    p[i] = Fp[i].x + Fp[i].y;
 }
 
 // ---------------------------------------------------------------- pair kernel
@@ -216,10 +237,10 @@ template <bool WITH_A>
 __global__ __launch_bounds__(kItemThreads) __attribute__((amdgpu_waves_per_eu(8, 8))) void
 k_exact_items(const float4 *__restrict__ Qt, const float4 *__restrict__ Q,
               const float4 *__restrict__ P, int64_t npad, const int4 *__restrict__ items,
-              ItemGeom geom, double *__restrict__ part) {
+              ItemGeom geom, float2 *__restrict__ part) {
     constexpr int B = 4;  // sources per pipeline stage (kTile is a multiple)
     constexpr int NV = WITH_A ? 6 : 3;
-    __shared__ double red[kItemSplit > 1 ? kItemSplit - 1 : 1][NV][kItemRows];
+    __shared__ float2 red[kItemSplit > 1 ? kItemSplit - 1 : 1][NV][kItemRows];
     const int4 it = work_item(items, geom, blockIdx.x);
     if (it.w < 0) return;  // padding item: the whole block leaves before any barrier
     const int wv = wave_in_block();
@@ -235,7 +256,9 @@ k_exact_items(const float4 *__restrict__ Qt, const float4 *__restrict__ Q,
         py = b.y;
         pz = b.z;
     }
-    double sv[3] = {0, 0, 0}, sa[3] = {0, 0, 0};
+    // compensated sums of the tile sums: value = s - c
+    float sv[3] = {0.f, 0.f, 0.f}, cv[3] = {0.f, 0.f, 0.f};
+    float sa[3] = {0.f, 0.f, 0.f}, ca[3] = {0.f, 0.f, 0.f};
     // this wave's share of the chunk in whole tiles; 32-bit source indices, so
     // the loop and prefetch-clamp compares run on the scalar unit
     const int ntile = (it.z - it.y) / kTile;
@@ -293,47 +316,70 @@ k_exact_items(const float4 *__restrict__ Qt, const float4 *__restrict__ Q,
             }
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                sv[c] += (double)tv[c];
-                if (WITH_A) sa[c] += (double)ta[c];
+                kahan_add(sv[c], cv[c], tv[c]);
+                if (WITH_A) kahan_add(sa[c], ca[c], ta[c]);
             }
         }
     }
-    // the waves of a target group add their sums in split order
+    // as double-float values; the waves of a target group add theirs in
+    // split order
+    ff xv[3], xa[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        xv[c] = ff_fast_two_sum(sv[c], -cv[c]);
+        xa[c] = ff_fast_two_sum(sa[c], -ca[c]);
+    }
     if (kItemSplit > 1) {
         if (w > 0)
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                red[w - 1][c][r] = sv[c];
-                if (WITH_A) red[w - 1][3 + c][r] = sa[c];
+                red[w - 1][c][r] = make_float2(xv[c].h, xv[c].l);
+                if (WITH_A) red[w - 1][3 + c][r] = make_float2(xa[c].h, xa[c].l);
             }
         __syncthreads();
         if (w == 0)
             for (int k = 0; k < kItemSplit - 1; ++k)
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    sv[c] += red[k][c][r];
-                    if (WITH_A) sa[c] += red[k][3 + c][r];
+                    const float2 u = red[k][c][r];
+                    xv[c] = ff_add(xv[c], ff{u.x, u.y});
+                    if (WITH_A) {
+                        const float2 e = red[k][3 + c][r];
+                        xa[c] = ff_add(xa[c], ff{e.x, e.y});
+                    }
                 }
     }
     if (w != 0) return;
-    double *dst = part + (int64_t)it.w * 6 * npad;
+    float2 *dst = part + (int64_t)it.w * 6 * npad;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        dst[c * npad + t0] = sv[c];
-        if (WITH_A) dst[(3 + c) * npad + t0] = sa[c];
+        dst[c * npad + t0] = make_float2(xv[c].h, xv[c].l);
+        if (WITH_A) dst[(3 + c) * npad + t0] = make_float2(xa[c].h, xa[c].l);
     }
 }
 
-// Sums the partial slots of each row.  mode 0: (dq, dp) = (v, a) (dp
-// nullable: velocity field).  mode 1: energy partial of the block into Hpart
-// (nullable), the velocity into vout (FP64 [n][3], nullable) and, if dt > 0,
-// the Euler step of the FP64 state and its packed copies.  inv_s2 here is
-// 1 / (k sigma^2): the a-sums were taken on scaled positions.
+// Constants of the combine kernel: 1 / (k sigma^2) (the a-sums were taken on
+// scaled positions), k and dt, in FP64 for the FP64 state and as
+// double-float for the hi+lo state.
+struct CombineConst {
+    double inv_s2, ks, dt;
+    ff inv_s2f, ksf, dtf;
+};
+
+// Sums the partial slots of each row (double-float, in slot order).  mode 0:
+// (dq, dp) = (v, a) (dp nullable: velocity field).  mode 1: energy partial of
+// the block into Hpart (nullable; FP64, the energy reduction), the velocity
+// into vout (FP64 [n][3], nullable) and, if dt > 0, the Euler step of the
+// state and its packed copies: the hi+lo state (Fq, Fp) in double-float
+// arithmetic when Fq is non-null, else the FP64 state (Sq, Sp) of the
+// backward stage.  A slot's components are loaded together before they are
+// added (the loop bounds are fixed, so acc stays in registers).
 __global__ __launch_bounds__(256) void k_combine_rows(
-    const double *__restrict__ part, int64_t npad, const int4 *__restrict__ blk, RowGeom rg,
-    double inv_s2, double ks, int mode, float *__restrict__ dq, float *__restrict__ dp, double dt,
-    double *__restrict__ Sq, double *__restrict__ Sp, float4 *__restrict__ Q,
-    float4 *__restrict__ P, const double *__restrict__ cen, double *__restrict__ Hpart,
+    const float2 *__restrict__ part, int64_t npad, const int4 *__restrict__ blk, RowGeom rg,
+    CombineConst k, int mode, float *__restrict__ dq, float *__restrict__ dp,
+    double *__restrict__ Sq, double *__restrict__ Sp, float2 *__restrict__ Fq,
+    float2 *__restrict__ Fp, float4 *__restrict__ Q, float4 *__restrict__ P,
+    const double *__restrict__ cen, const float2 *__restrict__ cenf, double *__restrict__ Hpart,
     double *__restrict__ vout) {
     __shared__ double lds[8];
     const int4 d = row_block(blk, rg, blockIdx.x);
@@ -341,38 +387,77 @@ __global__ __launch_bounds__(256) void k_combine_rows(
     double e = 0.0;
     if ((int)threadIdx.x < d.y) {
         const int64_t i = (int64_t)d.x + threadIdx.x;
-        double acc[6] = {0, 0, 0, 0, 0, 0};
-        const int na = (mode == 0 && !dp) ? 3 : 6;
-        for (int s = 0; s < d.w; ++s)
-            for (int c = 0; c < na; ++c) acc[c] += part[((int64_t)s * 6 + c) * npad + row];
+        ff acc[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) acc[c] = ff{0.f, 0.f};
+        const bool with_a = !(mode == 0 && !dp);
+        for (int s = 0; s < d.w; ++s) {
+            float2 u[6];
+#pragma unroll
+            for (int c = 0; c < 6; ++c)
+                u[c] = (c < 3 || with_a) ? part[((int64_t)s * 6 + c) * npad + row]
+                                         : make_float2(0.f, 0.f);
+#pragma unroll
+            for (int c = 0; c < 6; ++c) acc[c] = ff_add(acc[c], ff{u[c].x, u[c].y});
+        }
         if (mode == 0) {  // right-hand side or velocity field
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                dq[3 * i + c] = (float)acc[c];
-                if (dp) dp[3 * i + c] = (float)(acc[3 + c] * inv_s2);
+                dq[3 * i + c] = acc[c].h + acc[c].l;
+                if (dp) {
+                    const ff a = ff_mul(acc[3 + c], k.inv_s2f);
+                    dp[3 * i + c] = a.h + a.l;
+                }
             }
-        } else {
-            double q[3], p[3];
+        } else if (Fq) {  // shooting: hi+lo state
+            ff q[3], p[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
+                const float2 fq = Fq[3 * i + c], fp = Fp[3 * i + c];
+                q[c] = ff{fq.x, fq.y};
+                p[c] = ff{fp.x, fp.y};
+                e += ((double)p[c].h + (double)p[c].l) * ((double)acc[c].h + (double)acc[c].l);
+                if (vout) vout[3 * i + c] = (double)acc[c].h + (double)acc[c].l;
+            }
+            if (k.dt > 0.0) {
+                const float2 *c0 = cenf + 3 * d.z;
+                float xq[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    q[c] = ff_add(q[c], ff_mul(k.dtf, acc[c]));
+                    p[c] = ff_add(p[c], ff_mul(k.dtf, ff_mul(acc[3 + c], k.inv_s2f)));
+                    Fq[3 * i + c] = make_float2(q[c].h, q[c].l);
+                    Fp[3 * i + c] = make_float2(p[c].h, p[c].l);
+                    const ff r = ff_mul(k.ksf, ff_add(q[c], ff{-c0[c].x, -c0[c].y}));
+                    xq[c] = r.h + r.l;
+                }
+                Q[row] = make_float4(xq[0], xq[1], xq[2], 0.f);
+                P[row] = make_float4(p[0].h + p[0].l, p[1].h + p[1].l, p[2].h + p[2].l, 0.f);
+            }
+        } else {  // the backward stage's forward steps: FP64 state
+            double v[3], a[3], q[3], p[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                v[c] = (double)acc[c].h + (double)acc[c].l;
+                a[c] = ((double)acc[3 + c].h + (double)acc[3 + c].l) * k.inv_s2;
                 q[c] = Sq[3 * i + c];
                 p[c] = Sp[3 * i + c];
             }
-            e = p[0] * acc[0] + p[1] * acc[1] + p[2] * acc[2];
+            e = p[0] * v[0] + p[1] * v[1] + p[2] * v[2];
             if (vout)
 #pragma unroll
-                for (int c = 0; c < 3; ++c) vout[3 * i + c] = acc[c];
-            if (dt > 0.0) {
+                for (int c = 0; c < 3; ++c) vout[3 * i + c] = v[c];
+            if (k.dt > 0.0) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    q[c] += dt * acc[c];
-                    p[c] += dt * (acc[3 + c] * inv_s2);
+                    q[c] += k.dt * v[c];
+                    p[c] += k.dt * a[c];
                     Sq[3 * i + c] = q[c];
                     Sp[3 * i + c] = p[c];
                 }
                 const double *c0 = cen + 3 * d.z;
-                Q[row] = make_float4((float)(ks * (q[0] - c0[0])), (float)(ks * (q[1] - c0[1])),
-                                     (float)(ks * (q[2] - c0[2])), 0.f);
+                Q[row] = make_float4((float)(k.ks * (q[0] - c0[0])), (float)(k.ks * (q[1] - c0[1])),
+                                     (float)(k.ks * (q[2] - c0[2])), 0.f);
                 P[row] = make_float4((float)p[0], (float)p[1], (float)p[2], 0.f);
             }
         }
@@ -605,18 +690,27 @@ ExactBatchPlan plan_exact_batch(const int64_t *offsets, int nsub, int64_t items)
     return pl;
 }
 
-void carve_exact_batch(Arena &a, const ExactBatchPlan &pl, int nt, ExactBatchBufs &b) {
+void carve_exact_batch(Arena &a, const ExactBatchPlan &pl, int nt, int state,
+                       ExactBatchBufs &b) {
     b.Q = a.take<float4>(pl.spad);
     b.P = a.take<float4>(pl.spad);
     b.X = b.Q;
-    b.part = a.take<double>((size_t)pl.max_chunks * 6 * pl.npad);
+    b.part = a.take<float2>((size_t)pl.max_chunks * 6 * pl.npad);
     const int64_t n = pl.ntot > 0 ? pl.ntot : 1;
-    b.Sq = a.take<double>(3 * n);
-    b.Sp = a.take<double>(3 * n);
+    b.Fq = b.Fp = nullptr;
+    b.Sq = b.Sp = nullptr;
+    if (state == kStateFF) {
+        b.Fq = a.take<float2>(3 * n);
+        b.Fp = a.take<float2>(3 * n);
+    } else if (state == kStateF64) {
+        b.Sq = a.take<double>(3 * n);
+        b.Sp = a.take<double>(3 * n);
+    }
     const size_t nb = (size_t)std::max<int64_t>(plan_block_count(pl), 1);
     b.Hpart = a.take<double>((size_t)(nt + 1) * nb);
     b.bpart = a.take<float>(6 * nb);
     b.cen = a.take<double>(3 * (size_t)std::max(pl.nsub, 1));
+    b.cenf = a.take<float2>(3 * (size_t)std::max(pl.nsub, 1));
 }
 
 // One set without tables: the same items, row blocks and centres as
@@ -665,11 +759,13 @@ void carve_exact_field(Arena &a, const ExactBatchPlan &pl, ExactBatchBufs &b) {
     b.Q = a.take<float4>(pl.spad);
     b.P = a.take<float4>(pl.spad);
     b.X = a.take<float4>(pl.npad);
-    b.part = a.take<double>((size_t)pl.max_chunks * 6 * pl.npad);
+    b.part = a.take<float2>((size_t)pl.max_chunks * 6 * pl.npad);
     b.Sq = b.Sp = nullptr;
+    b.Fq = b.Fp = nullptr;
     b.Hpart = nullptr;
     b.bpart = a.take<float>(6 * std::max<size_t>(pl.sblocks.size(), 1));
     b.cen = a.take<double>(3);
+    b.cenf = a.take<float2>(3);
 }
 
 // k = sqrt(log2(e) / (2 sigma^2)): the items kernel works on k (q - c).
@@ -693,7 +789,7 @@ gs_status launch_set_centres(const ExactBatchPlan &pl, const ExactBatchBufs &b, 
     const int *bseg = fld ? b.sbseg : b.bseg;
     hipLaunchKernelGGL(k_box_rows, dim3((unsigned)nb), dim3(256), 0, s, q, blk, pl.rows, b.bpart);
     hipLaunchKernelGGL(k_box_sets, dim3((unsigned)pl.nsub), dim3(64), 0, s, b.bpart, bseg, (int)nb,
-                       b.cen);
+                       b.cen, b.cenf);
     GS_LAUNCH_CHECK("set_centres");
     return GS_OK;
 }
@@ -715,7 +811,7 @@ gs_status launch_pack_state_rows(const ExactBatchPlan &pl, const ExactBatchBufs 
     if (nb == 0) return GS_OK;
     GS_TRY(launch_set_centres(pl, b, q, s));
     hipLaunchKernelGGL(k_pack_state_rows, dim3((unsigned)nb), dim3(256), 0, s, q, p, b.blk,
-                       pl.rows, position_scale(sigma), b.cen, b.Sq, b.Sp, b.Q, b.P);
+                       pl.rows, position_scale(sigma), b.cen, b.Sq, b.Sp, b.Fq, b.Fp, b.Q, b.P);
     GS_LAUNCH_CHECK("pack_state_rows");
     return GS_OK;
 }
@@ -726,7 +822,7 @@ gs_status launch_pack_field(const ExactBatchPlan &pl, const ExactBatchBufs &b, c
     const double ks = position_scale(sigma);
     const RowGeom none{};
     hipLaunchKernelGGL(k_pack_state_rows, dim3((unsigned)pl.sblocks.size()), dim3(256), 0, s, q,
-                       p, b.sblk, none, ks, b.cen, nullptr, nullptr, b.Q, b.P);
+                       p, b.sblk, none, ks, b.cen, nullptr, nullptr, nullptr, nullptr, b.Q, b.P);
     hipLaunchKernelGGL(k_pack_pos_rows, dim3((unsigned)pl.blocks.size()), dim3(256), 0, s, x,
                        b.blk, none, ks, b.cen, b.X);
     GS_LAUNCH_CHECK("pack_field");
@@ -756,18 +852,24 @@ gs_status launch_combine_rows(const ExactBatchPlan &pl, const ExactBatchBufs &b,
                               hipStream_t s, double *vout) {
     const int64_t nb = plan_block_count(pl);
     if (nb == 0) return GS_OK;
-    const double ks = position_scale(sigma);
+    CombineConst k{};
+    k.ks = position_scale(sigma);
+    k.inv_s2 = 1.0 / (k.ks * sigma * sigma);
+    k.dt = dt;
+    k.ksf = ff_from_double(k.ks);
+    k.inv_s2f = ff_from_double(k.inv_s2);
+    k.dtf = ff_from_double(dt);
     hipLaunchKernelGGL(k_combine_rows, dim3((unsigned)nb), dim3(256), 0, s, b.part, pl.npad, b.blk,
-                       pl.rows, 1.0 / (ks * sigma * sigma), ks, mode, dq, dp, dt, b.Sq, b.Sp, b.Q,
-                       b.P, b.cen, Hpart, vout);
+                       pl.rows, k, mode, dq, dp, b.Sq, b.Sp, b.Fq, b.Fp, b.Q,
+                       b.P, b.cen, b.cenf, Hpart, vout);
     GS_LAUNCH_CHECK("combine_rows");
     return GS_OK;
 }
 
-gs_status launch_unpack_state(const double *Sq, const double *Sp, int64_t n, float *q, float *p,
+gs_status launch_unpack_state(const float2 *Fq, const float2 *Fp, int64_t n, float *q, float *p,
                               hipStream_t s) {
     if (n == 0) return GS_OK;
-    hipLaunchKernelGGL(k_unpack_state, dim3(nblocks(3 * n)), dim3(kBlock), 0, s, Sq, Sp, n, q,
+    hipLaunchKernelGGL(k_unpack_state, dim3(nblocks(3 * n)), dim3(kBlock), 0, s, Fq, Fp, n, q,
                        p);
     GS_LAUNCH_CHECK("unpack_state");
     return GS_OK;

@@ -17,6 +17,56 @@ namespace gs {
 // otherwise be computed per lane and loaded through the vector memory path.
 __device__ inline int wave_in_block() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
+// ---------------------------------------------------------------- double-float
+// A value held as an unevaluated sum hi + lo of two FP32 numbers (|lo| at most
+// half an ulp of hi once normalised): about 48 significant bits from FP32
+// arithmetic.  The building blocks are Knuth's TwoSum (the exact rounding
+// error of a sum), Dekker's Fast2Sum (the same when |a| >= |b|) and the exact
+// product error given by one fused multiply-add.  None of these contains a
+// product that the compiler could contract, except where fmaf is meant.
+struct ff {
+    float h, l;
+};
+__host__ __device__ inline ff ff_two_sum(float a, float b) {
+    const float s = a + b;
+    const float bb = s - a;
+    return {s, (a - (s - bb)) + (b - bb)};
+}
+__host__ __device__ inline ff ff_fast_two_sum(float a, float b) {
+    const float s = a + b;
+    return {s, b - (s - a)};
+}
+__host__ __device__ inline ff ff_add(ff x, ff y) {
+    ff s = ff_two_sum(x.h, y.h);
+    s.l += x.l + y.l;
+    return ff_fast_two_sum(s.h, s.l);
+}
+__host__ __device__ inline ff ff_add(ff x, float y) {
+    ff s = ff_two_sum(x.h, y);
+    s.l += x.l;
+    return ff_fast_two_sum(s.h, s.l);
+}
+__device__ inline ff ff_mul(ff x, ff y) {
+    const float p = x.h * y.h;
+    float e = fmaf(x.h, y.h, -p);
+    e = fmaf(x.h, y.l, e);
+    e = fmaf(x.l, y.h, e);
+    return ff_fast_two_sum(p, e);
+}
+// The double-float nearest a double (host side: kernel parameters).
+inline ff ff_from_double(double x) {
+    const float h = (float)x;
+    return {h, (float)(x - (double)h)};
+}
+// Kahan's compensated sum in FP32: s holds the sum, c the negated error that
+// the next addition feeds back; the sum is s - c.
+__device__ inline void kahan_add(float &s, float &c, float x) {
+    const float y = x - c;
+    const float t = s + y;
+    c = (t - s) - y;
+    s = t;
+}
+
 // ---------------------------------------------------------------- errors
 void set_error(const char *fmt, ...);
 gs_status hip_fail(hipError_t e, const char *what);
@@ -90,7 +140,7 @@ inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 // Work items of the exact FP32 kernel.  One work item is one block of
 // kItemGroups x kItemSplit waves: kItemGroups groups of 64 consecutive target
 // rows, each against one chunk of source rows split among kItemSplit waves
-// whose sums are added in LDS, so the chunk count (the FP64 partial slots per
+// whose sums are added in LDS, so the chunk count (the partial slots per
 // target) is kItemSplit times smaller than with one wave per chunk.  The
 // defaults are the measured best; other shapes are compiled only by a tuning
 // build.
@@ -180,23 +230,30 @@ int64_t plan_block_count(const ExactBatchPlan &pl);
 struct ExactBatchBufs {
     float4 *Q, *P;                // [spad] packed FP32 sources k (q - c), p; zero padding
     float4 *X;                    // target rows (Q itself except for the field)
-    double *part;                 // [max_chunks][6][npad]
-    double *Sq, *Sp;              // [ntot][3] FP64 state
+    float2 *part;                 // [max_chunks][6][npad] compensated sums (hi, lo)
+    float2 *Fq, *Fp;              // [ntot][3] shooting state, FP32 (hi, lo) pairs (nullable)
+    double *Sq, *Sp;              // [ntot][3] FP64 state of the backward stage (nullable)
     double *Hpart;                // [nt + 1][blocks]
     float *bpart;                 // [source blocks][6] boxes of the row blocks
     double *cen;                  // [nsub][3] FP64 centres of the sets' boxes
+    float2 *cenf;                 // [nsub][3] the same as double-float
     const int4 *items = nullptr, *blk = nullptr;   // device tables (null: single set)
     const int *bseg = nullptr;
     const int4 *sblk = nullptr;   // field: source row blocks
     const int *sbseg = nullptr;
 };
+// The state a call keeps: none (right-hand side, field), FP32 hi+lo
+// (shooting), FP64 (the forward steps of the backward stage).
+enum StateKind { kStateNone = 0, kStateFF = 1, kStateF64 = 2 };
 // Carves the state and partial buffers (not the tables).
-void carve_exact_batch(Arena &a, const ExactBatchPlan &pl, int nt, ExactBatchBufs &b);
+void carve_exact_batch(Arena &a, const ExactBatchPlan &pl, int nt, int state,
+                       ExactBatchBufs &b);
 void carve_exact_field(Arena &a, const ExactBatchPlan &pl, ExactBatchBufs &b);
 // Centres of the sets' boxes (of the field's sources) into b.cen.
 gs_status launch_set_centres(const ExactBatchPlan &pl, const ExactBatchBufs &b, const float *q,
                              hipStream_t s);
-// Set centres, the FP64 state and its FP32 copies (positions k (q - c)).
+// Set centres, the state (hi+lo or FP64, whichever is carved) and its FP32
+// copies (positions k (q - c)).
 gs_status launch_pack_state_rows(const ExactBatchPlan &pl, const ExactBatchBufs &b,
                                  const float *q, const float *p, double sigma, hipStream_t s);
 // Field: source centre, packed sources and targets.
@@ -205,8 +262,9 @@ gs_status launch_pack_field(const ExactBatchPlan &pl, const ExactBatchBufs &b, c
 gs_status launch_exact_items(const ExactBatchPlan &pl, const ExactBatchBufs &b, bool with_a,
                              hipStream_t s);
 // mode 0: (dq, dp) = (v, a) (dp nullable); mode 1: energy partials into Hpart
-// (nullable), the velocity into vout (FP64 [ntot][3], nullable) and, if
-// dt > 0, the Euler step of the FP64 state and its packed copies.
+// (nullable; FP64), the velocity into vout (FP64 [ntot][3], nullable) and, if
+// dt > 0, the Euler step of the state (hi+lo when carved, else FP64) and its
+// packed copies.
 gs_status launch_combine_rows(const ExactBatchPlan &pl, const ExactBatchBufs &b, double sigma,
                               int mode, float *dq, float *dp, double dt, double *Hpart,
                               hipStream_t s, double *vout = nullptr);
@@ -217,7 +275,8 @@ double position_scale(double sigma);
 gs_status launch_pack_rows64(const ExactBatchPlan &pl, const ExactBatchBufs &b, const double *a,
                              const double *bb, double sa, float4 *A, float4 *B, hipStream_t s,
                              double sb, bool centre);
-gs_status launch_unpack_state(const double *Sq, const double *Sp, int64_t n, float *q, float *p,
+// q = hi + lo of the FP32 hi+lo state (Fq, Fp: [2][n][3]), rounded to FP32.
+gs_status launch_unpack_state(const float2 *Fq, const float2 *Fp, int64_t n, float *q, float *p,
                               hipStream_t s);
 int combine_blocks(int64_t n);
 // H[t] = sum_b Hpart[t * nblk + b] for t in [0, count).

@@ -104,6 +104,38 @@ __device__ inline void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// A target's (v, a) sums in a forward-traversal wave: FP32 with Kahan
+// compensation (value = s - c).  Each leaf or monopole batch is summed in
+// plain FP32 and then added here.
+struct TAcc {
+    float sV[3], cV[3], sA[3], cA[3];
+};
+__device__ inline void tacc_zero(TAcc &k) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) k.sV[c] = k.cV[c] = k.sA[c] = k.cA[c] = 0.f;
+}
+template <bool WITH_A>
+__device__ inline void tacc_add(TAcc &k, const float *tv, const float *ta) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        kahan_add(k.sV[c], k.cV[c], tv[c]);
+        if (WITH_A) kahan_add(k.sA[c], k.cA[c], ta[c]);
+    }
+}
+
+// A target's compensated sums as double-float (hi, lo) partials.
+__device__ inline void write_part_ff(float2 *__restrict__ part, int slot, int64_t npad,
+                                     int64_t t, const TAcc &k) {
+    float2 *d = part + ((int64_t)slot * npad + t) * 6;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const ff v = ff_fast_two_sum(k.sV[c], -k.cV[c]), a = ff_fast_two_sum(k.sA[c], -k.cA[c]);
+        d[c] = make_float2(v.h, v.l);
+        d[3 + c] = make_float2(a.h, a.l);
+    }
+}
+
+// FP64 partials of the backward stage.
 __device__ inline void write_part(double *__restrict__ part, int slot, int64_t npad, int64_t t,
                                   const double *V, const double *A) {
     double *d = part + ((int64_t)slot * npad + t) * 6;

@@ -14,8 +14,9 @@
 // The node records of a block of siblings are staged in LDS with one vector
 // load and read back as broadcasts; the decisions are taken in FP64 from the
 // FP32 target position as given, the node's exact FP32 box and FP64 centre,
-// as in the definition.  The contributions are FP32 with per-leaf sums
-// accumulated in FP64: exact pairs use the positions relative to the set's
+// as in the definition.  The contributions are FP32; each leaf's sums (and
+// the wave's monopoles) are added to Kahan-compensated FP32 sums per target,
+// handed to phase 3 as double-float partials: exact pairs use the positions relative to the set's
 // frame origin (Qc; the box centre rounded to a multiple of a power of two,
 // 0 for a set around the origin), and a monopole's offset x - C_k is taken
 // in FP64 and rounded once, so no difference loses precision to the set's
@@ -78,15 +79,16 @@ __device__ __forceinline__ void group_pairs(const float4 *qj, const float4 *pj, 
 // lanes with `mine` set.  first and count are wave-uniform, so the points are
 // read with wave-uniform addresses (scalar loads straight into SGPRs, as in
 // the all-pairs kernel); lanes outside the leaf's mask are switched off by
-// the branch.  The leaf is summed in FP32 and added to the FP64 sums.
+// the branch.  The leaf's FP32 sums go to tv, ta (zero for other lanes).
 template <bool WITH_A>
 __device__ __forceinline__ void leaf_direct(const float4 *__restrict__ Qs,
                                             const float4 *__restrict__ Ps, int first, int count,
                                             bool mine, float4 xq, float4 xp, float negc,
-                                            double *V, double *A) {
+                                            float *tv, float *ta) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) tv[c] = ta[c] = 0.f;
     if (!mine) return;
     constexpr int B = 4;  // sources per pipeline stage
-    float tv[3] = {0.f, 0.f, 0.f}, ta[3] = {0.f, 0.f, 0.f};
     const int end = first + count;
     int j = first;
     if (count >= B) {
@@ -117,11 +119,6 @@ __device__ __forceinline__ void leaf_direct(const float4 *__restrict__ Qs,
     for (; j < end; ++j) {
         const float4 qj = Qs[j], pj = Ps[j];
         group_pairs<WITH_A, 1>(&qj, &pj, xq, xp, negc, tv, ta);
-    }
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        V[c] += (double)tv[c];
-        if (WITH_A) A[c] += (double)ta[c];
     }
 }
 
@@ -210,7 +207,7 @@ __device__ inline void entry_batch_init(EntryBatch &eb, const LeafEntry *__restr
 // The dense entries of [v0, v1) as one stream of source groups: the next
 // group of B sources (the next dense leaf's first group at the end of a leaf)
 // is loaded while the current group is evaluated.  Every lane evaluates every
-// leaf and adds the leaf's FP32 sums to its FP64 sums only when the leaf's
+// leaf and adds the leaf's FP32 sums to its compensated sums only when the leaf's
 // mask holds it; per leaf the sums are those of leaf_direct (groups of B in
 // order, then single sources).
 template <bool WITH_A>
@@ -219,7 +216,7 @@ __device__ __forceinline__ void leaf_dense(const float4 *__restrict__ Qs,
                                            const LeafEntry *__restrict__ list,
                                            const int *__restrict__ list_n, int64_t grp,
                                            TravSplit split, int v0, int v1, int lane, float4 xq,
-                                           float4 xp, float negc, double *V, double *A,
+                                           float4 xp, float negc, TAcc &K,
                                            unsigned &steps) {
     constexpr int B = 4;
     if (v0 >= v1) return;
@@ -272,13 +269,7 @@ __device__ __forceinline__ void leaf_dense(const float4 *__restrict__ Qs,
                 pn[u] = uniform_f4(Ps[nfirst + u]);
             }
         }
-        if ((mask >> lane) & 1ull) {
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                V[c] += (double)tv[c];
-                if (WITH_A) A[c] += (double)ta[c];
-            }
-        }
+        if ((mask >> lane) & 1ull) tacc_add<WITH_A>(K, tv, ta);
         first = nfirst;
         count = ncount;
         mask = nmask;
@@ -292,14 +283,14 @@ __device__ __forceinline__ void leaf_dense(const float4 *__restrict__ Qs,
 // run side by side; the leaf's points are staged in LDS (the next sparse
 // leaf's points are loaded while the current one is summed).  The R partial
 // sums of a target are added across lanes (butterfly over the row bits) and
-// moved to the target's lane, which adds them to its FP64 sums.
+// moved to the target's lane, which adds them to its compensated sums.
 template <bool WITH_A>
 __device__ __forceinline__ void leaf_sparse(const float4 *__restrict__ Qs,
                                             const float4 *__restrict__ Ps,
                                             const LeafEntry *__restrict__ list,
                                             const int *__restrict__ list_n, int64_t grp,
                                             TravSplit split, int v0, int v1, int lane,
-                                            float negc, LeafLds &L, double *V, double *A,
+                                            float negc, LeafLds &L, TAcc &K,
                                             unsigned &steps) {
     if (v0 >= v1) return;
     EntryBatch eb;
@@ -369,13 +360,7 @@ __device__ __forceinline__ void leaf_sparse(const float4 *__restrict__ Qs,
             gv[c] = __shfl(tv[c], rank, 64);
             ga[c] = WITH_A ? __shfl(ta[c], rank, 64) : 0.f;
         }
-        if (mine) {
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                V[c] += (double)gv[c];
-                if (WITH_A) A[c] += (double)ga[c];
-            }
-        }
+        if (mine) tacc_add<WITH_A>(K, gv, ga);
         v = vn;
         first = nfirst;
         count = ncount;
@@ -392,7 +377,7 @@ template <bool WITH_A>
 __global__ __launch_bounds__(256) void k_bh_decide(
     const BhNode *__restrict__ nodes, const float4 *__restrict__ Qs,
     const float4 *__restrict__ Qc, const float4 *__restrict__ Ps, int64_t n, const GroupDesc *__restrict__ gtab, int64_t groups, TravSplit split, BhParams bp,
-    LeafEntry *__restrict__ list, int *__restrict__ list_n, double *__restrict__ part,
+    LeafEntry *__restrict__ list, int *__restrict__ list_n, float2 *__restrict__ part,
     u64 *__restrict__ counters, const TreeTotals *__restrict__ totals, int *__restrict__ status) {
     __shared__ DecideLds lds_all[4];
     const int lane = threadIdx.x & 63, wv = wave_in_block();
@@ -410,7 +395,8 @@ __global__ __launch_bounds__(256) void k_bh_decide(
     const double xd = xa.x, yd = xa.y, zd = xa.z;
     LeafEntry *mylist = list + grp * kListPerGroup + (int64_t)sub * split.segcap;
 
-    double V[3] = {0, 0, 0}, A[3] = {0, 0, 0};
+    TAcc K;
+    tacc_zero(K);
     float mv[3] = {0.f, 0.f, 0.f}, ma[3] = {0.f, 0.f, 0.f};
     u64 c_pairs = 0, c_mono = 0, c_visit = 0;  // wave totals (scalars)
     unsigned w_steps = 0, w_nodes = 0;
@@ -498,8 +484,10 @@ __global__ __launch_bounds__(256) void k_bh_decide(
                     // list full: sum this leaf here
                     w_steps += (unsigned)nn;
                     const float4 xc = active ? Qc[t] : make_float4(0.f, 0.f, 0.f, 0.f);
+                    float tv[3], ta[3];
                     leaf_direct<WITH_A>(Qc, Ps, nfirst, nn, (open >> lane) & 1ull, xc, xp,
-                                        bp.negc, V, A);
+                                        bp.negc, tv, ta);
+                    tacc_add<WITH_A>(K, tv, ta);
                 }
             } else {
                 if (sp >= kBlockStack) {
@@ -527,12 +515,8 @@ __global__ __launch_bounds__(256) void k_bh_decide(
         }
         wave_sync();
     }
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        V[c] += (double)mv[c];
-        A[c] += (double)ma[c];
-    }
-    write_part(part, sub, npad, grp * 64 + lane, V, A);
+    tacc_add<true>(K, mv, ma);
+    write_part_ff(part, sub, npad, grp * 64 + lane, K);
     if (lane == 0) list_n[grp * kSub + sub] = nlist;
 
     // counters: one atomic per wave and counter (integer, order-free)
@@ -561,7 +545,7 @@ __global__ __launch_bounds__(256) void k_bh_leaves(const float4 *__restrict__ Qc
                                                    int64_t groups, TravSplit split, float negc,
                                                    const LeafEntry *__restrict__ list,
                                                    const int *__restrict__ list_n,
-                                                   double *__restrict__ part,
+                                                   float2 *__restrict__ part,
                                                    u64 *__restrict__ counters) {
     const int lane = threadIdx.x & 63, wv = wave_in_block();
     const int64_t grp = blockIdx.x;
@@ -580,12 +564,12 @@ __global__ __launch_bounds__(256) void k_bh_leaves(const float4 *__restrict__ Qc
     LeafLds &L = lds_all[wv];
     L.tq[lane] = xq;
     L.tp[lane] = xp;
-    double V[3] = {0, 0, 0}, A[3] = {0, 0, 0};
+    TAcc K;
+    tacc_zero(K);
     unsigned steps = 0;
-    leaf_dense<WITH_A>(Qc, Ps, list, list_n, grp, split, v0, v1, lane, xq, xp, negc, V, A,
-                       steps);
-    leaf_sparse<WITH_A>(Qc, Ps, list, list_n, grp, split, v0, v1, lane, negc, L, V, A, steps);
-    write_part(part, split.nsub + chunk, npad, grp * 64 + lane, V, A);
+    leaf_dense<WITH_A>(Qc, Ps, list, list_n, grp, split, v0, v1, lane, xq, xp, negc, K, steps);
+    leaf_sparse<WITH_A>(Qc, Ps, list, list_n, grp, split, v0, v1, lane, negc, L, K, steps);
+    write_part_ff(part, split.nsub + chunk, npad, grp * 64 + lane, K);
     if (lane == 0 && counters) {
         u64 *c = counter_slot(counters, blockIdx.x, blockIdx.y);
         atomicAdd(&c[4], (u64)steps);
@@ -593,17 +577,22 @@ __global__ __launch_bounds__(256) void k_bh_leaves(const float4 *__restrict__ Qc
     }
 }
 
-// Phase 3: fixed-order sum of a target's parts and the output of the mode.
-// One thread per (group, lane) slot; the energy sum of each group (one wave)
-// goes to Hpart[group].
+// Phase 3: fixed-order double-float sum of a target's parts and the output of
+// the mode.  One thread per (group, lane) slot; the energy sum of each group
+// (one wave, FP64) goes to Hpart[group].
+//   MODE_RHS: v and a / sigma^2 rounded to FP32 into dq, dp;
+//   MODE_SHOOT: one Euler step of the state, hi+lo (Fq, Fp: the step in
+//     double-float) or FP64 (Sq, Sp), and its FP32 copies q32, p32;
+//   MODE_ENERGY: only p . v (and v into v64 when given).
 template <bool WITH_A>
 __global__ __launch_bounds__(256) void k_bh_combine(
-    const double *__restrict__ part, const int *__restrict__ list_n,
+    const float2 *__restrict__ part, const int *__restrict__ list_n,
     const GroupDesc *__restrict__ gtab, int64_t groups, TravSplit split,
-    const unsigned *__restrict__ perm, int64_t n, double inv_s2, int mode,
-    float *__restrict__ dq, float *__restrict__ dp, double *__restrict__ Sq,
-    double *__restrict__ Sp, float *__restrict__ q32, float *__restrict__ p32,
-    const double *__restrict__ c0, double dt, double *__restrict__ Hpart,
+    const unsigned *__restrict__ perm, int64_t n, double inv_s2, ff inv_s2f, int mode,
+    float *__restrict__ dq, float *__restrict__ dp, float2 *__restrict__ Fq,
+    float2 *__restrict__ Fp, double *__restrict__ Sq, double *__restrict__ Sp,
+    float *__restrict__ q32, float *__restrict__ p32, const double *__restrict__ c0,
+    const float2 *__restrict__ c0f, double dt, ff dtf, double *__restrict__ Hpart,
     double *__restrict__ v64) {
     const int lane = threadIdx.x & 63;
     const int64_t grp = (int64_t)blockIdx.x * 4 + wave_in_block();
@@ -614,26 +603,57 @@ __global__ __launch_bounds__(256) void k_bh_combine(
     double e = 0.0;
     if (lane < gd.count) {
         const int nslots = split.nsub + chunk_split(list_n, grp, split).chunks;
-        double V[3] = {0, 0, 0}, A[3] = {0, 0, 0};
-        for (int s = 0; s < nslots; ++s) {
-            const double *d = part + ((int64_t)s * npad + slot) * 6;
+        ff acc[6];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                V[c] += d[c];
-                A[c] += d[3 + c];
+        for (int c = 0; c < 6; ++c) acc[c] = ff{0.f, 0.f};
+        for (int s = 0; s < nslots; ++s) {
+            const float2 *d = part + ((int64_t)s * npad + slot) * 6;
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+                if (c >= 3 && !WITH_A) break;
+                const float2 u = d[c];
+                acc[c] = ff_add(acc[c], ff{u.x, u.y});
             }
         }
         const int64_t i = perm[(int64_t)gd.first + lane];
+        double V[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) V[c] = (double)acc[c].h + (double)acc[c].l;
         if (v64)
 #pragma unroll
             for (int c = 0; c < 3; ++c) v64[3 * i + c] = V[c];
         if (mode == MODE_RHS) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                dq[3 * i + c] = (float)V[c];
-                if (WITH_A) dp[3 * i + c] = (float)(A[c] * inv_s2);
+                dq[3 * i + c] = acc[c].h + acc[c].l;
+                if (WITH_A) {
+                    const ff a = ff_mul(acc[3 + c], inv_s2f);
+                    dp[3 * i + c] = a.h + a.l;
+                }
             }
-        } else {
+        } else if (Fq) {  // hi+lo state
+            ff q[3], p[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const float2 fq = Fq[3 * i + c], fp = Fp[3 * i + c];
+                q[c] = ff{fq.x, fq.y};
+                p[c] = ff{fp.x, fp.y};
+                e += ((double)p[c].h + (double)p[c].l) * V[c];
+            }
+            if (mode == MODE_SHOOT) {
+                const float2 *cs = c0f + 3 * gd.sub;  // the shooting's frame of this set
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    q[c] = ff_add(q[c], ff_mul(dtf, acc[c]));
+                    if (WITH_A) p[c] = ff_add(p[c], ff_mul(dtf, ff_mul(acc[3 + c], inv_s2f)));
+                    Fq[3 * i + c] = make_float2(q[c].h, q[c].l);
+                    Fp[3 * i + c] = make_float2(p[c].h, p[c].l);
+                    const ff r = ff_add(q[c], ff{-cs[c].x, -cs[c].y});
+                    q32[3 * i + c] = r.h + r.l;
+                    p32[3 * i + c] = p[c].h + p[c].l;
+                }
+            }
+        } else {  // FP64 state
             double q[3], p[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
@@ -642,11 +662,12 @@ __global__ __launch_bounds__(256) void k_bh_combine(
             }
             e = p[0] * V[0] + p[1] * V[1] + p[2] * V[2];
             if (mode == MODE_SHOOT) {
-                const double *cs = c0 + 3 * gd.sub;  // the shooting's frame of this set
+                const double *cs = c0 + 3 * gd.sub;
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
+                    const double a = WITH_A ? ((double)acc[3 + c].h + (double)acc[3 + c].l) : 0.0;
                     q[c] += dt * V[c];
-                    p[c] += dt * (A[c] * inv_s2);
+                    p[c] += dt * (a * inv_s2);
                     Sq[3 * i + c] = q[c];
                     Sp[3 * i + c] = p[c];
                     q32[3 * i + c] = (float)(q[c] - cs[c]);
@@ -660,14 +681,6 @@ __global__ __launch_bounds__(256) void k_bh_combine(
         for (int off = 32; off > 0; off >>= 1) e += __shfl_down(e, off, 64);
         if (lane == 0) Hpart[grp] = e;
     }
-}
-
-__global__ void k_state_out(const double *__restrict__ Sq, const double *__restrict__ Sp,
-                            int64_t n3, float *__restrict__ q, float *__restrict__ p) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n3) return;
-    q[i] = (float)Sq[i];
-    p[i] = (float)Sp[i];
 }
 
 // Clears the status word with a kernel (no memset nodes, so the launch
@@ -737,19 +750,24 @@ gs_status launch_bh_traverse(const TreeBufs &t, const BhParams &bp, bool with_a,
     LeafEntry *list = reinterpret_cast<LeafEntry *>(t.list);
     const int kind = with_a ? KIND_TRAVERSE : KIND_TRAVERSE_V;
     const TravSplit split = traverse_split(groups);
+    // the partial sums of this traversal are double-float pairs (the buffer
+    // holds the backward stage's FP64 partials, of the same size)
+    float2 *part = reinterpret_cast<float2 *>(t.part);
+    const ff inv_s2f = ff_from_double(bp.inv_s2), dtf = ff_from_double(o.dt);
     const dim3 g1((unsigned)((groups * split.nsub + 3) / 4)), g2((unsigned)groups, (split.maxc + 3) / 4),
         g3((unsigned)((groups + 3) / 4));
     timing_begin(kind, s);
 #define GS_PHASES(A)                                                                         \
     do {                                                                                     \
         hipLaunchKernelGGL(k_bh_decide<A>, g1, dim3(256), 0, s, t.nodes, t.Qs, t.Qc, t.Ps,    \
-                           t.n, t.gtab, groups, split, bp, list, t.list_n, t.part, counters,   \
+                           t.n, t.gtab, groups, split, bp, list, t.list_n, part, counters,     \
                            t.totals, status);                                               \
         hipLaunchKernelGGL(k_bh_leaves<A>, g2, dim3(256), 0, s, t.Qc, t.Ps, t.n, t.gtab,      \
-                           groups, split, bp.negc, list, t.list_n, t.part, counters);          \
-        hipLaunchKernelGGL(k_bh_combine<A>, g3, dim3(256), 0, s, t.part, t.list_n, t.gtab,    \
-                           groups, split, t.perm, t.n, bp.inv_s2, mode, o.dq, o.dp, o.Sq, o.Sp, \
-                           o.q32, o.p32, o.c0, o.dt, o.Hpart, o.v64);                       \
+                           groups, split, bp.negc, list, t.list_n, part, counters);            \
+        hipLaunchKernelGGL(k_bh_combine<A>, g3, dim3(256), 0, s, part, t.list_n, t.gtab,      \
+                           groups, split, t.perm, t.n, bp.inv_s2, inv_s2f, mode, o.dq, o.dp,   \
+                           o.Fq, o.Fp, o.Sq, o.Sp, o.q32, o.p32, o.c0, o.c0f, o.dt, dtf,       \
+                           o.Hpart, o.v64);                                                 \
     } while (0)
     if (with_a)
         GS_PHASES(true);
@@ -766,28 +784,34 @@ gs_status launch_bh_traverse(const TreeBufs &t, const BhParams &bp, bool with_a,
     return launch_bh_traverse(t, bp, with_a, o, counters, s, MODE_RHS, nullptr);
 }
 
-static void carve_state(Arena &a, int64_t n, int nt, ShootBhBufs &b) {
+static void carve_state(Arena &a, int64_t n, int nt, int state, ShootBhBufs &b) {
     b.c0 = a.take<double>(3 * (size_t)b.tree.nsub);
-    b.Sq = a.take<double>(3 * n);
-    b.Sp = a.take<double>(3 * n);
+    if (state == kStateFF) {
+        b.c0f = a.take<float2>(3 * (size_t)b.tree.nsub);
+        b.Fq = a.take<float2>(3 * n);
+        b.Fp = a.take<float2>(3 * n);
+    } else {
+        b.Sq = a.take<double>(3 * n);
+        b.Sp = a.take<double>(3 * n);
+    }
     b.q32 = a.take<float>(3 * n);
     b.p32 = a.take<float>(3 * n);
     b.Hpart = a.take<double>((size_t)(nt + 1) * (b.tree.groups > 0 ? b.tree.groups : 1));
 }
 
-ShootBhBufs layout_shoot_bh(Arena &a, int64_t n, int nt) {
+ShootBhBufs layout_shoot_bh(Arena &a, int64_t n, int nt, int state) {
     ShootBhBufs b{};
     carve_tree(a, n, b.tree);
-    carve_state(a, n, nt, b);
+    carve_state(a, n, nt, state, b);
     b.gseg = nullptr;
     return b;
 }
 
 ShootBhBufs layout_shoot_forest(Arena &a, int64_t n, int nsub, int64_t groups, int64_t max_set,
-                                int nt) {
+                                int nt, int state) {
     ShootBhBufs b{};
     carve_forest(a, n, nsub, groups, max_set, b.tree);
-    carve_state(a, n, nt, b);
+    carve_state(a, n, nt, state, b);
     b.gseg = nullptr;
     return b;
 }
@@ -812,16 +836,18 @@ gs_status shoot_bh(const float *q0, const float *p0, int64_t n, const gs_params 
     // the FP32 copies that every step's tree and pairs are built from are kept
     // relative to the frame origin of q0 (fixed for the call), so their rounding
     // does not depend on where the set lies
-    GS_TRY(tree_set_centres(q0, b.tree, b.c0, status, s));
-    GS_TRY(launch_state_init(q0, p0, b.tree, b.c0, b.Sq, b.Sp, b.q32, b.p32, s));
+    GS_TRY(tree_set_centres(q0, b.tree, b.c0, b.c0f, status, s));
+    GS_TRY(launch_state_init(q0, p0, b.tree, b.c0, b.c0f, nullptr, nullptr, b.Fq, b.Fp, b.q32,
+                             b.p32, s));
     const BhParams bp = make_bh_params(prm);
     const int64_t ng = b.tree.groups;
     TraverseOut o{};
-    o.Sq = b.Sq;
-    o.Sp = b.Sp;
+    o.Fq = b.Fq;
+    o.Fp = b.Fp;
     o.q32 = b.q32;
     o.p32 = b.p32;
     o.c0 = b.c0;
+    o.c0f = b.c0f;
     o.dt = 1.0 / prm.nt;
     for (int t = 0; t < prm.nt; ++t) {
         GS_TRY(build_tree(b.q32, b.p32, n, prm.leaf_cap, b.tree, status, s));
@@ -834,10 +860,7 @@ gs_status shoot_bh(const float *q0, const float *p0, int64_t n, const gs_params 
         GS_TRY(launch_bh_traverse(b.tree, bp, false, o, counters, s, MODE_ENERGY, status));
         GS_TRY(launch_reduce_h_seg(b.Hpart, ng, b.gseg, b.tree.nsub, prm.nt + 1, H, s));
     }
-    hipLaunchKernelGGL(k_state_out, dim3(nblk(3 * n)), dim3(kBlock), 0, s, b.Sq, b.Sp, 3 * n, q1,
-                       p1);
-    GS_LAUNCH_CHECK("state_out");
-    return GS_OK;
+    return launch_unpack_state(b.Fq, b.Fp, n, q1, p1, s);
 }
 
 }  // namespace gs

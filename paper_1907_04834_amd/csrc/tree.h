@@ -113,7 +113,8 @@ struct TreeBufs {
     // traversal work split (see traverse.hip)
     char *list;                // leaf entries of each group, one segment per phase-1 wave
     int *list_n;               // entries used per segment
-    double *part;              // [1 + chunks][groups * 64][6] partial (v, a) sums
+    double *part;              // [slots][groups * 64][6] partial (v, a) sums: FP64 (backward
+                               // stage) or, reinterpreted, float2 hi+lo (forward traversal)
 };
 // Sizes of the traversal's work-split buffers (defined in traverse.hip).
 size_t traverse_list_bytes(int64_t groups);
@@ -133,11 +134,14 @@ gs_status build_tree(const float *q, const float *p, int64_t n, int leaf_cap, Tr
 // Frame origin of every set of q (FP32 [n][3]; its box centre rounded to a
 // multiple of a power of two, see frame_origin) into c0 (FP64 [nsub][3]); uses
 // the tree's box buffers and sets `status` for non-finite coordinates.
-gs_status tree_set_centres(const float *q, TreeBufs &t, double *c0, int *status, hipStream_t s);
-// The FP64 state of float inputs (Sq, Sp) and its FP32 copies q32 = q - c0[set],
-// p32 = p; one thread per point.
+// c0f (nullable) receives the same origins as double-float.
+gs_status tree_set_centres(const float *q, TreeBufs &t, double *c0, float2 *c0f, int *status,
+                           hipStream_t s);
+// The state of float inputs, FP64 (Sq, Sp) or hi+lo (Fq, Fp; the other pair
+// null), and its FP32 copies q32 = q - c0[set], p32 = p; one thread per point.
 gs_status launch_state_init(const float *q0, const float *p0, const TreeBufs &t, const double *c0,
-                            double *Sq, double *Sp, float *q32, float *p32, hipStream_t s);
+                            const float2 *c0f, double *Sq, double *Sp, float2 *Fq, float2 *Fp,
+                            float *q32, float *p32, hipStream_t s);
 // FP32 copies q32 = Sq - c0[set], p32 = Sp of an FP64 state.
 gs_status launch_state_to_f32(const double *Sq, const double *Sp, const TreeBufs &t,
                               const double *c0, float *q32, float *p32, hipStream_t s);
@@ -189,16 +193,19 @@ __device__ __forceinline__ unsigned long long uniform_u64(unsigned long long v) 
 }
 
 // Forward traversal.  Writes (v, a) for every point in original order: as FP32
-// into dq/dp when they are non-null, else it advances the FP64 state
-// (Sq += dt v, Sp += dt a), refreshes the FP32 copies q32/p32 and writes
-// the sum of p . v of every traversal group into Hpart[group] (nullable).
+// into dq/dp (MODE_RHS), or it advances the state (MODE_SHOOT: q += dt v,
+// p += dt a, hi+lo in Fq/Fp when Fq is set, else FP64 in Sq/Sp), refreshes
+// the FP32 copies q32/p32 and writes the sum of p . v of every traversal
+// group into Hpart[group] (nullable).
 // counters (zeroed by the caller) receive exact pairs, monopoles, node
 // visits and the wave statistics.
 struct TraverseOut {
     float *dq, *dp;                    // RHS mode
-    double *Sq, *Sp;                   // shooting mode
-    float *q32, *p32;                  // FP32 copies: q32 = Sq - c0[set]
-    const double *c0;                  // [nsub][3] centres of the shooting's frame
+    float2 *Fq, *Fp;                   // shooting: hi+lo state [n][3] (hi, lo) pairs
+    double *Sq, *Sp;                   // the backward stage's forward steps: FP64 state
+    float *q32, *p32;                  // FP32 copies: q32 = q - c0[set]
+    const double *c0;                  // [nsub][3] frame origins of the shooting
+    const float2 *c0f;                 // [nsub][3] the same as double-float (hi+lo state)
     double dt;
     double *Hpart;
     double *v64;                       // velocity only (energy pass), nullable
@@ -218,16 +225,19 @@ gs_status tree_range_sums(const float4 *A, const float4 *B, TreeBufs &t, double 
 
 struct ShootBhBufs {
     TreeBufs tree;
-    double *Sq, *Sp;   // FP64 state [n][3]
+    float2 *Fq, *Fp;   // shooting state, FP32 (hi, lo) pairs [n][3]
+    double *Sq, *Sp;   // FP64 state [n][3] (the backward stage's forward steps)
     float *q32, *p32;  // FP32 copies [n][3], q32 relative to c0
     double *c0;        // [nsub][3] frame origins of q0, fixed for the call
+    float2 *c0f;       // [nsub][3] the same as double-float
     double *Hpart;     // [nt + 1][groups]
     const int *gseg;   // [nsub + 1] group range of each set (nullable: one set)
 };
-ShootBhBufs layout_shoot_bh(Arena &a, int64_t n, int nt);
+// state: kStateFF (shooting) or kStateF64 (the backward stage's forward steps).
+ShootBhBufs layout_shoot_bh(Arena &a, int64_t n, int nt, int state = kStateFF);
 // The same for a forest; the caller sets tree.seg, tree.gtab and gseg.
 ShootBhBufs layout_shoot_forest(Arena &a, int64_t n, int nsub, int64_t groups, int64_t max_set,
-                                int nt);
+                                int nt, int state = kStateFF);
 
 gs_status rhs_bh(const float *q, const float *p, int64_t n, const gs_params &prm, float *dq,
                  float *dp, TreeBufs &t, char *ws, hipStream_t s);

@@ -931,24 +931,41 @@ __global__ __launch_bounds__(256) void k_node_sums(const float4 *__restrict__ A,
 }
 
 __global__ void k_copy_centres(const TreeMeta *__restrict__ meta, int nsub,
-                               double *__restrict__ c0) {
+                               double *__restrict__ c0, float2 *__restrict__ c0f) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < 3 * nsub) c0[i] = meta[i / 3].cen[i % 3];
+    if (i >= 3 * nsub) return;
+    const double c = meta[i / 3].cen[i % 3];
+    c0[i] = c;
+    if (c0f) {
+        const float ch = (float)c;
+        c0f[i] = make_float2(ch, (float)(c - (double)ch));  // exact split
+    }
 }
 
+// The state of float inputs: FP64 (Sq, Sp non-null) or hi+lo (Fq, Fp,
+// (hi, lo) pairs), and its FP32 copies q32 = q - c0[set], p32 = p.
 __global__ void k_state_init(const float *__restrict__ q, const float *__restrict__ p, int64_t n,
                              const long long *__restrict__ seg, int nsub,
-                             const double *__restrict__ c0, double *__restrict__ Sq,
-                             double *__restrict__ Sp, float *__restrict__ q32,
-                             float *__restrict__ p32) {
+                             const double *__restrict__ c0, const float2 *__restrict__ c0f,
+                             double *__restrict__ Sq, double *__restrict__ Sp,
+                             float2 *__restrict__ Fq, float2 *__restrict__ Fp,
+                             float *__restrict__ q32, float *__restrict__ p32) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const double *c = c0 + 3 * set_of(seg, nsub, i);
+    const int si = set_of(seg, nsub, i);
     for (int k = 0; k < 3; ++k) {
         const float a = q[3 * i + k], b = p[3 * i + k];
-        Sq[3 * i + k] = a;
-        Sp[3 * i + k] = b;
-        q32[3 * i + k] = (float)((double)a - c[k]);
+        if (Fq) {
+            Fq[3 * i + k] = make_float2(a, 0.f);
+            Fp[3 * i + k] = make_float2(b, 0.f);
+            const float2 c = c0f[3 * si + k];
+            const ff r = ff_add(ff_two_sum(a, -c.x), -c.y);
+            q32[3 * i + k] = r.h + r.l;
+        } else {
+            Sq[3 * i + k] = a;
+            Sp[3 * i + k] = b;
+            q32[3 * i + k] = (float)((double)a - c0[3 * si + k]);
+        }
         p32[3 * i + k] = b;
     }
 }
@@ -1104,23 +1121,25 @@ gs_status build_tree(const float *q, const float *p, int64_t n, int leaf_cap, Tr
     return GS_OK;
 }
 
-gs_status tree_set_centres(const float *q, TreeBufs &t, double *c0, int *status, hipStream_t s) {
+gs_status tree_set_centres(const float *q, TreeBufs &t, double *c0, float2 *c0f, int *status,
+                           hipStream_t s) {
     const int nsub = t.nsub;
     hipLaunchKernelGGL(k_bbox_partial, dim3(t.bbox_blocks, nsub), dim3(256), 0, s, q, t.n, t.seg,
                        t.bbox_part, nullptr, (int64_t)0);
     hipLaunchKernelGGL(k_bbox_final, dim3(nsub), dim3(64), 0, s, t.bbox_part, t.bbox_blocks,
                        t.meta, status);
     hipLaunchKernelGGL(k_copy_centres, dim3(nblk(3 * (int64_t)nsub)), dim3(256), 0, s, t.meta,
-                       nsub, c0);
+                       nsub, c0, c0f);
     GS_LAUNCH_CHECK("set_centres");
     return GS_OK;
 }
 
 gs_status launch_state_init(const float *q0, const float *p0, const TreeBufs &t, const double *c0,
-                            double *Sq, double *Sp, float *q32, float *p32, hipStream_t s) {
+                            const float2 *c0f, double *Sq, double *Sp, float2 *Fq, float2 *Fp,
+                            float *q32, float *p32, hipStream_t s) {
     if (t.n == 0) return GS_OK;
     hipLaunchKernelGGL(k_state_init, dim3(nblk(t.n)), dim3(256), 0, s, q0, p0, t.n, t.seg, t.nsub,
-                       c0, Sq, Sp, q32, p32);
+                       c0, c0f, Sq, Sp, Fq, Fp, q32, p32);
     GS_LAUNCH_CHECK("state_init");
     return GS_OK;
 }
