@@ -93,6 +93,10 @@ def host_info(torch):
     info["compute_units"] = p.multi_processor_count
     clk = getattr(p, "clock_rate", None)
     info["gpu_max_sclk_mhz"] = clk / 1000.0 if clk else None
+    if any(k.startswith("ROCPROF") for k in os.environ):
+        # under a profiler its preloaded library would start in the child too
+        info["rocm_smi_clocks"] = None
+        return info
     try:
         import subprocess
         r = subprocess.run(["rocm-smi", "--showclocks"], capture_output=True, text=True,
