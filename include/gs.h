@@ -124,7 +124,8 @@ typedef struct {
                               waves) that a launch aims at; 0 = the library
                               default (24576), else
                               256..4194304.  Changes speed and workspace
-                              size, not results beyond FP64 summation order;
+                              size, not results beyond the order in which
+                              the partial sums are added;
                               gs_autotune_exact picks it.                    */
 } gs_params;
 
@@ -171,7 +172,9 @@ gs_status gs_rhs_bh(const float *q, const float *p, int64_t n, const gs_params *
  * prm->nt forward-Euler steps of size 1/nt from (q0, p0), each step using the
  * right-hand side of `method` evaluated at the state at the start of the
  * step.  Writes q1 = q(1), p1 = p(1).  H (nullable, DEVICE double[nt + 1])
- * receives <p_t, v_t> for t = 0..nt (FP64 reduction; v from `method`). */
+ * receives <p_t, v_t> for t = 0..nt (FP64 reduction; v from `method`).  The
+ * state is carried as FP32 (hi, lo) pairs and each step is taken in
+ * double-float arithmetic; FP64 serves only the H reduction. */
 gs_status gs_shoot(const float *q0, const float *p0, int64_t n, const gs_params *prm,
                    int32_t method, float *q1, float *p1, double *H, void *ws,
                    size_t ws_bytes, hipStream_t stream);
@@ -207,8 +210,8 @@ gs_status gs_shoot_adjoint(const float *q0, const float *p0, const float *target
 
 /* Velocity field of eq. (3) at m arbitrary points x (DEVICE float[m][3]):
  * v(x) = sum_j G(|x - q_j|) p_j over the n sources (q, p).  Exact sum, FP32
- * pairs with FP64 accumulation, positions relative to the sources' box
- * centre.  The workspace comes from gs_field_workspace_bytes (0 for invalid
+ * pairs with compensated FP32 accumulation, positions relative to the
+ * sources' box centre.  The workspace comes from gs_field_workspace_bytes (0 for invalid
  * arguments). */
 size_t gs_field_workspace_bytes(int64_t m, int64_t n, const gs_params *prm);
 gs_status gs_field(const float *x, int64_t m, const float *q, const float *p, int64_t n,
@@ -326,7 +329,7 @@ gs_status gs_tree_export(const float *q, const float *p, int64_t n, const gs_par
  * most GS_STATIC_MAX_N (500 000): larger n returns GS_ERR_WORKSPACE before any
  * device work.  The work-item target (prm->exact_items, 0 = the default) is
  * halved, not below 256, until the workspace fits the array, which changes
- * only the FP64 summation order.  The call copies nothing from the host and
+ * only the order in which partial sums are added.  The call copies nothing from the host and
  * only enqueues kernels on `stream`, so it may be captured into a HIP graph.
  * Every call on a device shares that device's array, which keeps the last
  * call's contents (no result depends on them): calls that overlap on one

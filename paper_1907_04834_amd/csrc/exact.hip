@@ -6,7 +6,7 @@
 //   * a work item is one block: kItemGroups groups of 64 consecutive target
 //     rows (one target per lane) against one chunk of source rows of the same
 //     point set; the chunk is split among kItemSplit waves per target group,
-//     whose FP64 sums are added in LDS in a fixed order and written as one
+//     whose double-float sums are added in LDS in a fixed order and written as one
 //     partial per (target, chunk); the combine kernel adds a target's
 //     partials in chunk order (bitwise deterministic);
 //   * sources are read with wave-uniform addresses, so they arrive through
