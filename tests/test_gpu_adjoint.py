@@ -2,7 +2,7 @@
 oracle, finite differences and its own invariances.
 
 Tolerances: the GPU adjoint uses FP32 pair arithmetic with FP64 sums and an
-FP64 state, like the forward: gradient rel-L2 1e-5 against the oracle's
+FP64 state (the gradient computation keeps FP64): gradient rel-L2 1e-5 against the oracle's
 exact adjoint; directional derivatives within 1e-4 relative of central
 differences (h = 1e-4) of the FP64 GPU forward; the Barnes-Hut backward stage
 within 1e-5 of the oracle's Barnes-Hut gradient (measured ~5e-8; the
