@@ -38,8 +38,14 @@ typedef unsigned long long u64;
 constexpr int kBlockStack = 192;  // entries of (first child, count, lane mask, ownership)
 constexpr int kSub = 8;           // phase-1 waves per group, at most
 constexpr int kListPerGroup = 4096;  // list entries of a group, shared out among its phase-1 waves
-constexpr int kMaxChunks = 16;    // phase-2 waves per group, at most
-constexpr int kMinChunk = 32;     // entries per phase-2 wave, at least (unless fewer in all)
+#ifndef GS_MAX_CHUNKS
+#define GS_MAX_CHUNKS 16
+#endif
+#ifndef GS_MIN_CHUNK
+#define GS_MIN_CHUNK 32
+#endif
+constexpr int kMaxChunks = GS_MAX_CHUNKS;  // phase-2 waves per group, at most
+constexpr int kMinChunk = GS_MIN_CHUNK;    // entries per phase-2 wave, at least (unless fewer in all)
 constexpr int kParts = kSub + kMaxChunks;
 
 // Waves per group: nsub (<= kSub) in phase 1, each with a list segment of
