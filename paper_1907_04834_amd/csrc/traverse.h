@@ -42,7 +42,7 @@ constexpr int kListPerGroup = 4096;  // list entries of a group, shared out amon
 #define GS_MAX_CHUNKS 16
 #endif
 #ifndef GS_MIN_CHUNK
-#define GS_MIN_CHUNK 32
+#define GS_MIN_CHUNK 16
 #endif
 constexpr int kMaxChunks = GS_MAX_CHUNKS;  // phase-2 waves per group, at most
 constexpr int kMinChunk = GS_MIN_CHUNK;    // entries per phase-2 wave, at least (unless fewer in all)
