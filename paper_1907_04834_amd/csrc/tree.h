@@ -85,6 +85,7 @@ struct TreeBufs {
     int sort_tiles;            // radix-sort tiles
     int sort_sbs;              // superblocks of 16 tiles
     int sort_passes;
+    int block_sort;            // every set has at most 2048 points: one block sorts each set
     TreeMeta *meta;            // [nsub]
     TreeTotals *totals;
     float *bbox_part;          // [nsub][bbox_blocks][6]

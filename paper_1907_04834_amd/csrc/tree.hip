@@ -437,6 +437,65 @@ __global__ __launch_bounds__(256) void k_os_scatter(
     }
 }
 
+// Sets of at most kBlockSortMax points: one block per set computes the keys
+// of its points and sorts (key, index within the set) pairs in LDS with a
+// bitonic network.  The pairs are distinct, so the order is that of the
+// stable radix sort (key, then index): identical results in one launch
+// instead of 15 to 17.
+constexpr int kBlockSortMax = 2048;
+__global__ __launch_bounds__(1024) void k_block_sort(const float *__restrict__ q,
+                                                     const long long *__restrict__ seg,
+                                                     const TreeMeta *__restrict__ meta_all,
+                                                     int64_t n, u64 *__restrict__ kout,
+                                                     unsigned *__restrict__ vout) {
+    __shared__ u64 sk[kBlockSortMax];
+    __shared__ unsigned sv[kBlockSortMax];
+    const int set = blockIdx.x;
+    const int64_t base = seg ? seg[set] : 0;
+    const int m = (int)((seg ? seg[set + 1] : n) - base);
+    if (m <= 0) return;  // block-uniform
+    int mp = 1;
+    while (mp < m) mp <<= 1;
+    const TreeMeta *meta = meta_all + set;
+    const double sc = meta->scale;
+    for (int i = threadIdx.x; i < mp; i += blockDim.x) {
+        if (i < m) {
+            const int64_t g = base + i;
+            const unsigned cx = quantize(q[3 * g], meta->lo[0], sc);
+            const unsigned cy = quantize(q[3 * g + 1], meta->lo[1], sc);
+            const unsigned cz = quantize(q[3 * g + 2], meta->lo[2], sc);
+            sk[i] = (spread3(cx) << 2) | (spread3(cy) << 1) | spread3(cz);
+            sv[i] = (unsigned)i;
+        } else {  // padding sorts last
+            sk[i] = ~0ull;
+            sv[i] = 0xffffffffu;
+        }
+    }
+    for (int k = 2; k <= mp; k <<= 1)
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            __syncthreads();
+            for (int i = threadIdx.x; i < mp; i += blockDim.x) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const u64 a = sk[i], b = sk[l];
+                    const unsigned va = sv[i], vb = sv[l];
+                    const bool gt = a > b || (a == b && va > vb);
+                    if (gt == ((i & k) == 0)) {  // ascending where bit k of i is clear
+                        sk[i] = b;
+                        sk[l] = a;
+                        sv[i] = vb;
+                        sv[l] = va;
+                    }
+                }
+            }
+        }
+    __syncthreads();
+    for (int i = threadIdx.x; i < m; i += blockDim.x) {
+        kout[base + i] = sk[i];
+        vout[base + i] = (unsigned)(base + sv[i]);
+    }
+}
+
 // Statistics of contiguous ranges of sorted points.  A two-level summary
 // (chunks of 64 points, super-chunks of 64 chunks) lets every node reduce
 // its own range [start, start + n) independently: no inter-node ordering,
@@ -1012,6 +1071,7 @@ void carve_forest(Arena &a, int64_t n, int nsub, int64_t groups, int64_t max_set
     t.sort_tiles = (int)((m + 256 * t.sort_per - 1) / (256 * t.sort_per));
     t.sort_sbs = (t.sort_tiles + kSbTiles - 1) / kSbTiles;
     t.sort_passes = kKeyPasses + (nsub > 1 ? (nsub > kOsBins ? 2 : 1) : 0);
+    t.block_sort = max_set <= kBlockSortMax ? 1 : 0;
     t.meta = a.take<TreeMeta>(nsub);
     t.totals = a.take<TreeTotals>(1);
     t.bbox_part = a.take<float>(6 * (size_t)t.bbox_blocks * nsub);
@@ -1019,8 +1079,8 @@ void carve_forest(Arena &a, int64_t n, int nsub, int64_t groups, int64_t max_set
     t.keyB = a.take<u64>(m);
     t.valA = a.take<unsigned>(m);
     t.valB = a.take<unsigned>(m);
-    t.K = (t.sort_passes & 1) ? t.keyB : t.keyA;
-    t.perm = (t.sort_passes & 1) ? t.valB : t.valA;
+    t.K = (t.sort_passes & 1) && !t.block_sort ? t.keyB : t.keyA;
+    t.perm = (t.sort_passes & 1) && !t.block_sort ? t.valB : t.valA;
     t.hist = a.take<unsigned>((size_t)kOsBins * t.sort_tiles);
     t.sb = a.take<unsigned>((size_t)2 * kOsBins * t.sort_sbs);
     t.scan_part = a.take<unsigned>((m + kScanTile - 1) / kScanTile + 1);
@@ -1050,6 +1110,9 @@ void carve_forest(Arena &a, int64_t n, int nsub, int64_t groups, int64_t max_set
 
 void carve_tree(Arena &a, int64_t n, TreeBufs &t) { carve_forest(a, n, 1, (n + 63) / 64, n, t); }
 
+static gs_status build_from_sorted(const float *q, const float *p, int64_t n, int leaf_cap,
+                                   TreeBufs &t, hipStream_t s);
+
 gs_status build_tree(const float *q, const float *p, int64_t n, int leaf_cap, TreeBufs &t,
                      int *status, hipStream_t s) {
     timing_begin(KIND_TREE, s);
@@ -1059,6 +1122,12 @@ gs_status build_tree(const float *q, const float *p, int64_t n, int leaf_cap, Tr
                        t.bbox_part, t.sb, sbn);
     hipLaunchKernelGGL(k_bbox_final, dim3(nsub), dim3(64), 0, s, t.bbox_part, t.bbox_blocks,
                        t.meta, status);
+    if (t.block_sort) {
+        hipLaunchKernelGGL(k_block_sort, dim3(nsub), dim3(1024), 0, s, q, t.seg, t.meta, n,
+                           t.keyA, t.valA);
+        GS_LAUNCH_CHECK("block sort");
+        return build_from_sorted(q, p, n, leaf_cap, t, s);
+    }
     const unsigned tiles = (unsigned)t.sort_tiles;
     const bool large = t.sort_per == kOsPerLarge;
     if (large)
@@ -1093,7 +1162,14 @@ gs_status build_tree(const float *q, const float *p, int64_t n, int leaf_cap, Tr
         vo = tv;
     }
     GS_LAUNCH_CHECK("radix sort");
-    const u64 *K = t.K;  // where the last pass left the sorted data
+    return build_from_sorted(q, p, n, leaf_cap, t, s);
+}
+
+// The octree from the sorted keys and permutation (t.K, t.perm).
+static gs_status build_from_sorted(const float *q, const float *p, int64_t n, int leaf_cap,
+                                   TreeBufs &t, hipStream_t s) {
+    const int nsub = t.nsub;
+    const u64 *K = t.K;
     const int64_t nc0 = (n + kChunk - 1) / kChunk, nc1 = (nc0 + kChunk - 1) / kChunk;
     RangeStat *c0 = reinterpret_cast<RangeStat *>(t.chunk0);
     RangeStat *c1 = reinterpret_cast<RangeStat *>(t.chunk1);
