@@ -288,6 +288,55 @@ __global__ __launch_bounds__(256) void k_adj_decide(
     }
 }
 
+// A list entry needed by at most kSparseMax of the wave's targets, summed
+// compacted (as in the forward leaf phase): with k targets in the mask and k'
+// the power of two >= k, lane l takes target slot i = l mod k' (the i-th lane
+// of the mask; its target data are read from that lane) and the staged
+// source rows l / k' + R j, R = 64 / k'.  The R partial sums of a slot are
+// added across lanes (butterfly over the row bits) and moved to the target's
+// lane, which adds them to its FP64 sums.  All lanes of the wave call it;
+// the leaf's points (count <= 64) are already staged in st.
+__device__ __forceinline__ void leaf_adjoint_compact(u64 mask, int count, float4 x, float4 px,
+                                                     float4 ax, float4 bx, float negc,
+                                                     float inv_s2, double *GQ, double *GP,
+                                                     float4 (*st)[64], int *slot, int lane) {
+    const int k = __popcll(mask);
+    const u64 below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    const bool mine = (mask >> lane) & 1ull;
+    const int rank = __popcll(mask & below);
+    if (mine) slot[rank] = lane;
+    wave_sync();
+    const int lg = k <= 1 ? 0 : 32 - __clz(k - 1);  // k' = 2^lg >= k
+    const int R = 64 >> lg;
+    const int i = lane & ((1 << lg) - 1), r = lane >> lg;
+    const bool valid = i < k;
+    const int tl = valid ? slot[i] : lane;
+    // the slot's target data, from its lane
+    const float4 tx = make_float4(__shfl(x.x, tl, 64), __shfl(x.y, tl, 64), __shfl(x.z, tl, 64), 0.f);
+    const float4 tp = make_float4(__shfl(px.x, tl, 64), __shfl(px.y, tl, 64), __shfl(px.z, tl, 64), 0.f);
+    const float4 ta = make_float4(__shfl(ax.x, tl, 64), __shfl(ax.y, tl, 64), __shfl(ax.z, tl, 64), 0.f);
+    const float4 tb = make_float4(__shfl(bx.x, tl, 64), __shfl(bx.y, tl, 64), __shfl(bx.z, tl, 64), 0.f);
+    float gq[3] = {0.f, 0.f, 0.f}, gp[3] = {0.f, 0.f, 0.f};
+    if (valid)
+        for (int j = r; j < count; j += R)
+            adj_pair(tx, tp, ta, tb, st[0][j], st[1][j], st[2][j], st[3][j], negc, inv_s2, gq, gp);
+    for (int off = 1 << lg; off < 64; off <<= 1)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            gq[c] += __shfl_xor(gq[c], off, 64);
+            gp[c] += __shfl_xor(gp[c], off, 64);
+        }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const float vq = __shfl(gq[c], rank, 64), vp = __shfl(gp[c], rank, 64);
+        if (mine) {
+            GQ[c] += (double)vq;
+            GP[c] += (double)vp;
+        }
+    }
+    wave_sync();  // slot is rewritten by the next entry
+}
+
 // Phase 2: one wave per (group, chunk of its list entries), on the positions
 // relative to the set's frame origin.
 __global__ __launch_bounds__(256) void k_adj_leaves(
@@ -297,6 +346,7 @@ __global__ __launch_bounds__(256) void k_adj_leaves(
     const int *__restrict__ list_n,
     double *__restrict__ part) {
     __shared__ float4 stage[4][4][64];
+    __shared__ int slots[4][64];
     const int lane = threadIdx.x & 63, wv = wave_in_block();
     const int64_t grp = blockIdx.x;
     const int chunk = blockIdx.y * 4 + wv;
@@ -317,8 +367,22 @@ __global__ __launch_bounds__(256) void k_adj_leaves(
         const LeafEntry e = list_take(list, list_n, grp, split, cur);
         const int first = __builtin_amdgcn_readfirstlane(e.first);
         const int count = __builtin_amdgcn_readfirstlane(e.count);
-        leaf_adjoint_staged(Qs, Ps, As, Bs, first, count, ((e.mask >> lane) & 1ull) != 0, xq, xp,
-                            xa, xb, negc, inv_s2, GQ, GP, stage[wv], lane);
+        const u64 mask = uniform_u64(e.mask);
+        if (sparse_entry(count, mask)) {
+            wave_sync();
+            if (lane < count) {
+                const int j = first + lane;
+                stage[wv][0][lane] = Qs[j];
+                stage[wv][1][lane] = Ps[j];
+                stage[wv][2][lane] = As[j];
+                stage[wv][3][lane] = Bs[j];
+            }
+            leaf_adjoint_compact(mask, count, xq, xp, xa, xb, negc, inv_s2, GQ, GP, stage[wv],
+                                 slots[wv], lane);
+        } else {
+            leaf_adjoint_staged(Qs, Ps, As, Bs, first, count, ((mask >> lane) & 1ull) != 0, xq,
+                                xp, xa, xb, negc, inv_s2, GQ, GP, stage[wv], lane);
+        }
     }
     write_part(part, split.nsub + chunk, npad, grp * 64 + lane, GQ, GP);
 }

@@ -82,6 +82,18 @@ __device__ __forceinline__ int child_ownership(int own) {
     return own + 1 < kDealDepth ? own + 1 : kOwnDealt;
 }
 
+// List entries needed by at most kSparseMax of the wave's targets, of at
+// most 64 points, are summed compacted (forward and backward leaf phases); the
+// others by every lane.  (A leaf can exceed leaf_cap only when its points share
+// one level-21 cell.)
+#ifndef GS_SPARSE_MAX
+#define GS_SPARSE_MAX 32
+#endif
+constexpr int kSparseMax = GS_SPARSE_MAX;  // a tuning build may change it (at most 32)
+__device__ inline bool sparse_entry(int count, u64 mask) {
+    return __popcll(mask) <= kSparseMax && count <= 64;
+}
+
 struct DecideLds {
     u64 mask[kBlockStack];
     int first[kBlockStack];

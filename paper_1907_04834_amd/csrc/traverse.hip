@@ -167,17 +167,6 @@ __device__ inline void batch_get(const EntryBatch &b, int v, int &first, int &co
            (u64)(unsigned)__builtin_amdgcn_readlane(b.mlo, i);
 }
 
-// List entries needed by at most kSparseMax of the wave's targets, of at
-// most 64 points, are summed compacted (see leaf_sparse); the others by every
-// lane (leaf_dense).  (A leaf can exceed leaf_cap only when its points share
-// one level-21 cell.)
-#ifndef GS_SPARSE_MAX
-#define GS_SPARSE_MAX 32
-#endif
-constexpr int kSparseMax = GS_SPARSE_MAX;  // a tuning build may change it (at most 32)
-__device__ inline bool sparse_entry(int count, u64 mask) {
-    return __popcll(mask) <= kSparseMax && count <= 64;
-}
 
 struct LeafLds {
     float4 tq[64], tp[64];  // the wave's targets (positions in the set's frame, momenta)
