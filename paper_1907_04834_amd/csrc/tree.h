@@ -85,7 +85,8 @@ struct TreeBufs {
     int sort_tiles;            // radix-sort tiles
     int sort_sbs;              // superblocks of 16 tiles
     int sort_passes;
-    int block_sort;            // every set has at most 2048 points: one block sorts each set
+    int block_sort;            // 1: every set has at most 2048 points, one block sorts each;
+                               // 2: one set of at most 32768, sorted in tiles and merged
     TreeMeta *meta;            // [nsub]
     TreeTotals *totals;
     float *bbox_part;          // [nsub][bbox_blocks][6]

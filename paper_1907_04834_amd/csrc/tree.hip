@@ -438,62 +438,156 @@ __global__ __launch_bounds__(256) void k_os_scatter(
 }
 
 // Sets of at most kBlockSortMax points: one block per set computes the keys
-// of its points and sorts (key, index within the set) pairs in LDS with a
-// bitonic network.  The pairs are distinct, so the order is that of the
+// of its points and sorts (key, index within the set) pairs with a bitonic
+// network.  The pairs are distinct, so the order is that of the
 // stable radix sort (key, then index): identical results in one launch
-// instead of 15 to 17.
+// instead of 15 to 17.  With tile > 0 (one set of n points) block b sorts the
+// tile [b tile, (b + 1) tile) instead, for k_merge_rank.
 constexpr int kBlockSortMax = 2048;
-__global__ __launch_bounds__(1024) void k_block_sort(const float *__restrict__ q,
-                                                     const long long *__restrict__ seg,
-                                                     const TreeMeta *__restrict__ meta_all,
-                                                     int64_t n, u64 *__restrict__ kout,
-                                                     unsigned *__restrict__ vout) {
+constexpr int kMergeTiles = 16;  // one set of at most 16 x 2048 points: tiles + merge
+
+// (no short-circuit operators: the comparisons stay branch-free)
+__device__ __forceinline__ bool kv_less(u64 ka, unsigned va, u64 kb, unsigned vb) {
+    return (ka < kb) | ((ka == kb) & (va < vb));
+}
+// One compare-exchange of a bitonic stage seen from one element: (a, va) at
+// position i, its partner (b, vb) at i ^ j; the lower position keeps the
+// smaller pair where bit k of i is clear (ascending runs), the larger where
+// it is set.  Returns whether the partner's pair is taken.
+__device__ __forceinline__ bool take_partner(u64 a, unsigned va, u64 b, unsigned vb, bool lower,
+                                             bool asc) {
+    const bool bl = kv_less(b, vb, a, va);
+    const bool al = !bl & ((a != b) | (va != vb));  // a before b (the pairs differ or are equal)
+    return (lower == asc) ? bl : al;
+}
+
+// 256 threads, 8 consecutive positions per thread (2048 in all, padded with
+// the largest pair): exchanges between positions of one thread in
+// registers, within a wave by lane shuffles, across waves through LDS.
+__global__ __launch_bounds__(256) void k_block_sort(const float *__restrict__ q,
+                                                    const long long *__restrict__ seg,
+                                                    const TreeMeta *__restrict__ meta_all,
+                                                    int64_t n, int tile, u64 *__restrict__ kout,
+                                                    unsigned *__restrict__ vout) {
     __shared__ u64 sk[kBlockSortMax];
     __shared__ unsigned sv[kBlockSortMax];
-    const int set = blockIdx.x;
-    const int64_t base = seg ? seg[set] : 0;
-    const int m = (int)((seg ? seg[set + 1] : n) - base);
+    const int set = tile > 0 ? 0 : blockIdx.x;
+    const int64_t base = tile > 0 ? (int64_t)blockIdx.x * tile : (seg ? seg[set] : 0);
+    const int64_t end = tile > 0 ? (base + tile < n ? base + tile : n) : (seg ? seg[set + 1] : n);
+    const int m = (int)(end - base);
     if (m <= 0) return;  // block-uniform
-    int mp = 1;
-    while (mp < m) mp <<= 1;
     const TreeMeta *meta = meta_all + set;
     const double sc = meta->scale;
-    for (int i = threadIdx.x; i < mp; i += blockDim.x) {
+    const int t = threadIdx.x;
+    u64 K[8];
+    unsigned V[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int i = 8 * t + e;
         if (i < m) {
             const int64_t g = base + i;
             const unsigned cx = quantize(q[3 * g], meta->lo[0], sc);
             const unsigned cy = quantize(q[3 * g + 1], meta->lo[1], sc);
             const unsigned cz = quantize(q[3 * g + 2], meta->lo[2], sc);
-            sk[i] = (spread3(cx) << 2) | (spread3(cy) << 1) | spread3(cz);
-            sv[i] = (unsigned)i;
+            K[e] = (spread3(cx) << 2) | (spread3(cy) << 1) | spread3(cz);
+            V[e] = (unsigned)i;
         } else {  // padding sorts last
-            sk[i] = ~0ull;
-            sv[i] = 0xffffffffu;
+            K[e] = ~0ull;
+            V[e] = 0xffffffffu;
         }
     }
-    for (int k = 2; k <= mp; k <<= 1)
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            __syncthreads();
-            for (int i = threadIdx.x; i < mp; i += blockDim.x) {
-                const int l = i ^ j;
-                if (l > i) {
-                    const u64 a = sk[i], b = sk[l];
-                    const unsigned va = sv[i], vb = sv[l];
-                    const bool gt = a > b || (a == b && va > vb);
-                    if (gt == ((i & k) == 0)) {  // ascending where bit k of i is clear
-                        sk[i] = b;
-                        sk[l] = a;
-                        sv[i] = vb;
-                        sv[l] = va;
-                    }
+#pragma unroll
+    for (int lk = 1; lk <= 11; ++lk) {
+        const int k = 1 << lk;
+#pragma unroll
+        for (int lj = lk - 1; lj >= 0; --lj) {
+            const int j = 1 << lj;
+            if (j < 8) {  // both positions in this thread
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    if (e & j) continue;
+                    const int e2 = e | j;
+                    const bool asc = ((8 * t + e) & k) == 0;
+                    const bool sw = take_partner(K[e], V[e], K[e2], V[e2], true, asc);
+                    const u64 ka = K[e], kb = K[e2];
+                    const unsigned va = V[e], vb = V[e2];
+                    K[e] = sw ? kb : ka;
+                    K[e2] = sw ? ka : kb;
+                    V[e] = sw ? vb : va;
+                    V[e2] = sw ? va : vb;
+                }
+            } else if (j < 512) {  // partner lane in the same wave
+                const int lx = j >> 3;
+                const bool lower = (t & lx) == 0;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const u64 b = __shfl_xor(K[e], lx, 64);
+                    const unsigned vb = __shfl_xor(V[e], lx, 64);
+                    const bool asc = ((8 * t + e) & k) == 0;
+                    const bool sw = take_partner(K[e], V[e], b, vb, lower, asc);
+                    K[e] = sw ? b : K[e];
+                    V[e] = sw ? vb : V[e];
+                }
+            } else {  // partner in another wave
+                __syncthreads();
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    sk[8 * t + e] = K[e];
+                    sv[8 * t + e] = V[e];
+                }
+                __syncthreads();
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int i = 8 * t + e, l = i ^ j;
+                    const u64 b = sk[l];
+                    const unsigned vb = sv[l];
+                    const bool sw = take_partner(K[e], V[e], b, vb, i < l, (i & k) == 0);
+                    K[e] = sw ? b : K[e];
+                    V[e] = sw ? vb : V[e];
                 }
             }
         }
-    __syncthreads();
-    for (int i = threadIdx.x; i < m; i += blockDim.x) {
-        kout[base + i] = sk[i];
-        vout[base + i] = (unsigned)(base + sv[i]);
     }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int i = 8 * t + e;
+        if (i < m) {
+            kout[base + i] = K[e];
+            vout[base + i] = (unsigned)(base + V[e]);
+        }
+    }
+}
+
+// Merge of the sorted tiles of one set: the final position of a pair is its
+// rank in its own tile plus, in every other tile, the number of pairs that
+// order before it (binary search by key, then index).
+__global__ __launch_bounds__(256) void k_merge_rank(const u64 *__restrict__ tk,
+                                                    const unsigned *__restrict__ tv, int64_t n,
+                                                    int tile, u64 *__restrict__ kout,
+                                                    unsigned *__restrict__ vout) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const u64 key = tk[t];
+    const unsigned idx = tv[t];
+    const int64_t mine = t / tile;
+    int64_t rank = t - mine * tile;
+    const int64_t tiles = (n + tile - 1) / tile;
+    for (int64_t u = 0; u < tiles; ++u) {
+        if (u == mine) continue;
+        const int64_t lo = u * tile;
+        int64_t a = lo, b = lo + tile < n ? lo + tile : n;
+        while (a < b) {
+            const int64_t mid = (a + b) >> 1;
+            const u64 km = tk[mid];
+            if (km < key || (km == key && tv[mid] < idx))
+                a = mid + 1;
+            else
+                b = mid;
+        }
+        rank += a - lo;
+    }
+    kout[rank] = key;
+    vout[rank] = idx;
 }
 
 // Statistics of contiguous ranges of sorted points.  A two-level summary
@@ -1071,7 +1165,10 @@ void carve_forest(Arena &a, int64_t n, int nsub, int64_t groups, int64_t max_set
     t.sort_tiles = (int)((m + 256 * t.sort_per - 1) / (256 * t.sort_per));
     t.sort_sbs = (t.sort_tiles + kSbTiles - 1) / kSbTiles;
     t.sort_passes = kKeyPasses + (nsub > 1 ? (nsub > kOsBins ? 2 : 1) : 0);
-    t.block_sort = max_set <= kBlockSortMax ? 1 : 0;
+    // 1: one block per set; 2: one set sorted in tiles and merged; 0: radix passes
+    t.block_sort = max_set <= kBlockSortMax                                   ? 1
+                   : nsub == 1 && n <= (int64_t)kMergeTiles * kBlockSortMax ? 2
+                                                                            : 0;
     t.meta = a.take<TreeMeta>(nsub);
     t.totals = a.take<TreeTotals>(1);
     t.bbox_part = a.take<float>(6 * (size_t)t.bbox_blocks * nsub);
@@ -1122,10 +1219,19 @@ gs_status build_tree(const float *q, const float *p, int64_t n, int leaf_cap, Tr
                        t.bbox_part, t.sb, sbn);
     hipLaunchKernelGGL(k_bbox_final, dim3(nsub), dim3(64), 0, s, t.bbox_part, t.bbox_blocks,
                        t.meta, status);
-    if (t.block_sort) {
-        hipLaunchKernelGGL(k_block_sort, dim3(nsub), dim3(1024), 0, s, q, t.seg, t.meta, n,
+    if (t.block_sort == 1) {
+        hipLaunchKernelGGL(k_block_sort, dim3(nsub), dim3(256), 0, s, q, t.seg, t.meta, n, 0,
                            t.keyA, t.valA);
         GS_LAUNCH_CHECK("block sort");
+        return build_from_sorted(q, p, n, leaf_cap, t, s);
+    }
+    if (t.block_sort == 2) {
+        const int tiles = (int)((n + kBlockSortMax - 1) / kBlockSortMax);
+        hipLaunchKernelGGL(k_block_sort, dim3(tiles), dim3(256), 0, s, q, t.seg, t.meta, n,
+                           kBlockSortMax, t.keyB, t.valB);
+        hipLaunchKernelGGL(k_merge_rank, dim3(nblk(n)), dim3(256), 0, s, t.keyB, t.valB, n,
+                           kBlockSortMax, t.keyA, t.valA);
+        GS_LAUNCH_CHECK("tile sort and merge");
         return build_from_sorted(q, p, n, leaf_cap, t, s);
     }
     const unsigned tiles = (unsigned)t.sort_tiles;
