@@ -438,39 +438,34 @@ __global__ __launch_bounds__(256) void k_os_scatter(
 }
 
 // Sets of at most kBlockSortMax points: one block per set computes the keys
-// of its points and sorts (key, index within the set) pairs with a bitonic
-// network.  The pairs are distinct, so the order is that of the
+// of its points and sorts them in LDS (k_block_radix), in the order of the
 // stable radix sort (key, then index): identical results in one launch
 // instead of 15 to 17.  With tile > 0 (one set of n points) block b sorts the
 // tile [b tile, (b + 1) tile) instead, for k_merge_rank.
 constexpr int kBlockSortMax = 2048;
 constexpr int kMergeTiles = 16;  // one set of at most 16 x 2048 points: tiles + merge
 
-// (no short-circuit operators: the comparisons stay branch-free)
-__device__ __forceinline__ bool kv_less(u64 ka, unsigned va, u64 kb, unsigned vb) {
-    return (ka < kb) | ((ka == kb) & (va < vb));
-}
-// One compare-exchange of a bitonic stage seen from one element: (a, va) at
-// position i, its partner (b, vb) at i ^ j; the lower position keeps the
-// smaller pair where bit k of i is clear (ascending runs), the larger where
-// it is set.  Returns whether the partner's pair is taken.
-__device__ __forceinline__ bool take_partner(u64 a, unsigned va, u64 b, unsigned vb, bool lower,
-                                             bool asc) {
-    const bool bl = kv_less(b, vb, a, va);
-    const bool al = !bl & ((a != b) | (va != vb));  // a before b (the pairs differ or are equal)
-    return (lower == asc) ? bl : al;
+// Orders this wave's LDS writes before its following LDS reads.
+__device__ inline void wave_lds_order() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// 256 threads, 8 consecutive positions per thread (2048 in all, padded with
-// the largest pair): exchanges between positions of one thread in
-// registers, within a wave by lane shuffles, across waves through LDS.
-__global__ __launch_bounds__(256) void k_block_sort(const float *__restrict__ q,
-                                                    const long long *__restrict__ seg,
-                                                    const TreeMeta *__restrict__ meta_all,
-                                                    int64_t n, int tile, u64 *__restrict__ kout,
-                                                    unsigned *__restrict__ vout) {
-    __shared__ u64 sk[kBlockSortMax];
-    __shared__ unsigned sv[kBlockSortMax];
+// LSD radix sort of one set or tile in LDS (7 passes of 9-bit digits, stable):
+// position p = 512 w + 64 r + l is held by lane l of wave w in round r.  In a
+// pass every wave ranks its 8 rounds by digit with ballots and its own
+// running digit counts (no block barrier), then the digit totals and the
+// counts of earlier waves give each key its place.
+__global__ __launch_bounds__(256) void k_block_radix(const float *__restrict__ q,
+                                                     const long long *__restrict__ seg,
+                                                     const TreeMeta *__restrict__ meta_all,
+                                                     int64_t n, int tile, u64 *__restrict__ kout,
+                                                     unsigned *__restrict__ vout) {
+    __shared__ u64 bk[kBlockSortMax];
+    __shared__ unsigned bv[kBlockSortMax];
+    __shared__ unsigned wrun[4][kOsBins];  // per wave: keys of each digit so far
+    __shared__ unsigned wsum[4];
     const int set = tile > 0 ? 0 : blockIdx.x;
     const int64_t base = tile > 0 ? (int64_t)blockIdx.x * tile : (seg ? seg[set] : 0);
     const int64_t end = tile > 0 ? (base + tile < n ? base + tile : n) : (seg ? seg[set + 1] : n);
@@ -478,82 +473,98 @@ __global__ __launch_bounds__(256) void k_block_sort(const float *__restrict__ q,
     if (m <= 0) return;  // block-uniform
     const TreeMeta *meta = meta_all + set;
     const double sc = meta->scale;
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const u64 lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     u64 K[8];
     unsigned V[8];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        const int i = 8 * t + e;
+    for (int r = 0; r < 8; ++r) {
+        const int i = 512 * wv + 64 * r + lane;
         if (i < m) {
             const int64_t g = base + i;
             const unsigned cx = quantize(q[3 * g], meta->lo[0], sc);
             const unsigned cy = quantize(q[3 * g + 1], meta->lo[1], sc);
             const unsigned cz = quantize(q[3 * g + 2], meta->lo[2], sc);
-            K[e] = (spread3(cx) << 2) | (spread3(cy) << 1) | spread3(cz);
-            V[e] = (unsigned)i;
-        } else {  // padding sorts last
-            K[e] = ~0ull;
-            V[e] = 0xffffffffu;
+            K[r] = (spread3(cx) << 2) | (spread3(cy) << 1) | spread3(cz);
+            V[r] = (unsigned)i;
+        } else {  // padding: the largest digit in every pass, after every key
+            K[r] = ~0ull;
+            V[r] = 0xffffffffu;
         }
     }
+    for (int pass = 0; pass < kKeyPasses; ++pass) {
+        const int sh = kOsBits * pass;
+        for (int d = t; d < 4 * kOsBins; d += 256) (&wrun[0][0])[d] = 0;
+        __syncthreads();
+        unsigned dig[8], rk[8];
 #pragma unroll
-    for (int lk = 1; lk <= 11; ++lk) {
-        const int k = 1 << lk;
+        for (int r = 0; r < 8; ++r) {
+            const unsigned d = (unsigned)(K[r] >> sh) & (kOsBins - 1);
+            dig[r] = d;
+            u64 peers = ~0ull;
 #pragma unroll
-        for (int lj = lk - 1; lj >= 0; --lj) {
-            const int j = 1 << lj;
-            if (j < 8) {  // both positions in this thread
-#pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    if (e & j) continue;
-                    const int e2 = e | j;
-                    const bool asc = ((8 * t + e) & k) == 0;
-                    const bool sw = take_partner(K[e], V[e], K[e2], V[e2], true, asc);
-                    const u64 ka = K[e], kb = K[e2];
-                    const unsigned va = V[e], vb = V[e2];
-                    K[e] = sw ? kb : ka;
-                    K[e2] = sw ? ka : kb;
-                    V[e] = sw ? vb : va;
-                    V[e2] = sw ? va : vb;
-                }
-            } else if (j < 512) {  // partner lane in the same wave
-                const int lx = j >> 3;
-                const bool lower = (t & lx) == 0;
-#pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const u64 b = __shfl_xor(K[e], lx, 64);
-                    const unsigned vb = __shfl_xor(V[e], lx, 64);
-                    const bool asc = ((8 * t + e) & k) == 0;
-                    const bool sw = take_partner(K[e], V[e], b, vb, lower, asc);
-                    K[e] = sw ? b : K[e];
-                    V[e] = sw ? vb : V[e];
-                }
-            } else {  // partner in another wave
-                __syncthreads();
-#pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    sk[8 * t + e] = K[e];
-                    sv[8 * t + e] = V[e];
-                }
-                __syncthreads();
-#pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const int i = 8 * t + e, l = i ^ j;
-                    const u64 b = sk[l];
-                    const unsigned vb = sv[l];
-                    const bool sw = take_partner(K[e], V[e], b, vb, i < l, (i & k) == 0);
-                    K[e] = sw ? b : K[e];
-                    V[e] = sw ? vb : V[e];
-                }
+            for (int b = 0; b < kOsBits; ++b) {
+                const u64 mb = __ballot((d >> b) & 1u);
+                peers &= ((d >> b) & 1u) ? mb : ~mb;
             }
+            const unsigned lr = __popcll(peers & lt);
+            rk[r] = wrun[wv][d] + lr;  // keys of this digit before this one in the wave
+            wave_lds_order();
+            if (lr == 0) wrun[wv][d] += __popcll(peers);
+            wave_lds_order();
+        }
+        __syncthreads();
+        // digits 2t, 2t + 1: totals over the waves, exclusive scan over the
+        // digits, and the counts of the waves before each wave
+        unsigned tot[2], pw[4][2];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            unsigned acc = 0;
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                pw[w][c] = acc;
+                acc += wrun[w][2 * t + c];
+            }
+            tot[c] = acc;
+        }
+        const unsigned s2 = tot[0] + tot[1];
+        unsigned incl = s2;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const unsigned u = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += u;
+        }
+        if (lane == 63) wsum[wv] = incl;
+        __syncthreads();
+        unsigned ex = incl - s2;
+        for (int w = 0; w < wv; ++w) ex += wsum[w];
+        // the place of digit d's first key of wave w: into wrun (read back below)
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            wrun[w][2 * t] = ex + pw[w][0];
+            wrun[w][2 * t + 1] = ex + tot[0] + pw[w][1];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const unsigned pos = wrun[wv][dig[r]] + rk[r];
+            bk[pos] = K[r];
+            bv[pos] = V[r];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int i = 512 * wv + 64 * r + lane;
+            K[r] = bk[i];
+            V[r] = bv[i];
         }
     }
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        const int i = 8 * t + e;
+    for (int r = 0; r < 8; ++r) {
+        const int i = 512 * wv + 64 * r + lane;
         if (i < m) {
-            kout[base + i] = K[e];
-            vout[base + i] = (unsigned)(base + V[e]);
+            kout[base + i] = K[r];
+            vout[base + i] = (unsigned)(base + V[r]);
         }
     }
 }
@@ -1220,14 +1231,14 @@ gs_status build_tree(const float *q, const float *p, int64_t n, int leaf_cap, Tr
     hipLaunchKernelGGL(k_bbox_final, dim3(nsub), dim3(64), 0, s, t.bbox_part, t.bbox_blocks,
                        t.meta, status);
     if (t.block_sort == 1) {
-        hipLaunchKernelGGL(k_block_sort, dim3(nsub), dim3(256), 0, s, q, t.seg, t.meta, n, 0,
+        hipLaunchKernelGGL(k_block_radix, dim3(nsub), dim3(256), 0, s, q, t.seg, t.meta, n, 0,
                            t.keyA, t.valA);
         GS_LAUNCH_CHECK("block sort");
         return build_from_sorted(q, p, n, leaf_cap, t, s);
     }
     if (t.block_sort == 2) {
         const int tiles = (int)((n + kBlockSortMax - 1) / kBlockSortMax);
-        hipLaunchKernelGGL(k_block_sort, dim3(tiles), dim3(256), 0, s, q, t.seg, t.meta, n,
+        hipLaunchKernelGGL(k_block_radix, dim3(tiles), dim3(256), 0, s, q, t.seg, t.meta, n,
                            kBlockSortMax, t.keyB, t.valB);
         hipLaunchKernelGGL(k_merge_rank, dim3(nblk(n)), dim3(256), 0, s, t.keyB, t.valB, n,
                            kBlockSortMax, t.keyA, t.valA);
