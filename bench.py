@@ -39,7 +39,7 @@ GOLDEN = os.path.join(ROOT, "tests", "golden")
 # rocprofv3 FETCH_SIZE and WRITE_SIZE runs (each scaled by what the counter
 # reads for an elementwise kernel of known traffic: x2.0 fetch, x1.0 write).
 # Valid only for the kernel source they were taken on (sha256 prefix).
-EXACT_TRAFFIC_BYTES = 134578215
+EXACT_TRAFFIC_BYTES = 134578710
 EXACT_TRAFFIC_SOURCE = "a510236523545181"
 EXACT_SOURCE = os.path.join(ROOT, "paper_1907_04834_amd", "csrc", "exact.hip")
 
