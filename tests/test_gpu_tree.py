@@ -9,8 +9,11 @@ single-child cells holds one point set and is stored once), obtained from the
 brute-force Morton cells, which test_oracle_pins.py pins to the oracle's tree;
 children partition their parent; leaves hold at most leaf_cap points (or
 points sharing one level-21 cell); and each node's statistics equal the
-oracle's dump of the same cell: tight box exactly, centre to 1e-15 relative
-to the extent, momentum sum to FP32 rounding.
+oracle's dump of the same cell: tight box exactly, centre within the FP64
+summation bound of its point count, momentum sum to FP32 rounding.  Sizes
+cover each sort the build selects (one block per set up to 2048 points,
+tiles and merge up to 32768, radix passes above), with ties between
+coincident points.
 """
 import numpy as np
 import pytest
@@ -52,6 +55,16 @@ def _cases():
         np.float32)
     w = W.ellipsoid_20k(n=2000)
     yield "ellipsoid20k-2000+100", (w.q0.astype(np.float64) + 100.0).astype(np.float32), w.p0
+    # larger sets: sorted in tiles and merged (up to 32768 points; ties between
+    # coincident points broken by index across tiles), then by the radix passes
+    c = np.repeat(rng.random((150, 3)), 40, axis=0)[rng.permutation(6000)]
+    yield "clusters-6000", c.astype(np.float32), (0.01 * rng.standard_normal(c.shape)).astype(
+        np.float32)
+    for n in (20000, 40000):
+        q = W.ellipsoid_surface(rng, n, (1.0, 0.6, 0.4), 0.01)
+        q[:20] = q[20]
+        yield f"ellipsoid-{n}", q.astype(np.float32), (0.02 * rng.standard_normal(q.shape)).astype(
+            np.float32)
 
 
 @pytest.mark.parametrize("leaf_cap", [1, 3, 8])
@@ -64,6 +77,11 @@ def test_tree_matches_definition(oracle, leaf_cap):
         perm = t["perm"].astype(np.int64)
         assert np.array_equal(np.sort(perm), np.arange(n)), name
         assert (np.diff(t["keys"].astype(np.uint64)) >= 0).all() if n > 1 else True
+        # equal keys (points of one level-21 cell) in index order, as a stable
+        # sort leaves them, whichever sort the size selects
+        ks = t["keys"].astype(np.uint64)
+        tie = ks[1:] == ks[:-1]
+        assert (perm[1:][tie] > perm[:-1][tie]).all(), name
         ic = oracle.int_coords(q64).astype(np.int64)
         assert np.array_equal(_deinterleave(t["keys"]), ic[perm]), name
         # node point sets = the distinct point sets of the oracle's tree
@@ -97,8 +115,11 @@ def test_tree_matches_definition(oracle, leaf_cap):
                 assert cnt <= leaf_cap or same, (name, cnt)
             np.testing.assert_array_equal(t["lo"][k], dump["lo"][i])
             np.testing.assert_array_equal(t["hi"][k], dump["hi"][i])
-            assert np.abs(t["C"][k] - dump["C"][i]).max() <= 1e-15 * max(extent, 1.0) + \
-                1e-15 * np.abs(dump["C"][i]).max()
+            # both centres are FP64 means of the same cnt exact values, summed in
+            # different orders: each within cnt * u of the true mean (recursive
+            # summation bound, u = 2^-53) relative to the coordinates' magnitude
+            mag = max(extent, 1.0) + np.abs(dump["C"][i]).max()
+            assert np.abs(t["C"][k] - dump["C"][i]).max() <= max(1e-15, 2 * cnt * 2.0**-53) * mag
             pn = np.abs(p64[list(mem)]).sum(0)
             assert (np.abs(t["P"][k] - dump["P"][i]) <= 1e-6 * pn + 1e-30).all()
             side = (dump["hi"][i] - dump["lo"][i]).max()
