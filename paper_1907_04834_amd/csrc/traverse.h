@@ -36,7 +36,10 @@ typedef unsigned long long u64;
 // launch is full anyway and splitting only adds partial sums to write and
 // read back.
 constexpr int kBlockStack = 192;  // entries of (first child, count, lane mask, ownership)
-constexpr int kSub = 8;           // phase-1 waves per group, at most
+#ifndef GS_KSUB
+#define GS_KSUB 8
+#endif
+constexpr int kSub = GS_KSUB;     // phase-1 waves per group, at most
 constexpr int kListPerGroup = 4096;  // list entries of a group, shared out among its phase-1 waves
 #ifndef GS_MAX_CHUNKS
 #define GS_MAX_CHUNKS 16
