@@ -126,165 +126,169 @@ __device__ __forceinline__ void leaf_adjoint_staged(
     }
 }
 
-struct AdjDecideLds {
-    DecideLds d;
-    double adj[8][6];  // A_k, B_k of the sibling block being decided
+// One wave's decisions of its group's nodes (backward stage); the records of
+// a block are staged with the per-node sums A_k, B_k of alpha and beta.
+struct AdjVisit {
+    const BhNode *__restrict__ nodes;
+    const double *__restrict__ adj;
+    const float4 *__restrict__ Qc;
+    const float4 *__restrict__ Ps;
+    const float4 *__restrict__ As;
+    const float4 *__restrict__ Bs;
+    BhNode *rec;      // LDS: the staged block
+    double (*radj)[6];  // LDS: its A_k, B_k
+    LeafEntry *mylist;
+    BhParams bp;
+    float4 xp, xa, xb;
+    double xd, yd, zd;
+    int64_t t;
+    bool active;
+    int lane, segcap, nlist;
+    double GQ[3], GP[3];
+    u64 c_pairs, c_mono;  // wave totals (scalars)
+
+    __device__ __forceinline__ void load(int first, int count, int l) {
+        if (l < kNodeF4 * count)
+            reinterpret_cast<float4 *>(rec)[l] = reinterpret_cast<const float4 *>(nodes + first)[l];
+        if (l < 3 * count)
+            reinterpret_cast<float4 *>(&radj[0][0])[l] =
+                reinterpret_cast<const float4 *>(adj + 6 * (int64_t)first)[l];
+    }
+    __device__ __forceinline__ u64 visit(int k, u64 m, int &nfirst, int &nchild) {
+        const bool mine = (m >> lane) & 1ull;
+        const BhNode nd = rec[k];
+        const int nn = __builtin_amdgcn_readfirstlane(nd.n);
+        u64 approx = 0ull;
+        if (nn >= 2) {  // a single point is never approximated
+            double d[3];
+            const bool ap = decide_far(nd, xd, yd, zd, bp, d) && mine;
+            approx = __ballot(ap);
+            if (ap) {
+                // n_k virtual points: (C, P / n, A / n, B / n)
+                const float inv_s2 = bp.inv_s2f;
+                const float Ax = (float)radj[k][0], Ay = (float)radj[k][1], Az = (float)radj[k][2];
+                const float inv_n = 1.f / (float)nn;
+                const float mbx = (float)radj[k][3] * inv_n, mby = (float)radj[k][4] * inv_n,
+                            mbz = (float)radj[k][5] * inv_n;
+                const float dx = (float)d[0], dy = (float)d[1], dz = (float)d[2];
+                const float g = __builtin_amdgcn_exp2f((dx * dx + dy * dy + dz * dz) * bp.negc);
+                const float s = xp.x * nd.px + xp.y * nd.py + xp.z * nd.pz;
+                const float cross = nd.px * xa.x + nd.py * xa.y + nd.pz * xa.z + xp.x * Ax +
+                                    xp.y * Ay + xp.z * Az;
+                const float dbx = xb.x - mbx, dby = xb.y - mby, dbz = xb.z - mbz;
+                const float ddb = dx * dbx + dy * dby + dz * dbz;
+                const float w1 = g * (-cross - s * ddb * inv_s2);
+                const float w2 = g * s;
+                const float w3 = g * ddb * inv_s2;
+                GQ[0] += (double)(w1 * dx + w2 * dbx);
+                GQ[1] += (double)(w1 * dy + w2 * dby);
+                GQ[2] += (double)(w1 * dz + w2 * dbz);
+                GP[0] += (double)(g * Ax + w3 * nd.px);
+                GP[1] += (double)(g * Ay + w3 * nd.py);
+                GP[2] += (double)(g * Az + w3 * nd.pz);
+            }
+        }
+        c_mono += (u64)__popcll(approx);
+        const u64 open = m & ~approx;
+        if (open == 0ull) return 0ull;
+        nfirst = __builtin_amdgcn_readfirstlane(nd.first);
+        nchild = __builtin_amdgcn_readfirstlane(nd.nchild);
+        if (nchild > 0) return open;
+        c_pairs += (u64)__popcll(open) * (u64)nn;
+        if (nlist < segcap) {
+            if (lane == 0) {
+                LeafEntry e;
+                e.mask = open;
+                e.first = nfirst;
+                e.count = nn;
+                mylist[nlist] = e;
+            }
+            ++nlist;
+        } else {  // segment full: sum this leaf here
+            const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+            const float4 xc = active ? Qc[t] : z4;
+            leaf_adjoint(Qc, Ps, As, Bs, nfirst, nn, (open >> lane) & 1ull, xc, xp, xa, xb,
+                         bp.negc, bp.inv_s2f, GQ, GP);
+        }
+        return 0ull;
+    }
 };
+constexpr size_t kAdjRec = 8 * sizeof(BhNode) + 8 * 6 * sizeof(double);
 
-// Loads the node records and adjoint sums of the block of `count` nodes
-// from `first` into the wave's LDS.
-__device__ inline void load_block(const BhNode *__restrict__ nodes,
-                                  const double *__restrict__ adj, int first, int count, int lane,
-                                  AdjDecideLds &L) {
-    if (lane < kNodeF4 * count)
-        reinterpret_cast<float4 *>(L.d.node)[lane] =
-            reinterpret_cast<const float4 *>(nodes + first)[lane];
-    if (lane < 3 * count)
-        reinterpret_cast<float4 *>(&L.adj[0][0])[lane] =
-            reinterpret_cast<const float4 *>(adj + 6 * (int64_t)first)[lane];
-}
-
-// Phase 1 of the backward products (the work split of the forward
+// Phase 1 of the backward products (the work split and walk of the forward
 // traversal): the decisions, the approximated nodes' contributions and the
-// list of leaves to sum exactly.
-__global__ __launch_bounds__(256) void k_adj_decide(
+// list of leaves to sum exactly.  Workgroups as k_bh_decide; dynamic LDS of
+// walk_lds_bytes(nsub, kAdjRec).
+// 6 waves per SIMD (80 VGPRs): with 5 / 7 / 8 the 50k gradient's backward
+// decide phase measured 143 / 177 / 322 us against 138 us.
+#ifndef GS_ADJ_DECIDE_WAVES
+#define GS_ADJ_DECIDE_WAVES 6
+#endif
+__global__ __launch_bounds__(512)
+__attribute__((amdgpu_waves_per_eu(GS_ADJ_DECIDE_WAVES, GS_ADJ_DECIDE_WAVES))) void k_adj_decide(
     const BhNode *__restrict__ nodes, const double *__restrict__ adj,
     const float4 *__restrict__ Qs, const float4 *__restrict__ Qc,
     const float4 *__restrict__ Ps, const float4 *__restrict__ As,
     const float4 *__restrict__ Bs, int64_t n, const GroupDesc *__restrict__ gtab, int64_t groups,
     TravSplit split, BhParams bp, LeafEntry *__restrict__ list, int *__restrict__ list_n,
     double *__restrict__ part, u64 *__restrict__ counters, int *__restrict__ status) {
-    __shared__ AdjDecideLds lds_all[4];
+    extern __shared__ __align__(16) char walk_lds[];
     const int lane = threadIdx.x & 63, wv = wave_in_block();
-    AdjDecideLds &L = lds_all[wv];
-    const int64_t wave = (int64_t)blockIdx.x * 4 + wv;
-    const int64_t grp = wave / split.nsub;
-    const int sub = (int)(wave % split.nsub);
-    if (grp >= groups) return;  // wave-uniform; this kernel has no block barrier
+    const int nsub = split.nsub;
+    const bool coop = nsub > 1;
+    const int64_t grp = coop ? (int64_t)blockIdx.x : (int64_t)blockIdx.x * 4 + wv;
+    const int sub = coop ? wv : 0;
+    if (grp >= groups) return;  // only when !coop (a whole group per workgroup otherwise)
+    char *wbase = walk_lds + (size_t)wv * (sizeof(WalkStack) + kAdjRec);
+    char *fbase = walk_lds + (size_t)walk_waves(nsub) * (sizeof(WalkStack) + kAdjRec) +
+                  (size_t)(coop ? 0 : wv) * walk_front_bytes(nsub);
+    WalkStack &S = *reinterpret_cast<WalkStack *>(wbase);
+    FrontEntry *fe = reinterpret_cast<FrontEntry *>(fbase);
+    int *fcnt = reinterpret_cast<int *>(fbase + (size_t)2 * nsub * kSegF * sizeof(FrontEntry));
+    int *fnod = fcnt + 2 * kSub;
+
     const int64_t npad = groups * 64;
     const GroupDesc gd = group_desc(gtab, grp, n);
-    const int64_t t = (int64_t)gd.first + lane;
-    const bool active = lane < gd.count;
+    AdjVisit vis;
+    vis.nodes = nodes;
+    vis.adj = adj;
+    vis.Qc = Qc;
+    vis.Ps = Ps;
+    vis.As = As;
+    vis.Bs = Bs;
+    vis.rec = reinterpret_cast<BhNode *>(wbase + sizeof(WalkStack));
+    vis.radj = reinterpret_cast<double(*)[6]>(wbase + sizeof(WalkStack) + 8 * sizeof(BhNode));
+    vis.mylist = list + grp * kListPerGroup + (int64_t)sub * split.segcap;
+    vis.bp = bp;
+    vis.t = (int64_t)gd.first + lane;
+    vis.active = lane < gd.count;
     const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
-    const float4 xs = active ? Qs[t] : z4, xp = active ? Ps[t] : z4;
-    const float4 xa = active ? As[t] : z4, xb = active ? Bs[t] : z4;
-    const double xd = xs.x, yd = xs.y, zd = xs.z;
-    const float inv_s2 = bp.inv_s2f;
-    LeafEntry *mylist = list + grp * kListPerGroup + (int64_t)sub * split.segcap;
-    double GQ[3] = {0, 0, 0}, GP[3] = {0, 0, 0};
-    u64 c_pairs = 0, c_mono = 0;  // wave totals (scalars)
-    int nlist = 0;
+    const float4 xs = vis.active ? Qs[vis.t] : z4;
+    vis.xp = vis.active ? Ps[vis.t] : z4;
+    vis.xa = vis.active ? As[vis.t] : z4;
+    vis.xb = vis.active ? Bs[vis.t] : z4;
+    vis.xd = xs.x;
+    vis.yd = xs.y;
+    vis.zd = xs.z;
+    vis.lane = lane;
+    vis.segcap = split.segcap;
+    vis.nlist = 0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) vis.GQ[c] = vis.GP[c] = 0.0;
+    vis.c_pairs = vis.c_mono = 0;
 
-    // the start block: the root's children (decided by every wave, their
-    // grandchildren dealt out by node index), or the root when it is a leaf
+    // the first block: the root's children, or the root itself when it is a leaf
     const int rchild = __builtin_amdgcn_readfirstlane(nodes[gd.root].nchild);
     const int rfirst = __builtin_amdgcn_readfirstlane(nodes[gd.root].first);
-    const int start = rchild == 0 ? (sub == 0 ? gd.root : -1) : rfirst;
-    const int start_n = rchild == 0 ? 1 : rchild;
-    int sp = 0;
-    const u64 live = __ballot(active);
-    if (live != 0ull && start >= 0) {
-        L.d.first[0] = start;
-        L.d.count[0] = start_n;
-        L.d.mask[0] = live;
-        L.d.own[0] = rchild == 0 ? kOwnAll : 0;
-        sp = 1;
-        load_block(nodes, adj, start, start_n, lane, L);
-    }
-    wave_sync();
-    while (sp > 0) {
-        --sp;
-        const int bc = __builtin_amdgcn_readfirstlane(L.d.count[sp]);
-        const int bfirst = __builtin_amdgcn_readfirstlane(L.d.first[sp]);
-        const int own = __builtin_amdgcn_readfirstlane(L.d.own[sp]);
-        const u64 m = uniform_u64(L.d.mask[sp]);
-        const bool mine = (m >> lane) & 1ull;
-        const bool rec = own < 0 || sub == 0;  // this wave records the block's results
-        const int child_own = child_ownership(own);
-        for (int k = 0; k < bc; ++k) {
-            if (own == kOwnDealt && (bfirst + k) % split.nsub != sub) continue;  // another wave's
-            const BhNode nd = L.d.node[k];
-            const int nn = __builtin_amdgcn_readfirstlane(nd.n);
-            u64 approx = 0ull;
-            if (nn >= 2) {  // a single point is never approximated
-                double d[3];
-                const bool ap = decide_far(nd, xd, yd, zd, bp, d) && mine;
-                approx = __ballot(ap);
-                if (rec && ap) {
-                    // n_k virtual points: (C, P / n, A / n, B / n)
-                    const float Ax = (float)L.adj[k][0], Ay = (float)L.adj[k][1],
-                                Az = (float)L.adj[k][2];
-                    const float inv_n = 1.f / (float)nn;
-                    const float mbx = (float)L.adj[k][3] * inv_n, mby = (float)L.adj[k][4] * inv_n,
-                                mbz = (float)L.adj[k][5] * inv_n;
-                    const float dx = (float)d[0], dy = (float)d[1], dz = (float)d[2];
-                    const float g =
-                        __builtin_amdgcn_exp2f((dx * dx + dy * dy + dz * dz) * bp.negc);
-                    const float s = xp.x * nd.px + xp.y * nd.py + xp.z * nd.pz;
-                    const float cross = nd.px * xa.x + nd.py * xa.y + nd.pz * xa.z + xp.x * Ax +
-                                        xp.y * Ay + xp.z * Az;
-                    const float dbx = xb.x - mbx, dby = xb.y - mby, dbz = xb.z - mbz;
-                    const float ddb = dx * dbx + dy * dby + dz * dbz;
-                    const float w1 = g * (-cross - s * ddb * inv_s2);
-                    const float w2 = g * s;
-                    const float w3 = g * ddb * inv_s2;
-                    GQ[0] += (double)(w1 * dx + w2 * dbx);
-                    GQ[1] += (double)(w1 * dy + w2 * dby);
-                    GQ[2] += (double)(w1 * dz + w2 * dbz);
-                    GP[0] += (double)(g * Ax + w3 * nd.px);
-                    GP[1] += (double)(g * Ay + w3 * nd.py);
-                    GP[2] += (double)(g * Az + w3 * nd.pz);
-                }
-            }
-            const u64 open = m & ~approx;
-            if (rec) c_mono += (u64)__popcll(approx);
-            if (open == 0ull) continue;
-            const int nfirst = __builtin_amdgcn_readfirstlane(nd.first);
-            const int nchild = __builtin_amdgcn_readfirstlane(nd.nchild);
-            if (nchild == 0) {
-                if (!rec) continue;
-                c_pairs += (u64)__popcll(open) * (u64)nn;
-                if (nlist < split.segcap) {
-                    if (lane == 0) {
-                        LeafEntry e;
-                        e.mask = open;
-                        e.first = nfirst;
-                        e.count = nn;
-                        mylist[nlist] = e;
-                    }
-                    ++nlist;
-                } else {  // segment full: sum this leaf here
-                    const float4 xc = active ? Qc[t] : z4;
-                    leaf_adjoint(Qc, Ps, As, Bs, nfirst, nn, (open >> lane) & 1ull, xc, xp, xa,
-                                 xb, bp.negc, inv_s2, GQ, GP);
-                }
-            } else {
-                if (sp >= kBlockStack) {
-                    // cannot happen for trees of at most 22 levels; stop safely
-                    if (lane == 0 && status) *status = kStatusOverflow;
-                    sp = -1;
-                    break;
-                }
-                L.d.first[sp] = nfirst;
-                L.d.count[sp] = nchild;
-                L.d.mask[sp] = open;
-                L.d.own[sp] = child_own;
-                ++sp;
-            }
-        }
-        if (sp < 0) break;
-        wave_sync();
-        if (sp > 0)
-            load_block(nodes, adj, __builtin_amdgcn_readfirstlane(L.d.first[sp - 1]),
-                       __builtin_amdgcn_readfirstlane(L.d.count[sp - 1]), lane, L);
-        wave_sync();
-    }
-    write_part(part, sub, npad, grp * 64 + lane, GQ, GP);
-    if (lane == 0) list_n[grp * kSub + sub] = nlist;
-    if (lane == 0 && counters && (c_pairs != 0 || c_mono != 0)) {
+    const u64 live = __ballot(vis.active);
+    decide_walk(vis, S, fe, fcnt, fnod, nsub, sub, coop, rchild == 0 ? gd.root : rfirst,
+                rchild == 0 ? 1 : rchild, live, lane, status);
+    write_part(part, sub, npad, grp * 64 + lane, vis.GQ, vis.GP);
+    if (lane == 0) list_n[grp * kSub + sub] = vis.nlist;
+    if (lane == 0 && counters && (vis.c_pairs != 0 || vis.c_mono != 0)) {
         u64 *c = counter_slot(counters, blockIdx.x);
-        if (c_pairs) atomicAdd(&c[0], c_pairs);
-        if (c_mono) atomicAdd(&c[1], c_mono);
+        if (vis.c_pairs) atomicAdd(&c[0], vis.c_pairs);
+        if (vis.c_mono) atomicAdd(&c[1], vis.c_mono);
     }
 }
 
@@ -471,8 +475,11 @@ gs_status bh_adjoint_step(AdjointBufs &b, const gs_params &prm, double dt, const
     LeafEntry *list = reinterpret_cast<LeafEntry *>(t.list);
     const TravSplit split = traverse_split(t.groups);
     timing_begin(KIND_ADJOINT, s);
-    hipLaunchKernelGGL(k_adj_decide, dim3((unsigned)((t.groups * split.nsub + 3) / 4)), dim3(256), 0,
-                       s, t.nodes, t.adj, t.Qs, t.Qc, t.Ps, b.bhadj.ALs, b.bhadj.BEs, n, t.gtab,
+    hipLaunchKernelGGL(k_adj_decide,
+                       dim3((unsigned)((t.groups + walk_groups(split.nsub) - 1) /
+                                       walk_groups(split.nsub))),
+                       dim3((unsigned)(64 * walk_waves(split.nsub))),
+                       walk_lds_bytes(split.nsub, kAdjRec), s, t.nodes, t.adj, t.Qs, t.Qc, t.Ps, b.bhadj.ALs, b.bhadj.BEs, n, t.gtab,
                        t.groups, split, bp, list, t.list_n, t.part, counters, status);
     hipLaunchKernelGGL(k_adj_leaves, dim3((unsigned)t.groups, (split.maxc + 3) / 4), dim3(256), 0, s,
                        t.Qc, t.Ps, b.bhadj.ALs, b.bhadj.BEs, n, t.gtab, t.groups, split, bp.negc,

@@ -13,17 +13,9 @@ typedef unsigned long long u64;
 // ---------------------------------------------------------------- layout
 // Work split.  A group is 64 consecutive targets of the Morton order (one
 // wave's lanes).  Phase 1 walks the tree for a group with up to kSub waves
-// (the root contains every target of its tree, so it is never approximated
-// and every target opens it).  Every wave decides the root's children; the
-// children of those (the nodes two levels below the root) are dealt out by
-// node index, node i to wave i % nsub, and each wave takes every decision
-// below its nodes, adds the monopoles, and records each leaf that some lane
-// must sum exactly as an entry (leaf, lane mask) of its own list segment.
-// Dealing out by index mixes the group's dense near field with far nodes in
-// every wave; an earlier split, each wave taking a contiguous share of the
-// root's children, left most of a group's work to the wave holding the
-// group's own region (at 200k points, theta 0.5, leaf_cap 64: 1143 node
-// decisions in the busiest wave against 195 on average).
+// (decide_walk below: every node is decided by one of them), which add the
+// monopoles and record each leaf that some lane must sum exactly as an entry
+// (leaf, lane mask) of the deciding wave's own list segment.
 // Phase 2 splits the group's entries, taken segment by segment, into at
 // most kMaxChunks chunks of at least kMinChunk entries and adds their exact
 // pairs with one wave per chunk, so the near-field work of a dense group is
@@ -35,7 +27,6 @@ typedef unsigned long long u64;
 // groups (TravSplit, chosen on the host): when there are many groups the
 // launch is full anyway and splitting only adds partial sums to write and
 // read back.
-constexpr int kBlockStack = 192;  // entries of (first child, count, lane mask, ownership)
 #ifndef GS_KSUB
 #define GS_KSUB 8
 #endif
@@ -66,25 +57,6 @@ struct LeafEntry {
     int count;
 };
 
-// Ownership of a block of sibling nodes among the phase-1 waves of a group.
-// A block at depth d >= 0 below the root (the root's children are depth 0)
-// with d < kDealDepth is decided by every wave, and wave 0 records its
-// monopoles, leaves and visits; the blocks at depth kDealDepth are dealt out,
-// node i to wave i % nsub; below those, a wave takes every node of its own
-// subtrees.
-#ifndef GS_DEAL_DEPTH
-#define GS_DEAL_DEPTH 1
-#endif
-constexpr int kDealDepth = GS_DEAL_DEPTH;
-static_assert(kDealDepth >= 1, "the root's children are decided by every wave");
-constexpr int kOwnAll = -2;    // this wave's own subtree: it takes every node
-constexpr int kOwnDealt = -1;  // node i belongs to wave i % nsub
-// (own >= 0: a shared block at that depth)
-__device__ __forceinline__ int child_ownership(int own) {
-    if (own < 0) return kOwnAll;
-    return own + 1 < kDealDepth ? own + 1 : kOwnDealt;
-}
-
 // List entries needed by at most kSparseMax of the wave's targets, of at
 // most 64 points, are summed compacted (forward and backward leaf phases); the
 // others by every lane.  (A leaf can exceed leaf_cap only when its points share
@@ -96,14 +68,6 @@ constexpr int kSparseMax = GS_SPARSE_MAX;  // a tuning build may change it (at m
 __device__ inline bool sparse_entry(int count, u64 mask) {
     return __popcll(mask) <= kSparseMax && count <= 64;
 }
-
-struct DecideLds {
-    u64 mask[kBlockStack];
-    int first[kBlockStack];
-    int count[kBlockStack];
-    int own[kBlockStack];
-    BhNode node[8];  // the sibling block being decided
-};
 
 // Targets of group g: the table entry, or 64 consecutive points of one tree.
 __device__ inline GroupDesc group_desc(const GroupDesc *__restrict__ gtab, int64_t g, int64_t n) {
@@ -123,6 +87,186 @@ __device__ inline void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// ---------------------------------------------------------------- decide walk
+// Phase 1 (both stages): the nsub waves of a group (one workgroup when nsub > 1)
+// walk the tree level by level while the frontier is small.  The frontier is
+// the list of sibling blocks that some target of the group still has to
+// decide; its j-th node (counted over the blocks in order) belongs to wave
+// j mod nsub, which decides it and adds the child block of an opened internal
+// node to its own segment of the next level's frontier; the waves wait for
+// each other (workgroup barrier) between levels.  The first level with more
+// than kSegF nodes per wave ends the level walk: each wave decides its nodes
+// of that level and walks below each of them depth-first on its own stack.
+// Every node is decided by one wave, and which wave depends only on the tree
+// and the targets, so the results do not depend on scheduling.  The walk is
+// bound by the latency of each block's record load more than by the busiest
+// wave: on MI355X with kSegF = 4 / 8 / 16 / 32 / 64 the 200k ellipsoids took
+// 448 / 445 / 443 / 448 / 462 us and the 64-subject population 763 / 747 /
+// 752 / 762 / 794 us per forward decide phase, against 454 / 814 us when the
+// nodes two levels below the root were dealt out by index with the levels
+// above decided by every wave (busiest decide wave 790 vs 675 decisions).
+#ifndef GS_SEGF
+#define GS_SEGF 16
+#endif
+constexpr int kSegF = GS_SEGF;  // frontier blocks a wave adds per level, at most
+// Depth-first entries of a wave.  Below a frontier node (depth >= 1 of at most
+// 21) the stack holds at most 8 + 7 * 19 = 141 sibling blocks: the blocks of
+// one node's children, then 7 waiting siblings for each level further down.
+constexpr int kWalkStack = 160;
+
+struct FrontEntry {
+    u64 mask;   // targets that still decide the block
+    int first;  // first node of the block
+    int count;  // nodes in the block
+};
+struct WalkStack {
+    u64 mask[kWalkStack];
+    int first[kWalkStack];
+    int count[kWalkStack];
+};
+
+// Workgroup shape of a decide launch: nsub waves (one group) per workgroup,
+// or four groups of one wave each when nsub == 1.
+__host__ __device__ inline int walk_waves(int nsub) { return nsub > 1 ? nsub : 4; }
+__host__ __device__ inline int walk_groups(int nsub) { return nsub > 1 ? 1 : 4; }
+// LDS of one group's frontier: two levels of nsub segments of kSegF entries,
+// then the entry and node counts of each segment of both levels.
+__host__ __device__ inline size_t walk_front_bytes(int nsub) {
+    return (size_t)2 * nsub * kSegF * sizeof(FrontEntry) + (size_t)4 * kSub * sizeof(int);
+}
+// Dynamic LDS of a decide workgroup whose waves each hold a WalkStack and a
+// staging area of rec_bytes (a multiple of 16).
+__host__ __device__ inline size_t walk_lds_bytes(int nsub, size_t rec_bytes) {
+    return (size_t)walk_waves(nsub) * (sizeof(WalkStack) + rec_bytes) +
+           (size_t)walk_groups(nsub) * walk_front_bytes(nsub);
+}
+
+__device__ inline void walk_sync(bool coop) {
+    if (coop)
+        __syncthreads();
+    else
+        wave_sync();
+}
+
+// The walk of one group.  V provides
+//   void load(int first, int count, int lane): stage the records of a block;
+//   u64 visit(int k, u64 m, int &nfirst, int &nchild): decide node k of the
+//     staged block for the targets in m (approximations, leaf entries and
+//     counters are the visitor's), returning the targets that open it when
+//     it is internal (its children: nfirst, nchild), else 0.
+// All lanes of every wave of the group call it; coop: the group's waves
+// share the workgroup (nsub > 1).  fe / fcnt / fnod: the group's frontier
+// (walk_front_bytes).  Returns false when the stack overflowed (the walk of
+// that wave stops; status receives kStatusOverflow).
+template <class V>
+__device__ __forceinline__ bool decide_walk(V &v, WalkStack &S, FrontEntry *fe, int *fcnt,
+                                            int *fnod, int nsub, int sub, bool coop,
+                                            int start_first, int start_count, u64 live, int lane,
+                                            int *status) {
+    if (lane == 0) {
+        const bool has = sub == 0 && live != 0ull;
+        if (has) {
+            fe[0].mask = live;
+            fe[0].first = start_first;
+            fe[0].count = start_count;
+        }
+        fcnt[sub] = has ? 1 : 0;
+        fnod[sub] = has ? start_count : 0;
+    }
+    walk_sync(coop);
+    bool ok = true;
+    int cur = 0;
+    for (;;) {
+        const FrontEntry *F = fe + cur * nsub * kSegF;
+        int N = 0;
+        for (int s = 0; s < nsub; ++s) N += __builtin_amdgcn_readfirstlane(fnod[cur * kSub + s]);
+        if (N == 0) break;
+        // wave- and group-uniform: this level's child blocks go to the next
+        // frontier (each wave decides at most ceil(N / nsub) <= kSegF nodes),
+        // else each wave walks below each of its nodes depth-first
+        const bool level = (N + nsub - 1) / nsub <= kSegF;
+        const int nxt = cur ^ 1;
+        FrontEntry *out = fe + nxt * nsub * kSegF + sub * kSegF;
+        int e = 0, enodes = 0, jm = 0;
+        for (int s = 0; s < nsub && ok; ++s) {
+            const int nb = __builtin_amdgcn_readfirstlane(fcnt[cur * kSub + s]);
+            for (int b = 0; b < nb && ok; ++b) {
+                const FrontEntry &f = F[s * kSegF + b];
+                const int bfirst = __builtin_amdgcn_readfirstlane(f.first);
+                const int bcount = __builtin_amdgcn_readfirstlane(f.count);
+                const u64 m = uniform_u64(f.mask);
+                // this wave's first node of the block (jm = index of the
+                // block's first node in the level, mod nsub)
+                int k = sub >= jm ? sub - jm : sub - jm + nsub;
+                jm += bcount;
+                while (jm >= nsub) jm -= nsub;
+                if (k >= bcount) continue;
+                v.load(bfirst, bcount, lane);
+                wave_sync();
+                int sp = 0;
+                for (; k < bcount; k += nsub) {
+                    int nf = 0, nc = 0;
+                    const u64 open = v.visit(k, m, nf, nc);
+                    if (open == 0ull) continue;
+                    if (level) {
+                        if (lane == 0) {
+                            out[e].mask = open;
+                            out[e].first = nf;
+                            out[e].count = nc;
+                        }
+                        ++e;
+                        enodes += nc;
+                    } else {  // at most 8 entries: no overflow
+                        if (lane == 0) {
+                            S.mask[sp] = open;
+                            S.first[sp] = nf;
+                            S.count[sp] = nc;
+                        }
+                        ++sp;
+                    }
+                }
+                // depth-first below this wave's nodes of the block
+                while (sp > 0) {
+                    wave_sync();
+                    --sp;
+                    const int cf = __builtin_amdgcn_readfirstlane(S.first[sp]);
+                    const int cc = __builtin_amdgcn_readfirstlane(S.count[sp]);
+                    const u64 cm = uniform_u64(S.mask[sp]);
+                    wave_sync();
+                    v.load(cf, cc, lane);
+                    wave_sync();
+                    for (int q = 0; q < cc; ++q) {
+                        int nf = 0, nc = 0;
+                        const u64 open = v.visit(q, cm, nf, nc);
+                        if (open == 0ull) continue;
+                        if (sp >= kWalkStack) {  // cannot happen for trees of at most 22 levels
+                            if (lane == 0 && status) *status = kStatusOverflow;
+                            ok = false;
+                            break;
+                        }
+                        if (lane == 0) {
+                            S.mask[sp] = open;
+                            S.first[sp] = nf;
+                            S.count[sp] = nc;
+                        }
+                        ++sp;
+                    }
+                    if (!ok) break;
+                }
+                wave_sync();
+            }
+        }
+        if (!level || !ok) break;  // no barrier follows for any wave
+        if (lane == 0) {
+            fcnt[nxt * kSub + sub] = e;
+            fnod[nxt * kSub + sub] = enodes;
+        }
+        walk_sync(coop);
+        cur = nxt;
+    }
+    return ok;
 }
 
 // A target's (v, a) sums in a forward-traversal wave: FP32 with Kahan

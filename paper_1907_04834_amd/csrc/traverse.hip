@@ -364,162 +364,158 @@ __device__ __forceinline__ void leaf_sparse(const float4 *__restrict__ Qs,
     }
 }
 
-// Phase 1: decisions, monopoles and the group's list of leaves.  Every lane
-// evaluates the decision of every node the wave reaches (the VALU issues for
-// the whole wave either way); the ballot restricted to the block's mask gives
-// the lanes that approximate it, and the wave's counters are kept as scalars
-// from the masks.
+// Phase 1: decisions, monopoles and the group's list of leaves (the walk of
+// decide_walk).  Every lane evaluates the decision of every node the wave
+// takes (the VALU issues for the whole wave either way); the ballot
+// restricted to the block's mask gives the lanes that approximate it, and the
+// wave's counters are kept as scalars from the masks.
 template <bool WITH_A>
-__global__ __launch_bounds__(256) GS_TRAVERSE_ATTR void k_bh_decide(
+struct FwdVisit {
+    const BhNode *__restrict__ nodes;
+    const float4 *__restrict__ Qc;
+    const float4 *__restrict__ Ps;
+    BhNode *rec;  // LDS: the staged block
+    LeafEntry *mylist;
+    BhParams bp;
+    float4 xp;
+    double xd, yd, zd;
+    int64_t t;
+    bool active;
+    int lane, segcap, nlist;
+    TAcc K;
+    float mv[3], ma[3];
+    u64 c_pairs, c_mono, c_visit;  // wave totals (scalars)
+    unsigned w_steps, w_nodes;
+
+    __device__ __forceinline__ void load(int first, int count, int l) {
+        if (l < kNodeF4 * count)
+            reinterpret_cast<float4 *>(rec)[l] = reinterpret_cast<const float4 *>(nodes + first)[l];
+    }
+    __device__ __forceinline__ u64 visit(int k, u64 m, int &nfirst, int &nchild) {
+        const bool mine = (m >> lane) & 1ull;
+        ++w_nodes;
+        c_visit += (u64)__popcll(m);
+        const BhNode nd = rec[k];
+        const int nn = __builtin_amdgcn_readfirstlane(nd.n);
+        u64 approx = 0ull;
+        if (nn >= 2) {  // a single point is never approximated
+            double d[3];
+            const bool ap = decide_far(nd, xd, yd, zd, bp, d) && mine;
+            approx = __ballot(ap);
+            if (ap) {
+                // n_k virtual points at C_k, momentum P_k / n_k each
+                const float dx = (float)d[0], dy = (float)d[1], dz = (float)d[2];
+                const float g = __builtin_amdgcn_exp2f((dx * dx + dy * dy + dz * dz) * bp.negc);
+                mv[0] += g * nd.px;
+                mv[1] += g * nd.py;
+                mv[2] += g * nd.pz;
+                if (WITH_A) {
+                    const float w = g * (xp.x * nd.px + xp.y * nd.py + xp.z * nd.pz);
+                    ma[0] += w * dx;
+                    ma[1] += w * dy;
+                    ma[2] += w * dz;
+                }
+            }
+        }
+        c_mono += (u64)__popcll(approx);
+        const u64 open = m & ~approx;
+        if (open == 0ull) return 0ull;
+        nfirst = __builtin_amdgcn_readfirstlane(nd.first);
+        nchild = __builtin_amdgcn_readfirstlane(nd.nchild);
+        if (nchild > 0) return open;
+        c_pairs += (u64)__popcll(open) * (u64)nn;
+        if (nlist < segcap) {
+            if (lane == 0) {
+                LeafEntry e;
+                e.mask = open;
+                e.first = nfirst;
+                e.count = nn;
+                mylist[nlist] = e;
+            }
+            ++nlist;
+        } else {
+            // list full: sum this leaf here
+            w_steps += (unsigned)nn;
+            const float4 xc = active ? Qc[t] : make_float4(0.f, 0.f, 0.f, 0.f);
+            float tv[3], ta[3];
+            leaf_direct<WITH_A>(Qc, Ps, nfirst, nn, (open >> lane) & 1ull, xc, xp, bp.negc, tv,
+                                ta);
+            tacc_add<WITH_A>(K, tv, ta);
+        }
+        return 0ull;
+    }
+};
+
+// Workgroups: one group of nsub waves, or (nsub == 1) four groups of one
+// wave; dynamic LDS of walk_lds_bytes(nsub, 8 records).
+template <bool WITH_A>
+__global__ __launch_bounds__(512) GS_TRAVERSE_ATTR void k_bh_decide(
     const BhNode *__restrict__ nodes, const float4 *__restrict__ Qs,
     const float4 *__restrict__ Qc, const float4 *__restrict__ Ps, int64_t n, const GroupDesc *__restrict__ gtab, int64_t groups, TravSplit split, BhParams bp,
     LeafEntry *__restrict__ list, int *__restrict__ list_n, float2 *__restrict__ part,
     u64 *__restrict__ counters, const TreeTotals *__restrict__ totals, int *__restrict__ status) {
-    __shared__ DecideLds lds_all[4];
+    extern __shared__ __align__(16) char walk_lds[];
     const int lane = threadIdx.x & 63, wv = wave_in_block();
-    DecideLds &L = lds_all[wv];
-    const int64_t wave = (int64_t)blockIdx.x * 4 + wv;
-    const int64_t grp = wave / split.nsub;
-    const int sub = (int)(wave % split.nsub);
-    if (grp >= groups) return;  // wave-uniform; this kernel has no block barrier
+    const int nsub = split.nsub;
+    const bool coop = nsub > 1;
+    const int64_t grp = coop ? (int64_t)blockIdx.x : (int64_t)blockIdx.x * 4 + wv;
+    const int sub = coop ? wv : 0;
+    if (grp >= groups) return;  // only when !coop (a whole group per workgroup otherwise)
+    constexpr size_t kRec = 8 * sizeof(BhNode);
+    char *wbase = walk_lds + (size_t)wv * (sizeof(WalkStack) + kRec);
+    char *fbase = walk_lds + (size_t)walk_waves(nsub) * (sizeof(WalkStack) + kRec) +
+                  (size_t)(coop ? 0 : wv) * walk_front_bytes(nsub);
+    WalkStack &S = *reinterpret_cast<WalkStack *>(wbase);
+    FrontEntry *fe = reinterpret_cast<FrontEntry *>(fbase);
+    int *fcnt = reinterpret_cast<int *>(fbase + (size_t)2 * nsub * kSegF * sizeof(FrontEntry));
+    int *fnod = fcnt + 2 * kSub;
+
     const int64_t npad = groups * 64;
     const GroupDesc gd = group_desc(gtab, grp, n);
-    const int64_t t = (int64_t)gd.first + lane;
-    const bool active = lane < gd.count;
-    const float4 xa = active ? Qs[t] : make_float4(0.f, 0.f, 0.f, 0.f);
-    const float4 xp = active ? Ps[t] : make_float4(0.f, 0.f, 0.f, 0.f);
-    const double xd = xa.x, yd = xa.y, zd = xa.z;
-    LeafEntry *mylist = list + grp * kListPerGroup + (int64_t)sub * split.segcap;
+    FwdVisit<WITH_A> vis;
+    vis.nodes = nodes;
+    vis.Qc = Qc;
+    vis.Ps = Ps;
+    vis.rec = reinterpret_cast<BhNode *>(wbase + sizeof(WalkStack));
+    vis.mylist = list + grp * kListPerGroup + (int64_t)sub * split.segcap;
+    vis.bp = bp;
+    vis.t = (int64_t)gd.first + lane;
+    vis.active = lane < gd.count;
+    const float4 xa = vis.active ? Qs[vis.t] : make_float4(0.f, 0.f, 0.f, 0.f);
+    vis.xp = vis.active ? Ps[vis.t] : make_float4(0.f, 0.f, 0.f, 0.f);
+    vis.xd = xa.x;
+    vis.yd = xa.y;
+    vis.zd = xa.z;
+    vis.lane = lane;
+    vis.segcap = split.segcap;
+    vis.nlist = 0;
+    tacc_zero(vis.K);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) vis.mv[c] = vis.ma[c] = 0.f;
+    vis.c_pairs = vis.c_mono = vis.c_visit = 0;
+    vis.w_steps = vis.w_nodes = 0;
 
-    TAcc K;
-    tacc_zero(K);
-    float mv[3] = {0.f, 0.f, 0.f}, ma[3] = {0.f, 0.f, 0.f};
-    u64 c_pairs = 0, c_mono = 0, c_visit = 0;  // wave totals (scalars)
-    unsigned w_steps = 0, w_nodes = 0;
-    int nlist = 0;
-
-    // the start block: the root's children (decided by every wave), or the
-    // root itself when it is a leaf (wave 0 only)
+    // the first block: the root's children, or the root itself when it is a leaf
     const int rchild = __builtin_amdgcn_readfirstlane(nodes[gd.root].nchild);
     const int rfirst = __builtin_amdgcn_readfirstlane(nodes[gd.root].first);
-    const int start = rchild == 0 ? (sub == 0 ? gd.root : -1) : rfirst;
-    const int start_n = rchild == 0 ? 1 : rchild;
-    const u64 live = __ballot(active);
+    const u64 live = __ballot(vis.active);
     if (rchild > 0 && sub == 0) {  // the root's visit, counted once
-        c_visit += (u64)__popcll(live);
-        ++w_nodes;
+        vis.c_visit += (u64)__popcll(live);
+        ++vis.w_nodes;
     }
-    int sp = 0;
-    if (live != 0ull && start >= 0) {
-        L.first[0] = start;
-        L.count[0] = start_n;
-        L.mask[0] = live;
-        L.own[0] = rchild == 0 ? kOwnAll : 0;
-        sp = 1;
-        float4 *dstn = reinterpret_cast<float4 *>(L.node);
-        if (lane < kNodeF4 * start_n)
-            dstn[lane] = reinterpret_cast<const float4 *>(nodes + start)[lane];
-    }
-    wave_sync();
-    while (sp > 0) {
-        --sp;
-        const int bc = __builtin_amdgcn_readfirstlane(L.count[sp]);
-        const int bfirst = __builtin_amdgcn_readfirstlane(L.first[sp]);
-        const int own = __builtin_amdgcn_readfirstlane(L.own[sp]);
-        const u64 m = uniform_u64(L.mask[sp]);
-        const bool mine = (m >> lane) & 1ull;
-        const bool rec = own < 0 || sub == 0;  // this wave records the block's results
-        const int child_own = child_ownership(own);
-        for (int k = 0; k < bc; ++k) {
-            if (own == kOwnDealt && (bfirst + k) % split.nsub != sub) continue;  // another wave's
-            ++w_nodes;
-            const BhNode nd = L.node[k];
-            const int nn = __builtin_amdgcn_readfirstlane(nd.n);
-            u64 approx = 0ull;
-            if (nn >= 2) {  // a single point is never approximated
-                double d[3];
-                const bool ap = decide_far(nd, xd, yd, zd, bp, d) && mine;
-                approx = __ballot(ap);
-                if (rec && ap) {
-                    // n_k virtual points at C_k, momentum P_k / n_k each
-                    const float dx = (float)d[0], dy = (float)d[1], dz = (float)d[2];
-                    const float g =
-                        __builtin_amdgcn_exp2f((dx * dx + dy * dy + dz * dz) * bp.negc);
-                    mv[0] += g * nd.px;
-                    mv[1] += g * nd.py;
-                    mv[2] += g * nd.pz;
-                    if (WITH_A) {
-                        const float w = g * (xp.x * nd.px + xp.y * nd.py + xp.z * nd.pz);
-                        ma[0] += w * dx;
-                        ma[1] += w * dy;
-                        ma[2] += w * dz;
-                    }
-                }
-            }
-            const u64 open = m & ~approx;
-            if (rec) {
-                c_visit += (u64)__popcll(m);
-                c_mono += (u64)__popcll(approx);
-            }
-            if (open == 0ull) continue;
-            const int nfirst = __builtin_amdgcn_readfirstlane(nd.first);
-            const int nchild = __builtin_amdgcn_readfirstlane(nd.nchild);
-            if (nchild == 0) {
-                if (!rec) continue;
-                c_pairs += (u64)__popcll(open) * (u64)nn;
-                if (nlist < split.segcap) {
-                    if (lane == 0) {
-                        LeafEntry e;
-                        e.mask = open;
-                        e.first = nfirst;
-                        e.count = nn;
-                        mylist[nlist] = e;
-                    }
-                    ++nlist;
-                } else {
-                    // list full: sum this leaf here
-                    w_steps += (unsigned)nn;
-                    const float4 xc = active ? Qc[t] : make_float4(0.f, 0.f, 0.f, 0.f);
-                    float tv[3], ta[3];
-                    leaf_direct<WITH_A>(Qc, Ps, nfirst, nn, (open >> lane) & 1ull, xc, xp,
-                                        bp.negc, tv, ta);
-                    tacc_add<WITH_A>(K, tv, ta);
-                }
-            } else {
-                if (sp >= kBlockStack) {
-                    // cannot happen for trees of at most 22 levels; stop safely
-                    if (lane == 0 && status) *status = kStatusOverflow;
-                    sp = -1;
-                    break;
-                }
-                L.first[sp] = nfirst;
-                L.count[sp] = nchild;
-                L.mask[sp] = open;
-                L.own[sp] = child_own;
-                ++sp;
-            }
-        }
-        if (sp < 0) break;
-        wave_sync();
-        // the next block's node records
-        if (sp > 0) {
-            const int nf = __builtin_amdgcn_readfirstlane(L.first[sp - 1]);
-            const int pre_n = kNodeF4 * __builtin_amdgcn_readfirstlane(L.count[sp - 1]);
-            if (lane < pre_n)
-                reinterpret_cast<float4 *>(L.node)[lane] =
-                    reinterpret_cast<const float4 *>(nodes + nf)[lane];
-        }
-        wave_sync();
-    }
-    tacc_add<true>(K, mv, ma);
-    write_part_ff(part, sub, npad, grp * 64 + lane, K);
-    if (lane == 0) list_n[grp * kSub + sub] = nlist;
+    decide_walk(vis, S, fe, fcnt, fnod, nsub, sub, coop, rchild == 0 ? gd.root : rfirst,
+                rchild == 0 ? 1 : rchild, live, lane, status);
+    tacc_add<true>(vis.K, vis.mv, vis.ma);
+    write_part_ff(part, sub, npad, grp * 64 + lane, vis.K);
+    if (lane == 0) list_n[grp * kSub + sub] = vis.nlist;
 
     // counters: one atomic per wave and counter (integer, order-free)
+    const u64 c_visit = vis.c_visit;
+    const unsigned w_nodes = vis.w_nodes, w_steps = vis.w_steps;
     if (lane == 0 && counters && (c_visit != 0 || w_nodes != 0)) {
         u64 *c = counter_slot(counters, blockIdx.x);
-        if (c_pairs) atomicAdd(&c[0], c_pairs);
-        if (c_mono) atomicAdd(&c[1], c_mono);
+        if (vis.c_pairs) atomicAdd(&c[0], vis.c_pairs);
+        if (vis.c_mono) atomicAdd(&c[1], vis.c_mono);
         atomicAdd(&c[2], c_visit);
         if (grp == 0 && sub == 0) atomicAdd(&c[3], (u64)totals->n_nodes);
         if (w_steps) atomicAdd(&c[4], (u64)w_steps);
@@ -751,12 +747,14 @@ gs_status launch_bh_traverse(const TreeBufs &t, const BhParams &bp, bool with_a,
     // holds the backward stage's FP64 partials, of the same size)
     float2 *part = reinterpret_cast<float2 *>(t.part);
     const ff inv_s2f = ff_from_double(bp.inv_s2), dtf = ff_from_double(o.dt);
-    const dim3 g1((unsigned)((groups * split.nsub + 3) / 4)), g2((unsigned)groups, (split.maxc + 3) / 4),
+    const dim3 g1((unsigned)((groups + walk_groups(split.nsub) - 1) / walk_groups(split.nsub))),
+        b1((unsigned)(64 * walk_waves(split.nsub))), g2((unsigned)groups, (split.maxc + 3) / 4),
         g3((unsigned)((groups + 3) / 4));
+    const size_t lds1 = walk_lds_bytes(split.nsub, 8 * sizeof(BhNode));
     timing_begin(kind, s);
 #define GS_PHASES(A)                                                                         \
     do {                                                                                     \
-        hipLaunchKernelGGL(k_bh_decide<A>, g1, dim3(256), 0, s, t.nodes, t.Qs, t.Qc, t.Ps,    \
+        hipLaunchKernelGGL(k_bh_decide<A>, g1, b1, lds1, s, t.nodes, t.Qs, t.Qc, t.Ps,        \
                            t.n, t.gtab, groups, split, bp, list, t.list_n, part, counters,     \
                            t.totals, status);                                               \
         hipLaunchKernelGGL(k_bh_leaves<A>, g2, dim3(256), 0, s, t.Qc, t.Ps, t.n, t.gtab,      \
