@@ -207,6 +207,13 @@ __device__ inline unsigned quantize(float x, float lo, double scale) {
     return (unsigned)f;
 }
 
+// Orders this wave's LDS writes before its following LDS reads.
+__device__ inline void wave_lds_order() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // ---------------------------------------------------------------- radix sort
 // Stable LSD radix sort of (key, original index) with 9-bit digits: 7 passes
 // over the 63-bit keys, then (forests) 1 or 2 passes over the set index of
@@ -309,26 +316,29 @@ __global__ __launch_bounds__(256) void k_os_hist(const u64 *__restrict__ keys,
 }
 
 // One pass's scatter.  sb_next (the other superblock buffer) is cleared for
-// the next pass's counts.
+// the next pass's counts.  Wave w holds tile positions [64 PER w, 64 PER (w +
+// 1)) and ranks them stably by digit with ballots and its own running counts
+// (no block barrier between rounds); the counts of the waves before it then
+// complete each key's place within the tile.
 template <int PER>
 __global__ __launch_bounds__(256) void k_os_scatter(
     const u64 *__restrict__ kin, const unsigned *__restrict__ vin, u64 *__restrict__ kout,
     unsigned *__restrict__ vout, int64_t n, int pass, const long long *__restrict__ seg,
     int nsub, const unsigned *__restrict__ hist, const unsigned *__restrict__ sb, int nsb,
     unsigned *__restrict__ sb_next) {
-    __shared__ unsigned dbase[kOsBins];  // output offset of each digit for this tile
-    __shared__ unsigned run[kOsBins];    // keys of each digit ranked so far
-    __shared__ unsigned wcnt[4][kOsBins];
+    __shared__ unsigned dbase[kOsBins];     // output offset of each digit for this tile
+    __shared__ unsigned wrun[4][kOsBins];   // per wave: keys of each digit ranked so far,
+                                            // then the counts of the waves before it
     __shared__ unsigned wsum[4];
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int tile = blockIdx.x, mysb = tile / kSbTiles;
     // this thread's keys first, so that their loads overlap the prefix reads
-    const int64_t base = (int64_t)tile * (256 * PER);
+    const int64_t base = (int64_t)tile * (256 * PER) + (int64_t)wv * (64 * PER) + lane;
     u64 key[PER];
     unsigned val[PER];
 #pragma unroll
     for (int r = 0; r < PER; ++r) {
-        const int64_t i = base + r * 256 + t;
+        const int64_t i = base + r * 64;
         key[r] = i < n ? kin[i] : 0ull;
         val[r] = i < n ? vin[i] : 0u;
     }
@@ -378,28 +388,25 @@ __global__ __launch_bounds__(256) void k_os_scatter(
         if (lane >= o) incl += u;
     }
     if (lane == 63) wsum[wv] = incl;
-    for (int d = t; d < kOsBins; d += 256) run[d] = 0;
-    for (int w = 0; w < 4; ++w)
-        for (int d = t; d < kOsBins; d += 256) wcnt[w][d] = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        wrun[w][2 * t] = 0;
+        wrun[w][2 * t + 1] = 0;
+    }
     __syncthreads();
     unsigned ex = incl - s2;
     for (int w = 0; w < wv; ++w) ex += wsum[w];
     dbase[2 * t] = ex + pre[0];
     dbase[2 * t + 1] = ex + tot[0] + pre[1];
-    __syncthreads();
-    // stable ranks within the tile: rounds in index order, lanes in order
+    // stable ranks within the wave's keys: rounds in index order, lanes in order
     const u64 lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     unsigned dig[PER], rank[PER];
 #pragma unroll
     for (int r = 0; r < PER; ++r) {
-        const unsigned d = base + r * 256 + t < n ? os_digit(pass, key[r], val[r], seg, nsub) : 0u;
-        dig[r] = d;
-    }
-#pragma unroll
-    for (int r = 0; r < PER; ++r) {
-        const int64_t i = base + r * 256 + t;
+        const int64_t i = base + r * 64;
         const bool valid = i < n;
-        const unsigned d = dig[r];
+        const unsigned d = valid ? os_digit(pass, key[r], val[r], seg, nsub) : 0u;
+        dig[r] = d;
         u64 peers = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < kOsBits; ++b) {
@@ -407,30 +414,31 @@ __global__ __launch_bounds__(256) void k_os_scatter(
             peers &= ((d >> b) & 1u) ? m : ~m;
         }
         const unsigned lr = __popcll(peers & lt);
-        if (valid && lr == 0) wcnt[wv][d] = __popcll(peers);
-        __syncthreads();
-        unsigned rk = 0;
-        if (valid) {
-            rk = run[d] + lr;
-            for (int w = 0; w < wv; ++w) rk += wcnt[w][d];
-        }
-        rank[r] = rk;
-        __syncthreads();
-        for (int d2 = t; d2 < kOsBins; d2 += 256) {
-            unsigned add = 0;
-            for (int w = 0; w < 4; ++w) {
-                add += wcnt[w][d2];
-                wcnt[w][d2] = 0;
-            }
-            run[d2] += add;
-        }
-        __syncthreads();
+        rank[r] = valid ? wrun[wv][d] + lr : 0u;
+        wave_lds_order();
+        if (valid && lr == 0) wrun[wv][d] += (unsigned)__popcll(peers);
+        wave_lds_order();
     }
+    __syncthreads();
+    // the counts of the waves before each wave, per digit
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int d = 2 * t + j;
+        unsigned acc = 0;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            const unsigned c = wrun[w][d];
+            wrun[w][d] = acc;
+            acc += c;
+        }
+    }
+    __syncthreads();
 #pragma unroll
     for (int r = 0; r < PER; ++r) {
-        const int64_t i = base + r * 256 + t;
+        const int64_t i = base + r * 64;
         if (i < n) {
-            const unsigned pos = dbase[dig[r]] + rank[r];
+            const unsigned d = dig[r];
+            const unsigned pos = dbase[d] + wrun[wv][d] + rank[r];
             kout[pos] = key[r];
             vout[pos] = val[r];
         }
@@ -444,13 +452,6 @@ __global__ __launch_bounds__(256) void k_os_scatter(
 // tile [b tile, (b + 1) tile) instead, for k_merge_rank.
 constexpr int kBlockSortMax = 2048;
 constexpr int kMergeTiles = 16;  // one set of at most 16 x 2048 points: tiles + merge
-
-// Orders this wave's LDS writes before its following LDS reads.
-__device__ inline void wave_lds_order() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // LSD radix sort of one set or tile in LDS (7 passes of 9-bit digits, stable):
 // position p = 512 w + 64 r + l is held by lane l of wave w in round r.  In a
