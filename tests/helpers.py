@@ -151,6 +151,23 @@ def _tree(q, leaf_cap):
     return nodes, kids, leaf
 
 
+def deepest_set(seed=11):
+    """Eight points at the corners of a cube of half-side 2^-k around one
+    centre for every k = 2..22 (all FP32-exact), plus two corners fixing the
+    box to [0, 1]^3: with leaf_cap 1 the octree reaches level 21, the
+    deepest the 21-bit coordinates allow.  Returns FP32 (q, p)."""
+    c = np.array([0.40625, 0.59375, 0.53125])
+    pts = [np.zeros(3), np.ones(3)]
+    for k in range(2, 23):
+        for cx in (-1.0, 1.0):
+            for cy in (-1.0, 1.0):
+                for cz in (-1.0, 1.0):
+                    pts.append(c + 2.0 ** -k * np.array([cx, cy, cz]))
+    q = np.array(pts, np.float32)
+    p = (0.1 * np.random.default_rng(seed).standard_normal(q.shape)).astype(np.float32)
+    return q, p
+
+
 def _adjoint_pairs(xq, xp, xa, xb, qj, pj, aj, bj, wj, sigma):
     """Backward-stage pair terms of targets (rows of xq..xb) against sources
     (rows of qj..bj, each standing for wj[j] identical points), summed over

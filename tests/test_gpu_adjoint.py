@@ -13,6 +13,7 @@ import numpy as np
 import pytest
 import torch
 
+import helpers as H
 from helpers import rel_l2
 from paper_1907_04834_amd import gs
 from paper_1907_04834_amd import workloads as W
@@ -112,6 +113,30 @@ def test_bh_adjoint(oracle):
              f"objective {abs(e - be) / abs(be):.3e}")
         assert rel_l2(g, bg) <= 1e-5
         assert abs(e - be) <= 1e-5 * abs(be)
+
+
+@pytest.mark.parametrize("theta", [0.5, np.inf])
+def test_bh_adjoint_deepest_tree(oracle, theta):
+    """One step from a set whose tree is 21 levels deep (leaf_cap 1): the
+    backward decide phase's level walk and depth-first stacks at their
+    deepest.  One step only: every decision is then taken on the FP32 input
+    itself (a later state would carry the FP32 rounding of the trajectory,
+    and on this set a one-ulp change of q0 moves the Barnes-Hut gradient of
+    three steps by 5e-3)."""
+    q, p = H.deepest_set()
+    y = q + 0.01 * np.sin(3.0 * q[:, [1, 2, 0]])
+    prm = gs.params(0.02, nt=1, theta=theta, leaf_cap=1)
+    e, g = gs.gs_shoot_adjoint(_t(q), _t(p), _t(y.astype(np.float32)), prm, gs.GS_BH, 0.01, 1)
+    torch.cuda.synchronize()
+    e, g = float(e), _np(g)
+    q64, p64, y64 = (x.astype(np.float64) for x in (q, p, y.astype(np.float32)))
+    be, bg = oracle.objective_grad(q64, p64, y64, 0.02, 1, 0.01, method="bh", theta=theta,
+                                   leaf_cap=1)
+    _, xg = oracle.objective_grad(q64, p64, y64, 0.02, 1, 0.01)
+    _say(f"  deepest tree theta={theta}: bh vs exact {rel_l2(bg, xg):.3e} "
+         f"gpu vs bh {rel_l2(g, bg):.3e}")
+    assert rel_l2(g, bg) <= 1e-5
+    assert abs(e - be) <= 1e-5 * abs(be)
 
 
 def test_bh_adjoint_long_leaf_lists(oracle):

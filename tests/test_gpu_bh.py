@@ -20,6 +20,7 @@ import numpy as np
 import pytest
 import torch
 
+import helpers as H
 from helpers import rel_l2
 from paper_1907_04834_amd import gs
 from paper_1907_04834_amd import workloads as W
@@ -119,6 +120,26 @@ def test_rhs_bh_degenerate_inputs(oracle):
             assert st == 0
             assert cnt["pairs"] == oc["pairs"] and cnt["monopoles"] == oc["monopoles"]
             assert _close(_np(dq), v) and _close(_np(dp), a)
+
+
+@pytest.mark.parametrize("theta", [0.0, 0.5, math.inf])
+@pytest.mark.parametrize("leaf_cap", [1, 3])
+def test_rhs_bh_deepest_tree(oracle, theta, leaf_cap):
+    """A 21-level tree: the decide phase's level walk and depth-first stacks
+    at their deepest, against the oracle."""
+    q, p = H.deepest_set()
+    if leaf_cap == 1:  # the input really is 21 levels deep
+        nodes = H.canonical_octree(H.int_coords_np(q), 1, H.LEVELS)
+        assert max(lv for lv, _ in nodes) == 21
+    _say(f"rhs_bh deepest tree theta={theta} leaf_cap={leaf_cap}")
+    dq, dp, cnt, st = _bh(q, p, 0.02, theta, leaf_cap)
+    v, a, oc = oracle.rhs_bh(q.astype(np.float64), p.astype(np.float64), 0.02, theta,
+                             leaf_cap=leaf_cap)
+    assert st == 0
+    # (visits are not compared: the GPU stores a chain of single-child cells,
+    # which all hold the same points, as one node)
+    assert cnt["pairs"] == oc["pairs"] and cnt["monopoles"] == oc["monopoles"]
+    assert _close(_np(dq), v) and _close(_np(dp), a)
 
 
 def test_rhs_bh_nonfinite_reports_status():

@@ -13,12 +13,13 @@ oracle's dump of the same cell: tight box exactly, centre within the FP64
 summation bound of its point count, momentum sum to FP32 rounding.  Sizes
 cover each sort the build selects (one block per set up to 2048 points,
 tiles and merge up to 32768, radix passes above), with ties between
-coincident points.
+coincident points, and a set whose tree reaches level 21.
 """
 import numpy as np
 import pytest
 import torch
 
+import helpers as H
 from helpers import canonical_octree
 from paper_1907_04834_amd import gs
 from paper_1907_04834_amd import workloads as W
@@ -60,6 +61,8 @@ def _cases():
     c = np.repeat(rng.random((150, 3)), 40, axis=0)[rng.permutation(6000)]
     yield "clusters-6000", c.astype(np.float32), (0.01 * rng.standard_normal(c.shape)).astype(
         np.float32)
+    # the deepest tree the 21-bit coordinates allow (level 21)
+    yield ("deepest-170",) + H.deepest_set()
     for n in (20000, 40000):
         q = W.ellipsoid_surface(rng, n, (1.0, 0.6, 0.4), 0.01)
         q[:20] = q[20]

@@ -11,7 +11,7 @@ import os
 import numpy as np
 import pytest
 
-from helpers import (adjoint_vjp_torch, bh_bruteforce, canonical_octree,
+from helpers import (adjoint_vjp_torch, bh_bruteforce, canonical_octree, deepest_set,
                      euler_objective_torch, kernel_matrix, morton_interleave, rel_l2,
                      rhs_autograd, rhs_numpy)
 from paper_1907_04834_amd import workloads as W
@@ -295,12 +295,15 @@ def test_bh_matches_bruteforce(oracle, theta, leaf_cap):
     tests/helpers.py) to rounding, with exactly the same counts of exact
     pairs, monopoles and node visits.  Two inputs: an ellipsoid surface, and
     coincident clusters whose members carry different p, alpha, beta (where
-    the node means are a real approximation)."""
+    the node means are a real approximation), and a set whose tree reaches
+    the deepest level (21) the 21-bit coordinates allow."""
     rng = np.random.default_rng(30 + leaf_cap)
     w = W.ellipsoid_20k(n=1200)
     sets = [(w.q0.astype(np.float64), w.p0.astype(np.float64), w.sigma)]
     qc, _ = _cluster_lattice(0.1, m=7, seed=31)
     sets.append((qc, 0.1 * rng.standard_normal(qc.shape), 0.1))
+    qd, pd = deepest_set()
+    sets.append((qd.astype(np.float64), pd.astype(np.float64), 0.02))
     for q, p, sigma in sets:
         al, be = 0.01 * rng.standard_normal(q.shape), 0.01 * rng.standard_normal(q.shape)
         ref = bh_bruteforce(q, p, sigma, theta, leaf_cap=leaf_cap, alpha=al, beta=be)
