@@ -695,13 +695,14 @@ size_t traverse_list_bytes(int64_t groups) {
 
 size_t traverse_count_ints(int64_t groups) { return (size_t)groups * kSub; }
 
-// Phase-1 waves aim at about kDecideWaves waves in all (8 per SIMD, the
-// phase's occupancy), phase-2 waves at kLeafWaves; sweeps on the 200k
+// Phase-1 waves aim at about kDecideWaves waves in all (1.5 per wave slot of
+// the chip at 8 per SIMD), phase-2 waves at kLeafWaves; sweeps on the 200k
 // ellipsoids and on the 64-subject population found these best (200k decide
-// phase with 2 / 3 / 4 waves per group: 520 / 454 / 530 us; other values are
-// compiled only by a tuning build).
+// phase with 3 / 4 / 6 / 8 waves per group: 444 / 400 / 433 / 446 us; the
+// population, at 1 wave per group, took 781 instead of 753 us with 2; other
+// values are compiled only by a tuning build).
 #ifndef GS_DECIDE_WAVES
-#define GS_DECIDE_WAVES 8192
+#define GS_DECIDE_WAVES 12288
 #endif
 #ifndef GS_LEAF_WAVES
 #define GS_LEAF_WAVES 65536
