@@ -557,15 +557,32 @@ inline unsigned nblocks(int64_t n, int b = kBlock) { return (unsigned)((n + b - 
 // ---------------------------------------------------------------- planning
 // Chunk length of a launch: about `items` work items of kItemRows targets
 // (kItemsDefault unless the caller chose), never below kMinWaveSources
-// sources per wave.  Small sets need short chunks to fill the GPU: one RHS of
+// sources per wave nor, for the default target, above kMaxChunk sources (4 MB
+// of packed rows, one XCD's L2: 400k / 500k points in 2 chunks of 200k / 250k
+// took 52.8 / 83.8 ms per RHS against 51.8 / 81.4 ms in 4).  A caller's
+// target is followed as given (the static-workspace entry lowers it until
+// the partial sums fit its array).  Small sets need short chunks to fill the GPU: one RHS of
 // 5000 / 20 000 points took 0.119 / 0.308 ms with chunks of at least 2048
 // sources, 0.025 / 0.152 ms with at least 256.
-static int64_t chunk_for(int64_t work_rows_x_sources, int64_t items) {
+constexpr int64_t kMaxChunk = 131072;
+
+static int64_t chunk_for(int64_t work_rows_x_sources, int64_t items, bool *at_min = nullptr) {
     const int64_t target = items > 0 ? items : kItemsDefault;
     int64_t chunk = round_up((work_rows_x_sources + kItemRows * target - 1) / (kItemRows * target),
                              kTile);
     const int64_t minc = (int64_t)kMinWaveSources * kItemSplit;
+    if (at_min) *at_min = chunk <= minc;
+    if (items <= 0 && chunk > kMaxChunk) chunk = kMaxChunk;
     return chunk < minc ? minc : chunk;
+}
+
+// XCDs sharing each of nch < kXcds chunks, and nch rounded up to a power of
+// two: chunk c's homes are c + pw r, r < rep (all XCDs busy for 1, 2, 4
+// chunks).
+static void chunk_homes(int nch, int &pw, int &rep) {
+    pw = 1;
+    while (pw < nch) pw *= 2;
+    rep = nch >= kXcds ? 1 : kXcds / pw;
 }
 
 ItemGeom item_geom(int64_t n, int64_t items) {
@@ -573,11 +590,23 @@ ItemGeom item_geom(int64_t n, int64_t items) {
     g.n = (int)n;
     g.ng = (int)((n + kItemRows - 1) / kItemRows);
     g.sp = (int)round_up(n > 0 ? n : 1, kTile);
-    const int64_t chunk = chunk_for((int64_t)g.ng * kItemRows * g.sp, items);
+    bool at_min = false;
+    const int64_t chunk = chunk_for((int64_t)g.ng * kItemRows * g.sp, items, &at_min);
     int nch = (int)((g.sp + chunk - 1) / chunk);
+    // fewer chunks than XCDs: a power of two of them, each shared by
+    // kXcds / nch XCDs (400k / 500k points: 51.6 / 80.9 ms per RHS against
+    // 101.8 / 159.6 ms with 4 chunks on 4 XCDs), unless the chunks are at
+    // their minimum length (small sets: more chunks mean more items)
+    if (nch < kXcds && !at_min) {
+        int p2 = 1;
+        while (p2 * 2 <= nch) p2 *= 2;
+        nch = items > 0 || (g.sp + p2 - 1) / p2 <= kMaxChunk ? p2 : 2 * p2;
+    }
     g.csz = (int)round_up((g.sp + nch - 1) / nch, kTile);
     g.nch = (g.sp + g.csz - 1) / g.csz;
-    g.qlen = ((g.nch + kXcds - 1) / kXcds) * g.ng;  // the queue of XCD 0 is the longest
+    chunk_homes(g.nch, g.pw, g.rep);
+    g.gpp = (g.ng + g.rep - 1) / g.rep;
+    g.qlen = g.rep > 1 ? g.gpp : ((g.nch + kXcds - 1) / kXcds) * g.ng;  // XCD 0's queue is the longest
     return g;
 }
 
@@ -592,7 +621,8 @@ RowGeom row_geom(int64_t n, int slots) {
 // [tbase_s, tbase_s + tn_s) of the target rows and [sbase_s, sbase_s + sn_s)
 // of the source rows).  Every source chunk gets a home XCD (the largest
 // chunks first, each to the least loaded XCD), so that an XCD streams only
-// its own chunks and they stay in its L2.  Workgroups are dealt to the 8
+// its own chunks and they stay in its L2; with fewer chunks than XCDs a
+// chunk's target groups are shared out among several homes.  Workgroups are dealt to the 8
 // XCDs in turn, so item i of the launch runs on XCD i % 8: the launch
 // interleaves the 8 queues, largest items first in each, and pads a short
 // queue with empty items (slot -1) to keep the interleave aligned.
@@ -627,10 +657,28 @@ static void plan_items(const std::vector<int64_t> &tn, const std::vector<int64_t
             chunks.push_back({(int)s, c, j0, j1, tr * (j1 - j0)});
         }
     }
-    std::vector<int> order(chunks.size());
+    // fewer chunks than XCDs: each chunk's target groups are split into
+    // pieces for several XCDs, so that every XCD has work
+    int pw = 1, rep = 1;
+    if (!chunks.empty()) chunk_homes((int)chunks.size(), pw, rep);
+    struct Piece {
+        int chunk;
+        int64_t g0, g1, work;
+    };
+    std::vector<Piece> pieces;
+    for (size_t k = 0; k < chunks.size(); ++k) {
+        const Chunk &ch = chunks[k];
+        const int64_t groups = (tn[ch.set] + kItemRows - 1) / kItemRows;
+        const int64_t per = (groups + rep - 1) / rep;
+        for (int64_t g0 = 0; g0 < groups; g0 += per) {
+            const int64_t g1 = std::min(groups, g0 + per);
+            pieces.push_back({(int)k, g0, g1, (g1 - g0) * kItemRows * (ch.j1 - ch.j0)});
+        }
+    }
+    std::vector<int> order(pieces.size());
     for (size_t k = 0; k < order.size(); ++k) order[k] = (int)k;
     std::stable_sort(order.begin(), order.end(),
-                     [&](int a, int b) { return chunks[a].work > chunks[b].work; });
+                     [&](int a, int b) { return pieces[a].work > pieces[b].work; });
     int64_t load[kXcds] = {};
     struct Item {
         int64_t cost;
@@ -641,10 +689,10 @@ static void plan_items(const std::vector<int64_t> &tn, const std::vector<int64_t
         int x = 0;
         for (int y = 1; y < kXcds; ++y)
             if (load[y] < load[x]) x = y;
-        const Chunk &ch = chunks[k];
-        load[x] += ch.work;
-        const int64_t groups = (tn[ch.set] + kItemRows - 1) / kItemRows;
-        for (int64_t g = 0; g < groups; ++g)
+        const Piece &pc = pieces[k];
+        const Chunk &ch = chunks[pc.chunk];
+        load[x] += pc.work;
+        for (int64_t g = pc.g0; g < pc.g1; ++g)
             queue[x].push_back({ch.j1 - ch.j0, make_int4((int)(tbase[ch.set] + kItemRows * g),
                                                          (int)ch.j0, (int)ch.j1, ch.c)});
     }

@@ -155,7 +155,10 @@ constexpr int kItemSplit = GS_ITEM_SPLIT;
 constexpr int kItemRows = 64 * kItemGroups;                  // target rows per item
 constexpr int kItemThreads = kItemRows * kItemSplit;
 constexpr int kMinWaveSources = 256;    // sources per wave of an item, at least
-constexpr int64_t kItemsDefault = 24576;  // work items per launch the chunk length aims at
+// Work items per launch the chunk length aims at.  At 200k points 12288
+// gives 4 chunks, each shared by 2 XCDs: 13.03 ms per RHS and half the
+// partial sums of 24576 (8 chunks, 13.10 ms).
+constexpr int64_t kItemsDefault = 12288;
 constexpr int kXcds = 8;                // MI355X: workgroups are dealt to 8 XCDs in turn
 static_assert(kItemThreads <= 1024, "work item too large");
 
@@ -168,6 +171,9 @@ struct ItemGeom {
     int csz;   // sources per chunk (multiple of kTile)
     int sp;    // sources padded to kTile
     int qlen;  // items in the queue of XCD 0 (the longest)
+    int rep;   // XCDs sharing each chunk (1 when nch >= kXcds, else kXcds / pw)
+    int pw;    // nch rounded up to a power of two (when rep > 1)
+    int gpp;   // target groups per XCD of a shared chunk
 };
 // Row blocks of 256 rows of one point set without tables.
 struct RowGeom {
@@ -178,10 +184,19 @@ struct RowGeom {
 // Work item b: (first target row, source rows [j0, j1), slot); slot -1 is a
 // padding item.  Source chunk c of a single set has home XCD c % 8 (equal
 // chunks, largest first, least-loaded XCD); XCD x's queue holds its chunks'
-// items chunk by chunk, and item b comes from the queue of XCD b % 8.
+// items chunk by chunk, and item b comes from the queue of XCD b % 8.  With
+// fewer chunks than XCDs, chunk c has the rep homes c + pw r, and home r
+// takes target groups [r gpp, (r + 1) gpp).
 __device__ inline int4 work_item(const int4 *__restrict__ items, const ItemGeom &g, int64_t b) {
     if (items) return items[b];
     const int x = (int)(b % kXcds), k = (int)(b / kXcds);
+    if (g.rep > 1) {
+        const int c = x % g.pw, grp = (x / g.pw) * g.gpp + k;
+        if (c >= g.nch || k >= g.gpp || grp >= g.ng) return make_int4(0, 0, 0, -1);
+        const int j0 = c * g.csz;
+        const int j1 = j0 + g.csz < g.sp ? j0 + g.csz : g.sp;
+        return make_int4(grp * kItemRows, j0, j1, c);
+    }
     if (x >= g.nch) return make_int4(0, 0, 0, -1);
     const int nq = (g.nch - x + kXcds - 1) / kXcds;
     if (k >= nq * g.ng) return make_int4(0, 0, 0, -1);
