@@ -38,10 +38,12 @@ GOLDEN = os.path.join(ROOT, "tests", "golden")
 # HBM bytes per launch of the exact work-item kernel at 200k points, from
 # rocprofv3 FETCH_SIZE and WRITE_SIZE runs (each scaled by what the counter
 # reads for an elementwise kernel of known traffic: x2.0 fetch, x1.0 write).
-# Valid only for the kernel source they were taken on (sha256 prefix).
+# Valid only for the kernel sources they were taken on (sha256 prefix of the
+# kernel file followed by the header that fixes the work-item geometry).
 EXACT_TRAFFIC_BYTES = 134578710
 EXACT_TRAFFIC_SOURCE = "a510236523545181"
-EXACT_SOURCE = os.path.join(ROOT, "paper_1907_04834_amd", "csrc", "exact.hip")
+EXACT_SOURCES = [os.path.join(ROOT, "paper_1907_04834_amd", "csrc", f)
+                 for f in ("exact.hip", "internal.h")]
 
 
 def _digest(*arrays):
@@ -51,11 +53,17 @@ def _digest(*arrays):
     return h.hexdigest()
 
 
+def exact_source_digest():
+    h = hashlib.sha256()
+    for path in EXACT_SOURCES:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
 def _traffic():
-    """The measured traffic while the kernel source is the measured one."""
-    with open(EXACT_SOURCE, "rb") as f:
-        h = hashlib.sha256(f.read()).hexdigest()[:16]
-    return EXACT_TRAFFIC_BYTES if h == EXACT_TRAFFIC_SOURCE else None
+    """The measured traffic while the kernel sources are the measured ones."""
+    return EXACT_TRAFFIC_BYTES if exact_source_digest() == EXACT_TRAFFIC_SOURCE else None
 
 
 def _rel(x, y):
