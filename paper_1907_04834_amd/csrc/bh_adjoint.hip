@@ -473,7 +473,7 @@ gs_status bh_adjoint_step(AdjointBufs &b, const gs_params &prm, double dt, const
     GS_TRY(tree_range_sums(b.bhadj.ALs, b.bhadj.BEs, t, t.adj, s));
     const BhParams bp = make_bh_params(prm);
     LeafEntry *list = reinterpret_cast<LeafEntry *>(t.list);
-    const TravSplit split = traverse_split(t.groups);
+    const TravSplit split = traverse_split(t.groups, n / (t.nsub > 0 ? t.nsub : 1));
     timing_begin(KIND_ADJOINT, s);
     hipLaunchKernelGGL(k_adj_decide,
                        dim3((unsigned)((t.groups + walk_groups(split.nsub) - 1) /

@@ -49,7 +49,7 @@ constexpr int kParts = kSub + kMaxChunks;
 struct TravSplit {
     int nsub, maxc, segcap;
 };
-TravSplit traverse_split(int64_t groups);
+TravSplit traverse_split(int64_t groups, int64_t set_points);
 
 struct LeafEntry {
     u64 mask;

@@ -711,10 +711,17 @@ constexpr int64_t kDecideWaves = GS_DECIDE_WAVES;
 constexpr int64_t kLeafWaves = GS_LEAF_WAVES;
 
 namespace trav {
-TravSplit traverse_split(int64_t groups) {
+// Sets of fewer than 4096 points on average (shallow trees) take at most 4
+// decide waves per group: 64 subjects of 500-2000 points shot in 8.69 ms
+// with at most 4, 8.76 ms with 2 and 9.47 ms with 8 (40 steps).
+#ifndef GS_SMALL_SET_NSUB
+#define GS_SMALL_SET_NSUB 4
+#endif
+TravSplit traverse_split(int64_t groups, int64_t set_points) {
     const int64_t g = groups > 0 ? groups : 1;
     TravSplit split;
     split.nsub = (int)std::min<int64_t>(kSub, std::max<int64_t>(1, (kDecideWaves + g - 1) / g));
+    if (set_points < 4096) split.nsub = std::min(split.nsub, GS_SMALL_SET_NSUB);
     split.maxc = (int)std::min<int64_t>(kMaxChunks, std::max<int64_t>(1, (kLeafWaves + g - 1) / g));
     split.segcap = kListPerGroup / split.nsub;
     return split;
@@ -743,7 +750,7 @@ gs_status launch_bh_traverse(const TreeBufs &t, const BhParams &bp, bool with_a,
     if (groups <= 0) return GS_OK;
     LeafEntry *list = reinterpret_cast<LeafEntry *>(t.list);
     const int kind = with_a ? KIND_TRAVERSE : KIND_TRAVERSE_V;
-    const TravSplit split = traverse_split(groups);
+    const TravSplit split = traverse_split(groups, t.n / (t.nsub > 0 ? t.nsub : 1));
     // the partial sums of this traversal are double-float pairs (the buffer
     // holds the backward stage's FP64 partials, of the same size)
     float2 *part = reinterpret_cast<float2 *>(t.part);
