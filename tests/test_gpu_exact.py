@@ -81,6 +81,26 @@ def test_rhs_exact_f32_full_size_sampled(oracle):
     assert ev < 1e-5 and ea < 1e-5
 
 
+@pytest.mark.parametrize("n,items", [(400000, 0), (400000, 12288), (5000, 0)])
+def test_rhs_exact_f32_shared_chunks_sampled(oracle, n, items):
+    """Sets whose source chunks are fewer than the XCDs: each chunk is shared
+    by several XCDs, which split its target groups (400k points at the
+    default target: 4 chunks on 2 XCDs each; with an explicit target of 12288:
+    2 chunks on 4 XCDs each), and a small set whose chunks are at their
+    minimum length (5000 points: 5 chunks, one XCD each).  1024 sampled
+    targets against the oracle."""
+    w = W.ellipsoids_200k(n=n)
+    _say(f"rhs_exact f32 n={n} items={items} (sampled)")
+    dq, dp = gs.gs_rhs_exact(_t(w.q0), _t(w.p0), gs.params(w.sigma, exact_items=items))
+    torch.cuda.synchronize()
+    idx = np.sort(np.random.default_rng(8).choice(n, min(n, 1024), replace=False))
+    v, a = oracle.rhs_exact_rows(idx, w.q0.astype(np.float64), w.p0.astype(np.float64),
+                                 w.sigma)
+    ev, ea = rel_l2(_np(dq)[idx], v), rel_l2(_np(dp)[idx], a)
+    _say(f"  rel-L2 v {ev:.3e} a {ea:.3e}")
+    assert ev < 1e-5 and ea < 1e-5
+
+
 @pytest.mark.parametrize("n", [1, 300, 1024])
 def test_rhs_exact_f64_matches_oracle(oracle, n):
     w = W.sphere_1024(n=n)
