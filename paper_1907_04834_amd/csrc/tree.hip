@@ -319,7 +319,9 @@ __global__ __launch_bounds__(256) void k_os_hist(const u64 *__restrict__ keys,
 // the next pass's counts.  Wave w holds tile positions [64 PER w, 64 PER (w +
 // 1)) and ranks them stably by digit with ballots and its own running counts
 // (no block barrier between rounds); the counts of the waves before it then
-// complete each key's place within the tile.
+// complete each key's place within the tile.  The keys go through LDS in the
+// tile's sorted order, so that the writes of a wave are runs of consecutive
+// addresses.
 template <int PER>
 __global__ __launch_bounds__(256) void k_os_scatter(
     const u64 *__restrict__ kin, const unsigned *__restrict__ vin, u64 *__restrict__ kout,
@@ -329,7 +331,11 @@ __global__ __launch_bounds__(256) void k_os_scatter(
     __shared__ unsigned dbase[kOsBins];     // output offset of each digit for this tile
     __shared__ unsigned wrun[4][kOsBins];   // per wave: keys of each digit ranked so far,
                                             // then the counts of the waves before it
-    __shared__ unsigned wsum[4];
+    __shared__ unsigned lbase[kOsBins];     // first place of each digit in the tile's order
+    __shared__ unsigned goff[kOsBins];      // dbase - lbase
+    __shared__ u64 skey[256 * PER];         // the tile's keys in sorted order
+    __shared__ unsigned sval[256 * PER];
+    __shared__ unsigned wsum[4], wsum2[4];
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int tile = blockIdx.x, mysb = tile / kSbTiles;
     // this thread's keys first, so that their loads overlap the prefix reads
@@ -420,7 +426,9 @@ __global__ __launch_bounds__(256) void k_os_scatter(
         wave_lds_order();
     }
     __syncthreads();
-    // the counts of the waves before each wave, per digit
+    // the counts of the waves before each wave, per digit, and the tile's
+    // count of each digit
+    unsigned cnt[2];
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
         const int d = 2 * t + j;
@@ -431,16 +439,49 @@ __global__ __launch_bounds__(256) void k_os_scatter(
             wrun[w][d] = acc;
             acc += c;
         }
+        cnt[j] = acc;
     }
+    // the tile's keys in sorted order go to LDS first (local offset lbase of
+    // each digit: an exclusive scan of the tile's counts), then out in that
+    // order, so that the lanes of a wave write runs of consecutive addresses
+    const unsigned c2 = cnt[0] + cnt[1];
+    unsigned lin = c2;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const unsigned u = __shfl_up(lin, o, 64);
+        if (lane >= o) lin += u;
+    }
+    if (lane == 63) wsum2[wv] = lin;
+    __syncthreads();
+    unsigned lex = lin - c2;
+    for (int w = 0; w < wv; ++w) lex += wsum2[w];
+    lbase[2 * t] = lex;
+    lbase[2 * t + 1] = lex + cnt[0];
+    goff[2 * t] = dbase[2 * t] - lex;
+    goff[2 * t + 1] = dbase[2 * t + 1] - (lex + cnt[0]);
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < PER; ++r) {
         const int64_t i = base + r * 64;
         if (i < n) {
             const unsigned d = dig[r];
-            const unsigned pos = dbase[d] + wrun[wv][d] + rank[r];
-            kout[pos] = key[r];
-            vout[pos] = val[r];
+            const unsigned lp = lbase[d] + wrun[wv][d] + rank[r];
+            skey[lp] = key[r];
+            sval[lp] = val[r];
+        }
+    }
+    __syncthreads();
+    const int64_t t0 = (int64_t)tile * (256 * PER);
+    const int cnt_tile = (int)(n - t0 < 256 * PER ? n - t0 : 256 * PER);
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+        const int e = r * 256 + t;
+        if (e < cnt_tile) {
+            const u64 k = skey[e];
+            const unsigned v = sval[e];
+            const unsigned pos = goff[os_digit(pass, k, v, seg, nsub)] + (unsigned)e;
+            kout[pos] = k;
+            vout[pos] = v;
         }
     }
 }
