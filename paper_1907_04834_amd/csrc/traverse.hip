@@ -29,12 +29,21 @@
 
 #include "traverse.h"
 
-// Both traversal phases are compiled for 8 waves per SIMD (at most 64 VGPRs;
-// the compiler moves the surplus scalar registers into VGPR lanes): against
-// the 7 their register use would otherwise allow, per right-hand side the
-// 200k decide phase took 525 instead of 552 us and the leaf phase 309
-// instead of 315 us; the 64-subject population 804 / 839 instead of 870 / 877.
+// The leaf phase is compiled for 8 waves per SIMD (at most 64 VGPRs; the
+// compiler moves the surplus scalar registers into VGPR lanes): against the 7
+// its register use would otherwise allow, per right-hand side the 200k leaf
+// phase took 309 instead of 315 us and the 64-subject population's 839
+// instead of 877 us (the decide phase of the former split: 525 / 804 instead
+// of 552 / 870 us).
 #define GS_TRAVERSE_ATTR __attribute__((amdgpu_waves_per_eu(8, 8)))
+// The decide phase of the level walk needs 70 VGPRs: held to 64 (8 waves per
+// SIMD) it spills to scratch memory, and the launch then waits longer for
+// its start (10.6 -> 8.6 us on average after the octree build); compiled for
+// 7 waves per SIMD the 200k Barnes-Hut shooting took 38.9 instead of 39.5 ms.
+#ifndef GS_DECIDE_WPE
+#define GS_DECIDE_WPE 7
+#endif
+#define GS_DECIDE_ATTR __attribute__((amdgpu_waves_per_eu(GS_DECIDE_WPE, 8)))
 
 namespace gs {
 
@@ -449,7 +458,7 @@ struct FwdVisit {
 // Workgroups: one group of nsub waves, or (nsub == 1) four groups of one
 // wave; dynamic LDS of walk_lds_bytes(nsub, 8 records).
 template <bool WITH_A>
-__global__ __launch_bounds__(512) GS_TRAVERSE_ATTR void k_bh_decide(
+__global__ __launch_bounds__(512) GS_DECIDE_ATTR void k_bh_decide(
     const BhNode *__restrict__ nodes, const float4 *__restrict__ Qs,
     const float4 *__restrict__ Qc, const float4 *__restrict__ Ps, int64_t n, const GroupDesc *__restrict__ gtab, int64_t groups, TravSplit split, BhParams bp,
     LeafEntry *__restrict__ list, int *__restrict__ list_n, float2 *__restrict__ part,
