@@ -102,11 +102,12 @@ __device__ inline void wave_sync() {
 // Every node is decided by one wave, and which wave depends only on the tree
 // and the targets, so the results do not depend on scheduling.  The walk is
 // bound by the latency of each block's record load more than by the busiest
-// wave: on MI355X with kSegF = 4 / 8 / 16 / 32 / 64 the 200k ellipsoids took
-// 448 / 445 / 443 / 448 / 462 us and the 64-subject population 763 / 747 /
-// 752 / 762 / 794 us per forward decide phase, against 454 / 814 us when the
-// nodes two levels below the root were dealt out by index with the levels
-// above decided by every wave (busiest decide wave 790 vs 675 decisions).
+// wave: on MI355X with kSegF = 4 / 8 / 16 / 32 / 64 the 200k ellipsoids (3
+// decide waves per group) took 448 / 445 / 443 / 448 / 462 us and the
+// 64-subject population 763 / 747 / 752 / 762 / 794 us per forward decide
+// phase, against 454 / 814 us when the nodes two levels below the root were
+// dealt out by index with the levels above decided by every wave (busiest
+// 200k decide wave: 790 decisions, against 675 with kSegF = 32).
 #ifndef GS_SEGF
 #define GS_SEGF 16
 #endif
