@@ -25,6 +25,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <utility>
 #include <cmath>
 
 #include "traverse.h"
@@ -590,8 +591,10 @@ __global__ __launch_bounds__(256) void k_bh_combine(
     const float2 *__restrict__ part, const int *__restrict__ list_n,
     const GroupDesc *__restrict__ gtab, int64_t groups, TravSplit split,
     const unsigned *__restrict__ perm, int64_t n, double inv_s2, ff inv_s2f, int mode,
-    float *__restrict__ dq, float *__restrict__ dp, float2 *__restrict__ Fq,
-    float2 *__restrict__ Fp, double *__restrict__ Sq, double *__restrict__ Sp,
+    float *__restrict__ dq, float *__restrict__ dp, const float2 *__restrict__ Fq,
+    const float2 *__restrict__ Fp, float2 *__restrict__ Fq_out, float2 *__restrict__ Fp_out,
+    const unsigned *__restrict__ ord_in, unsigned *__restrict__ ord_out,
+    double *__restrict__ Sq, double *__restrict__ Sp,
     float *__restrict__ q32, float *__restrict__ p32, const double *__restrict__ c0,
     const float2 *__restrict__ c0f, double dt, ff dtf, double *__restrict__ Hpart,
     double *__restrict__ v64) {
@@ -616,7 +619,10 @@ __global__ __launch_bounds__(256) void k_bh_combine(
                 acc[c] = ff_add(acc[c], ff{u.x, u.y});
             }
         }
-        const int64_t i = perm[(int64_t)gd.first + lane];
+        // k: the point's index in the order the tree was built from (the
+        // state's order); i: its original index
+        const int64_t j = (int64_t)gd.first + lane, k = perm[j];
+        const int64_t i = ord_in ? (int64_t)ord_in[k] : k;
         double V[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) V[c] = (double)acc[c].h + (double)acc[c].l;
@@ -632,27 +638,28 @@ __global__ __launch_bounds__(256) void k_bh_combine(
                     dp[3 * i + c] = a.h + a.l;
                 }
             }
-        } else if (Fq) {  // hi+lo state
+        } else if (Fq) {  // hi+lo state, in the order the tree was built from
             ff q[3], p[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                const float2 fq = Fq[3 * i + c], fp = Fp[3 * i + c];
+                const float2 fq = Fq[3 * k + c], fp = Fp[3 * k + c];
                 q[c] = ff{fq.x, fq.y};
                 p[c] = ff{fp.x, fp.y};
                 e += ((double)p[c].h + (double)p[c].l) * V[c];
             }
-            if (mode == MODE_SHOOT) {
+            if (mode == MODE_SHOOT) {  // advanced state in this tree's sorted order
                 const float2 *cs = c0f + 3 * gd.sub;  // the shooting's frame of this set
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     q[c] = ff_add(q[c], ff_mul(dtf, acc[c]));
                     if (WITH_A) p[c] = ff_add(p[c], ff_mul(dtf, ff_mul(acc[3 + c], inv_s2f)));
-                    Fq[3 * i + c] = make_float2(q[c].h, q[c].l);
-                    Fp[3 * i + c] = make_float2(p[c].h, p[c].l);
+                    Fq_out[3 * j + c] = make_float2(q[c].h, q[c].l);
+                    Fp_out[3 * j + c] = make_float2(p[c].h, p[c].l);
                     const ff r = ff_add(q[c], ff{-cs[c].x, -cs[c].y});
-                    q32[3 * i + c] = r.h + r.l;
-                    p32[3 * i + c] = p[c].h + p[c].l;
+                    q32[3 * j + c] = r.h + r.l;
+                    p32[3 * j + c] = p[c].h + p[c].l;
                 }
+                ord_out[j] = (unsigned)i;
             }
         } else {  // FP64 state
             double q[3], p[3];
@@ -778,8 +785,8 @@ gs_status launch_bh_traverse(const TreeBufs &t, const BhParams &bp, bool with_a,
                            groups, split, bp.negc, list, t.list_n, part, counters);            \
         hipLaunchKernelGGL(k_bh_combine<A>, g3, dim3(256), 0, s, part, t.list_n, t.gtab,      \
                            groups, split, t.perm, t.n, bp.inv_s2, inv_s2f, mode, o.dq, o.dp,   \
-                           o.Fq, o.Fp, o.Sq, o.Sp, o.q32, o.p32, o.c0, o.c0f, o.dt, dtf,       \
-                           o.Hpart, o.v64);                                                 \
+                           o.Fq, o.Fp, o.Fq_out, o.Fp_out, o.ord_in, o.ord_out, o.Sq, o.Sp,    \
+                           o.q32, o.p32, o.c0, o.c0f, o.dt, dtf, o.Hpart, o.v64);            \
     } while (0)
     if (with_a)
         GS_PHASES(true);
@@ -802,6 +809,10 @@ static void carve_state(Arena &a, int64_t n, int nt, int state, ShootBhBufs &b) 
         b.c0f = a.take<float2>(3 * (size_t)b.tree.nsub);
         b.Fq = a.take<float2>(3 * n);
         b.Fp = a.take<float2>(3 * n);
+        b.Fq2 = a.take<float2>(3 * n);
+        b.Fp2 = a.take<float2>(3 * n);
+        b.ord = a.take<unsigned>(n);
+        b.ord2 = a.take<unsigned>(n);
     } else {
         b.Sq = a.take<double>(3 * n);
         b.Sp = a.take<double>(3 * n);
@@ -840,6 +851,29 @@ gs_status rhs_bh(const float *q, const float *p, int64_t n, const gs_params &prm
     return launch_bh_traverse(t, make_bh_params(prm), true, o, counters, s, MODE_RHS, status);
 }
 
+// q = hi + lo of a state held in sorted order, rounded to FP32, at the
+// original index ord[j] of each sorted point j.
+__global__ void k_unpack_sorted(const float2 *__restrict__ Fq, const float2 *__restrict__ Fp,
+                                const unsigned *__restrict__ ord, int64_t n,
+                                float *__restrict__ q, float *__restrict__ p) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const int64_t i = ord ? (int64_t)ord[j] : j;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        q[3 * i + c] = Fq[3 * j + c].x + Fq[3 * j + c].y;
+        p[3 * i + c] = Fp[3 * j + c].x + Fp[3 * j + c].y;
+    }
+}
+
+static gs_status launch_unpack_sorted(const float2 *Fq, const float2 *Fp, const unsigned *ord,
+                                      int64_t n, float *q, float *p, hipStream_t s) {
+    if (n <= 0) return GS_OK;
+    hipLaunchKernelGGL(k_unpack_sorted, dim3(nblk(n)), dim3(kBlock), 0, s, Fq, Fp, ord, n, q, p);
+    GS_LAUNCH_CHECK("unpack sorted state");
+    return GS_OK;
+}
+
 gs_status shoot_bh(const float *q0, const float *p0, int64_t n, const gs_params &prm, float *q1,
                    float *p1, double *H, ShootBhBufs &b, char *ws, hipStream_t s) {
     int *status = reinterpret_cast<int *>(ws + kStatusOffset);
@@ -853,9 +887,12 @@ gs_status shoot_bh(const float *q0, const float *p0, int64_t n, const gs_params 
                              b.p32, s));
     const BhParams bp = make_bh_params(prm);
     const int64_t ng = b.tree.groups;
+    // Each step leaves the state, q32 and p32 in the order of its tree
+    // (ping-pong buffers), so the next build gathers points that are nearly
+    // in order already and the combine reads and writes the state in order.
+    float2 *fq = b.Fq, *fp = b.Fp, *fq_next = b.Fq2, *fp_next = b.Fp2;
+    unsigned *ord = nullptr, *ord_next = b.ord, *ord_free = b.ord2;
     TraverseOut o{};
-    o.Fq = b.Fq;
-    o.Fp = b.Fp;
     o.q32 = b.q32;
     o.p32 = b.p32;
     o.c0 = b.c0;
@@ -864,15 +901,31 @@ gs_status shoot_bh(const float *q0, const float *p0, int64_t n, const gs_params 
     for (int t = 0; t < prm.nt; ++t) {
         GS_TRY(build_tree(b.q32, b.p32, n, prm.leaf_cap, b.tree, status, s));
         o.Hpart = H ? b.Hpart + (size_t)t * ng : nullptr;
+        o.Fq = fq;
+        o.Fp = fp;
+        o.Fq_out = fq_next;
+        o.Fp_out = fp_next;
+        o.ord_in = ord;
+        o.ord_out = ord_next;
         GS_TRY(launch_bh_traverse(b.tree, bp, true, o, counters, s, MODE_SHOOT, status));
+        std::swap(fq, fq_next);
+        std::swap(fp, fp_next);
+        unsigned *spare = ord ? ord : ord_free;
+        ord = ord_next;
+        ord_next = spare;
     }
+    o.Fq = fq;
+    o.Fp = fp;
+    o.Fq_out = o.Fp_out = nullptr;
+    o.ord_in = ord;
+    o.ord_out = nullptr;
     if (H) {
         GS_TRY(build_tree(b.q32, b.p32, n, prm.leaf_cap, b.tree, status, s));
         o.Hpart = b.Hpart + (size_t)prm.nt * ng;
         GS_TRY(launch_bh_traverse(b.tree, bp, false, o, counters, s, MODE_ENERGY, status));
         GS_TRY(launch_reduce_h_seg(b.Hpart, ng, b.gseg, b.tree.nsub, prm.nt + 1, H, s));
     }
-    return launch_unpack_state(b.Fq, b.Fp, n, q1, p1, s);
+    return launch_unpack_sorted(fq, fp, ord, n, q1, p1, s);
 }
 
 }  // namespace gs

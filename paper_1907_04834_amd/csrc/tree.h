@@ -203,7 +203,16 @@ __device__ __forceinline__ unsigned long long uniform_u64(unsigned long long v) 
 // visits and the wave statistics.
 struct TraverseOut {
     float *dq, *dp;                    // RHS mode
-    float2 *Fq, *Fp;                   // shooting: hi+lo state [n][3] (hi, lo) pairs
+    // shooting: hi+lo state [n][3] (hi, lo) pairs, in the order of the points
+    // the tree was built from (the previous step's sorted order, or the
+    // original order at the first step); the advanced state, q32 and p32 are
+    // written in this tree's sorted order into Fq_out / Fp_out, and ord_out
+    // receives the original index of each sorted point (ord_in: the same for
+    // the build's input order; null: the original order itself)
+    const float2 *Fq, *Fp;
+    float2 *Fq_out, *Fp_out;
+    const unsigned *ord_in;
+    unsigned *ord_out;
     double *Sq, *Sp;                   // the backward stage's forward steps: FP64 state
     float *q32, *p32;                  // FP32 copies: q32 = q - c0[set]
     const double *c0;                  // [nsub][3] frame origins of the shooting
@@ -228,6 +237,9 @@ gs_status tree_range_sums(const float4 *A, const float4 *B, TreeBufs &t, double 
 struct ShootBhBufs {
     TreeBufs tree;
     float2 *Fq, *Fp;   // shooting state, FP32 (hi, lo) pairs [n][3]
+    float2 *Fq2, *Fp2; // the same, the other buffer (the state moves to each
+                       // step's sorted order)
+    unsigned *ord, *ord2;  // original index of each point of a sorted state [n]
     double *Sq, *Sp;   // FP64 state [n][3] (the backward stage's forward steps)
     float *q32, *p32;  // FP32 copies [n][3], q32 relative to c0
     double *c0;        // [nsub][3] frame origins of q0, fixed for the call
