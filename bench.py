@@ -40,7 +40,7 @@ GOLDEN = os.path.join(ROOT, "tests", "golden")
 # reads for an elementwise kernel of known traffic: x2.0 fetch, x1.0 write).
 # Valid only for the kernel sources they were taken on (sha256 prefix of the
 # kernel file followed by the header that fixes the work-item geometry).
-EXACT_TRAFFIC_BYTES = 134580732
+EXACT_TRAFFIC_BYTES = 134582430
 EXACT_TRAFFIC_SOURCE = "959eb099992f5104"
 EXACT_SOURCES = [os.path.join(ROOT, "paper_1907_04834_amd", "csrc", f)
                  for f in ("exact.hip", "internal.h")]
