@@ -190,6 +190,36 @@ def _one_ulp(q, seed=5):
     return np.nextafter(q, away)
 
 
+def test_shoot_bh_single_point():
+    """One point moves freely: q(1) = q0 + p0, p(1) = p0, H constant."""
+    q0 = torch.tensor([[0.1, -0.2, 0.3]], dtype=torch.float32, device=DEV)
+    p0 = torch.tensor([[0.5, 0.25, -1.0]], dtype=torch.float32, device=DEV)
+    q1, p1, H = gs.gs_shoot(q0, p0, gs.params(0.1, nt=7, theta=0.5), gs.GS_BH)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(_np(q1), _np(q0 + p0), atol=1e-6)
+    np.testing.assert_array_equal(_np(p1), _np(p0))
+    np.testing.assert_allclose(H.cpu().numpy(), np.full(8, (_np(p0) ** 2).sum()), rtol=1e-7)
+
+
+@pytest.mark.parametrize("leaf_cap", [1, 4])
+def test_shoot_bh_coincident_clusters(oracle, leaf_cap):
+    """Twelve clusters of nine coincident points with different momenta:
+    equal Morton keys at the first step, and a state that moves from one
+    tree order to the next, against the oracle's Barnes-Hut shooting (which
+    on this set equals its exact shooting to 1e-16, and moves by 8e-8 when
+    q0 moves by one FP32 ulp)."""
+    rng = np.random.default_rng(5)
+    q = np.repeat(rng.random((12, 3)) * 4.0, 9, axis=0).astype(np.float32)
+    p = (0.1 * rng.standard_normal(q.shape)).astype(np.float32)
+    q1, p1, H = gs.gs_shoot(_t(q), _t(p), gs.params(0.1, nt=6, theta=0.5, leaf_cap=leaf_cap),
+                            gs.GS_BH)
+    torch.cuda.synchronize()
+    bq, bp, bH = oracle.shoot(q.astype(np.float64), p.astype(np.float64), 0.1, 6, method="bh",
+                              theta=0.5, leaf_cap=leaf_cap)
+    assert rel_l2(_np(q1), bq) <= 1e-5 and rel_l2(_np(p1), bp) <= 1e-5
+    assert np.abs(H.cpu().numpy() - bH).max() <= 1e-6 * np.abs(bH).max()
+
+
 @pytest.mark.parametrize("theta", [0.3, 0.5, 0.8, math.inf])
 def test_shoot_bh_ellipsoid_20k(oracle, theta):
     """The 20k ellipsoid at every opening angle of the workload (and the
