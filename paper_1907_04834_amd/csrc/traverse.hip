@@ -851,6 +851,8 @@ gs_status rhs_bh(const float *q, const float *p, int64_t n, const gs_params &prm
     return launch_bh_traverse(t, make_bh_params(prm), true, o, counters, s, MODE_RHS, status);
 }
 
+namespace {
+
 // q = hi + lo of a state held in sorted order, rounded to FP32, at the
 // original index ord[j] of each sorted point j.
 __global__ void k_unpack_sorted(const float2 *__restrict__ Fq, const float2 *__restrict__ Fp,
@@ -866,13 +868,15 @@ __global__ void k_unpack_sorted(const float2 *__restrict__ Fq, const float2 *__r
     }
 }
 
-static gs_status launch_unpack_sorted(const float2 *Fq, const float2 *Fp, const unsigned *ord,
-                                      int64_t n, float *q, float *p, hipStream_t s) {
+gs_status launch_unpack_sorted(const float2 *Fq, const float2 *Fp, const unsigned *ord,
+                               int64_t n, float *q, float *p, hipStream_t s) {
     if (n <= 0) return GS_OK;
     hipLaunchKernelGGL(k_unpack_sorted, dim3(nblk(n)), dim3(kBlock), 0, s, Fq, Fp, ord, n, q, p);
     GS_LAUNCH_CHECK("unpack sorted state");
     return GS_OK;
 }
+
+}  // namespace
 
 gs_status shoot_bh(const float *q0, const float *p0, int64_t n, const gs_params &prm, float *q1,
                    float *p1, double *H, ShootBhBufs &b, char *ws, hipStream_t s) {
